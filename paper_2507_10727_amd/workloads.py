@@ -1,0 +1,297 @@
+"""Seeded synthetic workloads for the RZ PIC-MCC timestep.
+
+This module only *generates inputs*: problem presets, the static magnetron
+field, the electron-argon cross-section tables and the initial particle load.
+It holds none of the timestep's arithmetic (no gather, push, collision,
+deposit, field solve or circuit), so that the GPU library and the CPU oracle
+can both consume exactly the same inputs without sharing any method code.
+
+Physical setting (paper, Sections 3-4): a dc magnetron discharge in argon,
+2D R-Z with azimuthal symmetry, cathode on the z = 0 plane, anode at
+z = Z_max, a static magnetic field from magnets behind the cathode, electron
+impact elastic / excitation / ionization collisions with a uniform neutral
+background, ion-induced secondary emission at the cathode, and a cathode that
+floats through an external resistor.  The sizes below are synthetic stand-ins
+in the paper's regime (densities 1e15-1e17 m^-3, 1-30 mTorr, 300-700 V
+cathode, Introduction); the paper's own VSim inputs (QDB cross sections, the
+two-magnet scalar-potential field) are not available and are replaced by the
+analytic forms documented here.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+# CODATA 2018 values (SI).  Each consumer keeps its own copy; these are used
+# here only to build inputs (weights, thermal speeds, gas density for the
+# cross-section tables is *not* computed here).
+E_CHARGE = 1.602176634e-19
+M_E = 9.1093837015e-31
+AMU = 1.66053906660e-27
+M_AR = 39.948 * AMU
+K_B = 1.380649e-23
+MU0 = 4e-7 * math.pi
+TORR = 133.322368  # Pa
+
+MC_PIC = 0
+EC_PIC = 1
+F32 = 0
+F64 = 1
+FIXED_V = 0
+RESISTOR = 1
+ABSORB = 0
+REFLECT = 1
+
+
+@dataclasses.dataclass
+class Problem:
+    """One discharge: geometry, numerics, circuit, gas and species.
+
+    Grid sizes are numbers of *cells*; the node grid is (nr+1) x (nz+1), node
+    (i, j) at r = i*dr, z = j*dz, stored at linear index j*(nr+1)+i.
+    """
+
+    name: str = "custom"
+    nr: int = 64
+    nz: int = 64
+    lr: float = 0.02
+    lz: float = 0.02
+    dt: float = 5e-12
+    scheme: int = MC_PIC
+    precision: int = F64
+    cathode_rmax: Optional[float] = None  # defaults to lr (whole z = 0 plane)
+    circuit: int = FIXED_V
+    v_fixed: float = -400.0
+    v_ext: float = -400.0
+    r_ext: float = 100.0
+    gamma_i: float = 0.1
+    p_gas: float = 5e-3 * TORR
+    t_gas: float = 300.0
+    e_exc: float = 11.5
+    e_iz: float = 15.76
+    b_peak: float = 0.03
+    density: float = 1e15
+    te_ev: float = 2.0
+    ti_ev: float = 0.03
+    n_per_species: int = 200_000
+    steps: int = 200
+    seed: int = 250710727
+    run: int = 0
+    sort_every: int = 20
+    poisson_rtol: float = 1e-8
+    poisson_maxit: int = 200
+    wall_bc: tuple = (ABSORB, ABSORB, ABSORB)
+    frozen_ions: int = 0
+    mcc_on: int = 1
+    see_on: int = 1
+    field_solve: int = 1
+    extra_current: float = 0.0
+    capacity_factor: float = 1.5
+    weight: Optional[float] = None  # macroparticle weight; default n*V/N
+
+    def __post_init__(self):
+        if self.cathode_rmax is None:
+            self.cathode_rmax = self.lr
+
+    @property
+    def dr(self) -> float:
+        return self.lr / self.nr
+
+    @property
+    def dz(self) -> float:
+        return self.lz / self.nz
+
+    @property
+    def nodes(self) -> int:
+        return (self.nr + 1) * (self.nz + 1)
+
+    @property
+    def volume(self) -> float:
+        return math.pi * self.lr ** 2 * self.lz
+
+    def macro_weight(self) -> float:
+        if self.weight is not None:
+            return self.weight
+        return self.density * self.volume / max(self.n_per_species, 1)
+
+    def species(self):
+        """(q, m, w) for electrons (0) and Ar+ (1)."""
+        w = self.macro_weight()
+        return ((-E_CHARGE, M_E, w), (E_CHARGE, M_AR - M_E, w))
+
+    def capacity(self):
+        c = int(self.n_per_species * self.capacity_factor) + 4096
+        return (c, c)
+
+    def replace(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Presets (synthetic stand-ins in the paper's regime)
+# ---------------------------------------------------------------------------
+
+def preset(name: str) -> Problem:
+    """Named workloads.
+
+    small_mc64_f64   : 64x64 cells over 2x2 cm, 2e5 e- + 2e5 Ar+, n = 1e15,
+                       MC-PIC, FP64 state, cathode fixed at -400 V, 5 mTorr,
+                       peak B 0.03 T, 200 steps (the small parity case).
+    ec256x512_f32    : 256x512 cells over 4x8 cm, 1e7 + 1e7, n = 1e16,
+                       EC-PIC, FP32 state, -500 V through 100 ohm, 10 mTorr,
+                       peak B 0.05 T (the throughput case; mc256x512_f32 is
+                       the same with the MC gather).
+    ec512x1024_f32   : 512x1024 cells over 5x10 cm, 5e7 + 5e7, n = 1e17,
+                       20 mTorr, -500 V through 10/100 ohm (high-density case).
+    """
+    if name == "small_mc64_f64":
+        return Problem(name=name)
+    if name in ("ec256x512_f32", "mc256x512_f32"):
+        return Problem(
+            name=name, nr=256, nz=512, lr=0.04, lz=0.08,
+            scheme=EC_PIC if name.startswith("ec") else MC_PIC, precision=F32,
+            circuit=RESISTOR, v_ext=-500.0, v_fixed=-500.0, r_ext=100.0,
+            p_gas=10e-3 * TORR, b_peak=0.05, density=1e16,
+            n_per_species=10_000_000, steps=20000, seed=250710728,
+            capacity_factor=1.25)
+    if name in ("ec512x1024_f32", "mc512x1024_f32"):
+        return Problem(
+            name=name, nr=512, nz=1024, lr=0.05, lz=0.10,
+            scheme=EC_PIC if name.startswith("ec") else MC_PIC, precision=F32,
+            circuit=RESISTOR, v_ext=-500.0, v_fixed=-500.0, r_ext=100.0,
+            p_gas=20e-3 * TORR, b_peak=0.05, density=1e17,
+            n_per_species=50_000_000, steps=20000, seed=250710729,
+            capacity_factor=1.1)
+    raise KeyError(name)
+
+
+def scaled(p: Problem, n_per_species: int) -> Problem:
+    """Same discharge with fewer macroparticles (density kept, weight raised)."""
+    return p.replace(n_per_species=n_per_species, weight=None)
+
+
+# ---------------------------------------------------------------------------
+# Static magnetron field: one coaxial current loop behind the cathode
+# ---------------------------------------------------------------------------
+
+def loop_field(rho, z, a, current=1.0):
+    """B of a circular current loop of radius ``a`` in the plane z = 0.
+
+    Closed form with complete elliptic integrals K(m), E(m), m = k^2
+    (e.g. Jackson, Classical Electrodynamics, Sec. 5.5; Smythe).  Returns
+    (B_rho, B_z) in tesla for ``current`` amperes.
+    """
+    from scipy.special import ellipe, ellipk
+
+    rho = np.asarray(rho, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    ap2 = (a + rho) ** 2 + z ** 2
+    am2 = (a - rho) ** 2 + z ** 2
+    m = 4.0 * a * rho / ap2
+    kk = ellipk(m)
+    ee = ellipe(m)
+    c = MU0 * current / (2.0 * np.pi)
+    sq = np.sqrt(ap2)
+    bz = c / sq * (kk + (a * a - rho * rho - z * z) / am2 * ee)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        br = c * z / (rho * sq) * (-kk + (a * a + rho * rho + z * z) / am2 * ee)
+    br = np.where(rho > 0.0, br, 0.0)
+    return br, bz
+
+
+def magnetron_field(p: Problem):
+    """Nodal (B_r, B_z), each (nz+1)*(nr+1) flat, r fastest.
+
+    A single loop of radius 0.45*L_r placed 0.15*L_r behind the cathode plane,
+    scaled so that max |B| over the z = 0 node row equals ``b_peak``.
+    """
+    r = np.arange(p.nr + 1) * p.dr
+    z = np.arange(p.nz + 1) * p.dz
+    a = 0.45 * p.lr
+    z0 = -0.15 * p.lr
+    R, Z = np.meshgrid(r, z)  # shape (nz+1, nr+1)
+    br, bz = loop_field(R, Z - z0, a)
+    mag0 = np.sqrt(br[0] ** 2 + bz[0] ** 2).max()
+    s = p.b_peak / mag0 if mag0 > 0 else 0.0
+    return (np.ascontiguousarray((br * s).ravel()),
+            np.ascontiguousarray((bz * s).ravel()))
+
+
+# ---------------------------------------------------------------------------
+# Electron-argon cross sections (analytic fits; project-defined)
+# ---------------------------------------------------------------------------
+
+N_TABLE = 20001
+DE_TABLE = 0.05  # eV
+
+
+def cross_sections(e_exc=11.5, e_iz=15.76, n=N_TABLE, de=DE_TABLE):
+    """Tabulated cross sections (m^2) at E_k = k*de eV, k = 0..n-1.
+
+    Rows: elastic, excitation, ionization.  Smooth analytic forms in the
+    magnitude range of e-Ar data: an elastic curve peaking near 10-15 eV, a
+    Thomson-like excitation and a Lotz ionization.  Both inelastic forms vanish
+    at and below threshold.
+    """
+    e = np.arange(n, dtype=np.float64) * de
+    el = 1.5e-19 * (e / 12.0) ** 1.2 / (1.0 + (e / 12.0) ** 2.2) + 2.0e-21
+    el = el + 1.0e-20 / (1.0 + e)  # low-energy floor
+    x = np.where(e > e_exc, e / e_exc, 1.0)
+    ex = np.where(e > e_exc, 3.0e-20 * np.log(x) / x, 0.0)
+    # Lotz: sigma = a q ln(E/I) / (E I), a = 4.5e-18 eV^2 m^2, q = 6
+    y = np.where(e > e_iz, e, e_iz)
+    iz = np.where(e > e_iz, 4.5e-18 * 6.0 * np.log(y / e_iz) / (y * e_iz), 0.0)
+    return np.ascontiguousarray(np.stack([el, ex, iz]))
+
+
+# ---------------------------------------------------------------------------
+# Initial load (paper, Section 4: seed population of uniform-density e-, Ar+)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SpeciesArrays:
+    r: np.ndarray
+    z: np.ndarray
+    vr: np.ndarray
+    vt: np.ndarray
+    vz: np.ndarray
+    id: np.ndarray  # uint32
+
+    @property
+    def n(self):
+        return int(self.r.shape[0])
+
+    def copy(self):
+        return SpeciesArrays(*(a.copy() for a in
+                               (self.r, self.z, self.vr, self.vt, self.vz, self.id)))
+
+
+def load_uniform(p: Problem, n: Optional[int] = None, seed_offset: int = 0):
+    """Uniform-in-volume positions (r = R sqrt(U), z = L U) and Maxwellian
+    velocities (Te for electrons, Ti for ions); ids 0..N-1 per species.
+    Sampled velocities are taken as v^{n-1/2}.
+    """
+    n = p.n_per_species if n is None else n
+    rng = np.random.Generator(np.random.PCG64(p.seed + 7919 * seed_offset))
+    out = []
+    for s, t_ev in ((0, p.te_ev), (1, p.ti_ev)):
+        m = M_E if s == 0 else (M_AR - M_E)
+        vth = math.sqrt(t_ev * E_CHARGE / m)
+        r = p.lr * np.sqrt(rng.random(n))
+        z = p.lz * rng.random(n)
+        # keep strictly inside [0, L): rng.random() < 1 already
+        v = rng.standard_normal((3, n)) * vth
+        out.append(SpeciesArrays(r, z, v[0].copy(), v[1].copy(), v[2].copy(),
+                                 np.arange(n, dtype=np.uint32)))
+    return out
+
+
+def inputs(p: Problem, n: Optional[int] = None):
+    """Everything a run needs: (B_r, B_z, sigma table, [electrons, ions])."""
+    br, bz = magnetron_field(p)
+    sig = cross_sections(p.e_exc, p.e_iz)
+    parts = load_uniform(p, n)
+    return br, bz, sig, parts

@@ -1,0 +1,226 @@
+"""Pins for the oracle's collisions, secondary emission, circuit and restart.
+
+* null-collision MCC: per-process counts of a mono-energetic beam against
+  Binomial(N, P_null nu_j / nu_max) ~ N n sigma v dt; per-particle decisions
+  re-derived on tiny inputs from the published Philox definition;
+* collision energetics: exact threshold losses, ionization energy balance,
+  elastic loss bounds and mean 2 m/M;
+* ion-induced emission: Binomial(N_hit, gamma) counts, emitted at rest on the
+  cathode, ids in parent order, cathode charge bookkeeping;
+* circuit: in vacuum with a constant injected current the cathode voltage
+  relaxes geometrically, factor C / (C + dt/R), to V_ext + R I;
+* restart: 2N steps == N steps, copy of the state, N steps (bit-exact).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle_helpers import empty, make_oracle, species, zero_field_problem
+from paper_2507_10727_amd import workloads as W
+
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+KB = 1.380649e-23
+
+
+def _beam_problem(**kw):
+    base = dict(nr=16, nz=16, lr=0.02, lz=0.02, field_solve=0, see_on=0, frozen_ions=1,
+                v_fixed=0.0, v_ext=0.0, weight=1.0, p_gas=10e-3 * W.TORR)
+    base.update(kw)
+    return zero_field_problem(**base)
+
+
+def _beam(n, e0, seed=11):
+    rng = np.random.default_rng(seed)
+    v = math.sqrt(2 * QE * e0 / ME)
+    d = rng.normal(size=(3, n))
+    d /= np.linalg.norm(d, axis=0)
+    r = 0.005 + 0.01 * rng.random(n)
+    z = 0.005 + 0.01 * rng.random(n)
+    return species(r, z, v * d[0], v * d[1], v * d[2])
+
+
+def _energy(a):
+    return 0.5 * ME * (a["vr"] ** 2 + a["vt"] ** 2 + a["vz"] ** 2) / QE
+
+
+def test_mcc_counts_binomial():
+    e0 = 50.0  # on a table node, above both thresholds
+    n = 400_000
+    p = _beam_problem(dt=2e-11)
+    o = make_oracle(p, [_beam(n, e0), empty()], capacity=(2 * n, n))
+    o.init()
+    o.phi[:] = 0
+    d = o.step()
+    sig = o.sigma[:, int(round(e0 / 0.05))]
+    ng = p.p_gas / (KB * p.t_gas)
+    v = math.sqrt(2 * QE * e0 / ME)
+    nu, numax, tnull = o.nu_tables()
+    pnull = tnull / 2**32
+    assert abs(pnull - -math.expm1(-numax * p.dt)) <= 2.0 ** -32
+    for j in range(3):
+        prob = pnull * ng * sig[j] * v / numax
+        mean = n * prob
+        sd = math.sqrt(n * prob * (1 - prob))
+        assert abs(d["n_coll"][j] - mean) < 5 * sd + 1, (j, d["n_coll"][j], mean)
+        # small-probability limit: ~ N n sigma v dt
+        assert mean == pytest.approx(n * ng * sig[j] * v * p.dt, rel=2 * numax * p.dt)
+    assert d["n_child"] == (d["n_coll"][2], d["n_coll"][2])
+
+
+def test_mcc_decisions_bruteforce():
+    """Re-derive each electron's outcome from the published generator and
+    the null-collision rule on a tiny beam with a large P_null."""
+    e0 = 40.0
+    n = 3000
+    p = _beam_problem(dt=2e-9, p_gas=30e-3 * W.TORR,  # P_null ~ 0.5
+                      wall_bc=(W.REFLECT, W.REFLECT, W.REFLECT))
+    beam = _beam(n, e0, seed=12)
+    o = make_oracle(p, [beam, empty()], capacity=(2 * n, n))
+    o.init()
+    o.phi[:] = 0
+    d = o.step()
+    a = o.particles(0)
+    nu, numax, tnull = o.nu_tables()
+    k = int(round(e0 / 0.05))
+    c1 = nu[0, k]
+    c2 = c1 + nu[1, k]
+    c3 = c2 + nu[2, k]
+    key = [p.seed & 0xffffffff, p.seed >> 32]
+    expect = {}
+    for pid in range(n):
+        u = O.philox([pid, (p.run << 8) | 0, 0, 0], key)
+        if int(u[0]) >= tnull:
+            expect[pid] = "none"
+            continue
+        x = (int(u[1]) >> 8) / 2**24 * numax
+        expect[pid] = "el" if x < c1 else "ex" if x < c2 else "iz" if x < c3 else "none"
+    e = _energy(a)
+    ids = a["id"]
+    got = {}
+    for k_, pid in enumerate(ids):
+        if pid >= n:
+            continue
+        de = e0 - e[k_]
+        if abs(de) < 1e-9 * e0 and expect[pid] == "none":
+            got[pid] = "none"
+        elif abs(de - 11.5) < 1e-9 * e0:
+            got[pid] = "ex"
+        elif 0 <= de <= 4 * ME / (39.948 * 1.66053906660e-27) * e0 * 1.0001:
+            got[pid] = "el" if de > 0 or expect[pid] == "el" else "none"
+        else:
+            got[pid] = "iz"
+    mism = [pid for pid in got if got[pid] != expect[pid]]
+    assert not mism, mism[:10]
+    assert len(got) == n
+    assert sum(v == "iz" for v in expect.values()) == d["n_coll"][2] > 0
+
+
+def test_collision_energetics():
+    e0 = 60.0
+    n = 200_000
+    p = _beam_problem(dt=5e-10)
+    o = make_oracle(p, [_beam(n, e0, seed=13), empty()], capacity=(3 * n, n))
+    o.init()
+    o.phi[:] = 0
+    o.step()
+    a = o.particles(0)
+    e = _energy(a)
+    parent = a["id"] < n
+    m_ar = 39.948 * 1.66053906660e-27
+    frac = 1 - e[parent] / e0
+    ex = np.abs(e0 - e[parent] - 11.5) < 1e-9 * e0
+    assert ex.sum() > 100
+    # ionization: scattered + ejected energies sum to E - 15.76 (children are
+    # ordered by parent id, so the k-th child belongs to the k-th ionizer)
+    ion = o.particles(1)
+    nz_ = ion["id"].shape[0]
+    assert nz_ > 100
+    kids = a["id"] >= n
+    ekid = e[kids]
+    assert ekid.shape[0] == nz_
+    scat = ~ex & (frac > 4 * ME / m_ar * 1.001)
+    esc = e[parent][scat]
+    assert esc.shape[0] == nz_
+    assert np.abs(esc + ekid - (e0 - 15.76)).max() < 1e-9 * e0
+    # elastic: 0 <= loss fraction <= 4 m/M and mean 2 m/M
+    el = (frac > 1e-12) & (frac <= 4 * ME / m_ar * 1.0001) & ~ex
+    assert el.sum() > 1000
+    assert frac[el].mean() == pytest.approx(2 * ME / m_ar, rel=0.1)
+    # new ions: Maxwellian at the gas temperature
+    vt = math.sqrt(KB * p.t_gas / (m_ar - ME))
+    assert np.std(ion["vr"]) == pytest.approx(vt, rel=0.15)
+
+
+def test_secondary_emission():
+    n = 20000
+    gamma = 0.1
+    p = _beam_problem(gamma_i=gamma, see_on=1, frozen_ions=0, mcc_on=0, nr=16, nz=16)
+    rng = np.random.default_rng(14)
+    r = 0.018 * rng.random(n)
+    ions = species(r, 1e-9, 0.0, 0.0, -1e4)
+    o = make_oracle(p, [empty(), ions], capacity=(n, n))
+    o.init()
+    o.phi[:] = 0
+    d = o.step()
+    assert d["n_abs"][1][1] == n
+    nsee = d["n_see"]
+    assert abs(nsee - n * gamma) < 5 * math.sqrt(n * gamma * (1 - gamma))
+    e = o.particles(0)
+    assert e["id"].shape[0] == nsee
+    # ids consecutive from next_id, in parent order; emitted at rest on z = 0
+    assert list(e["id"]) == list(range(nsee))
+    assert (e["z"] == 0).all() and (e["vr"] == 0).all() and (e["vz"] == 0).all()
+    # which ions emitted: brute force from the generator
+    key = [p.seed & 0xffffffff, p.seed >> 32]
+    thr = math.floor(gamma * 2**32)
+    emit = [pid for pid in range(n) if int(O.philox([pid, (1 << 4) | 3, 0, 0], key)[0]) < thr]
+    rr = r - 1e4 * 0 * p.dt  # radial position unchanged (v_r = 0)
+    assert np.allclose(e["r"], rr[emit], rtol=0, atol=1e-18)
+    # cathode charge: N_hit q_i w + N_see e w_e
+    assert d["dq_conv"] == pytest.approx(n * QE + nsee * QE, rel=1e-12)
+
+
+def test_circuit_relaxation():
+    p = zero_field_problem(nr=16, nz=16, circuit=W.RESISTOR, v_ext=-300.0, r_ext=1.0,
+                           extra_current=0.05, mcc_on=0, see_on=0)
+    o = make_oracle(p)
+    o.init()
+    c = o.state.cap_c
+    a = c / (c + p.dt / p.r_ext)
+    vstar = p.v_ext + p.r_ext * p.extra_current
+    v0 = p.v_ext
+    for n in range(1, 40):
+        o.step()
+        expect = vstar + (v0 - vstar) * a ** n
+        assert o.state.vc == pytest.approx(expect, rel=1e-12, abs=1e-12)
+    assert 0.05 < a < 0.95
+
+
+def test_restart_bitexact():
+    p = W.preset("small_mc64_f64").replace(nr=16, nz=16, n_per_species=4000)
+    br, bz, sig, parts = W.inputs(p)
+    a = O.Oracle(p, br, bz, sig, [s.copy() for s in parts])
+    a.init()
+    for _ in range(6):
+        a.step()
+    b = O.Oracle(p, br, bz, sig, [s.copy() for s in parts])
+    b.init()
+    for _ in range(3):
+        b.step()
+    # copy state into a fresh run
+    c = O.Oracle(p, br, bz, sig, [W.SpeciesArrays(**{k: v for k, v in b.particles(s).items()})
+                                  for s in range(2)])
+    c.init()
+    c.phi[:] = b.phi; c.phi0[:] = b.phi0
+    c.state.step, c.state.vc, c.state.qc = b.state.step, b.state.vc, b.state.qc
+    c.state.next_id[0], c.state.next_id[1] = b.state.next_id[0], b.state.next_id[1]
+    for _ in range(3):
+        c.step()
+    for s in range(2):
+        x, y = a.particles(s), c.particles(s)
+        for k in x:
+            assert np.array_equal(x[k], y[k]), (s, k)
+    assert np.array_equal(a.phi, c.phi)
