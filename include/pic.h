@@ -1,0 +1,244 @@
+/*
+ * pic.h -- C ABI of libpic.so: one explicit electrostatic 2D R-Z PIC-MCC
+ * timestep of a dc magnetron discharge on an AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of Main et al., "Modeling the Role of Secondary
+ * Electron Emission in Direct Current Magnetron Sputtering using Explicit
+ * Energy-Conserving Particle-in-Cell Methods" (arXiv 2507.10727):
+ *   Section 2 -- momentum-conserving (MC-PIC) and energy-conserving (EC-PIC)
+ *                field gathers; nodal potential and charge, edge-centred E;
+ *                linear (tent) charge deposition;
+ *   Section 3 -- R-Z geometry with azimuthal symmetry; grounded anode at
+ *                z = Z_max; cathode on z = 0 floating through an external
+ *                circuit, with a Neumann block beside it; Gauss's law on the
+ *                axis; absorbing z and outer-r walls, reflective axis;
+ *                constant ion-induced secondary electron yield with electrons
+ *                emitted at rest; Monte Carlo collisions of electrons with a
+ *                static argon background (elastic, excitation, ground-state
+ *                ionization);
+ *   Section 4 -- uniform seed load; external resistor circuit.
+ *
+ * Conventions
+ *   - All units SI; energies of the collision tables in eV.
+ *   - Grid sizes count CELLS: nodes are (nr+1) x (nz+1); node (i, j) sits at
+ *     r = i*dr, z = j*dz and is stored at linear index j*(nr+1) + i.
+ *   - Species 0 = electrons, 1 = Ar+.
+ *   - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *     tensors); every other pointer is host memory.
+ *   - The library never allocates device memory: the caller passes one
+ *     workspace (size from pic_query_workspace) and keeps ownership of it;
+ *     pic_free never frees caller memory.  Host allocations are limited to
+ *     the handle and small metadata.
+ *   - Work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *     void*; NULL = the null stream).  Calls that return data to the host
+ *     synchronize that stream.
+ *   - Every call returns a pic_status; pic_last_error() gives a message.
+ *     Asynchronous device faults surface as PIC_EHIP at the next
+ *     synchronizing call.  A handle is not thread-safe.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pic_status {
+    PIC_OK = 0,
+    PIC_EINVAL = -1,     /* invalid argument or configuration               */
+    PIC_ECAPACITY = -2,  /* a particle or child buffer would overflow       */
+    PIC_EHIP = -3,       /* HIP runtime error (message has the HIP string)  */
+    PIC_ENOCONV = -4,    /* field solve did not reach its tolerance         */
+    PIC_ENAN = -5,       /* non-finite value detected                       */
+    PIC_ESTATE = -6      /* call not valid in the handle's current state    */
+} pic_status;
+
+enum { PIC_MC = 0, PIC_EC = 1 };              /* field-gather scheme (Section 2) */
+enum { PIC_F32 = 0, PIC_F64 = 1 };            /* particle-state precision        */
+enum { PIC_FIXED_V = 0, PIC_RESISTOR = 1 };   /* cathode circuit (Sections 3-4)  */
+enum { PIC_ABSORB = 0, PIC_REFLECT = 1 };     /* particle wall condition         */
+enum { PIC_MGCG = 0, PIC_LEARNED = 1 };       /* Poisson preconditioner          */
+
+typedef struct pic_handle pic_handle;         /* opaque, library-owned */
+
+/* Problem definition.  Host arrays are read during pic_init only. */
+typedef struct pic_config {
+    int32_t nr, nz;             /* cells in r and z (>= 2)                        */
+    double lr, lz;              /* domain r in [0, lr], z in [0, lz] (m)          */
+    double dt;                  /* timestep (s)                                   */
+    int32_t scheme;             /* PIC_MC or PIC_EC                               */
+    int32_t precision;          /* PIC_F32 or PIC_F64 particle state              */
+    double cathode_rmax;        /* z = 0 nodes with r < cathode_rmax are cathode;
+                                   the rest of z = 0 is a Neumann block (Section 3) */
+    int32_t circuit;            /* PIC_FIXED_V or PIC_RESISTOR                    */
+    double v_fixed;             /* cathode voltage in PIC_FIXED_V mode (V)        */
+    double v_ext, r_ext;        /* source voltage (V) and resistance (ohm)        */
+    double gamma_i;             /* ion-induced secondary electron yield           */
+    double p_gas, t_gas;        /* argon pressure (Pa), temperature (K)           */
+    double e_exc, e_iz;         /* excitation, ionization thresholds (eV)         */
+    const double *sigma;        /* host [3][n_table]: elastic, excitation,
+                                   ionization cross sections (m^2) at
+                                   E_k = k * de_table eV                          */
+    int32_t n_table;            /* >= 2                                           */
+    double de_table;            /* eV                                             */
+    const double *b_r, *b_z;    /* host nodal static magnetic field (T)           */
+    double q[2], m[2], w[2];    /* charge (C), mass (kg), macro weight            */
+    uint64_t seed;              /* Philox key                                     */
+    uint32_t run;               /* ensemble index, selects the random stream      */
+    int64_t capacity[2];        /* particle slots per species                     */
+    int32_t sort_every;         /* steps between cell sorts (>= 1)                */
+    int32_t poisson_mode;       /* PIC_MGCG (PIC_LEARNED needs weights)           */
+    double poisson_rtol;        /* FP64 relative residual target of each solve    */
+    int32_t poisson_maxit;      /* cap on preconditioned CG iterations per solve  */
+    int32_t wall_bc[3];         /* z = 0, z = lz, r = lr: PIC_ABSORB/PIC_REFLECT  */
+    int32_t frozen_ions;        /* 1: ions are not pushed (test configurations)   */
+    int32_t mcc_on, see_on;     /* enable collisions / secondary emission         */
+    int32_t field_solve;        /* 0: keep phi fixed (push-only configurations)   */
+    double extra_current;       /* synthetic current into the cathode (A)         */
+} pic_config;
+
+/* Initial particles of one species (host, FP64, absolute positions).
+ * Velocities are taken as v^{n-1/2}.  ids must be unique per species. */
+typedef struct pic_species_host {
+    const double *r, *z, *vr, *vt, *vz;
+    const uint32_t *id;
+    int64_t n;
+} pic_species_host;
+
+/* Device view of one species' particle arrays (valid until the next call
+ * that sorts: pic_step, pic_compact).  Slot k is live iff key[k] >= 0.
+ * key = j << 16 | i (cell), fr/fz = in-cell fraction in [0,1) of the
+ * precision given, so r = (i + fr) * dr; velocities are v^{n-1/2} in
+ * (r, theta, z) components. */
+typedef struct pic_particle_view {
+    int32_t *key_dev;
+    void *fr_dev, *fz_dev, *vr_dev, *vt_dev, *vz_dev;
+    uint32_t *id_dev;
+    int64_t count;              /* slots in use (live + not yet compacted)        */
+    int64_t capacity;
+    int32_t precision;
+} pic_particle_view;
+
+/* Device view of the node fields (FP64 unless stated). */
+typedef struct pic_field_view {
+    double *phi_dev;            /* phi^n = phi0 + V_c phi_L                        */
+    double *phi0_dev;           /* solve with the cathode at 0 V                   */
+    double *phi_l_dev;          /* unit-cathode Laplace solution                   */
+    void *q_dev[2];             /* deposited node charge per species (C), in the
+                                   particle precision                             */
+    int64_t nodes;
+    int32_t q_precision;
+} pic_field_view;
+
+typedef struct pic_poisson_stats {
+    int32_t iterations;         /* preconditioned CG iterations (all passes)     */
+    int32_t outer;              /* FP64 refinement passes                         */
+    double rel_res;             /* final ||b - K phi|| / ||b||, FP64              */
+    int32_t fell_back;          /* learned preconditioner replaced by MG          */
+    int32_t converged;
+} pic_poisson_stats;
+
+/* Diagnostics (FP64).  ke/pz/dq refer to the last completed step. */
+typedef struct pic_diag_out {
+    int64_t step;
+    double time;
+    int64_t count[2];           /* live particles                                */
+    double q_dep[2];            /* sum of deposited node charge                   */
+    double q_expect[2];         /* q_s w_s N_s                                    */
+    double ke[2];               /* 1/2 m w v^{n-1/2}.v^{n+1/2} summed            */
+    double pz[2];               /* axial momentum at the new half step           */
+    double w_field;             /* 1/2 sum_faces c (dphi)^2 of the current phi   */
+    double dq_conv;             /* charge delivered to the cathode, last step    */
+    double i_cathode;           /* dq_conv / dt                                   */
+    double vc, qc, cap_c;       /* cathode voltage, charge, capacitance           */
+    double n_peak[2];           /* max over nodes of Q_s / (q_s V_node)           */
+    double phi_max;             /* max over nodes of phi                          */
+    int64_t n_abs[2][5];        /* absorbed in the last step by wall code 1..4:
+                                   cathode, Neumann block, outer r, anode        */
+    int64_t n_cand, n_coll[3];  /* null-collision candidates; el, ex, iz          */
+    int64_t n_see;
+    int64_t n_child[2];
+    int64_t deposit_fallback;   /* particle chunks deposited without LDS tiles    */
+    pic_poisson_stats poisson;  /* last field solve                               */
+    int32_t flags;              /* bit 0 capacity, bit 1 child overflow, bit 2 NaN */
+} pic_diag_out;
+
+/* Scalar state for checkpoint/resume (particle and field arrays are read and
+ * written through the views). */
+typedef struct pic_scalar_state {
+    int64_t step;
+    double vc, qc;
+    uint32_t next_id[2];
+    int64_t count[2];
+} pic_scalar_state;
+
+/* Per-phase device time accumulated from HIP events (ms), when enabled. */
+typedef struct pic_timers {
+    double push_ms, children_ms, sort_ms, poisson_ms, circuit_ms, field_ms;
+    int64_t push_launches, sort_launches, poisson_solves;
+} pic_timers;
+
+/* Bytes of device workspace pic_init needs for cfg.  Errors: PIC_EINVAL. */
+pic_status pic_query_workspace(const pic_config *cfg, int64_t *bytes);
+
+/* Create a simulation in workspace_dev (>= the queried bytes, 256-byte
+ * aligned).  init may be NULL (no particles) or point to two species.
+ * Builds the collision tables, the multigrid hierarchy, phi_L and the
+ * cathode capacitance, uploads and cell-sorts the particles, deposits and
+ * solves the initial field.  Synchronizes the stream.
+ * Errors: PIC_EINVAL (config), PIC_ECAPACITY (init larger than capacity),
+ * PIC_EHIP, PIC_ENOCONV. */
+pic_status pic_init(const pic_config *cfg, void *workspace_dev, int64_t workspace_bytes,
+                    void *stream, const pic_species_host *init, pic_handle **out);
+
+/* Advance nsteps timesteps (gather, push, walls and emission, collisions,
+ * new particles, deposit, field solve, circuit).  Returns after the last
+ * step's work is enqueued; synchronizes only where the field solve checks
+ * its residual.  Errors: PIC_ECAPACITY, PIC_ENOCONV, PIC_EHIP. */
+pic_status pic_step(pic_handle *h, int32_t nsteps);
+
+/* Standalone field solve on the handle's grid: K phi = q with the cathode
+ * nodes at v_cathode and the other Dirichlet nodes at 0.  phi_dev holds the
+ * initial guess on entry (its Dirichlet entries are overwritten) and the
+ * solution on exit; q_dev is node charge (C), FP64.  Uses the handle's
+ * preconditioner mode, tolerance and iteration cap.  Synchronizes.
+ * Errors: PIC_ENOCONV (stats still filled), PIC_EHIP. */
+pic_status pic_poisson(pic_handle *h, const double *q_dev, double v_cathode, double *phi_dev,
+                       pic_poisson_stats *stats);
+
+/* FP64 diagnostics of the current state.  Synchronizes. */
+pic_status pic_diag(pic_handle *h, pic_diag_out *out);
+
+/* Device views (synchronize to read counts). */
+pic_status pic_particles(pic_handle *h, int32_t species, pic_particle_view *out);
+pic_status pic_fields(pic_handle *h, pic_field_view *out);
+
+/* Replace phi (host FP64 node array) and rebuild the gather fields; with
+ * field_solve = 0 it stays fixed.  Synchronizes. */
+pic_status pic_set_phi(pic_handle *h, const double *phi);
+
+/* Cell-sort and compact both species now (drops absorbed slots). */
+pic_status pic_compact(pic_handle *h);
+
+/* Scalar state (step, circuit, id counters, counts) for checkpointing. */
+pic_status pic_get_state(const pic_handle *h, pic_scalar_state *out);
+pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in);
+
+/* Enable (1) or disable (0) per-phase HIP-event timing; pic_get_timers
+ * returns the sums since the last reset and resets when reset != 0. */
+pic_status pic_enable_timers(pic_handle *h, int32_t on);
+pic_status pic_get_timers(pic_handle *h, pic_timers *out, int32_t reset);
+
+/* Destroy the handle (does not free the caller's workspace). */
+pic_status pic_free(pic_handle *h);
+
+/* Message of the last error on h (or of the last failed pic_init if h is
+ * NULL).  Valid until the next call on the same handle. */
+const char *pic_last_error(const pic_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

@@ -1,0 +1,1023 @@
+// Host side of the libpic.so C ABI (include/pic.h): configuration checks,
+// workspace layout, set-up tables, and the per-step launch sequence.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "common.h"
+
+using namespace pic;
+
+namespace {
+
+std::string g_init_error;
+
+struct Buf {
+    int32_t *key;
+    void *fr, *fz, *vr, *vt, *vz;
+    uint32_t *id;
+};
+
+struct LevelShape {
+    int nr, nz;
+    double lr, lz;
+};
+
+}  // namespace
+
+struct pic_handle {
+    pic_config cfg;
+    std::string err;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    int64_t ws_bytes = 0;
+    int prec = PIC_F32;
+    size_t ts = 4;
+    Buf buf[2][2];
+    int cur[2] = {0, 0};
+    int64_t cap[2] = {0, 0};
+    void *node = nullptr;
+    void *q[2] = {nullptr, nullptr};
+    DevScalars *sc = nullptr;
+    void *child = nullptr;
+    int32_t child_cap = 0;
+    void *nu = nullptr;
+    FieldDev f;
+    int32_t *hist = nullptr, *block_sums = nullptr;
+    double *diag_partials = nullptr;
+    int diag_blocks = 0;
+    unsigned long long *live = nullptr;
+    std::vector<LevelShape> levels;
+    double numax = 0.0;
+    unsigned long long t_null = 0, t_see = 0;
+    int64_t host_count[2] = {0, 0};
+    int steps_since_sort = 0;
+    pic_poisson_stats last = {};
+    bool timers_on = false;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> free_events;
+    pic_timers timers = {};
+};
+
+namespace {
+
+pic_status fail(pic_handle *h, pic_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    else g_init_error = buf;
+    return st;
+}
+
+#define HIPCHECK(h, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((h), PIC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+// Multigrid level shapes: halve while both cell counts are even and the
+// smaller one exceeds 4.
+std::vector<LevelShape> mg_shapes(const pic_config &c)
+{
+    std::vector<LevelShape> v;
+    LevelShape s{c.nr, c.nz, c.lr, c.lz};
+    v.push_back(s);
+    while ((int)v.size() < MAX_LEVELS && (s.nr % 2 == 0) && (s.nz % 2 == 0) &&
+           std::min(s.nr, s.nz) > 4) {
+        s.nr /= 2;
+        s.nz /= 2;
+        v.push_back(s);
+    }
+    return v;
+}
+
+int coarse_unknowns(const pic_config &c, const LevelShape &s)
+{
+    int n = 0;
+    for (int j = 0; j <= s.nz; ++j)
+        for (int i = 0; i <= s.nr; ++i)
+            if (host_node_kind(s.nr, s.nz, c.lr, c.cathode_rmax, i, j) == 0) ++n;
+    return n;
+}
+
+pic_status validate(const pic_config *c, pic_handle *h)
+{
+    if (!c) return fail(h, PIC_EINVAL, "config is NULL");
+    if (c->nr < 2 || c->nz < 2 || c->nr > 65535 || c->nz > 32767)
+        return fail(h, PIC_EINVAL, "grid %d x %d outside [2, 65535] x [2, 32767]", c->nr, c->nz);
+    if (!(c->lr > 0) || !(c->lz > 0) || !(c->dt > 0))
+        return fail(h, PIC_EINVAL, "lr, lz and dt must be positive");
+    if (c->scheme != PIC_MC && c->scheme != PIC_EC) return fail(h, PIC_EINVAL, "bad scheme");
+    if (c->precision != PIC_F32 && c->precision != PIC_F64)
+        return fail(h, PIC_EINVAL, "bad precision");
+    if (c->circuit != PIC_FIXED_V && c->circuit != PIC_RESISTOR)
+        return fail(h, PIC_EINVAL, "bad circuit");
+    if (c->circuit == PIC_RESISTOR && !(c->r_ext > 0))
+        return fail(h, PIC_EINVAL, "r_ext must be positive");
+    if (!(c->cathode_rmax >= 0) || c->cathode_rmax > c->lr)
+        return fail(h, PIC_EINVAL, "cathode_rmax outside [0, lr]");
+    if (!c->sigma || c->n_table < 2 || !(c->de_table > 0))
+        return fail(h, PIC_EINVAL, "cross-section table missing or too short");
+    if (!c->b_r || !c->b_z) return fail(h, PIC_EINVAL, "magnetic field arrays missing");
+    for (int s = 0; s < 2; ++s) {
+        if (!(c->m[s] > 0) || !(c->w[s] > 0))
+            return fail(h, PIC_EINVAL, "species %d: mass and weight must be positive", s);
+        if (c->capacity[s] < 0 || c->capacity[s] > (int64_t)2000000000)
+            return fail(h, PIC_EINVAL, "species %d: capacity out of range", s);
+    }
+    if (c->sort_every < 1) return fail(h, PIC_EINVAL, "sort_every must be >= 1");
+    if (!(c->poisson_rtol > 0) || c->poisson_maxit < 1 || c->poisson_maxit > MAX_PCG)
+        return fail(h, PIC_EINVAL, "poisson_rtol > 0 and 1 <= poisson_maxit <= %d required", MAX_PCG);
+    if (c->poisson_mode != PIC_MGCG)
+        return fail(h, PIC_EINVAL, "poisson_mode: only PIC_MGCG is available in this build");
+    if (c->gamma_i < 0 || c->p_gas < 0 || !(c->t_gas > 0))
+        return fail(h, PIC_EINVAL, "gamma_i, p_gas >= 0 and t_gas > 0 required");
+    for (int k = 0; k < 3; ++k)
+        if (c->wall_bc[k] != PIC_ABSORB && c->wall_bc[k] != PIC_REFLECT)
+            return fail(h, PIC_EINVAL, "bad wall_bc[%d]", k);
+    auto lv = mg_shapes(*c);
+    const int cu = coarse_unknowns(*c, lv.back());
+    if (cu > 2048)
+        return fail(h, PIC_EINVAL,
+                    "grid %d x %d does not coarsen below 2048 unknowns (coarsest %d x %d)", c->nr,
+                    c->nz, lv.back().nr, lv.back().nz);
+    return PIC_OK;
+}
+
+// Workspace layout.  With base == nullptr only the size is computed.
+struct Carver {
+    char *base;
+    int64_t off = 0;
+    template <typename P>
+    P *take(int64_t bytes)
+    {
+        off = (off + 255) & ~(int64_t)255;
+        P *p = base ? (P *)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+int64_t layout(const pic_config &c, char *base, pic_handle *h)
+{
+    Carver cv{base};
+    const size_t ts = (c.precision == PIC_F64) ? 8 : 4;
+    const int64_t nodes = (int64_t)(c.nr + 1) * (c.nz + 1);
+    const int64_t cap0 = c.capacity[0], cap1 = c.capacity[1];
+    const int32_t child_cap = (int32_t)std::max<int64_t>(1 << 16, (cap0 + cap1) / 64);
+    DevScalars *sc = cv.take<DevScalars>(sizeof(DevScalars));
+    Buf bufs[2][2];
+    for (int s = 0; s < 2; ++s) {
+        const int64_t cap = s ? cap1 : cap0;
+        for (int b = 0; b < 2; ++b) {
+            Buf &B = bufs[s][b];
+            B.key = cv.take<int32_t>(cap * 4);
+            B.fr = cv.take<char>(cap * ts);
+            B.fz = cv.take<char>(cap * ts);
+            B.vr = cv.take<char>(cap * ts);
+            B.vt = cv.take<char>(cap * ts);
+            B.vz = cv.take<char>(cap * ts);
+            B.id = cv.take<uint32_t>(cap * 4);
+        }
+    }
+    void *node = cv.take<char>(nodes * 4 * ts);
+    void *q0 = cv.take<char>(nodes * ts);
+    void *q1 = cv.take<char>(nodes * ts);
+    const size_t child_bytes = (ts == 8) ? sizeof(Child<double>) : sizeof(Child<float>);
+    void *child = cv.take<char>((int64_t)child_cap * child_bytes);
+    void *nu = cv.take<char>((int64_t)3 * c.n_table * ts);
+    FieldDev f;
+    memset(&f, 0, sizeof(f));
+    f.nr = c.nr;
+    f.nz = c.nz;
+    f.dr = c.lr / c.nr;
+    f.dz = c.lz / c.nz;
+    f.ce64 = cv.take<double>(nodes * 8);
+    f.cn64 = cv.take<double>(nodes * 8);
+    f.kind = cv.take<uint8_t>(nodes);
+    f.phi = cv.take<double>(nodes * 8);
+    f.phi0 = cv.take<double>(nodes * 8);
+    f.phi_l = cv.take<double>(nodes * 8);
+    f.r64 = cv.take<double>(nodes * 8);
+    f.b_r = cv.take<double>(nodes * 8);
+    f.b_z = cv.take<double>(nodes * 8);
+    f.vdep = cv.take<double>(nodes * 8);
+    f.e32 = cv.take<float>(nodes * 4);
+    f.r32 = cv.take<float>(nodes * 4);
+    f.z32 = cv.take<float>(nodes * 4);
+    f.p32 = cv.take<float>(nodes * 4);
+    f.q32 = cv.take<float>(nodes * 4);
+    auto shapes = mg_shapes(c);
+    f.nlevels = (int)shapes.size();
+    for (int l = 0; l < f.nlevels; ++l) {
+        const int64_t nl = (int64_t)(shapes[l].nr + 1) * (shapes[l].nz + 1);
+        Level &L = f.lv[l];
+        L.nr = shapes[l].nr;
+        L.nz = shapes[l].nz;
+        L.ce = cv.take<float>(nl * 4);
+        L.cn = cv.take<float>(nl * 4);
+        L.dinv = cv.take<float>(nl * 4);
+        if (l == 0) {
+            L.x = f.z32;
+            L.b = f.r32;
+        } else {
+            L.x = cv.take<float>(nl * 4);
+            L.b = cv.take<float>(nl * 4);
+        }
+    }
+    const int cu = coarse_unknowns(c, shapes.back());
+    f.coarse_n = cu;
+    f.coarse_inv = cv.take<float>((int64_t)cu * cu * 4);
+    f.coarse_map = cv.take<int32_t>((int64_t)cu * 4);
+    const int32_t nbins = c.nr * c.nz;
+    int32_t *hist = cv.take<int32_t>((int64_t)nbins * 4);
+    int32_t *bsums = cv.take<int32_t>((int64_t)((nbins + 1023) / 1024) * 4);
+    const int dblocks = 256;
+    double *dpart = cv.take<double>((int64_t)dblocks * 6 * 8);
+    unsigned long long *live = cv.take<unsigned long long>(2 * 8);
+    if (h) {
+        h->sc = sc;
+        for (int s = 0; s < 2; ++s)
+            for (int b = 0; b < 2; ++b) h->buf[s][b] = bufs[s][b];
+        h->node = node;
+        h->q[0] = q0;
+        h->q[1] = q1;
+        h->child = child;
+        h->child_cap = child_cap;
+        h->nu = nu;
+        h->f = f;
+        h->hist = hist;
+        h->block_sums = bsums;
+        h->diag_partials = dpart;
+        h->diag_blocks = dblocks;
+        h->live = live;
+        h->levels = shapes;
+    }
+    return cv.off + 256;
+}
+
+template <typename T>
+SpeciesDev<T> species_dev(const Buf &b)
+{
+    return SpeciesDev<T>{b.key, (T *)b.fr, (T *)b.fz, (T *)b.vr, (T *)b.vt, (T *)b.vz, b.id};
+}
+
+// ---- timers
+void timer_begin(pic_handle *h, hipEvent_t *a)
+{
+    if (!h->timers_on) return;
+    hipEvent_t e0, e1;
+    if (!h->free_events.empty()) {
+        e0 = h->free_events.back().first;
+        e1 = h->free_events.back().second;
+        h->free_events.pop_back();
+    } else {
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+    }
+    (void)hipEventRecord(e0, h->stream);
+    a[0] = e0;
+    a[1] = e1;
+}
+
+void timer_end(pic_handle *h, int phase, hipEvent_t *a)
+{
+    if (!h->timers_on) return;
+    (void)hipEventRecord(a[1], h->stream);
+    h->pending.emplace_back(phase, a[0], a[1]);
+}
+
+void timers_collect(pic_handle *h)
+{
+    for (auto &t : h->pending) {
+        hipEvent_t a = std::get<1>(t), b = std::get<2>(t);
+        (void)hipEventSynchronize(b);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        switch (std::get<0>(t)) {
+            case 0: h->timers.push_ms += ms; h->timers.push_launches++; break;
+            case 1: h->timers.children_ms += ms; break;
+            case 2: h->timers.sort_ms += ms; h->timers.sort_launches++; break;
+            case 3: h->timers.poisson_ms += ms; h->timers.poisson_solves++; break;
+            case 4: h->timers.circuit_ms += ms; break;
+            case 5: h->timers.field_ms += ms; break;
+        }
+        h->free_events.emplace_back(a, b);
+    }
+    h->pending.clear();
+}
+
+// ---- set-up of the multigrid hierarchy and the FP64 operator
+pic_status setup_field(pic_handle *h)
+{
+    const pic_config &c = h->cfg;
+    const int64_t nodes = (int64_t)(c.nr + 1) * (c.nz + 1);
+    std::vector<double> ce(nodes), cn(nodes), tmp(nodes);
+    std::vector<uint8_t> kind(nodes);
+    host_couplings(c.nr, c.nz, c.lr, c.lz, eps0(), ce.data(), cn.data());
+    for (int j = 0; j <= c.nz; ++j)
+        for (int i = 0; i <= c.nr; ++i)
+            kind[(int64_t)j * (c.nr + 1) + i] =
+                (uint8_t)host_node_kind(c.nr, c.nz, c.lr, c.cathode_rmax, i, j);
+    HIPCHECK(h, hipMemcpy((void *)h->f.ce64, ce.data(), nodes * 8, hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpy((void *)h->f.cn64, cn.data(), nodes * 8, hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpy((void *)h->f.kind, kind.data(), nodes, hipMemcpyHostToDevice));
+    host_node_volumes(c.nr, c.nz, c.lr, c.lz, tmp.data());
+    HIPCHECK(h, hipMemcpy((void *)h->f.vdep, tmp.data(), nodes * 8, hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpy((void *)h->f.b_r, c.b_r, nodes * 8, hipMemcpyHostToDevice));
+    HIPCHECK(h, hipMemcpy((void *)h->f.b_z, c.b_z, nodes * 8, hipMemcpyHostToDevice));
+
+    for (int l = 0; l < h->f.nlevels; ++l) {
+        const LevelShape &s = h->levels[l];
+        const int64_t nl = (int64_t)(s.nr + 1) * (s.nz + 1);
+        std::vector<double> a(nl), b(nl);
+        host_couplings(s.nr, s.nz, s.lr, s.lz, 1.0, a.data(), b.data());
+        std::vector<float> fa(nl), fb(nl), fd(nl);
+        for (int j = 0; j <= s.nz; ++j)
+            for (int i = 0; i <= s.nr; ++i) {
+                const int64_t n = (int64_t)j * (s.nr + 1) + i;
+                fa[n] = (float)a[n];
+                fb[n] = (float)b[n];
+                const int k = host_node_kind(s.nr, s.nz, c.lr, c.cathode_rmax, i, j);
+                double d = 0.0;
+                if (i < s.nr) d += a[n];
+                if (i > 0) d += a[n - 1];
+                if (j < s.nz) d += b[n];
+                if (j > 0) d += b[n - (s.nr + 1)];
+                fd[n] = (k == 0) ? (float)(1.0 / d) : 0.0f;
+            }
+        const Level &L = h->f.lv[l];
+        HIPCHECK(h, hipMemcpy(L.ce, fa.data(), nl * 4, hipMemcpyHostToDevice));
+        HIPCHECK(h, hipMemcpy(L.cn, fb.data(), nl * 4, hipMemcpyHostToDevice));
+        HIPCHECK(h, hipMemcpy(L.dinv, fd.data(), nl * 4, hipMemcpyHostToDevice));
+        launch_zero(L.x, nl * 4, h->stream);
+        launch_zero(L.b, nl * 4, h->stream);
+        if (l == h->f.nlevels - 1) {
+            // dense inverse of the coarsest operator on its unknowns
+            std::vector<int32_t> map;
+            std::vector<int> idx(nl, -1);
+            for (int64_t n = 0; n < nl; ++n)
+                if (fd[n] != 0.0f) {
+                    idx[n] = (int)map.size();
+                    map.push_back((int32_t)n);
+                }
+            const int m = (int)map.size();
+            std::vector<double> A((size_t)m * m, 0.0);
+            const int ld = s.nr + 1;
+            for (int u = 0; u < m; ++u) {
+                const int64_t n = map[u];
+                const int j = (int)(n / ld), i = (int)(n % ld);
+                double d = 0.0;
+                auto add = [&](int64_t nb, double cpl) {
+                    d += cpl;
+                    if (idx[nb] >= 0) A[(size_t)u * m + idx[nb]] -= cpl;
+                };
+                if (i < s.nr) add(n + 1, a[n]);
+                if (i > 0) add(n - 1, a[n - 1]);
+                if (j < s.nz) add(n + ld, b[n]);
+                if (j > 0) add(n - ld, b[n - ld]);
+                A[(size_t)u * m + u] += d;
+            }
+            if (m > 0 && host_dense_inverse(m, A.data()) != 0)
+                return fail(h, PIC_EINVAL, "coarsest operator is singular");
+            std::vector<float> Af(A.begin(), A.end());
+            if (m > 0) {
+                HIPCHECK(h, hipMemcpy((void *)h->f.coarse_inv, Af.data(), (size_t)m * m * 4,
+                                      hipMemcpyHostToDevice));
+                HIPCHECK(h, hipMemcpy((void *)h->f.coarse_map, map.data(), (size_t)m * 4,
+                                      hipMemcpyHostToDevice));
+            }
+            h->f.coarse_n = m;
+        }
+    }
+    launch_zero(h->f.e32, nodes * 4, h->stream);
+    launch_zero(h->f.p32, nodes * 4, h->stream);
+    launch_zero(h->f.q32, nodes * 4, h->stream);
+    return PIC_OK;
+}
+
+// ---- field solve: FP64 iterative refinement around an FP32 MG-PCG
+template <typename Q>
+pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_cathode,
+                 pic_poisson_stats *st)
+{
+    hipStream_t s = h->stream;
+    const FieldDev &f = h->f;
+    const double rtol = h->cfg.poisson_rtol;
+    const int maxit = h->cfg.poisson_maxit;
+    const double e0 = eps0();
+    pic_poisson_stats S = {};
+    launch_set_dirichlet(f, phi, v_cathode, s);
+    const int max_outer = 12;
+    for (int outer = 0;; ++outer) {
+        launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
+        double nrm[2];
+        HIPCHECK(h, hipMemcpyAsync(nrm, &h->sc->res_rr, 16, hipMemcpyDeviceToHost, s));
+        HIPCHECK(h, hipStreamSynchronize(s));
+        const double rr = nrm[0], bb = nrm[1];
+        if (!std::isfinite(rr) || !std::isfinite(bb)) {
+            S.rel_res = NAN;
+            h->last = S;
+            if (st) *st = S;
+            return fail(h, PIC_ENAN, "non-finite residual in the field solve");
+        }
+        if (bb == 0.0) {
+            launch_zero_unknowns(f, phi, s);
+            S.rel_res = 0.0;
+            S.converged = 1;
+            break;
+        }
+        S.rel_res = std::sqrt(rr / bb);
+        if (S.rel_res <= rtol) {
+            S.converged = 1;
+            break;
+        }
+        if (outer >= max_outer || S.iterations >= maxit) break;
+        S.outer++;
+        const double rn = std::sqrt(rr);
+        launch_cast_scale(f, 1.0 / rn, s);
+        // inner FP32 preconditioned CG on K_uu e = r / ||r||
+        const double inner_tol = std::max(0.3 * rtol / S.rel_res, 2e-6);
+        launch_zero(h->sc->pcg_rz, sizeof(double) * 3 * (MAX_PCG + 2), s);
+        launch_vcycle(f, s);
+        launch_pcg_dot_rz(f, h->sc, 0, s);
+        launch_copy_f32(f.p32, f.z32, (int64_t)(f.nr + 1) * (f.nz + 1), s);
+        int k = 0;
+        for (; k < MAX_PCG && S.iterations < maxit; ++k) {
+            launch_pcg_matvec_dot(f, h->sc, k, s);
+            launch_pcg_update(f, h->sc, k, s);
+            S.iterations++;
+            double rrk;
+            HIPCHECK(h, hipMemcpyAsync(&rrk, &h->sc->pcg_rr[k], 8, hipMemcpyDeviceToHost, s));
+            HIPCHECK(h, hipStreamSynchronize(s));
+            if (!(std::sqrt(rrk) > inner_tol)) break;
+            launch_vcycle(f, s);
+            launch_pcg_dot_rz(f, h->sc, k + 1, s);
+            launch_pcg_direction(f, h->sc, k, s);
+        }
+        launch_update64(f, phi, rn / e0, s);
+    }
+    h->last = S;
+    if (st) *st = S;
+    if (!S.converged)
+        return fail(h, PIC_ENOCONV, "field solve stopped at relative residual %.3e (target %.1e)",
+                    S.rel_res, rtol);
+    return PIC_OK;
+}
+
+template <typename T>
+PushParams<T> push_params(pic_handle *h, int deposit_only)
+{
+    const pic_config &c = h->cfg;
+    PushParams<T> P;
+    memset(&P, 0, sizeof(P));
+    for (int s = 0; s < 2; ++s) {
+        P.sp[s] = species_dev<T>(h->buf[s][h->cur[s]]);
+        P.cap[s] = h->cap[s];
+        P.q[s] = (T *)h->q[s];
+        P.hqm[s] = (T)(0.5 * c.q[s] / c.m[s] * c.dt);
+        P.qw[s] = (T)(c.q[s] * c.w[s]);
+        P.qw64[s] = c.q[s] * c.w[s];
+        P.mw[s] = c.m[s] * c.w[s];
+    }
+    P.node = (const typename Vec4<T>::type *)h->node;
+    P.sc = h->sc;
+    P.child = (Child<T> *)h->child;
+    P.child_cap = h->child_cap;
+    P.nu = (const T *)h->nu;
+    P.n_table = c.n_table;
+    P.inv_de = (T)(1.0 / c.de_table);
+    P.numax = (T)h->numax;
+    P.t_null = h->t_null;
+    P.t_see = h->t_see;
+    P.nr = c.nr;
+    P.nz = c.nz;
+    P.dr = (T)(c.lr / c.nr);
+    P.dz = (T)(c.lz / c.nz);
+    P.inv_dr = (T)(c.nr / c.lr);
+    P.inv_dz = (T)(c.nz / c.lz);
+    P.dt = (T)c.dt;
+    P.cathode_rmax = (T)c.cathode_rmax;
+    const double qe = 1.602176634e-19;
+    P.e_of_v2 = (T)(0.5 * c.m[0] / qe);
+    P.v2_of_e = (T)(2.0 * qe / c.m[0]);
+    P.two_m_over_M = (T)(2.0 * c.m[0] / c.m[1]);
+    P.e_exc = (T)c.e_exc;
+    P.e_iz = (T)c.e_iz;
+    P.sig_ion = (T)std::sqrt(1.380649e-23 * c.t_gas / c.m[1]);
+    for (int k = 0; k < 3; ++k) P.wall_bc[k] = c.wall_bc[k];
+    P.frozen_ions = c.frozen_ions;
+    P.mcc_on = c.mcc_on;
+    P.see_on = c.see_on;
+    P.deposit_only = deposit_only;
+    P.key0 = (uint32_t)(c.seed & 0xffffffffu);
+    P.key1 = (uint32_t)(c.seed >> 32);
+    P.run = c.run;
+    return P;
+}
+
+// Block split of the fused kernel between the species (electrons weigh a
+// little more: they also collide).
+void push_grid(pic_handle *h, int *nblk_e, int *nblocks)
+{
+    const double ne = (double)std::max<int64_t>(h->host_count[0], 1);
+    const double ni = (double)std::max<int64_t>(h->host_count[1], 1);
+    const int total = 2048;
+    int be = (int)std::lround(total * 1.3 * ne / (1.3 * ne + ni));
+    be = std::max(1, std::min(total - 1, be));
+    int bi = total - be;
+    be = std::max(1, (int)std::min<int64_t>(be, (h->host_count[0] + PUSH_CHUNK - 1) / PUSH_CHUNK + 1));
+    bi = std::max(1, (int)std::min<int64_t>(bi, (h->host_count[1] + PUSH_CHUNK - 1) / PUSH_CHUNK + 1));
+    *nblk_e = be;
+    *nblocks = be + bi;
+}
+
+template <typename T>
+void launch_push_h(pic_handle *h, int deposit_only)
+{
+    PushParams<T> P = push_params<T>(h, deposit_only);
+    int be, nb;
+    push_grid(h, &be, &nb);
+    P.nblk_e = be;
+    launch_push<T>(P, h->cfg.scheme, nb, h->stream);
+}
+
+template <typename T>
+void sort_species(pic_handle *h, int s)
+{
+    const int from = h->cur[s], to = 1 - from;
+    launch_sort<T>(species_dev<T>(h->buf[s][from]), species_dev<T>(h->buf[s][to]), h->sc, s,
+                   h->hist, h->block_sums, h->cfg.nr, h->cfg.nz, h->cap[s], h->stream);
+    h->cur[s] = to;
+}
+
+template <typename T>
+void sort_all(pic_handle *h)
+{
+    hipEvent_t ev[2];
+    timer_begin(h, ev);
+    sort_species<T>(h, 0);
+    sort_species<T>(h, 1);
+    timer_end(h, 2, ev);
+    h->steps_since_sort = 0;
+}
+
+pic_status read_scalars(pic_handle *h, DevScalars *out)
+{
+    HIPCHECK(h, hipMemcpyAsync(out, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    h->host_count[0] = out->count[0];
+    h->host_count[1] = out->count[1];
+    return PIC_OK;
+}
+
+pic_status check_flags(pic_handle *h)
+{
+    int32_t flags = 0;
+    int64_t counts[2];
+    HIPCHECK(h, hipMemcpyAsync(&flags, &h->sc->flags, 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(counts, h->sc->count, 16, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    h->host_count[0] = counts[0];
+    h->host_count[1] = counts[1];
+    if (flags & (FLAG_CAPACITY | FLAG_CHILD_OVERFLOW))
+        return fail(h, PIC_ECAPACITY, "particle capacity exceeded (flags %d)", flags);
+    return PIC_OK;
+}
+
+template <typename T>
+pic_status field_update(pic_handle *h)
+{
+    const pic_config &c = h->cfg;
+    hipEvent_t ev[2];
+    timer_begin(h, ev);
+    pic_status st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr);
+    timer_end(h, 3, ev);
+    if (st != PIC_OK) return st;
+    timer_begin(h, ev);
+    launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, c.circuit, c.v_fixed,
+                      c.v_ext, c.r_ext, c.dt, c.extra_current * c.dt, h->stream);
+    timer_end(h, 4, ev);
+    timer_begin(h, ev);
+    launch_field_prep<T>(h->f, (typename Vec4<T>::type *)h->node, h->sc, c.scheme, 0, h->stream);
+    timer_end(h, 5, ev);
+    return PIC_OK;
+}
+
+template <typename T>
+pic_status step_one(pic_handle *h)
+{
+    const pic_config &c = h->cfg;
+    if (h->steps_since_sort >= c.sort_every) sort_all<T>(h);
+    const int64_t nodes = (int64_t)(c.nr + 1) * (c.nz + 1);
+    launch_begin_step(h->sc, h->q[0], h->q[1], nodes, (int)sizeof(T), h->stream);
+    hipEvent_t ev[2];
+    timer_begin(h, ev);
+    launch_push_h<T>(h, 0);
+    timer_end(h, 0, ev);
+    timer_begin(h, ev);
+    ChildParams<T> C;
+    for (int s = 0; s < 2; ++s) {
+        C.sp[s] = species_dev<T>(h->buf[s][h->cur[s]]);
+        C.cap[s] = h->cap[s];
+        C.q[s] = (T *)h->q[s];
+        C.qw[s] = (T)(c.q[s] * c.w[s]);
+    }
+    C.sc = h->sc;
+    C.child = (const Child<T> *)h->child;
+    C.child_cap = h->child_cap;
+    C.nr = c.nr;
+    launch_children<T>(C, h->stream);
+    launch_finalize_step(h->sc, h->cap, h->stream);
+    timer_end(h, 1, ev);
+    h->steps_since_sort++;
+    if (c.field_solve) {
+        pic_status st = field_update<T>(h);
+        if (st != PIC_OK) return st;
+    } else {
+        // keep phi; add the synthetic current to the tally like the circuit does
+        if (c.extra_current != 0.0) {
+            launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, PIC_FIXED_V,
+                              0.0, 0.0, 1.0, c.dt, c.extra_current * c.dt, h->stream);
+        }
+    }
+    return check_flags(h);
+}
+
+template <typename T>
+pic_status init_typed(pic_handle *h, const pic_species_host *init)
+{
+    const pic_config &c = h->cfg;
+    hipStream_t s = h->stream;
+    // collision tables
+    std::vector<double> nu((size_t)3 * c.n_table);
+    h->numax = host_nu_tables(c, nu.data(), &h->t_null);
+    h->t_see = host_see_threshold(c);
+    std::vector<T> nut(nu.begin(), nu.end());
+    HIPCHECK(h, hipMemcpy(h->nu, nut.data(), nut.size() * sizeof(T), hipMemcpyHostToDevice));
+    pic_status st = setup_field(h);
+    if (st != PIC_OK) return st;
+    // scalars
+    launch_zero(h->sc, sizeof(DevScalars), s);
+    HIPCHECK(h, hipStreamSynchronize(s));
+    DevScalars sc0;
+    memset(&sc0, 0, sizeof(sc0));
+    for (int sp = 0; sp < 2; ++sp) {
+        const int64_t n = init ? init[sp].n : 0;
+        if (n > h->cap[sp])
+            return fail(h, PIC_ECAPACITY, "species %d: %lld initial particles > capacity %lld", sp,
+                        (long long)n, (long long)h->cap[sp]);
+        uint32_t mx = 0;
+        if (n > 0) {
+            const pic_species_host &I = init[sp];
+            if (!I.r || !I.z || !I.vr || !I.vt || !I.vz || !I.id)
+                return fail(h, PIC_EINVAL, "species %d: initial arrays missing", sp);
+            for (int64_t k = 0; k < n; ++k) {
+                if (!(I.r[k] >= 0.0 && I.r[k] < c.lr && I.z[k] >= 0.0 && I.z[k] < c.lz))
+                    return fail(h, PIC_EINVAL, "species %d particle %lld outside the domain", sp,
+                                (long long)k);
+                mx = std::max(mx, I.id[k] + 1u);
+            }
+            // upload in chunks through the second buffer
+            const Buf &stage = h->buf[sp][1];
+            const int64_t stage_bytes = h->cap[sp] * (8 + 5 * (int64_t)sizeof(T));
+            const int64_t chunk = std::max<int64_t>(1, stage_bytes / 48);
+            double *dr = (double *)stage.key;
+            for (int64_t o = 0; o < n; o += chunk) {
+                const int64_t m = std::min(chunk, n - o);
+                double *a0 = dr, *a1 = dr + m, *a2 = dr + 2 * m, *a3 = dr + 3 * m, *a4 = dr + 4 * m;
+                uint32_t *ai = (uint32_t *)(dr + 5 * m);
+                HIPCHECK(h, hipMemcpy(a0, I.r + o, m * 8, hipMemcpyHostToDevice));
+                HIPCHECK(h, hipMemcpy(a1, I.z + o, m * 8, hipMemcpyHostToDevice));
+                HIPCHECK(h, hipMemcpy(a2, I.vr + o, m * 8, hipMemcpyHostToDevice));
+                HIPCHECK(h, hipMemcpy(a3, I.vt + o, m * 8, hipMemcpyHostToDevice));
+                HIPCHECK(h, hipMemcpy(a4, I.vz + o, m * 8, hipMemcpyHostToDevice));
+                HIPCHECK(h, hipMemcpy(ai, I.id + o, m * 4, hipMemcpyHostToDevice));
+                launch_load<T>(species_dev<T>(h->buf[sp][0]), o, a0, a1, a2, a3, a4, ai, m, c.nr,
+                               c.nz, c.lr / c.nr, c.lz / c.nz, s);
+                HIPCHECK(h, hipStreamSynchronize(s));
+            }
+        }
+        sc0.count[sp] = n;
+        sc0.next_id[sp] = mx;
+        h->host_count[sp] = n;
+    }
+    sc0.cap_c = 0.0;
+    HIPCHECK(h, hipMemcpy(h->sc, &sc0, sizeof(DevScalars), hipMemcpyHostToDevice));
+    h->cur[0] = h->cur[1] = 0;
+    sort_all<T>(h);
+    const int64_t nodes = (int64_t)(c.nr + 1) * (c.nz + 1);
+    // phi_L: cathode at 1 V, no charge
+    launch_begin_step(h->sc, h->q[0], h->q[1], nodes, (int)sizeof(T), s);
+    launch_zero(h->f.phi_l, nodes * 8, s);
+    st = solve<T>(h, h->f.phi_l, (const T *)h->q[0], (const T *)h->q[1], 1.0, nullptr);
+    if (st != PIC_OK) return st;
+    // capacitance C = sum over cathode nodes of (K phi_L)
+    {
+        std::vector<double> pl(nodes), ce(nodes), cn(nodes);
+        HIPCHECK(h, hipMemcpy(pl.data(), h->f.phi_l, nodes * 8, hipMemcpyDeviceToHost));
+        host_couplings(c.nr, c.nz, c.lr, c.lz, eps0(), ce.data(), cn.data());
+        double cap = 0.0;
+        const int ld = c.nr + 1;
+        for (int i = 0; i <= c.nr; ++i) {
+            if (host_node_kind(c.nr, c.nz, c.lr, c.cathode_rmax, i, 0) != 1) continue;
+            double fl = 0.0;
+            if (i < c.nr) fl += ce[i] * (pl[i] - pl[i + 1]);
+            if (i > 0) fl += ce[i - 1] * (pl[i] - pl[i - 1]);
+            fl += cn[i] * (pl[i] - pl[i + ld]);
+            cap += fl;
+        }
+        HIPCHECK(h, hipMemcpy(&h->sc->cap_c, &cap, 8, hipMemcpyHostToDevice));
+    }
+    // initial deposit, phi0, circuit state at V0, gather fields
+    launch_begin_step(h->sc, h->q[0], h->q[1], nodes, (int)sizeof(T), s);
+    launch_push_h<T>(h, 1);
+    launch_zero(h->f.phi0, nodes * 8, s);
+    if (c.field_solve) {
+        st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr);
+        if (st != PIC_OK) return st;
+    }
+    const double v0 = (c.circuit == PIC_RESISTOR) ? c.v_ext : c.v_fixed;
+    launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, PIC_FIXED_V, v0, 0.0,
+                      1.0, c.dt, 0.0, s);
+    launch_field_prep<T>(h->f, (typename Vec4<T>::type *)h->node, h->sc, c.scheme, 0, s);
+    // clear the tallies of the deposit pass
+    launch_begin_step(h->sc, h->q[0], h->q[1], 0, (int)sizeof(T), s);
+    HIPCHECK(h, hipStreamSynchronize(s));
+    h->steps_since_sort = 0;
+    return check_flags(h);
+}
+
+}  // namespace
+
+extern "C" {
+
+pic_status pic_query_workspace(const pic_config *cfg, int64_t *bytes)
+{
+    pic_status st = validate(cfg, nullptr);
+    if (st != PIC_OK) return st;
+    if (!bytes) return fail(nullptr, PIC_EINVAL, "bytes is NULL");
+    *bytes = layout(*cfg, nullptr, nullptr);
+    return PIC_OK;
+}
+
+pic_status pic_init(const pic_config *cfg, void *workspace_dev, int64_t workspace_bytes,
+                    void *stream, const pic_species_host *init, pic_handle **out)
+{
+    if (!out) return fail(nullptr, PIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    pic_status st = validate(cfg, nullptr);
+    if (st != PIC_OK) return st;
+    const int64_t need = layout(*cfg, nullptr, nullptr);
+    if (!workspace_dev || workspace_bytes < need)
+        return fail(nullptr, PIC_EINVAL, "workspace of %lld bytes < %lld needed",
+                    (long long)workspace_bytes, (long long)need);
+    if (((uintptr_t)workspace_dev & 255) != 0)
+        return fail(nullptr, PIC_EINVAL, "workspace must be 256-byte aligned");
+    pic_handle *h = new pic_handle();
+    h->cfg = *cfg;
+    h->stream = (hipStream_t)stream;
+    h->ws = (char *)workspace_dev;
+    h->ws_bytes = workspace_bytes;
+    h->prec = cfg->precision;
+    h->ts = (cfg->precision == PIC_F64) ? 8 : 4;
+    h->cap[0] = cfg->capacity[0];
+    h->cap[1] = cfg->capacity[1];
+    layout(*cfg, h->ws, h);
+    st = (h->prec == PIC_F64) ? init_typed<double>(h, init) : init_typed<float>(h, init);
+    // the host arrays of the config are not kept
+    h->cfg.sigma = nullptr;
+    h->cfg.b_r = h->cfg.b_z = nullptr;
+    if (st != PIC_OK) {
+        g_init_error = h->err;
+        delete h;
+        return st;
+    }
+    *out = h;
+    return PIC_OK;
+}
+
+pic_status pic_step(pic_handle *h, int32_t nsteps)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(h, PIC_EINVAL, "nsteps < 0");
+    for (int k = 0; k < nsteps; ++k) {
+        pic_status st = (h->prec == PIC_F64) ? step_one<double>(h) : step_one<float>(h);
+        if (st != PIC_OK) return st;
+    }
+    return PIC_OK;
+}
+
+pic_status pic_poisson(pic_handle *h, const double *q_dev, double v_cathode, double *phi_dev,
+                       pic_poisson_stats *stats)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (!q_dev || !phi_dev) return fail(h, PIC_EINVAL, "q_dev and phi_dev are required");
+    hipEvent_t ev[2];
+    timer_begin(h, ev);
+    pic_status st = solve<double>(h, phi_dev, q_dev, (const double *)nullptr, v_cathode, stats);
+    timer_end(h, 3, ev);
+    return st;
+}
+
+pic_status pic_diag(pic_handle *h, pic_diag_out *out)
+{
+    if (!h || !out) return fail(h, PIC_EINVAL, "NULL argument");
+    const pic_config &c = h->cfg;
+    memset(out, 0, sizeof(*out));
+    launch_zero(h->live, 16, h->stream);
+    for (int s = 0; s < 2; ++s)
+        launch_count_live(h->buf[s][h->cur[s]].key, h->sc, s, h->live + s, h->stream);
+    if (h->prec == PIC_F64)
+        launch_diag_grid<double>(h->f, (const double *)h->q[0], (const double *)h->q[1], c.q[0],
+                                 c.q[1], h->diag_partials, h->diag_blocks, h->stream);
+    else
+        launch_diag_grid<float>(h->f, (const float *)h->q[0], (const float *)h->q[1], c.q[0],
+                                c.q[1], h->diag_partials, h->diag_blocks, h->stream);
+    std::vector<double> part((size_t)h->diag_blocks * 6);
+    unsigned long long live[2];
+    HIPCHECK(h, hipMemcpyAsync(part.data(), h->diag_partials, part.size() * 8,
+                               hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipMemcpyAsync(live, h->live, 16, hipMemcpyDeviceToHost, h->stream));
+    DevScalars sc;
+    pic_status st = read_scalars(h, &sc);
+    if (st != PIC_OK) return st;
+    double s0 = 0, s1 = 0, m0 = -1e300, m1 = -1e300, mp = -1e300, w = 0;
+    for (int b = 0; b < h->diag_blocks; ++b) {
+        s0 += part[b * 6 + 0];
+        s1 += part[b * 6 + 1];
+        m0 = std::max(m0, part[b * 6 + 2]);
+        m1 = std::max(m1, part[b * 6 + 3]);
+        mp = std::max(mp, part[b * 6 + 4]);
+        w += part[b * 6 + 5];
+    }
+    out->step = sc.step;
+    out->time = sc.step * c.dt;
+    for (int s = 0; s < 2; ++s) {
+        out->count[s] = (int64_t)live[s];
+        out->q_expect[s] = c.q[s] * c.w[s] * (double)live[s];
+        out->ke[s] = sc.ke[s];
+        out->pz[s] = sc.pz[s];
+        for (int k = 0; k < 5; ++k) out->n_abs[s][k] = (int64_t)sc.n_abs[s][k];
+    }
+    out->q_dep[0] = s0;
+    out->q_dep[1] = s1;
+    out->n_peak[0] = m0;
+    out->n_peak[1] = m1;
+    out->phi_max = mp;
+    out->w_field = w;
+    out->dq_conv = sc.dq_conv;
+    out->i_cathode = sc.dq_conv / c.dt;
+    out->vc = sc.vc;
+    out->qc = sc.qc;
+    out->cap_c = sc.cap_c;
+    out->n_cand = (int64_t)sc.n_cand;
+    for (int k = 0; k < 3; ++k) out->n_coll[k] = (int64_t)sc.n_coll[k];
+    out->n_see = (int64_t)sc.n_see;
+    out->deposit_fallback = (int64_t)sc.deposit_fallback;
+    out->poisson = h->last;
+    out->flags = sc.flags;
+    if (!std::isfinite(w) || !std::isfinite(sc.ke[0]) || !std::isfinite(sc.ke[1]))
+        out->flags |= FLAG_NAN;
+    return PIC_OK;
+}
+
+pic_status pic_particles(pic_handle *h, int32_t species, pic_particle_view *out)
+{
+    if (!h || !out || species < 0 || species > 1) return fail(h, PIC_EINVAL, "bad argument");
+    int64_t cnt;
+    HIPCHECK(h, hipMemcpyAsync(&cnt, &h->sc->count[species], 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    const Buf &b = h->buf[species][h->cur[species]];
+    out->key_dev = b.key;
+    out->fr_dev = b.fr;
+    out->fz_dev = b.fz;
+    out->vr_dev = b.vr;
+    out->vt_dev = b.vt;
+    out->vz_dev = b.vz;
+    out->id_dev = b.id;
+    out->count = cnt;
+    out->capacity = h->cap[species];
+    out->precision = h->prec;
+    return PIC_OK;
+}
+
+pic_status pic_fields(pic_handle *h, pic_field_view *out)
+{
+    if (!h || !out) return fail(h, PIC_EINVAL, "bad argument");
+    out->phi_dev = h->f.phi;
+    out->phi0_dev = h->f.phi0;
+    out->phi_l_dev = h->f.phi_l;
+    out->q_dev[0] = h->q[0];
+    out->q_dev[1] = h->q[1];
+    out->nodes = (int64_t)(h->cfg.nr + 1) * (h->cfg.nz + 1);
+    out->q_precision = h->prec;
+    return PIC_OK;
+}
+
+pic_status pic_set_phi(pic_handle *h, const double *phi)
+{
+    if (!h || !phi) return fail(h, PIC_EINVAL, "bad argument");
+    const int64_t nodes = (int64_t)(h->cfg.nr + 1) * (h->cfg.nz + 1);
+    HIPCHECK(h, hipMemcpy(h->f.phi, phi, nodes * 8, hipMemcpyHostToDevice));
+    if (h->prec == PIC_F64)
+        launch_field_prep<double>(h->f, (double4 *)h->node, h->sc, h->cfg.scheme, 1, h->stream);
+    else
+        launch_field_prep<float>(h->f, (float4 *)h->node, h->sc, h->cfg.scheme, 1, h->stream);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return PIC_OK;
+}
+
+pic_status pic_compact(pic_handle *h)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (h->prec == PIC_F64) sort_all<double>(h);
+    else sort_all<float>(h);
+    return check_flags(h);
+}
+
+pic_status pic_get_state(const pic_handle *hc, pic_scalar_state *out)
+{
+    pic_handle *h = const_cast<pic_handle *>(hc);
+    if (!h || !out) return fail(h, PIC_EINVAL, "bad argument");
+    DevScalars sc;
+    pic_status st = read_scalars(h, &sc);
+    if (st != PIC_OK) return st;
+    out->step = sc.step;
+    out->vc = sc.vc;
+    out->qc = sc.qc;
+    out->next_id[0] = sc.next_id[0];
+    out->next_id[1] = sc.next_id[1];
+    out->count[0] = sc.count[0];
+    out->count[1] = sc.count[1];
+    return PIC_OK;
+}
+
+pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in)
+{
+    if (!h || !in) return fail(h, PIC_EINVAL, "bad argument");
+    for (int s = 0; s < 2; ++s)
+        if (in->count[s] < 0 || in->count[s] > h->cap[s])
+            return fail(h, PIC_EINVAL, "count out of range");
+    DevScalars sc;
+    pic_status st = read_scalars(h, &sc);
+    if (st != PIC_OK) return st;
+    sc.step = in->step;
+    sc.vc = in->vc;
+    sc.qc = in->qc;
+    sc.next_id[0] = in->next_id[0];
+    sc.next_id[1] = in->next_id[1];
+    sc.count[0] = in->count[0];
+    sc.count[1] = in->count[1];
+    HIPCHECK(h, hipMemcpy(h->sc, &sc, sizeof(sc), hipMemcpyHostToDevice));
+    h->host_count[0] = in->count[0];
+    h->host_count[1] = in->count[1];
+    return PIC_OK;
+}
+
+pic_status pic_enable_timers(pic_handle *h, int32_t on)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    h->timers_on = on != 0;
+    return PIC_OK;
+}
+
+pic_status pic_get_timers(pic_handle *h, pic_timers *out, int32_t reset)
+{
+    if (!h || !out) return fail(h, PIC_EINVAL, "bad argument");
+    timers_collect(h);
+    *out = h->timers;
+    if (reset) h->timers = pic_timers{};
+    return PIC_OK;
+}
+
+pic_status pic_free(pic_handle *h)
+{
+    if (!h) return PIC_OK;
+    (void)hipStreamSynchronize(h->stream);
+    timers_collect(h);
+    for (auto &e : h->free_events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    delete h;
+    return PIC_OK;
+}
+
+const char *pic_last_error(const pic_handle *h)
+{
+    if (!h) return g_init_error.c_str();
+    return h->err.c_str();
+}
+
+}  // extern "C"

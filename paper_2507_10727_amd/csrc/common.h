@@ -1,0 +1,254 @@
+// Internal declarations of libpic.so (device structs, helpers, launchers).
+//
+// Layout in HBM (all carved from the caller's workspace):
+//   particles, per species, structure of arrays with `cap` slots, twice
+//   (ping-pong for the cell sort): key int32 (j << 16 | i, -1 = absorbed),
+//   fr, fz, vr, vt, vz in the state precision T, id uint32;
+//   node fields: one 4-vector per node (T4 = float4 / double4) holding the
+//   gather inputs (E_r, E_z, B_r, B_z); for EC-PIC the E entries are the
+//   edge values E_r(i+1/2, j) and E_z(i, j+1/2) of Section 2's staggering;
+//   node charge per species in T; phi, phi0, phi_L and the FP64 operator in
+//   FP64; the FP32 multigrid hierarchy.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pic.h"
+
+namespace pic {
+
+constexpr int PUSH_THREADS = 256;
+constexpr int PUSH_PPT = 4;                        // particles per thread per chunk
+constexpr int PUSH_CHUNK = PUSH_THREADS * PUSH_PPT;
+constexpr int LDS_NODES = 4096;                    // deposit tile capacity (nodes)
+constexpr int MAX_LEVELS = 16;
+constexpr int MAX_PCG = 512;
+
+enum : int32_t { FLAG_CAPACITY = 1, FLAG_CHILD_OVERFLOW = 2, FLAG_NAN = 4 };
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+// Device-resident scalar state of one simulation.
+struct DevScalars {
+    int64_t count[2];           // slots in use per species
+    int64_t step;
+    uint32_t next_id[2];
+    int32_t n_child;            // children recorded this step (all species)
+    int32_t n_child_s[2];       // children per new-particle species
+    int32_t flags;
+    double dq_conv;             // charge into the cathode this step
+    double ke[2], pz[2];
+    unsigned long long n_abs[2][5];
+    unsigned long long n_cand, n_coll[3], n_see;
+    unsigned long long deposit_fallback;
+    double vc, qc, cap_c, qc0;
+    // sort
+    int64_t sort_total[2];
+    // field solve accumulators
+    double res_rr, res_bb;      // FP64 residual and rhs norms^2
+    double pcg_rz[MAX_PCG + 2], pcg_pq[MAX_PCG + 2], pcg_rr[MAX_PCG + 2];
+};
+
+template <typename T>
+struct SpeciesDev {
+    int32_t *key;
+    T *fr, *fz, *vr, *vt, *vz;
+    uint32_t *id;
+};
+
+// A particle created during the push (ionization products, emitted
+// secondaries).  skey orders children by (parent species, parent id, kind).
+template <typename T>
+struct Child {
+    unsigned long long skey;
+    int32_t species;
+    int32_t key;
+    T fr, fz, vr, vt, vz;
+};
+
+template <typename T>
+struct PushParams {
+    SpeciesDev<T> sp[2];
+    int64_t cap[2];
+    const typename Vec4<T>::type *node;
+    T *q[2];
+    DevScalars *sc;
+    Child<T> *child;
+    int32_t child_cap;
+    const T *nu;                // [3][n_table] collision frequencies (1/s)
+    int32_t n_table;
+    T inv_de, numax;
+    unsigned long long t_null, t_see;
+    int32_t nr, nz;
+    T dr, dz, inv_dr, inv_dz, dt, cathode_rmax;
+    T hqm[2];                   // q dt / (2 m)
+    T qw[2];                    // q w (C per macroparticle)
+    double qw64[2];             // the same in FP64 for the cathode tally
+    double mw[2];               // m w (kg per macroparticle), diagnostics
+    T e_of_v2;                  // m_e / (2 e): eV per (m/s)^2
+    T v2_of_e;                  // 2 e / m_e
+    T two_m_over_M;             // elastic energy-loss factor 2 m_e / M
+    T e_exc, e_iz, sig_ion;     // thresholds (eV); ion thermal speed sqrt(kT/M)
+    int32_t wall_bc[3];
+    int32_t frozen_ions, mcc_on, see_on;
+    int32_t deposit_only;       // 1: only deposit the current positions
+    uint32_t key0, key1, run;
+    int32_t nblk_e;             // blocks [0, nblk_e) push electrons, the rest ions
+};
+
+template <typename T>
+struct ChildParams {
+    SpeciesDev<T> sp[2];
+    int64_t cap[2];
+    T *q[2];
+    T qw[2];
+    DevScalars *sc;
+    const Child<T> *child;
+    int32_t child_cap;
+    int32_t nr;
+};
+
+// ---------------------------------------------------------------- Philox --
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 products of counter words 0 and 2 with the round multipliers,
+// high halves xored with words 1, 3 and the key, key bumped by the Weyl
+// increments between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        uint32_t hi0 = __umulhi(m0, c.x), lo0 = m0 * c.x;
+        uint32_t hi1 = __umulhi(m1, c.z), lo1 = m1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Counter layout of every draw: (particle id, run << 8 | species << 4 |
+// purpose, step, 0).  Purposes: 0 collision (candidate, process, direction),
+// 1 ionization extras (energy split, ejected direction), 2 new-ion velocity,
+// 3 secondary emission.
+enum : uint32_t { PURPOSE_MCC = 0, PURPOSE_IZ = 1, PURPOSE_ION = 2, PURPOSE_SEE = 3 };
+
+template <typename T>
+__device__ __forceinline__ T u24(uint32_t u) { return (T)(u >> 8) * (T)(1.0 / 16777216.0); }
+template <typename T>
+__device__ __forceinline__ T u24_open(uint32_t u) { return ((T)(u >> 8) + (T)0.5) * (T)(1.0 / 16777216.0); }
+
+__device__ __forceinline__ void sincos_2pi(float u, float *s, float *c) { sincospif(2.0f * u, s, c); }
+__device__ __forceinline__ void sincos_2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
+
+// ----------------------------------------------------------- wave helpers --
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Global float/double atomic add using the hardware instruction (the
+// workspace is coarse-grained device memory).
+__device__ __forceinline__ void atomic_add_dev(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add_dev(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// --------------------------------------------------------------- launchers --
+// particles.hip
+template <typename T>
+void launch_push(const PushParams<T> &p, int scheme, int nblocks, hipStream_t s);
+template <typename T>
+void launch_children(const ChildParams<T> &p, hipStream_t s);
+void launch_finalize_step(DevScalars *sc, const int64_t cap[2], hipStream_t s);
+void launch_begin_step(DevScalars *sc, void *q0, void *q1, int64_t nodes, int elem_bytes,
+                       hipStream_t s);
+template <typename T>
+void launch_load(SpeciesDev<T> sp, int64_t offset, const double *r, const double *z,
+                 const double *vr, const double *vt, const double *vz, const uint32_t *id,
+                 int64_t n, int32_t nr, int32_t nz, double dr, double dz, hipStream_t s);
+
+// sort.hip
+template <typename T>
+void launch_sort(SpeciesDev<T> src, SpeciesDev<T> dst, DevScalars *sc, int species,
+                 int32_t *hist, int32_t *block_sums, int32_t nr, int32_t nz, int64_t cap,
+                 hipStream_t s);
+
+// field.hip (multigrid hierarchy and solver)
+struct Level {
+    int32_t nr, nz;
+    float *ce, *cn, *dinv;      // couplings / eps0 and inverse diagonal (0 = Dirichlet)
+    float *x, *b;               // correction and right-hand side
+};
+
+struct FieldDev {
+    int32_t nr, nz;
+    double dr, dz;
+    const double *ce64, *cn64;  // FP64 couplings (with eps0)
+    const uint8_t *kind;        // 0 unknown, 1 cathode, 2 grounded
+    double *phi, *phi0, *phi_l;
+    double *r64;                // FP64 residual
+    float *e32, *r32, *z32, *p32, *q32;  // inner PCG vectors (finest level)
+    Level lv[MAX_LEVELS];
+    int32_t nlevels;
+    const float *coarse_inv;    // dense inverse on the coarsest level's unknowns
+    const int32_t *coarse_map;  // unknown index -> node index
+    int32_t coarse_n;
+    const double *b_r, *b_z;    // static nodal B
+    const double *vdep;         // node volumes for densities
+};
+
+void launch_zero(void *p, int64_t bytes, hipStream_t s);
+template <typename T>
+void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const T *q1,
+                       DevScalars *sc, hipStream_t s);
+void launch_cast_scale(const FieldDev &f, double scale, hipStream_t s);
+void launch_update64(const FieldDev &f, double *phi, double scale, hipStream_t s);
+void launch_vcycle(const FieldDev &f, hipStream_t s);   // z32 = M r32
+void launch_pcg_matvec_dot(const FieldDev &f, DevScalars *sc, int k, hipStream_t s);
+void launch_pcg_update(const FieldDev &f, DevScalars *sc, int k, hipStream_t s);
+void launch_pcg_dot_rz(const FieldDev &f, DevScalars *sc, int k, hipStream_t s);
+void launch_pcg_direction(const FieldDev &f, DevScalars *sc, int k, hipStream_t s);
+void launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s);
+template <typename T>
+void launch_circuit(const FieldDev &f, const T *q0, const T *q1, DevScalars *sc, int circuit,
+                    double v_fixed, double v_ext, double r_ext, double dt, double extra_dq,
+                    hipStream_t s);
+template <typename T>
+void launch_field_prep(const FieldDev &f, typename Vec4<T>::type *node, DevScalars *sc,
+                       int scheme, int use_phi, hipStream_t s);
+void launch_set_dirichlet(const FieldDev &f, double *phi, double v_cathode, hipStream_t s);
+template <typename T>
+void launch_diag_grid(const FieldDev &f, const T *q0, const T *q1, double q_e, double q_i,
+                      double *partials, int nblocks, hipStream_t s);
+void launch_count_live(const int32_t *key, const DevScalars *sc, int species,
+                       unsigned long long *out, hipStream_t s);
+void launch_zero_unknowns(const FieldDev &f, double *phi, hipStream_t s);
+
+// host_tables.cpp (FP64 host arithmetic, built without FMA contraction)
+double host_nu_tables(const pic_config &c, double *nu, unsigned long long *t_null);
+unsigned long long host_see_threshold(const pic_config &c);
+void host_couplings(int nr, int nz, double lr, double lz, double scale, double *ce, double *cn);
+int host_node_kind(int nr, int nz, double lr, double cathode_rmax, int i, int j);
+int host_dense_inverse(int n, double *a);   // in place, returns 0 on success
+double eps0();
+void host_node_volumes(int nr, int nz, double lr, double lz, double *v);
+
+}  // namespace pic

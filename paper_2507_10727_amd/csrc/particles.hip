@@ -1,0 +1,624 @@
+// Particle kernels of libpic.so: the fused timestep kernel (field gather,
+// Boris push, R-Z drift, walls and ion-induced emission, null-collision MCC,
+// charge deposit), child insertion, per-step bookkeeping and the loader.
+#include <climits>
+
+#include "common.h"
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// Fused particle kernel.
+//
+// One launch covers both species: blocks [0, nblk_e) stream the electrons,
+// the rest the ions.  Each block walks its species in chunks of
+// PUSH_CHUNK consecutive slots (grid-stride), each thread owning PUSH_PPT
+// slots of a chunk at stride PUSH_THREADS so that every load and store of a
+// wavefront is one contiguous 256-byte (FP32) segment.  Particles are kept
+// sorted by cell, so the nodes a chunk deposits to form a small box; the
+// chunk's charge is accumulated in LDS over that box and flushed with one
+// global atomic per touched node.  A chunk whose box does not fit (rare, an
+// unsorted or badly scattered chunk) deposits with global atomics.
+//
+// Per particle (Section 2 for the gather, Section 3 for walls, emission and
+// collisions):
+//   E from the node 4-vectors: EC-PIC takes E_r from the two r-edges of the
+//     cell (NGP in r, linear in z) and E_z from the two z-edges (linear in r,
+//     NGP in z); MC-PIC interpolates nodal E with the deposit's tent weights;
+//     B is tent-interpolated in both.
+//   Boris rotation in the Cartesian frame (r-hat, theta-hat, z-hat) at the
+//     particle, drift, and rotation of (v_r, v_theta) into the new
+//     meridional plane; the radial displacement is formed as
+//     (2 r dx + dx^2 + dy^2) / (r + r') so that the cell-relative position
+//     keeps full precision in FP32.
+//   Walls in priority z < 0 (cathode if r < cathode_rmax, else the Neumann
+//     block), r >= R, z >= L; absorbed slots get key -1.
+//   Collisions for surviving electrons that existed before the step.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void iso_direction(uint32_t ua, uint32_t ub, T &d0, T &d1, T &d2)
+{
+    const T c = (T)1 - (T)2 * u24<T>(ua);
+    const T s = sqrt(fmax((T)0, (T)1 - c * c));
+    T sn, cs;
+    sincos_2pi(u24<T>(ub), &sn, &cs);
+    d0 = s * cs;
+    d1 = s * sn;
+    d2 = c;
+}
+
+template <typename T>
+__device__ __forceinline__ void record_child(const PushParams<T> &P, int parent_species,
+                                             uint32_t parent_id, int kind, int species, int i,
+                                             int j, T fr, T fz, T vr, T vt, T vz)
+{
+    const int slot = atomicAdd(&P.sc->n_child, 1);
+    atomicAdd(&P.sc->n_child_s[species], 1);
+    if (slot >= P.child_cap) {
+        atomicOr(&P.sc->flags, FLAG_CHILD_OVERFLOW);
+        return;
+    }
+    Child<T> c;
+    c.skey = ((unsigned long long)parent_species << 33) | ((unsigned long long)parent_id << 1) |
+             (unsigned long long)kind;
+    c.species = species;
+    c.key = (j << 16) | i;
+    c.fr = fr;
+    c.fz = fz;
+    c.vr = vr;
+    c.vt = vt;
+    c.vz = vz;
+    P.child[slot] = c;
+}
+
+template <typename T>
+__device__ __forceinline__ T interp_row(const T *row, int k, T f)
+{
+    return ((T)1 - f) * row[k] + f * row[k + 1];
+}
+
+template <typename T, int SCHEME>
+__global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
+{
+    using T4 = typename Vec4<T>::type;
+    __shared__ T lds_q[LDS_NODES];
+    __shared__ int red[4][PUSH_THREADS / 64];
+    __shared__ double dred[3][PUSH_THREADS / 64];
+    __shared__ unsigned long long cred[12][PUSH_THREADS / 64];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int s = ((int)blockIdx.x < P.nblk_e) ? 0 : 1;
+    const int blk = s ? (int)blockIdx.x - P.nblk_e : (int)blockIdx.x;
+    const int nblk = s ? (int)gridDim.x - P.nblk_e : P.nblk_e;
+    const SpeciesDev<T> S = P.sp[s];
+    const int64_t n = P.sc->count[s];
+    const uint32_t step = (uint32_t)P.sc->step;
+    const int nr = P.nr, nz = P.nz, ldn = nr + 1;
+    const T hqm = P.hqm[s], qw = P.qw[s];
+    const double mw = P.mw[s];
+    const bool frozen = P.deposit_only || ((s == 1) && P.frozen_ions);
+    const bool collide = (s == 0) && P.mcc_on;
+    const bool emit = (s == 1) && P.see_on;
+    const int nt = P.n_table;
+    T *Q = P.q[s];
+
+    double ke = 0.0, pzs = 0.0, dq = 0.0;
+    unsigned int n_abs1 = 0, n_abs2 = 0, n_abs3 = 0, n_abs4 = 0;
+    unsigned int n_cand = 0, n_el = 0, n_ex = 0, n_iz = 0, n_see = 0, n_fb = 0;
+
+    for (int64_t base = (int64_t)blk * PUSH_CHUNK; base < n;
+         base += (int64_t)nblk * PUSH_CHUNK) {
+        int ci[PUSH_PPT], cj[PUSH_PPT];
+        T cfr[PUSH_PPT], cfz[PUSH_PPT];
+        int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
+#pragma unroll
+        for (int k = 0; k < PUSH_PPT; ++k) {
+            const int64_t p = base + (int64_t)k * PUSH_THREADS + tid;
+            ci[k] = -1;
+            cj[k] = 0;
+            cfr[k] = 0;
+            cfz[k] = 0;
+            if (p >= n) continue;
+            const int key = S.key[p];
+            if (key < 0) continue;
+            const int i = key & 0xffff, j = key >> 16;
+            const T fr = S.fr[p], fz = S.fz[p];
+            const T vr = S.vr[p], vt = S.vt[p], vz = S.vz[p];
+            if (frozen) {
+                ke += 0.5 * mw * ((double)vr * vr + (double)vt * vt + (double)vz * vz);
+                pzs += mw * (double)vz;
+                ci[k] = i;
+                cj[k] = j;
+                cfr[k] = fr;
+                cfz[k] = fz;
+                imin = min(imin, i); imax = max(imax, i);
+                jmin = min(jmin, j); jmax = max(jmax, j);
+                continue;
+            }
+            // ---- gather
+            const T4 a00 = P.node[(int64_t)j * ldn + i];
+            const T4 a10 = P.node[(int64_t)j * ldn + i + 1];
+            const T4 a01 = P.node[(int64_t)(j + 1) * ldn + i];
+            const T4 a11 = P.node[(int64_t)(j + 1) * ldn + i + 1];
+            const T gr = (T)1 - fr, gz = (T)1 - fz;
+            const T w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
+            T er, ez;
+            if (SCHEME == PIC_EC) {
+                er = gz * a00.x + fz * a01.x;
+                ez = gr * a00.y + fr * a10.y;
+            } else {
+                er = w00 * a00.x + w10 * a10.x + w01 * a01.x + w11 * a11.x;
+                ez = w00 * a00.y + w10 * a10.y + w01 * a01.y + w11 * a11.y;
+            }
+            const T br = w00 * a00.z + w10 * a10.z + w01 * a01.z + w11 * a11.z;
+            const T bz = w00 * a00.w + w10 * a10.w + w01 * a01.w + w11 * a11.w;
+            // ---- Boris: half kick, rotation about t = (q dt / 2m) B, half kick
+            const T mx = vr + hqm * er, my = vt, mz = vz + hqm * ez;
+            const T tx = hqm * br, tz = hqm * bz;
+            const T f2 = (T)2 / ((T)1 + tx * tx + tz * tz);
+            const T sx = f2 * tx, sz = f2 * tz;
+            const T px = mx + my * tz;
+            const T py = my + (mz * tx - mx * tz);
+            const T pzz = mz - my * tx;
+            const T qx = mx + py * sz;
+            const T qy = my + (pzz * sx - px * sz);
+            const T qz = mz - py * sx;
+            const T nx = qx + hqm * er, ny = qy, nzv = qz + hqm * ez;
+            ke += 0.5 * mw * ((double)vr * nx + (double)vt * ny + (double)vz * nzv);
+            pzs += mw * (double)nzv;
+            // ---- drift in (x, y, z) = (r, 0, z), rotate into the new plane
+            const T r = ((T)i + fr) * P.dr;
+            const T dx = nx * P.dt, dy = ny * P.dt;
+            const T x1 = r + dx;
+            const T r1 = sqrt(x1 * x1 + dy * dy);
+            T vr1 = nx, vt1 = ny, vz1 = nzv;
+            if (r1 > (T)0) {
+                const T c = x1 / r1, sn = dy / r1;
+                vr1 = c * nx + sn * ny;
+                vt1 = c * ny - sn * nx;
+            }
+            const T den = r + r1;
+            const T drr = (den > (T)0) ? ((T)2 * r * dx + dx * dx + dy * dy) / den : (T)0;
+            const T xr = fr + drr * P.inv_dr;
+            const T xz = fz + nzv * P.dt * P.inv_dz;
+            const T flr = floor(xr), flz = floor(xz);
+            int i1 = i + (int)flr, j1 = j + (int)flz;
+            T fr1 = xr - flr, fz1 = xz - flz;
+            if (fr1 >= (T)1) { fr1 = (T)0; ++i1; }
+            if (fz1 >= (T)1) { fz1 = (T)0; ++j1; }
+            // ---- walls
+            int fate = 0;
+            if (j1 < 0) {
+                if (P.wall_bc[0] == PIC_REFLECT) {
+                    const T zg = -((T)j1 + fz1);
+                    const T fl = floor(zg);
+                    j1 = (int)fl;
+                    fz1 = zg - fl;
+                    if (fz1 >= (T)1) { fz1 = (T)0; ++j1; }
+                    vz1 = -vz1;
+                } else {
+                    fate = (r1 < P.cathode_rmax) ? 1 : 2;
+                }
+            }
+            if (fate == 0 && i1 >= nr) {
+                if (P.wall_bc[2] == PIC_REFLECT) {
+                    const T rg = (T)(2 * nr) - ((T)i1 + fr1);
+                    const T fl = floor(rg);
+                    i1 = (int)fl;
+                    fr1 = rg - fl;
+                    if (i1 >= nr) { i1 = nr - 1; fr1 = (T)1 - (T)1 / (T)16777216; }
+                    vr1 = -vr1;
+                } else {
+                    fate = 3;
+                }
+            }
+            if (fate == 0 && j1 >= nz) {
+                if (P.wall_bc[1] == PIC_REFLECT) {
+                    const T zg = (T)(2 * nz) - ((T)j1 + fz1);
+                    const T fl = floor(zg);
+                    j1 = (int)fl;
+                    fz1 = zg - fl;
+                    if (j1 >= nz) { j1 = nz - 1; fz1 = (T)1 - (T)1 / (T)16777216; }
+                    vz1 = -vz1;
+                } else {
+                    fate = 4;
+                }
+            }
+            if (fate == 0) {
+                // r' >= 0 exactly; round-off can put i' at -1 next to the axis.
+                // Any index still outside the grid (non-finite or absurd
+                // velocities under reflecting walls) is clamped so every
+                // access stays in bounds.
+                if (i1 < 0) { i1 = 0; fr1 = (T)0; }
+                if (i1 > nr - 1) { i1 = nr - 1; fr1 = (T)1 - (T)1 / (T)16777216; }
+                if (j1 < 0) { j1 = 0; fz1 = (T)0; }
+                if (j1 > nz - 1) { j1 = nz - 1; fz1 = (T)1 - (T)1 / (T)16777216; }
+                if (!(fr1 >= (T)0 && fr1 < (T)1)) fr1 = (T)0;
+                if (!(fz1 >= (T)0 && fz1 < (T)1)) fz1 = (T)0;
+            }
+            if (fate) {
+                S.key[p] = -1;
+                if (fate == 1) {
+                    ++n_abs1;
+                    dq += P.qw64[s];
+                    if (emit) {
+                        const uint32_t id = S.id[p];
+                        const uint4 u = philox4x32_10(
+                            make_uint4(id, (P.run << 8) | (1u << 4) | PURPOSE_SEE, step, 0u),
+                            P.key0, P.key1);
+                        if ((unsigned long long)u.x < P.t_see) {
+                            ++n_see;
+                            dq -= P.qw64[0];
+                            int ie = i1;
+                            T fe = fr1;
+                            if (ie >= nr) { ie = nr - 1; fe = (T)1 - (T)1 / (T)16777216; }
+                            if (ie < 0) { ie = 0; fe = (T)0; }
+                            record_child(P, 1, id, 0, 0, ie, 0, fe, (T)0, (T)0, (T)0, (T)0);
+                        }
+                    }
+                } else if (fate == 2) {
+                    ++n_abs2;
+                } else if (fate == 3) {
+                    ++n_abs3;
+                } else {
+                    ++n_abs4;
+                }
+                continue;
+            }
+            // ---- null-collision MCC (electrons)
+            if (collide) {
+                const uint32_t id = S.id[p];
+                const uint4 u = philox4x32_10(
+                    make_uint4(id, (P.run << 8) | PURPOSE_MCC, step, 0u), P.key0, P.key1);
+                if ((unsigned long long)u.x < P.t_null) {
+                    ++n_cand;
+                    const T v2 = vr1 * vr1 + vt1 * vt1 + vz1 * vz1;
+                    const T e = P.e_of_v2 * v2;
+                    const T x = e * P.inv_de;
+                    int kk;
+                    T f;
+                    if (x >= (T)(nt - 1)) { kk = nt - 2; f = (T)1; }
+                    else { const T fl = floor(x); kk = (int)fl; f = x - fl; }
+                    const T c1 = interp_row(P.nu, kk, f);
+                    const T c2 = c1 + interp_row(P.nu + nt, kk, f);
+                    const T c3 = c2 + interp_row(P.nu + 2 * nt, kk, f);
+                    const T rsel = u24<T>(u.y) * P.numax;
+                    int proc = -1;
+                    if (rsel < c1) proc = 0;
+                    else if (rsel < c2) proc = (e >= P.e_exc) ? 1 : -1;
+                    else if (rsel < c3) proc = (e >= P.e_iz) ? 2 : -1;
+                    if (proc >= 0) {
+                        T d0, d1, d2;
+                        iso_direction(u.z, u.w, d0, d1, d2);
+                        T enew;
+                        if (proc == 0) {
+                            ++n_el;
+                            const T vm = sqrt(v2);
+                            const T cth = (vr1 * d0 + vt1 * d1 + vz1 * d2) / vm;
+                            enew = e * ((T)1 - P.two_m_over_M * ((T)1 - cth));
+                        } else if (proc == 1) {
+                            ++n_ex;
+                            enew = e - P.e_exc;
+                        } else {
+                            ++n_iz;
+                            const T erem = e - P.e_iz;
+                            const uint4 ua = philox4x32_10(
+                                make_uint4(id, (P.run << 8) | PURPOSE_IZ, step, 0u), P.key0, P.key1);
+                            const uint4 ub = philox4x32_10(
+                                make_uint4(id, (P.run << 8) | PURPOSE_ION, step, 0u), P.key0, P.key1);
+                            const T eej = u24<T>(ua.x) * erem;
+                            enew = erem - eej;
+                            T e0, e1, e2;
+                            iso_direction(ua.y, ua.z, e0, e1, e2);
+                            const T vej = sqrt(P.v2_of_e * eej);
+                            record_child(P, 0, id, 0, 0, i1, j1, fr1, fz1, vej * e0, vej * e1,
+                                         vej * e2);
+                            const T a0 = sqrt((T)-2 * log(u24_open<T>(ub.x)));
+                            const T a1 = sqrt((T)-2 * log(u24_open<T>(ub.z)));
+                            T s0, c0, s1, c1b;
+                            sincos_2pi(u24<T>(ub.y), &s0, &c0);
+                            sincos_2pi(u24<T>(ub.w), &s1, &c1b);
+                            record_child(P, 0, id, 1, 1, i1, j1, fr1, fz1, P.sig_ion * a0 * c0,
+                                         P.sig_ion * a0 * s0, P.sig_ion * a1 * c1b);
+                        }
+                        const T vn = sqrt(P.v2_of_e * enew);
+                        vr1 = vn * d0;
+                        vt1 = vn * d1;
+                        vz1 = vn * d2;
+                    }
+                }
+            }
+            S.key[p] = (j1 << 16) | i1;
+            S.fr[p] = fr1;
+            S.fz[p] = fz1;
+            S.vr[p] = vr1;
+            S.vt[p] = vt1;
+            S.vz[p] = vz1;
+            ci[k] = i1;
+            cj[k] = j1;
+            cfr[k] = fr1;
+            cfz[k] = fz1;
+            imin = min(imin, i1); imax = max(imax, i1);
+            jmin = min(jmin, j1); jmax = max(jmax, j1);
+        }
+
+        // ---- deposit: block bounding box of the chunk's cells
+        imin = wave_min(imin); imax = wave_max(imax);
+        jmin = wave_min(jmin); jmax = wave_max(jmax);
+        if (lane == 0) {
+            red[0][wid] = imin; red[1][wid] = imax;
+            red[2][wid] = jmin; red[3][wid] = jmax;
+        }
+        __syncthreads();
+        imin = red[0][0]; imax = red[1][0]; jmin = red[2][0]; jmax = red[3][0];
+#pragma unroll
+        for (int w = 1; w < PUSH_THREADS / 64; ++w) {
+            imin = min(imin, red[0][w]); imax = max(imax, red[1][w]);
+            jmin = min(jmin, red[2][w]); jmax = max(jmax, red[3][w]);
+        }
+        if (imax >= imin) {
+            const int bw = imax - imin + 2, bh = jmax - jmin + 2;
+            if (bw * bh <= LDS_NODES) {
+                for (int t = tid; t < bw * bh; t += PUSH_THREADS) lds_q[t] = (T)0;
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < PUSH_PPT; ++k) {
+                    if (ci[k] < 0) continue;
+                    const int li = ci[k] - imin, lj = cj[k] - jmin;
+                    const T gr = (T)1 - cfr[k], gz = (T)1 - cfz[k];
+                    atomicAdd(&lds_q[lj * bw + li], qw * gr * gz);
+                    atomicAdd(&lds_q[lj * bw + li + 1], qw * cfr[k] * gz);
+                    atomicAdd(&lds_q[(lj + 1) * bw + li], qw * gr * cfz[k]);
+                    atomicAdd(&lds_q[(lj + 1) * bw + li + 1], qw * cfr[k] * cfz[k]);
+                }
+                __syncthreads();
+                for (int t = tid; t < bw * bh; t += PUSH_THREADS) {
+                    const T v = lds_q[t];
+                    if (v != (T)0) {
+                        const int lj = t / bw, li = t - lj * bw;
+                        atomic_add_dev(&Q[(int64_t)(jmin + lj) * ldn + imin + li], v);
+                    }
+                }
+            } else {
+                if (tid == 0) ++n_fb;
+#pragma unroll
+                for (int k = 0; k < PUSH_PPT; ++k) {
+                    if (ci[k] < 0) continue;
+                    const int64_t n0 = (int64_t)cj[k] * ldn + ci[k];
+                    const T gr = (T)1 - cfr[k], gz = (T)1 - cfz[k];
+                    atomic_add_dev(&Q[n0], qw * gr * gz);
+                    atomic_add_dev(&Q[n0 + 1], qw * cfr[k] * gz);
+                    atomic_add_dev(&Q[n0 + ldn], qw * gr * cfz[k]);
+                    atomic_add_dev(&Q[n0 + ldn + 1], qw * cfr[k] * cfz[k]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- block totals of the diagnostics, one atomic per quantity
+    ke = wave_sum(ke);
+    pzs = wave_sum(pzs);
+    dq = wave_sum(dq);
+    unsigned long long c[12] = {n_abs1, n_abs2, n_abs3, n_abs4, n_cand, n_el,
+                                n_ex,   n_iz,   n_see,  n_fb,   0,      0};
+#pragma unroll
+    for (int q = 0; q < 10; ++q) c[q] = wave_sum_u64(c[q]);
+    if (lane == 0) {
+        dred[0][wid] = ke;
+        dred[1][wid] = pzs;
+        dred[2][wid] = dq;
+#pragma unroll
+        for (int q = 0; q < 10; ++q) cred[q][wid] = c[q];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0, b = 0, d = 0;
+        unsigned long long t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int w = 0; w < PUSH_THREADS / 64; ++w) {
+            a += dred[0][w];
+            b += dred[1][w];
+            d += dred[2][w];
+            for (int q = 0; q < 10; ++q) t[q] += cred[q][w];
+        }
+        DevScalars *sc = P.sc;
+        if (a != 0.0) atomic_add_dev(&sc->ke[s], a);
+        if (b != 0.0) atomic_add_dev(&sc->pz[s], b);
+        if (d != 0.0) atomic_add_dev(&sc->dq_conv, d);
+        for (int q = 0; q < 4; ++q)
+            if (t[q]) atomicAdd(&sc->n_abs[s][q + 1], t[q]);
+        if (t[4]) atomicAdd(&sc->n_cand, t[4]);
+        for (int q = 0; q < 3; ++q)
+            if (t[5 + q]) atomicAdd(&sc->n_coll[q], t[5 + q]);
+        if (t[8]) atomicAdd(&sc->n_see, t[8]);
+        if (t[9]) atomicAdd(&sc->deposit_fallback, t[9]);
+    }
+}
+
+template <typename T>
+void launch_push(const PushParams<T> &p, int scheme, int nblocks, hipStream_t s)
+{
+    if (scheme == PIC_EC)
+        hipLaunchKernelGGL((k_push<T, PIC_EC>), dim3(nblocks), dim3(PUSH_THREADS), 0, s, p);
+    else
+        hipLaunchKernelGGL((k_push<T, PIC_MC>), dim3(nblocks), dim3(PUSH_THREADS), 0, s, p);
+}
+
+// ---------------------------------------------------------------------------
+// Children: ids and slots in (parent species, parent id, kind) order.
+// The rank of a child among the children of its species is the number of
+// such children with a smaller ordering key (keys are unique), counted over
+// LDS-staged tiles of the child list.  Its slot is count[s] + rank and its id
+// next_id[s] + rank; its charge is deposited with global atomics.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_children(ChildParams<T> P)
+{
+    __shared__ unsigned long long tk[256];
+    __shared__ int ts[256];
+    const int n = min(P.sc->n_child, P.child_cap);
+    const int ldn = P.nr + 1;
+    for (int base = blockIdx.x * 256; base < n; base += gridDim.x * 256) {
+        const int c = base + threadIdx.x;
+        unsigned long long my = ~0ull;
+        int ms = -1;
+        if (c < n) {
+            my = P.child[c].skey;
+            ms = P.child[c].species;
+        }
+        int rank = 0;
+        for (int t0 = 0; t0 < n; t0 += 256) {
+            __syncthreads();
+            const int t = t0 + threadIdx.x;
+            tk[threadIdx.x] = (t < n) ? P.child[t].skey : ~0ull;
+            ts[threadIdx.x] = (t < n) ? P.child[t].species : -2;
+            __syncthreads();
+            const int lim = min(256, n - t0);
+            for (int q = 0; q < lim; ++q) rank += (ts[q] == ms && tk[q] < my) ? 1 : 0;
+        }
+        if (c < n) {
+            const Child<T> ch = P.child[c];
+            const int s = ch.species;
+            const int64_t slot = P.sc->count[s] + rank;
+            if (slot >= P.cap[s]) {
+                atomicOr(&P.sc->flags, FLAG_CAPACITY);
+            } else {
+                const SpeciesDev<T> S = P.sp[s];
+                S.key[slot] = ch.key;
+                S.fr[slot] = ch.fr;
+                S.fz[slot] = ch.fz;
+                S.vr[slot] = ch.vr;
+                S.vt[slot] = ch.vt;
+                S.vz[slot] = ch.vz;
+                S.id[slot] = P.sc->next_id[s] + (uint32_t)rank;
+                const int i = ch.key & 0xffff, j = ch.key >> 16;
+                const int64_t n0 = (int64_t)j * ldn + i;
+                const T qw = P.qw[s], gr = (T)1 - ch.fr, gz = (T)1 - ch.fz;
+                atomic_add_dev(&P.q[s][n0], qw * gr * gz);
+                atomic_add_dev(&P.q[s][n0 + 1], qw * ch.fr * gz);
+                atomic_add_dev(&P.q[s][n0 + ldn], qw * gr * ch.fz);
+                atomic_add_dev(&P.q[s][n0 + ldn + 1], qw * ch.fr * ch.fz);
+            }
+        }
+    }
+}
+
+template <typename T>
+void launch_children(const ChildParams<T> &p, hipStream_t s)
+{
+    int blocks = (p.child_cap + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL((k_children<T>), dim3(blocks), dim3(256), 0, s, p);
+}
+
+// Counts and id counters advance by the children of the step; the step
+// counter advances.
+__global__ void k_finalize_step(DevScalars *sc, int64_t cap0, int64_t cap1)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t cap[2] = {cap0, cap1};
+    for (int s = 0; s < 2; ++s) {
+        int64_t c = sc->count[s] + sc->n_child_s[s];
+        if (c > cap[s]) c = cap[s];
+        sc->count[s] = c;
+        sc->next_id[s] += (uint32_t)sc->n_child_s[s];
+    }
+    sc->n_child = 0;
+    sc->n_child_s[0] = 0;
+    sc->n_child_s[1] = 0;
+    sc->step += 1;
+}
+
+void launch_finalize_step(DevScalars *sc, const int64_t cap[2], hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_step, dim3(1), dim3(64), 0, s, sc, cap[0], cap[1]);
+}
+
+// Zero the deposit targets and the per-step tallies.
+__global__ void k_begin_step(DevScalars *sc, uint32_t *q0, uint32_t *q1, int64_t words)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        q0[k] = 0u;
+        q1[k] = 0u;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->dq_conv = 0.0;
+        sc->ke[0] = sc->ke[1] = 0.0;
+        sc->pz[0] = sc->pz[1] = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 5; ++b) sc->n_abs[a][b] = 0;
+        sc->n_cand = 0;
+        sc->n_coll[0] = sc->n_coll[1] = sc->n_coll[2] = 0;
+        sc->n_see = 0;
+        sc->deposit_fallback = 0;
+    }
+}
+
+void launch_begin_step(DevScalars *sc, void *q0, void *q1, int64_t nodes, int elem_bytes,
+                       hipStream_t s)
+{
+    const int64_t words = nodes * elem_bytes / 4;
+    int blocks = (int)((words + 255) / 256);
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_begin_step, dim3(blocks), dim3(256), 0, s, sc, (uint32_t *)q0,
+                       (uint32_t *)q1, words);
+}
+
+// Loader: absolute FP64 positions -> cell key and in-cell fraction,
+// i = floor(r / dr) kept in [0, nr-1], fr = r/dr - i.
+template <typename T>
+__global__ void k_load(SpeciesDev<T> S, int64_t off, const double *r, const double *z,
+                       const double *vr, const double *vt, const double *vz, const uint32_t *id,
+                       int64_t n, int32_t nr, int32_t nz, double dr, double dz)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const double x = r[k] / dr, y = z[k] / dz;
+        int i = (int)floor(x), j = (int)floor(y);
+        i = max(0, min(nr - 1, i));
+        j = max(0, min(nz - 1, j));
+        T fr = (T)(x - i), fz = (T)(y - j);
+        if (fr >= (T)1) fr = (T)1 - (T)1 / (T)16777216;
+        if (fz >= (T)1) fz = (T)1 - (T)1 / (T)16777216;
+        if (fr < (T)0) fr = (T)0;
+        if (fz < (T)0) fz = (T)0;
+        const int64_t d = off + k;
+        S.key[d] = (j << 16) | i;
+        S.fr[d] = fr;
+        S.fz[d] = fz;
+        S.vr[d] = (T)vr[k];
+        S.vt[d] = (T)vt[k];
+        S.vz[d] = (T)vz[k];
+        S.id[d] = id[k];
+    }
+}
+
+template <typename T>
+void launch_load(SpeciesDev<T> sp, int64_t offset, const double *r, const double *z,
+                 const double *vr, const double *vt, const double *vz, const uint32_t *id,
+                 int64_t n, int32_t nr, int32_t nz, double dr, double dz, hipStream_t s)
+{
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_load<T>), dim3(blocks), dim3(256), 0, s, sp, offset, r, z, vr, vt, vz,
+                       id, n, nr, nz, dr, dz);
+}
+
+template void launch_push<float>(const PushParams<float> &, int, int, hipStream_t);
+template void launch_push<double>(const PushParams<double> &, int, int, hipStream_t);
+template void launch_children<float>(const ChildParams<float> &, hipStream_t);
+template void launch_children<double>(const ChildParams<double> &, hipStream_t);
+template void launch_load<float>(SpeciesDev<float>, int64_t, const double *, const double *,
+                                 const double *, const double *, const double *,
+                                 const uint32_t *, int64_t, int32_t, int32_t, double, double,
+                                 hipStream_t);
+template void launch_load<double>(SpeciesDev<double>, int64_t, const double *, const double *,
+                                  const double *, const double *, const double *,
+                                  const uint32_t *, int64_t, int32_t, int32_t, double, double,
+                                  hipStream_t);
+
+}  // namespace pic

@@ -1,0 +1,183 @@
+// Cell sort with compaction: a counting sort of live particles by cell
+// (bin = j * nr + i, row-major) into the second particle buffer.  Absorbed
+// slots (key < 0) are dropped, so the sort also compacts.
+//
+// Sorted particles let a chunk of consecutive slots touch only a small box
+// of nodes (LDS deposit tiles, cache-local gathers).  Runs of equal bins in
+// a wavefront are merged into one atomic (sorted input makes runs long), so
+// the histogram and the scatter issue about one global atomic per run.
+#include "common.h"
+
+namespace pic {
+
+namespace {
+
+constexpr int SCAN_TILE = 1024;
+
+// Run structure of the wavefront: lanes with the same valid bin that are
+// adjacent form a run; returns the run's first lane and length.
+__device__ __forceinline__ void wave_runs(int bin, bool valid, int lane, int &head, int &len)
+{
+    const int prev = __shfl_up(bin, 1, 64);
+    const int pvalid = __shfl_up((int)valid, 1, 64);
+    const bool is_head = valid && (lane == 0 || !pvalid || prev != bin);
+    const unsigned long long heads = __ballot(is_head);
+    const unsigned long long bounds = heads | __ballot(!valid);
+    const unsigned long long upto = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const unsigned long long h = heads & upto;
+    head = h ? 63 - __clzll(h) : lane;
+    const unsigned long long above = bounds & ~upto;
+    const int nxt = above ? (__ffsll((long long)above) - 1) : 64;
+    len = nxt - head;
+}
+
+__global__ void k_sort_hist(const int32_t *key, const DevScalars *sc, int species, int32_t nr,
+                            int32_t *hist)
+{
+    const int64_t n = sc->count[species];
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += stride) {
+        const int64_t p = b + threadIdx.x;
+        const int k = (p < n) ? key[p] : -1;
+        const bool valid = k >= 0;
+        const int bin = valid ? (k >> 16) * nr + (k & 0xffff) : -1;
+        int head, len;
+        wave_runs(bin, valid, lane, head, len);
+        if (valid && head == lane) atomicAdd(&hist[bin], len);
+    }
+}
+
+// Exclusive scan of hist[0, nbins) in three passes (tile sums, scan of the
+// tile sums in one block, tile scans with offsets).
+__global__ void k_scan_tiles(const int32_t *in, int32_t nbins, int32_t *tile_sums)
+{
+    __shared__ int32_t part[SCAN_TILE / 64];
+    const int t0 = blockIdx.x * SCAN_TILE;
+    int v = 0;
+    for (int q = threadIdx.x; q < SCAN_TILE; q += blockDim.x) {
+        const int b = t0 + q;
+        if (b < nbins) v += in[b];
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += part[w];
+        tile_sums[blockIdx.x] = s;
+    }
+}
+
+__global__ void k_scan_top(int32_t *tile_sums, int32_t ntiles, DevScalars *sc, int species)
+{
+    // one block of 1024 threads, ntiles <= 1024 * 64 handled by a serial loop per thread
+    __shared__ int32_t buf[1024];
+    const int per = (ntiles + 1023) / 1024;
+    const int start = threadIdx.x * per;
+    int local = 0;
+    for (int q = 0; q < per; ++q) {
+        const int t = start + q;
+        if (t < ntiles) local += tile_sums[t];
+    }
+    buf[threadIdx.x] = local;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the per-thread totals
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int v = (threadIdx.x >= (unsigned)o) ? buf[threadIdx.x - o] : 0;
+        __syncthreads();
+        buf[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = buf[threadIdx.x] - local;   // exclusive prefix of this thread
+    for (int q = 0; q < per; ++q) {
+        const int t = start + q;
+        if (t < ntiles) {
+            const int v = tile_sums[t];
+            tile_sums[t] = run;
+            run += v;
+        }
+    }
+    if (threadIdx.x == 1023) sc->sort_total[species] = buf[1023];
+}
+
+__global__ void k_scan_down(int32_t *data, int32_t nbins, const int32_t *tile_offsets)
+{
+    // one block of SCAN_TILE threads per tile
+    __shared__ int32_t buf[SCAN_TILE];
+    const int b = blockIdx.x * SCAN_TILE + threadIdx.x;
+    const int v = (b < nbins) ? data[b] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < SCAN_TILE; o <<= 1) {
+        const int a = (threadIdx.x >= (unsigned)o) ? buf[threadIdx.x - o] : 0;
+        __syncthreads();
+        buf[threadIdx.x] += a;
+        __syncthreads();
+    }
+    if (b < nbins) data[b] = tile_offsets[blockIdx.x] + buf[threadIdx.x] - v;
+}
+
+template <typename T>
+__global__ void k_sort_scatter(SpeciesDev<T> src, SpeciesDev<T> dst, const DevScalars *sc,
+                               int species, int32_t nr, int32_t *off)
+{
+    const int64_t n = sc->count[species];
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += stride) {
+        const int64_t p = b + threadIdx.x;
+        const int k = (p < n) ? src.key[p] : -1;
+        const bool valid = k >= 0;
+        const int bin = valid ? (k >> 16) * nr + (k & 0xffff) : -1;
+        int head, len;
+        wave_runs(bin, valid, lane, head, len);
+        int base = 0;
+        if (valid && head == lane) base = atomicAdd(&off[bin], len);
+        base = __shfl(base, head, 64);
+        if (valid) {
+            const int64_t d = (int64_t)base + (lane - head);
+            dst.key[d] = k;
+            dst.fr[d] = src.fr[p];
+            dst.fz[d] = src.fz[p];
+            dst.vr[d] = src.vr[p];
+            dst.vt[d] = src.vt[p];
+            dst.vz[d] = src.vz[p];
+            dst.id[d] = src.id[p];
+        }
+    }
+}
+
+__global__ void k_sort_finish(DevScalars *sc, int species)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) sc->count[species] = sc->sort_total[species];
+}
+
+}  // namespace
+
+template <typename T>
+void launch_sort(SpeciesDev<T> src, SpeciesDev<T> dst, DevScalars *sc, int species,
+                 int32_t *hist, int32_t *block_sums, int32_t nr, int32_t nz, int64_t cap,
+                 hipStream_t s)
+{
+    const int32_t nbins = nr * nz;
+    const int ntiles = (nbins + SCAN_TILE - 1) / SCAN_TILE;
+    launch_zero(hist, (int64_t)nbins * 4, s);
+    int blocks = (int)((cap + 255) / 256);
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(256), 0, s, src.key, sc, species, nr, hist);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, hist, nbins, block_sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, block_sums, ntiles, sc, species);
+    hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(SCAN_TILE), 0, s, hist, nbins, block_sums);
+    hipLaunchKernelGGL((k_sort_scatter<T>), dim3(blocks), dim3(256), 0, s, src, dst, sc, species,
+                       nr, hist);
+    hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(64), 0, s, sc, species);
+}
+
+template void launch_sort<float>(SpeciesDev<float>, SpeciesDev<float>, DevScalars *, int,
+                                 int32_t *, int32_t *, int32_t, int32_t, int64_t, hipStream_t);
+template void launch_sort<double>(SpeciesDev<double>, SpeciesDev<double>, DevScalars *, int,
+                                  int32_t *, int32_t *, int32_t, int32_t, int64_t, hipStream_t);
+
+}  // namespace pic

@@ -1,0 +1,208 @@
+"""Python front end of libpic.so.
+
+Torch provides the device workspace and the stream; every step of the
+timestep runs in the HIP library behind the C ABI.  Importing this module
+never falls back to a CPU path: without the built library it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+from . import workloads as W
+
+
+def make_config(prob: W.Problem, b_r, b_z, sigma, de_table=W.DE_TABLE, capacity=None):
+    """pic_config from a Problem; returns (config, keep-alive arrays)."""
+    sig = np.ascontiguousarray(sigma, np.float64)
+    br = np.ascontiguousarray(b_r, np.float64)
+    bz = np.ascontiguousarray(b_z, np.float64)
+    c = L.pic_config()
+    c.nr, c.nz = prob.nr, prob.nz
+    c.lr, c.lz, c.dt = prob.lr, prob.lz, prob.dt
+    c.scheme, c.precision = prob.scheme, prob.precision
+    c.cathode_rmax = prob.cathode_rmax
+    c.circuit = prob.circuit
+    c.v_fixed, c.v_ext, c.r_ext = prob.v_fixed, prob.v_ext, prob.r_ext
+    c.gamma_i = prob.gamma_i
+    c.p_gas, c.t_gas = prob.p_gas, prob.t_gas
+    c.e_exc, c.e_iz = prob.e_exc, prob.e_iz
+    c.sigma = sig.ctypes.data_as(C.POINTER(C.c_double))
+    c.n_table = sig.shape[1]
+    c.de_table = de_table
+    c.b_r = br.ctypes.data_as(C.POINTER(C.c_double))
+    c.b_z = bz.ctypes.data_as(C.POINTER(C.c_double))
+    for s, (q, m, w) in enumerate(prob.species()):
+        c.q[s], c.m[s], c.w[s] = q, m, w
+    c.seed = prob.seed
+    c.run = prob.run
+    cap = capacity or prob.capacity()
+    c.capacity[0], c.capacity[1] = int(cap[0]), int(cap[1])
+    c.sort_every = prob.sort_every
+    c.poisson_mode = 0
+    c.poisson_rtol = prob.poisson_rtol
+    c.poisson_maxit = prob.poisson_maxit
+    for k in range(3):
+        c.wall_bc[k] = prob.wall_bc[k]
+    c.frozen_ions, c.mcc_on, c.see_on = prob.frozen_ions, prob.mcc_on, prob.see_on
+    c.field_solve = prob.field_solve
+    c.extra_current = prob.extra_current
+    return c, (sig, br, bz)
+
+
+class Simulation:
+    """One discharge on one GPU.
+
+    ``particles`` is a pair of :class:`workloads.SpeciesArrays` (host FP64,
+    absolute positions) or None.
+    """
+
+    def __init__(self, prob: W.Problem, b_r, b_z, sigma, particles=None, device="cuda:0",
+                 capacity=None, timers=False):
+        import torch
+
+        self.torch = torch
+        self.prob = prob
+        self.lib = L.load()
+        self.device = torch.device(device)
+        cfg, keep = make_config(prob, b_r, b_z, sigma, capacity=capacity)
+        self.cfg = cfg
+        nbytes = C.c_int64()
+        L.check(self.lib.pic_query_workspace(C.byref(cfg), C.byref(nbytes)))
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        hosts = (L.pic_species_host * 2)()
+        keep_p = []
+        if particles is not None:
+            for s in range(2):
+                p = particles[s]
+                arrs = [np.ascontiguousarray(getattr(p, k), np.float64)
+                        for k in ("r", "z", "vr", "vt", "vz")]
+                ids = np.ascontiguousarray(p.id, np.uint32)
+                keep_p.append((arrs, ids))
+                h = hosts[s]
+                h.r, h.z, h.vr, h.vt, h.vz = (a.ctypes.data_as(C.POINTER(C.c_double)) for a in arrs)
+                h.id = ids.ctypes.data_as(C.POINTER(C.c_uint32))
+                h.n = p.n
+        handle = C.c_void_p()
+        status = self.lib.pic_init(C.byref(cfg), C.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                   C.c_void_p(self.stream.cuda_stream),
+                                   hosts if particles is not None else None, C.byref(handle))
+        L.check(status, None)
+        self.h = handle
+        del keep, keep_p
+        if timers:
+            L.check(self.lib.pic_enable_timers(self.h, 1), self.h)
+
+    # -- stepping ------------------------------------------------------------
+    def step(self, n=1):
+        L.check(self.lib.pic_step(self.h, int(n)), self.h)
+
+    def diag(self):
+        d = L.pic_diag_out()
+        L.check(self.lib.pic_diag(self.h, C.byref(d)), self.h)
+        return d.as_dict()
+
+    def compact(self):
+        L.check(self.lib.pic_compact(self.h), self.h)
+
+    def poisson(self, q, v_cathode, phi):
+        """Solve K phi = q in place on device tensors (float64); returns stats."""
+        st = L.pic_poisson_stats()
+        status = self.lib.pic_poisson(self.h, C.c_void_p(q.data_ptr()), float(v_cathode),
+                                      C.c_void_p(phi.data_ptr()), C.byref(st))
+        L.check(status, self.h)
+        return st.as_dict()
+
+    def poisson_status(self, q, v_cathode, phi):
+        st = L.pic_poisson_stats()
+        status = self.lib.pic_poisson(self.h, C.c_void_p(q.data_ptr()), float(v_cathode),
+                                      C.c_void_p(phi.data_ptr()), C.byref(st))
+        return status, st.as_dict()
+
+    def set_phi(self, phi):
+        a = np.ascontiguousarray(phi, np.float64)
+        L.check(self.lib.pic_set_phi(self.h, a.ctypes.data_as(C.POINTER(C.c_double))), self.h)
+
+    def get_state(self):
+        s = L.pic_scalar_state()
+        L.check(self.lib.pic_get_state(self.h, C.byref(s)), self.h)
+        return {"step": s.step, "vc": s.vc, "qc": s.qc, "next_id": tuple(s.next_id),
+                "count": tuple(s.count)}
+
+    def set_state(self, st):
+        s = L.pic_scalar_state()
+        s.step, s.vc, s.qc = st["step"], st["vc"], st["qc"]
+        s.next_id[0], s.next_id[1] = st["next_id"]
+        s.count[0], s.count[1] = st["count"]
+        L.check(self.lib.pic_set_state(self.h, C.byref(s)), self.h)
+
+    def timers(self, reset=True):
+        t = L.pic_timers()
+        L.check(self.lib.pic_get_timers(self.h, C.byref(t), int(reset)), self.h)
+        return t.as_dict()
+
+    # -- views into the workspace -------------------------------------------
+    def _view(self, ptr, n, dtype):
+        torch = self.torch
+        esz = torch.empty(0, dtype=dtype).element_size()
+        off = int(ptr) - self.ws.data_ptr()
+        assert 0 <= off and off + n * esz <= self.ws.numel()
+        return self.ws[off:off + n * esz].view(dtype)
+
+    def particle_tensors(self, s):
+        v = L.pic_particle_view()
+        L.check(self.lib.pic_particles(self.h, int(s), C.byref(v)), self.h)
+        torch = self.torch
+        ft = torch.float64 if v.precision == 1 else torch.float32
+        n = int(v.count)
+        out = {"key": self._view(v.key_dev, n, torch.int32), "id": self._view(v.id_dev, n, torch.int32)}
+        for k in ("fr", "fz", "vr", "vt", "vz"):
+            out[k] = self._view(getattr(v, k + "_dev"), n, ft)
+        return out
+
+    def particles(self, s, raw=False):
+        """Live particles of species s as host arrays (positions absolute, FP64)."""
+        t = self.particle_tensors(s)
+        self.torch.cuda.synchronize(self.device)
+        key = t["key"].cpu().numpy()
+        live = key >= 0
+        out = {k: v.cpu().numpy()[live] for k, v in t.items()}
+        out["id"] = out["id"].view(np.uint32)
+        i = (out["key"] & 0xFFFF).astype(np.float64)
+        j = (out["key"] >> 16).astype(np.float64)
+        out["i"] = i.astype(np.int64)
+        out["j"] = j.astype(np.int64)
+        out["r"] = (i + out["fr"].astype(np.float64)) * self.prob.dr
+        out["z"] = (j + out["fz"].astype(np.float64)) * self.prob.dz
+        for k in ("vr", "vt", "vz", "fr", "fz"):
+            out[k] = out[k].astype(np.float64)
+        return out
+
+    def fields(self):
+        v = L.pic_field_view()
+        L.check(self.lib.pic_fields(self.h, C.byref(v)), self.h)
+        torch = self.torch
+        n = int(v.nodes)
+        qt = torch.float64 if v.q_precision == 1 else torch.float32
+        return {"phi": self._view(v.phi_dev, n, torch.float64),
+                "phi0": self._view(v.phi0_dev, n, torch.float64),
+                "phi_l": self._view(v.phi_l_dev, n, torch.float64),
+                "q_e": self._view(v.q_dev[0], n, qt), "q_i": self._view(v.q_dev[1], n, qt)}
+
+    def fields_host(self):
+        self.torch.cuda.synchronize(self.device)
+        return {k: v.cpu().numpy().astype(np.float64) for k, v in self.fields().items()}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pic_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -127,6 +127,9 @@ class Problem:
         return (c, c)
 
     def replace(self, **kw) -> "Problem":
+        # a cathode spanning the whole z = 0 plane keeps doing so when lr changes
+        if "lr" in kw and "cathode_rmax" not in kw and self.cathode_rmax == self.lr:
+            kw["cathode_rmax"] = kw["lr"]
         return dataclasses.replace(self, **kw)
 
 

@@ -1,0 +1,70 @@
+"""The C ABI: libpic.so loads on the CPU host and exports every entry point
+that include/pic.h declares; configuration checks need no GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2507_10727_amd import _lib as L
+from paper_2507_10727_amd import workloads as W
+from paper_2507_10727_amd.sim import make_config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "pic.h")).read()
+    return sorted(set(re.findall(r"\b(pic_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_names_match_binding():
+    assert sorted(L.EXPORTS) == declared()
+
+
+def test_library_exports_all_symbols():
+    lib = L.load()
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def _cfg(**kw):
+    p = W.preset("small_mc64_f64").replace(**kw)
+    br, bz = W.magnetron_field(p)
+    sig = W.cross_sections()
+    return make_config(p, br, bz, sig)
+
+
+def test_query_workspace_sizes():
+    lib = L.load()
+    cfg, keep = _cfg()
+    n = C.c_int64()
+    assert lib.pic_query_workspace(C.byref(cfg), C.byref(n)) == 0
+    # particles dominate: two buffers x 2 species x cap x 48 B in FP64
+    cap = cfg.capacity[0]
+    assert n.value > 2 * 2 * cap * 48
+    assert n.value < 2 * 2 * cap * 48 + 64 * 1024 * 1024
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nr=1), dict(nz=40000), dict(dt=0.0), dict(scheme=7), dict(precision=3),
+    dict(circuit=W.RESISTOR, r_ext=0.0), dict(cathode_rmax=1.0), dict(sort_every=0),
+    dict(poisson_rtol=0.0), dict(poisson_maxit=0), dict(wall_bc=(0, 5, 0)),
+    dict(nr=101, nz=101),
+])
+def test_invalid_configs_rejected(bad):
+    lib = L.load()
+    cfg, keep = _cfg(**bad)
+    n = C.c_int64()
+    st = lib.pic_query_workspace(C.byref(cfg), C.byref(n))
+    assert st == L.PIC_EINVAL
+    assert lib.pic_last_error(None)
+
+
+def test_init_rejects_missing_workspace():
+    lib = L.load()
+    cfg, keep = _cfg()
+    h = C.c_void_p()
+    st = lib.pic_init(C.byref(cfg), None, 0, None, None, C.byref(h))
+    assert st == L.PIC_EINVAL and not h.value
+    assert b"workspace" in lib.pic_last_error(None)
