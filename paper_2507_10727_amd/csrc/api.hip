@@ -58,6 +58,8 @@ struct pic_handle {
     int64_t host_count[2] = {0, 0};
     int steps_since_sort = 0;
     pic_poisson_stats last = {};
+    double rho = 0.15, rel0_est = 1e-2;
+    int32_t host_flags = 0;
     bool timers_on = false;
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> free_events;
@@ -178,7 +180,8 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     DevScalars *sc = cv.take<DevScalars>(sizeof(DevScalars));
     Buf bufs[2][2];
     for (int s = 0; s < 2; ++s) {
-        const int64_t cap = s ? cap1 : cap0;
+        // slots rounded up to 4: the particle kernel moves 4 consecutive slots
+        const int64_t cap = ((s ? cap1 : cap0) + 3) & ~(int64_t)3;
         for (int b = 0; b < 2; ++b) {
             Buf &B = bufs[s][b];
             B.key = cv.take<int32_t>(cap * 4);
@@ -213,32 +216,52 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     f.b_z = cv.take<double>(nodes * 8);
     f.vdep = cv.take<double>(nodes * 8);
     f.e32 = cv.take<float>(nodes * 4);
-    f.r32 = cv.take<float>(nodes * 4);
-    f.z32 = cv.take<float>(nodes * 4);
-    f.p32 = cv.take<float>(nodes * 4);
     f.q32 = cv.take<float>(nodes * 4);
+    f.p32[0] = cv.take<float>(nodes * 4);
+    f.p32[1] = cv.take<float>(nodes * 4);
     auto shapes = mg_shapes(c);
-    f.nlevels = (int)shapes.size();
-    for (int l = 0; l < f.nlevels; ++l) {
+    MGHier &H = f.mg;
+    H.nlevels = (int)shapes.size();
+    for (int l = 0; l < H.nlevels; ++l) {
         const int64_t nl = (int64_t)(shapes[l].nr + 1) * (shapes[l].nz + 1);
-        Level &L = f.lv[l];
+        MGLevel &L = H.lv[l];
         L.nr = shapes[l].nr;
         L.nz = shapes[l].nz;
-        L.ce = cv.take<float>(nl * 4);
-        L.cn = cv.take<float>(nl * 4);
-        L.dinv = cv.take<float>(nl * 4);
-        if (l == 0) {
-            L.x = f.z32;
-            L.b = f.r32;
-        } else {
-            L.x = cv.take<float>(nl * 4);
-            L.b = cv.take<float>(nl * 4);
+        L.cath = 0;
+        for (int i = 0; i < L.nr; ++i)
+            if (host_node_kind(L.nr, L.nz, c.lr, c.cathode_rmax, i, 0) == 1) L.cath = i + 1;
+        const double dr = c.lr / L.nr, dz = c.lz / L.nz;
+        L.dz = (float)dz;
+        L.dr2dz = (float)(dr * dr / dz);
+        L.b = cv.take<float>(nl * 4);
+        L.xd = cv.take<float>(nl * 4);
+        L.xu = cv.take<float>(nl * 4);
+    }
+    // the coarse levels small enough for one workgroup (<= 2600 nodes on
+    // the first of them) run in the tail kernel, all in LDS
+    int first = H.nlevels - 1;
+    for (int l = 0; l < H.nlevels; ++l) {
+        int64_t words = (int64_t)(shapes[l].nr + 1) * (shapes[l].nz + 1);
+        const int64_t top = words;
+        for (int m = l; m < H.nlevels; ++m)
+            words += 2 * (int64_t)(shapes[m].nr + 1) * (shapes[m].nz + 1);
+        if (top <= 2600 && words * 4 <= 128 * 1024) {
+            first = l;
+            break;
         }
     }
+    H.tail.first = first;
+    H.tail.last = H.nlevels - 1;
+    H.tail.tmp_size = (shapes[first].nr + 1) * (shapes[first].nz + 1);
+    int64_t words = H.tail.tmp_size;
+    for (int m = first; m < H.nlevels; ++m)
+        words += 2 * (int64_t)(shapes[m].nr + 1) * (shapes[m].nz + 1);
+    H.tail_lds_bytes = (int32_t)(words * 4);
+    for (int l = 0; l < H.nlevels; ++l) H.tail.L[l] = H.lv[l];
     const int cu = coarse_unknowns(c, shapes.back());
-    f.coarse_n = cu;
-    f.coarse_inv = cv.take<float>((int64_t)cu * cu * 4);
-    f.coarse_map = cv.take<int32_t>((int64_t)cu * 4);
+    H.tail.ninv = cu;
+    H.tail.inv = cv.take<float>((int64_t)cu * cu * 4);
+    H.tail.map = cv.take<int32_t>((int64_t)cu * 4);
     const int32_t nbins = c.nr * c.nz;
     int32_t *hist = cv.take<int32_t>((int64_t)nbins * 4);
     int32_t *bsums = cv.take<int32_t>((int64_t)((nbins + 1023) / 1024) * 4);
@@ -337,135 +360,160 @@ pic_status setup_field(pic_handle *h)
     HIPCHECK(h, hipMemcpy((void *)h->f.b_r, c.b_r, nodes * 8, hipMemcpyHostToDevice));
     HIPCHECK(h, hipMemcpy((void *)h->f.b_z, c.b_z, nodes * 8, hipMemcpyHostToDevice));
 
-    for (int l = 0; l < h->f.nlevels; ++l) {
-        const LevelShape &s = h->levels[l];
+    // dense inverse of the coarsest level's operator (couplings / (2 pi eps0))
+    {
+        MGHier &H = h->f.mg;
+        const LevelShape &s = h->levels[H.nlevels - 1];
         const int64_t nl = (int64_t)(s.nr + 1) * (s.nz + 1);
         std::vector<double> a(nl), b(nl);
-        host_couplings(s.nr, s.nz, s.lr, s.lz, 1.0, a.data(), b.data());
-        std::vector<float> fa(nl), fb(nl), fd(nl);
-        for (int j = 0; j <= s.nz; ++j)
-            for (int i = 0; i <= s.nr; ++i) {
-                const int64_t n = (int64_t)j * (s.nr + 1) + i;
-                fa[n] = (float)a[n];
-                fb[n] = (float)b[n];
-                const int k = host_node_kind(s.nr, s.nz, c.lr, c.cathode_rmax, i, j);
-                double d = 0.0;
-                if (i < s.nr) d += a[n];
-                if (i > 0) d += a[n - 1];
-                if (j < s.nz) d += b[n];
-                if (j > 0) d += b[n - (s.nr + 1)];
-                fd[n] = (k == 0) ? (float)(1.0 / d) : 0.0f;
+        const double scale = 2.0 * 3.14159265358979323846;
+        host_couplings(s.nr, s.nz, s.lr, s.lz, 1.0 / scale, a.data(), b.data());
+        std::vector<int32_t> map;
+        std::vector<int> idx(nl, -1);
+        const int ld = s.nr + 1;
+        for (int64_t n = 0; n < nl; ++n) {
+            const int j = (int)(n / ld), i = (int)(n % ld);
+            if (host_node_kind(s.nr, s.nz, c.lr, c.cathode_rmax, i, j) == 0) {
+                idx[n] = (int)map.size();
+                map.push_back((int32_t)n);
             }
-        const Level &L = h->f.lv[l];
-        HIPCHECK(h, hipMemcpy(L.ce, fa.data(), nl * 4, hipMemcpyHostToDevice));
-        HIPCHECK(h, hipMemcpy(L.cn, fb.data(), nl * 4, hipMemcpyHostToDevice));
-        HIPCHECK(h, hipMemcpy(L.dinv, fd.data(), nl * 4, hipMemcpyHostToDevice));
-        launch_zero(L.x, nl * 4, h->stream);
-        launch_zero(L.b, nl * 4, h->stream);
-        if (l == h->f.nlevels - 1) {
-            // dense inverse of the coarsest operator on its unknowns
-            std::vector<int32_t> map;
-            std::vector<int> idx(nl, -1);
-            for (int64_t n = 0; n < nl; ++n)
-                if (fd[n] != 0.0f) {
-                    idx[n] = (int)map.size();
-                    map.push_back((int32_t)n);
-                }
-            const int m = (int)map.size();
-            std::vector<double> A((size_t)m * m, 0.0);
-            const int ld = s.nr + 1;
-            for (int u = 0; u < m; ++u) {
-                const int64_t n = map[u];
-                const int j = (int)(n / ld), i = (int)(n % ld);
-                double d = 0.0;
-                auto add = [&](int64_t nb, double cpl) {
-                    d += cpl;
-                    if (idx[nb] >= 0) A[(size_t)u * m + idx[nb]] -= cpl;
-                };
-                if (i < s.nr) add(n + 1, a[n]);
-                if (i > 0) add(n - 1, a[n - 1]);
-                if (j < s.nz) add(n + ld, b[n]);
-                if (j > 0) add(n - ld, b[n - ld]);
-                A[(size_t)u * m + u] += d;
-            }
-            if (m > 0 && host_dense_inverse(m, A.data()) != 0)
-                return fail(h, PIC_EINVAL, "coarsest operator is singular");
-            std::vector<float> Af(A.begin(), A.end());
-            if (m > 0) {
-                HIPCHECK(h, hipMemcpy((void *)h->f.coarse_inv, Af.data(), (size_t)m * m * 4,
-                                      hipMemcpyHostToDevice));
-                HIPCHECK(h, hipMemcpy((void *)h->f.coarse_map, map.data(), (size_t)m * 4,
-                                      hipMemcpyHostToDevice));
-            }
-            h->f.coarse_n = m;
         }
+        const int m = (int)map.size();
+        std::vector<double> A((size_t)m * m, 0.0);
+        for (int u = 0; u < m; ++u) {
+            const int64_t n = map[u];
+            const int j = (int)(n / ld), i = (int)(n % ld);
+            double d = 0.0;
+            auto add = [&](int64_t nb, double cpl) {
+                d += cpl;
+                if (idx[nb] >= 0) A[(size_t)u * m + idx[nb]] -= cpl;
+            };
+            if (i < s.nr) add(n + 1, a[n]);
+            if (i > 0) add(n - 1, a[n - 1]);
+            if (j < s.nz) add(n + ld, b[n]);
+            if (j > 0) add(n - ld, b[n - ld]);
+            A[(size_t)u * m + u] += d;
+        }
+        if (m > 0 && host_dense_inverse(m, A.data()) != 0)
+            return fail(h, PIC_EINVAL, "coarsest operator is singular");
+        std::vector<float> Af(A.begin(), A.end());
+        if (m > 0) {
+            HIPCHECK(h, hipMemcpy((void *)H.tail.inv, Af.data(), (size_t)m * m * 4,
+                                  hipMemcpyHostToDevice));
+            HIPCHECK(h, hipMemcpy((void *)H.tail.map, map.data(), (size_t)m * 4,
+                                  hipMemcpyHostToDevice));
+        }
+        H.tail.ninv = m;
+        for (int l = 0; l < H.nlevels; ++l) {
+            const int64_t n = (int64_t)(H.lv[l].nr + 1) * (H.lv[l].nz + 1);
+            launch_zero(H.lv[l].b, n * 4, h->stream);
+            launch_zero(H.lv[l].xd, n * 4, h->stream);
+            launch_zero(H.lv[l].xu, n * 4, h->stream);
+        }
+        if (mg_tail_setup(H) != 0)
+            return fail(h, PIC_EHIP, "cannot reserve %d bytes of LDS for the coarse levels",
+                        H.tail_lds_bytes);
     }
     launch_zero(h->f.e32, nodes * 4, h->stream);
-    launch_zero(h->f.p32, nodes * 4, h->stream);
+    launch_zero(h->f.p32[0], nodes * 4, h->stream);
+    launch_zero(h->f.p32[1], nodes * 4, h->stream);
     launch_zero(h->f.q32, nodes * 4, h->stream);
     return PIC_OK;
 }
 
 // ---- field solve: FP64 iterative refinement around an FP32 MG-PCG
+//
+// A pass: FP64 residual r = q - K phi (norm kept on the device), r / ||r||
+// to FP32, a fixed number of conjugate-gradient iterations on the FP32
+// operator K / (2 pi eps0) preconditioned by one multigrid V-cycle each,
+// phi += e ||r|| / (2 pi eps0) in FP64, and the FP64 residual of the result,
+// read back with the step's flags and counts in one copy (the pass's only
+// synchronization).  The iteration count is predicted from earlier solves
+// and, for a further pass, from the convergence rate the last pass reached.
+struct SolveReadback {
+    double rr, bb, rr0;
+    int32_t flags, pad;
+    int64_t count[2];
+};
+
+pic_status readback(pic_handle *h, SolveReadback *rb)
+{
+    static_assert(sizeof(SolveReadback) == 48, "readback layout");
+    HIPCHECK(h, hipMemcpyAsync(rb, &h->sc->res_rr, sizeof(SolveReadback), hipMemcpyDeviceToHost,
+                               h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    h->host_count[0] = rb->count[0];
+    h->host_count[1] = rb->count[1];
+    h->host_flags = rb->flags;
+    return PIC_OK;
+}
+
 template <typename Q>
 pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_cathode,
                  pic_poisson_stats *st)
 {
     hipStream_t s = h->stream;
-    const FieldDev &f = h->f;
+    FieldDev &f = h->f;
+    const MGHier &H = f.mg;
     const double rtol = h->cfg.poisson_rtol;
     const int maxit = h->cfg.poisson_maxit;
-    const double e0 = eps0();
+    const double inv_2pi_eps0 = 1.0 / (2.0 * 3.14159265358979323846 * eps0());
     pic_poisson_stats S = {};
     launch_set_dirichlet(f, phi, v_cathode, s);
-    const int max_outer = 12;
-    for (int outer = 0;; ++outer) {
+    launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
+    // iterations for a target reduction at the measured rate; one FP32 pass
+    // is asked for at most 1e-6 (about what single precision delivers)
+    auto iters_for = [&](double rel_now) {
+        const double target = std::max(0.5 * rtol / rel_now, 1e-6);
+        if (target >= 1.0) return 1;
+        const int n = (int)std::ceil(std::log(target) / std::log(h->rho));
+        return std::max(1, std::min(n, 64));
+    };
+    int n_iter = iters_for(h->rel0_est);
+    const int max_pass = 12;
+    for (int pass = 0;; ++pass) {
+        if (pass == max_pass || S.iterations >= maxit) break;
+        n_iter = std::max(1, std::min(n_iter, maxit - S.iterations));
+        launch_cast_scale(f, h->sc, s);
+        launch_zero(h->sc->pcg_rz, sizeof(double) * 3 * (MAX_PCG + 2), s);
+        launch_mg_vcycle(H, &h->sc->pcg_rz[0], s);
+        for (int k = 0; k < n_iter; ++k) {
+            launch_cg_matvec(H, H.lv[0].xu, f.p32[(k + 1) & 1], f.p32[k & 1], f.q32,
+                             h->sc->pcg_rz, k, &h->sc->pcg_pq[k], s);
+            launch_cg_update(H, f.p32[k & 1], f.q32, f.e32, H.lv[0].b, &h->sc->pcg_rz[k],
+                             &h->sc->pcg_pq[k], &h->sc->pcg_rr[k], s);
+            if (k + 1 < n_iter) launch_mg_vcycle(H, &h->sc->pcg_rz[k + 1], s);
+        }
+        S.iterations += n_iter;
+        S.outer++;
+        launch_update64(f, phi, h->sc, inv_2pi_eps0, s);
         launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
-        double nrm[2];
-        HIPCHECK(h, hipMemcpyAsync(nrm, &h->sc->res_rr, 16, hipMemcpyDeviceToHost, s));
-        HIPCHECK(h, hipStreamSynchronize(s));
-        const double rr = nrm[0], bb = nrm[1];
-        if (!std::isfinite(rr) || !std::isfinite(bb)) {
+        SolveReadback rb;
+        pic_status e = readback(h, &rb);
+        if (e != PIC_OK) return e;
+        if (!std::isfinite(rb.rr) || !std::isfinite(rb.bb)) {
             S.rel_res = NAN;
             h->last = S;
             if (st) *st = S;
             return fail(h, PIC_ENAN, "non-finite residual in the field solve");
         }
-        if (bb == 0.0) {
+        if (rb.bb == 0.0) {
             launch_zero_unknowns(f, phi, s);
             S.rel_res = 0.0;
             S.converged = 1;
             break;
         }
-        S.rel_res = std::sqrt(rr / bb);
-        if (S.rel_res <= rtol) {
+        const double rel0 = std::sqrt(rb.rr0 / rb.bb), rel = std::sqrt(rb.rr / rb.bb);
+        S.rel_res = rel;
+        if (pass == 0 && rel0 > 0.0) h->rel0_est = rel0;
+        // per-iteration rate, from passes that precision did not limit
+        if (rel0 > 0.0 && rel < rel0 && rel / rel0 > 1e-5)
+            h->rho = std::min(std::max(std::pow(rel / rel0, 1.0 / n_iter), 0.01), 0.9);
+        if (rel <= rtol) {
             S.converged = 1;
             break;
         }
-        if (outer >= max_outer || S.iterations >= maxit) break;
-        S.outer++;
-        const double rn = std::sqrt(rr);
-        launch_cast_scale(f, 1.0 / rn, s);
-        // inner FP32 preconditioned CG on K_uu e = r / ||r||
-        const double inner_tol = std::max(0.3 * rtol / S.rel_res, 2e-6);
-        launch_zero(h->sc->pcg_rz, sizeof(double) * 3 * (MAX_PCG + 2), s);
-        launch_vcycle(f, s);
-        launch_pcg_dot_rz(f, h->sc, 0, s);
-        launch_copy_f32(f.p32, f.z32, (int64_t)(f.nr + 1) * (f.nz + 1), s);
-        int k = 0;
-        for (; k < MAX_PCG && S.iterations < maxit; ++k) {
-            launch_pcg_matvec_dot(f, h->sc, k, s);
-            launch_pcg_update(f, h->sc, k, s);
-            S.iterations++;
-            double rrk;
-            HIPCHECK(h, hipMemcpyAsync(&rrk, &h->sc->pcg_rr[k], 8, hipMemcpyDeviceToHost, s));
-            HIPCHECK(h, hipStreamSynchronize(s));
-            if (!(std::sqrt(rrk) > inner_tol)) break;
-            launch_vcycle(f, s);
-            launch_pcg_dot_rz(f, h->sc, k + 1, s);
-            launch_pcg_direction(f, h->sc, k, s);
-        }
-        launch_update64(f, phi, rn / e0, s);
+        n_iter = iters_for(rel);
     }
     h->last = S;
     if (st) *st = S;
@@ -650,6 +698,11 @@ pic_status step_one(pic_handle *h)
             launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, PIC_FIXED_V,
                               0.0, 0.0, 1.0, c.dt, c.extra_current * c.dt, h->stream);
         }
+    }
+    if (c.field_solve) {
+        if (h->host_flags & (FLAG_CAPACITY | FLAG_CHILD_OVERFLOW))
+            return fail(h, PIC_ECAPACITY, "particle capacity exceeded (flags %d)", h->host_flags);
+        return PIC_OK;
     }
     return check_flags(h);
 }

@@ -33,12 +33,16 @@ template <> struct Vec4<double> { using type = double4; };
 
 // Device-resident scalar state of one simulation.
 struct DevScalars {
+    // read back together (one copy) after each field-solve pass
+    double res_rr, res_bb;      // FP64 residual and rhs norms^2
+    double res_rr0;             // residual norm^2 at the start of the pass
+    int32_t flags;
+    int32_t pad_;
     int64_t count[2];           // slots in use per species
     int64_t step;
     uint32_t next_id[2];
     int32_t n_child;            // children recorded this step (all species)
     int32_t n_child_s[2];       // children per new-particle species
-    int32_t flags;
     double dq_conv;             // charge into the cathode this step
     double ke[2], pz[2];
     unsigned long long n_abs[2][5];
@@ -48,7 +52,6 @@ struct DevScalars {
     // sort
     int64_t sort_total[2];
     // field solve accumulators
-    double res_rr, res_bb;      // FP64 residual and rhs norms^2
     double pcg_rz[MAX_PCG + 2], pcg_pq[MAX_PCG + 2], pcg_rr[MAX_PCG + 2];
 };
 
@@ -191,13 +194,40 @@ void launch_sort(SpeciesDev<T> src, SpeciesDev<T> dst, DevScalars *sc, int speci
                  int32_t *hist, int32_t *block_sums, int32_t nr, int32_t nz, int64_t cap,
                  hipStream_t s);
 
-// field.hip (multigrid hierarchy and solver)
-struct Level {
+// mg.hip: matrix-free multigrid levels (couplings / (2 pi eps0))
+struct MGLevel {
     int32_t nr, nz;
-    float *ce, *cn, *dinv;      // couplings / eps0 and inverse diagonal (0 = Dirichlet)
-    float *x, *b;               // correction and right-hand side
+    int32_t cath;               // nodes i < cath of row j = 0 are cathode (Dirichlet)
+    float dz, dr2dz;            // dz and dr^2 / dz of the level
+    float *b;                   // right-hand side
+    float *xd;                  // correction after pre-smoothing (down pass)
+    float *xu;                  // correction after post-smoothing (up pass)
 };
 
+struct MGTail {
+    MGLevel L[MAX_LEVELS];
+    int32_t first, last;        // levels handled inside one workgroup
+    int32_t tmp_size;           // nodes of level `first`
+    const float *inv;           // dense inverse on the coarsest unknowns
+    const int32_t *map;         // unknown index -> node index (coarsest level)
+    int32_t ninv;
+};
+
+struct MGHier {
+    MGLevel lv[MAX_LEVELS];
+    int32_t nlevels;
+    MGTail tail;
+    int32_t tail_lds_bytes;
+};
+
+void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s);   // lv[0].xu = M lv[0].b
+void launch_cg_matvec(const MGHier &H, const float *z, const float *pp, float *pc, float *q,
+                      const double *rz, int k, double *pq, hipStream_t s);
+void launch_cg_update(const MGHier &H, const float *p, const float *q, float *e, float *r,
+                      const double *rz, const double *pq, double *rr, hipStream_t s);
+int mg_tail_setup(MGHier &H);
+
+// field.hip
 struct FieldDev {
     int32_t nr, nz;
     double dr, dz;
@@ -205,12 +235,8 @@ struct FieldDev {
     const uint8_t *kind;        // 0 unknown, 1 cathode, 2 grounded
     double *phi, *phi0, *phi_l;
     double *r64;                // FP64 residual
-    float *e32, *r32, *z32, *p32, *q32;  // inner PCG vectors (finest level)
-    Level lv[MAX_LEVELS];
-    int32_t nlevels;
-    const float *coarse_inv;    // dense inverse on the coarsest level's unknowns
-    const int32_t *coarse_map;  // unknown index -> node index
-    int32_t coarse_n;
+    float *e32, *q32, *p32[2];  // inner CG vectors (finest level)
+    MGHier mg;                  // r32 = mg.lv[0].b, z32 = mg.lv[0].xu
     const double *b_r, *b_z;    // static nodal B
     const double *vdep;         // node volumes for densities
 };
@@ -219,14 +245,11 @@ void launch_zero(void *p, int64_t bytes, hipStream_t s);
 template <typename T>
 void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const T *q1,
                        DevScalars *sc, hipStream_t s);
-void launch_cast_scale(const FieldDev &f, double scale, hipStream_t s);
-void launch_update64(const FieldDev &f, double *phi, double scale, hipStream_t s);
-void launch_vcycle(const FieldDev &f, hipStream_t s);   // z32 = M r32
-void launch_pcg_matvec_dot(const FieldDev &f, DevScalars *sc, int k, hipStream_t s);
-void launch_pcg_update(const FieldDev &f, DevScalars *sc, int k, hipStream_t s);
-void launch_pcg_dot_rz(const FieldDev &f, DevScalars *sc, int k, hipStream_t s);
-void launch_pcg_direction(const FieldDev &f, DevScalars *sc, int k, hipStream_t s);
-void launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s);
+// r32 = r64 / ||r64|| (norm read on the device), e32 = 0
+void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s);
+// phi += e32 ||r64|| / (2 pi eps0) on unknown nodes
+void launch_update64(const FieldDev &f, double *phi, const DevScalars *sc, double inv_2pi_eps0,
+                     hipStream_t s);
 template <typename T>
 void launch_circuit(const FieldDev &f, const T *q0, const T *q1, DevScalars *sc, int circuit,
                     double v_fixed, double v_ext, double r_ext, double dt, double extra_dq,

@@ -1,19 +1,14 @@
 // Field kernels of libpic.so: FP64 residual and refinement of the R-Z
-// charge-form operator, the FP32 geometric-multigrid preconditioner and
-// conjugate-gradient pieces, the cathode circuit, the gather-field packing
-// and grid diagnostics.
+// charge-form operator, the cathode circuit, the gather-field packing and
+// grid diagnostics (the FP32 multigrid/CG inner solve is in mg.hip).
 //
 // Operator (reading of Section 3's "Gauss' law is obeyed along this axis"):
 //   (K phi)_n = sum over the faces f of node n of c_f (phi_n - phi_nb),
 // c_f = eps0 A_f / h_f of the clipped control volume; Dirichlet nodes are the
 // anode row, the outer column and the cathode part of z = 0.  The FP32
-// hierarchy stores c_f / eps0 and solves the correction equation
+// inner solve (mg.hip) works on K / (2 pi eps0) for the correction equation
 // K_uu e = r of the FP64 refinement, with zero correction on Dirichlet
-// nodes.  Levels are vertex-centred (coarse node (I, J) = fine (2I, 2J)),
-// re-discretised with the same face rule; prolongation is bilinear,
-// restriction its transpose (charge is summed, so total charge is kept), the
-// smoother red-black Gauss-Seidel (red-black before, black-red after, so the
-// V-cycle is a symmetric preconditioner), the coarsest level a dense inverse.
+// nodes.
 #include "common.h"
 
 namespace pic {
@@ -93,188 +88,23 @@ __global__ void __launch_bounds__(FB) k_residual64(int32_t nr, int32_t nz, const
     }
 }
 
-__global__ void k_cast_scale(int64_t nn, const double *r64, double scale, float *r32, float *e32)
+__global__ void k_cast_scale(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32)
 {
+    const double rr = sc->res_rr;
+    const double scale = (rr > 0.0) ? 1.0 / sqrt(rr) : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->res_rr0 = rr;
     for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
         r32[n] = (float)(r64[n] * scale);
         e32[n] = 0.0f;
     }
 }
 
-__global__ void k_update64(int64_t nn, const uint8_t *kind, double *phi, const float *e32, double scale)
+__global__ void k_update64(int64_t nn, const uint8_t *kind, double *phi, const float *e32,
+                           const DevScalars *sc, double inv_2pi_eps0)
 {
+    const double scale = sqrt(sc->res_rr0) * inv_2pi_eps0;
     for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB)
         if (kind[n] == 0) phi[n] += (double)e32[n] * scale;
-}
-
-// (A x)_n of a level (couplings / eps0), unknown node n.
-__device__ __forceinline__ float level_ax(const Level &L, const float *x, int i, int j, int64_t n,
-                                          float *diag_out)
-{
-    const int ld = L.nr + 1;
-    float diag = 0.0f, off = 0.0f;
-    if (i < L.nr) { const float c = L.ce[n]; diag += c; off += c * x[n + 1]; }
-    if (i > 0) { const float c = L.ce[n - 1]; diag += c; off += c * x[n - 1]; }
-    if (j < L.nz) { const float c = L.cn[n]; diag += c; off += c * x[n + ld]; }
-    if (j > 0) { const float c = L.cn[n - ld]; diag += c; off += c * x[n - ld]; }
-    *diag_out = diag;
-    return diag * x[n] - off;
-}
-
-// First half-sweep from a zero guess: red unknowns x = b / diag, black 0.
-__global__ void k_smooth_first(Level L)
-{
-    const int ld = L.nr + 1;
-    const int64_t nn = (int64_t)ld * (L.nz + 1);
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
-        const float d = L.dinv[n];
-        L.x[n] = (((i + j) & 1) == 0 && d != 0.0f) ? d * L.b[n] : 0.0f;
-    }
-}
-
-// Gauss-Seidel update of one colour ((i + j) & 1 == color).
-__global__ void k_rb(Level L, int color)
-{
-    const int ld = L.nr + 1;
-    const int64_t nn = (int64_t)ld * (L.nz + 1);
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
-        if (((i + j) & 1) != color) continue;
-        const float d = L.dinv[n];
-        if (d == 0.0f) continue;
-        float off = 0.0f;
-        if (i < L.nr) off += L.ce[n] * L.x[n + 1];
-        if (i > 0) off += L.ce[n - 1] * L.x[n - 1];
-        if (j < L.nz) off += L.cn[n] * L.x[n + ld];
-        if (j > 0) off += L.cn[n - ld] * L.x[n - ld];
-        L.x[n] = d * (L.b[n] + off);
-    }
-}
-
-// Coarse right-hand side = P^T (b - A x) of the fine level.
-__global__ void k_restrict(Level F, Level C)
-{
-    const int ldc = C.nr + 1, ldf = F.nr + 1;
-    const int64_t nn = (int64_t)ldc * (C.nz + 1);
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
-        const int J = (int)(n / ldc), I = (int)(n - (int64_t)J * ldc);
-        float acc = 0.0f;
-        if (C.dinv[n] != 0.0f) {
-            for (int b = -1; b <= 1; ++b) {
-                const int j = 2 * J + b;
-                if (j < 0 || j > F.nz) continue;
-                for (int a = -1; a <= 1; ++a) {
-                    const int i = 2 * I + a;
-                    if (i < 0 || i > F.nr) continue;
-                    const int64_t m = (int64_t)j * ldf + i;
-                    if (F.dinv[m] == 0.0f) continue;
-                    float dg;
-                    const float ax = level_ax(F, F.x, i, j, m, &dg);
-                    const float w = (a == 0 ? 1.0f : 0.5f) * (b == 0 ? 1.0f : 0.5f);
-                    acc += w * (F.b[m] - ax);
-                }
-            }
-        }
-        C.b[n] = acc;
-    }
-}
-
-// Fine correction += P x_coarse (bilinear).
-__global__ void k_prolong(Level C, Level F)
-{
-    const int ldc = C.nr + 1, ldf = F.nr + 1;
-    const int64_t nn = (int64_t)ldf * (F.nz + 1);
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
-        if (F.dinv[n] == 0.0f) continue;
-        const int j = (int)(n / ldf), i = (int)(n - (int64_t)j * ldf);
-        const int I = i >> 1, J = j >> 1;
-        const int64_t c = (int64_t)J * ldc + I;
-        float v;
-        if (!(i & 1) && !(j & 1)) v = C.x[c];
-        else if ((i & 1) && !(j & 1)) v = 0.5f * (C.x[c] + C.x[c + 1]);
-        else if (!(i & 1) && (j & 1)) v = 0.5f * (C.x[c] + C.x[c + ldc]);
-        else v = 0.25f * (C.x[c] + C.x[c + 1] + C.x[c + ldc] + C.x[c + ldc + 1]);
-        F.x[n] += v;
-    }
-}
-
-// Coarsest level: x_u = A_uu^{-1} b_u with the dense inverse (one block).
-__global__ void k_coarse_solve(Level L, const float *inv, const int32_t *map, int n)
-{
-    extern __shared__ float sb[];
-    for (int a = threadIdx.x; a < n; a += blockDim.x) sb[a] = L.b[map[a]];
-    __syncthreads();
-    for (int a = threadIdx.x; a < n; a += blockDim.x) {
-        float acc = 0.0f;
-        const float *row = inv + (int64_t)a * n;
-        for (int b = 0; b < n; ++b) acc += row[b] * sb[b];
-        L.x[map[a]] = acc;
-    }
-}
-
-// ---- conjugate-gradient pieces on the finest level (FP32 vectors, FP64 dots)
-__global__ void __launch_bounds__(FB) k_pcg_matvec_dot(Level L, const float *p, float *q, double *pq)
-{
-    __shared__ double buf[FB / 64];
-    const int ld = L.nr + 1;
-    const int64_t nn = (int64_t)ld * (L.nz + 1);
-    double acc = 0.0;
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
-        float v = 0.0f;
-        if (L.dinv[n] != 0.0f) {
-            const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
-            float dg;
-            v = level_ax(L, p, i, j, n, &dg);
-            acc += (double)p[n] * (double)v;
-        }
-        q[n] = v;
-    }
-    const double t = block_sum(acc, buf);
-    if (threadIdx.x == 0 && t != 0.0) atomic_add_dev(pq, t);
-}
-
-__global__ void __launch_bounds__(FB) k_pcg_update(int64_t nn, const double *rz, const double *pq,
-                                                   const float *p, const float *q, float *e,
-                                                   float *r, double *rr)
-{
-    __shared__ double buf[FB / 64];
-    const double den = *pq;
-    const float alpha = (den != 0.0) ? (float)(*rz / den) : 0.0f;
-    double acc = 0.0;
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
-        e[n] += alpha * p[n];
-        const float rv = r[n] - alpha * q[n];
-        r[n] = rv;
-        acc += (double)rv * (double)rv;
-    }
-    const double t = block_sum(acc, buf);
-    if (threadIdx.x == 0 && t != 0.0) atomic_add_dev(rr, t);
-}
-
-__global__ void __launch_bounds__(FB) k_pcg_dot(int64_t nn, const float *a, const float *b, double *out)
-{
-    __shared__ double buf[FB / 64];
-    double acc = 0.0;
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB)
-        acc += (double)a[n] * (double)b[n];
-    const double t = block_sum(acc, buf);
-    if (threadIdx.x == 0 && t != 0.0) atomic_add_dev(out, t);
-}
-
-__global__ void k_pcg_direction(int64_t nn, const double *rz_new, const double *rz_old,
-                                const float *z, float *p)
-{
-    const double den = *rz_old;
-    const float beta = (den != 0.0) ? (float)(*rz_new / den) : 0.0f;
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB)
-        p[n] = z[n] + beta * p[n];
-}
-
-__global__ void k_copy_f32(float *dst, const float *src, int64_t n)
-{
-    for (int64_t k = (int64_t)blockIdx.x * FB + threadIdx.x; k < n; k += (int64_t)gridDim.x * FB)
-        dst[k] = src[k];
 }
 
 // ---- circuit: induced cathode charge of phi0 and the cathode voltage update
@@ -428,80 +258,23 @@ void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const 
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     launch_zero(&sc->res_rr, 2 * sizeof(double), s);
-    hipLaunchKernelGGL((k_residual64<T>), dim3(blocks_for(nn, 1024)), dim3(FB), 0, s, f.nr, f.nz,
+    hipLaunchKernelGGL((k_residual64<T>), dim3(blocks_for(nn, 160)), dim3(FB), 0, s, f.nr, f.nz,
                        f.ce64, f.cn64, f.kind, phi, q0, q1, f.r64, sc);
 }
 
-void launch_cast_scale(const FieldDev &f, double scale, hipStream_t s)
+void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s)
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
-    hipLaunchKernelGGL(k_cast_scale, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.r64, scale,
-                       f.r32, f.e32);
+    hipLaunchKernelGGL(k_cast_scale, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.r64, sc,
+                       f.mg.lv[0].b, f.e32);
 }
 
-void launch_update64(const FieldDev &f, double *phi, double scale, hipStream_t s)
+void launch_update64(const FieldDev &f, double *phi, const DevScalars *sc, double inv_2pi_eps0,
+                     hipStream_t s)
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     hipLaunchKernelGGL(k_update64, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.kind, phi, f.e32,
-                       scale);
-}
-
-static void vcycle_level(const FieldDev &f, int l, hipStream_t s)
-{
-    const Level &L = f.lv[l];
-    const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
-    if (l == f.nlevels - 1) {
-        hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(256), f.coarse_n * sizeof(float), s, L,
-                           f.coarse_inv, f.coarse_map, f.coarse_n);
-        return;
-    }
-    const int nb = blocks_for(nn);
-    const Level &C = f.lv[l + 1];
-    const int64_t nc = (int64_t)(C.nr + 1) * (C.nz + 1);
-    hipLaunchKernelGGL(k_smooth_first, dim3(nb), dim3(FB), 0, s, L);
-    hipLaunchKernelGGL(k_rb, dim3(nb), dim3(FB), 0, s, L, 1);
-    hipLaunchKernelGGL(k_restrict, dim3(blocks_for(nc)), dim3(FB), 0, s, L, C);
-    vcycle_level(f, l + 1, s);
-    hipLaunchKernelGGL(k_prolong, dim3(nb), dim3(FB), 0, s, C, L);
-    hipLaunchKernelGGL(k_rb, dim3(nb), dim3(FB), 0, s, L, 1);
-    hipLaunchKernelGGL(k_rb, dim3(nb), dim3(FB), 0, s, L, 0);
-}
-
-void launch_vcycle(const FieldDev &f, hipStream_t s) { vcycle_level(f, 0, s); }
-
-void launch_pcg_matvec_dot(const FieldDev &f, DevScalars *sc, int k, hipStream_t s)
-{
-    const Level &L = f.lv[0];
-    const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
-    hipLaunchKernelGGL(k_pcg_matvec_dot, dim3(blocks_for(nn, 1024)), dim3(FB), 0, s, L, f.p32,
-                       f.q32, &sc->pcg_pq[k]);
-}
-
-void launch_pcg_update(const FieldDev &f, DevScalars *sc, int k, hipStream_t s)
-{
-    const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
-    hipLaunchKernelGGL(k_pcg_update, dim3(blocks_for(nn, 1024)), dim3(FB), 0, s, nn,
-                       &sc->pcg_rz[k], &sc->pcg_pq[k], f.p32, f.q32, f.e32, f.r32,
-                       &sc->pcg_rr[k]);
-}
-
-void launch_pcg_dot_rz(const FieldDev &f, DevScalars *sc, int k, hipStream_t s)
-{
-    const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
-    hipLaunchKernelGGL(k_pcg_dot, dim3(blocks_for(nn, 1024)), dim3(FB), 0, s, nn, f.r32, f.z32,
-                       &sc->pcg_rz[k]);
-}
-
-void launch_pcg_direction(const FieldDev &f, DevScalars *sc, int k, hipStream_t s)
-{
-    const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
-    hipLaunchKernelGGL(k_pcg_direction, dim3(blocks_for(nn)), dim3(FB), 0, s, nn,
-                       &sc->pcg_rz[k + 1], &sc->pcg_rz[k], f.z32, f.p32);
-}
-
-void launch_copy_f32(float *dst, const float *src, int64_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_copy_f32, dim3(blocks_for(n)), dim3(FB), 0, s, dst, src, n);
+                       sc, inv_2pi_eps0);
 }
 
 template <typename T>

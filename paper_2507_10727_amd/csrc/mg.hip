@@ -1,0 +1,463 @@
+// Geometric multigrid preconditioner and conjugate-gradient kernels of the
+// FP32 inner solve (correction equation of the FP64 refinement).
+//
+// The operator is matrix-free: on a level with cell sizes dr, dz the
+// couplings of the charge-form R-Z finite volumes, divided by 2 pi eps0, are
+//   east  face (i+1/2, j): (i + 1/2) hz_j,  hz_j = dz (dz/2 on the z walls),
+//   north face (i, j+1/2): g_i dr^2 / dz,   g_0 = 1/8, g_i = i, g_nr = nr/2 - 1/8,
+// i.e. the face areas of the clipped control volumes over their spacings
+// (Section 3's Gauss's law on the axis is the missing face at r = 0).
+// Dirichlet nodes (anode row, outer column, cathode nodes of z = 0) carry a
+// zero correction.
+//
+// One V-cycle is: per fine level a "down" kernel (red-black Gauss-Seidel
+// from a zero guess, residual, full-weighting restriction of the residual,
+// all in one LDS tile with a 3-node halo), one single-workgroup "tail" kernel
+// that runs every remaining coarse level in LDS and solves the coarsest with a
+// dense inverse, and per fine level an "up" kernel (bilinear prolongation,
+// black-red Gauss-Seidel, 2-node halo).  Pre-smoothing red-black and
+// post-smoothing black-red with restriction = prolongation^T make the
+// preconditioner symmetric, as conjugate gradients requires.
+#include "common.h"
+
+namespace pic {
+
+namespace {
+
+__device__ __forceinline__ bool mg_in(const MGLevel &L, int i, int j)
+{
+    return i >= 0 && j >= 0 && i <= L.nr && j <= L.nz;
+}
+__device__ __forceinline__ bool mg_unknown(const MGLevel &L, int i, int j)
+{
+    return i < L.nr && j < L.nz && !(j == 0 && i < L.cath);
+}
+__device__ __forceinline__ float mg_ae(const MGLevel &L, int i, int j)
+{
+    const float hz = (j == 0 || j == L.nz) ? 0.5f * L.dz : L.dz;
+    return ((float)i + 0.5f) * hz;
+}
+__device__ __forceinline__ float mg_an(const MGLevel &L, int i)
+{
+    const float g = (i == 0) ? 0.125f : ((i == L.nr) ? 0.5f * (float)L.nr - 0.125f : (float)i);
+    return g * L.dr2dz;
+}
+// couplings of an unknown node: west, east, south, north (0 if absent)
+__device__ __forceinline__ void mg_coup(const MGLevel &L, int i, int j, float &w, float &e,
+                                        float &s, float &n)
+{
+    w = (i > 0) ? mg_ae(L, i - 1, j) : 0.0f;
+    e = mg_ae(L, i, j);
+    s = (j > 0) ? mg_an(L, i) : 0.0f;
+    n = mg_an(L, i);
+}
+
+// bilinear prolongation of the coarse correction to fine node (i, j)
+__device__ __forceinline__ float mg_prolong(const float *xc, int ldc, int i, int j)
+{
+    const int I = i >> 1, J = j >> 1;
+    const float *c = xc + (int64_t)J * ldc + I;
+    if (!(i & 1) && !(j & 1)) return c[0];
+    if ((i & 1) && !(j & 1)) return 0.5f * (c[0] + c[1]);
+    if (!(i & 1) && (j & 1)) return 0.5f * (c[0] + c[ldc]);
+    return 0.25f * (c[0] + c[1] + c[ldc] + c[ldc + 1]);
+}
+
+constexpr int DTX = 16, DTY = 8;                 // coarse nodes per down tile
+constexpr int DLW = 2 * DTX + 5, DLH = 2 * DTY + 5;
+constexpr int UTX = 32, UTY = 16;                // fine nodes per up tile
+constexpr int ULW = UTX + 4, ULH = UTY + 4;
+
+// Down: pre-smooth from zero, residual, restriction.  F.b is the fine
+// right-hand side; writes the smoothed F.xd and the coarse C.b.
+__global__ void __launch_bounds__(256) k_mg_down(MGLevel F, MGLevel C)
+{
+    __shared__ float sb[DLH][DLW];
+    __shared__ float sx[DLH][DLW];
+    const int I0 = blockIdx.x * DTX, J0 = blockIdx.y * DTY;
+    const int fi0 = 2 * I0 - 3, fj0 = 2 * J0 - 3;
+    const int ld = F.nr + 1;
+    for (int t = threadIdx.x; t < DLW * DLH; t += 256) {
+        const int li = t % DLW, lj = t / DLW;
+        const int i = fi0 + li, j = fj0 + lj;
+        float bv = 0.0f, xv = 0.0f;
+        if (mg_in(F, i, j) && mg_unknown(F, i, j)) {
+            bv = F.b[(int64_t)j * ld + i];
+            if (((i + j) & 1) == 0) {
+                float w, e, s, n;
+                mg_coup(F, i, j, w, e, s, n);
+                xv = bv / (w + e + s + n);
+            }
+        }
+        sb[lj][li] = bv;
+        sx[lj][li] = xv;
+    }
+    __syncthreads();
+    // black nodes of the 1-halo region
+    for (int t = threadIdx.x; t < (DLW - 2) * (DLH - 2); t += 256) {
+        const int li = 1 + t % (DLW - 2), lj = 1 + t / (DLW - 2);
+        const int i = fi0 + li, j = fj0 + lj;
+        if (((i + j) & 1) != 1 || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
+        float w, e, s, n;
+        mg_coup(F, i, j, w, e, s, n);
+        const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
+                          n * sx[lj + 1][li];
+        sx[lj][li] = (sb[lj][li] + off) / (w + e + s + n);
+    }
+    __syncthreads();
+    // residual on the region the restriction reads (written over b)
+    for (int t = threadIdx.x; t < (DLW - 4) * (DLH - 4); t += 256) {
+        const int li = 2 + t % (DLW - 4), lj = 2 + t / (DLW - 4);
+        const int i = fi0 + li, j = fj0 + lj;
+        float r = 0.0f;
+        if (mg_in(F, i, j) && mg_unknown(F, i, j)) {
+            float w, e, s, n;
+            mg_coup(F, i, j, w, e, s, n);
+            const float ax = (w + e + s + n) * sx[lj][li] -
+                             (w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
+                              n * sx[lj + 1][li]);
+            r = sb[lj][li] - ax;
+        }
+        sb[lj][li] = r;
+    }
+    __syncthreads();
+    const int ldc = C.nr + 1;
+    for (int t = threadIdx.x; t < DTX * DTY; t += 256) {
+        const int I = I0 + t % DTX, J = J0 + t / DTX;
+        if (I > C.nr || J > C.nz) continue;
+        float v = 0.0f;
+        if (mg_unknown(C, I, J)) {
+            const int ci = 2 * I - fi0, cj = 2 * J - fj0;
+            v = sb[cj][ci] + 0.5f * (sb[cj][ci - 1] + sb[cj][ci + 1] + sb[cj - 1][ci] +
+                                     sb[cj + 1][ci]) +
+                0.25f * (sb[cj - 1][ci - 1] + sb[cj - 1][ci + 1] + sb[cj + 1][ci - 1] +
+                         sb[cj + 1][ci + 1]);
+        }
+        C.b[(int64_t)J * ldc + I] = v;
+    }
+    // fine nodes owned by this tile: [2 I0, 2 I0 + 2 DTX) x [2 J0, 2 J0 + 2 DTY)
+    for (int t = threadIdx.x; t < 4 * DTX * DTY; t += 256) {
+        const int i = 2 * I0 + t % (2 * DTX), j = 2 * J0 + t / (2 * DTX);
+        if (i > F.nr || j > F.nz) continue;
+        F.xd[(int64_t)j * ld + i] = sx[j - fj0][i - fi0];
+    }
+}
+
+// Up: x = xd + P xc, black then red Gauss-Seidel; writes F.xu on the owned
+// tile and, if dot != null, accumulates sum(b * x) over it.
+__global__ void __launch_bounds__(256) k_mg_up(MGLevel F, MGLevel C, double *dot)
+{
+    __shared__ float sb[ULH][ULW];
+    __shared__ float sx[ULH][ULW];
+    __shared__ double red[4];
+    const int i0 = blockIdx.x * UTX, j0 = blockIdx.y * UTY;
+    const int fi0 = i0 - 2, fj0 = j0 - 2;
+    const int ld = F.nr + 1, ldc = C.nr + 1;
+    for (int t = threadIdx.x; t < ULW * ULH; t += 256) {
+        const int li = t % ULW, lj = t / ULW;
+        const int i = fi0 + li, j = fj0 + lj;
+        float bv = 0.0f, xv = 0.0f;
+        if (mg_in(F, i, j) && mg_unknown(F, i, j)) {
+            const int64_t n = (int64_t)j * ld + i;
+            bv = F.b[n];
+            xv = F.xd[n] + mg_prolong(C.xu, ldc, i, j);
+        }
+        sb[lj][li] = bv;
+        sx[lj][li] = xv;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < (ULW - 2) * (ULH - 2); t += 256) {
+        const int li = 1 + t % (ULW - 2), lj = 1 + t / (ULW - 2);
+        const int i = fi0 + li, j = fj0 + lj;
+        if (((i + j) & 1) != 1 || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
+        float w, e, s, n;
+        mg_coup(F, i, j, w, e, s, n);
+        const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
+                          n * sx[lj + 1][li];
+        sx[lj][li] = (sb[lj][li] + off) / (w + e + s + n);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < (ULW - 4) * (ULH - 4); t += 256) {
+        const int li = 2 + t % (ULW - 4), lj = 2 + t / (ULW - 4);
+        const int i = fi0 + li, j = fj0 + lj;
+        if (((i + j) & 1) != 0 || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
+        float w, e, s, n;
+        mg_coup(F, i, j, w, e, s, n);
+        const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
+                          n * sx[lj + 1][li];
+        sx[lj][li] = (sb[lj][li] + off) / (w + e + s + n);
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < UTX * UTY; t += 256) {
+        const int i = i0 + t % UTX, j = j0 + t / UTX;
+        if (i > F.nr || j > F.nz) continue;
+        const float v = sx[j - fj0][i - fi0];
+        F.xu[(int64_t)j * ld + i] = v;
+        acc += (double)v * (double)sb[j - fj0][i - fi0];
+    }
+    if (dot) {
+        acc = wave_sum(acc);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double s = red[0] + red[1] + red[2] + red[3];
+            if (s != 0.0) atomic_add_dev(dot, s);
+        }
+    }
+}
+
+// Tail: every level from `first` down to the coarsest in one workgroup
+// (32 x 32 threads, thread (tx, ty) visits nodes i = tx + 32a, j = ty + 32b;
+// a colour sweep visits only its own parity).  Reads L[first].b, writes
+// L[first].xu (and sum(b * x) into dot if given).
+constexpr int TT = 32;
+
+__device__ __forceinline__ void tail_sweep(const MGLevel &L, float *x, const float *b, int c)
+{
+    const int ld = L.nr + 1;
+    for (int j = threadIdx.y; j < L.nz; j += TT) {
+        for (int i = 2 * threadIdx.x + ((j + c) & 1); i < L.nr; i += 2 * TT) {
+            if (j == 0 && i < L.cath) continue;
+            const int n = j * ld + i;
+            float w, e, s, nn;
+            mg_coup(L, i, j, w, e, s, nn);
+            const float o = (i > 0 ? w * x[n - 1] : 0.0f) + e * x[n + 1] +
+                            (j > 0 ? s * x[n - ld] : 0.0f) + nn * x[n + ld];
+            x[n] = (b[n] + o) / (w + e + s + nn);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
+{
+    extern __shared__ float sm[];
+    float *X[MAX_LEVELS], *B[MAX_LEVELS];
+    float *tmp = sm;
+    int off = T.tmp_size;
+    for (int l = T.first; l <= T.last; ++l) {
+        const int nl = (T.L[l].nr + 1) * (T.L[l].nz + 1);
+        X[l] = sm + off;
+        off += nl;
+        B[l] = sm + off;
+        off += nl;
+    }
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    {
+        const MGLevel &L = T.L[T.first];
+        const int ld = L.nr + 1;
+        for (int j = ty; j <= L.nz; j += TT)
+            for (int i = tx; i <= L.nr; i += TT) {
+                const int n = j * ld + i;
+                B[T.first][n] = L.b[n];
+                X[T.first][n] = 0.0f;
+            }
+    }
+    __syncthreads();
+    // descend: x = 0, red-black sweep, residual, restriction
+    for (int l = T.first; l < T.last; ++l) {
+        const MGLevel &L = T.L[l];
+        const int ld = L.nr + 1;
+        float *x = X[l], *b = B[l];
+        tail_sweep(L, x, b, 0);
+        __syncthreads();
+        tail_sweep(L, x, b, 1);
+        __syncthreads();
+        for (int j = ty; j <= L.nz; j += TT)
+            for (int i = tx; i <= L.nr; i += TT) {
+                const int n = j * ld + i;
+                float r = 0.0f;
+                if (mg_unknown(L, i, j)) {
+                    float w, e, s, nn;
+                    mg_coup(L, i, j, w, e, s, nn);
+                    const float o = (i > 0 ? w * x[n - 1] : 0.0f) + e * x[n + 1] +
+                                    (j > 0 ? s * x[n - ld] : 0.0f) + nn * x[n + ld];
+                    r = b[n] - ((w + e + s + nn) * x[n] - o);
+                }
+                tmp[n] = r;
+            }
+        __syncthreads();
+        const MGLevel &C = T.L[l + 1];
+        const int ldc = C.nr + 1;
+        for (int J = ty; J <= C.nz; J += TT)
+            for (int I = tx; I <= C.nr; I += TT) {
+                float v = 0.0f;
+                if (mg_unknown(C, I, J)) {
+                    const int c = 2 * J * ld + 2 * I;
+                    const bool w = I > 0, s = J > 0;   // fine 2I-1 / 2J-1 exist
+                    v = tmp[c] + 0.5f * ((w ? tmp[c - 1] : 0.0f) + tmp[c + 1] +
+                                         (s ? tmp[c - ld] : 0.0f) + tmp[c + ld]) +
+                        0.25f * ((w && s ? tmp[c - ld - 1] : 0.0f) + (s ? tmp[c - ld + 1] : 0.0f) +
+                                 (w ? tmp[c + ld - 1] : 0.0f) + tmp[c + ld + 1]);
+                }
+                B[l + 1][J * ldc + I] = v;
+                X[l + 1][J * ldc + I] = 0.0f;
+            }
+        __syncthreads();
+    }
+    // coarsest: dense inverse on the unknowns
+    {
+        const int tid = ty * TT + tx;
+        for (int a = tid; a < T.ninv; a += TT * TT) {
+            float acc = 0.0f;
+            const float *row = T.inv + (int64_t)a * T.ninv;
+            for (int c = 0; c < T.ninv; ++c) acc += row[c] * B[T.last][T.map[c]];
+            X[T.last][T.map[a]] = acc;
+        }
+        __syncthreads();
+    }
+    // ascend: prolongation, black-red sweep
+    for (int l = T.last - 1; l >= T.first; --l) {
+        const MGLevel &L = T.L[l];
+        const int ld = L.nr + 1, ldc = T.L[l + 1].nr + 1;
+        float *x = X[l], *b = B[l];
+        for (int j = ty; j <= L.nz; j += TT)
+            for (int i = tx; i <= L.nr; i += TT)
+                if (mg_unknown(L, i, j)) x[j * ld + i] += mg_prolong(X[l + 1], ldc, i, j);
+        __syncthreads();
+        tail_sweep(L, x, b, 1);
+        __syncthreads();
+        tail_sweep(L, x, b, 0);
+        __syncthreads();
+    }
+    {
+        const MGLevel &L = T.L[T.first];
+        const int ld = L.nr + 1;
+        double acc = 0.0;
+        for (int j = ty; j <= L.nz; j += TT)
+            for (int i = tx; i <= L.nr; i += TT) {
+                const int n = j * ld + i;
+                L.xu[n] = X[T.first][n];
+                acc += (double)X[T.first][n] * (double)B[T.first][n];
+            }
+        if (dot) {
+            __shared__ double red[16];
+            const int tid = ty * TT + tx;
+            acc = wave_sum(acc);
+            if ((tid & 63) == 0) red[tid >> 6] = acc;
+            __syncthreads();
+            if (tid == 0) {
+                double s = 0.0;
+                for (int w = 0; w < 16; ++w) s += red[w];
+                if (s != 0.0) atomic_add_dev(dot, s);
+            }
+        }
+    }
+}
+
+// ---- conjugate-gradient vector kernels on the finest level
+constexpr int CB = 256;
+
+// p_k = z + beta p_{k-1} (beta = rz_k / rz_{k-1}, 0 for k = 0) into pc,
+// q = A p_k, and p_k . q accumulated.
+__global__ void __launch_bounds__(CB) k_cg_matvec(MGLevel L, const float *z, const float *pp,
+                                                  float *pc, float *q, const double *rz, int k,
+                                                  double *pq)
+{
+    __shared__ double red[CB / 64];
+    const double bd = (k > 0 && rz[k - 1] != 0.0) ? rz[k] / rz[k - 1] : 0.0;
+    const float beta = (float)bd;
+    const int ld = L.nr + 1;
+    const int64_t nn = (int64_t)ld * (L.nz + 1);
+    double acc = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * CB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * CB) {
+        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        float pv = 0.0f, qv = 0.0f;
+        if (mg_unknown(L, i, j)) {
+            float w, e, s, nb;
+            mg_coup(L, i, j, w, e, s, nb);
+            pv = z[n] + beta * pp[n];
+            const float pe = z[n + 1] + beta * pp[n + 1];
+            const float pnn = z[n + ld] + beta * pp[n + ld];
+            const float pw = (i > 0) ? z[n - 1] + beta * pp[n - 1] : 0.0f;
+            const float ps = (j > 0) ? z[n - ld] + beta * pp[n - ld] : 0.0f;
+            qv = (w + e + s + nb) * pv - (w * pw + e * pe + s * ps + nb * pnn);
+            acc += (double)pv * (double)qv;
+        }
+        pc[n] = pv;
+        q[n] = qv;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < CB / 64; ++w) s += red[w];
+        if (s != 0.0) atomic_add_dev(pq, s);
+    }
+}
+
+// e += alpha p, r -= alpha q, ||r||^2 accumulated (alpha = rz_k / pq_k).
+__global__ void __launch_bounds__(CB) k_cg_update(int64_t nn, const float *p, const float *q,
+                                                  float *e, float *r, const double *rz,
+                                                  const double *pq, double *rr)
+{
+    __shared__ double red[CB / 64];
+    const float alpha = (*pq != 0.0) ? (float)(*rz / *pq) : 0.0f;
+    double acc = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * CB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * CB) {
+        e[n] += alpha * p[n];
+        const float v = r[n] - alpha * q[n];
+        r[n] = v;
+        acc += (double)v * (double)v;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < CB / 64; ++w) s += red[w];
+        if (s != 0.0) atomic_add_dev(rr, s);
+    }
+}
+
+inline int cg_blocks(int64_t n)
+{
+    int64_t b = (n + CB - 1) / CB;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 160));
+}
+
+}  // namespace
+
+void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s)
+{
+    // down the grid levels
+    for (int l = 0; l < H.tail.first; ++l) {
+        const MGLevel &F = H.lv[l], &C = H.lv[l + 1];
+        dim3 g((C.nr + 1 + DTX - 1) / DTX, (C.nz + 1 + DTY - 1) / DTY);
+        hipLaunchKernelGGL(k_mg_down, g, dim3(256), 0, s, F, C);
+    }
+    hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(TT, TT), H.tail_lds_bytes, s, H.tail,
+                       H.tail.first == 0 ? dot : nullptr);
+    for (int l = H.tail.first - 1; l >= 0; --l) {
+        const MGLevel &F = H.lv[l], &C = H.lv[l + 1];
+        dim3 g((F.nr + 1 + UTX - 1) / UTX, (F.nz + 1 + UTY - 1) / UTY);
+        hipLaunchKernelGGL(k_mg_up, g, dim3(256), 0, s, F, C, l == 0 ? dot : nullptr);
+    }
+}
+
+void launch_cg_matvec(const MGHier &H, const float *z, const float *pp, float *pc, float *q,
+                      const double *rz, int k, double *pq, hipStream_t s)
+{
+    const MGLevel &L = H.lv[0];
+    const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
+    hipLaunchKernelGGL(k_cg_matvec, dim3(cg_blocks(nn)), dim3(CB), 0, s, L, z, pp, pc, q, rz, k, pq);
+}
+
+void launch_cg_update(const MGHier &H, const float *p, const float *q, float *e, float *r,
+                      const double *rz, const double *pq, double *rr, hipStream_t s)
+{
+    const MGLevel &L = H.lv[0];
+    const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
+    hipLaunchKernelGGL(k_cg_update, dim3(cg_blocks(nn)), dim3(CB), 0, s, nn, p, q, e, r, rz, pq,
+                       rr);
+}
+
+int mg_tail_setup(MGHier &H)
+{
+    return (int)hipFuncSetAttribute((const void *)k_mg_tail,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    H.tail_lds_bytes);
+}
+
+}  // namespace pic

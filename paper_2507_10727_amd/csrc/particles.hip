@@ -11,14 +11,16 @@ namespace pic {
 // Fused particle kernel.
 //
 // One launch covers both species: blocks [0, nblk_e) stream the electrons,
-// the rest the ions.  Each block walks its species in chunks of
-// PUSH_CHUNK consecutive slots (grid-stride), each thread owning PUSH_PPT
-// slots of a chunk at stride PUSH_THREADS so that every load and store of a
-// wavefront is one contiguous 256-byte (FP32) segment.  Particles are kept
-// sorted by cell, so the nodes a chunk deposits to form a small box; the
-// chunk's charge is accumulated in LDS over that box and flushed with one
-// global atomic per touched node.  A chunk whose box does not fit (rare, an
-// unsorted or badly scattered chunk) deposits with global atomics.
+// the rest the ions.  Each block walks its species in chunks of PUSH_CHUNK
+// consecutive slots (grid-stride); thread t owns the 4 consecutive slots
+// 4t..4t+3 of a chunk and moves them with one 16-byte load and store per
+// array, so a wavefront reads and writes 1 KiB contiguous segments.
+// Particles are kept sorted by cell, so a thread's 4 particles usually share
+// a cell: the 4 node 4-vectors of the gather are loaded once per distinct
+// cell, and the deposit is summed in registers per run of equal cells before
+// it goes to LDS.  The chunk's charge is accumulated in LDS over the box of
+// nodes it touches and flushed with one global atomic per node; a chunk whose
+// box does not fit (an unsorted or scattered chunk) uses global atomics.
 //
 // Per particle (Section 2 for the gather, Section 3 for walls, emission and
 // collisions):
@@ -77,273 +79,379 @@ __device__ __forceinline__ T interp_row(const T *row, int k, T f)
     return ((T)1 - f) * row[k] + f * row[k + 1];
 }
 
+template <typename T> __device__ __forceinline__ T near_one();
+template <> __device__ __forceinline__ float near_one<float>() { return 0x1.fffffep-1f; }
+template <> __device__ __forceinline__ double near_one<double>() { return 0x1.fffffffffffffp-1; }
+
+struct Tally {
+    double ke = 0.0, pz = 0.0, dq = 0.0;
+    unsigned int abs1 = 0, abs2 = 0, abs3 = 0, abs4 = 0;
+    unsigned int cand = 0, el = 0, ex = 0, iz = 0, see = 0, fb = 0;
+};
+
+// Gather, Boris, drift and walls for one particle.  Updates the state in
+// place and returns 0 if it stays inside, else the wall code (1 cathode,
+// 2 Neumann block, 3 outer r, 4 anode).
+template <typename T, int SCHEME>
+__device__ __forceinline__ int advance(const PushParams<T> &P, T hqm, double mw,
+                                       const typename Vec4<T>::type &a00,
+                                       const typename Vec4<T>::type &a10,
+                                       const typename Vec4<T>::type &a01,
+                                       const typename Vec4<T>::type &a11, int &i, int &j, T &fr,
+                                       T &fz, T &vr, T &vt, T &vz, Tally &t, T &r1_out)
+{
+    const int nr = P.nr, nz = P.nz;
+    const T gr = (T)1 - fr, gz = (T)1 - fz;
+    const T w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
+    T er, ez;
+    if (SCHEME == PIC_EC) {
+        er = gz * a00.x + fz * a01.x;
+        ez = gr * a00.y + fr * a10.y;
+    } else {
+        er = w00 * a00.x + w10 * a10.x + w01 * a01.x + w11 * a11.x;
+        ez = w00 * a00.y + w10 * a10.y + w01 * a01.y + w11 * a11.y;
+    }
+    const T br = w00 * a00.z + w10 * a10.z + w01 * a01.z + w11 * a11.z;
+    const T bz = w00 * a00.w + w10 * a10.w + w01 * a01.w + w11 * a11.w;
+    // Boris: half kick, rotation about t = (q dt / 2m) B, half kick
+    const T mx = vr + hqm * er, my = vt, mz = vz + hqm * ez;
+    const T tx = hqm * br, tz = hqm * bz;
+    const T f2 = (T)2 / ((T)1 + tx * tx + tz * tz);
+    const T sx = f2 * tx, sz = f2 * tz;
+    const T px = mx + my * tz;
+    const T py = my + (mz * tx - mx * tz);
+    const T pzz = mz - my * tx;
+    const T qx = mx + py * sz;
+    const T qy = my + (pzz * sx - px * sz);
+    const T qz = mz - py * sx;
+    const T nx = qx + hqm * er, ny = qy, nzv = qz + hqm * ez;
+    t.ke += 0.5 * mw * ((double)vr * nx + (double)vt * ny + (double)vz * nzv);
+    t.pz += mw * (double)nzv;
+    // drift in (x, y, z) = (r, 0, z), rotate into the new meridional plane
+    const T r = ((T)i + fr) * P.dr;
+    const T dx = nx * P.dt, dy = ny * P.dt;
+    const T x1 = r + dx;
+    const T r1 = sqrt(x1 * x1 + dy * dy);
+    T vr1 = nx, vt1 = ny, vz1 = nzv;
+    if (r1 > (T)0) {
+        const T inv = (T)1 / r1;
+        const T c = x1 * inv, sn = dy * inv;
+        vr1 = c * nx + sn * ny;
+        vt1 = c * ny - sn * nx;
+    }
+    const T den = r + r1;
+    const T drr = (den > (T)0) ? ((T)2 * r * dx + dx * dx + dy * dy) / den : (T)0;
+    const T xr = fr + drr * P.inv_dr;
+    const T xz = fz + nzv * P.dt * P.inv_dz;
+    const T flr = floor(xr), flz = floor(xz);
+    int i1 = i + (int)flr, j1 = j + (int)flz;
+    T fr1 = xr - flr, fz1 = xz - flz;
+    if (fr1 >= (T)1) { fr1 = (T)0; ++i1; }
+    if (fz1 >= (T)1) { fz1 = (T)0; ++j1; }
+    int fate = 0;
+    if (j1 < 0) {
+        if (P.wall_bc[0] == PIC_REFLECT) {
+            const T zg = -((T)j1 + fz1);
+            const T fl = floor(zg);
+            j1 = (int)fl;
+            fz1 = zg - fl;
+            if (fz1 >= (T)1) { fz1 = (T)0; ++j1; }
+            vz1 = -vz1;
+        } else {
+            fate = (r1 < P.cathode_rmax) ? 1 : 2;
+        }
+    }
+    if (fate == 0 && i1 >= nr) {
+        if (P.wall_bc[2] == PIC_REFLECT) {
+            const T rg = (T)(2 * nr) - ((T)i1 + fr1);
+            const T fl = floor(rg);
+            i1 = (int)fl;
+            fr1 = rg - fl;
+            if (i1 >= nr) { i1 = nr - 1; fr1 = near_one<T>(); }
+            vr1 = -vr1;
+        } else {
+            fate = 3;
+        }
+    }
+    if (fate == 0 && j1 >= nz) {
+        if (P.wall_bc[1] == PIC_REFLECT) {
+            const T zg = (T)(2 * nz) - ((T)j1 + fz1);
+            const T fl = floor(zg);
+            j1 = (int)fl;
+            fz1 = zg - fl;
+            if (j1 >= nz) { j1 = nz - 1; fz1 = near_one<T>(); }
+            vz1 = -vz1;
+        } else {
+            fate = 4;
+        }
+    }
+    if (fate == 0) {
+        // r' >= 0 exactly; round-off can put i' at -1 next to the axis.  Any
+        // index still outside the grid (non-finite or absurd velocities under
+        // reflecting walls) is clamped so every access stays in bounds.
+        if (i1 < 0) { i1 = 0; fr1 = (T)0; }
+        if (i1 > nr - 1) { i1 = nr - 1; fr1 = near_one<T>(); }
+        if (j1 < 0) { j1 = 0; fz1 = (T)0; }
+        if (j1 > nz - 1) { j1 = nz - 1; fz1 = near_one<T>(); }
+        if (!(fr1 >= (T)0 && fr1 < (T)1)) fr1 = (T)0;
+        if (!(fz1 >= (T)0 && fz1 < (T)1)) fz1 = (T)0;
+    }
+    i = i1;
+    j = j1;
+    fr = fr1;
+    fz = fz1;
+    vr = vr1;
+    vt = vt1;
+    vz = vz1;
+    r1_out = r1;
+    return fate;
+}
+
+// Null-collision MCC of one electron (Section 3, processes (1a)-(1c)).
+template <typename T>
+__device__ __forceinline__ void collide(const PushParams<T> &P, uint32_t id, uint32_t step, int i,
+                                        int j, T fr, T fz, T &vr, T &vt, T &vz, Tally &t)
+{
+    const uint4 u = philox4x32_10(make_uint4(id, (P.run << 8) | PURPOSE_MCC, step, 0u), P.key0,
+                                  P.key1);
+    if ((unsigned long long)u.x >= P.t_null) return;
+    ++t.cand;
+    const int nt = P.n_table;
+    const T v2 = vr * vr + vt * vt + vz * vz;
+    const T e = P.e_of_v2 * v2;
+    const T x = e * P.inv_de;
+    int kk;
+    T f;
+    if (x >= (T)(nt - 1)) { kk = nt - 2; f = (T)1; }
+    else { const T fl = floor(x); kk = (int)fl; f = x - fl; }
+    const T c1 = interp_row(P.nu, kk, f);
+    const T c2 = c1 + interp_row(P.nu + nt, kk, f);
+    const T c3 = c2 + interp_row(P.nu + 2 * nt, kk, f);
+    const T rsel = u24<T>(u.y) * P.numax;
+    int proc = -1;
+    if (rsel < c1) proc = 0;
+    else if (rsel < c2) proc = (e >= P.e_exc) ? 1 : -1;
+    else if (rsel < c3) proc = (e >= P.e_iz) ? 2 : -1;
+    if (proc < 0) return;
+    T d0, d1, d2;
+    iso_direction(u.z, u.w, d0, d1, d2);
+    T enew;
+    if (proc == 0) {
+        ++t.el;
+        const T vm = sqrt(v2);
+        const T cth = (vr * d0 + vt * d1 + vz * d2) / vm;
+        enew = e * ((T)1 - P.two_m_over_M * ((T)1 - cth));
+    } else if (proc == 1) {
+        ++t.ex;
+        enew = e - P.e_exc;
+    } else {
+        ++t.iz;
+        const T erem = e - P.e_iz;
+        const uint4 ua = philox4x32_10(make_uint4(id, (P.run << 8) | PURPOSE_IZ, step, 0u),
+                                       P.key0, P.key1);
+        const uint4 ub = philox4x32_10(make_uint4(id, (P.run << 8) | PURPOSE_ION, step, 0u),
+                                       P.key0, P.key1);
+        const T eej = u24<T>(ua.x) * erem;
+        enew = erem - eej;
+        T e0, e1, e2;
+        iso_direction(ua.y, ua.z, e0, e1, e2);
+        const T vej = sqrt(P.v2_of_e * eej);
+        record_child(P, 0, id, 0, 0, i, j, fr, fz, vej * e0, vej * e1, vej * e2);
+        const T a0 = sqrt((T)-2 * log(u24_open<T>(ub.x)));
+        const T a1 = sqrt((T)-2 * log(u24_open<T>(ub.z)));
+        T s0, c0, s1, cb;
+        sincos_2pi(u24<T>(ub.y), &s0, &c0);
+        sincos_2pi(u24<T>(ub.w), &s1, &cb);
+        record_child(P, 0, id, 1, 1, i, j, fr, fz, P.sig_ion * a0 * c0, P.sig_ion * a0 * s0,
+                     P.sig_ion * a1 * cb);
+    }
+    const T vn = sqrt(P.v2_of_e * enew);
+    vr = vn * d0;
+    vt = vn * d1;
+    vz = vn * d2;
+}
+
+// Add one run's summed tent weights to its cell's four nodes.
+template <typename T>
+__device__ __forceinline__ void deposit_lds(T *lds, int ld, int key, T qw, T a00, T a10, T a01,
+                                            T a11)
+{
+    const int i = key & 0xffff, j = key >> 16;
+    T *p = lds + j * ld + i;
+    atomicAdd(p, qw * a00);
+    atomicAdd(p + 1, qw * a10);
+    atomicAdd(p + ld, qw * a01);
+    atomicAdd(p + ld + 1, qw * a11);
+}
+
+template <typename T>
+__device__ __forceinline__ void deposit_global(T *q, int ld, int key, T qw, T a00, T a10, T a01,
+                                               T a11)
+{
+    const int i = key & 0xffff, j = key >> 16;
+    T *p = q + (int64_t)j * ld + i;
+    atomic_add_dev(p, qw * a00);
+    atomic_add_dev(p + 1, qw * a10);
+    atomic_add_dev(p + ld, qw * a01);
+    atomic_add_dev(p + ld + 1, qw * a11);
+}
+
 template <typename T, int SCHEME>
 __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
 {
     using T4 = typename Vec4<T>::type;
+    constexpr int NW = PUSH_THREADS / 64;
     __shared__ T lds_q[LDS_NODES];
-    __shared__ int red[4][PUSH_THREADS / 64];
-    __shared__ double dred[3][PUSH_THREADS / 64];
-    __shared__ unsigned long long cred[12][PUSH_THREADS / 64];
+    __shared__ int red[4][NW];
+    __shared__ double dred[3][NW];
+    __shared__ unsigned long long cred[10][NW];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     const int s = ((int)blockIdx.x < P.nblk_e) ? 0 : 1;
     const int blk = s ? (int)blockIdx.x - P.nblk_e : (int)blockIdx.x;
     const int nblk = s ? (int)gridDim.x - P.nblk_e : P.nblk_e;
-    const SpeciesDev<T> S = P.sp[s];
+    int32_t *__restrict__ KEY = P.sp[s].key;
+    T *__restrict__ FR = P.sp[s].fr;
+    T *__restrict__ FZ = P.sp[s].fz;
+    T *__restrict__ VR = P.sp[s].vr;
+    T *__restrict__ VT = P.sp[s].vt;
+    T *__restrict__ VZ = P.sp[s].vz;
+    const uint32_t *__restrict__ ID = P.sp[s].id;
+    const T4 *__restrict__ NODE = P.node;
     const int64_t n = P.sc->count[s];
     const uint32_t step = (uint32_t)P.sc->step;
-    const int nr = P.nr, nz = P.nz, ldn = nr + 1;
+    const int ldn = P.nr + 1;
     const T hqm = P.hqm[s], qw = P.qw[s];
     const double mw = P.mw[s];
     const bool frozen = P.deposit_only || ((s == 1) && P.frozen_ions);
-    const bool collide = (s == 0) && P.mcc_on;
+    const bool collide_on = (s == 0) && P.mcc_on && !P.deposit_only;
     const bool emit = (s == 1) && P.see_on;
-    const int nt = P.n_table;
-    T *Q = P.q[s];
-
-    double ke = 0.0, pzs = 0.0, dq = 0.0;
-    unsigned int n_abs1 = 0, n_abs2 = 0, n_abs3 = 0, n_abs4 = 0;
-    unsigned int n_cand = 0, n_el = 0, n_ex = 0, n_iz = 0, n_see = 0, n_fb = 0;
+    T *__restrict__ Q = P.q[s];
+    Tally t;
 
     for (int64_t base = (int64_t)blk * PUSH_CHUNK; base < n;
          base += (int64_t)nblk * PUSH_CHUNK) {
-        int ci[PUSH_PPT], cj[PUSH_PPT];
-        T cfr[PUSH_PPT], cfz[PUSH_PPT];
-        int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
+        const int64_t p0 = base + 4 * tid;
+        int kk[4];
+        T fr[4], fz[4], vr[4], vt[4], vz[4];
+        uint32_t id[4] = {0u, 0u, 0u, 0u};
+        const bool any = p0 < n;
+        if (any) {
+            // slots p0..p0+3 are inside the (4-rounded) capacity; those at or
+            // beyond the count are masked and written back unchanged
+            const int4 k4 = *(const int4 *)(KEY + p0);
+            const T4 a = *(const T4 *)(FR + p0);
+            const T4 b = *(const T4 *)(FZ + p0);
+            const T4 c = *(const T4 *)(VR + p0);
+            const T4 d = *(const T4 *)(VT + p0);
+            const T4 e = *(const T4 *)(VZ + p0);
+            kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
+            fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
+            fz[0] = b.x; fz[1] = b.y; fz[2] = b.z; fz[3] = b.w;
+            vr[0] = c.x; vr[1] = c.y; vr[2] = c.z; vr[3] = c.w;
+            vt[0] = d.x; vt[1] = d.y; vt[2] = d.z; vt[3] = d.w;
+            vz[0] = e.x; vz[1] = e.y; vz[2] = e.z; vz[3] = e.w;
+            if (collide_on) {
+                const uint4 iv = *(const uint4 *)(ID + p0);
+                id[0] = iv.x; id[1] = iv.y; id[2] = iv.z; id[3] = iv.w;
+            }
 #pragma unroll
-        for (int k = 0; k < PUSH_PPT; ++k) {
-            const int64_t p = base + (int64_t)k * PUSH_THREADS + tid;
-            ci[k] = -1;
-            cj[k] = 0;
-            cfr[k] = 0;
-            cfz[k] = 0;
-            if (p >= n) continue;
-            const int key = S.key[p];
-            if (key < 0) continue;
-            const int i = key & 0xffff, j = key >> 16;
-            const T fr = S.fr[p], fz = S.fz[p];
-            const T vr = S.vr[p], vt = S.vt[p], vz = S.vz[p];
-            if (frozen) {
-                ke += 0.5 * mw * ((double)vr * vr + (double)vt * vt + (double)vz * vz);
-                pzs += mw * (double)vz;
-                ci[k] = i;
-                cj[k] = j;
-                cfr[k] = fr;
-                cfz[k] = fz;
-                imin = min(imin, i); imax = max(imax, i);
-                jmin = min(jmin, j); jmax = max(jmax, j);
-                continue;
-            }
-            // ---- gather
-            const T4 a00 = P.node[(int64_t)j * ldn + i];
-            const T4 a10 = P.node[(int64_t)j * ldn + i + 1];
-            const T4 a01 = P.node[(int64_t)(j + 1) * ldn + i];
-            const T4 a11 = P.node[(int64_t)(j + 1) * ldn + i + 1];
-            const T gr = (T)1 - fr, gz = (T)1 - fz;
-            const T w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
-            T er, ez;
-            if (SCHEME == PIC_EC) {
-                er = gz * a00.x + fz * a01.x;
-                ez = gr * a00.y + fr * a10.y;
-            } else {
-                er = w00 * a00.x + w10 * a10.x + w01 * a01.x + w11 * a11.x;
-                ez = w00 * a00.y + w10 * a10.y + w01 * a01.y + w11 * a11.y;
-            }
-            const T br = w00 * a00.z + w10 * a10.z + w01 * a01.z + w11 * a11.z;
-            const T bz = w00 * a00.w + w10 * a10.w + w01 * a01.w + w11 * a11.w;
-            // ---- Boris: half kick, rotation about t = (q dt / 2m) B, half kick
-            const T mx = vr + hqm * er, my = vt, mz = vz + hqm * ez;
-            const T tx = hqm * br, tz = hqm * bz;
-            const T f2 = (T)2 / ((T)1 + tx * tx + tz * tz);
-            const T sx = f2 * tx, sz = f2 * tz;
-            const T px = mx + my * tz;
-            const T py = my + (mz * tx - mx * tz);
-            const T pzz = mz - my * tx;
-            const T qx = mx + py * sz;
-            const T qy = my + (pzz * sx - px * sz);
-            const T qz = mz - py * sx;
-            const T nx = qx + hqm * er, ny = qy, nzv = qz + hqm * ez;
-            ke += 0.5 * mw * ((double)vr * nx + (double)vt * ny + (double)vz * nzv);
-            pzs += mw * (double)nzv;
-            // ---- drift in (x, y, z) = (r, 0, z), rotate into the new plane
-            const T r = ((T)i + fr) * P.dr;
-            const T dx = nx * P.dt, dy = ny * P.dt;
-            const T x1 = r + dx;
-            const T r1 = sqrt(x1 * x1 + dy * dy);
-            T vr1 = nx, vt1 = ny, vz1 = nzv;
-            if (r1 > (T)0) {
-                const T c = x1 / r1, sn = dy / r1;
-                vr1 = c * nx + sn * ny;
-                vt1 = c * ny - sn * nx;
-            }
-            const T den = r + r1;
-            const T drr = (den > (T)0) ? ((T)2 * r * dx + dx * dx + dy * dy) / den : (T)0;
-            const T xr = fr + drr * P.inv_dr;
-            const T xz = fz + nzv * P.dt * P.inv_dz;
-            const T flr = floor(xr), flz = floor(xz);
-            int i1 = i + (int)flr, j1 = j + (int)flz;
-            T fr1 = xr - flr, fz1 = xz - flz;
-            if (fr1 >= (T)1) { fr1 = (T)0; ++i1; }
-            if (fz1 >= (T)1) { fz1 = (T)0; ++j1; }
-            // ---- walls
-            int fate = 0;
-            if (j1 < 0) {
-                if (P.wall_bc[0] == PIC_REFLECT) {
-                    const T zg = -((T)j1 + fz1);
-                    const T fl = floor(zg);
-                    j1 = (int)fl;
-                    fz1 = zg - fl;
-                    if (fz1 >= (T)1) { fz1 = (T)0; ++j1; }
-                    vz1 = -vz1;
-                } else {
-                    fate = (r1 < P.cathode_rmax) ? 1 : 2;
+            for (int k = 1; k < 4; ++k)
+                if (p0 + k >= n) kk[k] = -1;
+        } else {
+            kk[0] = kk[1] = kk[2] = kk[3] = -1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) fr[k] = fz[k] = vr[k] = vt[k] = vz[k] = (T)0;
+        }
+        int ok[4];   // cell key after the push, -1 if none
+        if (!frozen) {
+            int prev = -2;
+            T4 a00, a10, a01, a11;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ok[k] = -1;
+                const int key = kk[k];
+                if (key < 0) continue;
+                int i = key & 0xffff, j = key >> 16;
+                if (key != prev) {
+                    const T4 *nb = NODE + (int64_t)j * ldn + i;
+                    a00 = nb[0];
+                    a10 = nb[1];
+                    a01 = nb[ldn];
+                    a11 = nb[ldn + 1];
+                    prev = key;
                 }
-            }
-            if (fate == 0 && i1 >= nr) {
-                if (P.wall_bc[2] == PIC_REFLECT) {
-                    const T rg = (T)(2 * nr) - ((T)i1 + fr1);
-                    const T fl = floor(rg);
-                    i1 = (int)fl;
-                    fr1 = rg - fl;
-                    if (i1 >= nr) { i1 = nr - 1; fr1 = (T)1 - (T)1 / (T)16777216; }
-                    vr1 = -vr1;
-                } else {
-                    fate = 3;
-                }
-            }
-            if (fate == 0 && j1 >= nz) {
-                if (P.wall_bc[1] == PIC_REFLECT) {
-                    const T zg = (T)(2 * nz) - ((T)j1 + fz1);
-                    const T fl = floor(zg);
-                    j1 = (int)fl;
-                    fz1 = zg - fl;
-                    if (j1 >= nz) { j1 = nz - 1; fz1 = (T)1 - (T)1 / (T)16777216; }
-                    vz1 = -vz1;
-                } else {
-                    fate = 4;
-                }
-            }
-            if (fate == 0) {
-                // r' >= 0 exactly; round-off can put i' at -1 next to the axis.
-                // Any index still outside the grid (non-finite or absurd
-                // velocities under reflecting walls) is clamped so every
-                // access stays in bounds.
-                if (i1 < 0) { i1 = 0; fr1 = (T)0; }
-                if (i1 > nr - 1) { i1 = nr - 1; fr1 = (T)1 - (T)1 / (T)16777216; }
-                if (j1 < 0) { j1 = 0; fz1 = (T)0; }
-                if (j1 > nz - 1) { j1 = nz - 1; fz1 = (T)1 - (T)1 / (T)16777216; }
-                if (!(fr1 >= (T)0 && fr1 < (T)1)) fr1 = (T)0;
-                if (!(fz1 >= (T)0 && fz1 < (T)1)) fz1 = (T)0;
-            }
-            if (fate) {
-                S.key[p] = -1;
-                if (fate == 1) {
-                    ++n_abs1;
-                    dq += P.qw64[s];
-                    if (emit) {
-                        const uint32_t id = S.id[p];
-                        const uint4 u = philox4x32_10(
-                            make_uint4(id, (P.run << 8) | (1u << 4) | PURPOSE_SEE, step, 0u),
-                            P.key0, P.key1);
-                        if ((unsigned long long)u.x < P.t_see) {
-                            ++n_see;
-                            dq -= P.qw64[0];
-                            int ie = i1;
-                            T fe = fr1;
-                            if (ie >= nr) { ie = nr - 1; fe = (T)1 - (T)1 / (T)16777216; }
-                            if (ie < 0) { ie = 0; fe = (T)0; }
-                            record_child(P, 1, id, 0, 0, ie, 0, fe, (T)0, (T)0, (T)0, (T)0);
+                T r1;
+                const int fate = advance<T, SCHEME>(P, hqm, mw, a00, a10, a01, a11, i, j, fr[k],
+                                                    fz[k], vr[k], vt[k], vz[k], t, r1);
+                if (fate) {
+                    kk[k] = -1;
+                    if (fate == 1) {
+                        ++t.abs1;
+                        t.dq += P.qw64[s];
+                        if (emit) {
+                            const uint32_t pid = ID[p0 + k];
+                            const uint4 u = philox4x32_10(
+                                make_uint4(pid, (P.run << 8) | (1u << 4) | PURPOSE_SEE, step, 0u),
+                                P.key0, P.key1);
+                            if ((unsigned long long)u.x < P.t_see) {
+                                ++t.see;
+                                t.dq -= P.qw64[0];
+                                int ie = i;
+                                T fe = fr[k];
+                                if (ie > P.nr - 1) { ie = P.nr - 1; fe = near_one<T>(); }
+                                if (ie < 0) { ie = 0; fe = (T)0; }
+                                record_child(P, 1, pid, 0, 0, ie, 0, fe, (T)0, (T)0, (T)0, (T)0);
+                            }
                         }
+                    } else if (fate == 2) {
+                        ++t.abs2;
+                    } else if (fate == 3) {
+                        ++t.abs3;
+                    } else {
+                        ++t.abs4;
                     }
-                } else if (fate == 2) {
-                    ++n_abs2;
-                } else if (fate == 3) {
-                    ++n_abs3;
-                } else {
-                    ++n_abs4;
+                    continue;
                 }
-                continue;
+                if (collide_on) collide(P, id[k], step, i, j, fr[k], fz[k], vr[k], vt[k], vz[k], t);
+                kk[k] = ok[k] = (j << 16) | i;
             }
-            // ---- null-collision MCC (electrons)
-            if (collide) {
-                const uint32_t id = S.id[p];
-                const uint4 u = philox4x32_10(
-                    make_uint4(id, (P.run << 8) | PURPOSE_MCC, step, 0u), P.key0, P.key1);
-                if ((unsigned long long)u.x < P.t_null) {
-                    ++n_cand;
-                    const T v2 = vr1 * vr1 + vt1 * vt1 + vz1 * vz1;
-                    const T e = P.e_of_v2 * v2;
-                    const T x = e * P.inv_de;
-                    int kk;
-                    T f;
-                    if (x >= (T)(nt - 1)) { kk = nt - 2; f = (T)1; }
-                    else { const T fl = floor(x); kk = (int)fl; f = x - fl; }
-                    const T c1 = interp_row(P.nu, kk, f);
-                    const T c2 = c1 + interp_row(P.nu + nt, kk, f);
-                    const T c3 = c2 + interp_row(P.nu + 2 * nt, kk, f);
-                    const T rsel = u24<T>(u.y) * P.numax;
-                    int proc = -1;
-                    if (rsel < c1) proc = 0;
-                    else if (rsel < c2) proc = (e >= P.e_exc) ? 1 : -1;
-                    else if (rsel < c3) proc = (e >= P.e_iz) ? 2 : -1;
-                    if (proc >= 0) {
-                        T d0, d1, d2;
-                        iso_direction(u.z, u.w, d0, d1, d2);
-                        T enew;
-                        if (proc == 0) {
-                            ++n_el;
-                            const T vm = sqrt(v2);
-                            const T cth = (vr1 * d0 + vt1 * d1 + vz1 * d2) / vm;
-                            enew = e * ((T)1 - P.two_m_over_M * ((T)1 - cth));
-                        } else if (proc == 1) {
-                            ++n_ex;
-                            enew = e - P.e_exc;
-                        } else {
-                            ++n_iz;
-                            const T erem = e - P.e_iz;
-                            const uint4 ua = philox4x32_10(
-                                make_uint4(id, (P.run << 8) | PURPOSE_IZ, step, 0u), P.key0, P.key1);
-                            const uint4 ub = philox4x32_10(
-                                make_uint4(id, (P.run << 8) | PURPOSE_ION, step, 0u), P.key0, P.key1);
-                            const T eej = u24<T>(ua.x) * erem;
-                            enew = erem - eej;
-                            T e0, e1, e2;
-                            iso_direction(ua.y, ua.z, e0, e1, e2);
-                            const T vej = sqrt(P.v2_of_e * eej);
-                            record_child(P, 0, id, 0, 0, i1, j1, fr1, fz1, vej * e0, vej * e1,
-                                         vej * e2);
-                            const T a0 = sqrt((T)-2 * log(u24_open<T>(ub.x)));
-                            const T a1 = sqrt((T)-2 * log(u24_open<T>(ub.z)));
-                            T s0, c0, s1, c1b;
-                            sincos_2pi(u24<T>(ub.y), &s0, &c0);
-                            sincos_2pi(u24<T>(ub.w), &s1, &c1b);
-                            record_child(P, 0, id, 1, 1, i1, j1, fr1, fz1, P.sig_ion * a0 * c0,
-                                         P.sig_ion * a0 * s0, P.sig_ion * a1 * c1b);
-                        }
-                        const T vn = sqrt(P.v2_of_e * enew);
-                        vr1 = vn * d0;
-                        vt1 = vn * d1;
-                        vz1 = vn * d2;
-                    }
+            if (any) {
+                *(int4 *)(KEY + p0) = make_int4(kk[0], kk[1], kk[2], kk[3]);
+                T4 a, b, c, d, e;
+                a.x = fr[0]; a.y = fr[1]; a.z = fr[2]; a.w = fr[3];
+                b.x = fz[0]; b.y = fz[1]; b.z = fz[2]; b.w = fz[3];
+                c.x = vr[0]; c.y = vr[1]; c.z = vr[2]; c.w = vr[3];
+                d.x = vt[0]; d.y = vt[1]; d.z = vt[2]; d.w = vt[3];
+                e.x = vz[0]; e.y = vz[1]; e.z = vz[2]; e.w = vz[3];
+                *(T4 *)(FR + p0) = a;
+                *(T4 *)(FZ + p0) = b;
+                *(T4 *)(VR + p0) = c;
+                *(T4 *)(VT + p0) = d;
+                *(T4 *)(VZ + p0) = e;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                ok[k] = kk[k];
+                if (kk[k] >= 0 && !P.deposit_only) {
+                    t.ke += 0.5 * mw * ((double)vr[k] * vr[k] + (double)vt[k] * vt[k] +
+                                        (double)vz[k] * vz[k]);
+                    t.pz += mw * (double)vz[k];
                 }
             }
-            S.key[p] = (j1 << 16) | i1;
-            S.fr[p] = fr1;
-            S.fz[p] = fz1;
-            S.vr[p] = vr1;
-            S.vt[p] = vt1;
-            S.vz[p] = vz1;
-            ci[k] = i1;
-            cj[k] = j1;
-            cfr[k] = fr1;
-            cfz[k] = fz1;
-            imin = min(imin, i1); imax = max(imax, i1);
-            jmin = min(jmin, j1); jmax = max(jmax, j1);
         }
 
         // ---- deposit: block bounding box of the chunk's cells
+        int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (ok[k] < 0) continue;
+            const int i = ok[k] & 0xffff, j = ok[k] >> 16;
+            imin = min(imin, i); imax = max(imax, i);
+            jmin = min(jmin, j); jmax = max(jmax, j);
+        }
         imin = wave_min(imin); imax = wave_max(imax);
         jmin = wave_min(jmin); jmax = wave_max(jmax);
         if (lane == 0) {
@@ -353,44 +461,52 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
         __syncthreads();
         imin = red[0][0]; imax = red[1][0]; jmin = red[2][0]; jmax = red[3][0];
 #pragma unroll
-        for (int w = 1; w < PUSH_THREADS / 64; ++w) {
+        for (int w = 1; w < NW; ++w) {
             imin = min(imin, red[0][w]); imax = max(imax, red[1][w]);
             jmin = min(jmin, red[2][w]); jmax = max(jmax, red[3][w]);
         }
         if (imax >= imin) {
             const int bw = imax - imin + 2, bh = jmax - jmin + 2;
-            if (bw * bh <= LDS_NODES) {
-                for (int t = tid; t < bw * bh; t += PUSH_THREADS) lds_q[t] = (T)0;
+            const bool use_lds = bw * bh <= LDS_NODES;
+            if (use_lds) {
+                for (int q = tid; q < bw * bh; q += PUSH_THREADS) lds_q[q] = (T)0;
                 __syncthreads();
+            } else if (tid == 0) {
+                ++t.fb;
+            }
+            const int shift = (jmin << 16) | imin;
+            // sum the thread's particles per run of equal cells, then add
+            int cur = -1;
+            T s00 = 0, s10 = 0, s01 = 0, s11 = 0;
 #pragma unroll
-                for (int k = 0; k < PUSH_PPT; ++k) {
-                    if (ci[k] < 0) continue;
-                    const int li = ci[k] - imin, lj = cj[k] - jmin;
-                    const T gr = (T)1 - cfr[k], gz = (T)1 - cfz[k];
-                    atomicAdd(&lds_q[lj * bw + li], qw * gr * gz);
-                    atomicAdd(&lds_q[lj * bw + li + 1], qw * cfr[k] * gz);
-                    atomicAdd(&lds_q[(lj + 1) * bw + li], qw * gr * cfz[k]);
-                    atomicAdd(&lds_q[(lj + 1) * bw + li + 1], qw * cfr[k] * cfz[k]);
+            for (int k = 0; k < 4; ++k) {
+                if (ok[k] < 0) continue;
+                if (ok[k] != cur) {
+                    if (cur >= 0) {
+                        if (use_lds) deposit_lds(lds_q, bw, cur - shift, qw, s00, s10, s01, s11);
+                        else deposit_global(Q, ldn, cur, qw, s00, s10, s01, s11);
+                    }
+                    cur = ok[k];
+                    s00 = s10 = s01 = s11 = (T)0;
                 }
+                const T gr = (T)1 - fr[k], gz = (T)1 - fz[k];
+                s00 += gr * gz;
+                s10 += fr[k] * gz;
+                s01 += gr * fz[k];
+                s11 += fr[k] * fz[k];
+            }
+            if (cur >= 0) {
+                if (use_lds) deposit_lds(lds_q, bw, cur - shift, qw, s00, s10, s01, s11);
+                else deposit_global(Q, ldn, cur, qw, s00, s10, s01, s11);
+            }
+            if (use_lds) {
                 __syncthreads();
-                for (int t = tid; t < bw * bh; t += PUSH_THREADS) {
-                    const T v = lds_q[t];
+                for (int q = tid; q < bw * bh; q += PUSH_THREADS) {
+                    const T v = lds_q[q];
                     if (v != (T)0) {
-                        const int lj = t / bw, li = t - lj * bw;
+                        const int lj = q / bw, li = q - lj * bw;
                         atomic_add_dev(&Q[(int64_t)(jmin + lj) * ldn + imin + li], v);
                     }
-                }
-            } else {
-                if (tid == 0) ++n_fb;
-#pragma unroll
-                for (int k = 0; k < PUSH_PPT; ++k) {
-                    if (ci[k] < 0) continue;
-                    const int64_t n0 = (int64_t)cj[k] * ldn + ci[k];
-                    const T gr = (T)1 - cfr[k], gz = (T)1 - cfz[k];
-                    atomic_add_dev(&Q[n0], qw * gr * gz);
-                    atomic_add_dev(&Q[n0 + 1], qw * cfr[k] * gz);
-                    atomic_add_dev(&Q[n0 + ldn], qw * gr * cfz[k]);
-                    atomic_add_dev(&Q[n0 + ldn + 1], qw * cfr[k] * cfz[k]);
                 }
             }
         }
@@ -398,41 +514,36 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
     }
 
     // ---- block totals of the diagnostics, one atomic per quantity
-    ke = wave_sum(ke);
-    pzs = wave_sum(pzs);
-    dq = wave_sum(dq);
-    unsigned long long c[12] = {n_abs1, n_abs2, n_abs3, n_abs4, n_cand, n_el,
-                                n_ex,   n_iz,   n_see,  n_fb,   0,      0};
+    double dv[3] = {wave_sum(t.ke), wave_sum(t.pz), wave_sum(t.dq)};
+    unsigned long long c[10] = {t.abs1, t.abs2, t.abs3, t.abs4, t.cand,
+                                t.el,   t.ex,   t.iz,   t.see,  t.fb};
 #pragma unroll
     for (int q = 0; q < 10; ++q) c[q] = wave_sum_u64(c[q]);
     if (lane == 0) {
-        dred[0][wid] = ke;
-        dred[1][wid] = pzs;
-        dred[2][wid] = dq;
-#pragma unroll
+        for (int q = 0; q < 3; ++q) dred[q][wid] = dv[q];
         for (int q = 0; q < 10; ++q) cred[q][wid] = c[q];
     }
     __syncthreads();
     if (tid == 0) {
         double a = 0, b = 0, d = 0;
-        unsigned long long t[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        for (int w = 0; w < PUSH_THREADS / 64; ++w) {
+        unsigned long long tt[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int w = 0; w < NW; ++w) {
             a += dred[0][w];
             b += dred[1][w];
             d += dred[2][w];
-            for (int q = 0; q < 10; ++q) t[q] += cred[q][w];
+            for (int q = 0; q < 10; ++q) tt[q] += cred[q][w];
         }
         DevScalars *sc = P.sc;
         if (a != 0.0) atomic_add_dev(&sc->ke[s], a);
         if (b != 0.0) atomic_add_dev(&sc->pz[s], b);
         if (d != 0.0) atomic_add_dev(&sc->dq_conv, d);
         for (int q = 0; q < 4; ++q)
-            if (t[q]) atomicAdd(&sc->n_abs[s][q + 1], t[q]);
-        if (t[4]) atomicAdd(&sc->n_cand, t[4]);
+            if (tt[q]) atomicAdd(&sc->n_abs[s][q + 1], tt[q]);
+        if (tt[4]) atomicAdd(&sc->n_cand, tt[4]);
         for (int q = 0; q < 3; ++q)
-            if (t[5 + q]) atomicAdd(&sc->n_coll[q], t[5 + q]);
-        if (t[8]) atomicAdd(&sc->n_see, t[8]);
-        if (t[9]) atomicAdd(&sc->deposit_fallback, t[9]);
+            if (tt[5 + q]) atomicAdd(&sc->n_coll[q], tt[5 + q]);
+        if (tt[8]) atomicAdd(&sc->n_see, tt[8]);
+        if (tt[9]) atomicAdd(&sc->deposit_fallback, tt[9]);
     }
 }
 
