@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <tuple>
@@ -59,6 +60,13 @@ struct pic_handle {
     int steps_since_sort = 0;
     pic_poisson_stats last = {};
     double rho = 0.15, rel0_est = 1e-2;
+    struct PassGraph {
+        const void *phi, *q0, *q1;
+        int n_iter;
+        hipGraphExec_t exec;
+    };
+    std::vector<PassGraph> graphs;
+    bool use_graphs = true;
     int32_t host_flags = 0;
     bool timers_on = false;
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
@@ -211,6 +219,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     f.phi = cv.take<double>(nodes * 8);
     f.phi0 = cv.take<double>(nodes * 8);
     f.phi_l = cv.take<double>(nodes * 8);
+    f.phi0_prev = cv.take<double>(nodes * 8);
     f.r64 = cv.take<double>(nodes * 8);
     f.b_r = cv.take<double>(nodes * 8);
     f.b_z = cv.take<double>(nodes * 8);
@@ -254,8 +263,13 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     H.tail.last = H.nlevels - 1;
     H.tail.tmp_size = (shapes[first].nr + 1) * (shapes[first].nz + 1);
     int64_t words = H.tail.tmp_size;
-    for (int m = first; m < H.nlevels; ++m)
-        words += 2 * (int64_t)(shapes[m].nr + 1) * (shapes[m].nz + 1);
+    for (int m = 0; m < MAX_LEVELS; ++m) H.tail.offx[m] = H.tail.offb[m] = 0;
+    for (int m = first; m < H.nlevels; ++m) {
+        const int64_t nm = (int64_t)(shapes[m].nr + 1) * (shapes[m].nz + 1);
+        H.tail.offx[m] = (int32_t)words;
+        H.tail.offb[m] = (int32_t)(words + nm);
+        words += 2 * nm;
+    }
     H.tail_lds_bytes = (int32_t)(words * 4);
     for (int l = 0; l < H.nlevels; ++l) H.tail.L[l] = H.lv[l];
     const int cu = coarse_unknowns(c, shapes.back());
@@ -448,16 +462,68 @@ pic_status readback(pic_handle *h, SolveReadback *rb)
     return PIC_OK;
 }
 
+// One refinement pass (after the residual that precedes it): scale, V-cycle,
+// n_iter preconditioned CG iterations, FP64 update and the new residual.
+template <typename Q>
+void enqueue_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_iter)
+{
+    hipStream_t s = h->stream;
+    FieldDev &f = h->f;
+    const MGHier &H = f.mg;
+    const double inv_2pi_eps0 = 1.0 / (2.0 * 3.14159265358979323846 * eps0());
+    launch_cast_scale(f, h->sc, s);
+    launch_zero(h->sc->pcg_rz, sizeof(double) * 3 * (MAX_PCG + 2), s);
+    launch_mg_vcycle(H, &h->sc->pcg_rz[0], s);
+    for (int k = 0; k < n_iter; ++k) {
+        launch_cg_matvec(H, H.lv[0].xu, f.p32[(k + 1) & 1], f.p32[k & 1], f.q32, h->sc->pcg_rz,
+                         k, &h->sc->pcg_pq[k], s);
+        launch_cg_update(H, f.p32[k & 1], f.q32, f.e32, H.lv[0].b, &h->sc->pcg_rz[k],
+                         &h->sc->pcg_pq[k], &h->sc->pcg_rr[k], s);
+        if (k + 1 < n_iter) launch_mg_vcycle(H, &h->sc->pcg_rz[k + 1], s);
+    }
+    launch_update64(f, phi, h->sc, inv_2pi_eps0, s);
+    launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
+}
+
+// The pass is replayed from a cached hipGraph per (buffers, iteration count)
+// when the stream allows capture; otherwise its kernels are launched directly.
+template <typename Q>
+pic_status run_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_iter)
+{
+    if (!h->use_graphs || h->stream == nullptr) {
+        enqueue_pass<Q>(h, phi, q0, q1, n_iter);
+        return PIC_OK;
+    }
+    for (auto &g : h->graphs)
+        if (g.phi == phi && g.q0 == q0 && g.q1 == q1 && g.n_iter == n_iter) {
+            HIPCHECK(h, hipGraphLaunch(g.exec, h->stream));
+            return PIC_OK;
+        }
+    hipGraph_t graph;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        h->use_graphs = false;
+        enqueue_pass<Q>(h, phi, q0, q1, n_iter);
+        return PIC_OK;
+    }
+    enqueue_pass<Q>(h, phi, q0, q1, n_iter);
+    HIPCHECK(h, hipStreamEndCapture(h->stream, &graph));
+    hipGraphExec_t exec;
+    HIPCHECK(h, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    h->graphs.push_back({phi, q0, q1, n_iter, exec});
+    HIPCHECK(h, hipGraphLaunch(exec, h->stream));
+    return PIC_OK;
+}
+
 template <typename Q>
 pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_cathode,
                  pic_poisson_stats *st)
 {
     hipStream_t s = h->stream;
     FieldDev &f = h->f;
-    const MGHier &H = f.mg;
     const double rtol = h->cfg.poisson_rtol;
     const int maxit = h->cfg.poisson_maxit;
-    const double inv_2pi_eps0 = 1.0 / (2.0 * 3.14159265358979323846 * eps0());
     pic_poisson_stats S = {};
     launch_set_dirichlet(f, phi, v_cathode, s);
     launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
@@ -474,20 +540,10 @@ pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_
     for (int pass = 0;; ++pass) {
         if (pass == max_pass || S.iterations >= maxit) break;
         n_iter = std::max(1, std::min(n_iter, maxit - S.iterations));
-        launch_cast_scale(f, h->sc, s);
-        launch_zero(h->sc->pcg_rz, sizeof(double) * 3 * (MAX_PCG + 2), s);
-        launch_mg_vcycle(H, &h->sc->pcg_rz[0], s);
-        for (int k = 0; k < n_iter; ++k) {
-            launch_cg_matvec(H, H.lv[0].xu, f.p32[(k + 1) & 1], f.p32[k & 1], f.q32,
-                             h->sc->pcg_rz, k, &h->sc->pcg_pq[k], s);
-            launch_cg_update(H, f.p32[k & 1], f.q32, f.e32, H.lv[0].b, &h->sc->pcg_rz[k],
-                             &h->sc->pcg_pq[k], &h->sc->pcg_rr[k], s);
-            if (k + 1 < n_iter) launch_mg_vcycle(H, &h->sc->pcg_rz[k + 1], s);
-        }
+        pic_status pe = run_pass<Q>(h, phi, q0, q1, n_iter);
+        if (pe != PIC_OK) return pe;
         S.iterations += n_iter;
         S.outer++;
-        launch_update64(f, phi, h->sc, inv_2pi_eps0, s);
-        launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
         SolveReadback rb;
         pic_status e = readback(h, &rb);
         if (e != PIC_OK) return e;
@@ -649,6 +705,7 @@ pic_status field_update(pic_handle *h)
     const pic_config &c = h->cfg;
     hipEvent_t ev[2];
     timer_begin(h, ev);
+    launch_extrapolate(h->f, 0, h->stream);
     pic_status st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr);
     timer_end(h, 3, ev);
     if (st != PIC_OK) return st;
@@ -800,6 +857,7 @@ pic_status init_typed(pic_handle *h, const pic_species_host *init)
         st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr);
         if (st != PIC_OK) return st;
     }
+    launch_extrapolate(h->f, 1, s);
     const double v0 = (c.circuit == PIC_RESISTOR) ? c.v_ext : c.v_fixed;
     launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, PIC_FIXED_V, v0, 0.0,
                       1.0, c.dt, 0.0, s);
@@ -846,6 +904,8 @@ pic_status pic_init(const pic_config *cfg, void *workspace_dev, int64_t workspac
     h->ts = (cfg->precision == PIC_F64) ? 8 : 4;
     h->cap[0] = cfg->capacity[0];
     h->cap[1] = cfg->capacity[1];
+    const char *ng = getenv("PIC_NO_GRAPHS");
+    h->use_graphs = !(ng && ng[0] == '1');
     layout(*cfg, h->ws, h);
     st = (h->prec == PIC_F64) ? init_typed<double>(h, init) : init_typed<float>(h, init);
     // the host arrays of the config are not kept
@@ -1059,6 +1119,7 @@ pic_status pic_free(pic_handle *h)
     if (!h) return PIC_OK;
     (void)hipStreamSynchronize(h->stream);
     timers_collect(h);
+    for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
     for (auto &e : h->free_events) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);

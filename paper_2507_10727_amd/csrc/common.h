@@ -208,6 +208,8 @@ struct MGTail {
     MGLevel L[MAX_LEVELS];
     int32_t first, last;        // levels handled inside one workgroup
     int32_t tmp_size;           // nodes of level `first`
+    int32_t offx[MAX_LEVELS];   // LDS float offsets of each level's x and b
+    int32_t offb[MAX_LEVELS];
     const float *inv;           // dense inverse on the coarsest unknowns
     const int32_t *map;         // unknown index -> node index (coarsest level)
     int32_t ninv;
@@ -234,6 +236,7 @@ struct FieldDev {
     const double *ce64, *cn64;  // FP64 couplings (with eps0)
     const uint8_t *kind;        // 0 unknown, 1 cathode, 2 grounded
     double *phi, *phi0, *phi_l;
+    double *phi0_prev;          // phi0 of the previous step (warm-start extrapolation)
     double *r64;                // FP64 residual
     float *e32, *q32, *p32[2];  // inner CG vectors (finest level)
     MGHier mg;                  // r32 = mg.lv[0].b, z32 = mg.lv[0].xu
@@ -264,6 +267,8 @@ void launch_diag_grid(const FieldDev &f, const T *q0, const T *q1, double q_e, d
 void launch_count_live(const int32_t *key, const DevScalars *sc, int species,
                        unsigned long long *out, hipStream_t s);
 void launch_zero_unknowns(const FieldDev &f, double *phi, hipStream_t s);
+// phi0 <- 2 phi0 - phi0_prev, phi0_prev <- phi0 (unknown nodes); copy when first
+void launch_extrapolate(const FieldDev &f, int first, hipStream_t s);
 
 // host_tables.cpp (FP64 host arithmetic, built without FMA contraction)
 double host_nu_tables(const pic_config &c, double *nu, unsigned long long *t_null);

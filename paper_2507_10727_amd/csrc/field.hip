@@ -185,6 +185,16 @@ __global__ void k_zero_unknowns(int64_t nn, const uint8_t *kind, double *phi)
         if (kind[n] == 0) phi[n] = 0.0;
 }
 
+__global__ void k_extrapolate(int64_t nn, const uint8_t *kind, double *phi0, double *prev,
+                              int first)
+{
+    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
+        const double t = phi0[n];
+        if (!first && kind[n] == 0) phi0[n] = 2.0 * t - prev[n];
+        prev[n] = t;
+    }
+}
+
 __global__ void k_set_dirichlet(int64_t nn, const uint8_t *kind, double *phi, double vcat)
 {
     for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
@@ -293,6 +303,13 @@ void launch_field_prep(const FieldDev &f, typename Vec4<T>::type *node, DevScala
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     hipLaunchKernelGGL((k_field_prep<T>), dim3(blocks_for(nn)), dim3(FB), 0, s, f.nr, f.nz, f.dr,
                        f.dz, f.phi, f.phi0, f.phi_l, f.b_r, f.b_z, node, sc, scheme, use_phi);
+}
+
+void launch_extrapolate(const FieldDev &f, int first, hipStream_t s)
+{
+    const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
+    hipLaunchKernelGGL(k_extrapolate, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.kind, f.phi0,
+                       f.phi0_prev, first);
 }
 
 void launch_set_dirichlet(const FieldDev &f, double *phi, double v_cathode, hipStream_t s)

@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) k_mg_down(MGLevel F, MGLevel C)
             if (((i + j) & 1) == 0) {
                 float w, e, s, n;
                 mg_coup(F, i, j, w, e, s, n);
-                xv = bv / (w + e + s + n);
+                xv = bv * __builtin_amdgcn_rcpf(w + e + s + n);
             }
         }
         sb[lj][li] = bv;
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(256) k_mg_down(MGLevel F, MGLevel C)
         mg_coup(F, i, j, w, e, s, n);
         const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
                           n * sx[lj + 1][li];
-        sx[lj][li] = (sb[lj][li] + off) / (w + e + s + n);
+        sx[lj][li] = (sb[lj][li] + off) * __builtin_amdgcn_rcpf(w + e + s + n);
     }
     __syncthreads();
     // residual on the region the restriction reads (written over b)
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) k_mg_up(MGLevel F, MGLevel C, double *dot
         mg_coup(F, i, j, w, e, s, n);
         const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
                           n * sx[lj + 1][li];
-        sx[lj][li] = (sb[lj][li] + off) / (w + e + s + n);
+        sx[lj][li] = (sb[lj][li] + off) * __builtin_amdgcn_rcpf(w + e + s + n);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < (ULW - 4) * (ULH - 4); t += 256) {
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(256) k_mg_up(MGLevel F, MGLevel C, double *dot
         mg_coup(F, i, j, w, e, s, n);
         const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
                           n * sx[lj + 1][li];
-        sx[lj][li] = (sb[lj][li] + off) / (w + e + s + n);
+        sx[lj][li] = (sb[lj][li] + off) * __builtin_amdgcn_rcpf(w + e + s + n);
     }
     __syncthreads();
     double acc = 0.0;
@@ -224,7 +224,7 @@ __device__ __forceinline__ void tail_sweep(const MGLevel &L, float *x, const flo
             mg_coup(L, i, j, w, e, s, nn);
             const float o = (i > 0 ? w * x[n - 1] : 0.0f) + e * x[n + 1] +
                             (j > 0 ? s * x[n - ld] : 0.0f) + nn * x[n + ld];
-            x[n] = (b[n] + o) / (w + e + s + nn);
+            x[n] = (b[n] + o) * __builtin_amdgcn_rcpf(w + e + s + nn);
         }
     }
 }
@@ -232,16 +232,9 @@ __device__ __forceinline__ void tail_sweep(const MGLevel &L, float *x, const flo
 __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
 {
     extern __shared__ float sm[];
-    float *X[MAX_LEVELS], *B[MAX_LEVELS];
     float *tmp = sm;
-    int off = T.tmp_size;
-    for (int l = T.first; l <= T.last; ++l) {
-        const int nl = (T.L[l].nr + 1) * (T.L[l].nz + 1);
-        X[l] = sm + off;
-        off += nl;
-        B[l] = sm + off;
-        off += nl;
-    }
+#define X(l) (sm + T.offx[(l)])
+#define B(l) (sm + T.offb[(l)])
     const int tx = threadIdx.x, ty = threadIdx.y;
     {
         const MGLevel &L = T.L[T.first];
@@ -249,8 +242,8 @@ __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
         for (int j = ty; j <= L.nz; j += TT)
             for (int i = tx; i <= L.nr; i += TT) {
                 const int n = j * ld + i;
-                B[T.first][n] = L.b[n];
-                X[T.first][n] = 0.0f;
+                B(T.first)[n] = L.b[n];
+                X(T.first)[n] = 0.0f;
             }
     }
     __syncthreads();
@@ -258,7 +251,7 @@ __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
     for (int l = T.first; l < T.last; ++l) {
         const MGLevel &L = T.L[l];
         const int ld = L.nr + 1;
-        float *x = X[l], *b = B[l];
+        float *x = X(l), *b = B(l);
         tail_sweep(L, x, b, 0);
         __syncthreads();
         tail_sweep(L, x, b, 1);
@@ -290,8 +283,8 @@ __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
                         0.25f * ((w && s ? tmp[c - ld - 1] : 0.0f) + (s ? tmp[c - ld + 1] : 0.0f) +
                                  (w ? tmp[c + ld - 1] : 0.0f) + tmp[c + ld + 1]);
                 }
-                B[l + 1][J * ldc + I] = v;
-                X[l + 1][J * ldc + I] = 0.0f;
+                B(l + 1)[J * ldc + I] = v;
+                X(l + 1)[J * ldc + I] = 0.0f;
             }
         __syncthreads();
     }
@@ -301,8 +294,8 @@ __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
         for (int a = tid; a < T.ninv; a += TT * TT) {
             float acc = 0.0f;
             const float *row = T.inv + (int64_t)a * T.ninv;
-            for (int c = 0; c < T.ninv; ++c) acc += row[c] * B[T.last][T.map[c]];
-            X[T.last][T.map[a]] = acc;
+            for (int c = 0; c < T.ninv; ++c) acc += row[c] * B(T.last)[T.map[c]];
+            X(T.last)[T.map[a]] = acc;
         }
         __syncthreads();
     }
@@ -310,10 +303,10 @@ __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
     for (int l = T.last - 1; l >= T.first; --l) {
         const MGLevel &L = T.L[l];
         const int ld = L.nr + 1, ldc = T.L[l + 1].nr + 1;
-        float *x = X[l], *b = B[l];
+        float *x = X(l), *b = B(l);
         for (int j = ty; j <= L.nz; j += TT)
             for (int i = tx; i <= L.nr; i += TT)
-                if (mg_unknown(L, i, j)) x[j * ld + i] += mg_prolong(X[l + 1], ldc, i, j);
+                if (mg_unknown(L, i, j)) x[j * ld + i] += mg_prolong(X(l + 1), ldc, i, j);
         __syncthreads();
         tail_sweep(L, x, b, 1);
         __syncthreads();
@@ -327,8 +320,8 @@ __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
         for (int j = ty; j <= L.nz; j += TT)
             for (int i = tx; i <= L.nr; i += TT) {
                 const int n = j * ld + i;
-                L.xu[n] = X[T.first][n];
-                acc += (double)X[T.first][n] * (double)B[T.first][n];
+                L.xu[n] = X(T.first)[n];
+                acc += (double)X(T.first)[n] * (double)B(T.first)[n];
             }
         if (dot) {
             __shared__ double red[16];
@@ -343,6 +336,8 @@ __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
             }
         }
     }
+#undef X
+#undef B
 }
 
 // ---- conjugate-gradient vector kernels on the finest level

@@ -72,7 +72,10 @@ class Simulation:
         nbytes = C.c_int64()
         L.check(self.lib.pic_query_workspace(C.byref(cfg), C.byref(nbytes)))
         self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
-        self.stream = torch.cuda.current_stream(self.device)
+        # a stream of our own (default priority): the library captures its
+        # field-solve passes as graphs, which the legacy null stream forbids
+        self.stream = torch.cuda.Stream(device=self.device)
+        torch.cuda.synchronize(self.device)
         hosts = (L.pic_species_host * 2)()
         keep_p = []
         if particles is not None:
@@ -110,6 +113,7 @@ class Simulation:
 
     def poisson(self, q, v_cathode, phi):
         """Solve K phi = q in place on device tensors (float64); returns stats."""
+        self.torch.cuda.synchronize(self.device)
         st = L.pic_poisson_stats()
         status = self.lib.pic_poisson(self.h, C.c_void_p(q.data_ptr()), float(v_cathode),
                                       C.c_void_p(phi.data_ptr()), C.byref(st))
@@ -117,6 +121,7 @@ class Simulation:
         return st.as_dict()
 
     def poisson_status(self, q, v_cathode, phi):
+        self.torch.cuda.synchronize(self.device)
         st = L.pic_poisson_stats()
         status = self.lib.pic_poisson(self.h, C.c_void_p(q.data_ptr()), float(v_cathode),
                                       C.c_void_p(phi.data_ptr()), C.byref(st))
