@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--workload", default="ec256x512_f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-poisson", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no "
@@ -127,6 +129,18 @@ def main():
     import torch
     from paper_2507_10727_amd import workloads as W
     from paper_2507_10727_amd.sim import Simulation
+
+    if args.copy_calibration:
+        # a plain device-to-device copy of known size: its FETCH_SIZE /
+        # WRITE_SIZE per dispatch calibrate the counters against 1 GiB
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+        log("[bench] copy calibration: 3 x 1 GiB device copies")
 
     p = W.preset(args.workload)
     log(f"[bench] generating {args.workload}: {p.nr}x{p.nz} cells, {p.n_per_species} per species")

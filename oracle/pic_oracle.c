@@ -76,8 +76,9 @@ static void draw(const orc_problem *p, uint32_t id, int species, int purpose,
 
 /* Uniform on [0,1) from the top 24 bits (exact in binary32 and binary64). */
 static double u24(uint32_t u) { return (double)(u >> 8) * (1.0 / 16777216.0); }
-/* Uniform on (0,1): midpoint of the 24-bit cell, safe for log(). */
-static double u24_open(uint32_t u) { return ((double)(u >> 8) + 0.5) * (1.0 / 16777216.0); }
+/* Uniform on (0,1) for log(): midpoint of a 23-bit cell, so that the value
+ * is exact in binary32 as well as binary64. */
+static double u_open(uint32_t u) { return ((double)(u >> 9) + 0.5) * (1.0 / 8388608.0); }
 
 /* ------------------------------------------------------------------------ */
 /* Field solve.                                                              */
@@ -413,7 +414,8 @@ static double interp(const double *row, int n, double de, double e)
 static void iso_dir(uint32_t ua, uint32_t ub, double d[3])
 {
     double c = 1.0 - 2.0 * u24(ua);
-    double s = sqrt(fmax(0.0, 1.0 - c * c));
+    /* sin(chi) from (1 - c)(1 + c): both factors are exact for c = 1 - 2U */
+    double s = sqrt(fmax(0.0, (1.0 - c) * (1.0 + c)));
     double ph = 2.0 * PI * u24(ub);
     d[0] = s * cos(ph);
     d[1] = s * sin(ph);
@@ -676,7 +678,7 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
                 draw(p, S->id[k], 0, PUR_IZ, st->step, ua);
                 draw(p, S->id[k], 0, PUR_ION, st->step, ub);
                 double eej = u24(ua[0]) * erem;
-                enew = erem - eej;
+                enew = (1.0 - u24(ua[0])) * erem;   /* = erem - eej, without cancellation */
                 double de_[3];
                 iso_dir(ua[1], ua[2], de_);
                 double vej = sqrt(2.0 * QE * eej / me);
@@ -684,8 +686,8 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
                             vej * de_[0], vej * de_[1], vej * de_[2]};
                 push_child(&kids, ce);
                 double sig = sqrt(KB * p->t_gas / p->m[1]);
-                double a0 = sqrt(-2.0 * log(u24_open(ub[0]))), p0 = 2.0 * PI * u24(ub[1]);
-                double a1 = sqrt(-2.0 * log(u24_open(ub[2]))), p1 = 2.0 * PI * u24(ub[3]);
+                double a0 = sqrt(-2.0 * log(u_open(ub[0]))), p0 = 2.0 * PI * u24(ub[1]);
+                double a1 = sqrt(-2.0 * log(u_open(ub[2]))), p1 = 2.0 * PI * u24(ub[3]);
                 child ci = {child_key(0, S->id[k], 1), 1, S->r[k], S->z[k],
                             sig * a0 * cos(p0), sig * a0 * sin(p0), sig * a1 * cos(p1)};
                 push_child(&kids, ci);

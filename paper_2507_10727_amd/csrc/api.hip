@@ -48,6 +48,9 @@ struct pic_handle {
     void *child = nullptr;
     int32_t child_cap = 0;
     void *nu = nullptr;
+    void *cold = nullptr;
+    int2 *mcc_q = nullptr, *see_q = nullptr;
+    int32_t ev_cap = 0;
     FieldDev f;
     int32_t *hist = nullptr, *block_sums = nullptr;
     double *diag_partials = nullptr;
@@ -207,6 +210,10 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     const size_t child_bytes = (ts == 8) ? sizeof(Child<double>) : sizeof(Child<float>);
     void *child = cv.take<char>((int64_t)child_cap * child_bytes);
     void *nu = cv.take<char>((int64_t)3 * c.n_table * ts);
+    void *cold = cv.take<char>(sizeof(PushCold<double>));
+    const int64_t ev_cap = std::max<int64_t>(1024, std::max(cap0, cap1));
+    int2 *mcc_q = cv.take<int2>(ev_cap * 8);
+    int2 *see_q = cv.take<int2>(ev_cap * 8);
     FieldDev f;
     memset(&f, 0, sizeof(f));
     f.nr = c.nr;
@@ -292,6 +299,10 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
         h->child = child;
         h->child_cap = child_cap;
         h->nu = nu;
+        h->cold = cold;
+        h->mcc_q = mcc_q;
+        h->see_q = see_q;
+        h->ev_cap = (int32_t)ev_cap;
         h->f = f;
         h->hist = hist;
         h->block_sums = bsums;
@@ -580,6 +591,32 @@ pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_
 }
 
 template <typename T>
+PushCold<T> push_cold(pic_handle *h)
+{
+    const pic_config &c = h->cfg;
+    PushCold<T> C;
+    memset(&C, 0, sizeof(C));
+    C.child = (Child<T> *)h->child;
+    C.child_cap = h->child_cap;
+    C.nu = (const T *)h->nu;
+    C.n_table = c.n_table;
+    C.inv_de = (T)(1.0 / c.de_table);
+    C.numax = (T)h->numax;
+    C.t_see = h->t_see;
+    const double qe = 1.602176634e-19;
+    C.e_of_v2 = (T)(0.5 * c.m[0] / qe);
+    C.v2_of_e = (T)(2.0 * qe / c.m[0]);
+    C.two_m_over_M = (T)(2.0 * c.m[0] / c.m[1]);
+    C.e_exc = (T)c.e_exc;
+    C.e_iz = (T)c.e_iz;
+    C.sig_ion = (T)std::sqrt(1.380649e-23 * c.t_gas / c.m[1]);
+    for (int s = 0; s < 2; ++s) C.qw64[s] = c.q[s] * c.w[s];
+    for (int k = 0; k < 3; ++k) C.wall_bc[k] = c.wall_bc[k];
+    C.cathode_rmax = (T)c.cathode_rmax;
+    return C;
+}
+
+template <typename T>
 PushParams<T> push_params(pic_handle *h, int deposit_only)
 {
     const pic_config &c = h->cfg;
@@ -587,42 +624,29 @@ PushParams<T> push_params(pic_handle *h, int deposit_only)
     memset(&P, 0, sizeof(P));
     for (int s = 0; s < 2; ++s) {
         P.sp[s] = species_dev<T>(h->buf[s][h->cur[s]]);
-        P.cap[s] = h->cap[s];
         P.q[s] = (T *)h->q[s];
         P.hqm[s] = (T)(0.5 * c.q[s] / c.m[s] * c.dt);
         P.qw[s] = (T)(c.q[s] * c.w[s]);
-        P.qw64[s] = c.q[s] * c.w[s];
-        P.mw[s] = c.m[s] * c.w[s];
+        P.mw[s] = (float)(c.m[s] * c.w[s]);
     }
     P.node = (const typename Vec4<T>::type *)h->node;
     P.sc = h->sc;
-    P.child = (Child<T> *)h->child;
-    P.child_cap = h->child_cap;
-    P.nu = (const T *)h->nu;
-    P.n_table = c.n_table;
-    P.inv_de = (T)(1.0 / c.de_table);
-    P.numax = (T)h->numax;
+    P.cold = (const PushCold<T> *)h->cold;
+    P.mcc_q = h->mcc_q;
+    P.see_q = h->see_q;
+    P.ev_cap = h->ev_cap;
     P.t_null = h->t_null;
-    P.t_see = h->t_see;
     P.nr = c.nr;
     P.nz = c.nz;
     P.dr = (T)(c.lr / c.nr);
-    P.dz = (T)(c.lz / c.nz);
     P.inv_dr = (T)(c.nr / c.lr);
     P.inv_dz = (T)(c.nz / c.lz);
     P.dt = (T)c.dt;
-    P.cathode_rmax = (T)c.cathode_rmax;
-    const double qe = 1.602176634e-19;
-    P.e_of_v2 = (T)(0.5 * c.m[0] / qe);
-    P.v2_of_e = (T)(2.0 * qe / c.m[0]);
-    P.two_m_over_M = (T)(2.0 * c.m[0] / c.m[1]);
-    P.e_exc = (T)c.e_exc;
-    P.e_iz = (T)c.e_iz;
-    P.sig_ion = (T)std::sqrt(1.380649e-23 * c.t_gas / c.m[1]);
-    for (int k = 0; k < 3; ++k) P.wall_bc[k] = c.wall_bc[k];
     P.frozen_ions = c.frozen_ions;
     P.mcc_on = c.mcc_on;
     P.see_on = c.see_on;
+    P.any_reflect = (c.wall_bc[0] == PIC_REFLECT || c.wall_bc[1] == PIC_REFLECT ||
+                     c.wall_bc[2] == PIC_REFLECT) ? 1 : 0;
     P.deposit_only = deposit_only;
     P.key0 = (uint32_t)(c.seed & 0xffffffffu);
     P.key1 = (uint32_t)(c.seed >> 32);
@@ -731,6 +755,18 @@ pic_status step_one(pic_handle *h)
     launch_push_h<T>(h, 0);
     timer_end(h, 0, ev);
     timer_begin(h, ev);
+    EventParams<T> E;
+    for (int s = 0; s < 2; ++s) E.sp[s] = species_dev<T>(h->buf[s][h->cur[s]]);
+    E.cold = (const PushCold<T> *)h->cold;
+    E.sc = h->sc;
+    E.mcc_q = h->mcc_q;
+    E.see_q = h->see_q;
+    E.ev_cap = h->ev_cap;
+    E.nr = c.nr;
+    E.key0 = (uint32_t)(c.seed & 0xffffffffu);
+    E.key1 = (uint32_t)(c.seed >> 32);
+    E.run = c.run;
+    launch_events<T>(E, h->stream);
     ChildParams<T> C;
     for (int s = 0; s < 2; ++s) {
         C.sp[s] = species_dev<T>(h->buf[s][h->cur[s]]);
@@ -777,6 +813,10 @@ pic_status init_typed(pic_handle *h, const pic_species_host *init)
     HIPCHECK(h, hipMemcpy(h->nu, nut.data(), nut.size() * sizeof(T), hipMemcpyHostToDevice));
     pic_status st = setup_field(h);
     if (st != PIC_OK) return st;
+    {
+        PushCold<T> C = push_cold<T>(h);
+        HIPCHECK(h, hipMemcpy(h->cold, &C, sizeof(C), hipMemcpyHostToDevice));
+    }
     // scalars
     launch_zero(h->sc, sizeof(DevScalars), s);
     HIPCHECK(h, hipStreamSynchronize(s));

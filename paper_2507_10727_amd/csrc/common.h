@@ -42,6 +42,7 @@ struct DevScalars {
     int64_t step;
     uint32_t next_id[2];
     int32_t n_child;            // children recorded this step (all species)
+    int32_t n_mcc_q, n_see_q;   // event-queue lengths of the step
     int32_t n_child_s[2];       // children per new-particle species
     double dq_conv;             // charge into the cathode this step
     double ke[2], pz[2];
@@ -72,34 +73,57 @@ struct Child {
     T fr, fz, vr, vt, vz;
 };
 
+// Constants of the rare branches of the particle kernel (collisions,
+// emission, new particles), kept in device memory so that the kernel reads
+// them where they are used instead of holding them in scalar registers.
 template <typename T>
-struct PushParams {
-    SpeciesDev<T> sp[2];
-    int64_t cap[2];
-    const typename Vec4<T>::type *node;
-    T *q[2];
-    DevScalars *sc;
+struct PushCold {
     Child<T> *child;
     int32_t child_cap;
     const T *nu;                // [3][n_table] collision frequencies (1/s)
     int32_t n_table;
     T inv_de, numax;
-    unsigned long long t_null, t_see;
-    int32_t nr, nz;
-    T dr, dz, inv_dr, inv_dz, dt, cathode_rmax;
-    T hqm[2];                   // q dt / (2 m)
-    T qw[2];                    // q w (C per macroparticle)
-    double qw64[2];             // the same in FP64 for the cathode tally
-    double mw[2];               // m w (kg per macroparticle), diagnostics
+    unsigned long long t_see;
     T e_of_v2;                  // m_e / (2 e): eV per (m/s)^2
     T v2_of_e;                  // 2 e / m_e
     T two_m_over_M;             // elastic energy-loss factor 2 m_e / M
     T e_exc, e_iz, sig_ion;     // thresholds (eV); ion thermal speed sqrt(kT/M)
+    double qw64[2];             // q w in FP64 for the cathode tally
     int32_t wall_bc[3];
+    T cathode_rmax;
+};
+
+template <typename T>
+struct PushParams {
+    SpeciesDev<T> sp[2];
+    const typename Vec4<T>::type *node;
+    T *q[2];
+    DevScalars *sc;
+    const PushCold<T> *cold;
+    int2 *mcc_q, *see_q;        // event queues (slot, aux)
+    int32_t ev_cap;
+    unsigned long long t_null;
+    int32_t nr, nz;
+    T dr, inv_dr, inv_dz, dt;
+    T hqm[2];                   // q dt / (2 m)
+    T qw[2];                    // q w (C per macroparticle)
+    float mw[2];                // m w (kg per macroparticle), diagnostics
     int32_t frozen_ions, mcc_on, see_on;
+    int32_t any_reflect;        // some wall reflects (test configurations)
     int32_t deposit_only;       // 1: only deposit the current positions
     uint32_t key0, key1, run;
     int32_t nblk_e;             // blocks [0, nblk_e) push electrons, the rest ions
+};
+
+template <typename T>
+struct EventParams {
+    SpeciesDev<T> sp[2];
+    const PushCold<T> *cold;
+    DevScalars *sc;
+    const int2 *mcc_q, *see_q;
+    int32_t ev_cap;
+    int32_t nr;
+    uint32_t key0, key1, run;
 };
 
 template <typename T>
@@ -141,8 +165,9 @@ enum : uint32_t { PURPOSE_MCC = 0, PURPOSE_IZ = 1, PURPOSE_ION = 2, PURPOSE_SEE 
 
 template <typename T>
 __device__ __forceinline__ T u24(uint32_t u) { return (T)(u >> 8) * (T)(1.0 / 16777216.0); }
+// Uniform on (0,1) for log(): midpoint of a 23-bit cell, exact in binary32.
 template <typename T>
-__device__ __forceinline__ T u24_open(uint32_t u) { return ((T)(u >> 8) + (T)0.5) * (T)(1.0 / 16777216.0); }
+__device__ __forceinline__ T u_open(uint32_t u) { return ((T)(u >> 9) + (T)0.5) * (T)(1.0 / 8388608.0); }
 
 __device__ __forceinline__ void sincos_2pi(float u, float *s, float *c) { sincospif(2.0f * u, s, c); }
 __device__ __forceinline__ void sincos_2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
@@ -178,6 +203,8 @@ __device__ __forceinline__ void atomic_add_dev(double *p, double v) { unsafeAtom
 // particles.hip
 template <typename T>
 void launch_push(const PushParams<T> &p, int scheme, int nblocks, hipStream_t s);
+template <typename T>
+void launch_events(const EventParams<T> &p, hipStream_t s);
 template <typename T>
 void launch_children(const ChildParams<T> &p, hipStream_t s);
 void launch_finalize_step(DevScalars *sc, const int64_t cap[2], hipStream_t s);

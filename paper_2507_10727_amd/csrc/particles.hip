@@ -41,7 +41,9 @@ template <typename T>
 __device__ __forceinline__ void iso_direction(uint32_t ua, uint32_t ub, T &d0, T &d1, T &d2)
 {
     const T c = (T)1 - (T)2 * u24<T>(ua);
-    const T s = sqrt(fmax((T)0, (T)1 - c * c));
+    // sin(chi) from (1 - c)(1 + c): both factors are exact for c = 1 - 2U,
+    // where 1 - c^2 would cancel near c = +-1
+    const T s = sqrt(fmax((T)0, ((T)1 - c) * ((T)1 + c)));
     T sn, cs;
     sincos_2pi(u24<T>(ub), &sn, &cs);
     d0 = s * cs;
@@ -50,14 +52,15 @@ __device__ __forceinline__ void iso_direction(uint32_t ua, uint32_t ub, T &d0, T
 }
 
 template <typename T>
-__device__ __forceinline__ void record_child(const PushParams<T> &P, int parent_species,
-                                             uint32_t parent_id, int kind, int species, int i,
-                                             int j, T fr, T fz, T vr, T vt, T vz)
+__device__ __forceinline__ void record_child(const PushCold<T> *C, DevScalars *sc,
+                                             int parent_species, uint32_t parent_id, int kind,
+                                             int species, int i, int j, T fr, T fz, T vr, T vt,
+                                             T vz)
 {
-    const int slot = atomicAdd(&P.sc->n_child, 1);
-    atomicAdd(&P.sc->n_child_s[species], 1);
-    if (slot >= P.child_cap) {
-        atomicOr(&P.sc->flags, FLAG_CHILD_OVERFLOW);
+    const int slot = atomicAdd(&sc->n_child, 1);
+    atomicAdd(&sc->n_child_s[species], 1);
+    if (slot >= C->child_cap) {
+        atomicOr(&sc->flags, FLAG_CHILD_OVERFLOW);
         return;
     }
     Child<T> c;
@@ -70,7 +73,7 @@ __device__ __forceinline__ void record_child(const PushParams<T> &P, int parent_
     c.vr = vr;
     c.vt = vt;
     c.vz = vz;
-    P.child[slot] = c;
+    C->child[slot] = c;
 }
 
 template <typename T>
@@ -83,6 +86,12 @@ template <typename T> __device__ __forceinline__ T near_one();
 template <> __device__ __forceinline__ float near_one<float>() { return 0x1.fffffep-1f; }
 template <> __device__ __forceinline__ double near_one<double>() { return 0x1.fffffffffffffp-1; }
 
+// Reciprocal: the hardware approximation (about 1 ulp) in FP32, exact
+// division in FP64 (the FP64 state is compared with the oracle at 1e-12).
+template <typename T> __device__ __forceinline__ T rcp(T x);
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+
 struct Tally {
     double ke = 0.0, pz = 0.0, dq = 0.0;
     unsigned int abs1 = 0, abs2 = 0, abs3 = 0, abs4 = 0;
@@ -91,14 +100,15 @@ struct Tally {
 
 // Gather, Boris, drift and walls for one particle.  Updates the state in
 // place and returns 0 if it stays inside, else the wall code (1 cathode,
-// 2 Neumann block, 3 outer r, 4 anode).
+// 2 Neumann block, 3 outer r, 4 anode).  ke_dot / pz_v receive
+// v^{n-1/2}.v^{n+1/2} and v_z^{n+1/2} for the diagnostics.
 template <typename T, int SCHEME>
-__device__ __forceinline__ int advance(const PushParams<T> &P, T hqm, double mw,
+__device__ __forceinline__ int advance(const PushParams<T> &P, T hqm,
                                        const typename Vec4<T>::type &a00,
                                        const typename Vec4<T>::type &a10,
                                        const typename Vec4<T>::type &a01,
                                        const typename Vec4<T>::type &a11, int &i, int &j, T &fr,
-                                       T &fz, T &vr, T &vt, T &vz, Tally &t, T &r1_out)
+                                       T &fz, T &vr, T &vt, T &vz, T &ke_dot, T &pz_v)
 {
     const int nr = P.nr, nz = P.nz;
     const T gr = (T)1 - fr, gz = (T)1 - fz;
@@ -116,7 +126,7 @@ __device__ __forceinline__ int advance(const PushParams<T> &P, T hqm, double mw,
     // Boris: half kick, rotation about t = (q dt / 2m) B, half kick
     const T mx = vr + hqm * er, my = vt, mz = vz + hqm * ez;
     const T tx = hqm * br, tz = hqm * bz;
-    const T f2 = (T)2 / ((T)1 + tx * tx + tz * tz);
+    const T f2 = (T)2 * rcp<T>((T)1 + tx * tx + tz * tz);
     const T sx = f2 * tx, sz = f2 * tz;
     const T px = mx + my * tz;
     const T py = my + (mz * tx - mx * tz);
@@ -125,8 +135,8 @@ __device__ __forceinline__ int advance(const PushParams<T> &P, T hqm, double mw,
     const T qy = my + (pzz * sx - px * sz);
     const T qz = mz - py * sx;
     const T nx = qx + hqm * er, ny = qy, nzv = qz + hqm * ez;
-    t.ke += 0.5 * mw * ((double)vr * nx + (double)vt * ny + (double)vz * nzv);
-    t.pz += mw * (double)nzv;
+    ke_dot = vr * nx + vt * ny + vz * nzv;
+    pz_v = nzv;
     // drift in (x, y, z) = (r, 0, z), rotate into the new meridional plane
     const T r = ((T)i + fr) * P.dr;
     const T dx = nx * P.dt, dy = ny * P.dt;
@@ -134,13 +144,13 @@ __device__ __forceinline__ int advance(const PushParams<T> &P, T hqm, double mw,
     const T r1 = sqrt(x1 * x1 + dy * dy);
     T vr1 = nx, vt1 = ny, vz1 = nzv;
     if (r1 > (T)0) {
-        const T inv = (T)1 / r1;
+        const T inv = rcp<T>(r1);
         const T c = x1 * inv, sn = dy * inv;
         vr1 = c * nx + sn * ny;
         vt1 = c * ny - sn * nx;
     }
     const T den = r + r1;
-    const T drr = (den > (T)0) ? ((T)2 * r * dx + dx * dx + dy * dy) / den : (T)0;
+    const T drr = (den > (T)0) ? ((T)2 * r * dx + dx * dx + dy * dy) * rcp<T>(den) : (T)0;
     const T xr = fr + drr * P.inv_dr;
     const T xz = fz + nzv * P.dt * P.inv_dz;
     const T flr = floor(xr), flz = floor(xz);
@@ -149,40 +159,47 @@ __device__ __forceinline__ int advance(const PushParams<T> &P, T hqm, double mw,
     if (fr1 >= (T)1) { fr1 = (T)0; ++i1; }
     if (fz1 >= (T)1) { fz1 = (T)0; ++j1; }
     int fate = 0;
-    if (j1 < 0) {
-        if (P.wall_bc[0] == PIC_REFLECT) {
-            const T zg = -((T)j1 + fz1);
-            const T fl = floor(zg);
-            j1 = (int)fl;
-            fz1 = zg - fl;
-            if (fz1 >= (T)1) { fz1 = (T)0; ++j1; }
-            vz1 = -vz1;
-        } else {
-            fate = (r1 < P.cathode_rmax) ? 1 : 2;
+    if (!P.any_reflect) {
+        if (j1 < 0) fate = (r1 < P.cold->cathode_rmax) ? 1 : 2;
+        else if (i1 >= nr) fate = 3;
+        else if (j1 >= nz) fate = 4;
+    } else {
+        const int *wbc = P.cold->wall_bc;
+        if (j1 < 0) {
+            if (wbc[0] == PIC_REFLECT) {
+                const T zg = -((T)j1 + fz1);
+                const T fl = floor(zg);
+                j1 = (int)fl;
+                fz1 = zg - fl;
+                if (fz1 >= (T)1) { fz1 = (T)0; ++j1; }
+                vz1 = -vz1;
+            } else {
+                fate = (r1 < P.cold->cathode_rmax) ? 1 : 2;
+            }
         }
-    }
-    if (fate == 0 && i1 >= nr) {
-        if (P.wall_bc[2] == PIC_REFLECT) {
-            const T rg = (T)(2 * nr) - ((T)i1 + fr1);
-            const T fl = floor(rg);
-            i1 = (int)fl;
-            fr1 = rg - fl;
-            if (i1 >= nr) { i1 = nr - 1; fr1 = near_one<T>(); }
-            vr1 = -vr1;
-        } else {
-            fate = 3;
+        if (fate == 0 && i1 >= nr) {
+            if (wbc[2] == PIC_REFLECT) {
+                const T rg = (T)(2 * nr) - ((T)i1 + fr1);
+                const T fl = floor(rg);
+                i1 = (int)fl;
+                fr1 = rg - fl;
+                if (i1 >= nr) { i1 = nr - 1; fr1 = near_one<T>(); }
+                vr1 = -vr1;
+            } else {
+                fate = 3;
+            }
         }
-    }
-    if (fate == 0 && j1 >= nz) {
-        if (P.wall_bc[1] == PIC_REFLECT) {
-            const T zg = (T)(2 * nz) - ((T)j1 + fz1);
-            const T fl = floor(zg);
-            j1 = (int)fl;
-            fz1 = zg - fl;
-            if (j1 >= nz) { j1 = nz - 1; fz1 = near_one<T>(); }
-            vz1 = -vz1;
-        } else {
-            fate = 4;
+        if (fate == 0 && j1 >= nz) {
+            if (wbc[1] == PIC_REFLECT) {
+                const T zg = (T)(2 * nz) - ((T)j1 + fz1);
+                const T fl = floor(zg);
+                j1 = (int)fl;
+                fz1 = zg - fl;
+                if (j1 >= nz) { j1 = nz - 1; fz1 = near_one<T>(); }
+                vz1 = -vz1;
+            } else {
+                fate = 4;
+            }
         }
     }
     if (fate == 0) {
@@ -203,72 +220,76 @@ __device__ __forceinline__ int advance(const PushParams<T> &P, T hqm, double mw,
     vr = vr1;
     vt = vt1;
     vz = vz1;
-    r1_out = r1;
     return fate;
 }
 
-// Null-collision MCC of one electron (Section 3, processes (1a)-(1c)).
+// Ionization products of one collision.  Returns the scattered electron's energy; records the ejected electron and
+// the new ion as children.
 template <typename T>
-__device__ __forceinline__ void collide(const PushParams<T> &P, uint32_t id, uint32_t step, int i,
-                                        int j, T fr, T fz, T &vr, T &vt, T &vz, Tally &t)
+__device__ __forceinline__ T ionize(const PushCold<T> *C, DevScalars *sc, uint32_t id,
+                                 uint32_t word1, uint32_t step, uint32_t key0, uint32_t key1,
+                                 int i, int j, T fr, T fz, T e)
 {
-    const uint4 u = philox4x32_10(make_uint4(id, (P.run << 8) | PURPOSE_MCC, step, 0u), P.key0,
-                                  P.key1);
-    if ((unsigned long long)u.x >= P.t_null) return;
-    ++t.cand;
-    const int nt = P.n_table;
+    const T erem = e - C->e_iz;
+    const uint4 ua = philox4x32_10(make_uint4(id, word1 | PURPOSE_IZ, step, 0u), key0, key1);
+    const uint4 ub = philox4x32_10(make_uint4(id, word1 | PURPOSE_ION, step, 0u), key0, key1);
+    const T eej = u24<T>(ua.x) * erem;
+    T e0, e1, e2;
+    iso_direction(ua.y, ua.z, e0, e1, e2);
+    const T vej = sqrt(C->v2_of_e * eej);
+    record_child(C, sc, 0, id, 0, 0, i, j, fr, fz, vej * e0, vej * e1, vej * e2);
+    const T a0 = sqrt((T)-2 * log(u_open<T>(ub.x)));
+    const T a1 = sqrt((T)-2 * log(u_open<T>(ub.z)));
+    T s0, c0, s1, cb;
+    sincos_2pi(u24<T>(ub.y), &s0, &c0);
+    sincos_2pi(u24<T>(ub.w), &s1, &cb);
+    const T sg = C->sig_ion;
+    record_child(C, sc, 0, id, 1, 1, i, j, fr, fz, sg * a0 * c0, sg * a0 * s0, sg * a1 * cb);
+    return ((T)1 - u24<T>(ua.x)) * erem;   // = erem - eej, without cancellation
+}
+
+// The selected collision of one candidate electron: energy, process, new
+// velocity, ionization products.
+template <typename T>
+__device__ __forceinline__ void scatter(const PushCold<T> *C, DevScalars *sc, uint4 u, uint32_t id,
+                                     uint32_t word1, uint32_t step, uint32_t key0, uint32_t key1,
+                                     int i, int j, T fr, T fz, T *v, unsigned int *counts)
+{
+    T vr = v[0], vt = v[1], vz = v[2];
+    const int nt = C->n_table;
     const T v2 = vr * vr + vt * vt + vz * vz;
-    const T e = P.e_of_v2 * v2;
-    const T x = e * P.inv_de;
+    const T e = C->e_of_v2 * v2;
+    const T x = e * C->inv_de;
     int kk;
     T f;
     if (x >= (T)(nt - 1)) { kk = nt - 2; f = (T)1; }
     else { const T fl = floor(x); kk = (int)fl; f = x - fl; }
-    const T c1 = interp_row(P.nu, kk, f);
-    const T c2 = c1 + interp_row(P.nu + nt, kk, f);
-    const T c3 = c2 + interp_row(P.nu + 2 * nt, kk, f);
-    const T rsel = u24<T>(u.y) * P.numax;
+    const T c1 = interp_row(C->nu, kk, f);
+    const T c2 = c1 + interp_row(C->nu + nt, kk, f);
+    const T c3 = c2 + interp_row(C->nu + 2 * nt, kk, f);
+    const T rsel = u24<T>(u.y) * C->numax;
     int proc = -1;
     if (rsel < c1) proc = 0;
-    else if (rsel < c2) proc = (e >= P.e_exc) ? 1 : -1;
-    else if (rsel < c3) proc = (e >= P.e_iz) ? 2 : -1;
+    else if (rsel < c2) proc = (e >= C->e_exc) ? 1 : -1;
+    else if (rsel < c3) proc = (e >= C->e_iz) ? 2 : -1;
     if (proc < 0) return;
+    counts[proc]++;
     T d0, d1, d2;
     iso_direction(u.z, u.w, d0, d1, d2);
     T enew;
     if (proc == 0) {
-        ++t.el;
         const T vm = sqrt(v2);
         const T cth = (vr * d0 + vt * d1 + vz * d2) / vm;
-        enew = e * ((T)1 - P.two_m_over_M * ((T)1 - cth));
+        enew = e * ((T)1 - C->two_m_over_M * ((T)1 - cth));
     } else if (proc == 1) {
-        ++t.ex;
-        enew = e - P.e_exc;
+        enew = e - C->e_exc;
     } else {
-        ++t.iz;
-        const T erem = e - P.e_iz;
-        const uint4 ua = philox4x32_10(make_uint4(id, (P.run << 8) | PURPOSE_IZ, step, 0u),
-                                       P.key0, P.key1);
-        const uint4 ub = philox4x32_10(make_uint4(id, (P.run << 8) | PURPOSE_ION, step, 0u),
-                                       P.key0, P.key1);
-        const T eej = u24<T>(ua.x) * erem;
-        enew = erem - eej;
-        T e0, e1, e2;
-        iso_direction(ua.y, ua.z, e0, e1, e2);
-        const T vej = sqrt(P.v2_of_e * eej);
-        record_child(P, 0, id, 0, 0, i, j, fr, fz, vej * e0, vej * e1, vej * e2);
-        const T a0 = sqrt((T)-2 * log(u24_open<T>(ub.x)));
-        const T a1 = sqrt((T)-2 * log(u24_open<T>(ub.z)));
-        T s0, c0, s1, cb;
-        sincos_2pi(u24<T>(ub.y), &s0, &c0);
-        sincos_2pi(u24<T>(ub.w), &s1, &cb);
-        record_child(P, 0, id, 1, 1, i, j, fr, fz, P.sig_ion * a0 * c0, P.sig_ion * a0 * s0,
-                     P.sig_ion * a1 * cb);
+        enew = ionize(C, sc, id, word1, step, key0, key1, i, j, fr, fz, e);
     }
-    const T vn = sqrt(P.v2_of_e * enew);
-    vr = vn * d0;
-    vt = vn * d1;
-    vz = vn * d2;
+    const T vn = sqrt(C->v2_of_e * enew);
+    v[0] = vn * d0;
+    v[1] = vn * d1;
+    v[2] = vn * d2;
 }
 
 // Add one run's summed tent weights to its cell's four nodes.
@@ -294,6 +315,14 @@ __device__ __forceinline__ void deposit_global(T *q, int ld, int key, T qw, T a0
     atomic_add_dev(p + 1, qw * a10);
     atomic_add_dev(p + ld, qw * a01);
     atomic_add_dev(p + ld + 1, qw * a11);
+}
+
+// Append (slot, aux) to an event queue.  Entries past the capacity are
+// dropped and flagged.
+__device__ __forceinline__ void enqueue(int2 *q, int *count, int cap, int slot, int aux)
+{
+    const int e = atomicAdd(count, 1);
+    if (e < cap) q[e] = make_int2(slot, aux);
 }
 
 template <typename T, int SCHEME>
@@ -323,10 +352,10 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
     const uint32_t step = (uint32_t)P.sc->step;
     const int ldn = P.nr + 1;
     const T hqm = P.hqm[s], qw = P.qw[s];
-    const double mw = P.mw[s];
     const bool frozen = P.deposit_only || ((s == 1) && P.frozen_ions);
     const bool collide_on = (s == 0) && P.mcc_on && !P.deposit_only;
     const bool emit = (s == 1) && P.see_on;
+    const uint32_t word1 = (P.run << 8) | ((uint32_t)s << 4);
     T *__restrict__ Q = P.q[s];
     Tally t;
 
@@ -365,6 +394,7 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
             for (int k = 0; k < 4; ++k) fr[k] = fz[k] = vr[k] = vt[k] = vz[k] = (T)0;
         }
         int ok[4];   // cell key after the push, -1 if none
+        T ke_c = (T)0, pz_c = (T)0;
         if (!frozen) {
             int prev = -2;
             T4 a00, a10, a01, a11;
@@ -382,29 +412,18 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
                     a11 = nb[ldn + 1];
                     prev = key;
                 }
-                T r1;
-                const int fate = advance<T, SCHEME>(P, hqm, mw, a00, a10, a01, a11, i, j, fr[k],
-                                                    fz[k], vr[k], vt[k], vz[k], t, r1);
+                T kd, pv;
+                const int fate = advance<T, SCHEME>(P, hqm, a00, a10, a01, a11, i, j, fr[k],
+                                                    fz[k], vr[k], vt[k], vz[k], kd, pv);
+                ke_c += kd;
+                pz_c += pv;
                 if (fate) {
                     kk[k] = -1;
                     if (fate == 1) {
                         ++t.abs1;
-                        t.dq += P.qw64[s];
-                        if (emit) {
-                            const uint32_t pid = ID[p0 + k];
-                            const uint4 u = philox4x32_10(
-                                make_uint4(pid, (P.run << 8) | (1u << 4) | PURPOSE_SEE, step, 0u),
-                                P.key0, P.key1);
-                            if ((unsigned long long)u.x < P.t_see) {
-                                ++t.see;
-                                t.dq -= P.qw64[0];
-                                int ie = i;
-                                T fe = fr[k];
-                                if (ie > P.nr - 1) { ie = P.nr - 1; fe = near_one<T>(); }
-                                if (ie < 0) { ie = 0; fe = (T)0; }
-                                record_child(P, 1, pid, 0, 0, ie, 0, fe, (T)0, (T)0, (T)0, (T)0);
-                            }
-                        }
+                        t.dq += P.cold->qw64[s];
+                        // emission is decided in the event kernel
+                        if (emit) enqueue(P.see_q, &P.sc->n_see_q, P.ev_cap, (int)(p0 + k), i);
                     } else if (fate == 2) {
                         ++t.abs2;
                     } else if (fate == 3) {
@@ -414,7 +433,14 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
                     }
                     continue;
                 }
-                if (collide_on) collide(P, id[k], step, i, j, fr[k], fz[k], vr[k], vt[k], vz[k], t);
+                if (collide_on) {
+                    // null-collision candidate test; the collision itself is
+                    // done in the event kernel for the few candidates
+                    const uint4 u = philox4x32_10(make_uint4(id[k], word1 | PURPOSE_MCC, step, 0u),
+                                                  P.key0, P.key1);
+                    if ((unsigned long long)u.x < P.t_null)
+                        enqueue(P.mcc_q, &P.sc->n_mcc_q, P.ev_cap, (int)(p0 + k), 0);
+                }
                 kk[k] = ok[k] = (j << 16) | i;
             }
             if (any) {
@@ -436,12 +462,14 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
             for (int k = 0; k < 4; ++k) {
                 ok[k] = kk[k];
                 if (kk[k] >= 0 && !P.deposit_only) {
-                    t.ke += 0.5 * mw * ((double)vr[k] * vr[k] + (double)vt[k] * vt[k] +
-                                        (double)vz[k] * vz[k]);
-                    t.pz += mw * (double)vz[k];
+                    ke_c += vr[k] * vr[k] + vt[k] * vt[k] + vz[k] * vz[k];
+                    pz_c += vz[k];
                 }
             }
         }
+        // per-chunk diagnostics in FP32, summed over chunks in FP64
+        t.ke += (double)ke_c;
+        t.pz += (double)pz_c;
 
         // ---- deposit: block bounding box of the chunk's cells
         int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
@@ -514,9 +542,9 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
     }
 
     // ---- block totals of the diagnostics, one atomic per quantity
-    double dv[3] = {wave_sum(t.ke), wave_sum(t.pz), wave_sum(t.dq)};
-    unsigned long long c[10] = {t.abs1, t.abs2, t.abs3, t.abs4, t.cand,
-                                t.el,   t.ex,   t.iz,   t.see,  t.fb};
+    const double mw = (double)P.mw[s];
+    double dv[3] = {wave_sum(0.5 * mw * t.ke), wave_sum(mw * t.pz), wave_sum(t.dq)};
+    unsigned long long c[10] = {t.abs1, t.abs2, t.abs3, t.abs4, 0, 0, 0, 0, 0, t.fb};
 #pragma unroll
     for (int q = 0; q < 10; ++q) c[q] = wave_sum_u64(c[q]);
     if (lane == 0) {
@@ -545,6 +573,68 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
         if (tt[8]) atomicAdd(&sc->n_see, tt[8]);
         if (tt[9]) atomicAdd(&sc->deposit_fallback, tt[9]);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Events of the step: collisions of the null-collision candidates (queue of
+// electron slots) and secondary emission of the ions absorbed on the cathode
+// (queue of ion slots with their radial cell).  Each outcome depends only on
+// the particle's id, the step and its state after the push, so processing
+// order does not matter.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_events(EventParams<T> P)
+{
+    const PushCold<T> *C = P.cold;
+    DevScalars *sc = P.sc;
+    const uint32_t step = (uint32_t)sc->step;
+    const int nm = min(sc->n_mcc_q, P.ev_cap);
+    const int ns = min(sc->n_see_q, P.ev_cap);
+    unsigned int coll[3] = {0u, 0u, 0u}, see = 0u;
+    double dq = 0.0;
+    const uint32_t w_e = P.run << 8, w_i = (P.run << 8) | (1u << 4);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nm + ns; e += gridDim.x * blockDim.x) {
+        if (e < nm) {
+            const int p = P.mcc_q[e].x;
+            const SpeciesDev<T> S = P.sp[0];
+            const int key = S.key[p];
+            const uint32_t id = S.id[p];
+            const uint4 u = philox4x32_10(make_uint4(id, w_e | PURPOSE_MCC, step, 0u), P.key0, P.key1);
+            T v[3] = {S.vr[p], S.vt[p], S.vz[p]};
+            scatter(C, sc, u, id, w_e, step, P.key0, P.key1, key & 0xffff, key >> 16, S.fr[p],
+                    S.fz[p], v, coll);
+            S.vr[p] = v[0];
+            S.vt[p] = v[1];
+            S.vz[p] = v[2];
+        } else {
+            const int2 q = P.see_q[e - nm];
+            const uint32_t pid = P.sp[1].id[q.x];
+            const uint4 u = philox4x32_10(make_uint4(pid, w_i | PURPOSE_SEE, step, 0u), P.key0, P.key1);
+            if ((unsigned long long)u.x < C->t_see) {
+                ++see;
+                dq -= C->qw64[0];
+                int ie = q.y;
+                T fe = P.sp[1].fr[q.x];
+                if (ie > P.nr - 1) { ie = P.nr - 1; fe = near_one<T>(); }
+                if (ie < 0) { ie = 0; fe = (T)0; }
+                record_child(C, sc, 1, pid, 0, 0, ie, 0, fe, (T)0, (T)0, (T)0, (T)0);
+            }
+        }
+    }
+    for (int q = 0; q < 3; ++q)
+        if (coll[q]) atomicAdd(&sc->n_coll[q], (unsigned long long)coll[q]);
+    if (see) atomicAdd(&sc->n_see, (unsigned long long)see);
+    if (dq != 0.0) atomic_add_dev(&sc->dq_conv, dq);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->n_cand = (unsigned long long)nm;
+        if (sc->n_mcc_q > P.ev_cap || sc->n_see_q > P.ev_cap) atomicOr(&sc->flags, FLAG_CHILD_OVERFLOW);
+    }
+}
+
+template <typename T>
+void launch_events(const EventParams<T> &p, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_events<T>), dim3(256), dim3(256), 0, s, p);
 }
 
 template <typename T>
@@ -638,6 +728,8 @@ __global__ void k_finalize_step(DevScalars *sc, int64_t cap0, int64_t cap1)
     sc->n_child = 0;
     sc->n_child_s[0] = 0;
     sc->n_child_s[1] = 0;
+    sc->n_mcc_q = 0;
+    sc->n_see_q = 0;
     sc->step += 1;
 }
 
@@ -721,6 +813,8 @@ void launch_load(SpeciesDev<T> sp, int64_t offset, const double *r, const double
 
 template void launch_push<float>(const PushParams<float> &, int, int, hipStream_t);
 template void launch_push<double>(const PushParams<double> &, int, int, hipStream_t);
+template void launch_events<float>(const EventParams<float> &, hipStream_t);
+template void launch_events<double>(const EventParams<double> &, hipStream_t);
 template void launch_children<float>(const ChildParams<float> &, hipStream_t);
 template void launch_children<double>(const ChildParams<double> &, hipStream_t);
 template void launch_load<float>(SpeciesDev<float>, int64_t, const double *, const double *,

@@ -1,0 +1,115 @@
+"""Collision and emission outcomes of the HIP library against the oracle.
+
+A mono-energetic electron beam with a large null-collision probability
+(about half the electrons are candidates) and an ion sheet hitting the
+cathode, both in FP64 with fixed fields: every particle -- including the
+new electrons and ions, whose ids follow the (parent species, parent id,
+kind) rule -- must match the oracle by id.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import compare_particles, gpu_sim, say
+from oracle import oracle as O
+from oracle_helpers import empty, species
+from paper_2507_10727_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+
+
+def _beam(n, e0, seed):
+    rng = np.random.default_rng(seed)
+    v = math.sqrt(2 * QE * e0 / ME)
+    d = rng.normal(size=(3, n))
+    d /= np.linalg.norm(d, axis=0)
+    r = 0.004 + 0.012 * rng.random(n)
+    z = 0.004 + 0.012 * rng.random(n)
+    return species(r, z, v * d[0], v * d[1], v * d[2])
+
+
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+def test_collisions_match_oracle(precision):
+    n = 20000
+    p = W.Problem(name="beam", nr=16, nz=16, lr=0.02, lz=0.02, dt=2e-9, precision=precision,
+                  p_gas=30e-3 * W.TORR, field_solve=0, see_on=0, frozen_ions=1, v_fixed=0.0,
+                  weight=1.0, wall_bc=(W.REFLECT, W.REFLECT, W.REFLECT), poisson_rtol=1e-13)
+    nn = p.nodes
+    b = (np.zeros(nn), np.zeros(nn))
+    sig = W.cross_sections()
+    beam = _beam(n, 40.0, 21)
+    cap = (3 * n, 2 * n)
+    say("case collisions", precision)
+    sim = gpu_sim(p, b[0], b[1], sig, [beam.copy(), empty()], capacity=cap)
+    if precision == W.F32:
+        # the oracle starts from the GPU's FP32 state
+        g0 = sim.particles(0)
+        start = W.SpeciesArrays(g0["r"], g0["z"], g0["vr"], g0["vt"], g0["vz"], g0["id"])
+    else:
+        start = beam.copy()
+    o = O.Oracle(p, b[0], b[1], sig, [start, empty()], capacity=cap)
+    o.init()
+    o.phi[:] = 0.0
+    sim.set_phi(np.zeros(nn))
+    for step in range(3):
+        if precision == W.F32 and step > 0:
+            # FP32 is compared one step at a time from the GPU's own state
+            st = sim.get_state()
+            parts = []
+            for s_ in range(2):
+                g = sim.particles(s_)
+                parts.append(W.SpeciesArrays(g["r"], g["z"], g["vr"], g["vt"], g["vz"], g["id"]))
+            o = O.Oracle(p, b[0], b[1], sig, parts, capacity=cap)
+            o.init()
+            o.phi[:] = 0.0
+            o.state.step = st["step"]
+            o.state.next_id[0], o.state.next_id[1] = st["next_id"]
+        d_o = o.step()
+        sim.step(1)
+        d_g = sim.diag()
+        say("step", step, "oracle", d_o["n_cand"], d_o["n_coll"], "gpu", d_g["n_cand"], d_g["n_coll"])
+        tol = 1e-12 if precision == W.F64 else 2e-5
+        slack = 0 if precision == W.F64 else 3
+        assert abs(d_g["n_cand"] - d_o["n_cand"]) <= slack
+        for j in range(3):
+            assert abs(d_g["n_coll"][j] - d_o["n_coll"][j]) <= slack
+        for s in range(2):
+            ep, ev, only = compare_particles(p, sim.particles(s), o.particles(s), s, tol,
+                                             max_mismatch=2 * slack)
+            say("  species", s, "pos", ep, "vel", ev, "only-one-side", only)
+            assert ep < tol and ev < tol
+    assert d_o["n_coll"][2] > 0 and o.count(1) > 0
+
+
+def test_emission_matches_oracle():
+    n = 20000
+    p = W.Problem(name="see", nr=16, nz=16, lr=0.02, lz=0.02, gamma_i=0.1, see_on=1,
+                  mcc_on=0, field_solve=0, v_fixed=0.0, weight=1.0, poisson_rtol=1e-13)
+    nn = p.nodes
+    rng = np.random.default_rng(14)
+    r = 0.019 * rng.random(n)
+    ions = species(r, 1e-9 + 3e-7 * rng.random(n), 0.0, 0.0, -2e4)  # hits spread over 3 steps
+    sig = W.cross_sections()
+    cap = (n, n)
+    say("case emission")
+    sim = gpu_sim(p, np.zeros(nn), np.zeros(nn), sig, [empty(), ions.copy()], capacity=cap)
+    o = O.Oracle(p, np.zeros(nn), np.zeros(nn), sig, [empty(), ions.copy()], capacity=cap)
+    o.init()
+    o.phi[:] = 0.0
+    sim.set_phi(np.zeros(nn))
+    for step in range(3):
+        d_o = o.step()
+        sim.step(1)
+        d_g = sim.diag()
+        say("step", step, d_o["n_see"], d_g["n_see"], d_o["dq_conv"], d_g["dq_conv"])
+        assert d_g["n_see"] == d_o["n_see"]
+        assert d_g["n_abs"][1][1] == d_o["n_abs"][1][1]
+        assert d_g["dq_conv"] == pytest.approx(d_o["dq_conv"], rel=1e-12, abs=1e-25)
+        for s in range(2):
+            ep, ev, only = compare_particles(p, sim.particles(s), o.particles(s), s, 1e-12)
+            assert ep < 1e-12 and ev < 1e-12 and only == 0
+    assert o.count(0) > 1000
