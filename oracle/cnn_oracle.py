@@ -31,12 +31,20 @@ network and its training are this project's reading, not the paper's:
   pool = 2x2 average over the nodes present (a last odd row or column
   averages fewer nodes), coarse size ceil(n / 2); up = nearest neighbour,
   fine (y, x) <- coarse (y // 2, x // 2).
-* Preconditioner.  z = out_scale * rms(r) * out on unknown nodes, 0 on
-  Dirichlet nodes.
-* Loss of one pair (b, phi) with A phi = b: with rho = rms(b) over the
-  unknown nodes, rhat = b / rho, phihat = phi / rho, z = out_scale * out,
-  e = z - phihat on unknown nodes, the relative A-norm error
-  L = (1/2) e.A e / (phihat.A phihat); a batch averages L.
+* Smoothing.  A red-black Gauss-Seidel half sweep of colour c (red: i + j
+  even) sets x_p <- x_p + (b - A x)_p / A_pp on the unknown nodes of that
+  colour (nodes of one colour do not couple, so the order within a colour
+  does not matter).  pre(b): red then black from x = 0; post(x, b): black
+  then red.
+* Preconditioner.  x1 = pre(r), r1 = r - A x1, the network correction
+  c = out_scale * rms(r1) * net(r1 / rms(r1)) on unknown nodes (0 on
+  Dirichlet nodes), z = post(x1 + c, r).  With a zero network this is the
+  symmetric Gauss-Seidel preconditioner; the network supplies the smooth
+  part of the error that the sweeps leave.
+* Loss of one pair (b, phi) with A phi = b: x1 = pre(b), r1 = b - A x1,
+  e1 = phi - x1 (so A e1 = r1), rho = rms(r1) over the unknown nodes,
+  input r1 / rho, target t = e1 / rho, e = out_scale * out - t on unknown
+  nodes, L = (1/2) e.A e / (t.A t); a batch averages L.
 * Adam with the usual bias corrections.
 * Flexible conjugate gradients: beta = z_k.(r_k - r_{k-1}) / z_{k-1}.r_{k-1}
   (the Polak-Ribiere form), which stays convergent with a preconditioner
@@ -242,6 +250,35 @@ def backward(theta, a, g_out):
 
 # ---- preconditioner and loss -------------------------------------------------
 
+def diagonal(apply_a, kind, nr, nz):
+    """A_pp of every unknown node: A applied to the indicator of one colour
+    equals the diagonal on that colour (same-colour nodes do not couple)."""
+    red, black = colours(kind, nr, nz)
+    return np.where(red, apply_a(red * 1.0), 0.0) + np.where(black, apply_a(black * 1.0), 0.0)
+
+
+def colours(kind, nr, nz):
+    j, i = np.divmod(np.arange((nr + 1) * (nz + 1)), nr + 1)
+    unk = kind == 0
+    return unk & ((i + j) % 2 == 0), unk & ((i + j) % 2 == 1)
+
+
+def half_sweep(x, b, colour, apply_a, diag):
+    return np.where(colour, x + (b - apply_a(x)) / np.where(colour, diag, 1.0), x)
+
+
+def pre_smooth(b, kind, nr, nz, apply_a, diag):
+    red, black = colours(kind, nr, nz)
+    x = half_sweep(np.zeros_like(b), b, red, apply_a, diag)
+    return half_sweep(x, b, black, apply_a, diag)
+
+
+def post_smooth(x, b, kind, nr, nz, apply_a, diag):
+    red, black = colours(kind, nr, nz)
+    x = half_sweep(x, b, black, apply_a, diag)
+    return half_sweep(x, b, red, apply_a, diag)
+
+
 def features(r, kind, nr, nz):
     """Network input [2][H][W] of one node vector r, and rms(r) over unknowns."""
     unk = kind == 0
@@ -253,25 +290,38 @@ def features(r, kind, nr, nz):
     return x, rms
 
 
-def precondition(theta, out_scale, r, kind, nr, nz):
-    """z = out_scale * rms(r) * net(r / rms(r)) on unknown nodes."""
+def network_correction(theta, out_scale, r, kind, nr, nz):
+    """out_scale * rms(r) * net(r / rms(r)) on unknown nodes."""
     x, rms = features(r, kind, nr, nz)
     out, _ = forward(theta, x[None])
     z = out_scale * rms * out[0, 0].ravel()
     return np.where(kind == 0, z, 0.0)
 
 
+def precondition(theta, out_scale, r, kind, nr, nz, apply_a):
+    """z = post(x1 + network_correction(r - A x1), r) with x1 = pre(r)."""
+    diag = diagonal(apply_a, kind, nr, nz)
+    x1 = pre_smooth(r, kind, nr, nz, apply_a, diag)
+    r1 = np.where(kind == 0, r - apply_a(x1), 0.0)
+    x2 = x1 + network_correction(theta, out_scale, r1, kind, nr, nz)
+    return post_smooth(x2, r, kind, nr, nz, apply_a, diag)
+
+
 def loss_and_grad(theta, out_scale, b, phi, kind, nr, nz, apply_a):
-    """Mean relative A-norm error over a batch of pairs (b[k], phi[k]) with
-    A phi = b, and its gradient in theta.  ``apply_a`` maps a node vector
+    """Mean relative A-norm error of the network correction over a batch of
+    pairs (b[k], phi[k]) with A phi = b (after pre-smoothing), and its
+    gradient in theta.  ``apply_a`` maps a node vector
     (zero on Dirichlet nodes) to A times it on the unknown nodes."""
     unk = kind == 0
     nb = len(b)
+    diag = diagonal(apply_a, kind, nr, nz)
     xs, scaled_phi = [], []
     for k in range(nb):
-        x, rho = features(b[k], kind, nr, nz)
+        x1 = pre_smooth(b[k], kind, nr, nz, apply_a, diag)
+        r1 = np.where(unk, b[k] - apply_a(x1), 0.0)
+        x, rho = features(r1, kind, nr, nz)
         xs.append(x)
-        scaled_phi.append(np.where(unk, phi[k] / rho, 0.0))
+        scaled_phi.append(np.where(unk, (phi[k] - x1) / rho, 0.0))
     out, acts = forward(theta, np.stack(xs))
     L = 0.0
     g_out = np.zeros_like(out)

@@ -167,7 +167,7 @@ def test_adam_first_step_closed_form():
     assert np.allclose(th1, th - lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
 
 
-@pytest.mark.parametrize("pc", ["identity", "jacobi", "network"])
+@pytest.mark.parametrize("pc", ["identity", "jacobi", "network", "sgs", "sandwich"])
 def test_fpcg_reaches_direct_solution(pc):
     p = zero_field_problem(nr=12, nz=14, lr=0.012, lz=0.014, cathode_rmax=0.006)
     o, kind, apply_a = operator(p)
@@ -182,6 +182,12 @@ def test_fpcg_reaches_direct_solution(pc):
         d = np.zeros(kind.size)
         d[idx] = np.diag(A)
         M = lambda r: np.where(kind == 0, r / np.where(d > 0, d, 1.0), 0.0)
+    elif pc == "sgs":
+        theta = np.zeros(N.param_count())
+        M = lambda r: N.precondition(theta, 1.0, r, kind, p.nr, p.nz, apply_a)
+    elif pc == "sandwich":
+        theta = N.init_params(np.random.default_rng(4))
+        M = lambda r: N.precondition(theta, 1e-3, r, kind, p.nr, p.nz, apply_a)
     else:
         # nonlinear: Jacobi plus an untrained network's output at 30% of it
         # (an untrained network alone need not give descent directions)
@@ -192,13 +198,13 @@ def test_fpcg_reaches_direct_solution(pc):
 
         def M(r):
             zj = jac(r)
-            zn = N.precondition(theta, 1.0, r, kind, p.nr, p.nz)
+            zn = N.network_correction(theta, 1.0, r, kind, p.nr, p.nz)
             nn = np.linalg.norm(zn)
             return zj + (0.3 * np.linalg.norm(zj) / nn) * zn if nn > 0 else zj
     x, it, rel = N.fpcg(apply_a, M, b, np.zeros(kind.size), 1e-10, 2000)
     assert rel <= 1e-10
     assert np.abs(x - x_direct).max() <= 1e-8 * np.abs(x_direct).max()
-    if pc != "network":
+    if pc in ("identity", "jacobi", "sgs"):
         # finite termination for a fixed SPD preconditioner (up to rounding)
         assert it <= idx.size + 5
 
@@ -220,3 +226,31 @@ def test_training_lowers_loss():
         theta = N.adam_step(theta, g, st, 2e-3)
     L1, _ = N.loss_and_grad(theta, scale, bs, phis, kind, p.nr, p.nz, apply_a)
     assert L1 < 0.7 * L0
+
+
+def test_zero_network_is_symmetric_gauss_seidel():
+    """With a zero network the preconditioner is red-black symmetric
+    Gauss-Seidel: z1 = (D + L)^-1 r, z = z1 + (D + U)^-1 (r - A z1) in the
+    ordering red nodes first, from a dense matrix; and it is symmetric."""
+    from scipy.linalg import solve_triangular
+    p = zero_field_problem(nr=9, nz=11, lr=0.009, lz=0.011, cathode_rmax=0.005)
+    o, kind, apply_a = operator(p)
+    A, idx = dense(apply_a, kind)
+    red, black = N.colours(kind, p.nr, p.nz)
+    order = np.concatenate([np.flatnonzero(red[idx]), np.flatnonzero(black[idx])])
+    Ao = A[np.ix_(order, order)]
+    rng = np.random.default_rng(3)
+    r = np.zeros(kind.size)
+    r[idx] = rng.normal(size=idx.size)
+    theta = np.zeros(N.param_count())
+    z = N.precondition(theta, 1.0, r, kind, p.nr, p.nz, apply_a)
+    ro = r[idx][order]
+    z1 = solve_triangular(np.tril(Ao), ro, lower=True)
+    zo = z1 + solve_triangular(np.triu(Ao), ro - Ao @ z1, lower=False)
+    ref = np.zeros(kind.size)
+    ref[idx[order]] = zo
+    assert np.abs(z - ref).max() <= 1e-12 * np.abs(ref).max()
+    s2 = np.zeros(kind.size)
+    s2[idx] = rng.normal(size=idx.size)
+    z2 = N.precondition(theta, 1.0, s2, kind, p.nr, p.nz, apply_a)
+    assert abs(s2 @ z - r @ z2) <= 1e-12 * abs(r @ z2)
