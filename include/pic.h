@@ -59,7 +59,8 @@ enum { PIC_MC = 0, PIC_EC = 1 };              /* field-gather scheme (Section 2)
 enum { PIC_F32 = 0, PIC_F64 = 1 };            /* particle-state precision        */
 enum { PIC_FIXED_V = 0, PIC_RESISTOR = 1 };   /* cathode circuit (Sections 3-4)  */
 enum { PIC_ABSORB = 0, PIC_REFLECT = 1 };     /* particle wall condition         */
-enum { PIC_MGCG = 0, PIC_LEARNED = 1 };       /* Poisson preconditioner          */
+enum { PIC_MGCG = 0, PIC_LEARNED = 1, PIC_CG = 2 }; /* field-solve preconditioner:
+                                   multigrid, learned network, none       */
 
 typedef struct pic_handle pic_handle;         /* opaque, library-owned */
 
@@ -89,7 +90,7 @@ typedef struct pic_config {
     uint32_t run;               /* ensemble index, selects the random stream      */
     int64_t capacity[2];        /* particle slots per species                     */
     int32_t sort_every;         /* steps between cell sorts (>= 1)                */
-    int32_t poisson_mode;       /* PIC_MGCG (PIC_LEARNED needs weights)           */
+    int32_t poisson_mode;       /* PIC_MGCG, PIC_LEARNED (needs weights) or PIC_CG */
     double poisson_rtol;        /* FP64 relative residual target of each solve    */
     int32_t poisson_maxit;      /* cap on preconditioned CG iterations per solve  */
     int32_t wall_bc[3];         /* z = 0, z = lz, r = lr: PIC_ABSORB/PIC_REFLECT  */
@@ -97,6 +98,12 @@ typedef struct pic_config {
     int32_t mcc_on, see_on;     /* enable collisions / secondary emission         */
     int32_t field_solve;        /* 0: keep phi fixed (push-only configurations)   */
     double extra_current;       /* synthetic current into the cathode (A)         */
+    int32_t pc_batch;           /* training batch of the learned preconditioner;
+                                   its buffers exist when pc_batch > 0 or
+                                   poisson_mode = PIC_LEARNED (0..64)             */
+    int32_t pc_maxit;           /* cap on learned-preconditioner iterations per
+                                   solve before the multigrid fallback
+                                   (0: poisson_maxit)                             */
 } pic_config;
 
 /* Initial particles of one species (host, FP64, absolute positions).
@@ -138,6 +145,8 @@ typedef struct pic_poisson_stats {
     double rel_res;             /* final ||b - K phi|| / ||b||, FP64              */
     int32_t fell_back;          /* learned preconditioner replaced by MG          */
     int32_t converged;
+    int32_t pc_iterations;      /* of `iterations`, those with the learned
+                                   preconditioner                                 */
 } pic_poisson_stats;
 
 /* Diagnostics (FP64).  ke/pz/dq refer to the last completed step. */
@@ -230,6 +239,49 @@ pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in);
  * returns the sums since the last reset and resets when reset != 0. */
 pic_status pic_enable_timers(pic_handle *h, int32_t on);
 pic_status pic_get_timers(pic_handle *h, pic_timers *out, int32_t reset);
+
+/* ---- learned preconditioner of the field solve -----------------------------
+ * The field solve of every step (Section 3's Gauss's law over the R-Z control
+ * volumes, K phi = Q) runs conjugate gradients; PIC_LEARNED preconditions
+ * them with a 4-level convolutional network z = out_scale rms(r) f(r / rms(r),
+ * i / 256) (15 3x3 convolutions with ReLU, average pooling, nearest
+ * upsampling and additive skips; channels 16, 16, 48, 80), BF16 MFMA with
+ * FP32 accumulation.  Because f is nonlinear the iteration is flexible CG
+ * (Polak-Ribiere beta); when it reaches pc_maxit iterations without meeting
+ * poisson_rtol, or stops reducing the residual, the solve continues from its
+ * current iterate with multigrid-preconditioned CG (stats.fell_back = 1).
+ * The set-up solves of pic_init always use multigrid.
+ *
+ * Parameters are one flat FP32 vector: for each convolution in order, its
+ * weights [cout][cin][3][3] then its bias [cout]. */
+
+/* Number of parameters of the network (196753). */
+pic_status pic_pc_param_count(int64_t *n);
+
+/* Load weights (host, n floats) and the output scale; resets Adam.
+ * Errors: PIC_EINVAL (n mismatch), PIC_ESTATE (no preconditioner buffers:
+ * pc_batch = 0 and poisson_mode != PIC_LEARNED).  Synchronizes. */
+pic_status pic_pc_set_weights(pic_handle *h, const float *theta, int64_t n, double out_scale);
+pic_status pic_pc_get_weights(pic_handle *h, float *theta, int64_t n, double *out_scale);
+
+/* One Adam step (learning rate lr; lr = 0 computes loss and gradient only)
+ * on `batch` pairs (q_dev: node charge in C, phi_dev: potential in V, FP64,
+ * [batch][nodes]) with K phi = q and phi = 0 on every Dirichlet node, such
+ * as (Q, phi0) of a step.  Loss: the mean over the pairs of
+ * (1/2) e.A e / (phihat.A phihat), e = out_scale f(b / rho) - phi / rho on
+ * unknown nodes, A = K / (2 pi eps0), b = A phi, rho = rms(b).  *loss gets
+ * the loss before the update; grad (host, nullable, param_count floats)
+ * the gradient.  1 <= batch <= pc_batch.  Synchronizes. */
+pic_status pic_pc_train_step(pic_handle *h, const double *q_dev, const double *phi_dev,
+                             int32_t batch, float lr, double *loss, float *grad);
+
+/* z = out_scale rms(r) f(r / rms(r)) on unknown nodes (0 on Dirichlet
+ * nodes); r_dev, z_dev FP64 node vectors in units of A = K / (2 pi eps0).
+ * Synchronizes. */
+pic_status pic_pc_apply(pic_handle *h, const double *r_dev, double *z_dev);
+
+/* Switch the preconditioner of later solves (PIC_LEARNED needs weights). */
+pic_status pic_set_poisson_mode(pic_handle *h, int32_t mode);
 
 /* Destroy the handle (does not free the caller's workspace). */
 pic_status pic_free(pic_handle *h);

@@ -48,6 +48,7 @@ class pic_config(C.Structure):
         ("frozen_ions", C.c_int32), ("mcc_on", C.c_int32), ("see_on", C.c_int32),
         ("field_solve", C.c_int32),
         ("extra_current", C.c_double),
+        ("pc_batch", C.c_int32), ("pc_maxit", C.c_int32),
     ]
 
 
@@ -70,7 +71,8 @@ class pic_field_view(C.Structure):
 
 class pic_poisson_stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("outer", C.c_int32), ("rel_res", C.c_double),
-                ("fell_back", C.c_int32), ("converged", C.c_int32)]
+                ("fell_back", C.c_int32), ("converged", C.c_int32),
+                ("pc_iterations", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -123,7 +125,11 @@ EXPORTS = [
     "pic_query_workspace", "pic_init", "pic_step", "pic_poisson", "pic_diag",
     "pic_particles", "pic_fields", "pic_set_phi", "pic_compact", "pic_get_state",
     "pic_set_state", "pic_enable_timers", "pic_get_timers", "pic_free", "pic_last_error",
+    "pic_pc_param_count", "pic_pc_set_weights", "pic_pc_get_weights", "pic_pc_train_step",
+    "pic_pc_apply", "pic_set_poisson_mode",
 ]
+
+PIC_MGCG, PIC_LEARNED, PIC_CG = 0, 1, 2
 
 _lib = None
 
@@ -154,6 +160,14 @@ def load():
     L.pic_enable_timers.argtypes = [H, C.c_int32]
     L.pic_get_timers.argtypes = [H, C.POINTER(pic_timers), C.c_int32]
     L.pic_free.argtypes = [H]
+    _fp = C.POINTER(C.c_float)
+    L.pic_pc_param_count.argtypes = [C.POINTER(C.c_int64)]
+    L.pic_pc_set_weights.argtypes = [H, _fp, C.c_int64, C.c_double]
+    L.pic_pc_get_weights.argtypes = [H, _fp, C.c_int64, C.POINTER(C.c_double)]
+    L.pic_pc_train_step.argtypes = [H, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                    C.POINTER(C.c_double), _fp]
+    L.pic_pc_apply.argtypes = [H, C.c_void_p, C.c_void_p]
+    L.pic_set_poisson_mode.argtypes = [H, C.c_int32]
     L.pic_last_error.argtypes = [H]
     L.pic_last_error.restype = C.c_char_p
     for name in EXPORTS:

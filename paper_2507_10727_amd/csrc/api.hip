@@ -10,6 +10,7 @@
 #include <tuple>
 #include <vector>
 
+#include "cnn.h"
 #include "common.h"
 
 using namespace pic;
@@ -65,11 +66,17 @@ struct pic_handle {
     double rho = 0.15, rel0_est = 1e-2;
     struct PassGraph {
         const void *phi, *q0, *q1;
-        int n_iter;
+        int n_iter, mode;
         hipGraphExec_t exec;
     };
     std::vector<PassGraph> graphs;
     bool use_graphs = true;
+    // learned preconditioner
+    PcNet net;
+    bool pc_on = false;
+    int pmode = PIC_MGCG;
+    int64_t n_unknown = 0;
+    double rho_pc = 0.5, rho_cg = 0.9;
     int32_t host_flags = 0;
     bool timers_on = false;
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
@@ -151,8 +158,12 @@ pic_status validate(const pic_config *c, pic_handle *h)
     if (c->sort_every < 1) return fail(h, PIC_EINVAL, "sort_every must be >= 1");
     if (!(c->poisson_rtol > 0) || c->poisson_maxit < 1 || c->poisson_maxit > MAX_PCG)
         return fail(h, PIC_EINVAL, "poisson_rtol > 0 and 1 <= poisson_maxit <= %d required", MAX_PCG);
-    if (c->poisson_mode != PIC_MGCG)
-        return fail(h, PIC_EINVAL, "poisson_mode: only PIC_MGCG is available in this build");
+    if (c->poisson_mode != PIC_MGCG && c->poisson_mode != PIC_LEARNED && c->poisson_mode != PIC_CG)
+        return fail(h, PIC_EINVAL, "poisson_mode must be PIC_MGCG, PIC_LEARNED or PIC_CG");
+    if (c->pc_batch < 0 || c->pc_batch > 64)
+        return fail(h, PIC_EINVAL, "pc_batch outside [0, 64]");
+    if (c->pc_maxit < 0 || c->pc_maxit > MAX_PCG)
+        return fail(h, PIC_EINVAL, "pc_maxit outside [0, %d]", MAX_PCG);
     if (c->gamma_i < 0 || c->p_gas < 0 || !(c->t_gas > 0))
         return fail(h, PIC_EINVAL, "gamma_i, p_gas >= 0 and t_gas > 0 required");
     for (int k = 0; k < 3; ++k)
@@ -289,7 +300,20 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     const int dblocks = 256;
     double *dpart = cv.take<double>((int64_t)dblocks * 6 * 8);
     unsigned long long *live = cv.take<unsigned long long>(2 * 8);
+    // learned preconditioner: network, Adam state and activations
+    const bool pc_on = c.pc_batch > 0 || c.poisson_mode == PIC_LEARNED;
+    PcNet net;
+    char *pc_base = nullptr;
+    if (pc_on) {
+        pc_describe(net, c.nr, c.nz, std::max(1, c.pc_batch));
+        pc_base = cv.take<char>(pc_bytes(net));
+    }
     if (h) {
+        h->pc_on = pc_on;
+        if (pc_on) {
+            h->net = net;
+            pc_bind(h->net, pc_base);
+        }
         h->sc = sc;
         for (int s = 0; s < 2; ++s)
             for (int b = 0; b < 2; ++b) h->buf[s][b] = bufs[s][b];
@@ -380,6 +404,9 @@ pic_status setup_field(pic_handle *h)
     HIPCHECK(h, hipMemcpy((void *)h->f.ce64, ce.data(), nodes * 8, hipMemcpyHostToDevice));
     HIPCHECK(h, hipMemcpy((void *)h->f.cn64, cn.data(), nodes * 8, hipMemcpyHostToDevice));
     HIPCHECK(h, hipMemcpy((void *)h->f.kind, kind.data(), nodes, hipMemcpyHostToDevice));
+    h->n_unknown = std::count(kind.begin(), kind.end(), (uint8_t)0);
+    if (h->pc_on && pc_kernel_setup() != 0)
+        return fail(h, PIC_EHIP, "cannot raise the LDS limit of the convolution kernels");
     host_node_volumes(c.nr, c.nz, c.lr, c.lz, tmp.data());
     HIPCHECK(h, hipMemcpy((void *)h->f.vdep, tmp.data(), nodes * 8, hipMemcpyHostToDevice));
     HIPCHECK(h, hipMemcpy((void *)h->f.b_r, c.b_r, nodes * 8, hipMemcpyHostToDevice));
@@ -461,11 +488,16 @@ struct SolveReadback {
     int64_t count[2];
 };
 
-pic_status readback(pic_handle *h, SolveReadback *rb)
+// With hist, also the inner iterations' squared residuals of the pass (the
+// FP32 residual starts at unit norm), in the same synchronization.
+pic_status readback(pic_handle *h, SolveReadback *rb, double *hist = nullptr, int n_hist = 0)
 {
     static_assert(sizeof(SolveReadback) == 48, "readback layout");
     HIPCHECK(h, hipMemcpyAsync(rb, &h->sc->res_rr, sizeof(SolveReadback), hipMemcpyDeviceToHost,
                                h->stream));
+    if (hist && n_hist > 0)
+        HIPCHECK(h, hipMemcpyAsync(hist, h->sc->pcg_rr, (size_t)n_hist * 8, hipMemcpyDeviceToHost,
+                                   h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     h->host_count[0] = rb->count[0];
     h->host_count[1] = rb->count[1];
@@ -473,40 +505,65 @@ pic_status readback(pic_handle *h, SolveReadback *rb)
     return PIC_OK;
 }
 
-// One refinement pass (after the residual that precedes it): scale, V-cycle,
-// n_iter preconditioned CG iterations, FP64 update and the new residual.
+// Preconditioner of CG iteration k: z = M r on the finest level, r.z into
+// pcg_rz[k] (and z_k.q_{k-1} into pcg_zq[k] for the learned one).
+void enqueue_precond(pic_handle *h, int mode, int k)
+{
+    hipStream_t s = h->stream;
+    FieldDev &f = h->f;
+    const MGHier &H = f.mg;
+    if (mode == PIC_LEARNED)
+        pc_apply32(h->net, H.lv[0], h->n_unknown, H.lv[0].b, H.lv[0].xu, k > 0 ? f.q32 : nullptr,
+                   &h->sc->pcg_rz[k], &h->sc->pcg_zq[k], &h->sc->pcg_ss[k], s);
+    else if (mode == PIC_CG)
+        pc_identity32(H.lv[0], H.lv[0].b, H.lv[0].xu, &h->sc->pcg_rz[k], s);
+    else
+        launch_mg_vcycle(H, &h->sc->pcg_rz[k], s);
+}
+
+// One refinement pass (after the residual that precedes it): scale, n_iter
+// preconditioned CG iterations (flexible CG for the learned preconditioner),
+// FP64 update and the new residual.
 template <typename Q>
-void enqueue_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_iter)
+void enqueue_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_iter, int mode)
 {
     hipStream_t s = h->stream;
     FieldDev &f = h->f;
     const MGHier &H = f.mg;
     const double inv_2pi_eps0 = 1.0 / (2.0 * 3.14159265358979323846 * eps0());
     launch_cast_scale(f, h->sc, s);
-    launch_zero(h->sc->pcg_rz, sizeof(double) * 3 * (MAX_PCG + 2), s);
-    launch_mg_vcycle(H, &h->sc->pcg_rz[0], s);
+    launch_zero(h->sc->pcg_rz, sizeof(double) * 5 * (MAX_PCG + 2), s);
+    const double *zq = (mode == PIC_LEARNED) ? h->sc->pcg_zq : nullptr;
+    enqueue_precond(h, mode, 0);
     for (int k = 0; k < n_iter; ++k) {
         launch_cg_matvec(H, H.lv[0].xu, f.p32[(k + 1) & 1], f.p32[k & 1], f.q32, h->sc->pcg_rz,
-                         k, &h->sc->pcg_pq[k], s);
+                         k, &h->sc->pcg_pq[k], zq, s);
         launch_cg_update(H, f.p32[k & 1], f.q32, f.e32, H.lv[0].b, &h->sc->pcg_rz[k],
                          &h->sc->pcg_pq[k], &h->sc->pcg_rr[k], s);
-        if (k + 1 < n_iter) launch_mg_vcycle(H, &h->sc->pcg_rz[k + 1], s);
+        if (k + 1 < n_iter) enqueue_precond(h, mode, k + 1);
     }
     launch_update64(f, phi, h->sc, inv_2pi_eps0, s);
     launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
 }
 
-// The pass is replayed from a cached hipGraph per (buffers, iteration count)
-// when the stream allows capture; otherwise its kernels are launched directly.
+void drop_graphs(pic_handle *h)
+{
+    for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+}
+
+// The pass is replayed from a cached hipGraph per (buffers, iteration count,
+// preconditioner) when the stream allows capture; otherwise its kernels are
+// launched directly.
 template <typename Q>
-pic_status run_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_iter)
+pic_status run_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_iter, int mode)
 {
     if (!h->use_graphs || h->stream == nullptr) {
-        enqueue_pass<Q>(h, phi, q0, q1, n_iter);
+        enqueue_pass<Q>(h, phi, q0, q1, n_iter, mode);
         return PIC_OK;
     }
     for (auto &g : h->graphs)
-        if (g.phi == phi && g.q0 == q0 && g.q1 == q1 && g.n_iter == n_iter) {
+        if (g.phi == phi && g.q0 == q0 && g.q1 == q1 && g.n_iter == n_iter && g.mode == mode) {
             HIPCHECK(h, hipGraphLaunch(g.exec, h->stream));
             return PIC_OK;
         }
@@ -514,49 +571,75 @@ pic_status run_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_
     if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
         h->use_graphs = false;
-        enqueue_pass<Q>(h, phi, q0, q1, n_iter);
+        enqueue_pass<Q>(h, phi, q0, q1, n_iter, mode);
         return PIC_OK;
     }
-    enqueue_pass<Q>(h, phi, q0, q1, n_iter);
+    enqueue_pass<Q>(h, phi, q0, q1, n_iter, mode);
     HIPCHECK(h, hipStreamEndCapture(h->stream, &graph));
     hipGraphExec_t exec;
     HIPCHECK(h, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     (void)hipGraphDestroy(graph);
-    h->graphs.push_back({phi, q0, q1, n_iter, exec});
+    h->graphs.push_back({phi, q0, q1, n_iter, mode, exec});
     HIPCHECK(h, hipGraphLaunch(exec, h->stream));
     return PIC_OK;
 }
 
+// FP64-refined solve.  With the learned preconditioner, after pc_maxit of
+// its iterations without convergence, or a pass that does not lower the
+// residual, the remaining passes use the multigrid preconditioner.
 template <typename Q>
 pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_cathode,
-                 pic_poisson_stats *st)
+                 pic_poisson_stats *st, int mode)
 {
     hipStream_t s = h->stream;
     FieldDev &f = h->f;
     const double rtol = h->cfg.poisson_rtol;
     const int maxit = h->cfg.poisson_maxit;
+    const int pc_cap = h->cfg.pc_maxit > 0 ? h->cfg.pc_maxit : maxit;
+    if (mode == PIC_LEARNED && !(h->pc_on && h->net.has_weights))
+        return fail(h, PIC_ESTATE, "the learned preconditioner has no weights");
+    pic_status pe = PIC_OK;
     pic_poisson_stats S = {};
     launch_set_dirichlet(f, phi, v_cathode, s);
     launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
+    auto rate = [&]() -> double & {
+        return mode == PIC_LEARNED ? h->rho_pc : (mode == PIC_CG ? h->rho_cg : h->rho);
+    };
     // iterations for a target reduction at the measured rate; one FP32 pass
     // is asked for at most 1e-6 (about what single precision delivers)
     auto iters_for = [&](double rel_now) {
         const double target = std::max(0.5 * rtol / rel_now, 1e-6);
         if (target >= 1.0) return 1;
-        const int n = (int)std::ceil(std::log(target) / std::log(h->rho));
+        const int n = (int)std::ceil(std::log(target) / std::log(rate()));
         return std::max(1, std::min(n, 64));
     };
-    int n_iter = iters_for(h->rel0_est);
-    const int max_pass = 12;
+    double rel_now = h->rel0_est;
+    int n_iter = iters_for(rel_now);
+    const int max_pass = 24;
     for (int pass = 0;; ++pass) {
-        if (pass == max_pass || S.iterations >= maxit) break;
-        n_iter = std::max(1, std::min(n_iter, maxit - S.iterations));
-        pic_status pe = run_pass<Q>(h, phi, q0, q1, n_iter);
+        if (pass == max_pass) break;
+        int left;
+        if (mode == PIC_LEARNED) {
+            left = pc_cap - S.pc_iterations;
+            if (left <= 0) {
+                mode = PIC_MGCG;
+                S.fell_back = 1;
+                n_iter = iters_for(rel_now);
+                left = maxit;
+            }
+        } else {
+            left = maxit - (S.iterations - S.pc_iterations);
+        }
+        if (left <= 0) break;
+        n_iter = std::max(1, std::min(n_iter, left));
+        pe = run_pass<Q>(h, phi, q0, q1, n_iter, mode);
         if (pe != PIC_OK) return pe;
         S.iterations += n_iter;
+        if (mode == PIC_LEARNED) S.pc_iterations += n_iter;
         S.outer++;
         SolveReadback rb;
-        pic_status e = readback(h, &rb);
+        double hist[MAX_PCG];
+        pic_status e = readback(h, &rb, hist, n_iter);
         if (e != PIC_OK) return e;
         if (!std::isfinite(rb.rr) || !std::isfinite(rb.bb)) {
             S.rel_res = NAN;
@@ -572,13 +655,30 @@ pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_
         }
         const double rel0 = std::sqrt(rb.rr0 / rb.bb), rel = std::sqrt(rb.rr / rb.bb);
         S.rel_res = rel;
+        rel_now = rel;
         if (pass == 0 && rel0 > 0.0) h->rel0_est = rel0;
-        // per-iteration rate, from passes that precision did not limit
-        if (rel0 > 0.0 && rel < rel0 && rel / rel0 > 1e-5)
-            h->rho = std::min(std::max(std::pow(rel / rel0, 1.0 / n_iter), 0.01), 0.9);
+        // per-iteration rate from the inner residuals: the iterations the
+        // pass needed for its target, else the average over the pass
+        {
+            const double target = std::max(0.5 * rtol / std::max(rel0, 1e-300), 1e-6);
+            int hit = -1;
+            for (int k = 0; k < n_iter; ++k)
+                if (std::sqrt(std::max(hist[k], 0.0)) <= target) {
+                    hit = k;
+                    break;
+                }
+            double est;
+            if (hit >= 0) est = std::pow(target, 1.0 / (hit + 1));
+            else est = std::pow(std::sqrt(std::max(hist[n_iter - 1], 1e-300)), 1.0 / n_iter);
+            if (std::isfinite(est) && est > 0.0) rate() = std::min(std::max(est, 0.01), 0.97);
+        }
         if (rel <= rtol) {
             S.converged = 1;
             break;
+        }
+        if (mode == PIC_LEARNED && !(rel < rel0)) {
+            mode = PIC_MGCG;
+            S.fell_back = 1;
         }
         n_iter = iters_for(rel);
     }
@@ -730,7 +830,8 @@ pic_status field_update(pic_handle *h)
     hipEvent_t ev[2];
     timer_begin(h, ev);
     launch_extrapolate(h->f, 0, h->stream);
-    pic_status st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr);
+    pic_status st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr,
+                              h->pmode);
     timer_end(h, 3, ev);
     if (st != PIC_OK) return st;
     timer_begin(h, ev);
@@ -870,7 +971,7 @@ pic_status init_typed(pic_handle *h, const pic_species_host *init)
     // phi_L: cathode at 1 V, no charge
     launch_begin_step(h->sc, h->q[0], h->q[1], nodes, (int)sizeof(T), s);
     launch_zero(h->f.phi_l, nodes * 8, s);
-    st = solve<T>(h, h->f.phi_l, (const T *)h->q[0], (const T *)h->q[1], 1.0, nullptr);
+    st = solve<T>(h, h->f.phi_l, (const T *)h->q[0], (const T *)h->q[1], 1.0, nullptr, PIC_MGCG);
     if (st != PIC_OK) return st;
     // capacitance C = sum over cathode nodes of (K phi_L)
     {
@@ -894,7 +995,8 @@ pic_status init_typed(pic_handle *h, const pic_species_host *init)
     launch_push_h<T>(h, 1);
     launch_zero(h->f.phi0, nodes * 8, s);
     if (c.field_solve) {
-        st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr);
+        st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr,
+                      PIC_MGCG);
         if (st != PIC_OK) return st;
     }
     launch_extrapolate(h->f, 1, s);
@@ -946,6 +1048,7 @@ pic_status pic_init(const pic_config *cfg, void *workspace_dev, int64_t workspac
     h->cap[1] = cfg->capacity[1];
     const char *ng = getenv("PIC_NO_GRAPHS");
     h->use_graphs = !(ng && ng[0] == '1');
+    h->pmode = cfg->poisson_mode;
     layout(*cfg, h->ws, h);
     st = (h->prec == PIC_F64) ? init_typed<double>(h, init) : init_typed<float>(h, init);
     // the host arrays of the config are not kept
@@ -978,7 +1081,8 @@ pic_status pic_poisson(pic_handle *h, const double *q_dev, double v_cathode, dou
     if (!q_dev || !phi_dev) return fail(h, PIC_EINVAL, "q_dev and phi_dev are required");
     hipEvent_t ev[2];
     timer_begin(h, ev);
-    pic_status st = solve<double>(h, phi_dev, q_dev, (const double *)nullptr, v_cathode, stats);
+    pic_status st = solve<double>(h, phi_dev, q_dev, (const double *)nullptr, v_cathode, stats,
+                                  h->pmode);
     timer_end(h, 3, ev);
     return st;
 }
@@ -1151,6 +1255,98 @@ pic_status pic_get_timers(pic_handle *h, pic_timers *out, int32_t reset)
     timers_collect(h);
     *out = h->timers;
     if (reset) h->timers = pic_timers{};
+    return PIC_OK;
+}
+
+pic_status pic_pc_param_count(int64_t *n)
+{
+    if (!n) return fail(nullptr, PIC_EINVAL, "n is NULL");
+    PcNet t;
+    pc_describe(t, 4, 4, 1);
+    *n = t.n_flat;
+    return PIC_OK;
+}
+
+pic_status pic_pc_set_weights(pic_handle *h, const float *theta, int64_t n, double out_scale)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (!h->pc_on) return fail(h, PIC_ESTATE, "no learned-preconditioner buffers (pc_batch = 0)");
+    if (!theta || n != h->net.n_flat)
+        return fail(h, PIC_EINVAL, "expected %lld parameters", (long long)h->net.n_flat);
+    if (!std::isfinite(out_scale) || !(out_scale > 0.0))
+        return fail(h, PIC_EINVAL, "out_scale must be positive and finite");
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(theta[k])) return fail(h, PIC_EINVAL, "parameter %lld is not finite", (long long)k);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    // cached solve graphs hold the output scale by value
+    drop_graphs(h);
+    h->net.out_scale = out_scale;
+    pc_upload(h->net, theta, h->stream);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipGetLastError());
+    h->net.has_weights = true;
+    return PIC_OK;
+}
+
+pic_status pic_pc_get_weights(pic_handle *h, float *theta, int64_t n, double *out_scale)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (!h->pc_on || !h->net.has_weights) return fail(h, PIC_ESTATE, "no weights loaded");
+    if (!theta || n != h->net.n_flat)
+        return fail(h, PIC_EINVAL, "expected %lld parameters", (long long)h->net.n_flat);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    std::vector<float> tmp;
+    pc_download_flat(h->net, h->net.master, theta, tmp);
+    if (out_scale) *out_scale = h->net.out_scale;
+    return PIC_OK;
+}
+
+pic_status pic_pc_train_step(pic_handle *h, const double *q_dev, const double *phi_dev,
+                             int32_t batch, float lr, double *loss, float *grad)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (!h->pc_on || !h->net.has_weights) return fail(h, PIC_ESTATE, "no weights loaded");
+    if (!q_dev || !phi_dev) return fail(h, PIC_EINVAL, "q_dev and phi_dev are required");
+    if (batch < 1 || batch > h->net.batch)
+        return fail(h, PIC_EINVAL, "batch %d outside [1, %d]", batch, h->net.batch);
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(h, PIC_EINVAL, "lr must be >= 0");
+    const double inv_2pi_eps0 = 1.0 / (2.0 * 3.14159265358979323846 * eps0());
+    pc_train_enqueue(h->net, h->f.mg.lv[0], h->n_unknown, q_dev, phi_dev, batch, lr, inv_2pi_eps0,
+                     h->stream);
+    double l = 0.0;
+    HIPCHECK(h, hipMemcpyAsync(&l, pc_loss_ptr(h->net, batch), 8, hipMemcpyDeviceToHost,
+                               h->stream));
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipGetLastError());
+    if (loss) *loss = l;
+    if (grad) {
+        std::vector<float> tmp;
+        pc_download_flat(h->net, h->net.grad, grad, tmp);
+    }
+    if (!std::isfinite(l)) return fail(h, PIC_ENAN, "non-finite training loss");
+    return PIC_OK;
+}
+
+pic_status pic_pc_apply(pic_handle *h, const double *r_dev, double *z_dev)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (!h->pc_on || !h->net.has_weights) return fail(h, PIC_ESTATE, "no weights loaded");
+    if (!r_dev || !z_dev) return fail(h, PIC_EINVAL, "r_dev and z_dev are required");
+    pc_apply64(h->net, h->f.mg.lv[0], h->n_unknown, r_dev, z_dev, &h->sc->pcg_ss[MAX_PCG + 1],
+               h->stream);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipGetLastError());
+    return PIC_OK;
+}
+
+pic_status pic_set_poisson_mode(pic_handle *h, int32_t mode)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (mode != PIC_MGCG && mode != PIC_LEARNED && mode != PIC_CG)
+        return fail(h, PIC_EINVAL, "mode must be PIC_MGCG, PIC_LEARNED or PIC_CG");
+    if (mode == PIC_LEARNED && !h->pc_on)
+        return fail(h, PIC_ESTATE, "no learned-preconditioner buffers (pc_batch = 0)");
+    h->pmode = mode;
     return PIC_OK;
 }
 

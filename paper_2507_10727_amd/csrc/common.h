@@ -54,6 +54,8 @@ struct DevScalars {
     int64_t sort_total[2];
     // field solve accumulators
     double pcg_rz[MAX_PCG + 2], pcg_pq[MAX_PCG + 2], pcg_rr[MAX_PCG + 2];
+    double pcg_zq[MAX_PCG + 2];     // z_k . q_{k-1} (flexible CG)
+    double pcg_ss[MAX_PCG + 2];     // sum r^2 of each learned-preconditioner input
 };
 
 template <typename T>
@@ -231,6 +233,38 @@ struct MGLevel {
     float *xu;                  // correction after post-smoothing (up pass)
 };
 
+// Matrix-free operator of a level, divided by 2 pi eps0: east face (i+1/2, j)
+// coupling (i + 1/2) hz_j with hz_j = dz (dz/2 on the z walls); north face
+// (i, j+1/2) coupling g_i dr^2 / dz with g_0 = 1/8, g_i = i, g_nr = nr/2 - 1/8.
+// Unknown nodes exclude the anode row, the outer column and the cathode.
+__device__ __forceinline__ bool mg_in(const MGLevel &L, int i, int j)
+{
+    return i >= 0 && j >= 0 && i <= L.nr && j <= L.nz;
+}
+__device__ __forceinline__ bool mg_unknown(const MGLevel &L, int i, int j)
+{
+    return i < L.nr && j < L.nz && !(j == 0 && i < L.cath);
+}
+__device__ __forceinline__ float mg_ae(const MGLevel &L, int i, int j)
+{
+    const float hz = (j == 0 || j == L.nz) ? 0.5f * L.dz : L.dz;
+    return ((float)i + 0.5f) * hz;
+}
+__device__ __forceinline__ float mg_an(const MGLevel &L, int i)
+{
+    const float g = (i == 0) ? 0.125f : ((i == L.nr) ? 0.5f * (float)L.nr - 0.125f : (float)i);
+    return g * L.dr2dz;
+}
+// couplings of an unknown node: west, east, south, north (0 if absent)
+__device__ __forceinline__ void mg_coup(const MGLevel &L, int i, int j, float &w, float &e,
+                                        float &s, float &n)
+{
+    w = (i > 0) ? mg_ae(L, i - 1, j) : 0.0f;
+    e = mg_ae(L, i, j);
+    s = (j > 0) ? mg_an(L, i) : 0.0f;
+    n = mg_an(L, i);
+}
+
 struct MGTail {
     MGLevel L[MAX_LEVELS];
     int32_t first, last;        // levels handled inside one workgroup
@@ -250,8 +284,10 @@ struct MGHier {
 };
 
 void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s);   // lv[0].xu = M lv[0].b
+// p = z + beta p_prev, q = A p, pq[0] += p.q (pq = &pcg_pq[k]); beta from
+// rz (Fletcher-Reeves) or, when zq is given, Polak-Ribiere (flexible CG)
 void launch_cg_matvec(const MGHier &H, const float *z, const float *pp, float *pc, float *q,
-                      const double *rz, int k, double *pq, hipStream_t s);
+                      const double *rz, int k, double *pq, const double *zq, hipStream_t s);
 void launch_cg_update(const MGHier &H, const float *p, const float *q, float *e, float *r,
                       const double *rz, const double *pq, double *rr, hipStream_t s);
 int mg_tail_setup(MGHier &H);

@@ -24,34 +24,6 @@ namespace pic {
 
 namespace {
 
-__device__ __forceinline__ bool mg_in(const MGLevel &L, int i, int j)
-{
-    return i >= 0 && j >= 0 && i <= L.nr && j <= L.nz;
-}
-__device__ __forceinline__ bool mg_unknown(const MGLevel &L, int i, int j)
-{
-    return i < L.nr && j < L.nz && !(j == 0 && i < L.cath);
-}
-__device__ __forceinline__ float mg_ae(const MGLevel &L, int i, int j)
-{
-    const float hz = (j == 0 || j == L.nz) ? 0.5f * L.dz : L.dz;
-    return ((float)i + 0.5f) * hz;
-}
-__device__ __forceinline__ float mg_an(const MGLevel &L, int i)
-{
-    const float g = (i == 0) ? 0.125f : ((i == L.nr) ? 0.5f * (float)L.nr - 0.125f : (float)i);
-    return g * L.dr2dz;
-}
-// couplings of an unknown node: west, east, south, north (0 if absent)
-__device__ __forceinline__ void mg_coup(const MGLevel &L, int i, int j, float &w, float &e,
-                                        float &s, float &n)
-{
-    w = (i > 0) ? mg_ae(L, i - 1, j) : 0.0f;
-    e = mg_ae(L, i, j);
-    s = (j > 0) ? mg_an(L, i) : 0.0f;
-    n = mg_an(L, i);
-}
-
 // bilinear prolongation of the coarse correction to fine node (i, j)
 __device__ __forceinline__ float mg_prolong(const float *xc, int ldc, int i, int j)
 {
@@ -347,10 +319,15 @@ constexpr int CB = 256;
 // q = A p_k, and p_k . q accumulated.
 __global__ void __launch_bounds__(CB) k_cg_matvec(MGLevel L, const float *z, const float *pp,
                                                   float *pc, float *q, const double *rz, int k,
-                                                  double *pq)
+                                                  double *pq, const double *zq)
 {
     __shared__ double red[CB / 64];
-    const double bd = (k > 0 && rz[k - 1] != 0.0) ? rz[k] / rz[k - 1] : 0.0;
+    // Fletcher-Reeves beta for a fixed preconditioner; with zq (z_k.q_{k-1})
+    // the Polak-Ribiere beta of flexible CG, z_k.(r_k - r_{k-1}) / z_{k-1}.r_{k-1}
+    // = -z_k.q_{k-1} / p_{k-1}.q_{k-1}
+    double bd = 0.0;
+    if (zq) bd = (k > 0 && pq[-1] != 0.0) ? -zq[k] / pq[-1] : 0.0;
+    else bd = (k > 0 && rz[k - 1] != 0.0) ? rz[k] / rz[k - 1] : 0.0;
     const float beta = (float)bd;
     const int ld = L.nr + 1;
     const int64_t nn = (int64_t)ld * (L.nz + 1);
@@ -432,11 +409,12 @@ void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s)
 }
 
 void launch_cg_matvec(const MGHier &H, const float *z, const float *pp, float *pc, float *q,
-                      const double *rz, int k, double *pq, hipStream_t s)
+                      const double *rz, int k, double *pq, const double *zq, hipStream_t s)
 {
     const MGLevel &L = H.lv[0];
     const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
-    hipLaunchKernelGGL(k_cg_matvec, dim3(cg_blocks(nn)), dim3(CB), 0, s, L, z, pp, pc, q, rz, k, pq);
+    hipLaunchKernelGGL(k_cg_matvec, dim3(cg_blocks(nn)), dim3(CB), 0, s, L, z, pp, pc, q, rz, k, pq,
+                       zq);
 }
 
 void launch_cg_update(const MGHier &H, const float *p, const float *q, float *e, float *r,

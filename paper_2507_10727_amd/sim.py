@@ -41,7 +41,9 @@ def make_config(prob: W.Problem, b_r, b_z, sigma, de_table=W.DE_TABLE, capacity=
     cap = capacity or prob.capacity()
     c.capacity[0], c.capacity[1] = int(cap[0]), int(cap[1])
     c.sort_every = prob.sort_every
-    c.poisson_mode = 0
+    c.poisson_mode = prob.poisson_mode
+    c.pc_batch = prob.pc_batch
+    c.pc_maxit = prob.pc_maxit
     c.poisson_rtol = prob.poisson_rtol
     c.poisson_maxit = prob.poisson_maxit
     for k in range(3):
@@ -143,6 +145,44 @@ class Simulation:
         s.next_id[0], s.next_id[1] = st["next_id"]
         s.count[0], s.count[1] = st["count"]
         L.check(self.lib.pic_set_state(self.h, C.byref(s)), self.h)
+
+    # -- learned preconditioner ----------------------------------------------
+    def pc_param_count(self):
+        n = C.c_int64()
+        L.check(self.lib.pic_pc_param_count(C.byref(n)), self.h)
+        return int(n.value)
+
+    def pc_set_weights(self, theta, out_scale):
+        a = np.ascontiguousarray(theta, np.float32)
+        L.check(self.lib.pic_pc_set_weights(self.h, a.ctypes.data_as(C.POINTER(C.c_float)),
+                                            a.size, float(out_scale)), self.h)
+
+    def pc_get_weights(self):
+        a = np.zeros(self.pc_param_count(), np.float32)
+        sc = C.c_double()
+        L.check(self.lib.pic_pc_get_weights(self.h, a.ctypes.data_as(C.POINTER(C.c_float)),
+                                            a.size, C.byref(sc)), self.h)
+        return a, sc.value
+
+    def pc_train_step(self, q, phi, lr, want_grad=False):
+        """One Adam step on device tensors q, phi (float64, [batch, nodes]);
+        returns the loss before the update (and the gradient if asked)."""
+        self.torch.cuda.synchronize(self.device)
+        loss = C.c_double()
+        g = np.zeros(self.pc_param_count(), np.float32) if want_grad else None
+        gp = g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None
+        L.check(self.lib.pic_pc_train_step(self.h, C.c_void_p(q.data_ptr()),
+                                           C.c_void_p(phi.data_ptr()), int(q.shape[0]),
+                                           float(lr), C.byref(loss), gp), self.h)
+        return (loss.value, g) if want_grad else loss.value
+
+    def pc_apply(self, r, z):
+        self.torch.cuda.synchronize(self.device)
+        L.check(self.lib.pic_pc_apply(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr())),
+                self.h)
+
+    def set_poisson_mode(self, mode):
+        L.check(self.lib.pic_set_poisson_mode(self.h, int(mode)), self.h)
 
     def timers(self, reset=True):
         t = L.pic_timers()

@@ -44,6 +44,9 @@ FIXED_V = 0
 RESISTOR = 1
 ABSORB = 0
 REFLECT = 1
+POISSON_MGCG = 0       # field-solve preconditioner: multigrid
+POISSON_LEARNED = 1    # learned network (flexible CG)
+POISSON_CG = 2         # none
 
 
 @dataclasses.dataclass
@@ -90,6 +93,9 @@ class Problem:
     field_solve: int = 1
     extra_current: float = 0.0
     capacity_factor: float = 1.5
+    poisson_mode: int = 0       # 0 multigrid, 1 learned network, 2 none (plain CG)
+    pc_batch: int = 0           # training batch of the learned preconditioner
+    pc_maxit: int = 0           # learned iterations before the multigrid fallback
     weight: Optional[float] = None  # macroparticle weight; default n*V/N
 
     def __post_init__(self):

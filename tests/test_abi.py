@@ -50,7 +50,8 @@ def test_query_workspace_sizes():
     dict(nr=1), dict(nz=40000), dict(dt=0.0), dict(scheme=7), dict(precision=3),
     dict(circuit=W.RESISTOR, r_ext=0.0), dict(cathode_rmax=1.0), dict(sort_every=0),
     dict(poisson_rtol=0.0), dict(poisson_maxit=0), dict(wall_bc=(0, 5, 0)),
-    dict(nr=101, nz=101),
+    dict(nr=101, nz=101), dict(poisson_mode=5), dict(pc_batch=-1), dict(pc_batch=65),
+    dict(pc_maxit=-1), dict(pc_maxit=100000),
 ])
 def test_invalid_configs_rejected(bad):
     lib = L.load()
@@ -68,3 +69,27 @@ def test_init_rejects_missing_workspace():
     st = lib.pic_init(C.byref(cfg), None, 0, None, None, C.byref(h))
     assert st == L.PIC_EINVAL and not h.value
     assert b"workspace" in lib.pic_last_error(None)
+
+
+def test_learned_preconditioner_sizes():
+    lib = L.load()
+    n = C.c_int64()
+    assert lib.pic_pc_param_count(C.byref(n)) == 0
+    assert n.value == 196753
+    base = C.c_int64()
+    cfg, keep = _cfg()
+    assert lib.pic_query_workspace(C.byref(cfg), C.byref(base)) == 0
+    sizes = []
+    for b in (1, 4):
+        cfg, keep = _cfg(pc_batch=b)
+        m = C.c_int64()
+        assert lib.pic_query_workspace(C.byref(cfg), C.byref(m)) == 0
+        sizes.append(m.value - base.value)
+    # activations and gradients grow with the batch; 65 x 65 nodes, about
+    # 184 floats per node and sample, plus the weight-gradient partials
+    assert sizes[0] > 65 * 65 * 150 * 4
+    assert sizes[1] - sizes[0] > 3 * 65 * 65 * 150 * 4
+    cfg, keep = _cfg(poisson_mode=W.POISSON_LEARNED)
+    m = C.c_int64()
+    assert lib.pic_query_workspace(C.byref(cfg), C.byref(m)) == 0
+    assert m.value - base.value == sizes[0]
