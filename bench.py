@@ -70,44 +70,67 @@ def cpu_baseline(prob, br, bz, sig, parts, max_seconds=40.0):
             "seconds": dt}
 
 
-def poisson_bench(reps=5):
-    """MG-preconditioned CG to an FP64-checked 1e-8 relative residual on the
-    512 x 1024 R-Z operator, cold (phi = 0) and warm (previous solution)."""
+def poisson_bench(train_seconds=60.0, reps=6):
+    """Field solve on the 512 x 1024 R-Z operator to an FP64-checked 1e-8
+    relative residual: multigrid-preconditioned CG against flexible CG with
+    the learned preconditioner, on held-out charge snapshots of a discharge
+    at that grid, cold (phi = 0) and warm (previous snapshot's solution).
+
+    The network is trained first, on the GPU, on pairs the simulation makes:
+    (Q, phi0) snapshots of the same discharge and random potentials with
+    Q = K phi (see pc_train)."""
     import numpy as np
     import torch
+    from paper_2507_10727_amd import pc_train
     from paper_2507_10727_amd import workloads as W
     from paper_2507_10727_amd.sim import Simulation
-    p = W.preset("ec512x1024_f32").replace(poisson_rtol=1e-8, poisson_maxit=500)
-    br, bz = W.magnetron_field(p)
-    sig = W.cross_sections()
-    sim = Simulation(p, br, bz, sig, None, capacity=(1024, 1024))
-    rng = np.random.default_rng(250710730)
-    nn = p.nodes
-    # a charge snapshot shape: smooth positive bulk plus noise
-    r = np.arange(p.nr + 1) * p.dr
-    z = np.arange(p.nz + 1) * p.dz
-    R, Z = np.meshgrid(r, z)
-    base = np.exp(-((R - 0.4 * p.lr) / (0.1 * p.lr)) ** 2 - (Z / (0.1 * p.lz)) ** 2)
-    out = {}
-    for mode in ("cold", "warm"):
-        times, its = [], []
-        phi = torch.zeros(nn, dtype=torch.float64, device="cuda")
-        for k in range(reps):
-            q = (base * 1e-12 * (1 + 0.05 * k) + rng.normal(size=base.shape) * 1e-13).ravel()
-            qd = torch.tensor(q, dtype=torch.float64, device="cuda")
-            if mode == "cold":
-                phi.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = sim.poisson(qd, -500.0, phi)
-            torch.cuda.synchronize()
-            times.append((time.perf_counter() - t0) * 1e3)
-            its.append(st["iterations"])
-        out[mode] = {"ms": float(np.median(times[1:])), "iterations": int(np.median(its[1:])),
-                     "rel_res_target": 1e-8}
+    p = W.preset("ec512x1024_f32").replace(n_per_species=2_000_000, poisson_rtol=1e-8,
+                                           poisson_maxit=500, pc_batch=8)
+    br, bz, sig, parts = W.inputs(p)
+    sim = Simulation(p, br, bz, sig, parts)
+    sim.step(50)
+    log("[bench] poisson: collecting snapshot pairs")
+    Qs, Ps = pc_train.snapshot_pairs(sim, 72, every=2)
+    held_q = Qs[64:].clone()
+    Qs, Ps = Qs[:64], Ps[:64]
+    Qf, Pf = pc_train.field_pairs(sim, 96, seed=250710731)
+    Q = torch.cat([Qs, -Qs, Qf])
+    P = torch.cat([Ps, -Ps, Pf])
+    del Qs, Ps, Qf, Pf
+    log(f"[bench] poisson: training on {Q.shape[0]} pairs for <= {train_seconds:.0f} s")
+    tr = pc_train.train(sim, Q, P, steps=3000, batch=8, lr=1e-3, seed=1,
+                        time_limit=train_seconds)
+    log(f"[bench] poisson: {tr['steps']} steps, loss {tr['loss_first']:.3f} -> "
+        f"{tr['loss_last']:.4f}, {tr['ms_per_step']:.1f} ms/step")
+    del Q, P
+    torch.cuda.empty_cache()
+    out = {"grid": "512x1024", "rtol": 1e-8, "rhs": "held-out charge snapshots",
+           "training": tr}
+    for name, mode in (("mg_cg", W.POISSON_MGCG), ("learned_fcg", W.POISSON_LEARNED)):
+        sim.set_poisson_mode(mode)
+        res = {}
+        for start in ("cold", "warm"):
+            times, its, fb = [], [], 0
+            phi = torch.zeros(p.nodes, dtype=torch.float64, device="cuda")
+            for k in range(reps + 1):
+                q = held_q[k % held_q.shape[0]].contiguous()
+                if start == "cold":
+                    phi.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = sim.poisson(q, 0.0, phi)
+                torch.cuda.synchronize()
+                if k == 0:
+                    continue          # the first solve sets the iteration prediction
+                times.append((time.perf_counter() - t0) * 1e3)
+                its.append(st["iterations"])
+                fb += st["fell_back"]
+            res[start] = {"ms": float(np.median(times)), "iterations": int(np.median(its)),
+                          "fell_back": fb, "solves": reps}
+        out[name] = res
+        log(f"[bench] poisson {name}: {res}")
     sim.close()
-    return {"grid": "512x1024", "method": "MG-PCG (FP32 V-cycle, FP64 refinement)", **out,
-            "learned_pc": None}
+    return out
 
 
 def main():
@@ -118,6 +141,9 @@ def main():
     ap.add_argument("--workload", default="ec256x512_f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-poisson", action="store_true")
+    ap.add_argument("--poisson-only", action="store_true",
+                    help="only the field-solve comparison (prints its JSON)")
+    ap.add_argument("--train-seconds", type=float, default=60.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -129,6 +155,10 @@ def main():
     import torch
     from paper_2507_10727_amd import workloads as W
     from paper_2507_10727_amd.sim import Simulation
+
+    if args.poisson_only:
+        print(json.dumps({"poisson": poisson_bench(args.train_seconds)}), flush=True)
+        return
 
     if args.copy_calibration:
         # a plain device-to-device copy of known size: its FETCH_SIZE /
@@ -188,7 +218,7 @@ def main():
     poisson = None
     if not args.no_poisson:
         log("[bench] poisson 512x1024")
-        poisson = poisson_bench()
+        poisson = poisson_bench(args.train_seconds)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, 1 step)")

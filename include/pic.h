@@ -217,6 +217,12 @@ pic_status pic_step(pic_handle *h, int32_t nsteps);
 pic_status pic_poisson(pic_handle *h, const double *q_dev, double v_cathode, double *phi_dev,
                        pic_poisson_stats *stats);
 
+/* out_dev = K phi_dev: the charge-form field operator of the solve (C per V;
+ * Section 3's Gauss's law over each node's control volume) on unknown nodes,
+ * 0 on Dirichlet nodes; phi_dev's Dirichlet entries are used as given.  FP64
+ * node vectors.  Synchronizes. */
+pic_status pic_apply_operator(pic_handle *h, const double *phi_dev, double *out_dev);
+
 /* FP64 diagnostics of the current state.  Synchronizes. */
 pic_status pic_diag(pic_handle *h, pic_diag_out *out);
 

@@ -126,7 +126,7 @@ EXPORTS = [
     "pic_particles", "pic_fields", "pic_set_phi", "pic_compact", "pic_get_state",
     "pic_set_state", "pic_enable_timers", "pic_get_timers", "pic_free", "pic_last_error",
     "pic_pc_param_count", "pic_pc_set_weights", "pic_pc_get_weights", "pic_pc_train_step",
-    "pic_pc_apply", "pic_set_poisson_mode",
+    "pic_pc_apply", "pic_set_poisson_mode", "pic_apply_operator",
 ]
 
 PIC_MGCG, PIC_LEARNED, PIC_CG = 0, 1, 2
@@ -168,6 +168,7 @@ def load():
                                     C.POINTER(C.c_double), _fp]
     L.pic_pc_apply.argtypes = [H, C.c_void_p, C.c_void_p]
     L.pic_set_poisson_mode.argtypes = [H, C.c_int32]
+    L.pic_apply_operator.argtypes = [H, C.c_void_p, C.c_void_p]
     L.pic_last_error.argtypes = [H]
     L.pic_last_error.restype = C.c_char_p
     for name in EXPORTS:

@@ -1258,6 +1258,16 @@ pic_status pic_get_timers(pic_handle *h, pic_timers *out, int32_t reset)
     return PIC_OK;
 }
 
+pic_status pic_apply_operator(pic_handle *h, const double *phi_dev, double *out_dev)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (!phi_dev || !out_dev) return fail(h, PIC_EINVAL, "phi_dev and out_dev are required");
+    launch_apply_k64(h->f, phi_dev, out_dev, h->stream);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    HIPCHECK(h, hipGetLastError());
+    return PIC_OK;
+}
+
 pic_status pic_pc_param_count(int64_t *n)
 {
     if (!n) return fail(nullptr, PIC_EINVAL, "n is NULL");

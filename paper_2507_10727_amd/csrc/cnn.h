@@ -24,7 +24,7 @@ namespace pic {
 
 constexpr int PC_LAYERS = 15;
 constexpr int PC_LEVELS = 4;
-constexpr int PC_WGRAD_SPLITS = 256;   // pixel ranges of the weight-gradient kernel
+constexpr int PC_WGRAD_SPLITS = 2048;  // most pixel ranges of the weight-gradient kernel
 
 struct PcLayer {
     int32_t cin, cout;          // channels

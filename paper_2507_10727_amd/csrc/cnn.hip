@@ -174,7 +174,7 @@ struct WgradArgs {
     float *partial;             // [gridDim.y][nt * 16][kw]
 };
 
-constexpr int PPW = 8;
+constexpr int PPW = 4;
 
 __global__ void __launch_bounds__(256) k_conv3x3_wgrad(WgradArgs a)
 {
@@ -267,14 +267,17 @@ __global__ void __launch_bounds__(256) k_conv3x3_wgrad(WgradArgs a)
     }
 }
 
+// out[t] += sum over the splits [64 blockIdx.y, 64 blockIdx.y + 64) of
+// partial[split][t] (out zeroed before)
+constexpr int RED_CHUNK = 64;
 __global__ void k_wgrad_reduce(const float *partial, int splits, int64_t n, float *out)
 {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (int k = 0; k < splits; ++k) s += partial[(int64_t)k * n + t];
-        out[t] = s;
-    }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int k0 = blockIdx.y * RED_CHUNK, k1 = min(splits, k0 + RED_CHUNK);
+    float s = 0.0f;
+    for (int k = k0; k < k1; ++k) s += partial[(int64_t)k * n + t];
+    unsafeAtomicAdd(out + t, s);
 }
 
 // ---- pooling and upsampling (NHWC float4 quads) ----------------------------
@@ -719,6 +722,17 @@ void conv(const PcNet &n, int li, bool dgrad, const float *x, const float *skip,
     }
 }
 
+// pair groups (blocks in x) and pixel-range splits (blocks in y, at most)
+int wgrad_groups(const PcLayer &l)
+{
+    const int npairs = l.nt * (l.kw / 16);
+    return (npairs + 4 * PPW - 1) / (4 * PPW);
+}
+int wgrad_splits(const PcLayer &l)
+{
+    return std::max(1, std::min(PC_WGRAD_SPLITS, (2048 + wgrad_groups(l) - 1) / wgrad_groups(l)));
+}
+
 // weight gradient of layer li from its forward input x and output gradient g
 void wgrad(PcNet &n, int li, const float *x, const float *g, int B, hipStream_t s)
 {
@@ -740,17 +754,17 @@ void wgrad(PcNet &n, int li, const float *x, const float *g, int B, hipStream_t 
     a.tiles_x = (a.W + TX - 1) / TX;
     a.tiles_y = (a.H + TR - 1) / TR;
     const int64_t ntiles = (int64_t)B * a.tiles_x * a.tiles_y;
-    const int npairs = l.nt * (l.kw / 16);
-    const int gx = (npairs + 4 * PPW - 1) / (4 * PPW);
-    const int splits = (int)std::min<int64_t>(ntiles, PC_WGRAD_SPLITS);
+    const int gx = wgrad_groups(l);
+    const int splits = (int)std::min<int64_t>(ntiles, wgrad_splits(l));
     a.tiles_per_block = (int)((ntiles + splits - 1) / splits);
     const int gy = (int)((ntiles + a.tiles_per_block - 1) / a.tiles_per_block);
     a.partial = n.partial;
     const int lds = l.cout_p * TR * TX * 2 + l.cin_p * PH * PW * 2;
     hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(gx, gy), dim3(256), lds, s, a);
     const int64_t ne = (int64_t)l.nt * 16 * l.kw;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(eblocks(ne)), dim3(EB), 0, s, (const float *)n.partial,
-                       gy, ne, n.grad + l.o_master);
+    launch_zero(n.grad + l.o_master, ne * 4, s);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((ne + EB - 1) / EB), (gy + RED_CHUNK - 1) / RED_CHUNK),
+                       dim3(EB), 0, s, (const float *)n.partial, gy, ne, n.grad + l.o_master);
 }
 
 void pool(const PcNet &n, int level, const float *x, float *y, int C_p, int B, hipStream_t s)
@@ -918,7 +932,7 @@ int64_t pc_carve(PcNet &n, char *base)
         nbias += l.cout_p;
         nwf += (int64_t)l.nt * 16 * l.kpad;
         nwt += (int64_t)l.nt_t * 16 * l.kpad_t;
-        npart = std::max<int64_t>(npart, (int64_t)PC_WGRAD_SPLITS * l.nt * 16 * l.kw);
+        npart = std::max<int64_t>(npart, (int64_t)wgrad_splits(l) * l.nt * 16 * l.kw);
     }
     n.master = c.take<float>(n.n_master);
     n.grad = c.take<float>(n.n_master);
@@ -1047,7 +1061,7 @@ void sandwich(PcNet &n, const MGLevel &L, double inv_nunk, const float *r, float
               const float *q, double *rz, double *zq, double *ss, hipStream_t s)
 {
     const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
-    const dim3 g(std::min(eblocks(nn), 160), 1);
+    const dim3 g(std::min(eblocks((nn + 1) / 2), 1024), 1);
     const float *nf = nullptr;
     double *nd = nullptr;
     hipLaunchKernelGGL(k_rb_sweep, g, dim3(EB), 0, s, L, r, n.vx, nn, 0, 1, nf, nf, nd, nd);
@@ -1085,7 +1099,7 @@ void pc_apply64(PcNet &n, const MGLevel &L, int64_t n_unknown, const double *r, 
 void pc_identity32(const MGLevel &L, const float *r, float *z, double *rz, hipStream_t s)
 {
     const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
-    hipLaunchKernelGGL(k_pc_identity, dim3(std::min(eblocks(nn), 160)), dim3(EB), 0, s, L, r, z, rz);
+    hipLaunchKernelGGL(k_pc_identity, dim3(std::min(eblocks((nn + 1) / 2), 1024)), dim3(EB), 0, s, L, r, z, rz);
 }
 
 // ---- training -------------------------------------------------------------------------
@@ -1097,7 +1111,7 @@ void pc_train_enqueue(PcNet &n, const MGLevel &L, int64_t n_unknown, const doubl
     const double inv = n_unknown > 0 ? 1.0 / (double)n_unknown : 0.0;
     double *ss0 = n.scal, *ss1 = n.scal + B, *den = n.scal + 2 * B, *loss = n.scal + 3 * B;
     launch_zero(n.scal, 4 * (int64_t)B * 8, s);
-    const dim3 gb(std::min(eblocks(nn), 160), B);
+    const dim3 gb(std::min(eblocks((nn + 1) / 2), 1024), B);
     const float *nf = nullptr;
     double *nd = nullptr;
     hipLaunchKernelGGL(k_pc_sumsq<double>, gb, dim3(EB), 0, s, q, nn, inv_2pi_eps0, L, ss0);

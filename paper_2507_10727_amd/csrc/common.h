@@ -311,6 +311,8 @@ void launch_zero(void *p, int64_t bytes, hipStream_t s);
 template <typename T>
 void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const T *q1,
                        DevScalars *sc, hipStream_t s);
+// out = K phi on unknown nodes, 0 on Dirichlet nodes (FP64)
+void launch_apply_k64(const FieldDev &f, const double *phi, double *out, hipStream_t s);
 // r32 = r64 / ||r64|| (norm read on the device), e32 = 0
 void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s);
 // phi += e32 ||r64|| / (2 pi eps0) on unknown nodes

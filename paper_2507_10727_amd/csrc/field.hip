@@ -88,6 +88,26 @@ __global__ void __launch_bounds__(FB) k_residual64(int32_t nr, int32_t nz, const
     }
 }
 
+// out = K phi on unknown nodes (charge form, C), 0 on Dirichlet nodes
+__global__ void __launch_bounds__(FB) k_apply_k64(int32_t nr, int32_t nz, const double *ce,
+                                                  const double *cn, const uint8_t *kind,
+                                                  const double *phi, double *out)
+{
+    const int ld = nr + 1;
+    const int64_t nn = (int64_t)ld * (nz + 1);
+    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
+        if (kind[n] != 0) { out[n] = 0.0; continue; }
+        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        const double p = phi[n];
+        double flux = 0.0;
+        if (i < nr) flux += ce[n] * (p - phi[n + 1]);
+        if (i > 0) flux += ce[n - 1] * (p - phi[n - 1]);
+        if (j < nz) flux += cn[n] * (p - phi[n + ld]);
+        if (j > 0) flux += cn[n - ld] * (p - phi[n - ld]);
+        out[n] = flux;
+    }
+}
+
 __global__ void k_cast_scale(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32)
 {
     const double rr = sc->res_rr;
@@ -268,8 +288,15 @@ void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const 
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     launch_zero(&sc->res_rr, 2 * sizeof(double), s);
-    hipLaunchKernelGGL((k_residual64<T>), dim3(blocks_for(nn, 160)), dim3(FB), 0, s, f.nr, f.nz,
+    hipLaunchKernelGGL((k_residual64<T>), dim3(blocks_for((nn + 1) / 2, 1024)), dim3(FB), 0, s, f.nr, f.nz,
                        f.ce64, f.cn64, f.kind, phi, q0, q1, f.r64, sc);
+}
+
+void launch_apply_k64(const FieldDev &f, const double *phi, double *out, hipStream_t s)
+{
+    const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
+    hipLaunchKernelGGL(k_apply_k64, dim3(blocks_for(nn)), dim3(FB), 0, s, f.nr, f.nz, f.ce64,
+                       f.cn64, f.kind, phi, out);
 }
 
 void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s)

@@ -386,7 +386,8 @@ __global__ void __launch_bounds__(CB) k_cg_update(int64_t nn, const float *p, co
 inline int cg_blocks(int64_t n)
 {
     int64_t b = (n + CB - 1) / CB;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 160));
+    // about two nodes per thread: enough waves for every CU, few FP64 atomics
+    return (int)std::max<int64_t>(1, std::min<int64_t>((b + 1) / 2, 1024));
 }
 
 }  // namespace

@@ -181,6 +181,12 @@ class Simulation:
         L.check(self.lib.pic_pc_apply(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr())),
                 self.h)
 
+    def apply_operator(self, phi, out):
+        """out = K phi (device float64 tensors)."""
+        self.torch.cuda.synchronize(self.device)
+        L.check(self.lib.pic_apply_operator(self.h, C.c_void_p(phi.data_ptr()),
+                                            C.c_void_p(out.data_ptr())), self.h)
+
     def set_poisson_mode(self, mode):
         L.check(self.lib.pic_set_poisson_mode(self.h, int(mode)), self.h)
 

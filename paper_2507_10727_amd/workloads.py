@@ -143,6 +143,30 @@ class Problem:
 # Presets (synthetic stand-ins in the paper's regime)
 # ---------------------------------------------------------------------------
 
+def unknown_mask(p: Problem) -> np.ndarray:
+    """True on the nodes the field solve determines: all but the anode row
+    (j = nz), the outer column (i = nr) and the cathode nodes of z = 0
+    (r < cathode_rmax).  Node-major (j * (nr + 1) + i)."""
+    j, i = np.divmod(np.arange(p.nodes), p.nr + 1)
+    dirichlet = (j == p.nz) | (i == p.nr) | ((j == 0) & (i * (p.lr / p.nr) < p.cathode_rmax))
+    return ~dirichlet
+
+
+def random_potentials(p: Problem, n: int, seed: int) -> list:
+    """Random potentials: white noise smoothed by a Gaussian of 0.7 to 24
+    cells (cycling through six scales), unit rms, zero on Dirichlet nodes."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    unk = unknown_mask(p)
+    out = []
+    for k in range(n):
+        s = (0.7, 1.5, 3.0, 6.0, 12.0, 24.0)[k % 6]
+        f = gaussian_filter(rng.normal(size=(p.nz + 1, p.nr + 1)), s).ravel()
+        f = np.where(unk, f, 0.0)
+        out.append(f / np.sqrt(np.mean(f[unk] ** 2)))
+    return out
+
+
 def preset(name: str) -> Problem:
     """Named workloads.
 

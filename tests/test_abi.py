@@ -4,6 +4,8 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2507_10727_amd import _lib as L
@@ -93,3 +95,16 @@ def test_learned_preconditioner_sizes():
     m = C.c_int64()
     assert lib.pic_query_workspace(C.byref(cfg), C.byref(m)) == 0
     assert m.value - base.value == sizes[0]
+
+
+@pytest.mark.parametrize("rmax", [None, 0.6])
+def test_unknown_mask_matches_oracle(rmax):
+    from oracle_helpers import make_oracle, zero_field_problem
+    kw = dict(nr=12, nz=9, lr=0.012, lz=0.009)
+    if rmax is not None:
+        kw["cathode_rmax"] = rmax * 0.012
+    p = zero_field_problem(**kw)
+    o = make_oracle(p)
+    assert np.array_equal(W.unknown_mask(p), o.node_kind() == 0)
+    f = W.random_potentials(p, 3, 1)
+    assert all(np.all(x[~W.unknown_mask(p)] == 0) for x in f)
