@@ -63,6 +63,7 @@ enum { PIC_MGCG = 0, PIC_LEARNED = 1, PIC_CG = 2 }; /* field-solve preconditione
                                    multigrid, learned network, none       */
 
 typedef struct pic_handle pic_handle;         /* opaque, library-owned */
+typedef struct pic_ensemble pic_ensemble;     /* opaque, library-owned */
 
 /* Problem definition.  Host arrays are read during pic_init only. */
 typedef struct pic_config {
@@ -288,6 +289,27 @@ pic_status pic_pc_apply(pic_handle *h, const double *r_dev, double *z_dev);
 
 /* Switch the preconditioner of later solves (PIC_LEARNED needs weights). */
 pic_status pic_set_poisson_mode(pic_handle *h, int32_t mode);
+
+/* ---- ensembles of independent discharges -----------------------------------
+ * Many runs (each created by pic_init, with its own grid, particles,
+ * secondary yield and circuit; Section 4's study varies the yield and the
+ * external resistance) advance together: one step of every run is captured
+ * once into a hipGraph, its runs spread over nstreams streams, and replayed
+ * each step as a single launch, with one synchronization per step for the
+ * runs' status.  Inside the graph each field solve is multigrid-
+ * preconditioned and controlled on the device (its passes stop once the
+ * FP64 residual meets poisson_rtol, at most three passes), so a run advances
+ * exactly as pic_step would to within the solve tolerance.  The runs must
+ * share sort_every and their step phase, have timers off, and are not used
+ * through other calls while pic_ensemble_step runs.  The library owns the
+ * streams, graphs and a small pinned status buffer; stream (nullable) is
+ * where the graph launches.  Errors of pic_ensemble_step name the run:
+ * PIC_ECAPACITY, PIC_ENOCONV, PIC_EHIP. */
+pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *stream,
+                               int32_t nstreams, pic_ensemble **out);
+pic_status pic_ensemble_step(pic_ensemble *e, int32_t nsteps);
+pic_status pic_ensemble_free(pic_ensemble *e);
+const char *pic_ensemble_last_error(const pic_ensemble *e);
 
 /* Destroy the handle (does not free the caller's workspace). */
 pic_status pic_free(pic_handle *h);

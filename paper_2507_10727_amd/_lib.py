@@ -127,6 +127,7 @@ EXPORTS = [
     "pic_set_state", "pic_enable_timers", "pic_get_timers", "pic_free", "pic_last_error",
     "pic_pc_param_count", "pic_pc_set_weights", "pic_pc_get_weights", "pic_pc_train_step",
     "pic_pc_apply", "pic_set_poisson_mode", "pic_apply_operator",
+    "pic_ensemble_create", "pic_ensemble_step", "pic_ensemble_free", "pic_ensemble_last_error",
 ]
 
 PIC_MGCG, PIC_LEARNED, PIC_CG = 0, 1, 2
@@ -169,10 +170,16 @@ def load():
     L.pic_pc_apply.argtypes = [H, C.c_void_p, C.c_void_p]
     L.pic_set_poisson_mode.argtypes = [H, C.c_int32]
     L.pic_apply_operator.argtypes = [H, C.c_void_p, C.c_void_p]
+    L.pic_ensemble_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_int32,
+                                      C.POINTER(C.c_void_p)]
+    L.pic_ensemble_step.argtypes = [C.c_void_p, C.c_int32]
+    L.pic_ensemble_free.argtypes = [C.c_void_p]
+    L.pic_ensemble_last_error.argtypes = [C.c_void_p]
+    L.pic_ensemble_last_error.restype = C.c_char_p
     L.pic_last_error.argtypes = [H]
     L.pic_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name != "pic_last_error":
+        if name not in ("pic_last_error", "pic_ensemble_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L

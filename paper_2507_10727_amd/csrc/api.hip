@@ -532,7 +532,7 @@ void enqueue_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_it
     const MGHier &H = f.mg;
     const double inv_2pi_eps0 = 1.0 / (2.0 * 3.14159265358979323846 * eps0());
     launch_cast_scale(f, h->sc, s);
-    launch_zero(h->sc->pcg_rz, sizeof(double) * 5 * (MAX_PCG + 2), s);
+    launch_zero_gated(h->sc->pcg_rz, sizeof(double) * 5 * (MAX_PCG + 2), f.gate, s);
     const double *zq = (mode == PIC_LEARNED) ? h->sc->pcg_zq : nullptr;
     enqueue_precond(h, mode, 0);
     for (int k = 0; k < n_iter; ++k) {
@@ -844,11 +844,13 @@ pic_status field_update(pic_handle *h)
     return PIC_OK;
 }
 
+// Particle phase of a step: begin (clear tallies and node charge), push
+// (gather, Boris, walls, candidate queues, deposit), events (collisions,
+// emission), children (ids, append, deposit), finalize (counts).
 template <typename T>
-pic_status step_one(pic_handle *h)
+void particle_phase(pic_handle *h)
 {
     const pic_config &c = h->cfg;
-    if (h->steps_since_sort >= c.sort_every) sort_all<T>(h);
     const int64_t nodes = (int64_t)(c.nr + 1) * (c.nz + 1);
     launch_begin_step(h->sc, h->q[0], h->q[1], nodes, (int)sizeof(T), h->stream);
     hipEvent_t ev[2];
@@ -882,6 +884,14 @@ pic_status step_one(pic_handle *h)
     launch_children<T>(C, h->stream);
     launch_finalize_step(h->sc, h->cap, h->stream);
     timer_end(h, 1, ev);
+}
+
+template <typename T>
+pic_status step_one(pic_handle *h)
+{
+    const pic_config &c = h->cfg;
+    if (h->steps_since_sort >= c.sort_every) sort_all<T>(h);
+    particle_phase<T>(h);
     h->steps_since_sort++;
     if (c.field_solve) {
         pic_status st = field_update<T>(h);
@@ -899,6 +909,63 @@ pic_status step_one(pic_handle *h)
         return PIC_OK;
     }
     return check_flags(h);
+}
+
+// ---- a step with no host synchronization (for graph capture) ---------------
+void set_gate(pic_handle *h, const int32_t *g)
+{
+    h->f.gate = g;
+    for (int l = 0; l < MAX_LEVELS; ++l) {
+        h->f.mg.lv[l].gate = g;
+        h->f.mg.tail.L[l].gate = g;
+    }
+}
+
+// Field solve whose passes are controlled on the device: after the first
+// residual, up to three multigrid-preconditioned passes, each skipped once
+// the FP64 residual meets the tolerance (their kernels return at once).  The
+// pass lengths come from the handle's measured convergence rate: the first
+// for the usual starting residual, the others for a full FP32 pass.
+template <typename Q>
+void solve_gated(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_cathode)
+{
+    hipStream_t s = h->stream;
+    FieldDev &f = h->f;
+    const double rtol = h->cfg.poisson_rtol;
+    launch_set_dirichlet(f, phi, v_cathode, s);
+    launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
+    launch_solve_init(f, phi, h->sc, rtol, s);
+    auto iters = [&](double target) {
+        const int n = (int)std::ceil(std::log(target) / std::log(h->rho));
+        return std::max(1, std::min(n, 64));
+    };
+    const int n0 = iters(std::max(0.5 * rtol / h->rel0_est, 1e-6));
+    const int n1 = iters(1e-6);
+    set_gate(h, &h->sc->solve_done);
+    for (int p = 0; p < 3; ++p) {
+        const int n = p == 0 ? n0 : n1;
+        enqueue_pass<Q>(h, phi, q0, q1, n, PIC_MGCG);
+        launch_solve_gate(h->sc, rtol, n, s);
+    }
+    set_gate(h, nullptr);
+}
+
+template <typename T>
+void step_enqueue(pic_handle *h, bool do_sort)
+{
+    const pic_config &c = h->cfg;
+    if (do_sort) sort_all<T>(h);
+    particle_phase<T>(h);
+    if (c.field_solve) {
+        launch_extrapolate(h->f, 0, h->stream);
+        solve_gated<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0);
+        launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, c.circuit,
+                          c.v_fixed, c.v_ext, c.r_ext, c.dt, c.extra_current * c.dt, h->stream);
+        launch_field_prep<T>(h->f, (typename Vec4<T>::type *)h->node, h->sc, c.scheme, 0, h->stream);
+    } else if (c.extra_current != 0.0) {
+        launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, PIC_FIXED_V, 0.0,
+                          0.0, 1.0, c.dt, c.extra_current * c.dt, h->stream);
+    }
 }
 
 template <typename T>
@@ -1009,6 +1076,156 @@ pic_status init_typed(pic_handle *h, const pic_species_host *init)
     HIPCHECK(h, hipStreamSynchronize(s));
     h->steps_since_sort = 0;
     return check_flags(h);
+}
+
+// ---- ensembles ---------------------------------------------------------------
+struct EnsembleStatus {
+    double rr, bb, rr0;
+    int32_t flags, pad;
+    int64_t count[2];
+    int32_t solve_done, solve_passes, solve_iters, solve_pad;
+};
+
+}  // namespace
+
+struct pic_ensemble {
+    std::vector<pic_handle *> runs;
+    hipStream_t s0 = nullptr;
+    bool own_s0 = false;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;     // fork + one join per stream
+    EnsembleStatus *status = nullptr;   // pinned host memory, one per run
+    struct G {
+        int sort, cur0, cur1;
+        hipGraphExec_t exec;
+    };
+    std::vector<G> graphs;
+    std::vector<int64_t> captured;      // particles per run when the graphs were captured
+    std::string err;
+};
+
+namespace {
+
+pic_status efail(pic_ensemble *e, pic_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (e) e->err = buf;
+    else g_init_error = buf;
+    return st;
+}
+
+#define EHIPCHECK(e, call)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return efail((e), PIC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+void drop_ensemble_graphs(pic_ensemble *e)
+{
+    for (auto &g : e->graphs) (void)hipGraphExecDestroy(g.exec);
+    e->graphs.clear();
+}
+
+// Capture one step of every run, each run on one of the ensemble's streams
+// (round robin), with the status copy of each run at its end.
+pic_status capture_ensemble(pic_ensemble *e, bool do_sort, hipGraphExec_t *out)
+{
+    const int ns = (int)e->streams.size();
+    std::vector<int> cur0, cur1, since;
+    for (pic_handle *h : e->runs) {
+        cur0.push_back(h->cur[0]);
+        cur1.push_back(h->cur[1]);
+        since.push_back(h->steps_since_sort);
+    }
+    EHIPCHECK(e, hipStreamBeginCapture(e->s0, hipStreamCaptureModeThreadLocal));
+    (void)hipEventRecord(e->events[0], e->s0);
+    for (int k = 0; k < ns; ++k) (void)hipStreamWaitEvent(e->streams[k], e->events[0], 0);
+    for (size_t r = 0; r < e->runs.size(); ++r) {
+        pic_handle *h = e->runs[r];
+        hipStream_t saved = h->stream;
+        h->stream = e->streams[r % ns];
+        if (h->prec == PIC_F64) step_enqueue<double>(h, do_sort);
+        else step_enqueue<float>(h, do_sort);
+        (void)hipMemcpyAsync(&e->status[r], &h->sc->res_rr, 48, hipMemcpyDeviceToHost, h->stream);
+        (void)hipMemcpyAsync(&e->status[r].solve_done, &h->sc->solve_done, 16,
+                             hipMemcpyDeviceToHost, h->stream);
+        h->stream = saved;
+    }
+    for (int k = 0; k < ns; ++k) {
+        (void)hipEventRecord(e->events[1 + k], e->streams[k]);
+        (void)hipStreamWaitEvent(e->s0, e->events[1 + k], 0);
+    }
+    hipGraph_t graph;
+    const hipError_t ec = hipStreamEndCapture(e->s0, &graph);
+    // the capture ran nothing: restore the host-side particle-buffer state
+    for (size_t r = 0; r < e->runs.size(); ++r) {
+        e->runs[r]->cur[0] = cur0[r];
+        e->runs[r]->cur[1] = cur1[r];
+        e->runs[r]->steps_since_sort = since[r];
+    }
+    if (ec != hipSuccess)
+        return efail(e, PIC_EHIP, "capture of the ensemble step failed: %s", hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess)
+        return efail(e, PIC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    return PIC_OK;
+}
+
+pic_status ensemble_step(pic_ensemble *e)
+{
+    pic_handle *h0 = e->runs[0];
+    const bool do_sort = h0->steps_since_sort >= h0->cfg.sort_every;
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : e->graphs)
+        if (g.sort == (int)do_sort && g.cur0 == h0->cur[0] && g.cur1 == h0->cur[1]) exec = g.exec;
+    if (!exec) {
+        pic_status st = capture_ensemble(e, do_sort, &exec);
+        if (st != PIC_OK) return st;
+        e->graphs.push_back({(int)do_sort, h0->cur[0], h0->cur[1], exec});
+        e->captured.clear();
+        for (pic_handle *h : e->runs) e->captured.push_back(h->host_count[0] + h->host_count[1]);
+    }
+    // work a run's own stream still holds goes first
+    for (pic_handle *h : e->runs) EHIPCHECK(e, hipStreamSynchronize(h->stream));
+    EHIPCHECK(e, hipGraphLaunch(exec, e->s0));
+    EHIPCHECK(e, hipStreamSynchronize(e->s0));
+    bool drift = false;
+    for (size_t r = 0; r < e->runs.size(); ++r) {
+        pic_handle *h = e->runs[r];
+        const EnsembleStatus &S = e->status[r];
+        if (do_sort) {
+            h->cur[0] = 1 - h->cur[0];
+            h->cur[1] = 1 - h->cur[1];
+            h->steps_since_sort = 0;
+        }
+        h->steps_since_sort++;
+        h->host_count[0] = S.count[0];
+        h->host_count[1] = S.count[1];
+        h->host_flags = S.flags;
+        pic_poisson_stats P = {};
+        P.iterations = S.solve_iters;
+        P.outer = S.solve_passes;
+        P.rel_res = S.bb > 0.0 ? std::sqrt(S.rr / S.bb) : 0.0;
+        P.converged = S.solve_done;
+        h->last = P;
+        if (S.flags & (FLAG_CAPACITY | FLAG_CHILD_OVERFLOW))
+            return efail(e, PIC_ECAPACITY, "run %zu: particle capacity exceeded (flags %d)", r,
+                         S.flags);
+        if (h->cfg.field_solve && !S.solve_done)
+            return efail(e, PIC_ENOCONV, "run %zu: field solve stopped at relative residual %.3e",
+                         r, P.rel_res);
+        const int64_t n = S.count[0] + S.count[1], c = e->captured[r];
+        if (std::llabs(n - c) > std::max<int64_t>(c / 5, 1024)) drift = true;
+    }
+    // the push launches split their blocks by the counts seen at capture
+    if (drift) drop_ensemble_graphs(e);
+    return PIC_OK;
 }
 
 }  // namespace
@@ -1358,6 +1575,86 @@ pic_status pic_set_poisson_mode(pic_handle *h, int32_t mode)
         return fail(h, PIC_ESTATE, "no learned-preconditioner buffers (pc_batch = 0)");
     h->pmode = mode;
     return PIC_OK;
+}
+
+pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *stream,
+                               int32_t nstreams, pic_ensemble **out)
+{
+    if (!out) return efail(nullptr, PIC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!runs || nruns < 1) return efail(nullptr, PIC_EINVAL, "no runs");
+    if (nstreams < 1 || nstreams > 16) return efail(nullptr, PIC_EINVAL, "nstreams outside [1, 16]");
+    for (int r = 0; r < nruns; ++r) {
+        const pic_handle *h = runs[r];
+        if (!h) return efail(nullptr, PIC_EINVAL, "run %d is NULL", r);
+        for (int q = 0; q < r; ++q)
+            if (runs[q] == h) return efail(nullptr, PIC_EINVAL, "run %d appears twice", r);
+        if (h->cfg.sort_every != runs[0]->cfg.sort_every ||
+            h->steps_since_sort != runs[0]->steps_since_sort || h->cur[0] != runs[0]->cur[0] ||
+            h->cur[1] != runs[0]->cur[1])
+            return efail(nullptr, PIC_EINVAL,
+                         "run %d: every run must share sort_every and its sort phase", r);
+        if (h->timers_on) return efail(nullptr, PIC_EINVAL, "run %d: timers must be off", r);
+    }
+    pic_ensemble *e = new pic_ensemble();
+    e->runs.assign(runs, runs + nruns);
+    if (stream) {
+        e->s0 = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&e->s0, hipStreamNonBlocking) != hipSuccess) {
+            delete e;
+            return efail(nullptr, PIC_EHIP, "cannot create a stream");
+        }
+        e->own_s0 = true;
+    }
+    e->streams.resize(nstreams);
+    e->events.resize(nstreams + 1);
+    bool ok = true;
+    for (auto &s : e->streams) ok &= hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    for (auto &v : e->events)
+        ok &= hipEventCreateWithFlags(&v, hipEventDisableTiming) == hipSuccess;
+    ok &= hipHostMalloc((void **)&e->status, sizeof(EnsembleStatus) * nruns) == hipSuccess;
+    if (!ok) {
+        pic_ensemble_free(e);
+        return efail(nullptr, PIC_EHIP, "cannot create the ensemble's streams or status buffer");
+    }
+    memset(e->status, 0, sizeof(EnsembleStatus) * nruns);
+    // every run's own stream must be idle before its work moves to the ensemble
+    for (pic_handle *h : e->runs) (void)hipStreamSynchronize(h->stream);
+    *out = e;
+    return PIC_OK;
+}
+
+pic_status pic_ensemble_step(pic_ensemble *e, int32_t nsteps)
+{
+    if (!e) return efail(nullptr, PIC_EINVAL, "ensemble is NULL");
+    if (nsteps < 0) return efail(e, PIC_EINVAL, "nsteps < 0");
+    for (int k = 0; k < nsteps; ++k) {
+        pic_status st = ensemble_step(e);
+        if (st != PIC_OK) return st;
+    }
+    return PIC_OK;
+}
+
+pic_status pic_ensemble_free(pic_ensemble *e)
+{
+    if (!e) return PIC_OK;
+    if (e->s0) (void)hipStreamSynchronize(e->s0);
+    drop_ensemble_graphs(e);
+    for (auto &s : e->streams)
+        if (s) (void)hipStreamDestroy(s);
+    for (auto &v : e->events)
+        if (v) (void)hipEventDestroy(v);
+    if (e->status) (void)hipHostFree(e->status);
+    if (e->own_s0 && e->s0) (void)hipStreamDestroy(e->s0);
+    delete e;
+    return PIC_OK;
+}
+
+const char *pic_ensemble_last_error(const pic_ensemble *e)
+{
+    if (!e) return g_init_error.c_str();
+    return e->err.c_str();
 }
 
 pic_status pic_free(pic_handle *h)

@@ -56,6 +56,9 @@ struct DevScalars {
     double pcg_rz[MAX_PCG + 2], pcg_pq[MAX_PCG + 2], pcg_rr[MAX_PCG + 2];
     double pcg_zq[MAX_PCG + 2];     // z_k . q_{k-1} (flexible CG)
     double pcg_ss[MAX_PCG + 2];     // sum r^2 of each learned-preconditioner input
+    // device-controlled solve of a captured step: done flag (gates the pass
+    // kernels), passes and iterations run
+    int32_t solve_done, solve_passes, solve_iters, solve_pad;
 };
 
 template <typename T>
@@ -231,6 +234,7 @@ struct MGLevel {
     float *b;                   // right-hand side
     float *xd;                  // correction after pre-smoothing (down pass)
     float *xu;                  // correction after post-smoothing (up pass)
+    const int32_t *gate;        // when set and nonzero, the kernels return at once
 };
 
 // Matrix-free operator of a level, divided by 2 pi eps0: east face (i+1/2, j)
@@ -305,9 +309,16 @@ struct FieldDev {
     MGHier mg;                  // r32 = mg.lv[0].b, z32 = mg.lv[0].xu
     const double *b_r, *b_z;    // static nodal B
     const double *vdep;         // node volumes for densities
+    const int32_t *gate;        // when set and nonzero, the solve's kernels return at once
 };
 
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
+void launch_zero_gated(void *p, int64_t bytes, const int32_t *gate, hipStream_t s);
+// captured-solve control: done = (bb == 0 or rr <= rtol^2 bb) after the first
+// residual (zeroing phi's unknowns when bb == 0); after each pass that ran,
+// passes += 1, iters += n_iter, done updated
+void launch_solve_init(const FieldDev &f, double *phi, DevScalars *sc, double rtol, hipStream_t s);
+void launch_solve_gate(DevScalars *sc, double rtol, int n_iter, hipStream_t s);
 template <typename T>
 void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const T *q1,
                        DevScalars *sc, hipStream_t s);

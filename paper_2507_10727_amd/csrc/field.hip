@@ -38,8 +38,9 @@ __device__ __forceinline__ double block_sum(double v, double *buf)
     return t;   // valid in thread 0
 }
 
-__global__ void k_zero(uint32_t *p, int64_t words)
+__global__ void k_zero(uint32_t *p, int64_t words, const int32_t *gate)
 {
+    if (gate && *gate) return;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words;
          k += (int64_t)gridDim.x * blockDim.x)
         p[k] = 0u;
@@ -59,8 +60,10 @@ template <typename T>
 __global__ void __launch_bounds__(FB) k_residual64(int32_t nr, int32_t nz, const double *ce,
                                                    const double *cn, const uint8_t *kind,
                                                    const double *phi, const T *q0, const T *q1,
-                                                   double *r64, DevScalars *sc)
+                                                   double *r64, DevScalars *sc,
+                                                   const int32_t *gate)
 {
+    if (gate && *gate) return;
     __shared__ double buf[FB / 64];
     const int ld = nr + 1;
     const int64_t nn = (int64_t)ld * (nz + 1);
@@ -108,8 +111,10 @@ __global__ void __launch_bounds__(FB) k_apply_k64(int32_t nr, int32_t nz, const 
     }
 }
 
-__global__ void k_cast_scale(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32)
+__global__ void k_cast_scale(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32,
+                             const int32_t *gate)
 {
+    if (gate && *gate) return;
     const double rr = sc->res_rr;
     const double scale = (rr > 0.0) ? 1.0 / sqrt(rr) : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) sc->res_rr0 = rr;
@@ -120,8 +125,9 @@ __global__ void k_cast_scale(int64_t nn, const double *r64, DevScalars *sc, floa
 }
 
 __global__ void k_update64(int64_t nn, const uint8_t *kind, double *phi, const float *e32,
-                           const DevScalars *sc, double inv_2pi_eps0)
+                           const DevScalars *sc, double inv_2pi_eps0, const int32_t *gate)
 {
+    if (gate && *gate) return;
     const double scale = sqrt(sc->res_rr0) * inv_2pi_eps0;
     for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB)
         if (kind[n] == 0) phi[n] += (double)e32[n] * scale;
@@ -279,7 +285,54 @@ __global__ void k_count_live(const int32_t *key, const DevScalars *sc, int speci
 void launch_zero(void *p, int64_t bytes, hipStream_t s)
 {
     const int64_t words = (bytes + 3) / 4;
-    hipLaunchKernelGGL(k_zero, dim3(blocks_for(words, 2048)), dim3(FB), 0, s, (uint32_t *)p, words);
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(words, 2048)), dim3(FB), 0, s, (uint32_t *)p, words,
+                       (const int32_t *)nullptr);
+}
+
+void launch_zero_gated(void *p, int64_t bytes, const int32_t *gate, hipStream_t s)
+{
+    const int64_t words = (bytes + 3) / 4;
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(words, 2048)), dim3(FB), 0, s, (uint32_t *)p, words,
+                       gate);
+}
+
+__global__ void k_solve_init(DevScalars *sc, double rtol2)
+{
+    if (threadIdx.x != 0) return;
+    const double rr = sc->res_rr, bb = sc->res_bb;
+    sc->solve_done = (bb == 0.0 || rr <= rtol2 * bb) ? 1 : 0;
+    sc->solve_passes = 0;
+    sc->solve_iters = 0;
+}
+
+__global__ void k_zero_unknowns_if_empty(int64_t nn, const uint8_t *kind, double *phi,
+                                         const DevScalars *sc)
+{
+    if (sc->res_bb != 0.0) return;
+    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB)
+        if (kind[n] == 0) phi[n] = 0.0;
+}
+
+__global__ void k_solve_gate(DevScalars *sc, double rtol2, int n_iter)
+{
+    if (threadIdx.x != 0 || sc->solve_done) return;
+    sc->solve_passes += 1;
+    sc->solve_iters += n_iter;
+    const double rr = sc->res_rr, bb = sc->res_bb;
+    sc->solve_done = (bb == 0.0 || rr <= rtol2 * bb) ? 1 : 0;
+}
+
+void launch_solve_init(const FieldDev &f, double *phi, DevScalars *sc, double rtol, hipStream_t s)
+{
+    const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
+    hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, s, sc, rtol * rtol);
+    hipLaunchKernelGGL(k_zero_unknowns_if_empty, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.kind,
+                       phi, (const DevScalars *)sc);
+}
+
+void launch_solve_gate(DevScalars *sc, double rtol, int n_iter, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_solve_gate, dim3(1), dim3(64), 0, s, sc, rtol * rtol, n_iter);
 }
 
 template <typename T>
@@ -287,9 +340,9 @@ void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const 
                        DevScalars *sc, hipStream_t s)
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
-    launch_zero(&sc->res_rr, 2 * sizeof(double), s);
-    hipLaunchKernelGGL((k_residual64<T>), dim3(blocks_for((nn + 1) / 2, 1024)), dim3(FB), 0, s, f.nr, f.nz,
-                       f.ce64, f.cn64, f.kind, phi, q0, q1, f.r64, sc);
+    launch_zero_gated(&sc->res_rr, 2 * sizeof(double), f.gate, s);
+    hipLaunchKernelGGL((k_residual64<T>), dim3(blocks_for((nn + 1) / 2, 1024)), dim3(FB), 0, s, f.nr,
+                       f.nz, f.ce64, f.cn64, f.kind, phi, q0, q1, f.r64, sc, f.gate);
 }
 
 void launch_apply_k64(const FieldDev &f, const double *phi, double *out, hipStream_t s)
@@ -303,7 +356,7 @@ void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s)
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     hipLaunchKernelGGL(k_cast_scale, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.r64, sc,
-                       f.mg.lv[0].b, f.e32);
+                       f.mg.lv[0].b, f.e32, f.gate);
 }
 
 void launch_update64(const FieldDev &f, double *phi, const DevScalars *sc, double inv_2pi_eps0,
@@ -311,7 +364,7 @@ void launch_update64(const FieldDev &f, double *phi, const DevScalars *sc, doubl
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     hipLaunchKernelGGL(k_update64, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.kind, phi, f.e32,
-                       sc, inv_2pi_eps0);
+                       sc, inv_2pi_eps0, f.gate);
 }
 
 template <typename T>

@@ -44,6 +44,7 @@ constexpr int ULW = UTX + 4, ULH = UTY + 4;
 // right-hand side; writes the smoothed F.xd and the coarse C.b.
 __global__ void __launch_bounds__(256) k_mg_down(MGLevel F, MGLevel C)
 {
+    if (F.gate && *F.gate) return;
     __shared__ float sb[DLH][DLW];
     __shared__ float sx[DLH][DLW];
     const int I0 = blockIdx.x * DTX, J0 = blockIdx.y * DTY;
@@ -119,6 +120,7 @@ __global__ void __launch_bounds__(256) k_mg_down(MGLevel F, MGLevel C)
 // tile and, if dot != null, accumulates sum(b * x) over it.
 __global__ void __launch_bounds__(256) k_mg_up(MGLevel F, MGLevel C, double *dot)
 {
+    if (F.gate && *F.gate) return;
     __shared__ float sb[ULH][ULW];
     __shared__ float sx[ULH][ULW];
     __shared__ double red[4];
@@ -203,6 +205,7 @@ __device__ __forceinline__ void tail_sweep(const MGLevel &L, float *x, const flo
 
 __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
 {
+    if (T.L[T.first].gate && *T.L[T.first].gate) return;
     extern __shared__ float sm[];
     float *tmp = sm;
 #define X(l) (sm + T.offx[(l)])
@@ -321,6 +324,7 @@ __global__ void __launch_bounds__(CB) k_cg_matvec(MGLevel L, const float *z, con
                                                   float *pc, float *q, const double *rz, int k,
                                                   double *pq, const double *zq)
 {
+    if (L.gate && *L.gate) return;
     __shared__ double red[CB / 64];
     // Fletcher-Reeves beta for a fixed preconditioner; with zq (z_k.q_{k-1})
     // the Polak-Ribiere beta of flexible CG, z_k.(r_k - r_{k-1}) / z_{k-1}.r_{k-1}
@@ -362,8 +366,10 @@ __global__ void __launch_bounds__(CB) k_cg_matvec(MGLevel L, const float *z, con
 // e += alpha p, r -= alpha q, ||r||^2 accumulated (alpha = rz_k / pq_k).
 __global__ void __launch_bounds__(CB) k_cg_update(int64_t nn, const float *p, const float *q,
                                                   float *e, float *r, const double *rz,
-                                                  const double *pq, double *rr)
+                                                  const double *pq, double *rr,
+                                                  const int32_t *gate)
 {
+    if (gate && *gate) return;
     __shared__ double red[CB / 64];
     const float alpha = (*pq != 0.0) ? (float)(*rz / *pq) : 0.0f;
     double acc = 0.0;
@@ -424,7 +430,7 @@ void launch_cg_update(const MGHier &H, const float *p, const float *q, float *e,
     const MGLevel &L = H.lv[0];
     const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
     hipLaunchKernelGGL(k_cg_update, dim3(cg_blocks(nn)), dim3(CB), 0, s, nn, p, q, e, r, rz, pq,
-                       rr);
+                       rr, L.gate);
 }
 
 int mg_tail_setup(MGHier &H)

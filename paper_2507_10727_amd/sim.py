@@ -257,3 +257,41 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+class Ensemble:
+    """Independent Simulations advanced together: one step of all of them is
+    a single replay of a captured hipGraph (see pic_ensemble_create)."""
+
+    def __init__(self, sims, nstreams=4):
+        import torch
+
+        self.torch = torch
+        self.sims = list(sims)
+        self.lib = L.load()
+        arr = (C.c_void_p * len(self.sims))(*[s.h.value for s in self.sims])
+        self.stream = torch.cuda.Stream(device=self.sims[0].device)
+        e = C.c_void_p()
+        st = self.lib.pic_ensemble_create(arr, len(self.sims), C.c_void_p(self.stream.cuda_stream),
+                                          int(nstreams), C.byref(e))
+        self._check(st, None)
+        self.e = e
+
+    def _check(self, status, e):
+        if status != L.PIC_OK:
+            msg = self.lib.pic_ensemble_last_error(e)
+            raise L.PicError(status, msg.decode() if msg else "")
+
+    def step(self, n=1):
+        self._check(self.lib.pic_ensemble_step(self.e, int(n)), self.e)
+
+    def close(self):
+        if getattr(self, "e", None):
+            self.lib.pic_ensemble_free(self.e)
+            self.e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

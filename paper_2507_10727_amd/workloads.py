@@ -201,6 +201,33 @@ def preset(name: str) -> Problem:
     raise KeyError(name)
 
 
+ENSEMBLE_GRIDS = (64, 96, 128, 160, 192, 224, 256)
+ENSEMBLE_GAMMA = (0.05, 0.1, 0.15, 0.2, 0.3)
+ENSEMBLE_R = (10.0, 30.0, 100.0, 300.0, 1000.0)
+
+
+def ensemble_problems(n_runs: int = 64, scale: float = 1.0, seed: int = 250710732) -> list:
+    """The secondary-yield / resistance sweep: n_runs square discharges of
+    uneven size.  Cell 312.5 um (domain N x 312.5 um), N from 64 to 256;
+    particles per species 1e5 (N / 64)^2 (1e5 to 1.6e6) times `scale`;
+    density 1e15 to 1e16 m^-3 (log-spaced over the runs); run k takes yield
+    ENSEMBLE_GAMMA[k % 5] and resistance ENSEMBLE_R[(k // 5) % 5], so the 25
+    combinations recur over the sizes.  EC-PIC, FP32 state, -500 V source,
+    10 mTorr, peak B 0.03 T, dt 5 ps; run k draws the random stream `run = k`."""
+    out = []
+    for k in range(n_runs):
+        n = ENSEMBLE_GRIDS[(k * 3) % len(ENSEMBLE_GRIDS)]
+        L = n * 312.5e-6
+        dens = 10.0 ** (15.0 + (k % 8) / 7.0)
+        npart = max(1000, int(1e5 * (n / 64.0) ** 2 * scale))
+        out.append(Problem(
+            name=f"sweep{k:02d}", nr=n, nz=n, lr=L, lz=L, scheme=EC_PIC, precision=F32,
+            circuit=RESISTOR, v_ext=-500.0, v_fixed=-500.0, r_ext=ENSEMBLE_R[(k // 5) % 5],
+            gamma_i=ENSEMBLE_GAMMA[k % 5], p_gas=10e-3 * TORR, b_peak=0.03, density=dens,
+            n_per_species=npart, seed=seed, run=k, capacity_factor=1.25, steps=800000))
+    return out
+
+
 def scaled(p: Problem, n_per_species: int) -> Problem:
     """Same discharge with fewer macroparticles (density kept, weight raised)."""
     return p.replace(n_per_species=n_per_species, weight=None)

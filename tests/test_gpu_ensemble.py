@@ -1,0 +1,78 @@
+"""Ensembles: runs advanced together by one captured graph per step give the
+same results as each run advanced alone with pic_step.
+
+The two paths differ only in how the field solve decides its iteration
+counts (on the device, from a fixed pass plan, in the ensemble; on the host
+between passes alone); both stop at the same FP64 residual, so potentials
+agree to the solve tolerance and the particle decisions (cells, collisions,
+emission, ids) are the same.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_sim, say
+from paper_2507_10727_amd import _lib as L
+from paper_2507_10727_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def sweep(n_runs, scale, sort_every=3):
+    ps = W.ensemble_problems(n_runs=n_runs, scale=scale)
+    return [p.replace(sort_every=sort_every, poisson_rtol=1e-8) for p in ps]
+
+
+def make(ps):
+    sims = []
+    for p in ps:
+        br, bz, sig, parts = W.inputs(p)
+        sims.append(gpu_sim(p, br, bz, sig, parts))
+    return sims
+
+
+def test_ensemble_equals_sequential():
+    from paper_2507_10727_amd.sim import Ensemble
+    ps = sweep(5, 0.05)
+    say("case ensemble", [(p.nr, p.n_per_species, p.gamma_i, p.r_ext) for p in ps])
+    alone = make(ps)
+    for s in alone:
+        s.step(7)
+    batch = make(ps)
+    ens = Ensemble(batch, nstreams=3)
+    ens.step(7)
+    for k, (a, b) in enumerate(zip(alone, batch)):
+        da, db = a.diag(), b.diag()
+        say(f"run {k}: counts {da['count']} / {db['count']}, coll {da['n_coll']} / {db['n_coll']}, "
+            f"see {da['n_see']} / {db['n_see']}, vc {da['vc']:.6f} / {db['vc']:.6f}, "
+            f"solve {db['poisson']}")
+        assert da["step"] == db["step"] == 7
+        assert da["count"] == db["count"]
+        assert da["n_coll"] == db["n_coll"] and da["n_see"] == db["n_see"]
+        assert da["n_abs"] == db["n_abs"]
+        assert db["poisson"]["converged"] == 1 and db["poisson"]["rel_res"] <= 1e-8
+        assert abs(da["vc"] - db["vc"]) <= 1e-6 * abs(da["vc"])
+        fa, fb = a.fields_host(), b.fields_host()
+        assert np.abs(fa["phi"] - fb["phi"]).max() <= 1e-6 * np.abs(fa["phi"]).max()
+        for s in range(2):
+            pa, pb = a.particles(s), b.particles(s)
+            ia, ib = np.argsort(pa["id"]), np.argsort(pb["id"])
+            assert np.array_equal(pa["id"][ia], pb["id"][ib])
+            dr = ps[k].dr
+            assert np.abs(pa["r"][ia] - pb["r"][ib]).max() <= 1e-5 * dr
+            assert np.abs(pa["z"][ia] - pb["z"][ib]).max() <= 1e-5 * dr
+            same_cell = np.mean(pa["key"][ia] == pb["key"][ib])
+            assert same_cell >= 1 - 1e-4
+    ens.close()
+    # the runs stay usable on their own afterwards
+    batch[0].step(1)
+    assert batch[0].diag()["step"] == 8
+
+
+def test_ensemble_rejects_mixed_sort_phase():
+    from paper_2507_10727_amd.sim import Ensemble
+    ps = sweep(2, 0.02)
+    ps[1] = ps[1].replace(sort_every=5)
+    sims = make(ps)
+    with pytest.raises(L.PicError) as ei:
+        Ensemble(sims)
+    assert ei.value.status == L.PIC_EINVAL
