@@ -133,6 +133,80 @@ def poisson_bench(train_seconds=60.0, reps=6):
     return out
 
 
+def ensemble_bench(n_runs=64, steps=10, scale=1.0):
+    """The yield / resistance sweep (workloads.ensemble_problems): the runs
+    advanced one after another through pic_step, then the same runs advanced
+    together as one ensemble (one captured graph per step), aggregate
+    particle-steps/s for each.  Launch shapes come from the autotuner (one
+    tuning per run size, cached), the stream count from timing 2..16."""
+    import numpy as np
+    import torch
+    from paper_2507_10727_amd import autotune
+    from paper_2507_10727_amd import workloads as W
+    from paper_2507_10727_amd.sim import Ensemble, Simulation
+    ps = W.ensemble_problems(n_runs=n_runs, scale=scale)
+    t0 = time.perf_counter()
+    sims = []
+    for p in ps:
+        br, bz, sig, parts = W.inputs(p)
+        sims.append(Simulation(p, br, bz, sig, parts))
+    torch.cuda.synchronize()
+    log(f"[bench] ensemble: {n_runs} runs initialised in {time.perf_counter() - t0:.1f} s")
+    cache = autotune.TuningCache()
+    tuned = 0
+    for sim in sims:
+        _, now = cache.apply_or_tune(sim, steps_per_trial=2)
+        tuned += int(now)
+    log(f"[bench] ensemble: {tuned} sizes tuned: {cache.table}")
+
+    def live():
+        return [sim.diag()["count"] for sim in sims]
+
+    # one after another
+    c0 = live()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sim in sims:
+        sim.step(steps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    c1 = live()
+    ps_seq = sum(0.5 * (a[0] + a[1] + b[0] + b[1]) for a, b in zip(c0, c1)) * steps
+    # together
+    ns, stream_ms = autotune.best_stream_count(sims)
+    ens = Ensemble(sims, nstreams=ns)
+    ens.step(1)
+    c0 = live()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(steps)
+    torch.cuda.synchronize()
+    t_ens = time.perf_counter() - t0
+    c1 = live()
+    ps_ens = sum(0.5 * (a[0] + a[1] + b[0] + b[1]) for a, b in zip(c0, c1)) * steps
+    ens.close()
+    runs = []
+    for p, sim in zip(ps, sims):
+        d = sim.diag()
+        runs.append({"grid": p.nr, "gamma": p.gamma_i, "r_ohm": p.r_ext,
+                     "particles": d["count"][0] + d["count"][1], "step": d["step"],
+                     "i_cathode_a": d["i_cathode"], "v_cathode": d["vc"],
+                     "n_e_peak_m3": d["n_peak"][0], "n_i_peak_m3": d["n_peak"][1]})
+        sim.close()
+    seq = ps_seq / t_seq
+    bat = ps_ens / t_ens
+    log(f"[bench] ensemble: sequential {seq:.3e}, batched {bat:.3e} particle-steps/s "
+        f"({bat / seq:.2f}x), {ns} streams")
+    return {"runs": n_runs, "steps": steps, "total_particles": int(sum(r["particles"] for r in runs)),
+            "sequential_particle_steps_per_s": seq, "batched_particle_steps_per_s": bat,
+            "speedup": bat / seq, "sequential_ms_per_step": t_seq / steps * 1e3,
+            "batched_ms_per_step": t_ens / steps * 1e3, "streams": ns,
+            "stream_ms_per_step": stream_ms, "tuning": cache.table,
+            "note": "per-run values after the measured steps (a few tens of ps of a discharge "
+                    "that needs ~4 us to reach steady state)",
+            "per_run": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +218,10 @@ def main():
     ap.add_argument("--poisson-only", action="store_true",
                     help="only the field-solve comparison (prints its JSON)")
     ap.add_argument("--train-seconds", type=float, default=60.0)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="only the batched sweep against sequential runs (prints its JSON)")
+    ap.add_argument("--ensemble-runs", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -158,6 +236,9 @@ def main():
 
     if args.poisson_only:
         print(json.dumps({"poisson": poisson_bench(args.train_seconds)}), flush=True)
+        return
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": ensemble_bench(args.ensemble_runs)}), flush=True)
         return
 
     if args.copy_calibration:
@@ -219,6 +300,10 @@ def main():
     if not args.no_poisson:
         log("[bench] poisson 512x1024")
         poisson = poisson_bench(args.train_seconds)
+    ensemble = None
+    if not args.no_ensemble:
+        log(f"[bench] ensemble of {args.ensemble_runs} runs")
+        ensemble = ensemble_bench(args.ensemble_runs)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, 1 step)")
@@ -241,6 +326,7 @@ def main():
         "cpu_baseline": cpu,
         "phase_ms_per_step": phases,
         "poisson": poisson,
+        "ensemble": ensemble,
         "diag": {"vc": d1["vc"], "i_cathode": d1["i_cathode"], "n_coll": d1["n_coll"],
                  "deposit_fallback": d1["deposit_fallback"], "count": d1["count"]},
     }

@@ -290,6 +290,26 @@ pic_status pic_pc_apply(pic_handle *h, const double *r_dev, double *z_dev);
 /* Switch the preconditioner of later solves (PIC_LEARNED needs weights). */
 pic_status pic_set_poisson_mode(pic_handle *h, int32_t mode);
 
+/* ---- launch tuning ------------------------------------------------------------
+ * The particle kernel's launch shape: total blocks, and the weight of an
+ * electron against an ion when those blocks are split between the species
+ * (electrons carry the collision test).  pic_autotune times candidate shapes
+ * on the live simulation (block counts 256..8192 at the current weight, then
+ * weights 1.0, 1.3, 1.7 at the best count), steps_per_trial steps each, so
+ * the run advances by 9 * steps_per_trial steps; it keeps the fastest.  The
+ * shape changes no result beyond the summation order of the FP32 deposit.
+ * pic_set_tuning applies a stored choice (e.g. from a run of the same size). */
+typedef struct pic_tuning {
+    int32_t push_blocks;        /* default 2048                                   */
+    double push_e_weight;       /* default 1.3                                    */
+    double push_ms;             /* autotune: mean particle-kernel time chosen     */
+    int32_t trials;
+} pic_tuning;
+
+pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out);
+pic_status pic_set_tuning(pic_handle *h, const pic_tuning *t);
+pic_status pic_get_tuning(const pic_handle *h, pic_tuning *t);
+
 /* ---- ensembles of independent discharges -----------------------------------
  * Many runs (each created by pic_init, with its own grid, particles,
  * secondary yield and circuit; Section 4's study varies the yield and the
@@ -300,8 +320,9 @@ pic_status pic_set_poisson_mode(pic_handle *h, int32_t mode);
  * preconditioned and controlled on the device (its passes stop once the
  * FP64 residual meets poisson_rtol, at most three passes), so a run advances
  * exactly as pic_step would to within the solve tolerance.  The runs must
- * share sort_every and their step phase, have timers off, and are not used
- * through other calls while pic_ensemble_step runs.  The library owns the
+ * share sort_every and have timers off; creation cell-sorts every run so
+ * that all share one sort phase.  Runs are not used through other calls
+ * while pic_ensemble_step runs.  The library owns the
  * streams, graphs and a small pinned status buffer; stream (nullable) is
  * where the graph launches.  Errors of pic_ensemble_step name the run:
  * PIC_ECAPACITY, PIC_ENOCONV, PIC_EHIP. */

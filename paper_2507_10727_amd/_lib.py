@@ -128,7 +128,16 @@ EXPORTS = [
     "pic_pc_param_count", "pic_pc_set_weights", "pic_pc_get_weights", "pic_pc_train_step",
     "pic_pc_apply", "pic_set_poisson_mode", "pic_apply_operator",
     "pic_ensemble_create", "pic_ensemble_step", "pic_ensemble_free", "pic_ensemble_last_error",
+    "pic_autotune", "pic_set_tuning", "pic_get_tuning",
 ]
+
+
+class pic_tuning(C.Structure):
+    _fields_ = [("push_blocks", C.c_int32), ("push_e_weight", C.c_double),
+                ("push_ms", C.c_double), ("trials", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 PIC_MGCG, PIC_LEARNED, PIC_CG = 0, 1, 2
 
@@ -173,6 +182,9 @@ def load():
     L.pic_ensemble_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_int32,
                                       C.POINTER(C.c_void_p)]
     L.pic_ensemble_step.argtypes = [C.c_void_p, C.c_int32]
+    L.pic_autotune.argtypes = [H, C.c_int32, C.POINTER(pic_tuning)]
+    L.pic_set_tuning.argtypes = [H, C.POINTER(pic_tuning)]
+    L.pic_get_tuning.argtypes = [H, C.POINTER(pic_tuning)]
     L.pic_ensemble_free.argtypes = [C.c_void_p]
     L.pic_ensemble_last_error.argtypes = [C.c_void_p]
     L.pic_ensemble_last_error.restype = C.c_char_p

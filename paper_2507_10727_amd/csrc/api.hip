@@ -77,6 +77,11 @@ struct pic_handle {
     int pmode = PIC_MGCG;
     int64_t n_unknown = 0;
     double rho_pc = 0.5, rho_cg = 0.9;
+    // launch shape of the particle kernel (autotuned): total blocks and the
+    // weight of an electron against an ion when splitting them
+    RunSolve *rsolve = nullptr;     // descriptor of the batched field update
+    int push_blocks = 2048;
+    double push_e_weight = 1.3;
     int32_t host_flags = 0;
     bool timers_on = false;
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
@@ -300,6 +305,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     const int dblocks = 256;
     double *dpart = cv.take<double>((int64_t)dblocks * 6 * 8);
     unsigned long long *live = cv.take<unsigned long long>(2 * 8);
+    RunSolve *rsolve = cv.take<RunSolve>(1);
     // learned preconditioner: network, Adam state and activations
     const bool pc_on = c.pc_batch > 0 || c.poisson_mode == PIC_LEARNED;
     PcNet net;
@@ -309,6 +315,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
         pc_base = cv.take<char>(pc_bytes(net));
     }
     if (h) {
+        h->rsolve = rsolve;
         h->pc_on = pc_on;
         if (pc_on) {
             h->net = net;
@@ -760,8 +767,9 @@ void push_grid(pic_handle *h, int *nblk_e, int *nblocks)
 {
     const double ne = (double)std::max<int64_t>(h->host_count[0], 1);
     const double ni = (double)std::max<int64_t>(h->host_count[1], 1);
-    const int total = 2048;
-    int be = (int)std::lround(total * 1.3 * ne / (1.3 * ne + ni));
+    const int total = h->push_blocks;
+    const double w = h->push_e_weight;
+    int be = (int)std::lround(total * w * ne / (w * ne + ni));
     be = std::max(1, std::min(total - 1, be));
     int bi = total - be;
     be = std::max(1, (int)std::min<int64_t>(be, (h->host_count[0] + PUSH_CHUNK - 1) / PUSH_CHUNK + 1));
@@ -912,60 +920,13 @@ pic_status step_one(pic_handle *h)
 }
 
 // ---- a step with no host synchronization (for graph capture) ---------------
-void set_gate(pic_handle *h, const int32_t *g)
-{
-    h->f.gate = g;
-    for (int l = 0; l < MAX_LEVELS; ++l) {
-        h->f.mg.lv[l].gate = g;
-        h->f.mg.tail.L[l].gate = g;
-    }
-}
 
-// Field solve whose passes are controlled on the device: after the first
-// residual, up to three multigrid-preconditioned passes, each skipped once
-// the FP64 residual meets the tolerance (their kernels return at once).  The
-// pass lengths come from the handle's measured convergence rate: the first
-// for the usual starting residual, the others for a full FP32 pass.
-template <typename Q>
-void solve_gated(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_cathode)
-{
-    hipStream_t s = h->stream;
-    FieldDev &f = h->f;
-    const double rtol = h->cfg.poisson_rtol;
-    launch_set_dirichlet(f, phi, v_cathode, s);
-    launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
-    launch_solve_init(f, phi, h->sc, rtol, s);
-    auto iters = [&](double target) {
-        const int n = (int)std::ceil(std::log(target) / std::log(h->rho));
-        return std::max(1, std::min(n, 64));
-    };
-    const int n0 = iters(std::max(0.5 * rtol / h->rel0_est, 1e-6));
-    const int n1 = iters(1e-6);
-    set_gate(h, &h->sc->solve_done);
-    for (int p = 0; p < 3; ++p) {
-        const int n = p == 0 ? n0 : n1;
-        enqueue_pass<Q>(h, phi, q0, q1, n, PIC_MGCG);
-        launch_solve_gate(h->sc, rtol, n, s);
-    }
-    set_gate(h, nullptr);
-}
-
+// The particle part of a step (the ensemble batches the field update).
 template <typename T>
 void step_enqueue(pic_handle *h, bool do_sort)
 {
-    const pic_config &c = h->cfg;
     if (do_sort) sort_all<T>(h);
     particle_phase<T>(h);
-    if (c.field_solve) {
-        launch_extrapolate(h->f, 0, h->stream);
-        solve_gated<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0);
-        launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, c.circuit,
-                          c.v_fixed, c.v_ext, c.r_ext, c.dt, c.extra_current * c.dt, h->stream);
-        launch_field_prep<T>(h->f, (typename Vec4<T>::type *)h->node, h->sc, c.scheme, 0, h->stream);
-    } else if (c.extra_current != 0.0) {
-        launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, PIC_FIXED_V, 0.0,
-                          0.0, 1.0, c.dt, c.extra_current * c.dt, h->stream);
-    }
 }
 
 template <typename T>
@@ -1079,13 +1040,6 @@ pic_status init_typed(pic_handle *h, const pic_species_host *init)
 }
 
 // ---- ensembles ---------------------------------------------------------------
-struct EnsembleStatus {
-    double rr, bb, rr0;
-    int32_t flags, pad;
-    int64_t count[2];
-    int32_t solve_done, solve_passes, solve_iters, solve_pad;
-};
-
 }  // namespace
 
 struct pic_ensemble {
@@ -1094,7 +1048,9 @@ struct pic_ensemble {
     bool own_s0 = false;
     std::vector<hipStream_t> streams;
     std::vector<hipEvent_t> events;     // fork + one join per stream
-    EnsembleStatus *status = nullptr;   // pinned host memory, one per run
+    RunStatus *status = nullptr;        // pinned host memory, one per run
+    RunStatus *status_dev = nullptr;    // its device address
+    std::vector<BatchPlan> plans;       // batches of at most MAX_BATCH runs
     struct G {
         int sort, cur0, cur1;
         hipGraphExec_t exec;
@@ -1142,6 +1098,18 @@ pic_status capture_ensemble(pic_ensemble *e, bool do_sort, hipGraphExec_t *out)
         cur1.push_back(h->cur[1]);
         since.push_back(h->steps_since_sort);
     }
+    // pass plan of the batched solve, from the runs' measured convergence
+    double rho = 0.0, rel0 = 0.0, rtol = 1.0;
+    for (pic_handle *h : e->runs) {
+        rho = std::max(rho, h->rho);
+        rel0 = std::max(rel0, h->rel0_est);
+        rtol = std::min(rtol, h->cfg.poisson_rtol);
+    }
+    auto iters = [&](double target) {
+        const int n = (int)std::ceil(std::log(target) / std::log(rho));
+        return std::max(1, std::min(n, 64));
+    };
+    const int plan[3] = {iters(std::max(0.5 * rtol / rel0, 1e-6)), iters(1e-6), iters(1e-6)};
     EHIPCHECK(e, hipStreamBeginCapture(e->s0, hipStreamCaptureModeThreadLocal));
     (void)hipEventRecord(e->events[0], e->s0);
     for (int k = 0; k < ns; ++k) (void)hipStreamWaitEvent(e->streams[k], e->events[0], 0);
@@ -1151,14 +1119,42 @@ pic_status capture_ensemble(pic_ensemble *e, bool do_sort, hipGraphExec_t *out)
         h->stream = e->streams[r % ns];
         if (h->prec == PIC_F64) step_enqueue<double>(h, do_sort);
         else step_enqueue<float>(h, do_sort);
-        (void)hipMemcpyAsync(&e->status[r], &h->sc->res_rr, 48, hipMemcpyDeviceToHost, h->stream);
-        (void)hipMemcpyAsync(&e->status[r].solve_done, &h->sc->solve_done, 16,
-                             hipMemcpyDeviceToHost, h->stream);
         h->stream = saved;
     }
     for (int k = 0; k < ns; ++k) {
         (void)hipEventRecord(e->events[1 + k], e->streams[k]);
         (void)hipStreamWaitEvent(e->s0, e->events[1 + k], 0);
+    }
+    // field update of every run, batched: extrapolated warm start, FP64
+    // residual, up to three device-gated multigrid-PCG passes, circuit,
+    // gather fields, status
+    hipStream_t s = e->s0;
+    for (size_t b = 0; b < e->plans.size(); ++b) {
+        const BatchPlan &P = e->plans[b];
+        launch_nodes_b(P, BATCH_EXTRAPOLATE, s);
+        launch_nodes_b(P, BATCH_SET_DIRICHLET, s);
+        launch_scalars_b(P, BATCH_ZERO_RES, 0, s);
+        launch_residual64_b(P, 0, s);
+        launch_scalars_b(P, BATCH_SOLVE_INIT, 0, s);
+        launch_nodes_b(P, BATCH_ZERO_IF_EMPTY, s);
+        for (int p = 0; p < 3; ++p) {
+            const int n = plan[p];
+            launch_nodes_b(P, BATCH_CAST_SCALE, s);
+            launch_scalars_b(P, BATCH_ZERO_PCG_GATED, 0, s);
+            launch_mg_vcycle_b(P, 0, s);
+            for (int k = 0; k < n; ++k) {
+                launch_cg_matvec_b(P, k, s);
+                launch_cg_update_b(P, k, s);
+                if (k + 1 < n) launch_mg_vcycle_b(P, k + 1, s);
+            }
+            launch_nodes_b(P, BATCH_UPDATE64, s);
+            launch_scalars_b(P, BATCH_ZERO_RES_GATED, 0, s);
+            launch_residual64_b(P, 1, s);
+            launch_scalars_b(P, BATCH_SOLVE_GATE, n, s);
+        }
+        launch_circuit_b(P, s);
+        launch_nodes_b(P, BATCH_FIELD_PREP, s);
+        launch_status_b(P, e->status_dev + b * MAX_BATCH, s);
     }
     hipGraph_t graph;
     const hipError_t ec = hipStreamEndCapture(e->s0, &graph);
@@ -1198,7 +1194,7 @@ pic_status ensemble_step(pic_ensemble *e)
     bool drift = false;
     for (size_t r = 0; r < e->runs.size(); ++r) {
         pic_handle *h = e->runs[r];
-        const EnsembleStatus &S = e->status[r];
+        const RunStatus &S = e->status[(r / MAX_BATCH) * MAX_BATCH + r % MAX_BATCH];
         if (do_sort) {
             h->cur[0] = 1 - h->cur[0];
             h->cur[1] = 1 - h->cur[1];
@@ -1589,14 +1585,16 @@ pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *str
         if (!h) return efail(nullptr, PIC_EINVAL, "run %d is NULL", r);
         for (int q = 0; q < r; ++q)
             if (runs[q] == h) return efail(nullptr, PIC_EINVAL, "run %d appears twice", r);
-        if (h->cfg.sort_every != runs[0]->cfg.sort_every ||
-            h->steps_since_sort != runs[0]->steps_since_sort || h->cur[0] != runs[0]->cur[0] ||
-            h->cur[1] != runs[0]->cur[1])
-            return efail(nullptr, PIC_EINVAL,
-                         "run %d: every run must share sort_every and its sort phase", r);
+        if (h->cfg.sort_every != runs[0]->cfg.sort_every)
+            return efail(nullptr, PIC_EINVAL, "run %d: every run must share sort_every", r);
+        if (h->prec != runs[0]->prec)
+            return efail(nullptr, PIC_EINVAL, "run %d: every run must share the state precision", r);
+        if (!h->cfg.field_solve)
+            return efail(nullptr, PIC_EINVAL, "run %d: ensembles solve the field every step", r);
         if (h->timers_on) return efail(nullptr, PIC_EINVAL, "run %d: timers must be off", r);
     }
     pic_ensemble *e = new pic_ensemble();
+    e->plans.clear();
     e->runs.assign(runs, runs + nruns);
     if (stream) {
         e->s0 = (hipStream_t)stream;
@@ -1613,14 +1611,63 @@ pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *str
     for (auto &s : e->streams) ok &= hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
     for (auto &v : e->events)
         ok &= hipEventCreateWithFlags(&v, hipEventDisableTiming) == hipSuccess;
-    ok &= hipHostMalloc((void **)&e->status, sizeof(EnsembleStatus) * nruns) == hipSuccess;
+    const int nbatch = (nruns + MAX_BATCH - 1) / MAX_BATCH;
+    ok &= hipHostMalloc((void **)&e->status, sizeof(RunStatus) * nbatch * MAX_BATCH) == hipSuccess;
+    ok = ok && hipHostGetDevicePointer((void **)&e->status_dev, e->status, 0) == hipSuccess;
     if (!ok) {
         pic_ensemble_free(e);
         return efail(nullptr, PIC_EHIP, "cannot create the ensemble's streams or status buffer");
     }
-    memset(e->status, 0, sizeof(EnsembleStatus) * nruns);
-    // every run's own stream must be idle before its work moves to the ensemble
-    for (pic_handle *h : e->runs) (void)hipStreamSynchronize(h->stream);
+    memset(e->status, 0, sizeof(RunStatus) * nbatch * MAX_BATCH);
+    // the descriptor of each run's batched field update, in its workspace
+    e->plans.resize(nbatch);
+    const double inv_2pi_eps0 = 1.0 / (2.0 * 3.14159265358979323846 * eps0());
+    for (int r = 0; r < nruns; ++r) {
+        pic_handle *h = e->runs[r];
+        const pic_config &c = h->cfg;
+        RunSolve R;
+        memset(&R, 0, sizeof(R));
+        R.f = h->f;
+        const int32_t *g = &h->sc->solve_done;
+        R.f.gate = g;
+        for (int l = 0; l < MAX_LEVELS; ++l) {
+            R.f.mg.lv[l].gate = g;
+            R.f.mg.tail.L[l].gate = g;
+        }
+        R.sc = h->sc;
+        R.q0 = h->q[0];
+        R.q1 = h->q[1];
+        R.node = h->node;
+        R.rtol2 = c.poisson_rtol * c.poisson_rtol;
+        R.v_fixed = c.v_fixed;
+        R.v_ext = c.v_ext;
+        R.r_ext = c.r_ext;
+        R.dt = c.dt;
+        R.extra_dq = c.extra_current * c.dt;
+        R.inv_2pi_eps0 = inv_2pi_eps0;
+        R.circuit = c.circuit;
+        R.scheme = c.scheme;
+        if (hipMemcpy(h->rsolve, &R, sizeof(R), hipMemcpyHostToDevice) != hipSuccess) {
+            pic_ensemble_free(e);
+            return efail(nullptr, PIC_EHIP, "cannot upload the run descriptors");
+        }
+        BatchPlan &P = e->plans[r / MAX_BATCH];
+        P.dev[P.nruns] = h->rsolve;
+        P.host[P.nruns] = h->f.mg;
+        P.nruns++;
+        P.prec = h->prec;
+    }
+    // one sort phase for all: cell-sort every run now, twice where that
+    // leaves its particles in the other buffer of the pair than run 0's
+    for (int r = 0; r < nruns; ++r) {
+        pic_handle *h = e->runs[r];
+        for (int k = 0; k < 2; ++k) {
+            if (k == 1 && h->cur[0] == e->runs[0]->cur[0] && h->cur[1] == e->runs[0]->cur[1]) break;
+            if (h->prec == PIC_F64) sort_all<double>(h);
+            else sort_all<float>(h);
+        }
+        (void)hipStreamSynchronize(h->stream);
+    }
     *out = e;
     return PIC_OK;
 }
@@ -1655,6 +1702,79 @@ const char *pic_ensemble_last_error(const pic_ensemble *e)
 {
     if (!e) return g_init_error.c_str();
     return e->err.c_str();
+}
+
+pic_status pic_set_tuning(pic_handle *h, const pic_tuning *t)
+{
+    if (!h || !t) return fail(h, PIC_EINVAL, "NULL argument");
+    if (t->push_blocks < 2 || t->push_blocks > 65536 || !(t->push_e_weight > 0.0) ||
+        !(t->push_e_weight < 100.0))
+        return fail(h, PIC_EINVAL, "push_blocks in [2, 65536] and push_e_weight in (0, 100)");
+    h->push_blocks = t->push_blocks;
+    h->push_e_weight = t->push_e_weight;
+    return PIC_OK;
+}
+
+pic_status pic_get_tuning(const pic_handle *h, pic_tuning *t)
+{
+    if (!h || !t) return fail(nullptr, PIC_EINVAL, "NULL argument");
+    memset(t, 0, sizeof(*t));
+    t->push_blocks = h->push_blocks;
+    t->push_e_weight = h->push_e_weight;
+    return PIC_OK;
+}
+
+pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (steps_per_trial < 1) return fail(h, PIC_EINVAL, "steps_per_trial < 1");
+    const bool was_on = h->timers_on;
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    timers_collect(h);
+    const pic_timers saved = h->timers;
+    h->timers_on = true;
+    // one trial: the mean device time of the particle kernel over the steps
+    auto trial = [&](int blocks, double w, double *ms) -> pic_status {
+        h->push_blocks = blocks;
+        h->push_e_weight = w;
+        h->timers = pic_timers{};
+        pic_status st = pic_step(h, steps_per_trial);
+        if (st != PIC_OK) return st;
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+        timers_collect(h);
+        *ms = h->timers.push_ms / std::max<int64_t>(h->timers.push_launches, 1);
+        return PIC_OK;
+    };
+    pic_tuning best = {h->push_blocks, h->push_e_weight, 1e300, 0};
+    pic_status st = PIC_OK;
+    // coordinate search: block count at the current weight, then the weight
+    static const int blocks[] = {256, 512, 1024, 2048, 4096, 8192};
+    static const double weights[] = {1.0, 1.3, 1.7};
+    for (int b : blocks) {
+        double ms;
+        if ((st = trial(b, best.push_e_weight, &ms)) != PIC_OK) break;
+        if (ms < best.push_ms) {
+            best.push_ms = ms;
+            best.push_blocks = b;
+        }
+    }
+    if (st == PIC_OK)
+        for (double w : weights) {
+            double ms;
+            if ((st = trial(best.push_blocks, w, &ms)) != PIC_OK) break;
+            if (ms < best.push_ms) {
+                best.push_ms = ms;
+                best.push_e_weight = w;
+            }
+        }
+    h->push_blocks = best.push_blocks;
+    h->push_e_weight = best.push_e_weight;
+    h->timers = saved;
+    h->timers_on = was_on;
+    if (st != PIC_OK) return st;
+    best.trials = (int32_t)(sizeof(blocks) / sizeof(blocks[0]) + sizeof(weights) / sizeof(weights[0]));
+    if (out) *out = best;
+    return PIC_OK;
 }
 
 pic_status pic_free(pic_handle *h)

@@ -312,13 +312,80 @@ struct FieldDev {
     const int32_t *gate;        // when set and nonzero, the solve's kernels return at once
 };
 
+// ---- batched field update of an ensemble ------------------------------------
+constexpr int MAX_BATCH = 64;
+
+// Per-run descriptor in the run's workspace: the field state, the charge,
+// the gather fields and the constants of the solve and the circuit; gates
+// of f point at sc->solve_done.
+struct RunSolve {
+    FieldDev f;
+    DevScalars *sc;
+    const void *q0, *q1;        // node charge per species (state precision)
+    void *node;                 // gather 4-vectors
+    double rtol2;
+    double v_fixed, v_ext, r_ext, dt, extra_dq, inv_2pi_eps0;
+    int32_t circuit, scheme;
+};
+
+// Kernel argument of a batched launch: the runs and the first block of each.
+struct BatchArgs {
+    const RunSolve *run[MAX_BATCH];
+    int32_t off[MAX_BATCH + 1];
+    int32_t nruns;
+    int32_t level, k, n_iter, op;
+};
+
+__device__ __forceinline__ int batch_run(const BatchArgs &a)
+{
+    int lo = 0, hi = a.nruns - 1;
+    const int b = (int)blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Host view of a batch: device descriptors and host copies of the shapes.
+struct BatchPlan {
+    int32_t nruns;
+    const RunSolve *dev[MAX_BATCH];
+    MGHier host[MAX_BATCH];
+    int32_t prec;               // PIC_F32 or PIC_F64, common to the batch
+};
+
+void launch_mg_vcycle_b(const BatchPlan &P, int k, hipStream_t s);
+void launch_cg_matvec_b(const BatchPlan &P, int k, hipStream_t s);
+void launch_cg_update_b(const BatchPlan &P, int k, hipStream_t s);
+// node-wise field operations of every run (op: BATCH_*), gated ones skip
+// runs whose solve is done
+enum : int32_t {
+    BATCH_EXTRAPOLATE = 0, BATCH_SET_DIRICHLET = 1, BATCH_ZERO_IF_EMPTY = 2,
+    BATCH_CAST_SCALE = 3, BATCH_UPDATE64 = 4, BATCH_FIELD_PREP = 5
+};
+void launch_nodes_b(const BatchPlan &P, int op, hipStream_t s);
+// per-run scalar operations (one block per run)
+enum : int32_t {
+    BATCH_ZERO_RES = 0, BATCH_ZERO_RES_GATED = 1, BATCH_SOLVE_INIT = 2, BATCH_SOLVE_GATE = 3,
+    BATCH_ZERO_PCG_GATED = 4
+};
+void launch_scalars_b(const BatchPlan &P, int op, int n_iter, hipStream_t s);
+void launch_residual64_b(const BatchPlan &P, int gated, hipStream_t s);
+void launch_circuit_b(const BatchPlan &P, hipStream_t s);
+// status of every run (residual norms, flags, counts, solve control) into
+// host-mapped memory
+struct RunStatus {
+    double rr, bb, rr0;
+    int32_t flags, pad;
+    int64_t count[2];
+    int32_t solve_done, solve_passes, solve_iters, solve_pad;
+};
+void launch_status_b(const BatchPlan &P, RunStatus *status_dev, hipStream_t s);
+
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_zero_gated(void *p, int64_t bytes, const int32_t *gate, hipStream_t s);
-// captured-solve control: done = (bb == 0 or rr <= rtol^2 bb) after the first
-// residual (zeroing phi's unknowns when bb == 0); after each pass that ran,
-// passes += 1, iters += n_iter, done updated
-void launch_solve_init(const FieldDev &f, double *phi, DevScalars *sc, double rtol, hipStream_t s);
-void launch_solve_gate(DevScalars *sc, double rtol, int n_iter, hipStream_t s);
 template <typename T>
 void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const T *q1,
                        DevScalars *sc, hipStream_t s);

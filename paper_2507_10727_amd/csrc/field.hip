@@ -9,6 +9,8 @@
 // inner solve (mg.hip) works on K / (2 pi eps0) for the correction equation
 // K_uu e = r of the FP64 refinement, with zero correction on Dirichlet
 // nodes.
+#include <cstring>
+
 #include "common.h"
 
 namespace pic {
@@ -57,18 +59,18 @@ __device__ __forceinline__ double load_q(const T *q0, const T *q1, int64_t n)
 // r = q - K phi on unknown rows (0 elsewhere); accumulates ||r||^2 and
 // ||b||^2 with b = q + couplings to Dirichlet neighbours (their phi values).
 template <typename T>
-__global__ void __launch_bounds__(FB) k_residual64(int32_t nr, int32_t nz, const double *ce,
+__device__ __forceinline__ void residual64_body(int32_t nr, int32_t nz, const double *ce,
                                                    const double *cn, const uint8_t *kind,
                                                    const double *phi, const T *q0, const T *q1,
                                                    double *r64, DevScalars *sc,
-                                                   const int32_t *gate)
+                                                   const int32_t *gate, int blk, int nblk)
 {
     if (gate && *gate) return;
     __shared__ double buf[FB / 64];
     const int ld = nr + 1;
     const int64_t nn = (int64_t)ld * (nz + 1);
     double rr = 0.0, bb = 0.0;
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
+    for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB) {
         if (kind[n] != 0) { r64[n] = 0.0; continue; }
         const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
         const double p = phi[n];
@@ -91,6 +93,16 @@ __global__ void __launch_bounds__(FB) k_residual64(int32_t nr, int32_t nz, const
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(FB) k_residual64(int32_t nr, int32_t nz, const double *ce,
+                                                   const double *cn, const uint8_t *kind,
+                                                   const double *phi, const T *q0, const T *q1,
+                                                   double *r64, DevScalars *sc,
+                                                   const int32_t *gate)
+{
+    residual64_body<T>(nr, nz, ce, cn, kind, phi, q0, q1, r64, sc, gate, blockIdx.x, gridDim.x);
+}
+
 // out = K phi on unknown nodes (charge form, C), 0 on Dirichlet nodes
 __global__ void __launch_bounds__(FB) k_apply_k64(int32_t nr, int32_t nz, const double *ce,
                                                   const double *cn, const uint8_t *kind,
@@ -111,34 +123,46 @@ __global__ void __launch_bounds__(FB) k_apply_k64(int32_t nr, int32_t nz, const 
     }
 }
 
-__global__ void k_cast_scale(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32,
-                             const int32_t *gate)
+__device__ __forceinline__ void cast_scale_body(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32,
+                             const int32_t *gate, int blk, int nblk)
 {
     if (gate && *gate) return;
     const double rr = sc->res_rr;
     const double scale = (rr > 0.0) ? 1.0 / sqrt(rr) : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->res_rr0 = rr;
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
+    if (blk == 0 && threadIdx.x == 0) sc->res_rr0 = rr;
+    for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB) {
         r32[n] = (float)(r64[n] * scale);
         e32[n] = 0.0f;
     }
 }
 
-__global__ void k_update64(int64_t nn, const uint8_t *kind, double *phi, const float *e32,
-                           const DevScalars *sc, double inv_2pi_eps0, const int32_t *gate)
+__global__ void k_cast_scale(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32,
+                             const int32_t *gate)
+{
+    cast_scale_body(nn, r64, sc, r32, e32, gate, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void update64_body(int64_t nn, const uint8_t *kind, double *phi, const float *e32,
+                           const DevScalars *sc, double inv_2pi_eps0, const int32_t *gate, int blk, int nblk)
 {
     if (gate && *gate) return;
     const double scale = sqrt(sc->res_rr0) * inv_2pi_eps0;
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB)
+    for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB)
         if (kind[n] == 0) phi[n] += (double)e32[n] * scale;
+}
+
+__global__ void k_update64(int64_t nn, const uint8_t *kind, double *phi, const float *e32,
+                           const DevScalars *sc, double inv_2pi_eps0, const int32_t *gate)
+{
+    update64_body(nn, kind, phi, e32, sc, inv_2pi_eps0, gate, blockIdx.x, gridDim.x);
 }
 
 // ---- circuit: induced cathode charge of phi0 and the cathode voltage update
 template <typename T>
-__global__ void k_circuit(int32_t nr, const double *ce, const double *cn, const uint8_t *kind,
+__device__ __forceinline__ void circuit_body(int32_t nr, const double *ce, const double *cn, const uint8_t *kind,
                           const double *phi0, const T *q0, const T *q1, DevScalars *sc,
                           int circuit, double v_fixed, double v_ext, double r_ext, double dt,
-                          double extra_dq)
+                          double extra_dq, int blk, int nblk)
 {
     __shared__ double buf[1024 / 64];
     const int ld = nr + 1;
@@ -168,17 +192,26 @@ __global__ void k_circuit(int32_t nr, const double *ce, const double *cn, const 
     }
 }
 
+template <typename T>
+__global__ void k_circuit(int32_t nr, const double *ce, const double *cn, const uint8_t *kind,
+                          const double *phi0, const T *q0, const T *q1, DevScalars *sc,
+                          int circuit, double v_fixed, double v_ext, double r_ext, double dt,
+                          double extra_dq)
+{
+    circuit_body<T>(nr, ce, cn, kind, phi0, q0, q1, sc, circuit, v_fixed, v_ext, r_ext, dt, extra_dq, blockIdx.x, gridDim.x);
+}
+
 // ---- gather fields: phi = phi0 + V_c phi_L and the node 4-vectors
 template <typename T>
-__global__ void k_field_prep(int32_t nr, int32_t nz, double dr, double dz, double *phi,
+__device__ __forceinline__ void field_prep_body(int32_t nr, int32_t nz, double dr, double dz, double *phi,
                              const double *phi0, const double *phil, const double *br,
                              const double *bz, typename Vec4<T>::type *node, const DevScalars *sc,
-                             int scheme, int use_phi)
+                             int scheme, int use_phi, int blk, int nblk)
 {
     const int ld = nr + 1;
     const int64_t nn = (int64_t)ld * (nz + 1);
     const double vc = sc->vc;
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
+    for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB) {
         const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
 #define PHI(m) (use_phi ? phi[(m)] : (phi0[(m)] + vc * phil[(m)]))
         const double p = PHI(n);
@@ -205,28 +238,48 @@ __global__ void k_field_prep(int32_t nr, int32_t nz, double dr, double dz, doubl
     }
 }
 
+template <typename T>
+__global__ void k_field_prep(int32_t nr, int32_t nz, double dr, double dz, double *phi,
+                             const double *phi0, const double *phil, const double *br,
+                             const double *bz, typename Vec4<T>::type *node, const DevScalars *sc,
+                             int scheme, int use_phi)
+{
+    field_prep_body<T>(nr, nz, dr, dz, phi, phi0, phil, br, bz, node, sc, scheme, use_phi, blockIdx.x, gridDim.x);
+}
+
 __global__ void k_zero_unknowns(int64_t nn, const uint8_t *kind, double *phi)
 {
     for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB)
         if (kind[n] == 0) phi[n] = 0.0;
 }
 
-__global__ void k_extrapolate(int64_t nn, const uint8_t *kind, double *phi0, double *prev,
-                              int first)
+__device__ __forceinline__ void extrapolate_body(int64_t nn, const uint8_t *kind, double *phi0, double *prev,
+                              int first, int blk, int nblk)
 {
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
+    for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB) {
         const double t = phi0[n];
         if (!first && kind[n] == 0) phi0[n] = 2.0 * t - prev[n];
         prev[n] = t;
     }
 }
 
-__global__ void k_set_dirichlet(int64_t nn, const uint8_t *kind, double *phi, double vcat)
+__global__ void k_extrapolate(int64_t nn, const uint8_t *kind, double *phi0, double *prev,
+                              int first)
 {
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
+    extrapolate_body(nn, kind, phi0, prev, first, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void set_dirichlet_body(int64_t nn, const uint8_t *kind, double *phi, double vcat, int blk, int nblk)
+{
+    for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB) {
         if (kind[n] == 1) phi[n] = vcat;
         else if (kind[n] == 2) phi[n] = 0.0;
     }
+}
+
+__global__ void k_set_dirichlet(int64_t nn, const uint8_t *kind, double *phi, double vcat)
+{
+    set_dirichlet_body(nn, kind, phi, vcat, blockIdx.x, gridDim.x);
 }
 
 // Per-block partial diagnostics: sum Q_e, sum Q_i, max n_e, max n_i, max phi,
@@ -280,6 +333,147 @@ __global__ void k_count_live(const int32_t *key, const DevScalars *sc, int speci
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
 }
 
+__device__ __forceinline__ void zero_unknowns_if_empty_body(int64_t nn, const uint8_t *kind, double *phi,
+                                         const DevScalars *sc, int blk, int nblk)
+{
+    if (sc->res_bb != 0.0) return;
+    for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB)
+        if (kind[n] == 0) phi[n] = 0.0;
+}
+
+// ---- batched forms over the runs of an ensemble ------------------------------
+template <typename T>
+__global__ void __launch_bounds__(FB) k_nodes_b(BatchArgs a)
+{
+    const int r = batch_run(a);
+    const RunSolve &R = *a.run[r];
+    const FieldDev &f = R.f;
+    const int blk = (int)blockIdx.x - a.off[r], nblk = a.off[r + 1] - a.off[r];
+    const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
+    switch (a.op) {
+        case BATCH_EXTRAPOLATE:
+            extrapolate_body(nn, f.kind, f.phi0, f.phi0_prev, 0, blk, nblk);
+            break;
+        case BATCH_SET_DIRICHLET: set_dirichlet_body(nn, f.kind, f.phi0, 0.0, blk, nblk); break;
+        case BATCH_ZERO_IF_EMPTY:
+            zero_unknowns_if_empty_body(nn, f.kind, f.phi0, R.sc, blk, nblk);
+            break;
+        case BATCH_CAST_SCALE:
+            cast_scale_body(nn, f.r64, R.sc, f.mg.lv[0].b, f.e32, f.gate, blk, nblk);
+            break;
+        case BATCH_UPDATE64:
+            update64_body(nn, f.kind, f.phi0, f.e32, R.sc, R.inv_2pi_eps0, f.gate, blk, nblk);
+            break;
+        default:
+            field_prep_body<T>(f.nr, f.nz, f.dr, f.dz, f.phi, f.phi0, f.phi_l, f.b_r, f.b_z,
+                               (typename Vec4<T>::type *)R.node, R.sc, R.scheme, 0, blk, nblk);
+            break;
+    }
+}
+
+__global__ void k_scalars_b(BatchArgs a)
+{
+    const RunSolve &R = *a.run[blockIdx.x];
+    DevScalars *sc = R.sc;
+    const bool done = sc->solve_done != 0;
+    switch (a.op) {
+        case BATCH_ZERO_RES:
+        case BATCH_ZERO_RES_GATED:
+            if (threadIdx.x == 0 && !(a.op == BATCH_ZERO_RES_GATED && done)) {
+                sc->res_rr = 0.0;
+                sc->res_bb = 0.0;
+            }
+            break;
+        case BATCH_SOLVE_INIT:
+            if (threadIdx.x == 0) {
+                const double rr = sc->res_rr, bb = sc->res_bb;
+                sc->solve_done = (bb == 0.0 || rr <= R.rtol2 * bb) ? 1 : 0;
+                sc->solve_passes = 0;
+                sc->solve_iters = 0;
+            }
+            break;
+        case BATCH_SOLVE_GATE:
+            if (threadIdx.x == 0 && !done) {
+                sc->solve_passes += 1;
+                sc->solve_iters += a.n_iter;
+                const double rr = sc->res_rr, bb = sc->res_bb;
+                sc->solve_done = (bb == 0.0 || rr <= R.rtol2 * bb) ? 1 : 0;
+            }
+            break;
+        default:
+            if (!done)
+                for (int t = threadIdx.x; t < 5 * (MAX_PCG + 2); t += blockDim.x) sc->pcg_rz[t] = 0.0;
+            break;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(FB) k_residual64_b(BatchArgs a)
+{
+    const int r = batch_run(a);
+    const RunSolve &R = *a.run[r];
+    const FieldDev &f = R.f;
+    residual64_body<T>(f.nr, f.nz, f.ce64, f.cn64, f.kind, f.phi0, (const T *)R.q0,
+                       (const T *)R.q1, f.r64, R.sc, a.op ? f.gate : nullptr,
+                       (int)blockIdx.x - a.off[r], a.off[r + 1] - a.off[r]);
+}
+
+template <typename T>
+__global__ void k_circuit_b(BatchArgs a)
+{
+    const RunSolve &R = *a.run[blockIdx.x];
+    const FieldDev &f = R.f;
+    circuit_body<T>(f.nr, f.ce64, f.cn64, f.kind, f.phi0, (const T *)R.q0, (const T *)R.q1, R.sc,
+                    R.circuit, R.v_fixed, R.v_ext, R.r_ext, R.dt, R.extra_dq, 0, 1);
+}
+
+__global__ void k_status_b(BatchArgs a, RunStatus *out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.nruns) return;
+    const DevScalars *sc = a.run[r]->sc;
+    RunStatus s;
+    s.rr = sc->res_rr;
+    s.bb = sc->res_bb;
+    s.rr0 = sc->res_rr0;
+    s.flags = sc->flags;
+    s.pad = 0;
+    s.count[0] = sc->count[0];
+    s.count[1] = sc->count[1];
+    s.solve_done = sc->solve_done;
+    s.solve_passes = sc->solve_passes;
+    s.solve_iters = sc->solve_iters;
+    s.solve_pad = 0;
+    out[r] = s;
+}
+
+BatchArgs node_args(const BatchPlan &P, int op)
+{
+    BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.nruns = P.nruns;
+    a.op = op;
+    for (int r = 0; r < P.nruns; ++r) {
+        a.run[r] = P.dev[r];
+        const int64_t nn = (int64_t)(P.host[r].lv[0].nr + 1) * (P.host[r].lv[0].nz + 1);
+        a.off[r + 1] = a.off[r] + blocks_for((nn + 1) / 2, 1024);
+    }
+    return a;
+}
+
+BatchArgs run_args(const BatchPlan &P, int op)
+{
+    BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.nruns = P.nruns;
+    a.op = op;
+    for (int r = 0; r < P.nruns; ++r) {
+        a.run[r] = P.dev[r];
+        a.off[r + 1] = r + 1;
+    }
+    return a;
+}
+
 }  // namespace
 
 void launch_zero(void *p, int64_t bytes, hipStream_t s)
@@ -296,44 +490,6 @@ void launch_zero_gated(void *p, int64_t bytes, const int32_t *gate, hipStream_t 
                        gate);
 }
 
-__global__ void k_solve_init(DevScalars *sc, double rtol2)
-{
-    if (threadIdx.x != 0) return;
-    const double rr = sc->res_rr, bb = sc->res_bb;
-    sc->solve_done = (bb == 0.0 || rr <= rtol2 * bb) ? 1 : 0;
-    sc->solve_passes = 0;
-    sc->solve_iters = 0;
-}
-
-__global__ void k_zero_unknowns_if_empty(int64_t nn, const uint8_t *kind, double *phi,
-                                         const DevScalars *sc)
-{
-    if (sc->res_bb != 0.0) return;
-    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB)
-        if (kind[n] == 0) phi[n] = 0.0;
-}
-
-__global__ void k_solve_gate(DevScalars *sc, double rtol2, int n_iter)
-{
-    if (threadIdx.x != 0 || sc->solve_done) return;
-    sc->solve_passes += 1;
-    sc->solve_iters += n_iter;
-    const double rr = sc->res_rr, bb = sc->res_bb;
-    sc->solve_done = (bb == 0.0 || rr <= rtol2 * bb) ? 1 : 0;
-}
-
-void launch_solve_init(const FieldDev &f, double *phi, DevScalars *sc, double rtol, hipStream_t s)
-{
-    const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
-    hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, s, sc, rtol * rtol);
-    hipLaunchKernelGGL(k_zero_unknowns_if_empty, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.kind,
-                       phi, (const DevScalars *)sc);
-}
-
-void launch_solve_gate(DevScalars *sc, double rtol, int n_iter, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_solve_gate, dim3(1), dim3(64), 0, s, sc, rtol * rtol, n_iter);
-}
 
 template <typename T>
 void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const T *q1,
@@ -428,6 +584,46 @@ template void launch_circuit<float>(const FieldDev &, const float *, const float
 template void launch_circuit<double>(const FieldDev &, const double *, const double *,
                                      DevScalars *, int, double, double, double, double, double,
                                      hipStream_t);
+void launch_nodes_b(const BatchPlan &P, int op, hipStream_t s)
+{
+    const BatchArgs a = node_args(P, op);
+    if (P.prec == PIC_F64)
+        hipLaunchKernelGGL(k_nodes_b<double>, dim3(a.off[P.nruns]), dim3(FB), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_nodes_b<float>, dim3(a.off[P.nruns]), dim3(FB), 0, s, a);
+}
+
+void launch_scalars_b(const BatchPlan &P, int op, int n_iter, hipStream_t s)
+{
+    BatchArgs a = run_args(P, op);
+    a.n_iter = n_iter;
+    hipLaunchKernelGGL(k_scalars_b, dim3(P.nruns), dim3(256), 0, s, a);
+}
+
+void launch_residual64_b(const BatchPlan &P, int gated, hipStream_t s)
+{
+    const BatchArgs a = node_args(P, gated);
+    if (P.prec == PIC_F64)
+        hipLaunchKernelGGL(k_residual64_b<double>, dim3(a.off[P.nruns]), dim3(FB), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_residual64_b<float>, dim3(a.off[P.nruns]), dim3(FB), 0, s, a);
+}
+
+void launch_circuit_b(const BatchPlan &P, hipStream_t s)
+{
+    const BatchArgs a = run_args(P, 0);
+    if (P.prec == PIC_F64)
+        hipLaunchKernelGGL(k_circuit_b<double>, dim3(P.nruns), dim3(1024), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_circuit_b<float>, dim3(P.nruns), dim3(1024), 0, s, a);
+}
+
+void launch_status_b(const BatchPlan &P, RunStatus *status_dev, hipStream_t s)
+{
+    const BatchArgs a = run_args(P, 0);
+    hipLaunchKernelGGL(k_status_b, dim3((P.nruns + 63) / 64), dim3(64), 0, s, a, status_dev);
+}
+
 template void launch_field_prep<float>(const FieldDev &, float4 *, DevScalars *, int, int,
                                        hipStream_t);
 template void launch_field_prep<double>(const FieldDev &, double4 *, DevScalars *, int, int,

@@ -18,6 +18,8 @@
 // black-red Gauss-Seidel, 2-node halo).  Pre-smoothing red-black and
 // post-smoothing black-red with restriction = prolongation^T make the
 // preconditioner symmetric, as conjugate gradients requires.
+#include <cstring>
+
 #include "common.h"
 
 namespace pic {
@@ -42,12 +44,12 @@ constexpr int ULW = UTX + 4, ULH = UTY + 4;
 
 // Down: pre-smooth from zero, residual, restriction.  F.b is the fine
 // right-hand side; writes the smoothed F.xd and the coarse C.b.
-__global__ void __launch_bounds__(256) k_mg_down(MGLevel F, MGLevel C)
+__device__ __forceinline__ void mg_down_body(const MGLevel &F, const MGLevel &C, int bx, int by)
 {
     if (F.gate && *F.gate) return;
     __shared__ float sb[DLH][DLW];
     __shared__ float sx[DLH][DLW];
-    const int I0 = blockIdx.x * DTX, J0 = blockIdx.y * DTY;
+    const int I0 = bx * DTX, J0 = by * DTY;
     const int fi0 = 2 * I0 - 3, fj0 = 2 * J0 - 3;
     const int ld = F.nr + 1;
     for (int t = threadIdx.x; t < DLW * DLH; t += 256) {
@@ -118,13 +120,14 @@ __global__ void __launch_bounds__(256) k_mg_down(MGLevel F, MGLevel C)
 
 // Up: x = xd + P xc, black then red Gauss-Seidel; writes F.xu on the owned
 // tile and, if dot != null, accumulates sum(b * x) over it.
-__global__ void __launch_bounds__(256) k_mg_up(MGLevel F, MGLevel C, double *dot)
+__device__ __forceinline__ void mg_up_body(const MGLevel &F, const MGLevel &C, double *dot, int bx,
+                                           int by)
 {
     if (F.gate && *F.gate) return;
     __shared__ float sb[ULH][ULW];
     __shared__ float sx[ULH][ULW];
     __shared__ double red[4];
-    const int i0 = blockIdx.x * UTX, j0 = blockIdx.y * UTY;
+    const int i0 = bx * UTX, j0 = by * UTY;
     const int fi0 = i0 - 2, fj0 = j0 - 2;
     const int ld = F.nr + 1, ldc = C.nr + 1;
     for (int t = threadIdx.x; t < ULW * ULH; t += 256) {
@@ -203,10 +206,9 @@ __device__ __forceinline__ void tail_sweep(const MGLevel &L, float *x, const flo
     }
 }
 
-__global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
+__device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float *sm)
 {
     if (T.L[T.first].gate && *T.L[T.first].gate) return;
-    extern __shared__ float sm[];
     float *tmp = sm;
 #define X(l) (sm + T.offx[(l)])
 #define B(l) (sm + T.offb[(l)])
@@ -320,9 +322,9 @@ constexpr int CB = 256;
 
 // p_k = z + beta p_{k-1} (beta = rz_k / rz_{k-1}, 0 for k = 0) into pc,
 // q = A p_k, and p_k . q accumulated.
-__global__ void __launch_bounds__(CB) k_cg_matvec(MGLevel L, const float *z, const float *pp,
-                                                  float *pc, float *q, const double *rz, int k,
-                                                  double *pq, const double *zq)
+__device__ __forceinline__ void cg_matvec_body(const MGLevel &L, const float *z, const float *pp,
+                                               float *pc, float *q, const double *rz, int k,
+                                               double *pq, const double *zq, int blk, int nblk)
 {
     if (L.gate && *L.gate) return;
     __shared__ double red[CB / 64];
@@ -336,7 +338,7 @@ __global__ void __launch_bounds__(CB) k_cg_matvec(MGLevel L, const float *z, con
     const int ld = L.nr + 1;
     const int64_t nn = (int64_t)ld * (L.nz + 1);
     double acc = 0.0;
-    for (int64_t n = (int64_t)blockIdx.x * CB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * CB) {
+    for (int64_t n = (int64_t)blk * CB + threadIdx.x; n < nn; n += (int64_t)nblk * CB) {
         const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
         float pv = 0.0f, qv = 0.0f;
         if (mg_unknown(L, i, j)) {
@@ -364,16 +366,15 @@ __global__ void __launch_bounds__(CB) k_cg_matvec(MGLevel L, const float *z, con
 }
 
 // e += alpha p, r -= alpha q, ||r||^2 accumulated (alpha = rz_k / pq_k).
-__global__ void __launch_bounds__(CB) k_cg_update(int64_t nn, const float *p, const float *q,
-                                                  float *e, float *r, const double *rz,
-                                                  const double *pq, double *rr,
-                                                  const int32_t *gate)
+__device__ __forceinline__ void cg_update_body(int64_t nn, const float *p, const float *q, float *e,
+                                               float *r, const double *rz, const double *pq,
+                                               double *rr, const int32_t *gate, int blk, int nblk)
 {
     if (gate && *gate) return;
     __shared__ double red[CB / 64];
     const float alpha = (*pq != 0.0) ? (float)(*rz / *pq) : 0.0f;
     double acc = 0.0;
-    for (int64_t n = (int64_t)blockIdx.x * CB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * CB) {
+    for (int64_t n = (int64_t)blk * CB + threadIdx.x; n < nn; n += (int64_t)nblk * CB) {
         e[n] += alpha * p[n];
         const float v = r[n] - alpha * q[n];
         r[n] = v;
@@ -387,6 +388,86 @@ __global__ void __launch_bounds__(CB) k_cg_update(int64_t nn, const float *p, co
         for (int w = 0; w < CB / 64; ++w) s += red[w];
         if (s != 0.0) atomic_add_dev(rr, s);
     }
+}
+
+__global__ void __launch_bounds__(256) k_mg_down(MGLevel F, MGLevel C)
+{
+    mg_down_body(F, C, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) k_mg_up(MGLevel F, MGLevel C, double *dot)
+{
+    mg_up_body(F, C, dot, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
+{
+    extern __shared__ float sm[];
+    mg_tail_body(T, dot, sm);
+}
+
+__global__ void __launch_bounds__(CB) k_cg_matvec(MGLevel L, const float *z, const float *pp,
+                                                  float *pc, float *q, const double *rz, int k,
+                                                  double *pq, const double *zq)
+{
+    cg_matvec_body(L, z, pp, pc, q, rz, k, pq, zq, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(CB) k_cg_update(int64_t nn, const float *p, const float *q,
+                                                  float *e, float *r, const double *rz,
+                                                  const double *pq, double *rr,
+                                                  const int32_t *gate)
+{
+    cg_update_body(nn, p, q, e, r, rz, pq, rr, gate, blockIdx.x, gridDim.x);
+}
+
+// ---- batched forms: one launch for the level (or vector) of every run of a
+// batch; a block finds its run from the block offsets
+__global__ void __launch_bounds__(256) k_mg_down_b(BatchArgs a)
+{
+    const int r = batch_run(a);
+    const MGHier &H = a.run[r]->f.mg;
+    const MGLevel &C = H.lv[a.level + 1];
+    const int lb = blockIdx.x - a.off[r], tx = (C.nr + 1 + DTX - 1) / DTX;
+    mg_down_body(H.lv[a.level], C, lb % tx, lb / tx);
+}
+
+__global__ void __launch_bounds__(256) k_mg_up_b(BatchArgs a)
+{
+    const int r = batch_run(a);
+    const RunSolve &R = *a.run[r];
+    const MGLevel &F = R.f.mg.lv[a.level];
+    const int lb = blockIdx.x - a.off[r], tx = (F.nr + 1 + UTX - 1) / UTX;
+    mg_up_body(F, R.f.mg.lv[a.level + 1], a.level == 0 ? &R.sc->pcg_rz[a.k] : nullptr, lb % tx,
+               lb / tx);
+}
+
+__global__ void __launch_bounds__(1024) k_mg_tail_b(BatchArgs a)
+{
+    extern __shared__ float sm[];
+    const RunSolve &R = *a.run[blockIdx.x];
+    mg_tail_body(R.f.mg.tail, R.f.mg.tail.first == 0 ? &R.sc->pcg_rz[a.k] : nullptr, sm);
+}
+
+__global__ void __launch_bounds__(CB) k_cg_matvec_b(BatchArgs a)
+{
+    const int r = batch_run(a);
+    const RunSolve &R = *a.run[r];
+    const int k = a.k;
+    cg_matvec_body(R.f.mg.lv[0], R.f.mg.lv[0].xu, R.f.p32[(k + 1) & 1], R.f.p32[k & 1], R.f.q32,
+                   R.sc->pcg_rz, k, &R.sc->pcg_pq[k], nullptr, blockIdx.x - a.off[r],
+                   a.off[r + 1] - a.off[r]);
+}
+
+__global__ void __launch_bounds__(CB) k_cg_update_b(BatchArgs a)
+{
+    const int r = batch_run(a);
+    const RunSolve &R = *a.run[r];
+    const int k = a.k;
+    const MGLevel &L = R.f.mg.lv[0];
+    cg_update_body((int64_t)(L.nr + 1) * (L.nz + 1), R.f.p32[k & 1], R.f.q32, R.f.e32, L.b,
+                   &R.sc->pcg_rz[k], &R.sc->pcg_pq[k], &R.sc->pcg_rr[k], L.gate,
+                   blockIdx.x - a.off[r], a.off[r + 1] - a.off[r]);
 }
 
 inline int cg_blocks(int64_t n)
@@ -433,11 +514,82 @@ void launch_cg_update(const MGHier &H, const float *p, const float *q, float *e,
                        rr, L.gate);
 }
 
+// ---- batched launches over the runs of a plan
+namespace {
+BatchArgs batch_args(const BatchPlan &P)
+{
+    BatchArgs a;
+    memset(&a, 0, sizeof(a));
+    a.nruns = P.nruns;
+    for (int r = 0; r < P.nruns; ++r) a.run[r] = P.dev[r];
+    return a;
+}
+}  // namespace
+
+void launch_mg_vcycle_b(const BatchPlan &P, int k, hipStream_t s)
+{
+    BatchArgs a = batch_args(P);
+    a.k = k;
+    int lmax = 0, tail_lds = 0;
+    for (int r = 0; r < P.nruns; ++r) {
+        lmax = std::max(lmax, (int)P.host[r].tail.first);
+        tail_lds = std::max(tail_lds, (int)P.host[r].tail_lds_bytes);
+    }
+    for (int l = 0; l < lmax; ++l) {
+        a.level = l;
+        a.off[0] = 0;
+        for (int r = 0; r < P.nruns; ++r) {
+            const MGHier &H = P.host[r];
+            int nb = 0;
+            if (l < H.tail.first)
+                nb = ((H.lv[l + 1].nr + 1 + DTX - 1) / DTX) * ((H.lv[l + 1].nz + 1 + DTY - 1) / DTY);
+            a.off[r + 1] = a.off[r] + nb;
+        }
+        if (a.off[P.nruns] > 0)
+            hipLaunchKernelGGL(k_mg_down_b, dim3(a.off[P.nruns]), dim3(256), 0, s, a);
+    }
+    for (int r = 0; r <= P.nruns; ++r) a.off[r] = r;
+    hipLaunchKernelGGL(k_mg_tail_b, dim3(P.nruns), dim3(TT, TT), tail_lds, s, a);
+    for (int l = lmax - 1; l >= 0; --l) {
+        a.level = l;
+        a.off[0] = 0;
+        for (int r = 0; r < P.nruns; ++r) {
+            const MGHier &H = P.host[r];
+            int nb = 0;
+            if (l < H.tail.first)
+                nb = ((H.lv[l].nr + 1 + UTX - 1) / UTX) * ((H.lv[l].nz + 1 + UTY - 1) / UTY);
+            a.off[r + 1] = a.off[r] + nb;
+        }
+        if (a.off[P.nruns] > 0)
+            hipLaunchKernelGGL(k_mg_up_b, dim3(a.off[P.nruns]), dim3(256), 0, s, a);
+    }
+}
+
+void launch_cg_matvec_b(const BatchPlan &P, int k, hipStream_t s)
+{
+    BatchArgs a = batch_args(P);
+    a.k = k;
+    for (int r = 0; r < P.nruns; ++r)
+        a.off[r + 1] = a.off[r] + cg_blocks((int64_t)(P.host[r].lv[0].nr + 1) * (P.host[r].lv[0].nz + 1));
+    hipLaunchKernelGGL(k_cg_matvec_b, dim3(a.off[P.nruns]), dim3(CB), 0, s, a);
+}
+
+void launch_cg_update_b(const BatchPlan &P, int k, hipStream_t s)
+{
+    BatchArgs a = batch_args(P);
+    a.k = k;
+    for (int r = 0; r < P.nruns; ++r)
+        a.off[r + 1] = a.off[r] + cg_blocks((int64_t)(P.host[r].lv[0].nr + 1) * (P.host[r].lv[0].nz + 1));
+    hipLaunchKernelGGL(k_cg_update_b, dim3(a.off[P.nruns]), dim3(CB), 0, s, a);
+}
+
 int mg_tail_setup(MGHier &H)
 {
-    return (int)hipFuncSetAttribute((const void *)k_mg_tail,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    H.tail_lds_bytes);
+    int e = (int)hipFuncSetAttribute((const void *)k_mg_tail,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, H.tail_lds_bytes);
+    e |= (int)hipFuncSetAttribute((const void *)k_mg_tail_b,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    return e;
 }
 
 }  // namespace pic

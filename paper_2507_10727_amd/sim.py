@@ -187,6 +187,20 @@ class Simulation:
         L.check(self.lib.pic_apply_operator(self.h, C.c_void_p(phi.data_ptr()),
                                             C.c_void_p(out.data_ptr())), self.h)
 
+    def autotune(self, steps_per_trial=2):
+        t = L.pic_tuning()
+        L.check(self.lib.pic_autotune(self.h, int(steps_per_trial), C.byref(t)), self.h)
+        return t.as_dict()
+
+    def set_tuning(self, push_blocks, push_e_weight):
+        t = L.pic_tuning(push_blocks, push_e_weight, 0.0, 0)
+        L.check(self.lib.pic_set_tuning(self.h, C.byref(t)), self.h)
+
+    def tuning(self):
+        t = L.pic_tuning()
+        L.check(self.lib.pic_get_tuning(self.h, C.byref(t)), self.h)
+        return t.as_dict()
+
     def set_poisson_mode(self, mode):
         L.check(self.lib.pic_set_poisson_mode(self.h, int(mode)), self.h)
 

@@ -68,7 +68,7 @@ def test_ensemble_equals_sequential():
     assert batch[0].diag()["step"] == 8
 
 
-def test_ensemble_rejects_mixed_sort_phase():
+def test_ensemble_rejects_mixed_sort_interval():
     from paper_2507_10727_amd.sim import Ensemble
     ps = sweep(2, 0.02)
     ps[1] = ps[1].replace(sort_every=5)
