@@ -1578,6 +1578,11 @@ pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *str
 {
     if (!out) return efail(nullptr, PIC_EINVAL, "out is NULL");
     *out = nullptr;
+    // Switched off: one 64-run ensemble step ended in a GPU memory fault whose
+    // cause is not yet found (see pic.h); nothing below runs until it is.
+    return efail(nullptr, PIC_ESTATE,
+                 "ensembles are switched off: a GPU memory fault in an ensemble step is not "
+                 "yet explained");
     if (!runs || nruns < 1) return efail(nullptr, PIC_EINVAL, "no runs");
     if (nstreams < 1 || nstreams > 16) return efail(nullptr, PIC_EINVAL, "nstreams outside [1, 16]");
     for (int r = 0; r < nruns; ++r) {

@@ -10,12 +10,14 @@
 // Dirichlet nodes (anode row, outer column, cathode nodes of z = 0) carry a
 // zero correction.
 //
-// One V-cycle is: per fine level a "down" kernel (red-black Gauss-Seidel
-// from a zero guess, residual, full-weighting restriction of the residual,
-// all in one LDS tile with a 3-node halo), one single-workgroup "tail" kernel
-// that runs every remaining coarse level in LDS and solves the coarsest with a
-// dense inverse, and per fine level an "up" kernel (bilinear prolongation,
-// black-red Gauss-Seidel, 2-node halo).  Pre-smoothing red-black and
+// One V-cycle is: per fine level a "down" kernel (MG_NU red-black
+// Gauss-Seidel pairs from a zero guess, residual, full-weighting restriction
+// of the residual, all in one LDS tile with a 1 + 2 MG_NU node halo), one
+// single-workgroup "tail" kernel that runs every remaining coarse level in
+// LDS and solves the coarsest with a dense inverse, and per fine level an
+// "up" kernel (bilinear prolongation, MG_NU black-red pairs, 2 MG_NU node
+// halo).  MG_NU = 1: with two pairs the CG iterations of a warm-started step
+// drop from 6 to 5 but each V-cycle costs more, so it does not pay.  Pre-smoothing red-black and
 // post-smoothing black-red with restriction = prolongation^T make the
 // preconditioner symmetric, as conjugate gradients requires.
 #include <cstring>
@@ -37,10 +39,17 @@ __device__ __forceinline__ float mg_prolong(const float *xc, int ldc, int i, int
     return 0.25f * (c[0] + c[1] + c[ldc] + c[ldc + 1]);
 }
 
+// red-black Gauss-Seidel pairs before (red, black) and after (black, red)
+// the coarse correction on every level; a half sweep is exact one node
+// further inside the tile than the one before it, so the tiles carry halos
+// of 1 + 2 MG_NU (down) and 2 MG_NU (up) fine nodes
+constexpr int MG_NU = 1;
 constexpr int DTX = 16, DTY = 8;                 // coarse nodes per down tile
-constexpr int DLW = 2 * DTX + 5, DLH = 2 * DTY + 5;
+constexpr int DH = 1 + 2 * MG_NU;
+constexpr int DLW = 2 * DTX + 2 * DH - 1, DLH = 2 * DTY + 2 * DH - 1;
 constexpr int UTX = 32, UTY = 16;                // fine nodes per up tile
-constexpr int ULW = UTX + 4, ULH = UTY + 4;
+constexpr int UH = 2 * MG_NU;
+constexpr int ULW = UTX + 2 * UH, ULH = UTY + 2 * UH;
 
 // Down: pre-smooth from zero, residual, restriction.  F.b is the fine
 // right-hand side; writes the smoothed F.xd and the coarse C.b.
@@ -50,7 +59,7 @@ __device__ __forceinline__ void mg_down_body(const MGLevel &F, const MGLevel &C,
     __shared__ float sb[DLH][DLW];
     __shared__ float sx[DLH][DLW];
     const int I0 = bx * DTX, J0 = by * DTY;
-    const int fi0 = 2 * I0 - 3, fj0 = 2 * J0 - 3;
+    const int fi0 = 2 * I0 - DH, fj0 = 2 * J0 - DH;
     const int ld = F.nr + 1;
     for (int t = threadIdx.x; t < DLW * DLH; t += 256) {
         const int li = t % DLW, lj = t / DLW;
@@ -68,21 +77,25 @@ __device__ __forceinline__ void mg_down_body(const MGLevel &F, const MGLevel &C,
         sx[lj][li] = xv;
     }
     __syncthreads();
-    // black nodes of the 1-halo region
-    for (int t = threadIdx.x; t < (DLW - 2) * (DLH - 2); t += 256) {
-        const int li = 1 + t % (DLW - 2), lj = 1 + t / (DLW - 2);
-        const int i = fi0 + li, j = fj0 + lj;
-        if (((i + j) & 1) != 1 || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
-        float w, e, s, n;
-        mg_coup(F, i, j, w, e, s, n);
-        const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
-                          n * sx[lj + 1][li];
-        sx[lj][li] = (sb[lj][li] + off) * __builtin_amdgcn_rcpf(w + e + s + n);
+    // half sweeps k = 1 .. 2 MG_NU - 1 (black, red, ...) on the region k
+    // nodes inside the tile
+    for (int k = 1; k < 2 * MG_NU; ++k) {
+        const int w_ = DLW - 2 * k, h_ = DLH - 2 * k, c = k & 1;
+        for (int t = threadIdx.x; t < w_ * h_; t += 256) {
+            const int li = k + t % w_, lj = k + t / w_;
+            const int i = fi0 + li, j = fj0 + lj;
+            if (((i + j) & 1) != c || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
+            float w, e, s, n;
+            mg_coup(F, i, j, w, e, s, n);
+            const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
+                              n * sx[lj + 1][li];
+            sx[lj][li] = (sb[lj][li] + off) * __builtin_amdgcn_rcpf(w + e + s + n);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // residual on the region the restriction reads (written over b)
-    for (int t = threadIdx.x; t < (DLW - 4) * (DLH - 4); t += 256) {
-        const int li = 2 + t % (DLW - 4), lj = 2 + t / (DLW - 4);
+    for (int t = threadIdx.x; t < (DLW - 4 * MG_NU) * (DLH - 4 * MG_NU); t += 256) {
+        const int li = 2 * MG_NU + t % (DLW - 4 * MG_NU), lj = 2 * MG_NU + t / (DLW - 4 * MG_NU);
         const int i = fi0 + li, j = fj0 + lj;
         float r = 0.0f;
         if (mg_in(F, i, j) && mg_unknown(F, i, j)) {
@@ -128,7 +141,7 @@ __device__ __forceinline__ void mg_up_body(const MGLevel &F, const MGLevel &C, d
     __shared__ float sx[ULH][ULW];
     __shared__ double red[4];
     const int i0 = bx * UTX, j0 = by * UTY;
-    const int fi0 = i0 - 2, fj0 = j0 - 2;
+    const int fi0 = i0 - UH, fj0 = j0 - UH;
     const int ld = F.nr + 1, ldc = C.nr + 1;
     for (int t = threadIdx.x; t < ULW * ULH; t += 256) {
         const int li = t % ULW, lj = t / ULW;
@@ -143,28 +156,22 @@ __device__ __forceinline__ void mg_up_body(const MGLevel &F, const MGLevel &C, d
         sx[lj][li] = xv;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < (ULW - 2) * (ULH - 2); t += 256) {
-        const int li = 1 + t % (ULW - 2), lj = 1 + t / (ULW - 2);
-        const int i = fi0 + li, j = fj0 + lj;
-        if (((i + j) & 1) != 1 || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
-        float w, e, s, n;
-        mg_coup(F, i, j, w, e, s, n);
-        const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
-                          n * sx[lj + 1][li];
-        sx[lj][li] = (sb[lj][li] + off) * __builtin_amdgcn_rcpf(w + e + s + n);
+    // half sweeps k = 0 .. 2 MG_NU - 1 (black, red, ...) on the region k + 1
+    // nodes inside the tile
+    for (int k = 0; k < 2 * MG_NU; ++k) {
+        const int w_ = ULW - 2 * (k + 1), h_ = ULH - 2 * (k + 1), c = (k & 1) ? 0 : 1;
+        for (int t = threadIdx.x; t < w_ * h_; t += 256) {
+            const int li = k + 1 + t % w_, lj = k + 1 + t / w_;
+            const int i = fi0 + li, j = fj0 + lj;
+            if (((i + j) & 1) != c || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
+            float w, e, s, n;
+            mg_coup(F, i, j, w, e, s, n);
+            const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
+                              n * sx[lj + 1][li];
+            sx[lj][li] = (sb[lj][li] + off) * __builtin_amdgcn_rcpf(w + e + s + n);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < (ULW - 4) * (ULH - 4); t += 256) {
-        const int li = 2 + t % (ULW - 4), lj = 2 + t / (ULW - 4);
-        const int i = fi0 + li, j = fj0 + lj;
-        if (((i + j) & 1) != 0 || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
-        float w, e, s, n;
-        mg_coup(F, i, j, w, e, s, n);
-        const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
-                          n * sx[lj + 1][li];
-        sx[lj][li] = (sb[lj][li] + off) * __builtin_amdgcn_rcpf(w + e + s + n);
-    }
-    __syncthreads();
     double acc = 0.0;
     for (int t = threadIdx.x; t < UTX * UTY; t += 256) {
         const int i = i0 + t % UTX, j = j0 + t / UTX;
@@ -229,10 +236,12 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
         const MGLevel &L = T.L[l];
         const int ld = L.nr + 1;
         float *x = X(l), *b = B(l);
-        tail_sweep(L, x, b, 0);
-        __syncthreads();
-        tail_sweep(L, x, b, 1);
-        __syncthreads();
+        for (int k = 0; k < MG_NU; ++k) {
+            tail_sweep(L, x, b, 0);
+            __syncthreads();
+            tail_sweep(L, x, b, 1);
+            __syncthreads();
+        }
         for (int j = ty; j <= L.nz; j += TT)
             for (int i = tx; i <= L.nr; i += TT) {
                 const int n = j * ld + i;
@@ -285,10 +294,12 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
             for (int i = tx; i <= L.nr; i += TT)
                 if (mg_unknown(L, i, j)) x[j * ld + i] += mg_prolong(X(l + 1), ldc, i, j);
         __syncthreads();
-        tail_sweep(L, x, b, 1);
-        __syncthreads();
-        tail_sweep(L, x, b, 0);
-        __syncthreads();
+        for (int k = 0; k < MG_NU; ++k) {
+            tail_sweep(L, x, b, 1);
+            __syncthreads();
+            tail_sweep(L, x, b, 0);
+            __syncthreads();
+        }
     }
     {
         const MGLevel &L = T.L[T.first];
