@@ -218,8 +218,8 @@ def main():
     ap.add_argument("--poisson-only", action="store_true",
                     help="only the field-solve comparison (prints its JSON)")
     ap.add_argument("--train-seconds", type=float, default=60.0)
-    ap.add_argument("--ensemble", action="store_true",
-                    help="also the batched sweep (ensembles are switched off in the library)")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the batched sweep of 64 runs")
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched sweep against sequential runs (prints its JSON)")
     ap.add_argument("--ensemble-runs", type=int, default=64)
@@ -302,7 +302,7 @@ def main():
         log("[bench] poisson 512x1024")
         poisson = poisson_bench(args.train_seconds)
     ensemble = None
-    if args.ensemble:
+    if not args.no_ensemble:
         log(f"[bench] ensemble of {args.ensemble_runs} runs")
         ensemble = ensemble_bench(args.ensemble_runs)
     cpu = None

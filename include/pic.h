@@ -325,10 +325,8 @@ pic_status pic_get_tuning(const pic_handle *h, pic_tuning *t);
  * while pic_ensemble_step runs.  The library owns the
  * streams, graphs and a small pinned status buffer; stream (nullable) is
  * where the graph launches.  Errors of pic_ensemble_step name the run:
- * PIC_ECAPACITY, PIC_ENOCONV, PIC_EHIP.
- * Currently switched off: pic_ensemble_create returns PIC_ESTATE, because one
- * step of a 64-run ensemble ended in a GPU memory fault whose cause has not
- * been found. */
+ * PIC_ECAPACITY, PIC_ENOCONV, PIC_EHIP.  Each run's descriptor of the
+ * batched solve is written into its own workspace at creation. */
 pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *stream,
                                int32_t nstreams, pic_ensemble **out);
 pic_status pic_ensemble_step(pic_ensemble *e, int32_t nsteps);

@@ -277,7 +277,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
         const int64_t top = words;
         for (int m = l; m < H.nlevels; ++m)
             words += 2 * (int64_t)(shapes[m].nr + 1) * (shapes[m].nz + 1);
-        if (top <= 2600 && words * 4 <= 128 * 1024) {
+        if (top <= 2600 && words * 4 <= MG_TAIL_LDS_MAX) {
             first = l;
             break;
         }
@@ -305,7 +305,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     const int dblocks = 256;
     double *dpart = cv.take<double>((int64_t)dblocks * 6 * 8);
     unsigned long long *live = cv.take<unsigned long long>(2 * 8);
-    RunSolve *rsolve = cv.take<RunSolve>(1);
+    RunSolve *rsolve = cv.take<RunSolve>(sizeof(RunSolve));
     // learned preconditioner: network, Adam state and activations
     const bool pc_on = c.pc_batch > 0 || c.poisson_mode == PIC_LEARNED;
     PcNet net;
@@ -1578,11 +1578,6 @@ pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *str
 {
     if (!out) return efail(nullptr, PIC_EINVAL, "out is NULL");
     *out = nullptr;
-    // Switched off: one 64-run ensemble step ended in a GPU memory fault whose
-    // cause is not yet found (see pic.h); nothing below runs until it is.
-    return efail(nullptr, PIC_ESTATE,
-                 "ensembles are switched off: a GPU memory fault in an ensemble step is not "
-                 "yet explained");
     if (!runs || nruns < 1) return efail(nullptr, PIC_EINVAL, "no runs");
     if (nstreams < 1 || nstreams > 16) return efail(nullptr, PIC_EINVAL, "nstreams outside [1, 16]");
     for (int r = 0; r < nruns; ++r) {
@@ -1652,6 +1647,10 @@ pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *str
         R.inv_2pi_eps0 = inv_2pi_eps0;
         R.circuit = c.circuit;
         R.scheme = c.scheme;
+        if ((const char *)h->rsolve + sizeof(RunSolve) > h->ws + h->ws_bytes) {
+            pic_ensemble_free(e);
+            return efail(nullptr, PIC_EINVAL, "run %d: no room for the run descriptor", r);
+        }
         if (hipMemcpy(h->rsolve, &R, sizeof(R), hipMemcpyHostToDevice) != hipSuccess) {
             pic_ensemble_free(e);
             return efail(nullptr, PIC_EHIP, "cannot upload the run descriptors");
@@ -1671,7 +1670,12 @@ pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *str
             if (h->prec == PIC_F64) sort_all<double>(h);
             else sort_all<float>(h);
         }
-        (void)hipStreamSynchronize(h->stream);
+        const hipError_t es = hipStreamSynchronize(h->stream);
+        if (es != hipSuccess) {
+            pic_ensemble_free(e);
+            return efail(nullptr, PIC_EHIP, "run %d: sort before the first step failed: %s", r,
+                         hipGetErrorString(es));
+        }
     }
     *out = e;
     return PIC_OK;

@@ -23,6 +23,7 @@ constexpr int PUSH_PPT = 4;                        // particles per thread per c
 constexpr int PUSH_CHUNK = PUSH_THREADS * PUSH_PPT;
 constexpr int LDS_NODES = 4096;                    // deposit tile capacity (nodes)
 constexpr int MAX_LEVELS = 16;
+constexpr int MG_TAIL_LDS_MAX = 128 * 1024;        // dynamic LDS of the coarse-level kernels
 constexpr int MAX_PCG = 512;
 
 enum : int32_t { FLAG_CAPACITY = 1, FLAG_CHILD_OVERFLOW = 2, FLAG_NAN = 4 };

@@ -594,12 +594,16 @@ void launch_cg_update_b(const BatchPlan &P, int k, hipStream_t s)
     hipLaunchKernelGGL(k_cg_update_b, dim3(a.off[P.nruns]), dim3(CB), 0, s, a);
 }
 
+// The attribute is per kernel, not per hierarchy: both tail kernels get the
+// largest tail any hierarchy may have, so runs of different sizes in one
+// process never launch above the limit another run set.
 int mg_tail_setup(MGHier &H)
 {
+    if (H.tail_lds_bytes > MG_TAIL_LDS_MAX) return 1;
     int e = (int)hipFuncSetAttribute((const void *)k_mg_tail,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, H.tail_lds_bytes);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, MG_TAIL_LDS_MAX);
     e |= (int)hipFuncSetAttribute((const void *)k_mg_tail_b,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, MG_TAIL_LDS_MAX);
     return e;
 }
 

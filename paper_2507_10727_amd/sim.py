@@ -54,6 +54,15 @@ def make_config(prob: W.Problem, b_r, b_z, sigma, de_table=W.DE_TABLE, capacity=
     return c, (sig, br, bz)
 
 
+def workspace_bytes(prob: W.Problem, b_r, b_z, sigma, capacity=None) -> int:
+    """Device bytes a Simulation of prob needs (pic_query_workspace)."""
+    cfg, keep = make_config(prob, b_r, b_z, sigma, capacity=capacity)
+    nbytes = C.c_int64()
+    L.check(L.load().pic_query_workspace(C.byref(cfg), C.byref(nbytes)))
+    del keep
+    return int(nbytes.value)
+
+
 class Simulation:
     """One discharge on one GPU.
 
@@ -62,7 +71,7 @@ class Simulation:
     """
 
     def __init__(self, prob: W.Problem, b_r, b_z, sigma, particles=None, device="cuda:0",
-                 capacity=None, timers=False):
+                 capacity=None, timers=False, workspace=None):
         import torch
 
         self.torch = torch
@@ -73,7 +82,15 @@ class Simulation:
         self.cfg = cfg
         nbytes = C.c_int64()
         L.check(self.lib.pic_query_workspace(C.byref(cfg), C.byref(nbytes)))
-        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        else:
+            # caller-provided device bytes (e.g. a slice of a larger buffer)
+            if (workspace.dtype != torch.uint8 or not workspace.is_cuda
+                    or workspace.numel() < nbytes.value or workspace.data_ptr() % 256):
+                raise ValueError(f"workspace must be a 256-byte aligned CUDA uint8 tensor of at "
+                                 f"least {nbytes.value} bytes")
+            self.ws = workspace
         # a stream of our own (default priority): the library captures its
         # field-solve passes as graphs, which the legacy null stream forbids
         self.stream = torch.cuda.Stream(device=self.device)
