@@ -300,7 +300,7 @@ pic_status pic_set_poisson_mode(pic_handle *h, int32_t mode);
  * shape changes no result beyond the summation order of the FP32 deposit.
  * pic_set_tuning applies a stored choice (e.g. from a run of the same size). */
 typedef struct pic_tuning {
-    int32_t push_blocks;        /* default 2048                                   */
+    int32_t push_blocks;        /* default 1024                                   */
     double push_e_weight;       /* default 1.3                                    */
     double push_ms;             /* autotune: mean particle-kernel time chosen     */
     int32_t trials;

@@ -80,7 +80,7 @@ struct pic_handle {
     // launch shape of the particle kernel (autotuned): total blocks and the
     // weight of an electron against an ion when splitting them
     RunSolve *rsolve = nullptr;     // descriptor of the batched field update
-    int push_blocks = 2048;
+    int push_blocks = 1024;
     double push_e_weight = 1.3;
     int32_t host_flags = 0;
     bool timers_on = false;

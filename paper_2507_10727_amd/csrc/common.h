@@ -21,7 +21,7 @@ namespace pic {
 constexpr int PUSH_THREADS = 256;
 constexpr int PUSH_PPT = 4;                        // particles per thread per chunk
 constexpr int PUSH_CHUNK = PUSH_THREADS * PUSH_PPT;
-constexpr int LDS_NODES = 4096;                    // deposit tile capacity (nodes)
+constexpr int LDS_NODES = 4096;                    // deposit tiles of a block (nodes)
 constexpr int MAX_LEVELS = 16;
 constexpr int MG_TAIL_LDS_MAX = 128 * 1024;        // dynamic LDS of the coarse-level kernels
 constexpr int MAX_PCG = 512;
@@ -179,6 +179,15 @@ __device__ __forceinline__ void sincos_2pi(float u, float *s, float *c) { sincos
 __device__ __forceinline__ void sincos_2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
 
 // ----------------------------------------------------------- wave helpers --
+// Order the LDS accesses of one wavefront's lanes before and after this point
+// (the lanes of a wavefront share the instruction stream; this keeps the
+// compiler from moving LDS accesses across it).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ int wave_min(int v)
 {
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));

@@ -18,9 +18,11 @@ namespace pic {
 // Particles are kept sorted by cell, so a thread's 4 particles usually share
 // a cell: the 4 node 4-vectors of the gather are loaded once per distinct
 // cell, and the deposit is summed in registers per run of equal cells before
-// it goes to LDS.  The chunk's charge is accumulated in LDS over the box of
-// nodes it touches and flushed with one global atomic per node; a chunk whose
-// box does not fit (an unsorted or scattered chunk) uses global atomics.
+// it goes to LDS.  Each wavefront accumulates its 256 particles' charge in
+// its own LDS tile over the box of nodes they touch and flushes it with one
+// global atomic per node; a box that does not fit (unsorted or scattered
+// particles) uses global atomics.  The wavefronts of a block never wait for
+// each other inside the chunk loop, so one's loads overlap another's deposit.
 //
 // Per particle (Section 2 for the gather, Section 3 for walls, emission and
 // collisions):
@@ -292,6 +294,49 @@ __device__ __forceinline__ void scatter(const PushCold<T> *C, DevScalars *sc, ui
     v[2] = vn * d2;
 }
 
+// Lane moves of the data-parallel primitives (DPP): row_shr:n shifts by n
+// lanes within rows of 16, row_bcast:15 / :31 pass lane 15 of a row (lane 31)
+// to the next row (to the upper half).  Lanes without a source read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Segmented inclusive sum over the wavefront: lane l ends with the sum of
+// lanes first..l of its segment (first = the segment's first lane), computed
+// with four in-row shifts and two row broadcasts.
+template <typename T>
+__device__ __forceinline__ void wave_segment_sum(T &a0, T &a1, T &a2, T &a3, int lane, int first)
+{
+#define PIC_SEG_STEP(CTRL, ROWS, COND)                                                  \
+    {                                                                                 \
+        const T b0 = dpp_move<CTRL, ROWS>(a0), b1 = dpp_move<CTRL, ROWS>(a1);         \
+        const T b2 = dpp_move<CTRL, ROWS>(a2), b3 = dpp_move<CTRL, ROWS>(a3);         \
+        if (COND) {                                                                   \
+            a0 += b0;                                                                 \
+            a1 += b1;                                                                 \
+            a2 += b2;                                                                 \
+            a3 += b3;                                                                 \
+        }                                                                             \
+    }
+    PIC_SEG_STEP(0x111, 0xF, (lane & 15) >= 1 && lane - 1 >= first)
+    PIC_SEG_STEP(0x112, 0xF, (lane & 15) >= 2 && lane - 2 >= first)
+    PIC_SEG_STEP(0x114, 0xF, (lane & 15) >= 4 && lane - 4 >= first)
+    PIC_SEG_STEP(0x118, 0xF, (lane & 15) >= 8 && lane - 8 >= first)
+    PIC_SEG_STEP(0x142, 0xA, ((lane >> 4) & 1) && first <= (lane & ~15) - 1)
+    PIC_SEG_STEP(0x143, 0xC, lane >= 32 && first <= 31)
+#undef PIC_SEG_STEP
+}
+
 // Add one run's summed tent weights to its cell's four nodes.
 template <typename T>
 __device__ __forceinline__ void deposit_lds(T *lds, int ld, int key, T qw, T a00, T a10, T a01,
@@ -325,18 +370,49 @@ __device__ __forceinline__ void enqueue(int2 *q, int *count, int cap, int slot, 
     if (e < cap) q[e] = make_int2(slot, aux);
 }
 
+// Streaming 16-byte loads and stores of the particle arrays.  The arrays
+// pass through once per step, so they are marked non-temporal: they do not
+// displace the node arrays of the gather from the caches.
+template <typename V, typename E>
+__device__ __forceinline__ V stream_load_v(const V *p)
+{
+    typedef E vec __attribute__((ext_vector_type(4)));
+    const vec t = __builtin_nontemporal_load((const vec *)p);
+    V r;
+    r.x = t[0];
+    r.y = t[1];
+    r.z = t[2];
+    r.w = t[3];
+    return r;
+}
+template <typename V, typename E>
+__device__ __forceinline__ void stream_store_v(V *p, const V &v)
+{
+    typedef E vec __attribute__((ext_vector_type(4)));
+    const vec t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, (vec *)p);
+}
+__device__ __forceinline__ int4 stream_load(const int4 *p) { return stream_load_v<int4, int>(p); }
+__device__ __forceinline__ uint4 stream_load(const uint4 *p) { return stream_load_v<uint4, unsigned>(p); }
+__device__ __forceinline__ float4 stream_load(const float4 *p) { return stream_load_v<float4, float>(p); }
+__device__ __forceinline__ double4 stream_load(const double4 *p) { return stream_load_v<double4, double>(p); }
+__device__ __forceinline__ void stream_store(int4 *p, const int4 &v) { stream_store_v<int4, int>(p, v); }
+__device__ __forceinline__ void stream_store(float4 *p, const float4 &v) { stream_store_v<float4, float>(p, v); }
+__device__ __forceinline__ void stream_store(double4 *p, const double4 &v) { stream_store_v<double4, double>(p, v); }
+
 template <typename T, int SCHEME>
 __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
 {
     using T4 = typename Vec4<T>::type;
     constexpr int NW = PUSH_THREADS / 64;
+    constexpr int WAVE_NODES = LDS_NODES / NW;
     __shared__ T lds_q[LDS_NODES];
-    __shared__ int red[4][NW];
     __shared__ double dred[3][NW];
     __shared__ unsigned long long cred[10][NW];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
+    T *const tile = lds_q + wid * WAVE_NODES;
     const int s = ((int)blockIdx.x < P.nblk_e) ? 0 : 1;
     const int blk = s ? (int)blockIdx.x - P.nblk_e : (int)blockIdx.x;
     const int nblk = s ? (int)gridDim.x - P.nblk_e : P.nblk_e;
@@ -369,12 +445,12 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
         if (any) {
             // slots p0..p0+3 are inside the (4-rounded) capacity; those at or
             // beyond the count are masked and written back unchanged
-            const int4 k4 = *(const int4 *)(KEY + p0);
-            const T4 a = *(const T4 *)(FR + p0);
-            const T4 b = *(const T4 *)(FZ + p0);
-            const T4 c = *(const T4 *)(VR + p0);
-            const T4 d = *(const T4 *)(VT + p0);
-            const T4 e = *(const T4 *)(VZ + p0);
+            const int4 k4 = stream_load((const int4 *)(KEY + p0));
+            const T4 a = stream_load((const T4 *)(FR + p0));
+            const T4 b = stream_load((const T4 *)(FZ + p0));
+            const T4 c = stream_load((const T4 *)(VR + p0));
+            const T4 d = stream_load((const T4 *)(VT + p0));
+            const T4 e = stream_load((const T4 *)(VZ + p0));
             kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
             fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
             fz[0] = b.x; fz[1] = b.y; fz[2] = b.z; fz[3] = b.w;
@@ -382,7 +458,7 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
             vt[0] = d.x; vt[1] = d.y; vt[2] = d.z; vt[3] = d.w;
             vz[0] = e.x; vz[1] = e.y; vz[2] = e.z; vz[3] = e.w;
             if (collide_on) {
-                const uint4 iv = *(const uint4 *)(ID + p0);
+                const uint4 iv = stream_load((const uint4 *)(ID + p0));
                 id[0] = iv.x; id[1] = iv.y; id[2] = iv.z; id[3] = iv.w;
             }
 #pragma unroll
@@ -444,18 +520,18 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
                 kk[k] = ok[k] = (j << 16) | i;
             }
             if (any) {
-                *(int4 *)(KEY + p0) = make_int4(kk[0], kk[1], kk[2], kk[3]);
+                stream_store((int4 *)(KEY + p0), make_int4(kk[0], kk[1], kk[2], kk[3]));
                 T4 a, b, c, d, e;
                 a.x = fr[0]; a.y = fr[1]; a.z = fr[2]; a.w = fr[3];
                 b.x = fz[0]; b.y = fz[1]; b.z = fz[2]; b.w = fz[3];
                 c.x = vr[0]; c.y = vr[1]; c.z = vr[2]; c.w = vr[3];
                 d.x = vt[0]; d.y = vt[1]; d.z = vt[2]; d.w = vt[3];
                 e.x = vz[0]; e.y = vz[1]; e.z = vz[2]; e.w = vz[3];
-                *(T4 *)(FR + p0) = a;
-                *(T4 *)(FZ + p0) = b;
-                *(T4 *)(VR + p0) = c;
-                *(T4 *)(VT + p0) = d;
-                *(T4 *)(VZ + p0) = e;
+                stream_store((T4 *)(FR + p0), a);
+                stream_store((T4 *)(FZ + p0), b);
+                stream_store((T4 *)(VR + p0), c);
+                stream_store((T4 *)(VT + p0), d);
+                stream_store((T4 *)(VZ + p0), e);
             }
         } else {
 #pragma unroll
@@ -471,7 +547,8 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
         t.ke += (double)ke_c;
         t.pz += (double)pz_c;
 
-        // ---- deposit: block bounding box of the chunk's cells
+        // ---- deposit: bounding box of the wavefront's cells, accumulated
+        // in the wavefront's own LDS tile (no wavefront waits for another)
         int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -482,37 +559,37 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
         }
         imin = wave_min(imin); imax = wave_max(imax);
         jmin = wave_min(jmin); jmax = wave_max(jmax);
-        if (lane == 0) {
-            red[0][wid] = imin; red[1][wid] = imax;
-            red[2][wid] = jmin; red[3][wid] = jmax;
-        }
-        __syncthreads();
-        imin = red[0][0]; imax = red[1][0]; jmin = red[2][0]; jmax = red[3][0];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) {
-            imin = min(imin, red[0][w]); imax = max(imax, red[1][w]);
-            jmin = min(jmin, red[2][w]); jmax = max(jmax, red[3][w]);
-        }
         if (imax >= imin) {
             const int bw = imax - imin + 2, bh = jmax - jmin + 2;
-            const bool use_lds = bw * bh <= LDS_NODES;
+            const bool use_lds = bw * bh <= WAVE_NODES;
             if (use_lds) {
-                for (int q = tid; q < bw * bh; q += PUSH_THREADS) lds_q[q] = (T)0;
-                __syncthreads();
-            } else if (tid == 0) {
+                for (int q = lane; q < bw * bh; q += 64) tile[q] = (T)0;
+                wave_sync();
+            } else if (lane == 0) {
                 ++t.fb;
             }
             const int shift = (jmin << 16) | imin;
-            // sum the thread's particles per run of equal cells, then add
-            int cur = -1;
+            auto add_run = [&](int key, T a00, T a10, T a01, T a11) {
+                if (use_lds) deposit_lds(tile, bw, key - shift, qw, a00, a10, a01, a11);
+                else deposit_global(Q, ldn, key, qw, a00, a10, a01, a11);
+            };
+            // the thread's particles summed per run of equal cells: the first
+            // run joins the wavefront's per-cell sum, later runs (the thread's
+            // particles span a cell boundary) are added directly
+            int cur = -1, key0 = -1;
             T s00 = 0, s10 = 0, s01 = 0, s11 = 0;
+            T f00 = 0, f10 = 0, f01 = 0, f11 = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (ok[k] < 0) continue;
                 if (ok[k] != cur) {
                     if (cur >= 0) {
-                        if (use_lds) deposit_lds(lds_q, bw, cur - shift, qw, s00, s10, s01, s11);
-                        else deposit_global(Q, ldn, cur, qw, s00, s10, s01, s11);
+                        if (key0 < 0) {
+                            key0 = cur;
+                            f00 = s00; f10 = s10; f01 = s01; f11 = s11;
+                        } else {
+                            add_run(cur, s00, s10, s01, s11);
+                        }
                     }
                     cur = ok[k];
                     s00 = s10 = s01 = s11 = (T)0;
@@ -524,21 +601,39 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
                 s11 += fr[k] * fz[k];
             }
             if (cur >= 0) {
-                if (use_lds) deposit_lds(lds_q, bw, cur - shift, qw, s00, s10, s01, s11);
-                else deposit_global(Q, ldn, cur, qw, s00, s10, s01, s11);
+                if (key0 < 0) {
+                    key0 = cur;
+                    f00 = s00; f10 = s10; f01 = s01; f11 = s11;
+                } else {
+                    add_run(cur, s00, s10, s01, s11);
+                }
             }
+            // per-cell sums over the wavefront's lanes: adjacent lanes whose
+            // first runs share a cell form a segment, its last lane adds the
+            // total (sorted particles make segments long, so few lanes add
+            // and the LDS atomics rarely meet on one address)
+            const bool valid = key0 >= 0;
+            const int prev = __shfl_up(key0, 1, 64), next = __shfl_down(key0, 1, 64);
+            const bool head = valid && (lane == 0 || prev != key0);
+            const bool tail = valid && (lane == 63 || next != key0);
+            const unsigned long long upto =
+                (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+            const unsigned long long hb = __ballot(head) & upto;
+            const int first = hb ? 63 - __clzll(hb) : lane;
+            wave_segment_sum(f00, f10, f01, f11, lane, first);
+            if (tail) add_run(key0, f00, f10, f01, f11);
             if (use_lds) {
-                __syncthreads();
-                for (int q = tid; q < bw * bh; q += PUSH_THREADS) {
-                    const T v = lds_q[q];
+                wave_sync();
+                for (int q = lane; q < bw * bh; q += 64) {
+                    const T v = tile[q];
                     if (v != (T)0) {
                         const int lj = q / bw, li = q - lj * bw;
                         atomic_add_dev(&Q[(int64_t)(jmin + lj) * ldn + imin + li], v);
                     }
                 }
+                wave_sync();
             }
         }
-        __syncthreads();
     }
 
     // ---- block totals of the diagnostics, one atomic per quantity
