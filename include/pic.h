@@ -116,10 +116,15 @@ typedef struct pic_species_host {
 } pic_species_host;
 
 /* Device view of one species' particle arrays (valid until the next call
- * that sorts: pic_step, pic_compact).  Slot k is live iff key[k] >= 0.
- * key = j << 16 | i (cell), fr/fz = in-cell fraction in [0,1) of the
- * precision given, so r = (i + fr) * dr; velocities are v^{n-1/2} in
- * (r, theta, z) components. */
+ * that sorts: pic_step, pic_compact).  Positions are relative to the cell
+ * (i, j), so r = (i + fr) * dr; velocities are v^{n-1/2} in (r, theta, z)
+ * components.
+ *   FP64 state (pos_bits = 0): key = j << 16 | i (-1: absorbed slot), fr/fz
+ *     the in-cell fractions in [0,1) as doubles.
+ *   FP32 state (pos_bits = 21, key_dev = NULL): fr_dev / fz_dev hold packed
+ *     32-bit words pr = i << 21 | round(fr 2^21), pz = j << 21 |
+ *     round(fz 2^21), pz = -1 for an absorbed slot (no key word is stored;
+ *     cells are limited to 1024 per axis). */
 typedef struct pic_particle_view {
     int32_t *key_dev;
     void *fr_dev, *fz_dev, *vr_dev, *vt_dev, *vz_dev;
@@ -127,6 +132,7 @@ typedef struct pic_particle_view {
     int64_t count;              /* slots in use (live + not yet compacted)        */
     int64_t capacity;
     int32_t precision;
+    int32_t pos_bits;           /* 0: key + fractions; 21: packed FP32 words      */
 } pic_particle_view;
 
 /* Device view of the node fields (FP64 unless stated). */

@@ -61,7 +61,7 @@ class pic_particle_view(C.Structure):
     _fields_ = [("key_dev", C.c_void_p), ("fr_dev", C.c_void_p), ("fz_dev", C.c_void_p),
                 ("vr_dev", C.c_void_p), ("vt_dev", C.c_void_p), ("vz_dev", C.c_void_p),
                 ("id_dev", C.c_void_p), ("count", C.c_int64), ("capacity", C.c_int64),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("pos_bits", C.c_int32)]
 
 
 class pic_field_view(C.Structure):

@@ -140,6 +140,9 @@ pic_status validate(const pic_config *c, pic_handle *h)
     if (!c) return fail(h, PIC_EINVAL, "config is NULL");
     if (c->nr < 2 || c->nz < 2 || c->nr > 65535 || c->nz > 32767)
         return fail(h, PIC_EINVAL, "grid %d x %d outside [2, 65535] x [2, 32767]", c->nr, c->nz);
+    if (c->precision == PIC_F32 && (c->nr > POS_MAX_CELLS || c->nz > POS_MAX_CELLS))
+        return fail(h, PIC_EINVAL, "FP32 state packs the cell into %d bits: at most %d cells per axis",
+                    31 - POS_BITS, POS_MAX_CELLS);
     if (!(c->lr > 0) || !(c->lz > 0) || !(c->dt > 0))
         return fail(h, PIC_EINVAL, "lr, lz and dt must be positive");
     if (c->scheme != PIC_MC && c->scheme != PIC_EC) return fail(h, PIC_EINVAL, "bad scheme");
@@ -349,6 +352,14 @@ template <typename T>
 SpeciesDev<T> species_dev(const Buf &b)
 {
     return SpeciesDev<T>{b.key, (T *)b.fr, (T *)b.fz, (T *)b.vr, (T *)b.vt, (T *)b.vz, b.id};
+}
+
+// Words of the current buffer that are negative exactly for absorbed slots:
+// the key (FP64 state) or the packed z word (FP32 state).
+const int32_t *live_key_words(const pic_handle *h, int s)
+{
+    const Buf &b = h->buf[s][h->cur[s]];
+    return h->prec == PIC_F64 ? b.key : (const int32_t *)b.fz;
 }
 
 // ---- timers
@@ -1307,7 +1318,7 @@ pic_status pic_diag(pic_handle *h, pic_diag_out *out)
     memset(out, 0, sizeof(*out));
     launch_zero(h->live, 16, h->stream);
     for (int s = 0; s < 2; ++s)
-        launch_count_live(h->buf[s][h->cur[s]].key, h->sc, s, h->live + s, h->stream);
+        launch_count_live(live_key_words(h, s), h->sc, s, h->live + s, h->stream);
     if (h->prec == PIC_F64)
         launch_diag_grid<double>(h->f, (const double *)h->q[0], (const double *)h->q[1], c.q[0],
                                  c.q[1], h->diag_partials, h->diag_blocks, h->stream);
@@ -1369,7 +1380,8 @@ pic_status pic_particles(pic_handle *h, int32_t species, pic_particle_view *out)
     HIPCHECK(h, hipMemcpyAsync(&cnt, &h->sc->count[species], 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     const Buf &b = h->buf[species][h->cur[species]];
-    out->key_dev = b.key;
+    out->key_dev = h->prec == PIC_F64 ? b.key : nullptr;
+    out->pos_bits = h->prec == PIC_F64 ? 0 : POS_BITS;
     out->fr_dev = b.fr;
     out->fz_dev = b.fz;
     out->vr_dev = b.vr;

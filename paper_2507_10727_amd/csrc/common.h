@@ -62,12 +62,92 @@ struct DevScalars {
     int32_t solve_done, solve_passes, solve_iters, solve_pad;
 };
 
+// Particle arrays of one species (structure of arrays).
+//
+// Positions are kept relative to the particle's cell.  FP64 state: key =
+// j << 16 | i (-1 once absorbed) and the in-cell fractions fr, fz in [0, 1)
+// as FP64.  FP32 state packs the cell into the fraction words, so a particle
+// carries no key word: pr = i << 21 | round(fr 2^21) and pz = j << 21 |
+// round(fz 2^21) (-1 once absorbed), stored in the fr / fz arrays, key unused.
+// Both words are non-negative for live particles (cells < 1024 per axis),
+// and the fractions resolve 2^-21 of a cell.
 template <typename T>
 struct SpeciesDev {
     int32_t *key;
     T *fr, *fz, *vr, *vt, *vz;
     uint32_t *id;
 };
+
+constexpr int POS_BITS = 21;                       // fraction bits of a packed word
+constexpr int POS_MAX_CELLS = 1 << (31 - POS_BITS); // cells per axis with FP32 state
+constexpr uint32_t POS_MASK = (1u << POS_BITS) - 1u;
+
+// packed word of cell index c and in-cell fraction f in [0, 1), rounded to
+// nearest (the top 2^-22 of a cell rounds down, never into the next cell)
+__device__ __forceinline__ uint32_t pos_pack(int c, float f)
+{
+    const uint32_t q = (uint32_t)rintf(f * (float)(1u << POS_BITS));
+    return ((uint32_t)c << POS_BITS) | min(q, POS_MASK);
+}
+__device__ __forceinline__ int pos_cell(uint32_t w) { return (int)(w >> POS_BITS); }
+__device__ __forceinline__ float pos_frac(uint32_t w)
+{
+    return (float)(w & POS_MASK) * (1.0f / (float)(1u << POS_BITS));
+}
+
+// An in-cell offset as the state stores it: FP32 rounds to the packed
+// fraction, FP64 keeps it.
+__device__ __forceinline__ float pos_round(float f)
+{
+    const float q = fminf(rintf(f * (float)(1u << POS_BITS)), (float)POS_MASK);
+    return fmaxf(q, 0.0f) * (1.0f / (float)(1u << POS_BITS));
+}
+__device__ __forceinline__ double pos_round(double f) { return f; }
+
+// Position of slot p: returns the key j << 16 | i (-1 if absorbed) and the
+// fractions (also of an absorbed slot: its last cell and offsets).
+template <typename T>
+__device__ __forceinline__ int load_pos(const SpeciesDev<T> &S, int64_t p, T &fr, T &fz, int &i)
+{
+    if constexpr (sizeof(T) == 4) {
+        const uint32_t wr = ((const uint32_t *)S.fr)[p];
+        const int32_t wz = ((const int32_t *)S.fz)[p];
+        i = pos_cell(wr);
+        fr = pos_frac(wr);
+        fz = wz >= 0 ? pos_frac((uint32_t)wz) : (T)0;
+        return wz >= 0 ? (pos_cell((uint32_t)wz) << 16) | i : -1;
+    } else {
+        const int k = S.key[p];
+        fr = S.fr[p];
+        fz = S.fz[p];
+        i = k >= 0 ? (k & 0xffff) : 0;
+        return k;
+    }
+}
+
+// Store the position of slot p: live in cell (i, j), or absorbed (alive =
+// false; FP32 keeps i and fr in the pr word).
+template <typename T>
+__device__ __forceinline__ void store_pos(const SpeciesDev<T> &S, int64_t p, bool alive, int i,
+                                          int j, T fr, T fz)
+{
+    if constexpr (sizeof(T) == 4) {
+        ((uint32_t *)S.fr)[p] = pos_pack(min(max(i, 0), POS_MAX_CELLS - 1), fr);
+        ((int32_t *)S.fz)[p] = alive ? (int32_t)pos_pack(j, fz) : -1;
+    } else {
+        S.key[p] = alive ? ((j << 16) | i) : -1;
+        S.fr[p] = fr;
+        S.fz[p] = fz;
+    }
+}
+
+// Word that is negative exactly for absorbed slots (sort, live counts).
+template <typename T>
+__host__ __device__ __forceinline__ const int32_t *live_words(const SpeciesDev<T> &S)
+{
+    if constexpr (sizeof(T) == 4) return (const int32_t *)S.fz;
+    else return S.key;
+}
 
 // A particle created during the push (ionization products, emitted
 // secondaries).  skey orders children by (parent species, parent id, kind).
@@ -153,9 +233,12 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        uint32_t hi0 = __umulhi(m0, c.x), lo0 = m0 * c.x;
-        uint32_t hi1 = __umulhi(m1, c.z), lo1 = m1 * c.z;
+        // one 32 x 32 -> 64-bit product per multiplier (a single
+        // v_mad_u64_u32, instead of separate high and low multiplies)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;

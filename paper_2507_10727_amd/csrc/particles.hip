@@ -370,6 +370,28 @@ __device__ __forceinline__ void enqueue(int2 *q, int *count, int cap, int slot, 
     if (e < cap) q[e] = make_int2(slot, aux);
 }
 
+// Impact point of an ion absorbed on the cathode, carried by its emission
+// queue entry: FP32 state passes the packed radial word (the slot keeps no
+// position once absorbed), FP64 state the radial cell, the offset staying in
+// the slot.
+template <typename T>
+__device__ __forceinline__ int see_aux(int i, T fr)
+{
+    if constexpr (sizeof(T) == 4) return (int)pos_pack(min(max(i, 0), POS_MAX_CELLS - 1), fr);
+    else return i;
+}
+template <typename T>
+__device__ __forceinline__ void see_impact(const SpeciesDev<T> &S, int2 q, int &i, T &fr)
+{
+    if constexpr (sizeof(T) == 4) {
+        i = pos_cell((uint32_t)q.y);
+        fr = pos_frac((uint32_t)q.y);
+    } else {
+        i = q.y;
+        fr = S.fr[q.x];
+    }
+}
+
 // Streaming 16-byte loads and stores of the particle arrays.  The arrays
 // pass through once per step, so they are marked non-temporal: they do not
 // displace the node arrays of the gather from the caches.
@@ -445,15 +467,29 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
         if (any) {
             // slots p0..p0+3 are inside the (4-rounded) capacity; those at or
             // beyond the count are masked and written back unchanged
-            const int4 k4 = stream_load((const int4 *)(KEY + p0));
-            const T4 a = stream_load((const T4 *)(FR + p0));
-            const T4 b = stream_load((const T4 *)(FZ + p0));
+            if constexpr (sizeof(T) == 4) {
+                const uint4 wr = stream_load((const uint4 *)(FR + p0));
+                const int4 wz = stream_load((const int4 *)(FZ + p0));
+                const uint32_t r4[4] = {wr.x, wr.y, wr.z, wr.w};
+                const int32_t z4[4] = {wz.x, wz.y, wz.z, wz.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    fr[k] = pos_frac(r4[k]);
+                    const bool live = z4[k] >= 0;
+                    fz[k] = live ? pos_frac((uint32_t)z4[k]) : (T)0;
+                    kk[k] = live ? ((pos_cell((uint32_t)z4[k]) << 16) | pos_cell(r4[k])) : -1;
+                }
+            } else {
+                const int4 k4 = stream_load((const int4 *)(KEY + p0));
+                const T4 a = stream_load((const T4 *)(FR + p0));
+                const T4 b = stream_load((const T4 *)(FZ + p0));
+                kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
+                fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
+                fz[0] = b.x; fz[1] = b.y; fz[2] = b.z; fz[3] = b.w;
+            }
             const T4 c = stream_load((const T4 *)(VR + p0));
             const T4 d = stream_load((const T4 *)(VT + p0));
             const T4 e = stream_load((const T4 *)(VZ + p0));
-            kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
-            fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
-            fz[0] = b.x; fz[1] = b.y; fz[2] = b.z; fz[3] = b.w;
             vr[0] = c.x; vr[1] = c.y; vr[2] = c.z; vr[3] = c.w;
             vt[0] = d.x; vt[1] = d.y; vt[2] = d.z; vt[3] = d.w;
             vz[0] = e.x; vz[1] = e.y; vz[2] = e.z; vz[3] = e.w;
@@ -499,7 +535,9 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
                         ++t.abs1;
                         t.dq += P.cold->qw64[s];
                         // emission is decided in the event kernel
-                        if (emit) enqueue(P.see_q, &P.sc->n_see_q, P.ev_cap, (int)(p0 + k), i);
+                        if (emit)
+                            enqueue(P.see_q, &P.sc->n_see_q, P.ev_cap, (int)(p0 + k),
+                                    see_aux<T>(i, fr[k]));
                     } else if (fate == 2) {
                         ++t.abs2;
                     } else if (fate == 3) {
@@ -517,18 +555,34 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
                     if ((unsigned long long)u.x < P.t_null)
                         enqueue(P.mcc_q, &P.sc->n_mcc_q, P.ev_cap, (int)(p0 + k), 0);
                 }
+                fr[k] = pos_round(fr[k]);   // the stored (FP32: rounded) offsets
+                fz[k] = pos_round(fz[k]);
                 kk[k] = ok[k] = (j << 16) | i;
             }
             if (any) {
-                stream_store((int4 *)(KEY + p0), make_int4(kk[0], kk[1], kk[2], kk[3]));
-                T4 a, b, c, d, e;
-                a.x = fr[0]; a.y = fr[1]; a.z = fr[2]; a.w = fr[3];
-                b.x = fz[0]; b.y = fz[1]; b.z = fz[2]; b.w = fz[3];
+                if constexpr (sizeof(T) == 4) {
+                    uint32_t r4[4];
+                    int32_t z4[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        // an absorbed slot keeps no position (pz = -1, pr = 0)
+                        r4[k] = kk[k] >= 0 ? pos_pack(kk[k] & 0xffff, fr[k]) : 0u;
+                        z4[k] = kk[k] >= 0 ? (int32_t)pos_pack(kk[k] >> 16, fz[k]) : -1;
+                    }
+                    stream_store((int4 *)(FR + p0), make_int4((int)r4[0], (int)r4[1], (int)r4[2], (int)r4[3]));
+                    stream_store((int4 *)(FZ + p0), make_int4(z4[0], z4[1], z4[2], z4[3]));
+                } else {
+                    stream_store((int4 *)(KEY + p0), make_int4(kk[0], kk[1], kk[2], kk[3]));
+                    T4 a, b;
+                    a.x = fr[0]; a.y = fr[1]; a.z = fr[2]; a.w = fr[3];
+                    b.x = fz[0]; b.y = fz[1]; b.z = fz[2]; b.w = fz[3];
+                    stream_store((T4 *)(FR + p0), a);
+                    stream_store((T4 *)(FZ + p0), b);
+                }
+                T4 c, d, e;
                 c.x = vr[0]; c.y = vr[1]; c.z = vr[2]; c.w = vr[3];
                 d.x = vt[0]; d.y = vt[1]; d.z = vt[2]; d.w = vt[3];
                 e.x = vz[0]; e.y = vz[1]; e.z = vz[2]; e.w = vz[3];
-                stream_store((T4 *)(FR + p0), a);
-                stream_store((T4 *)(FZ + p0), b);
                 stream_store((T4 *)(VR + p0), c);
                 stream_store((T4 *)(VT + p0), d);
                 stream_store((T4 *)(VZ + p0), e);
@@ -692,12 +746,14 @@ __global__ void __launch_bounds__(256) k_events(EventParams<T> P)
         if (e < nm) {
             const int p = P.mcc_q[e].x;
             const SpeciesDev<T> S = P.sp[0];
-            const int key = S.key[p];
+            T pfr, pfz;
+            int pi;
+            const int key = load_pos(S, p, pfr, pfz, pi);
             const uint32_t id = S.id[p];
             const uint4 u = philox4x32_10(make_uint4(id, w_e | PURPOSE_MCC, step, 0u), P.key0, P.key1);
             T v[3] = {S.vr[p], S.vt[p], S.vz[p]};
-            scatter(C, sc, u, id, w_e, step, P.key0, P.key1, key & 0xffff, key >> 16, S.fr[p],
-                    S.fz[p], v, coll);
+            scatter(C, sc, u, id, w_e, step, P.key0, P.key1, key & 0xffff, key >> 16, pfr, pfz, v,
+                    coll);
             S.vr[p] = v[0];
             S.vt[p] = v[1];
             S.vz[p] = v[2];
@@ -708,8 +764,9 @@ __global__ void __launch_bounds__(256) k_events(EventParams<T> P)
             if ((unsigned long long)u.x < C->t_see) {
                 ++see;
                 dq -= C->qw64[0];
-                int ie = q.y;
-                T fe = P.sp[1].fr[q.x];
+                int ie;
+                T fe;
+                see_impact(P.sp[1], q, ie, fe);
                 if (ie > P.nr - 1) { ie = P.nr - 1; fe = near_one<T>(); }
                 if (ie < 0) { ie = 0; fe = (T)0; }
                 record_child(C, sc, 1, pid, 0, 0, ie, 0, fe, (T)0, (T)0, (T)0, (T)0);
@@ -781,20 +838,19 @@ __global__ void __launch_bounds__(256) k_children(ChildParams<T> P)
                 atomicOr(&P.sc->flags, FLAG_CAPACITY);
             } else {
                 const SpeciesDev<T> S = P.sp[s];
-                S.key[slot] = ch.key;
-                S.fr[slot] = ch.fr;
-                S.fz[slot] = ch.fz;
+                const int i = ch.key & 0xffff, j = ch.key >> 16;
+                const T fr = pos_round(ch.fr), fz = pos_round(ch.fz);
+                store_pos(S, slot, true, i, j, fr, fz);
                 S.vr[slot] = ch.vr;
                 S.vt[slot] = ch.vt;
                 S.vz[slot] = ch.vz;
                 S.id[slot] = P.sc->next_id[s] + (uint32_t)rank;
-                const int i = ch.key & 0xffff, j = ch.key >> 16;
                 const int64_t n0 = (int64_t)j * ldn + i;
-                const T qw = P.qw[s], gr = (T)1 - ch.fr, gz = (T)1 - ch.fz;
+                const T qw = P.qw[s], gr = (T)1 - fr, gz = (T)1 - fz;
                 atomic_add_dev(&P.q[s][n0], qw * gr * gz);
-                atomic_add_dev(&P.q[s][n0 + 1], qw * ch.fr * gz);
-                atomic_add_dev(&P.q[s][n0 + ldn], qw * gr * ch.fz);
-                atomic_add_dev(&P.q[s][n0 + ldn + 1], qw * ch.fr * ch.fz);
+                atomic_add_dev(&P.q[s][n0 + 1], qw * fr * gz);
+                atomic_add_dev(&P.q[s][n0 + ldn], qw * gr * fz);
+                atomic_add_dev(&P.q[s][n0 + ldn + 1], qw * fr * fz);
             }
         }
     }
@@ -884,9 +940,7 @@ __global__ void k_load(SpeciesDev<T> S, int64_t off, const double *r, const doub
         if (fr < (T)0) fr = (T)0;
         if (fz < (T)0) fz = (T)0;
         const int64_t d = off + k;
-        S.key[d] = (j << 16) | i;
-        S.fr[d] = fr;
-        S.fz[d] = fz;
+        store_pos(S, d, true, i, j, fr, fz);
         S.vr[d] = (T)vr[k];
         S.vt[d] = (T)vt[k];
         S.vz[d] = (T)vz[k];

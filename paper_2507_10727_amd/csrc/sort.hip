@@ -31,7 +31,22 @@ __device__ __forceinline__ void wave_runs(int bin, bool valid, int lane, int &he
     len = nxt - head;
 }
 
-__global__ void k_sort_hist(const int32_t *key, const DevScalars *sc, int species, int32_t nr,
+// Bin (cell j * nr + i) of slot p, -1 if absorbed.
+template <typename T>
+__device__ __forceinline__ int sort_bin(const SpeciesDev<T> &S, int64_t p, int32_t nr)
+{
+    if constexpr (sizeof(T) == 4) {
+        const int32_t wz = ((const int32_t *)S.fz)[p];
+        if (wz < 0) return -1;
+        return pos_cell((uint32_t)wz) * nr + pos_cell(((const uint32_t *)S.fr)[p]);
+    } else {
+        const int k = S.key[p];
+        return k >= 0 ? (k >> 16) * nr + (k & 0xffff) : -1;
+    }
+}
+
+template <typename T>
+__global__ void k_sort_hist(SpeciesDev<T> S, const DevScalars *sc, int species, int32_t nr,
                             int32_t *hist)
 {
     const int64_t n = sc->count[species];
@@ -39,9 +54,8 @@ __global__ void k_sort_hist(const int32_t *key, const DevScalars *sc, int specie
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += stride) {
         const int64_t p = b + threadIdx.x;
-        const int k = (p < n) ? key[p] : -1;
-        const bool valid = k >= 0;
-        const int bin = valid ? (k >> 16) * nr + (k & 0xffff) : -1;
+        const int bin = (p < n) ? sort_bin(S, p, nr) : -1;
+        const bool valid = bin >= 0;
         int head, len;
         wave_runs(bin, valid, lane, head, len);
         if (valid && head == lane) atomicAdd(&hist[bin], len);
@@ -127,9 +141,8 @@ __global__ void k_sort_scatter(SpeciesDev<T> src, SpeciesDev<T> dst, const DevSc
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += stride) {
         const int64_t p = b + threadIdx.x;
-        const int k = (p < n) ? src.key[p] : -1;
-        const bool valid = k >= 0;
-        const int bin = valid ? (k >> 16) * nr + (k & 0xffff) : -1;
+        const int bin = (p < n) ? sort_bin(src, p, nr) : -1;
+        const bool valid = bin >= 0;
         int head, len;
         wave_runs(bin, valid, lane, head, len);
         int base = 0;
@@ -137,9 +150,15 @@ __global__ void k_sort_scatter(SpeciesDev<T> src, SpeciesDev<T> dst, const DevSc
         base = __shfl(base, head, 64);
         if (valid) {
             const int64_t d = (int64_t)base + (lane - head);
-            dst.key[d] = k;
-            dst.fr[d] = src.fr[p];
-            dst.fz[d] = src.fz[p];
+            if constexpr (sizeof(T) == 4) {
+                // packed position words, copied as bits
+                ((uint32_t *)dst.fr)[d] = ((const uint32_t *)src.fr)[p];
+                ((uint32_t *)dst.fz)[d] = ((const uint32_t *)src.fz)[p];
+            } else {
+                dst.key[d] = src.key[p];
+                dst.fr[d] = src.fr[p];
+                dst.fz[d] = src.fz[p];
+            }
             dst.vr[d] = src.vr[p];
             dst.vt[d] = src.vt[p];
             dst.vz[d] = src.vz[p];
@@ -166,7 +185,7 @@ void launch_sort(SpeciesDev<T> src, SpeciesDev<T> dst, DevScalars *sc, int speci
     int blocks = (int)((cap + 255) / 256);
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_sort_hist, dim3(blocks), dim3(256), 0, s, src.key, sc, species, nr, hist);
+    hipLaunchKernelGGL((k_sort_hist<T>), dim3(blocks), dim3(256), 0, s, src, sc, species, nr, hist);
     hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, hist, nbins, block_sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, block_sums, ntiles, sc, species);
     hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(SCAN_TILE), 0, s, hist, nbins, block_sums);

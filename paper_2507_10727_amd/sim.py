@@ -63,6 +63,24 @@ def workspace_bytes(prob: W.Problem, b_r, b_z, sigma, capacity=None) -> int:
     return int(nbytes.value)
 
 
+def unpack_positions(h, pos_bits):
+    """key (j << 16 | i, -1 absorbed), fr, fz from host copies of a species'
+    arrays: as stored (FP64 state) or decoded from the packed FP32 words."""
+    if not pos_bits:
+        return {"key": h["key"], "fr": h["fr"], "fz": h["fz"]}
+    pr = h["pr"].view(np.uint32).astype(np.int64)
+    pz = h["pz"].astype(np.int64)
+    mask = (1 << pos_bits) - 1
+    scale = np.float32(1.0 / (1 << pos_bits))
+    live = pz >= 0
+    i = pr >> pos_bits
+    j = np.where(live, pz, 0) >> pos_bits
+    key = np.where(live, (j << 16) | i, -1).astype(np.int32)
+    fr = (pr & mask).astype(np.float32) * scale
+    fz = np.where(live, (np.where(live, pz, 0) & mask).astype(np.float32) * scale, np.float32(0))
+    return {"key": key, "fr": fr, "fz": fz.astype(np.float32)}
+
+
 class Simulation:
     """One discharge on one GPU.
 
@@ -235,23 +253,35 @@ class Simulation:
         return self.ws[off:off + n * esz].view(dtype)
 
     def particle_tensors(self, s):
+        """Device views of species s's arrays (slots 0..count-1).  FP64
+        state: key, fr, fz, ...; FP32 state: the packed words pr, pz (see
+        pic_particle_view) instead of key, fr, fz."""
         v = L.pic_particle_view()
         L.check(self.lib.pic_particles(self.h, int(s), C.byref(v)), self.h)
         torch = self.torch
         ft = torch.float64 if v.precision == 1 else torch.float32
         n = int(v.count)
-        out = {"key": self._view(v.key_dev, n, torch.int32), "id": self._view(v.id_dev, n, torch.int32)}
-        for k in ("fr", "fz", "vr", "vt", "vz"):
+        out = {"id": self._view(v.id_dev, n, torch.int32)}
+        if v.pos_bits:
+            out["pr"] = self._view(v.fr_dev, n, torch.int32)
+            out["pz"] = self._view(v.fz_dev, n, torch.int32)
+        else:
+            out["key"] = self._view(v.key_dev, n, torch.int32)
+            out["fr"] = self._view(v.fr_dev, n, ft)
+            out["fz"] = self._view(v.fz_dev, n, ft)
+        for k in ("vr", "vt", "vz"):
             out[k] = self._view(getattr(v, k + "_dev"), n, ft)
+        self._pos_bits = int(v.pos_bits)
         return out
 
     def particles(self, s, raw=False):
         """Live particles of species s as host arrays (positions absolute, FP64)."""
         t = self.particle_tensors(s)
         self.torch.cuda.synchronize(self.device)
-        key = t["key"].cpu().numpy()
-        live = key >= 0
-        out = {k: v.cpu().numpy()[live] for k, v in t.items()}
+        h = {k: v.cpu().numpy() for k, v in t.items()}
+        h.update(unpack_positions(h, self._pos_bits))
+        live = h["key"] >= 0
+        out = {k: h[k][live] for k in ("key", "fr", "fz", "vr", "vt", "vz", "id")}
         out["id"] = out["id"].view(np.uint32)
         i = (out["key"] & 0xFFFF).astype(np.float64)
         j = (out["key"] >> 16).astype(np.float64)

@@ -54,6 +54,7 @@ def test_query_workspace_sizes():
     dict(poisson_rtol=0.0), dict(poisson_maxit=0), dict(wall_bc=(0, 5, 0)),
     dict(nr=101, nz=101), dict(poisson_mode=5), dict(pc_batch=-1), dict(pc_batch=65),
     dict(pc_maxit=-1), dict(pc_maxit=100000),
+    dict(precision=W.F32, nr=2048), dict(precision=W.F32, nz=2048),
 ])
 def test_invalid_configs_rejected(bad):
     lib = L.load()
@@ -62,6 +63,19 @@ def test_invalid_configs_rejected(bad):
     st = lib.pic_query_workspace(C.byref(cfg), C.byref(n))
     assert st == L.PIC_EINVAL
     assert lib.pic_last_error(None)
+
+
+def test_fp32_grid_limit_of_packed_positions():
+    # FP32 state packs the cell index into 10 bits of each position word
+    lib = L.load()
+    n = C.c_int64()
+    for nr, nz, ok in ((1024, 64, True), (64, 1024, True), (2048, 64, False)):
+        cfg, keep = _cfg(precision=W.F32, nr=nr, nz=nz)
+        st = lib.pic_query_workspace(C.byref(cfg), C.byref(n))
+        assert (st == 0) == ok, (nr, nz, st)
+    # the FP64 layout keeps a key word and has no such limit
+    cfg, keep = _cfg(precision=W.F64, nr=2048)
+    assert lib.pic_query_workspace(C.byref(cfg), C.byref(n)) == 0
 
 
 def test_init_rejects_missing_workspace():

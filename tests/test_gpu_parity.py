@@ -160,17 +160,22 @@ def test_empty_and_ragged():
     assert sim.particles(0)["id"].shape[0] == o.count(0)
 
 
-def test_sort_compacts_and_orders():
-    p = W.scaled(W.preset("small_mc64_f64"), 30_000).replace(sort_every=1000)
+@pytest.mark.parametrize("prec", [W.F64, W.F32])
+def test_sort_compacts_and_orders(prec):
+    """After compaction every slot is live and slots are ordered by cell, in
+    the FP64 layout (key word) and the packed FP32 layout alike."""
+    from paper_2507_10727_amd.sim import unpack_positions
+    p = W.scaled(W.preset("small_mc64_f64"), 30_000).replace(sort_every=1000, precision=prec)
     br, bz, sig, parts = W.inputs(p)
-    say("case sort/compaction")
+    say("case sort/compaction", prec)
     sim = gpu_sim(p, br, bz, sig, parts)
     sim.step(5)
     before = {s: sim.particles(s) for s in range(2)}
     sim.compact()
     for s in range(2):
         t = sim.particle_tensors(s)
-        key = t["key"].cpu().numpy()
+        h = {k: v.cpu().numpy() for k, v in t.items()}
+        key = unpack_positions(h, sim._pos_bits)["key"]
         assert (key >= 0).all()
         bins = (key >> 16) * p.nr + (key & 0xFFFF)
         assert (np.diff(bins) >= 0).all()
