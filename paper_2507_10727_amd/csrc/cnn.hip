@@ -32,6 +32,7 @@ constexpr int TX = 64;           // columns per block
 constexpr int PW = TX + 2;       // patch columns
 constexpr int PH = TR + 2;       // patch rows
 constexpr int EB = 256;          // threads of elementwise kernels
+constexpr int CONV_LDS_MAX = 150 * 1024;   // dynamic LDS of one conv block
 
 __device__ __forceinline__ uint32_t bf16_rne(float f)
 {
@@ -54,6 +55,7 @@ struct ConvArgs {
     float *y;                   // output NHWC [B][H][W][cout_p]
     int32_t H, W, cout_p;
     int32_t relu, accumulate;
+    int32_t nsplit;             // blocks per sample along the output tiles
 };
 
 // input value quad (4 channels from c4) of output-grid pixel (ys, xs)
@@ -67,14 +69,33 @@ __device__ __forceinline__ float4 load_in(const float *x, int b, int ys, int xs,
     return *(const float4 *)(x + pix * cin_p + c4);
 }
 
+// Row stride (shorts) of the weight rows staged in LDS: padded by 8 so that
+// the 16 rows a wavefront reads at one column fall in different banks.
+__host__ __device__ __forceinline__ int wrow_lds(int kpad) { return kpad + 8; }
+
 template <int NT>
 __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
 {
     extern __shared__ __align__(16) char lds[];
     const int cst = a.cin_p + 4;
     short *patch = (short *)lds;
-    int *off4 = (int *)(lds + ((PH * PW * cst * 2 + 15) & ~15));
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TR, b = blockIdx.z;
+    const int patch_bytes = (PH * PW * cst * 2 + 15) & ~15;
+    int *off4 = (int *)(lds + patch_bytes);
+    short *wl = (short *)(lds + patch_bytes + (((a.kpad >> 2) * 4 + 15) & ~15));
+    const int wst = wrow_lds(a.kpad);
+    // blockIdx.z = sample * nsplit + split: this block's 16-channel output
+    // tiles are [split * NT, split * NT + NT)
+    const int b = blockIdx.z / a.nsplit, tile0 = (blockIdx.z - b * a.nsplit) * NT;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TR;
+    // the block's weight rows, once, into LDS (16-byte pieces)
+    {
+        const int pieces = a.kpad >> 3;            // 8 shorts per piece
+        const short *wsrc = a.w + (int64_t)tile0 * 16 * a.kpad;
+        for (int t = threadIdx.x; t < NT * 16 * pieces; t += 256) {
+            const int row = t / pieces, pc = t - row * pieces;
+            *(uint4 *)(wl + row * wst + 8 * pc) = *(const uint4 *)(wsrc + (int64_t)row * a.kpad + 8 * pc);
+        }
+    }
     const int quads = a.cin_p >> 2;
     for (int t = threadIdx.x; t < PH * PW * quads; t += 256) {
         const int q = t % quads, pix = t / quads;
@@ -102,12 +123,12 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[t][n] = v4f{0.f, 0.f, 0.f, 0.f};
-    const short *wbase = a.w + (int64_t)m * a.kpad + kq;
+    const short *wbase = wl + m * wst + kq;
     const short *pbase = patch + (wave * PW + m) * cst;
     for (int kc = 0; kc < a.kpad; kc += 16) {
         v4s wa[NT];
 #pragma unroll
-        for (int n = 0; n < NT; ++n) wa[n] = *(const v4s *)(wbase + (int64_t)n * 16 * a.kpad + kc);
+        for (int n = 0; n < NT; ++n) wa[n] = *(const v4s *)(wbase + n * 16 * wst + kc);
         const int o = off4[(kc + kq) >> 2];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -127,7 +148,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
         const int64_t pix = ((int64_t)b * a.H + yy) * a.W + xx;
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-            const int ch = n * 16 + kq;
+            const int ch = (tile0 + n) * 16 + kq;
             if (ch >= a.cout_p) continue;
             const int64_t o = pix * a.cout_p + ch;
             float4 v = make_float4(acc[t][n][0], acc[t][n][1], acc[t][n][2], acc[t][n][3]);
@@ -397,7 +418,8 @@ __global__ void __launch_bounds__(EB) k_pc_sumsq(const T *v, int64_t stride, dou
     const T *s = v + (int64_t)blockIdx.y * stride;
     double acc = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * EB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * EB) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         if (mg_unknown(L, i, j)) {
             const double t = scale * (double)s[n];
             acc += t * t;
@@ -415,9 +437,10 @@ __global__ void k_pc_input(const T *v, int64_t stride, double scale, const doubl
     const int64_t nn = (int64_t)ld * (L.nz + 1);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)B * nn;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int b = (int)(t / nn);
+        const int b = (int)((uint32_t)t / (uint32_t)nn);
         const int64_t n = t - (int64_t)b * nn;
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         const double rho = sqrt(ss[b] * inv_nunk);
         float r = 0.0f;
         if (rho > 0.0 && mg_unknown(L, i, j)) r = (float)(scale * (double)v[b * stride + n] / rho);
@@ -467,7 +490,8 @@ __global__ void __launch_bounds__(EB) k_rb_sweep(MGLevel L, const float *bv, flo
     float *x = xv + (int64_t)blockIdx.y * stride;
     double arz = 0.0, azq = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * EB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * EB) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         const bool unk = mg_unknown(L, i, j);
         float v;
         if (unk && ((i + j) & 1) == colour) {
@@ -507,7 +531,8 @@ __global__ void __launch_bounds__(EB) k_residual32(MGLevel L, const float *bv, c
     float *r = rv + (int64_t)blockIdx.y * stride;
     double acc = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * EB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * EB) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         float v = 0.0f;
         if (mg_unknown(L, i, j)) {
             float cw, ce, cs, cn;
@@ -532,7 +557,8 @@ __global__ void k_pc_combine(const float *net, const double *ss, double inv_nunk
     const float sc = (float)(out_scale * sqrt(ss[0] * inv_nunk));
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn;
          n += (int64_t)gridDim.x * blockDim.x) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         z[n] = mg_unknown(L, i, j) ? x1[n] + sc * net[n * 4] : 0.0f;
     }
 }
@@ -546,9 +572,10 @@ __global__ void k_pc_scale_in(const T *q, int64_t stride, double scale, const do
     const int64_t nn = (int64_t)ld * (L.nz + 1);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)B * nn;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int b = (int)(t / nn);
+        const int b = (int)((uint32_t)t / (uint32_t)nn);
         const int64_t n = t - (int64_t)b * nn;
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         const double rho = ss0 ? sqrt(ss0[b] * inv_nunk) : 1.0;
         float v = 0.0f;
         if (rho > 0.0 && mg_unknown(L, i, j)) v = (float)(scale * (double)q[b * stride + n] / rho);
@@ -582,7 +609,8 @@ __global__ void __launch_bounds__(EB) k_pc_targets(const double *phi, int64_t st
     };
     double acc = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * EB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * EB) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         float out = 0.0f;
         if (mg_unknown(L, i, j)) {
             const double c = tv(i, j);
@@ -612,7 +640,8 @@ __global__ void __launch_bounds__(EB) k_pc_loss(const float *net, const float *t
     const double w = 1.0 / ((double)B * den[b]);
     double acc = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * EB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * EB) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         float g = 0.0f;
         if (mg_unknown(L, i, j)) {
             auto e = [&](int ii, int jj) {
@@ -681,9 +710,10 @@ inline int eblocks(int64_t n)
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 // ---- launch helpers ------------------------------------------------------------
-int conv_lds(int cin_p, int kpad)
+int conv_lds(int cin_p, int kpad, int ntb)
 {
-    return ((PH * PW * (cin_p + 4) * 2 + 15) & ~15) + (kpad / 4) * 4;
+    return ((PH * PW * (cin_p + 4) * 2 + 15) & ~15) + (((kpad / 4) * 4 + 15) & ~15) +
+           ntb * 16 * wrow_lds(kpad) * 2;
 }
 
 void conv(const PcNet &n, int li, bool dgrad, const float *x, const float *skip, const float *mask,
@@ -711,13 +741,18 @@ void conv(const PcNet &n, int li, bool dgrad, const float *x, const float *skip,
     a.relu = relu;
     a.accumulate = accumulate;
     const int nt = dgrad ? l.nt_t : l.nt;
-    dim3 g((a.W + TX - 1) / TX, (a.H + TR - 1) / TR, B);
-    const int lds = conv_lds(a.cin_p, a.kpad);
-    switch (nt) {
+    const int gx = (a.W + TX - 1) / TX, gy = (a.H + TR - 1) / TR;
+    // one block per tile of output channels when the grid alone is too
+    // small to fill the chip or the block's weights would not fit in LDS
+    int ntb = (nt > 1 && ((int64_t)gx * gy * B < 1024 || conv_lds(a.cin_p, a.kpad, nt) > CONV_LDS_MAX))
+                  ? 1 : nt;
+    if (ntb != 3 && ntb != 5) ntb = 1;            // instantiated tile counts
+    a.nsplit = nt / ntb;
+    dim3 g(gx, gy, B * a.nsplit);
+    const int lds = conv_lds(a.cin_p, a.kpad, ntb);
+    switch (ntb) {
         case 1: hipLaunchKernelGGL(k_conv3x3<1>, g, dim3(256), lds, s, a); break;
-        case 2: hipLaunchKernelGGL(k_conv3x3<2>, g, dim3(256), lds, s, a); break;
         case 3: hipLaunchKernelGGL(k_conv3x3<3>, g, dim3(256), lds, s, a); break;
-        case 4: hipLaunchKernelGGL(k_conv3x3<4>, g, dim3(256), lds, s, a); break;
         default: hipLaunchKernelGGL(k_conv3x3<5>, g, dim3(256), lds, s, a); break;
     }
 }
@@ -998,9 +1033,7 @@ int pc_kernel_setup()
     const int lim = 160 * 1024;
     int e = 0;
     e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<5>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     e |= (int)hipFuncSetAttribute((const void *)k_conv3x3_wgrad, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     return e;

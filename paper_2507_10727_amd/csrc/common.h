@@ -262,6 +262,16 @@ __device__ __forceinline__ void sincos_2pi(float u, float *s, float *c) { sincos
 __device__ __forceinline__ void sincos_2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
 
 // ----------------------------------------------------------- wave helpers --
+// Column i and row j of node n of a grid with ld nodes per row.  Node
+// indices stay below 2^31, so a 32-bit division does (a 64-bit one is an
+// expensive software routine on the GPU).
+__device__ __forceinline__ void node_ij(int64_t n, int ld, int &i, int &j)
+{
+    const uint32_t u = (uint32_t)n;
+    j = (int)(u / (uint32_t)ld);
+    i = (int)(u - (uint32_t)j * (uint32_t)ld);
+}
+
 // Order the LDS accesses of one wavefront's lanes before and after this point
 // (the lanes of a wavefront share the instruction stream; this keeps the
 // compiler from moving LDS accesses across it).

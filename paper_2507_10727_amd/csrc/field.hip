@@ -72,7 +72,8 @@ __device__ __forceinline__ void residual64_body(int32_t nr, int32_t nz, const do
     double rr = 0.0, bb = 0.0;
     for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB) {
         if (kind[n] != 0) { r64[n] = 0.0; continue; }
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         const double p = phi[n];
         double flux = 0.0, dir = 0.0;
         if (i < nr) { const double c = ce[n]; flux += c * (p - phi[n + 1]); if (kind[n + 1]) dir += c * phi[n + 1]; }
@@ -112,7 +113,8 @@ __global__ void __launch_bounds__(FB) k_apply_k64(int32_t nr, int32_t nz, const 
     const int64_t nn = (int64_t)ld * (nz + 1);
     for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
         if (kind[n] != 0) { out[n] = 0.0; continue; }
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         const double p = phi[n];
         double flux = 0.0;
         if (i < nr) flux += ce[n] * (p - phi[n + 1]);
@@ -212,7 +214,8 @@ __device__ __forceinline__ void field_prep_body(int32_t nr, int32_t nz, double d
     const int64_t nn = (int64_t)ld * (nz + 1);
     const double vc = sc->vc;
     for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
 #define PHI(m) (use_phi ? phi[(m)] : (phi0[(m)] + vc * phil[(m)]))
         const double p = PHI(n);
         double ex, ey;
@@ -295,7 +298,8 @@ __global__ void __launch_bounds__(FB) k_diag_grid(int32_t nr, int32_t nz, const 
     const int64_t nn = (int64_t)ld * (nz + 1);
     double s0 = 0, s1 = 0, m0 = -1e300, m1 = -1e300, mp = -1e300, w = 0;
     for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         const double a = (double)q0[n], b = (double)q1[n];
         s0 += a;
         s1 += b;

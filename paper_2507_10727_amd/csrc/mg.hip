@@ -350,7 +350,8 @@ __device__ __forceinline__ void cg_matvec_body(const MGLevel &L, const float *z,
     const int64_t nn = (int64_t)ld * (L.nz + 1);
     double acc = 0.0;
     for (int64_t n = (int64_t)blk * CB + threadIdx.x; n < nn; n += (int64_t)nblk * CB) {
-        const int j = (int)(n / ld), i = (int)(n - (int64_t)j * ld);
+        int i, j;
+        node_ij(n, ld, i, j);
         float pv = 0.0f, qv = 0.0f;
         if (mg_unknown(L, i, j)) {
             float w, e, s, nb;

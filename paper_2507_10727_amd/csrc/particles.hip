@@ -88,11 +88,15 @@ template <typename T> __device__ __forceinline__ T near_one();
 template <> __device__ __forceinline__ float near_one<float>() { return 0x1.fffffep-1f; }
 template <> __device__ __forceinline__ double near_one<double>() { return 0x1.fffffffffffffp-1; }
 
-// Reciprocal: the hardware approximation (about 1 ulp) in FP32, exact
-// division in FP64 (the FP64 state is compared with the oracle at 1e-12).
+// Reciprocal and square root: the hardware approximations (about 1 ulp) in
+// FP32, exact operations in FP64 (the FP64 state is compared with the oracle
+// at 1e-12).
 template <typename T> __device__ __forceinline__ T rcp(T x);
 template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+template <typename T> __device__ __forceinline__ T fast_sqrt(T x);
+template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
 
 struct Tally {
     double ke = 0.0, pz = 0.0, dq = 0.0;
@@ -143,7 +147,7 @@ __device__ __forceinline__ int advance(const PushParams<T> &P, T hqm,
     const T r = ((T)i + fr) * P.dr;
     const T dx = nx * P.dt, dy = ny * P.dt;
     const T x1 = r + dx;
-    const T r1 = sqrt(x1 * x1 + dy * dy);
+    const T r1 = fast_sqrt(x1 * x1 + dy * dy);
     T vr1 = nx, vt1 = ny, vz1 = nzv;
     if (r1 > (T)0) {
         const T inv = rcp<T>(r1);
@@ -466,35 +470,46 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
         const bool any = p0 < n;
         if (any) {
             // slots p0..p0+3 are inside the (4-rounded) capacity; those at or
-            // beyond the count are masked and written back unchanged
+            // beyond the count are masked and written back unchanged.  Every
+            // load of the chunk is issued before any of them is used, so the
+            // wavefront waits for memory once per chunk.
             if constexpr (sizeof(T) == 4) {
                 const uint4 wr = stream_load((const uint4 *)(FR + p0));
                 const int4 wz = stream_load((const int4 *)(FZ + p0));
+                const T4 c = stream_load((const T4 *)(VR + p0));
+                const T4 d = stream_load((const T4 *)(VT + p0));
+                const T4 e = stream_load((const T4 *)(VZ + p0));
+                uint4 iv = make_uint4(0u, 0u, 0u, 0u);
+                if (collide_on) iv = stream_load((const uint4 *)(ID + p0));
                 const uint32_t r4[4] = {wr.x, wr.y, wr.z, wr.w};
                 const int32_t z4[4] = {wz.x, wz.y, wz.z, wz.w};
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
+                    // branch-free: an absorbed slot (pz = -1) gives key -1, fz 0
+                    const uint32_t zc = (uint32_t)max(z4[k], 0);
                     fr[k] = pos_frac(r4[k]);
-                    const bool live = z4[k] >= 0;
-                    fz[k] = live ? pos_frac((uint32_t)z4[k]) : (T)0;
-                    kk[k] = live ? ((pos_cell((uint32_t)z4[k]) << 16) | pos_cell(r4[k])) : -1;
+                    fz[k] = pos_frac(zc);
+                    kk[k] = ((pos_cell(zc) << 16) | pos_cell(r4[k])) | (z4[k] >> 31);
                 }
+                vr[0] = c.x; vr[1] = c.y; vr[2] = c.z; vr[3] = c.w;
+                vt[0] = d.x; vt[1] = d.y; vt[2] = d.z; vt[3] = d.w;
+                vz[0] = e.x; vz[1] = e.y; vz[2] = e.z; vz[3] = e.w;
+                id[0] = iv.x; id[1] = iv.y; id[2] = iv.z; id[3] = iv.w;
             } else {
                 const int4 k4 = stream_load((const int4 *)(KEY + p0));
                 const T4 a = stream_load((const T4 *)(FR + p0));
                 const T4 b = stream_load((const T4 *)(FZ + p0));
+                const T4 c = stream_load((const T4 *)(VR + p0));
+                const T4 d = stream_load((const T4 *)(VT + p0));
+                const T4 e = stream_load((const T4 *)(VZ + p0));
+                uint4 iv = make_uint4(0u, 0u, 0u, 0u);
+                if (collide_on) iv = stream_load((const uint4 *)(ID + p0));
                 kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
                 fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
                 fz[0] = b.x; fz[1] = b.y; fz[2] = b.z; fz[3] = b.w;
-            }
-            const T4 c = stream_load((const T4 *)(VR + p0));
-            const T4 d = stream_load((const T4 *)(VT + p0));
-            const T4 e = stream_load((const T4 *)(VZ + p0));
-            vr[0] = c.x; vr[1] = c.y; vr[2] = c.z; vr[3] = c.w;
-            vt[0] = d.x; vt[1] = d.y; vt[2] = d.z; vt[3] = d.w;
-            vz[0] = e.x; vz[1] = e.y; vz[2] = e.z; vz[3] = e.w;
-            if (collide_on) {
-                const uint4 iv = stream_load((const uint4 *)(ID + p0));
+                vr[0] = c.x; vr[1] = c.y; vr[2] = c.z; vr[3] = c.w;
+                vt[0] = d.x; vt[1] = d.y; vt[2] = d.z; vt[3] = d.w;
+                vz[0] = e.x; vz[1] = e.y; vz[2] = e.z; vz[3] = e.w;
                 id[0] = iv.x; id[1] = iv.y; id[2] = iv.z; id[3] = iv.w;
             }
 #pragma unroll
