@@ -293,6 +293,7 @@ def main():
                                               "circuit_ms", "field_ms")}
     log(f"[bench] {value:.3e} particle-steps/s, {wall / args.steps * 1e3:.3f} ms/step, "
         f"push {push_avg_ms:.3f} ms ({achieved:.0f} GB/s algorithmic)")
+    log(f"[bench] last field solve: {d1['poisson']}")
     sim.close()
     del sim
     torch.cuda.empty_cache()

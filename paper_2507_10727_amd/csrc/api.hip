@@ -112,20 +112,6 @@ pic_status fail(pic_handle *h, pic_status st, const char *fmt, ...)
 
 // Multigrid level shapes: halve while both cell counts are even and the
 // smaller one exceeds 4.
-std::vector<LevelShape> mg_shapes(const pic_config &c)
-{
-    std::vector<LevelShape> v;
-    LevelShape s{c.nr, c.nz, c.lr, c.lz};
-    v.push_back(s);
-    while ((int)v.size() < MAX_LEVELS && (s.nr % 2 == 0) && (s.nz % 2 == 0) &&
-           std::min(s.nr, s.nz) > 4) {
-        s.nr /= 2;
-        s.nz /= 2;
-        v.push_back(s);
-    }
-    return v;
-}
-
 int coarse_unknowns(const pic_config &c, const LevelShape &s)
 {
     int n = 0;
@@ -133,6 +119,28 @@ int coarse_unknowns(const pic_config &c, const LevelShape &s)
         for (int i = 0; i <= s.nr; ++i)
             if (host_node_kind(s.nr, s.nz, c.lr, c.cathode_rmax, i, j) == 0) ++n;
     return n;
+}
+
+// Multigrid levels: halve while both cell counts are even and the level
+// still has more than MG_DENSE_MAX unknowns; the coarsest level is solved
+// exactly with its dense inverse, one parallel matrix-vector product in
+// place of the barrier-separated sweeps of the levels below it.  The bound
+// keeps the inverse small: the coarse-level kernel runs on one CU, which
+// reads it from L2 at a few hundred GB/s.
+constexpr int MG_DENSE_MAX = 200;
+
+std::vector<LevelShape> mg_shapes(const pic_config &c)
+{
+    std::vector<LevelShape> v;
+    LevelShape s{c.nr, c.nz, c.lr, c.lz};
+    v.push_back(s);
+    while ((int)v.size() < MAX_LEVELS && (s.nr % 2 == 0) && (s.nz % 2 == 0) &&
+           std::min(s.nr, s.nz) > 4 && coarse_unknowns(c, s) > MG_DENSE_MAX) {
+        s.nr /= 2;
+        s.nz /= 2;
+        v.push_back(s);
+    }
+    return v;
 }
 
 pic_status validate(const pic_config *c, pic_handle *h)

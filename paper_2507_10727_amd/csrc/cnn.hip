@@ -33,6 +33,9 @@ constexpr int PW = TX + 2;       // patch columns
 constexpr int PH = TR + 2;       // patch rows
 constexpr int EB = 256;          // threads of elementwise kernels
 constexpr int CONV_LDS_MAX = 150 * 1024;   // dynamic LDS of one conv block
+constexpr int STAGE = 8;                   // loads in flight per thread when staging tiles
+constexpr int RB = 1024;                   // threads of the kernels ending in an FP64 block sum
+inline int rblocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + RB - 1) / RB, 256)); }
 
 __device__ __forceinline__ uint32_t bf16_rne(float f)
 {
@@ -88,21 +91,57 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
     const int b = blockIdx.z / a.nsplit, tile0 = (blockIdx.z - b * a.nsplit) * NT;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TR;
     // the block's weight rows, once, into LDS (16-byte pieces)
+    // (every staging loop issues STAGE loads per thread before it stores any,
+    // so a block waits for memory a few times, not once per piece)
     {
         const int pieces = a.kpad >> 3;            // 8 shorts per piece
+        const int total = NT * 16 * pieces;
         const short *wsrc = a.w + (int64_t)tile0 * 16 * a.kpad;
-        for (int t = threadIdx.x; t < NT * 16 * pieces; t += 256) {
-            const int row = t / pieces, pc = t - row * pieces;
-            *(uint4 *)(wl + row * wst + 8 * pc) = *(const uint4 *)(wsrc + (int64_t)row * a.kpad + 8 * pc);
+        for (int t0 = threadIdx.x; t0 < total; t0 += 256 * STAGE) {
+            uint4 v[STAGE];
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u) {
+                const int t = t0 + u * 256;
+                if (t < total) {
+                    const int row = t / pieces, pc = t - row * pieces;
+                    v[u] = *(const uint4 *)(wsrc + (int64_t)row * a.kpad + 8 * pc);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u) {
+                const int t = t0 + u * 256;
+                if (t < total) {
+                    const int row = t / pieces, pc = t - row * pieces;
+                    *(uint4 *)(wl + row * wst + 8 * pc) = v[u];
+                }
+            }
         }
     }
     const int quads = a.cin_p >> 2;
-    for (int t = threadIdx.x; t < PH * PW * quads; t += 256) {
-        const int q = t % quads, pix = t / quads;
-        const int r = pix / PW, col = pix - r * PW;
-        const float4 v = load_in(a.x, b, y0 + r - 1, x0 + col - 1, a.H, a.W, a.Hin, a.Win,
-                                 a.up_in, a.cin_p, 4 * q);
-        *(uint2 *)(patch + pix * cst + 4 * q) = pack4(v);
+    {
+        const int total = PH * PW * quads;
+        for (int t0 = threadIdx.x; t0 < total; t0 += 256 * STAGE) {
+            float4 v[STAGE];
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u) {
+                const int t = t0 + u * 256;
+                v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t < total) {
+                    const int q = t % quads, pix = t / quads;
+                    const int r = pix / PW, col = pix - r * PW;
+                    v[u] = load_in(a.x, b, y0 + r - 1, x0 + col - 1, a.H, a.W, a.Hin, a.Win,
+                                   a.up_in, a.cin_p, 4 * q);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u) {
+                const int t = t0 + u * 256;
+                if (t < total) {
+                    const int q = t % quads, pix = t / quads;
+                    *(uint2 *)(patch + pix * cst + 4 * q) = pack4(v[u]);
+                }
+            }
+        }
     }
     const int K = 9 * a.cin_p;
     for (int kk = threadIdx.x; kk < (a.kpad >> 2); kk += 256) {
@@ -220,28 +259,58 @@ __global__ void __launch_bounds__(256) k_conv3x3_wgrad(WgradArgs a)
         const int ty = (int)(rest % a.tiles_y), b = (int)(rest / a.tiles_y);
         const int x0 = tx * TX, y0 = ty * TR;
         __syncthreads();
-        for (int t = threadIdx.x; t < TR * TX * gq; t += 256) {
-            const int q = t % gq, pix = t / gq;
-            const int r = pix / TX, col = pix - r * TX;
-            const int yy = y0 + r, xx = x0 + col;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (yy < a.H && xx < a.W)
-                v = *(const float4 *)(a.g + (((int64_t)b * a.H + yy) * a.W + xx) * a.cout_p + 4 * q);
-            gs[(4 * q + 0) * TR * TX + pix] = (short)bf16_rne(v.x);
-            gs[(4 * q + 1) * TR * TX + pix] = (short)bf16_rne(v.y);
-            gs[(4 * q + 2) * TR * TX + pix] = (short)bf16_rne(v.z);
-            gs[(4 * q + 3) * TR * TX + pix] = (short)bf16_rne(v.w);
+        for (int t0 = threadIdx.x; t0 < TR * TX * gq; t0 += 256 * STAGE) {
+            float4 v[STAGE];
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u) {
+                const int t = t0 + u * 256;
+                v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t < TR * TX * gq) {
+                    const int q = t % gq, pix = t / gq;
+                    const int r = pix / TX, col = pix - r * TX;
+                    const int yy = y0 + r, xx = x0 + col;
+                    if (yy < a.H && xx < a.W)
+                        v[u] = *(const float4 *)(a.g + (((int64_t)b * a.H + yy) * a.W + xx) * a.cout_p + 4 * q);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u) {
+                const int t = t0 + u * 256;
+                if (t < TR * TX * gq) {
+                    const int q = t % gq, pix = t / gq;
+                    gs[(4 * q + 0) * TR * TX + pix] = (short)bf16_rne(v[u].x);
+                    gs[(4 * q + 1) * TR * TX + pix] = (short)bf16_rne(v[u].y);
+                    gs[(4 * q + 2) * TR * TX + pix] = (short)bf16_rne(v[u].z);
+                    gs[(4 * q + 3) * TR * TX + pix] = (short)bf16_rne(v[u].w);
+                }
+            }
         }
-        for (int t = threadIdx.x; t < PH * PW * xq; t += 256) {
-            const int q = t % xq, pix = t / xq;
-            const int r = pix / PW, col = pix - r * PW;
-            const float4 v = load_in(a.x, b, y0 + r - 1, x0 + col - 1, a.H, a.W, a.Hin, a.Win,
-                                     a.up_in, a.cin_p, 4 * q);
-            const int base = ((4 * q) * PH + r) * PW + col;
-            xs[base] = (short)bf16_rne(v.x);
-            xs[base + PH * PW] = (short)bf16_rne(v.y);
-            xs[base + 2 * PH * PW] = (short)bf16_rne(v.z);
-            xs[base + 3 * PH * PW] = (short)bf16_rne(v.w);
+        for (int t0 = threadIdx.x; t0 < PH * PW * xq; t0 += 256 * STAGE) {
+            float4 v[STAGE];
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u) {
+                const int t = t0 + u * 256;
+                v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (t < PH * PW * xq) {
+                    const int q = t % xq, pix = t / xq;
+                    const int r = pix / PW, col = pix - r * PW;
+                    v[u] = load_in(a.x, b, y0 + r - 1, x0 + col - 1, a.H, a.W, a.Hin, a.Win,
+                                   a.up_in, a.cin_p, 4 * q);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u) {
+                const int t = t0 + u * 256;
+                if (t < PH * PW * xq) {
+                    const int q = t % xq, pix = t / xq;
+                    const int r = pix / PW, col = pix - r * PW;
+                    const int base = ((4 * q) * PH + r) * PW + col;
+                    xs[base] = (short)bf16_rne(v[u].x);
+                    xs[base + PH * PW] = (short)bf16_rne(v[u].y);
+                    xs[base + 2 * PH * PW] = (short)bf16_rne(v[u].z);
+                    xs[base + 3 * PH * PW] = (short)bf16_rne(v[u].w);
+                }
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -393,15 +462,16 @@ __global__ void k_up2_bwd(const float *dy, float *dx, const float *mask, int B, 
 }
 
 // ---- block reduction helper -------------------------------------------------
+// (blocks of up to 1024 threads; one FP64 atomic per block)
 __device__ __forceinline__ void block_add(double v, double *dst)
 {
-    __shared__ double red[EB / 64];
+    __shared__ double red[16];
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int w = 0; w < EB / 64; ++w) s += red[w];
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
         if (s != 0.0) atomic_add_dev(dst, s);
     }
     __syncthreads();
@@ -448,12 +518,12 @@ __global__ void k_pc_input(const T *v, int64_t stride, double scale, const doubl
     }
 }
 
-__global__ void __launch_bounds__(EB) k_pc_identity(MGLevel L, const float *r, float *z, double *rz)
+__global__ void __launch_bounds__(RB) k_pc_identity(MGLevel L, const float *r, float *z, double *rz)
 {
     const int ld = L.nr + 1;
     const int64_t nn = (int64_t)ld * (L.nz + 1);
     double acc = 0.0;
-    for (int64_t n = (int64_t)blockIdx.x * EB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * EB) {
+    for (int64_t n = (int64_t)blockIdx.x * RB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * RB) {
         const float v = r[n];
         z[n] = v;
         acc += (double)v * (double)v;
@@ -479,7 +549,7 @@ __device__ __forceinline__ double op_an(const MGLevel &L, int i)
 // other colour and the Dirichlet nodes are set to 0 (x = 0 before the
 // sweep).  With rz: rz += z.dot_r and, with zq, zq += z.dot_q over all nodes
 // after the sweep.  Sample b = blockIdx.y at offset b * stride.
-__global__ void __launch_bounds__(EB) k_rb_sweep(MGLevel L, const float *bv, float *xv,
+__global__ void __launch_bounds__(RB) k_rb_sweep(MGLevel L, const float *bv, float *xv,
                                                   int64_t stride, int colour, int from_zero,
                                                   const float *dot_r, const float *dot_q,
                                                   double *rz, double *zq)
@@ -489,7 +559,7 @@ __global__ void __launch_bounds__(EB) k_rb_sweep(MGLevel L, const float *bv, flo
     const float *b = bv + (int64_t)blockIdx.y * stride;
     float *x = xv + (int64_t)blockIdx.y * stride;
     double arz = 0.0, azq = 0.0;
-    for (int64_t n = (int64_t)blockIdx.x * EB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * EB) {
+    for (int64_t n = (int64_t)blockIdx.x * RB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * RB) {
         int i, j;
         node_ij(n, ld, i, j);
         const bool unk = mg_unknown(L, i, j);
@@ -521,7 +591,7 @@ __global__ void __launch_bounds__(EB) k_rb_sweep(MGLevel L, const float *bv, flo
 }
 
 // r = b - A x on unknown nodes (0 elsewhere); ss[sample] += r^2
-__global__ void __launch_bounds__(EB) k_residual32(MGLevel L, const float *bv, const float *xv,
+__global__ void __launch_bounds__(RB) k_residual32(MGLevel L, const float *bv, const float *xv,
                                                     float *rv, int64_t stride, double *ss)
 {
     const int ld = L.nr + 1;
@@ -530,7 +600,7 @@ __global__ void __launch_bounds__(EB) k_residual32(MGLevel L, const float *bv, c
     const float *x = xv + (int64_t)blockIdx.y * stride;
     float *r = rv + (int64_t)blockIdx.y * stride;
     double acc = 0.0;
-    for (int64_t n = (int64_t)blockIdx.x * EB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * EB) {
+    for (int64_t n = (int64_t)blockIdx.x * RB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * RB) {
         int i, j;
         node_ij(n, ld, i, j);
         float v = 0.0f;
@@ -1094,19 +1164,19 @@ void sandwich(PcNet &n, const MGLevel &L, double inv_nunk, const float *r, float
               const float *q, double *rz, double *zq, double *ss, hipStream_t s)
 {
     const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
-    const dim3 g(std::min(eblocks((nn + 1) / 2), 1024), 1);
+    const dim3 g(rblocks(nn), 1);
     const float *nf = nullptr;
     double *nd = nullptr;
-    hipLaunchKernelGGL(k_rb_sweep, g, dim3(EB), 0, s, L, r, n.vx, nn, 0, 1, nf, nf, nd, nd);
-    hipLaunchKernelGGL(k_rb_sweep, g, dim3(EB), 0, s, L, r, n.vx, nn, 1, 0, nf, nf, nd, nd);
-    hipLaunchKernelGGL(k_residual32, g, dim3(EB), 0, s, L, r, (const float *)n.vx, n.vr, nn, ss);
+    hipLaunchKernelGGL(k_rb_sweep, g, dim3(RB), 0, s, L, r, n.vx, nn, 0, 1, nf, nf, nd, nd);
+    hipLaunchKernelGGL(k_rb_sweep, g, dim3(RB), 0, s, L, r, n.vx, nn, 1, 0, nf, nf, nd, nd);
+    hipLaunchKernelGGL(k_residual32, g, dim3(RB), 0, s, L, r, (const float *)n.vx, n.vr, nn, ss);
     hipLaunchKernelGGL(k_pc_input<float>, dim3(eblocks(nn)), dim3(EB), 0, s, (const float *)n.vr,
                        nn, 1.0, (const double *)ss, inv_nunk, L, n.x, 1);
     forward(n, 1, s);
     hipLaunchKernelGGL(k_pc_combine, dim3(eblocks(nn)), dim3(EB), 0, s, (const float *)n.out,
                        (const double *)ss, inv_nunk, n.out_scale, L, (const float *)n.vx, z);
-    hipLaunchKernelGGL(k_rb_sweep, g, dim3(EB), 0, s, L, r, z, nn, 1, 0, nf, nf, nd, nd);
-    hipLaunchKernelGGL(k_rb_sweep, g, dim3(EB), 0, s, L, r, z, nn, 0, 0, r, q, rz, q ? zq : nd);
+    hipLaunchKernelGGL(k_rb_sweep, g, dim3(RB), 0, s, L, r, z, nn, 1, 0, nf, nf, nd, nd);
+    hipLaunchKernelGGL(k_rb_sweep, g, dim3(RB), 0, s, L, r, z, nn, 0, 0, r, q, rz, q ? zq : nd);
 }
 }  // namespace
 
@@ -1132,7 +1202,7 @@ void pc_apply64(PcNet &n, const MGLevel &L, int64_t n_unknown, const double *r, 
 void pc_identity32(const MGLevel &L, const float *r, float *z, double *rz, hipStream_t s)
 {
     const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
-    hipLaunchKernelGGL(k_pc_identity, dim3(std::min(eblocks((nn + 1) / 2), 1024)), dim3(EB), 0, s, L, r, z, rz);
+    hipLaunchKernelGGL(k_pc_identity, dim3(rblocks(nn)), dim3(RB), 0, s, L, r, z, rz);
 }
 
 // ---- training -------------------------------------------------------------------------
@@ -1144,24 +1214,25 @@ void pc_train_enqueue(PcNet &n, const MGLevel &L, int64_t n_unknown, const doubl
     const double inv = n_unknown > 0 ? 1.0 / (double)n_unknown : 0.0;
     double *ss0 = n.scal, *ss1 = n.scal + B, *den = n.scal + 2 * B, *loss = n.scal + 3 * B;
     launch_zero(n.scal, 4 * (int64_t)B * 8, s);
-    const dim3 gb(std::min(eblocks((nn + 1) / 2), 1024), B);
+    const dim3 gb(rblocks(nn), B);
+    const dim3 gbe(std::min(eblocks((nn + 1) / 2), 1024), B);
     const float *nf = nullptr;
     double *nd = nullptr;
-    hipLaunchKernelGGL(k_pc_sumsq<double>, gb, dim3(EB), 0, s, q, nn, inv_2pi_eps0, L, ss0);
+    hipLaunchKernelGGL(k_pc_sumsq<double>, gbe, dim3(EB), 0, s, q, nn, inv_2pi_eps0, L, ss0);
     hipLaunchKernelGGL(k_pc_scale_in<double>, dim3(eblocks((int64_t)B * nn)), dim3(EB), 0, s, q, nn,
                        inv_2pi_eps0, (const double *)ss0, inv, L, n.vb, B);
-    hipLaunchKernelGGL(k_rb_sweep, gb, dim3(EB), 0, s, L, (const float *)n.vb, n.vx, nn, 0, 1, nf,
+    hipLaunchKernelGGL(k_rb_sweep, gb, dim3(RB), 0, s, L, (const float *)n.vb, n.vx, nn, 0, 1, nf,
                        nf, nd, nd);
-    hipLaunchKernelGGL(k_rb_sweep, gb, dim3(EB), 0, s, L, (const float *)n.vb, n.vx, nn, 1, 0, nf,
+    hipLaunchKernelGGL(k_rb_sweep, gb, dim3(RB), 0, s, L, (const float *)n.vb, n.vx, nn, 1, 0, nf,
                        nf, nd, nd);
-    hipLaunchKernelGGL(k_residual32, gb, dim3(EB), 0, s, L, (const float *)n.vb,
+    hipLaunchKernelGGL(k_residual32, gb, dim3(RB), 0, s, L, (const float *)n.vb,
                        (const float *)n.vx, n.vr, nn, ss1);
     hipLaunchKernelGGL(k_pc_input<float>, dim3(eblocks((int64_t)B * nn)), dim3(EB), 0, s,
                        (const float *)n.vr, nn, 1.0, (const double *)ss1, inv, L, n.x, B);
-    hipLaunchKernelGGL(k_pc_targets, gb, dim3(EB), 0, s, phi, nn, (const double *)ss0,
+    hipLaunchKernelGGL(k_pc_targets, gbe, dim3(EB), 0, s, phi, nn, (const double *)ss0,
                        (const double *)ss1, inv, (const float *)n.vx, L, n.tgt, den);
     forward(n, B, s);
-    hipLaunchKernelGGL(k_pc_loss, gb, dim3(EB), 0, s, (const float *)n.out, (const float *)n.tgt,
+    hipLaunchKernelGGL(k_pc_loss, gbe, dim3(EB), 0, s, (const float *)n.out, (const float *)n.tgt,
                        (const double *)den, n.out_scale, L, B, n.g_out, loss);
     backward(n, B, s);
     if (lr > 0.0f) {

@@ -11,6 +11,8 @@
 // nodes.
 #include <cstring>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace pic {
@@ -18,6 +20,16 @@ namespace pic {
 namespace {
 
 constexpr int FB = 256;
+// Kernels that end in a block sum added atomically to one FP64 scalar run
+// few large blocks: atomics on one address are serialized (about 15 ns each),
+// so 1024 blocks of 256 threads spent ~15 us in them where 256 blocks of
+// 1024 threads spend a quarter of that.
+constexpr int RB = 1024;
+inline int res_blocks(int64_t n)
+{
+    int64_t b = (n + RB - 1) / RB;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 256));
+}
 
 inline int blocks_for(int64_t n, int cap = 4096)
 {
@@ -66,11 +78,11 @@ __device__ __forceinline__ void residual64_body(int32_t nr, int32_t nz, const do
                                                    const int32_t *gate, int blk, int nblk)
 {
     if (gate && *gate) return;
-    __shared__ double buf[FB / 64];
+    __shared__ double buf[RB / 64];
     const int ld = nr + 1;
     const int64_t nn = (int64_t)ld * (nz + 1);
     double rr = 0.0, bb = 0.0;
-    for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB) {
+    for (int64_t n = (int64_t)blk * RB + threadIdx.x; n < nn; n += (int64_t)nblk * RB) {
         if (kind[n] != 0) { r64[n] = 0.0; continue; }
         int i, j;
         node_ij(n, ld, i, j);
@@ -95,7 +107,7 @@ __device__ __forceinline__ void residual64_body(int32_t nr, int32_t nz, const do
 }
 
 template <typename T>
-__global__ void __launch_bounds__(FB) k_residual64(int32_t nr, int32_t nz, const double *ce,
+__global__ void __launch_bounds__(RB) k_residual64(int32_t nr, int32_t nz, const double *ce,
                                                    const double *cn, const uint8_t *kind,
                                                    const double *phi, const T *q0, const T *q1,
                                                    double *r64, DevScalars *sc,
@@ -412,7 +424,7 @@ __global__ void k_scalars_b(BatchArgs a)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(FB) k_residual64_b(BatchArgs a)
+__global__ void __launch_bounds__(RB) k_residual64_b(BatchArgs a)
 {
     const int r = batch_run(a);
     const RunSolve &R = *a.run[r];
@@ -501,7 +513,7 @@ void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const 
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     launch_zero_gated(&sc->res_rr, 2 * sizeof(double), f.gate, s);
-    hipLaunchKernelGGL((k_residual64<T>), dim3(blocks_for((nn + 1) / 2, 1024)), dim3(FB), 0, s, f.nr,
+    hipLaunchKernelGGL((k_residual64<T>), dim3(res_blocks(nn)), dim3(RB), 0, s, f.nr,
                        f.nz, f.ce64, f.cn64, f.kind, phi, q0, q1, f.r64, sc, f.gate);
 }
 
@@ -606,11 +618,13 @@ void launch_scalars_b(const BatchPlan &P, int op, int n_iter, hipStream_t s)
 
 void launch_residual64_b(const BatchPlan &P, int gated, hipStream_t s)
 {
-    const BatchArgs a = node_args(P, gated);
+    BatchArgs a = node_args(P, gated);
+    for (int r = 0; r < P.nruns; ++r)
+        a.off[r + 1] = a.off[r] + res_blocks((int64_t)(P.host[r].lv[0].nr + 1) * (P.host[r].lv[0].nz + 1));
     if (P.prec == PIC_F64)
-        hipLaunchKernelGGL(k_residual64_b<double>, dim3(a.off[P.nruns]), dim3(FB), 0, s, a);
+        hipLaunchKernelGGL(k_residual64_b<double>, dim3(a.off[P.nruns]), dim3(RB), 0, s, a);
     else
-        hipLaunchKernelGGL(k_residual64_b<float>, dim3(a.off[P.nruns]), dim3(FB), 0, s, a);
+        hipLaunchKernelGGL(k_residual64_b<float>, dim3(a.off[P.nruns]), dim3(RB), 0, s, a);
 }
 
 void launch_circuit_b(const BatchPlan &P, hipStream_t s)

@@ -274,14 +274,22 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
             }
         __syncthreads();
     }
-    // coarsest: dense inverse on the unknowns
+    // coarsest: dense inverse on the unknowns, x = A^-1 b; 32 lanes per row
+    // (each a strided part of the row, summed with lane shuffles), so every
+    // thread has only a few independent loads of the inverse in flight
     {
         const int tid = ty * TT + tx;
-        for (int a = tid; a < T.ninv; a += TT * TT) {
+        const int g = tid >> 5, lane = tid & 31;
+        const float *bc = B(T.last);
+        for (int a0 = 0; a0 < T.ninv; a0 += (TT * TT) / 32) {
+            const int a = a0 + g;
             float acc = 0.0f;
-            const float *row = T.inv + (int64_t)a * T.ninv;
-            for (int c = 0; c < T.ninv; ++c) acc += row[c] * B(T.last)[T.map[c]];
-            X(T.last)[T.map[a]] = acc;
+            if (a < T.ninv) {
+                const float *row = T.inv + (int64_t)a * T.ninv;
+                for (int c = lane; c < T.ninv; c += 32) acc += row[c] * bc[T.map[c]];
+            }
+            for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+            if (a < T.ninv && lane == 0) X(T.last)[T.map[a]] = acc;
         }
         __syncthreads();
     }
@@ -319,7 +327,7 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
             __syncthreads();
             if (tid == 0) {
                 double s = 0.0;
-                for (int w = 0; w < 16; ++w) s += red[w];
+                for (int w = 0; w < (TT * TT) / 64; ++w) s += red[w];
                 if (s != 0.0) atomic_add_dev(dot, s);
             }
         }
@@ -329,7 +337,7 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
 }
 
 // ---- conjugate-gradient vector kernels on the finest level
-constexpr int CB = 256;
+constexpr int CB = 1024;   // CG vector kernels: few large blocks (one FP64 atomic each)
 
 // p_k = z + beta p_{k-1} (beta = rz_k / rz_{k-1}, 0 for k = 0) into pc,
 // q = A p_k, and p_k . q accumulated.
@@ -485,8 +493,9 @@ __global__ void __launch_bounds__(CB) k_cg_update_b(BatchArgs a)
 inline int cg_blocks(int64_t n)
 {
     int64_t b = (n + CB - 1) / CB;
-    // about two nodes per thread: enough waves for every CU, few FP64 atomics
-    return (int)std::max<int64_t>(1, std::min<int64_t>((b + 1) / 2, 1024));
+    // at most one block per CU: each ends in an FP64 atomic on one address,
+    // and those are serialized
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, 256));
 }
 
 }  // namespace
