@@ -3,9 +3,14 @@
 // slots (key < 0) are dropped, so the sort also compacts.
 //
 // Sorted particles let a chunk of consecutive slots touch only a small box
-// of nodes (LDS deposit tiles, cache-local gathers).  Runs of equal bins in
-// a wavefront are merged into one atomic (sorted input makes runs long), so
-// the histogram and the scatter issue about one global atomic per run.
+// of nodes (LDS deposit tiles, cache-local gathers).  Between sorts the
+// particles drift, so the array is only nearly sorted: each block takes
+// chunks of SORT_CHUNK consecutive slots and counts their bins in LDS over a
+// window of SORT_WIN bins starting at the chunk's lowest bin, then issues one
+// global atomic per bin of the window (histogram: add the count; scatter:
+// reserve the chunk's range of the bin and rank its particles in LDS).
+// Bins outside the window (new particles appended at the end, far jumps)
+// take one global atomic per wavefront run of equal bins.
 #include "common.h"
 
 namespace pic {
@@ -45,20 +50,63 @@ __device__ __forceinline__ int sort_bin(const SpeciesDev<T> &S, int64_t p, int32
     }
 }
 
-template <typename T>
-__global__ void k_sort_hist(SpeciesDev<T> S, const DevScalars *sc, int species, int32_t nr,
-                            int32_t *hist)
+constexpr int SORT_CHUNK = 4096;              // slots per block and chunk (16 per thread)
+constexpr int SORT_PER_THREAD = SORT_CHUNK / 256;
+constexpr int SORT_WIN = 4096;                // LDS bins per chunk
+
+// Lowest valid bin of the chunk (all threads; INT_MAX if none).  Ends with
+// a barrier.
+__device__ __forceinline__ int chunk_min_bin(const int *bins, int *red)
 {
+    int mn = 0x7fffffff;
+#pragma unroll
+    for (int m = 0; m < SORT_PER_THREAD; ++m)
+        if (bins[m] >= 0) mn = min(mn, bins[m]);
+    mn = wave_min(mn);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mn;
+    __syncthreads();
+    return min(min(red[0], red[1]), min(red[2], red[3]));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sort_hist(SpeciesDev<T> S, const DevScalars *sc,
+                                                    int species, int32_t nr, int32_t *hist)
+{
+    __shared__ int cnt[SORT_WIN];
+    __shared__ int red[4];
     const int64_t n = sc->count[species];
     const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += stride) {
-        const int64_t p = b + threadIdx.x;
-        const int bin = (p < n) ? sort_bin(S, p, nr) : -1;
-        const bool valid = bin >= 0;
-        int head, len;
-        wave_runs(bin, valid, lane, head, len);
-        if (valid && head == lane) atomicAdd(&hist[bin], len);
+    for (int q = threadIdx.x; q < SORT_WIN; q += 256) cnt[q] = 0;
+    for (int64_t base = (int64_t)blockIdx.x * SORT_CHUNK; base < n;
+         base += (int64_t)gridDim.x * SORT_CHUNK) {
+        int bins[SORT_PER_THREAD];
+#pragma unroll
+        for (int m = 0; m < SORT_PER_THREAD; ++m) {
+            const int64_t p = base + m * 256 + threadIdx.x;
+            bins[m] = (p < n) ? sort_bin(S, p, nr) : -1;
+        }
+        const int w0 = chunk_min_bin(bins, red);       // (barrier: cnt is zero)
+#pragma unroll
+        for (int m = 0; m < SORT_PER_THREAD; ++m) {
+            const bool valid = bins[m] >= 0;
+            int head, len;
+            wave_runs(bins[m], valid, lane, head, len);
+            if (valid && head == lane) {
+                const int w = bins[m] - w0;
+                if (w < SORT_WIN) atomicAdd(&cnt[w], len);
+                else atomicAdd(&hist[bins[m]], len);
+            }
+        }
+        __syncthreads();
+        // flush the window and leave it zero for the next chunk
+        for (int q = threadIdx.x; q < SORT_WIN; q += 256) {
+            const int c = cnt[q];
+            if (c) {
+                atomicAdd(&hist[w0 + q], c);
+                cnt[q] = 0;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -133,37 +181,79 @@ __global__ void k_scan_down(int32_t *data, int32_t nbins, const int32_t *tile_of
 }
 
 template <typename T>
-__global__ void k_sort_scatter(SpeciesDev<T> src, SpeciesDev<T> dst, const DevScalars *sc,
-                               int species, int32_t nr, int32_t *off)
+__device__ __forceinline__ void copy_slot(const SpeciesDev<T> &src, const SpeciesDev<T> &dst,
+                                          int64_t p, int64_t d)
 {
+    if constexpr (sizeof(T) == 4) {
+        // packed position words, copied as bits
+        ((uint32_t *)dst.fr)[d] = ((const uint32_t *)src.fr)[p];
+        ((uint32_t *)dst.fz)[d] = ((const uint32_t *)src.fz)[p];
+    } else {
+        dst.key[d] = src.key[p];
+        dst.fr[d] = src.fr[p];
+        dst.fz[d] = src.fz[p];
+    }
+    dst.vr[d] = src.vr[p];
+    dst.vt[d] = src.vt[p];
+    dst.vz[d] = src.vz[p];
+    dst.id[d] = src.id[p];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sort_scatter(SpeciesDev<T> src, SpeciesDev<T> dst,
+                                                       const DevScalars *sc, int species,
+                                                       int32_t nr, int32_t *off)
+{
+    __shared__ int cnt[SORT_WIN];     // counts, then the chunk's first slot per bin
+    __shared__ int rk[SORT_WIN];      // slots of the bin handed out so far
+    __shared__ int red[4];
     const int64_t n = sc->count[species];
     const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += stride) {
-        const int64_t p = b + threadIdx.x;
-        const int bin = (p < n) ? sort_bin(src, p, nr) : -1;
-        const bool valid = bin >= 0;
-        int head, len;
-        wave_runs(bin, valid, lane, head, len);
-        int base = 0;
-        if (valid && head == lane) base = atomicAdd(&off[bin], len);
-        base = __shfl(base, head, 64);
-        if (valid) {
-            const int64_t d = (int64_t)base + (lane - head);
-            if constexpr (sizeof(T) == 4) {
-                // packed position words, copied as bits
-                ((uint32_t *)dst.fr)[d] = ((const uint32_t *)src.fr)[p];
-                ((uint32_t *)dst.fz)[d] = ((const uint32_t *)src.fz)[p];
-            } else {
-                dst.key[d] = src.key[p];
-                dst.fr[d] = src.fr[p];
-                dst.fz[d] = src.fz[p];
-            }
-            dst.vr[d] = src.vr[p];
-            dst.vt[d] = src.vt[p];
-            dst.vz[d] = src.vz[p];
-            dst.id[d] = src.id[p];
+    for (int q = threadIdx.x; q < SORT_WIN; q += 256) cnt[q] = 0;
+    for (int64_t base = (int64_t)blockIdx.x * SORT_CHUNK; base < n;
+         base += (int64_t)gridDim.x * SORT_CHUNK) {
+        int bins[SORT_PER_THREAD];
+#pragma unroll
+        for (int m = 0; m < SORT_PER_THREAD; ++m) {
+            const int64_t p = base + m * 256 + threadIdx.x;
+            bins[m] = (p < n) ? sort_bin(src, p, nr) : -1;
         }
+        const int w0 = chunk_min_bin(bins, red);       // (barrier: cnt is zero)
+        // count the window's bins
+#pragma unroll
+        for (int m = 0; m < SORT_PER_THREAD; ++m) {
+            const bool valid = bins[m] >= 0;
+            int head, len;
+            wave_runs(bins[m], valid, lane, head, len);
+            if (valid && head == lane && bins[m] - w0 < SORT_WIN) atomicAdd(&cnt[bins[m] - w0], len);
+        }
+        __syncthreads();
+        // reserve each bin's range for this chunk: one global atomic per bin
+        for (int q = threadIdx.x; q < SORT_WIN; q += 256) {
+            const int c = cnt[q];
+            if (c) cnt[q] = atomicAdd(&off[w0 + q], c);
+            rk[q] = 0;
+        }
+        __syncthreads();
+        // rank within the bin (LDS) and move
+#pragma unroll
+        for (int m = 0; m < SORT_PER_THREAD; ++m) {
+            const int bin = bins[m];
+            const bool valid = bin >= 0;
+            int head, len;
+            wave_runs(bin, valid, lane, head, len);
+            int first = 0;
+            if (valid && head == lane) {
+                const int w = bin - w0;
+                if (w < SORT_WIN) first = cnt[w] + atomicAdd(&rk[w], len);
+                else first = atomicAdd(&off[bin], len);
+            }
+            first = __shfl(first, head, 64);
+            if (valid) copy_slot(src, dst, base + m * 256 + threadIdx.x, (int64_t)first + (lane - head));
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < SORT_WIN; q += 256) cnt[q] = 0;
+        __syncthreads();
     }
 }
 
@@ -182,8 +272,8 @@ void launch_sort(SpeciesDev<T> src, SpeciesDev<T> dst, DevScalars *sc, int speci
     const int32_t nbins = nr * nz;
     const int ntiles = (nbins + SCAN_TILE - 1) / SCAN_TILE;
     launch_zero(hist, (int64_t)nbins * 4, s);
-    int blocks = (int)((cap + 255) / 256);
-    if (blocks > 8192) blocks = 8192;
+    int blocks = (int)((cap + SORT_CHUNK - 1) / SORT_CHUNK);
+    if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL((k_sort_hist<T>), dim3(blocks), dim3(256), 0, s, src, sc, species, nr, hist);
     hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, hist, nbins, block_sums);
