@@ -12,7 +12,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import compare_particles, gpu_sim, oracle_from_gpu, say
+from gpu_helpers import to_species, compare_particles, gpu_sim, oracle_from_gpu, say
 from oracle import oracle as O
 from paper_2507_10727_amd import workloads as W
 
@@ -128,6 +128,58 @@ def test_f32_single_step(scheme):
     for j in range(3):
         assert abs(d_g["n_coll"][j] - d_o["n_coll"][j]) <= 2
     assert abs(d_g["n_cand"] - d_o["n_cand"]) <= 2
+
+
+def test_f32_full_size_sampled():
+    """The benchmark workload at its full size and launch shape (256x512 cells,
+    1e7 electrons + 1e7 Ar+, FP32, default blocks): one GPU step of all
+    particles, and a random sample of 20000 per species advanced by the
+    oracle from the same state and fields.  A particle's push, wall handling
+    and collision depend only on its own state, its random stream (id, step)
+    and the fields before the step, so the sampled particles are compared
+    one by one; children (whose ids follow the global order) are left out."""
+    p = W.preset("ec256x512_f32")
+    br, bz, sig, parts = W.inputs(p)
+    say("case f32 full size", p.name, p.n_per_species)
+    sim = gpu_sim(p, br, bz, sig, parts)
+    del parts
+    sim.step(2)
+    f = sim.fields_host()
+    st = sim.get_state()
+    rng = np.random.default_rng(11)
+    sample, ids = [], []
+    for s in range(2):
+        g = sim.particles(s)
+        pick = np.sort(rng.choice(g["id"].shape[0], 20000, replace=False))
+        sample.append(to_species({k: g[k][pick] for k in ("r", "z", "vr", "vt", "vz", "id")}))
+        ids.append(g["id"][pick])
+    o = O.Oracle(p, br, bz, sig, sample, capacity=(40000, 40000), rtol=1e-11)
+    o.init()
+    o.phi[:] = f["phi"]
+    o.phi0[:] = f["phi0"]
+    o.set_state(step=st["step"], vc=st["vc"])
+    o.state.qc = st["qc"]
+    sim.step(1)
+    o.step()
+    for s in range(2):
+        g = sim.particles(s)
+        keep = np.isin(g["id"], ids[s])
+        g = {k: v[keep] for k, v in g.items()}
+        r = o.particles(s)
+        keep = np.isin(r["id"], ids[s])
+        r = {k: v[keep] for k, v in r.items()}
+        ep, ev, only = compare_particles(p, g, r, s, 1e-5)
+        say("species", s, "sample", len(ids[s]), "kept", g["id"].shape[0], "pos", ep, "vel", ev)
+        assert only == 0 and ep < 1e-5 and ev < 1e-5
+        assert g["id"].shape[0] > 0.99 * len(ids[s])
+        # cells: identical except where FP32 and FP64 land on opposite
+        # sides of a cell edge
+        gi, ri = np.argsort(g["id"]), np.argsort(r["id"])
+        oi = np.floor(r["r"][ri] / p.dr).astype(np.int64)
+        oj = np.floor(r["z"][ri] / p.dz).astype(np.int64)
+        same = np.mean((g["i"][gi] == oi) & (g["j"][gi] == oj))
+        say("species", s, "same cell", same)
+        assert same >= 1 - 1e-3
 
 
 def test_deposit_total_charge_f32_f64():
