@@ -176,7 +176,8 @@ typedef struct pic_diag_out {
     int64_t n_cand, n_coll[3];  /* null-collision candidates; el, ex, iz          */
     int64_t n_see;
     int64_t n_child[2];
-    int64_t deposit_fallback;   /* particle chunks deposited without LDS tiles    */
+    int64_t deposit_fallback;   /* wavefront chunks (256 particles) whose charge
+                                   did not fit the LDS tile (global atomics)      */
     pic_poisson_stats poisson;  /* last field solve                               */
     int32_t flags;              /* bit 0 capacity, bit 1 child overflow, bit 2 NaN */
 } pic_diag_out;
