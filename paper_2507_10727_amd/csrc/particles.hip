@@ -36,7 +36,8 @@ namespace pic {
 //     (2 r dx + dx^2 + dy^2) / (r + r') so that the cell-relative position
 //     keeps full precision in FP32.
 //   Walls in priority z < 0 (cathode if r < cathode_rmax, else the Neumann
-//     block), r >= R, z >= L; absorbed slots get key -1.
+//     block), r >= R, z >= L; an absorbed slot is marked (key -1, or pz = -1
+//     in the packed FP32 state).
 //   Collisions for surviving electrons that existed before the step.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -936,8 +937,9 @@ void launch_begin_step(DevScalars *sc, void *q0, void *q1, int64_t nodes, int el
                        (uint32_t *)q1, words);
 }
 
-// Loader: absolute FP64 positions -> cell key and in-cell fraction,
-// i = floor(r / dr) kept in [0, nr-1], fr = r/dr - i.
+// Loader: absolute FP64 positions -> cell and in-cell fraction (stored as
+// the state's layout has it), i = floor(r / dr) kept in [0, nr-1],
+// fr = r/dr - i.
 template <typename T>
 __global__ void k_load(SpeciesDev<T> S, int64_t off, const double *r, const double *z,
                        const double *vr, const double *vt, const double *vz, const uint32_t *id,
