@@ -311,6 +311,12 @@ typedef struct pic_tuning {
     double push_e_weight;       /* default 1.3                                    */
     double push_ms;             /* autotune: mean particle-kernel time chosen     */
     int32_t trials;
+    int32_t mg_one_level;       /* multigrid V-cycle: 0 (default) runs pairs of
+                                   the small grid levels above the single-
+                                   workgroup coarse levels in one kernel each;
+                                   1 runs one kernel per level.  Both apply
+                                   the same operations to every node: results
+                                   agree to FP32 rounding.                    */
 } pic_tuning;
 
 pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out);

@@ -82,6 +82,7 @@ struct pic_handle {
     RunSolve *rsolve = nullptr;     // descriptor of the batched field update
     int push_blocks = 1024;
     double push_e_weight = 1.3;
+    bool mg_one_level = false;      // V-cycle with one kernel per grid level
     int32_t host_flags = 0;
     bool timers_on = false;
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
@@ -143,6 +144,22 @@ std::vector<LevelShape> mg_shapes(const pic_config &c)
     return v;
 }
 
+// The coarse levels small enough for one workgroup (<= 2600 nodes on the
+// first of them) run in the tail kernel, all in LDS; the coarsest level
+// always does.
+int tail_first(const std::vector<LevelShape> &shapes)
+{
+    const int nl = (int)shapes.size();
+    for (int l = 0; l < nl; ++l) {
+        int64_t words = (int64_t)(shapes[l].nr + 1) * (shapes[l].nz + 1);
+        const int64_t top = words;
+        for (int m = l; m < nl; ++m)
+            words += 2 * (int64_t)(shapes[m].nr + 1) * (shapes[m].nz + 1);
+        if (top <= 2600 && words * 4 <= MG_TAIL_LDS_MAX) return l;
+    }
+    return nl - 1;
+}
+
 pic_status validate(const pic_config *c, pic_handle *h)
 {
     if (!c) return fail(h, PIC_EINVAL, "config is NULL");
@@ -191,6 +208,12 @@ pic_status validate(const pic_config *c, pic_handle *h)
         return fail(h, PIC_EINVAL,
                     "grid %d x %d does not coarsen below 2048 unknowns (coarsest %d x %d)", c->nr,
                     c->nz, lv.back().nr, lv.back().nz);
+    const LevelShape &top = lv[tail_first(lv)];
+    if ((int64_t)(top.nr + 1) * (top.nz + 1) > MG_TAIL_NODES_MAX)
+        return fail(h, PIC_EINVAL,
+                    "grid %d x %d: its coarse levels start at %d x %d cells, above the %d nodes "
+                    "one workgroup solves",
+                    c->nr, c->nz, top.nr, top.nz, MG_TAIL_NODES_MAX);
     return PIC_OK;
 }
 
@@ -280,19 +303,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
         L.xd = cv.take<float>(nl * 4);
         L.xu = cv.take<float>(nl * 4);
     }
-    // the coarse levels small enough for one workgroup (<= 2600 nodes on
-    // the first of them) run in the tail kernel, all in LDS
-    int first = H.nlevels - 1;
-    for (int l = 0; l < H.nlevels; ++l) {
-        int64_t words = (int64_t)(shapes[l].nr + 1) * (shapes[l].nz + 1);
-        const int64_t top = words;
-        for (int m = l; m < H.nlevels; ++m)
-            words += 2 * (int64_t)(shapes[m].nr + 1) * (shapes[m].nz + 1);
-        if (top <= 2600 && words * 4 <= MG_TAIL_LDS_MAX) {
-            first = l;
-            break;
-        }
-    }
+    const int first = tail_first(shapes);
     H.tail.first = first;
     H.tail.last = H.nlevels - 1;
     H.tail.tmp_size = (shapes[first].nr + 1) * (shapes[first].nz + 1);
@@ -544,7 +555,7 @@ void enqueue_precond(pic_handle *h, int mode, int k)
     else if (mode == PIC_CG)
         pc_identity32(H.lv[0], H.lv[0].b, H.lv[0].xu, &h->sc->pcg_rz[k], s);
     else
-        launch_mg_vcycle(H, &h->sc->pcg_rz[k], s);
+        launch_mg_vcycle(H, &h->sc->pcg_rz[k], s, !h->mg_one_level);
 }
 
 // One refinement pass (after the residual that precedes it): scale, n_iter
@@ -1739,8 +1750,14 @@ pic_status pic_set_tuning(pic_handle *h, const pic_tuning *t)
     if (t->push_blocks < 2 || t->push_blocks > 65536 || !(t->push_e_weight > 0.0) ||
         !(t->push_e_weight < 100.0))
         return fail(h, PIC_EINVAL, "push_blocks in [2, 65536] and push_e_weight in (0, 100)");
+    if (t->mg_one_level != 0 && t->mg_one_level != 1)
+        return fail(h, PIC_EINVAL, "mg_one_level must be 0 or 1");
     h->push_blocks = t->push_blocks;
     h->push_e_weight = t->push_e_weight;
+    if (h->mg_one_level != (t->mg_one_level != 0)) {
+        h->mg_one_level = t->mg_one_level != 0;
+        drop_graphs(h);   // captured solves hold the other launch sequence
+    }
     return PIC_OK;
 }
 
@@ -1750,6 +1767,7 @@ pic_status pic_get_tuning(const pic_handle *h, pic_tuning *t)
     memset(t, 0, sizeof(*t));
     t->push_blocks = h->push_blocks;
     t->push_e_weight = h->push_e_weight;
+    t->mg_one_level = h->mg_one_level ? 1 : 0;
     return PIC_OK;
 }
 
@@ -1774,7 +1792,7 @@ pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out)
         *ms = h->timers.push_ms / std::max<int64_t>(h->timers.push_launches, 1);
         return PIC_OK;
     };
-    pic_tuning best = {h->push_blocks, h->push_e_weight, 1e300, 0};
+    pic_tuning best = {h->push_blocks, h->push_e_weight, 1e300, 0, h->mg_one_level ? 1 : 0};
     pic_status st = PIC_OK;
     // coordinate search: block count at the current weight, then the weight
     static const int blocks[] = {256, 512, 1024, 2048, 4096, 8192};

@@ -24,6 +24,7 @@ constexpr int PUSH_CHUNK = PUSH_THREADS * PUSH_PPT;
 constexpr int LDS_NODES = 4096;                    // deposit tiles of a block (nodes)
 constexpr int MAX_LEVELS = 16;
 constexpr int MG_TAIL_LDS_MAX = 128 * 1024;        // dynamic LDS of the coarse-level kernels
+constexpr int MG_TAIL_NODES_MAX = 4096;            // nodes of the first level of that kernel
 constexpr int MAX_PCG = 512;
 
 enum : int32_t { FLAG_CAPACITY = 1, FLAG_CHILD_OVERFLOW = 2, FLAG_NAN = 4 };
@@ -272,6 +273,18 @@ __device__ __forceinline__ void node_ij(int64_t n, int ld, int &i, int &j)
     i = (int)(u - (uint32_t)j * (uint32_t)ld);
 }
 
+// A solve's gate flag (kernels return at once when it is set and nonzero),
+// read with a vector load from a flag that is always there (a zero one when
+// the solve has none): it then completes in order with the data loads a
+// kernel issues after it and is waited for only where it is tested, whereas
+// a scalar load, or a branch around the load, waits for it up front.
+static __device__ int32_t gate_never;
+__device__ __forceinline__ int32_t gate_load(const int32_t *gate)
+{
+    return __hip_atomic_load(gate ? gate : &gate_never, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Order the LDS accesses of one wavefront's lanes before and after this point
 // (the lanes of a wavefront share the instruction stream; this keeps the
 // compiler from moving LDS accesses across it).
@@ -352,24 +365,37 @@ __device__ __forceinline__ bool mg_unknown(const MGLevel &L, int i, int j)
 {
     return i < L.nr && j < L.nz && !(j == 0 && i < L.cath);
 }
-__device__ __forceinline__ float mg_ae(const MGLevel &L, int i, int j)
+// couplings of an unknown node (i, j) of a level with nr x nz cells: west,
+// east, south, north (0 if absent); every term is computed and the absent
+// ones selected away, so the code has no branches
+__device__ __forceinline__ void mg_coup_v(int nr, int nz, float dz, float dr2dz, int i, int j,
+                                          float &w, float &e, float &s, float &n)
 {
-    const float hz = (j == 0 || j == L.nz) ? 0.5f * L.dz : L.dz;
-    return ((float)i + 0.5f) * hz;
+    const float hz = (j == 0 || j == nz) ? 0.5f * dz : dz;
+    const float g = (i == 0) ? 0.125f : ((i == nr) ? 0.5f * (float)nr - 0.125f : (float)i);
+    const float an = g * dr2dz;
+    const float aw = ((float)(i - 1) + 0.5f) * hz;
+    w = (i > 0) ? aw : 0.0f;
+    e = ((float)i + 0.5f) * hz;
+    s = (j > 0) ? an : 0.0f;
+    n = an;
 }
-__device__ __forceinline__ float mg_an(const MGLevel &L, int i)
-{
-    const float g = (i == 0) ? 0.125f : ((i == L.nr) ? 0.5f * (float)L.nr - 0.125f : (float)i);
-    return g * L.dr2dz;
-}
-// couplings of an unknown node: west, east, south, north (0 if absent)
 __device__ __forceinline__ void mg_coup(const MGLevel &L, int i, int j, float &w, float &e,
                                         float &s, float &n)
 {
-    w = (i > 0) ? mg_ae(L, i - 1, j) : 0.0f;
-    e = mg_ae(L, i, j);
-    s = (j > 0) ? mg_an(L, i) : 0.0f;
-    n = mg_an(L, i);
+    mg_coup_v(L.nr, L.nz, L.dz, L.dr2dz, i, j, w, e, s, n);
+}
+
+// bilinear prolongation from the coarse values around fine node (i, j):
+// c0 at (i/2, j/2), c1 east of it, c2 north, c3 north-east (c1..c3 are read
+// only where the parity of i, j needs them)
+__device__ __forceinline__ float mg_prolong_sel(bool oi, bool oj, float c0, float c1, float c2,
+                                                float c3)
+{
+    return (oi && oj) ? 0.25f * (c0 + c1 + c2 + c3)
+           : oi       ? 0.5f * (c0 + c1)
+           : oj       ? 0.5f * (c0 + c2)
+                      : c0;
 }
 
 struct MGTail {
@@ -390,7 +416,8 @@ struct MGHier {
     int32_t tail_lds_bytes;
 };
 
-void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s);   // lv[0].xu = M lv[0].b
+// lv[0].xu = M lv[0].b; two_level: pairs of small grid levels in one kernel
+void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s, bool two_level);
 // p = z + beta p_prev, q = A p, pq[0] += p.q (pq = &pcg_pq[k]); beta from
 // rz (Fletcher-Reeves) or, when zq is given, Polak-Ribiere (flexible CG)
 void launch_cg_matvec(const MGHier &H, const float *z, const float *pp, float *pc, float *q,

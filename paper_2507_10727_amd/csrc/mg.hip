@@ -28,17 +28,6 @@ namespace pic {
 
 namespace {
 
-// bilinear prolongation of the coarse correction to fine node (i, j)
-__device__ __forceinline__ float mg_prolong(const float *xc, int ldc, int i, int j)
-{
-    const int I = i >> 1, J = j >> 1;
-    const float *c = xc + (int64_t)J * ldc + I;
-    if (!(i & 1) && !(j & 1)) return c[0];
-    if ((i & 1) && !(j & 1)) return 0.5f * (c[0] + c[1]);
-    if (!(i & 1) && (j & 1)) return 0.5f * (c[0] + c[ldc]);
-    return 0.25f * (c[0] + c[1] + c[ldc] + c[ldc + 1]);
-}
-
 // red-black Gauss-Seidel pairs before (red, black) and after (black, red)
 // the coarse correction on every level; a half sweep is exact one node
 // further inside the tile than the one before it, so the tiles carry halos
@@ -51,37 +40,35 @@ constexpr int UTX = 32, UTY = 16;                // fine nodes per up tile
 constexpr int UH = 2 * MG_NU;
 constexpr int ULW = UTX + 2 * UH, ULH = UTY + 2 * UH;
 
-// Down: pre-smooth from zero, residual, restriction.  F.b is the fine
-// right-hand side; writes the smoothed F.xd and the coarse C.b.
-__device__ __forceinline__ void mg_down_body(const MGLevel &F, const MGLevel &C, int bx, int by)
+// The coarse levels are latency-bound (a few dozen blocks each), so every
+// kernel here issues all global loads of a phase before it uses the first
+// one, and reads its gate only after the loads are in flight: a loop that
+// loads and stores one element at a time waits one memory latency per
+// element.
+
+// ---- LDS tiles of one level (W x H nodes from (fi0, fj0)), shared by the
+// one- and two-level kernels; NT threads per block
+
+// red initial value of pre-smoothing from zero: x = b / diag on red nodes
+__device__ __forceinline__ float down_red(const MGLevel &F, int i, int j, float bv)
 {
-    if (F.gate && *F.gate) return;
-    __shared__ float sb[DLH][DLW];
-    __shared__ float sx[DLH][DLW];
-    const int I0 = bx * DTX, J0 = by * DTY;
-    const int fi0 = 2 * I0 - DH, fj0 = 2 * J0 - DH;
-    const int ld = F.nr + 1;
-    for (int t = threadIdx.x; t < DLW * DLH; t += 256) {
-        const int li = t % DLW, lj = t / DLW;
-        const int i = fi0 + li, j = fj0 + lj;
-        float bv = 0.0f, xv = 0.0f;
-        if (mg_in(F, i, j) && mg_unknown(F, i, j)) {
-            bv = F.b[(int64_t)j * ld + i];
-            if (((i + j) & 1) == 0) {
-                float w, e, s, n;
-                mg_coup(F, i, j, w, e, s, n);
-                xv = bv * __builtin_amdgcn_rcpf(w + e + s + n);
-            }
-        }
-        sb[lj][li] = bv;
-        sx[lj][li] = xv;
-    }
-    __syncthreads();
-    // half sweeps k = 1 .. 2 MG_NU - 1 (black, red, ...) on the region k
-    // nodes inside the tile
+    if (((i + j) & 1) != 0) return 0.0f;
+    float w, e, s, n;
+    mg_coup(F, i, j, w, e, s, n);
+    return bv * __builtin_amdgcn_rcpf(w + e + s + n);
+}
+
+// Pre-smoothing after the red initial values: half sweeps k = 1 .. 2 MG_NU - 1
+// (black, red, ...) on the region k nodes inside the tile, then the residual
+// on the region 2 MG_NU inside, written over sb.  Every step ends in a
+// barrier.
+template <int W, int H, int NT>
+__device__ __forceinline__ void tile_down_smooth(const MGLevel &F, int fi0, int fj0, float (*sb)[W],
+                                                 float (*sx)[W])
+{
     for (int k = 1; k < 2 * MG_NU; ++k) {
-        const int w_ = DLW - 2 * k, h_ = DLH - 2 * k, c = k & 1;
-        for (int t = threadIdx.x; t < w_ * h_; t += 256) {
+        const int w_ = W - 2 * k, h_ = H - 2 * k, c = k & 1;
+        for (int t = threadIdx.x; t < w_ * h_; t += NT) {
             const int li = k + t % w_, lj = k + t / w_;
             const int i = fi0 + li, j = fj0 + lj;
             if (((i + j) & 1) != c || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
@@ -93,9 +80,9 @@ __device__ __forceinline__ void mg_down_body(const MGLevel &F, const MGLevel &C,
         }
         __syncthreads();
     }
-    // residual on the region the restriction reads (written over b)
-    for (int t = threadIdx.x; t < (DLW - 4 * MG_NU) * (DLH - 4 * MG_NU); t += 256) {
-        const int li = 2 * MG_NU + t % (DLW - 4 * MG_NU), lj = 2 * MG_NU + t / (DLW - 4 * MG_NU);
+    constexpr int RW = W - 4 * MG_NU, RH = H - 4 * MG_NU;
+    for (int t = threadIdx.x; t < RW * RH; t += NT) {
+        const int li = 2 * MG_NU + t % RW, lj = 2 * MG_NU + t / RW;
         const int i = fi0 + li, j = fj0 + lj;
         float r = 0.0f;
         if (mg_in(F, i, j) && mg_unknown(F, i, j)) {
@@ -109,19 +96,109 @@ __device__ __forceinline__ void mg_down_body(const MGLevel &F, const MGLevel &C,
         sb[lj][li] = r;
     }
     __syncthreads();
+}
+
+// full weighting of the fine residual in sb around tile position (ci, cj)
+template <int W>
+__device__ __forceinline__ float tile_restrict(const float (*sb)[W], int ci, int cj)
+{
+    return sb[cj][ci] + 0.5f * (sb[cj][ci - 1] + sb[cj][ci + 1] + sb[cj - 1][ci] + sb[cj + 1][ci]) +
+           0.25f * (sb[cj - 1][ci - 1] + sb[cj - 1][ci + 1] + sb[cj + 1][ci - 1] +
+                    sb[cj + 1][ci + 1]);
+}
+
+// Post-smoothing after the prolonged correction is in sx: half sweeps
+// k = 0 .. 2 MG_NU - 1 (black, red, ...) on the region k + 1 nodes inside the
+// tile, each ending in a barrier.
+template <int W, int H, int NT>
+__device__ __forceinline__ void tile_up_smooth(const MGLevel &F, int fi0, int fj0, float (*sb)[W],
+                                               float (*sx)[W])
+{
+    for (int k = 0; k < 2 * MG_NU; ++k) {
+        const int w_ = W - 2 * (k + 1), h_ = H - 2 * (k + 1), c = (k & 1) ? 0 : 1;
+        for (int t = threadIdx.x; t < w_ * h_; t += NT) {
+            const int li = k + 1 + t % w_, lj = k + 1 + t / w_;
+            const int i = fi0 + li, j = fj0 + lj;
+            if (((i + j) & 1) != c || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
+            float w, e, s, n;
+            mg_coup(F, i, j, w, e, s, n);
+            const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
+                              n * sx[lj + 1][li];
+            sx[lj][li] = (sb[lj][li] + off) * __builtin_amdgcn_rcpf(w + e + s + n);
+        }
+        __syncthreads();
+    }
+}
+
+// Loads of an up tile's unknown nodes: b, xd and the (up to four) coarse
+// values of C.xu the bilinear prolongation reads: the east one only for odd
+// i, the north one only for odd j (both exist there: a fine level has even nr
+// and nz); the others, and the nodes that are not unknowns, load a node's own
+// (or the first) value again.
+template <int W, int H, int NT, int N>
+__device__ __forceinline__ void up_loads(const MGLevel &F, const MGLevel &C, int fi0, int fj0,
+                                         float *bl, float *xl, float *c0, float *c1, float *c2,
+                                         float *c3)
+{
+    const int ld = F.nr + 1, ldc = C.nr + 1;
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+        const int t = threadIdx.x + NT * u;
+        const int i = fi0 + t % W, j = fj0 + t / W;
+        const bool un = t < W * H && mg_in(F, i, j) && mg_unknown(F, i, j);
+        const int64_t n = un ? (int64_t)j * ld + i : 0;
+        const int64_t c = un ? (int64_t)(j >> 1) * ldc + (i >> 1) : 0;
+        const int oi = un ? (i & 1) : 0, oj = un ? (j & 1) * ldc : 0;
+        bl[u] = F.b[n];
+        xl[u] = F.xd[n];
+        c0[u] = C.xu[c];
+        c1[u] = C.xu[c + oi];
+        c2[u] = C.xu[c + oj];
+        c3[u] = C.xu[c + oi + oj];
+    }
+}
+
+// ---- one level per kernel
+
+// Down: pre-smooth from zero, residual, restriction.  F.b is the fine
+// right-hand side; writes the smoothed F.xd and the coarse C.b.
+constexpr int DN = (DLW * DLH + 255) / 256;      // tile elements per thread (down)
+constexpr int UN = (ULW * ULH + 255) / 256;      // (up)
+
+__device__ __forceinline__ void mg_down_body(const MGLevel &F, const MGLevel &C, int bx, int by)
+{
+    const int32_t gated = gate_load(F.gate);
+    __shared__ float sb[DLH][DLW];
+    __shared__ float sx[DLH][DLW];
+    const int I0 = bx * DTX, J0 = by * DTY;
+    const int fi0 = 2 * I0 - DH, fj0 = 2 * J0 - DH;
+    const int ld = F.nr + 1;
+    float bl[DN];
+#pragma unroll
+    for (int u = 0; u < DN; ++u) {
+        const int t = threadIdx.x + 256 * u;
+        const int i = fi0 + t % DLW, j = fj0 + t / DLW;
+        const bool un = t < DLW * DLH && mg_in(F, i, j) && mg_unknown(F, i, j);
+        bl[u] = F.b[un ? (int64_t)j * ld + i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < DN; ++u) {
+        const int t = threadIdx.x + 256 * u;
+        if (t >= DLW * DLH) continue;
+        const int li = t % DLW, lj = t / DLW;
+        const int i = fi0 + li, j = fj0 + lj;
+        const bool un = mg_in(F, i, j) && mg_unknown(F, i, j);
+        sb[lj][li] = un ? bl[u] : 0.0f;
+        sx[lj][li] = un ? down_red(F, i, j, bl[u]) : 0.0f;
+    }
+    if (gated) return;   // uniform: the whole block leaves before its first barrier
+    __syncthreads();
+    tile_down_smooth<DLW, DLH, 256>(F, fi0, fj0, sb, sx);
     const int ldc = C.nr + 1;
     for (int t = threadIdx.x; t < DTX * DTY; t += 256) {
         const int I = I0 + t % DTX, J = J0 + t / DTX;
         if (I > C.nr || J > C.nz) continue;
-        float v = 0.0f;
-        if (mg_unknown(C, I, J)) {
-            const int ci = 2 * I - fi0, cj = 2 * J - fj0;
-            v = sb[cj][ci] + 0.5f * (sb[cj][ci - 1] + sb[cj][ci + 1] + sb[cj - 1][ci] +
-                                     sb[cj + 1][ci]) +
-                0.25f * (sb[cj - 1][ci - 1] + sb[cj - 1][ci + 1] + sb[cj + 1][ci - 1] +
-                         sb[cj + 1][ci + 1]);
-        }
-        C.b[(int64_t)J * ldc + I] = v;
+        C.b[(int64_t)J * ldc + I] = mg_unknown(C, I, J) ? tile_restrict<DLW>(sb, 2 * I - fi0, 2 * J - fj0) : 0.0f;
     }
     // fine nodes owned by this tile: [2 I0, 2 I0 + 2 DTX) x [2 J0, 2 J0 + 2 DTY)
     for (int t = threadIdx.x; t < 4 * DTX * DTY; t += 256) {
@@ -136,42 +213,28 @@ __device__ __forceinline__ void mg_down_body(const MGLevel &F, const MGLevel &C,
 __device__ __forceinline__ void mg_up_body(const MGLevel &F, const MGLevel &C, double *dot, int bx,
                                            int by)
 {
-    if (F.gate && *F.gate) return;
+    const int32_t gated = gate_load(F.gate);
     __shared__ float sb[ULH][ULW];
     __shared__ float sx[ULH][ULW];
     __shared__ double red[4];
     const int i0 = bx * UTX, j0 = by * UTY;
     const int fi0 = i0 - UH, fj0 = j0 - UH;
-    const int ld = F.nr + 1, ldc = C.nr + 1;
-    for (int t = threadIdx.x; t < ULW * ULH; t += 256) {
+    const int ld = F.nr + 1;
+    float bl[UN], xl[UN], c0[UN], c1[UN], c2[UN], c3[UN];
+    up_loads<ULW, ULH, 256, UN>(F, C, fi0, fj0, bl, xl, c0, c1, c2, c3);
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+        const int t = threadIdx.x + 256 * u;
+        if (t >= ULW * ULH) continue;
         const int li = t % ULW, lj = t / ULW;
         const int i = fi0 + li, j = fj0 + lj;
-        float bv = 0.0f, xv = 0.0f;
-        if (mg_in(F, i, j) && mg_unknown(F, i, j)) {
-            const int64_t n = (int64_t)j * ld + i;
-            bv = F.b[n];
-            xv = F.xd[n] + mg_prolong(C.xu, ldc, i, j);
-        }
-        sb[lj][li] = bv;
-        sx[lj][li] = xv;
+        const bool un = mg_in(F, i, j) && mg_unknown(F, i, j);
+        sb[lj][li] = un ? bl[u] : 0.0f;
+        sx[lj][li] = un ? xl[u] + mg_prolong_sel(i & 1, j & 1, c0[u], c1[u], c2[u], c3[u]) : 0.0f;
     }
+    if (gated) return;
     __syncthreads();
-    // half sweeps k = 0 .. 2 MG_NU - 1 (black, red, ...) on the region k + 1
-    // nodes inside the tile
-    for (int k = 0; k < 2 * MG_NU; ++k) {
-        const int w_ = ULW - 2 * (k + 1), h_ = ULH - 2 * (k + 1), c = (k & 1) ? 0 : 1;
-        for (int t = threadIdx.x; t < w_ * h_; t += 256) {
-            const int li = k + 1 + t % w_, lj = k + 1 + t / w_;
-            const int i = fi0 + li, j = fj0 + lj;
-            if (((i + j) & 1) != c || !mg_in(F, i, j) || !mg_unknown(F, i, j)) continue;
-            float w, e, s, n;
-            mg_coup(F, i, j, w, e, s, n);
-            const float off = w * sx[lj][li - 1] + e * sx[lj][li + 1] + s * sx[lj - 1][li] +
-                              n * sx[lj + 1][li];
-            sx[lj][li] = (sb[lj][li] + off) * __builtin_amdgcn_rcpf(w + e + s + n);
-        }
-        __syncthreads();
-    }
+    tile_up_smooth<ULW, ULH, 256>(F, fi0, fj0, sb, sx);
     double acc = 0.0;
     for (int t = threadIdx.x; t < UTX * UTY; t += 256) {
         const int i = i0 + t % UTX, j = j0 + t / UTX;
@@ -191,149 +254,424 @@ __device__ __forceinline__ void mg_up_body(const MGLevel &F, const MGLevel &C, d
     }
 }
 
-// Tail: every level from `first` down to the coarsest in one workgroup
-// (32 x 32 threads, thread (tx, ty) visits nodes i = tx + 32a, j = ty + 32b;
-// a colour sweep visits only its own parity).  Reads L[first].b, writes
-// L[first].xu (and sum(b * x) into dot if given).
-constexpr int TT = 32;
+// ---- two levels per kernel (F -> M -> C down, C -> M -> F up), for the
+// small grid levels just above the tail: one launch in place of two.  A tile
+// carries the halos of both levels, and every node is computed with the
+// operations of the one-level kernels (results agree to FP32 rounding: the
+// compiler may contract multiply-adds differently in the two kernels).
 
-__device__ __forceinline__ void tail_sweep(const MGLevel &L, float *x, const float *b, int c)
+// Down: tile of D2W x D2H coarse (C) nodes; the M region is what a one-level
+// down tile of that size loads, the F region what the M region's b needs.
+constexpr int D2W = 8, D2H = 4, D2T = 512;
+constexpr int D2MW = 2 * D2W + 2 * DH - 1, D2MH = 2 * D2H + 2 * DH - 1;
+constexpr int D2FW = 2 * D2MW + 2 * DH - 1, D2FH = 2 * D2MH + 2 * DH - 1;
+constexpr int D2N = (D2FW * D2FH + D2T - 1) / D2T;
+
+__device__ __forceinline__ void mg_down2_body(const MGLevel &F, const MGLevel &M, const MGLevel &C,
+                                              int bx, int by)
 {
-    const int ld = L.nr + 1;
-    for (int j = threadIdx.y; j < L.nz; j += TT) {
-        for (int i = 2 * threadIdx.x + ((j + c) & 1); i < L.nr; i += 2 * TT) {
-            if (j == 0 && i < L.cath) continue;
-            const int n = j * ld + i;
-            float w, e, s, nn;
-            mg_coup(L, i, j, w, e, s, nn);
-            const float o = (i > 0 ? w * x[n - 1] : 0.0f) + e * x[n + 1] +
-                            (j > 0 ? s * x[n - ld] : 0.0f) + nn * x[n + ld];
-            x[n] = (b[n] + o) * __builtin_amdgcn_rcpf(w + e + s + nn);
-        }
+    const int32_t gated = gate_load(F.gate);
+    __shared__ float fb[D2FH][D2FW], fx[D2FH][D2FW];
+    __shared__ float mb[D2MH][D2MW], mx[D2MH][D2MW];
+    const int I0 = bx * D2W, J0 = by * D2H;
+    const int mi0 = 2 * I0 - DH, mj0 = 2 * J0 - DH;
+    const int fi0 = 2 * mi0 - DH, fj0 = 2 * mj0 - DH;
+    const int ld = F.nr + 1, ldm = M.nr + 1, ldc = C.nr + 1;
+    float bl[D2N];
+#pragma unroll
+    for (int u = 0; u < D2N; ++u) {
+        const int t = threadIdx.x + D2T * u;
+        const int i = fi0 + t % D2FW, j = fj0 + t / D2FW;
+        const bool un = t < D2FW * D2FH && mg_in(F, i, j) && mg_unknown(F, i, j);
+        bl[u] = F.b[un ? (int64_t)j * ld + i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < D2N; ++u) {
+        const int t = threadIdx.x + D2T * u;
+        if (t >= D2FW * D2FH) continue;
+        const int li = t % D2FW, lj = t / D2FW;
+        const int i = fi0 + li, j = fj0 + lj;
+        const bool un = mg_in(F, i, j) && mg_unknown(F, i, j);
+        fb[lj][li] = un ? bl[u] : 0.0f;
+        fx[lj][li] = un ? down_red(F, i, j, bl[u]) : 0.0f;
+    }
+    if (gated) return;
+    __syncthreads();
+    tile_down_smooth<D2FW, D2FH, D2T>(F, fi0, fj0, fb, fx);
+    // M region: b restricted from F's residual, red initial x; the M nodes
+    // this block owns ([2 I0, 2 I0 + 2 D2W) x [2 J0, 2 J0 + 2 D2H)) store b
+    for (int t = threadIdx.x; t < D2MW * D2MH; t += D2T) {
+        const int li = t % D2MW, lj = t / D2MW;
+        const int I = mi0 + li, J = mj0 + lj;
+        const bool un = mg_in(M, I, J) && mg_unknown(M, I, J);
+        const float bv = un ? tile_restrict<D2FW>(fb, 2 * I - fi0, 2 * J - fj0) : 0.0f;
+        mb[lj][li] = bv;
+        mx[lj][li] = un ? down_red(M, I, J, bv) : 0.0f;
+        if (I >= 2 * I0 && I < 2 * I0 + 2 * D2W && J >= 2 * J0 && J < 2 * J0 + 2 * D2H &&
+            I <= M.nr && J <= M.nz)
+            M.b[(int64_t)J * ldm + I] = bv;
+    }
+    // F nodes owned: [4 I0, 4 I0 + 4 D2W) x [4 J0, 4 J0 + 4 D2H)
+    for (int t = threadIdx.x; t < 16 * D2W * D2H; t += D2T) {
+        const int i = 4 * I0 + t % (4 * D2W), j = 4 * J0 + t / (4 * D2W);
+        if (i > F.nr || j > F.nz) continue;
+        F.xd[(int64_t)j * ld + i] = fx[j - fj0][i - fi0];
+    }
+    __syncthreads();
+    tile_down_smooth<D2MW, D2MH, D2T>(M, mi0, mj0, mb, mx);
+    for (int t = threadIdx.x; t < D2W * D2H; t += D2T) {
+        const int I = I0 + t % D2W, J = J0 + t / D2W;
+        if (I > C.nr || J > C.nz) continue;
+        C.b[(int64_t)J * ldc + I] = mg_unknown(C, I, J) ? tile_restrict<D2MW>(mb, 2 * I - mi0, 2 * J - mj0) : 0.0f;
+    }
+    for (int t = threadIdx.x; t < 4 * D2W * D2H; t += D2T) {
+        const int I = 2 * I0 + t % (2 * D2W), J = 2 * J0 + t / (2 * D2W);
+        if (I > M.nr || J > M.nz) continue;
+        M.xd[(int64_t)J * ldm + I] = mx[J - mj0][I - mi0];
     }
 }
 
+// Up: tile of UTX x UTY fine (F) nodes as in the one-level kernel; the M
+// region covers the M nodes F's prolongation reads plus the M sweeps' halo.
+constexpr int U2MW = UTX / 2 + 3 * UH + 1, U2MH = UTY / 2 + 3 * UH + 1;
+constexpr int U2N = (U2MW * U2MH + 255) / 256;
+
+__device__ __forceinline__ void mg_up2_body(const MGLevel &F, const MGLevel &M, const MGLevel &C,
+                                            int bx, int by)
+{
+    const int32_t gated = gate_load(F.gate);
+    __shared__ float fb[ULH][ULW], fx[ULH][ULW];
+    __shared__ float mb[U2MH][U2MW], mx[U2MH][U2MW];
+    const int i0 = bx * UTX, j0 = by * UTY;
+    const int fi0 = i0 - UH, fj0 = j0 - UH;
+    const int mi0 = (fi0 >> 1) - UH, mj0 = (fj0 >> 1) - UH;
+    const int ld = F.nr + 1;
+    float mbl[U2N], mxl[U2N], c0[U2N], c1[U2N], c2[U2N], c3[U2N];
+    up_loads<U2MW, U2MH, 256, U2N>(M, C, mi0, mj0, mbl, mxl, c0, c1, c2, c3);
+    float fbl[UN], fxl[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+        const int t = threadIdx.x + 256 * u;
+        const int i = fi0 + t % ULW, j = fj0 + t / ULW;
+        const bool un = t < ULW * ULH && mg_in(F, i, j) && mg_unknown(F, i, j);
+        const int64_t n = un ? (int64_t)j * ld + i : 0;
+        fbl[u] = F.b[n];
+        fxl[u] = F.xd[n];
+    }
+#pragma unroll
+    for (int u = 0; u < U2N; ++u) {
+        const int t = threadIdx.x + 256 * u;
+        if (t >= U2MW * U2MH) continue;
+        const int li = t % U2MW, lj = t / U2MW;
+        const int I = mi0 + li, J = mj0 + lj;
+        const bool un = mg_in(M, I, J) && mg_unknown(M, I, J);
+        mb[lj][li] = un ? mbl[u] : 0.0f;
+        mx[lj][li] = un ? mxl[u] + mg_prolong_sel(I & 1, J & 1, c0[u], c1[u], c2[u], c3[u]) : 0.0f;
+    }
+    if (gated) return;
+    __syncthreads();
+    tile_up_smooth<U2MW, U2MH, 256>(M, mi0, mj0, mb, mx);
+    // F: xd plus the prolongation of M's smoothed values (exact on the M
+    // region UH nodes inside, which holds every M node read here)
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+        const int t = threadIdx.x + 256 * u;
+        if (t >= ULW * ULH) continue;
+        const int li = t % ULW, lj = t / ULW;
+        const int i = fi0 + li, j = fj0 + lj;
+        float bv = 0.0f, xv = 0.0f;
+        if (mg_in(F, i, j) && mg_unknown(F, i, j)) {
+            const int oi = i & 1, oj = j & 1;
+            const int mi = (i >> 1) - mi0, mj = (j >> 1) - mj0;
+            bv = fbl[u];
+            xv = fxl[u] + mg_prolong_sel(oi, oj, mx[mj][mi], mx[mj][mi + oi], mx[mj + oj][mi],
+                                         mx[mj + oj][mi + oi]);
+        }
+        fb[lj][li] = bv;
+        fx[lj][li] = xv;
+    }
+    __syncthreads();
+    tile_up_smooth<ULW, ULH, 256>(F, fi0, fj0, fb, fx);
+    for (int t = threadIdx.x; t < UTX * UTY; t += 256) {
+        const int i = i0 + t % UTX, j = j0 + t / UTX;
+        if (i > F.nr || j > F.nz) continue;
+        F.xu[(int64_t)j * ld + i] = fx[j - fj0][i - fi0];
+    }
+}
+
+// Tail: every level from `first` down to the coarsest in one workgroup of
+// TT x TT threads, all in LDS.  Reads L[first].b, writes L[first].xu (and
+// sum(b * x) into dot if given).  Loops run flat over a level's nodes (or
+// over one colour's nodes in a sweep); each pass of a thread issues all of
+// its LDS reads before it uses them, and the couplings and the absent
+// neighbours of boundary nodes are selected, not branched around, so a pass
+// waits for LDS once.
+constexpr int TT = 32;
+constexpr int TN = TT * TT;
+
+// Per-level constants, read from the kernel argument once per level and held
+// in scalar registers (the compiler would otherwise re-read the invariant
+// argument inside every loop and wait for each read).
+struct TailLevel {
+    int nr, nz, cath, ld;
+    float dz, dr2dz;
+    float *x, *b;
+};
+
+// (the batched kernel reads the same fields from device memory into vector
+// registers: readfirstlane moves the uniform value to a scalar register)
+__device__ __forceinline__ int in_sreg(int v)
+{
+    int r = __builtin_amdgcn_readfirstlane(v);
+    asm volatile("" : "+s"(r));
+    return r;
+}
+__device__ __forceinline__ float in_sreg(float v)
+{
+    return __builtin_bit_cast(float, in_sreg(__builtin_bit_cast(int, v)));
+}
+
+__device__ __forceinline__ TailLevel tail_level(const MGTail &T, float *sm, int l)
+{
+    TailLevel v;
+    v.nr = in_sreg(T.L[l].nr);
+    v.nz = in_sreg(T.L[l].nz);
+    v.cath = in_sreg(T.L[l].cath);
+    v.ld = v.nr + 1;
+    v.dz = in_sreg(T.L[l].dz);
+    v.dr2dz = in_sreg(T.L[l].dr2dz);
+    v.x = sm + in_sreg(T.offx[l]);
+    v.b = sm + in_sreg(T.offb[l]);
+    return v;
+}
+
+__device__ __forceinline__ bool tail_unknown(const TailLevel &L, int i, int j)
+{
+    return i < L.nr && j < L.nz && !(j == 0 && i < L.cath);
+}
+
+// A x - b's negative at unknown node (i, j) = m: b - (diag x - sum c x_nb);
+// the west / south neighbours of the first column / row read the node
+// itself, with a zero coupling
+__device__ __forceinline__ float tail_res(const TailLevel &L, int i, int j, int m)
+{
+    float w, e, s, n;
+    mg_coup_v(L.nr, L.nz, L.dz, L.dr2dz, i, j, w, e, s, n);
+    const float o = w * L.x[m - (i > 0 ? 1 : 0)] + e * L.x[m + 1] +
+                    s * L.x[m - (j > 0 ? L.ld : 0)] + n * L.x[m + L.ld];
+    return L.b[m] - ((w + e + s + n) * L.x[m] - o);
+}
+
+// One colour c of a red-black sweep: nodes with (i + j + c) even.  A swept
+// level has even nr (it has a coarser level), so each row holds nr / 2 nodes
+// of a colour; a thread updates two per pass.
+__device__ __forceinline__ void tail_sweep(const TailLevel &L, int c, int tid)
+{
+    const int half = L.nr >> 1, cnt = half * L.nz;
+    for (int h0 = tid; h0 < cnt; h0 += 2 * TN) {
+        float xn[2], dg[2], bb[2];
+        int mm[2];
+        bool ok[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int h = h0 + u * TN;
+            const int hh = h < cnt ? h : 0;
+            const int j = (int)((uint32_t)hh / (uint32_t)half);
+            const int i = 2 * (hh - j * half) + ((j + c) & 1);
+            ok[u] = h < cnt && !(j == 0 && i < L.cath);
+            float w, e, s, n;
+            mg_coup_v(L.nr, L.nz, L.dz, L.dr2dz, i, j, w, e, s, n);
+            const int m = j * L.ld + i;
+            mm[u] = m;
+            xn[u] = w * L.x[m - (i > 0 ? 1 : 0)] + e * L.x[m + 1] +
+                    s * L.x[m - (j > 0 ? L.ld : 0)] + n * L.x[m + L.ld];
+            bb[u] = L.b[m];
+            dg[u] = w + e + s + n;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (ok[u]) L.x[mm[u]] = (bb[u] + xn[u]) * __builtin_amdgcn_rcpf(dg[u]);
+    }
+}
+
+// Right-hand-side values per thread loaded up front, and the share of the
+// dense inverse held in registers (rows g + 32 r, columns lane + 32 m of a
+// 32-lane group g): inverses of up to 32 TDR unknowns arrive while the
+// levels above the coarsest are smoothed; larger ones are read when needed.
+constexpr int TBN = MG_TAIL_NODES_MAX / TN;
+constexpr int TDR = 7;
+static_assert(TBN * TN == MG_TAIL_NODES_MAX, "tail rows per thread");
+
 __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float *sm)
 {
-    if (T.L[T.first].gate && *T.L[T.first].gate) return;
+    const int32_t gated = gate_load(T.L[T.first].gate);
     float *tmp = sm;
-#define X(l) (sm + T.offx[(l)])
-#define B(l) (sm + T.offb[(l)])
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    {
-        const MGLevel &L = T.L[T.first];
-        const int ld = L.nr + 1;
-        for (int j = ty; j <= L.nz; j += TT)
-            for (int i = tx; i <= L.nr; i += TT) {
-                const int n = j * ld + i;
-                B(T.first)[n] = L.b[n];
-                X(T.first)[n] = 0.0f;
-            }
+    const int tid = threadIdx.y * TT + threadIdx.x;
+    const int g = tid >> 5, lane = tid & 31;
+    const bool dense_regs = T.ninv > 0 && T.ninv <= 32 * TDR;
+    float bl[TBN], inv[TDR][TDR];
+    int32_t col[TDR];
+#pragma unroll
+    for (int u = 0; u < TBN; ++u) {
+        const int n = tid + TN * u;
+        bl[u] = T.L[T.first].b[n < T.tmp_size ? n : 0];
     }
+    // loads complete in issue order: keep the right-hand side ahead of the
+    // inverse, so the first phase waits only for its own loads
+    asm volatile("" ::: "memory");
+    // issued unconditionally (a branch around them would make every later
+    // wait assume the worst case): an inverse too large for the registers
+    // reads the first right-hand-side word in their place
+    {
+        const float *ip = dense_regs ? T.inv : T.L[T.first].b;
+        const int32_t *mp = dense_regs ? T.map : (const int32_t *)T.L[T.first].b;
+#pragma unroll
+        for (int m = 0; m < TDR; ++m) {
+            const int c = lane + 32 * m;
+            const bool cv = dense_regs && c < T.ninv;
+            col[m] = mp[cv ? c : 0];
+#pragma unroll
+            for (int r = 0; r < TDR; ++r) {
+                const int a = g + 32 * r;
+                inv[r][m] = ip[(cv && a < T.ninv) ? (int64_t)a * T.ninv + c : 0];
+            }
+        }
+    }
+    {
+        const TailLevel L = tail_level(T, sm, T.first);
+#pragma unroll
+        for (int u = 0; u < TBN; ++u) {
+            const int n = tid + TN * u;
+            if (n < T.tmp_size) {
+                L.b[n] = bl[u];
+                L.x[n] = 0.0f;
+            }
+        }
+    }
+    if (gated) return;   // uniform: the whole block leaves before its first barrier
     __syncthreads();
     // descend: x = 0, red-black sweep, residual, restriction
     for (int l = T.first; l < T.last; ++l) {
-        const MGLevel &L = T.L[l];
-        const int ld = L.nr + 1;
-        float *x = X(l), *b = B(l);
+        const TailLevel L = tail_level(T, sm, l);
         for (int k = 0; k < MG_NU; ++k) {
-            tail_sweep(L, x, b, 0);
+            tail_sweep(L, 0, tid);
             __syncthreads();
-            tail_sweep(L, x, b, 1);
+            tail_sweep(L, 1, tid);
             __syncthreads();
         }
-        for (int j = ty; j <= L.nz; j += TT)
-            for (int i = tx; i <= L.nr; i += TT) {
-                const int n = j * ld + i;
-                float r = 0.0f;
-                if (mg_unknown(L, i, j)) {
-                    float w, e, s, nn;
-                    mg_coup(L, i, j, w, e, s, nn);
-                    const float o = (i > 0 ? w * x[n - 1] : 0.0f) + e * x[n + 1] +
-                                    (j > 0 ? s * x[n - ld] : 0.0f) + nn * x[n + ld];
-                    r = b[n] - ((w + e + s + nn) * x[n] - o);
-                }
-                tmp[n] = r;
-            }
+        const int nn = L.ld * (L.nz + 1);
+        for (int n = tid; n < nn; n += TN) {
+            int i, j;
+            node_ij(n, L.ld, i, j);
+            tmp[n] = tail_unknown(L, i, j) ? tail_res(L, i, j, n) : 0.0f;
+        }
         __syncthreads();
-        const MGLevel &C = T.L[l + 1];
-        const int ldc = C.nr + 1;
-        for (int J = ty; J <= C.nz; J += TT)
-            for (int I = tx; I <= C.nr; I += TT) {
-                float v = 0.0f;
-                if (mg_unknown(C, I, J)) {
-                    const int c = 2 * J * ld + 2 * I;
-                    const bool w = I > 0, s = J > 0;   // fine 2I-1 / 2J-1 exist
-                    v = tmp[c] + 0.5f * ((w ? tmp[c - 1] : 0.0f) + tmp[c + 1] +
-                                         (s ? tmp[c - ld] : 0.0f) + tmp[c + ld]) +
-                        0.25f * ((w && s ? tmp[c - ld - 1] : 0.0f) + (s ? tmp[c - ld + 1] : 0.0f) +
-                                 (w ? tmp[c + ld - 1] : 0.0f) + tmp[c + ld + 1]);
-                }
-                B(l + 1)[J * ldc + I] = v;
-                X(l + 1)[J * ldc + I] = 0.0f;
+        const TailLevel C = tail_level(T, sm, l + 1);
+        const int nc = C.ld * (C.nz + 1);
+        for (int n = tid; n < nc; n += TN) {
+            int I, J;
+            node_ij(n, C.ld, I, J);
+            float v = 0.0f;
+            if (tail_unknown(C, I, J)) {
+                // full weighting of the fine residual; fine nodes 2I-1 / 2J-1
+                // are absent on the first coarse column / row
+                const int c = 2 * J * L.ld + 2 * I;
+                const bool w = I > 0, s = J > 0;
+                const int dw = w ? 1 : 0, ds = s ? L.ld : 0;
+                const float tw = tmp[c - dw], ts = tmp[c - ds], tsw = tmp[c - ds - dw];
+                const float tse = tmp[c - ds + 1], tnw = tmp[c + L.ld - dw];
+                v = tmp[c] + 0.5f * ((w ? tw : 0.0f) + tmp[c + 1] + (s ? ts : 0.0f) + tmp[c + L.ld]) +
+                    0.25f * ((w && s ? tsw : 0.0f) + (s ? tse : 0.0f) + (w ? tnw : 0.0f) +
+                             tmp[c + L.ld + 1]);
             }
+            C.b[n] = v;
+            C.x[n] = 0.0f;
+        }
         __syncthreads();
     }
     // coarsest: dense inverse on the unknowns, x = A^-1 b; 32 lanes per row
-    // (each a strided part of the row, summed with lane shuffles), so every
-    // thread has only a few independent loads of the inverse in flight
+    // (each a strided part of the row, summed with lane shuffles)
     {
-        const int tid = ty * TT + tx;
-        const int g = tid >> 5, lane = tid & 31;
-        const float *bc = B(T.last);
-        for (int a0 = 0; a0 < T.ninv; a0 += (TT * TT) / 32) {
-            const int a = a0 + g;
-            float acc = 0.0f;
-            if (a < T.ninv) {
-                const float *row = T.inv + (int64_t)a * T.ninv;
-                for (int c = lane; c < T.ninv; c += 32) acc += row[c] * bc[T.map[c]];
+        const TailLevel C = tail_level(T, sm, T.last);
+        if (dense_regs) {
+            float bq[TDR], acc[TDR];
+#pragma unroll
+            for (int m = 0; m < TDR; ++m) bq[m] = C.b[col[m]];
+#pragma unroll
+            for (int r = 0; r < TDR; ++r) {
+                acc[r] = 0.0f;
+#pragma unroll
+                for (int m = 0; m < TDR; ++m)
+                    if (lane + 32 * m < T.ninv) acc[r] += inv[r][m] * bq[m];
             }
-            for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
-            if (a < T.ninv && lane == 0) X(T.last)[T.map[a]] = acc;
+            // the rows' shuffle steps interleaved: one LDS wait per step
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1)
+#pragma unroll
+                for (int r = 0; r < TDR; ++r) acc[r] += __shfl_xor(acc[r], o, 32);
+            // every lane holds the sums; lane g holds map[g + 32 r] = map[a]
+#pragma unroll
+            for (int r = 0; r < TDR; ++r)
+                if (g + 32 * r < T.ninv && lane == g) C.x[col[r]] = acc[r];
+        } else {
+            for (int a0 = 0; a0 < T.ninv; a0 += TN / 32) {
+                const int a = a0 + g;
+                float acc = 0.0f;
+                if (a < T.ninv) {
+                    const float *row = T.inv + (int64_t)a * T.ninv;
+                    for (int c = lane; c < T.ninv; c += 32) acc += row[c] * C.b[T.map[c]];
+                }
+                for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+                if (a < T.ninv && lane == 0) C.x[T.map[a]] = acc;
+            }
         }
         __syncthreads();
     }
     // ascend: prolongation, black-red sweep
     for (int l = T.last - 1; l >= T.first; --l) {
-        const MGLevel &L = T.L[l];
-        const int ld = L.nr + 1, ldc = T.L[l + 1].nr + 1;
-        float *x = X(l), *b = B(l);
-        for (int j = ty; j <= L.nz; j += TT)
-            for (int i = tx; i <= L.nr; i += TT)
-                if (mg_unknown(L, i, j)) x[j * ld + i] += mg_prolong(X(l + 1), ldc, i, j);
+        const TailLevel L = tail_level(T, sm, l);
+        const TailLevel C = tail_level(T, sm, l + 1);
+        const int nn = L.ld * (L.nz + 1);
+        for (int n = tid; n < nn; n += TN) {
+            int i, j;
+            node_ij(n, L.ld, i, j);
+            if (tail_unknown(L, i, j)) {
+                // unknown fine nodes have i < nr, j < nz: the east / north
+                // coarse values exist where odd i / j reads them
+                const int oi = i & 1, oj = (j & 1) ? C.ld : 0;
+                const float *c = C.x + (j >> 1) * C.ld + (i >> 1);
+                L.x[n] += mg_prolong_sel(oi, oj, c[0], c[oi], c[oj], c[oi + oj]);
+            }
+        }
         __syncthreads();
         for (int k = 0; k < MG_NU; ++k) {
-            tail_sweep(L, x, b, 1);
+            tail_sweep(L, 1, tid);
             __syncthreads();
-            tail_sweep(L, x, b, 0);
+            tail_sweep(L, 0, tid);
             __syncthreads();
         }
     }
     {
-        const MGLevel &L = T.L[T.first];
-        const int ld = L.nr + 1;
+        const TailLevel L = tail_level(T, sm, T.first);
+        float *xu = T.L[T.first].xu;
         double acc = 0.0;
-        for (int j = ty; j <= L.nz; j += TT)
-            for (int i = tx; i <= L.nr; i += TT) {
-                const int n = j * ld + i;
-                L.xu[n] = X(T.first)[n];
-                acc += (double)X(T.first)[n] * (double)B(T.first)[n];
-            }
+        for (int n = tid; n < T.tmp_size; n += TN) {
+            const float v = L.x[n];
+            xu[n] = v;
+            acc += (double)v * (double)L.b[n];
+        }
         if (dot) {
-            __shared__ double red[16];
-            const int tid = ty * TT + tx;
+            __shared__ double red[TN / 64];
             acc = wave_sum(acc);
             if ((tid & 63) == 0) red[tid >> 6] = acc;
             __syncthreads();
             if (tid == 0) {
                 double s = 0.0;
-                for (int w = 0; w < (TT * TT) / 64; ++w) s += red[w];
+                for (int w = 0; w < TN / 64; ++w) s += red[w];
                 if (s != 0.0) atomic_add_dev(dot, s);
             }
         }
     }
-#undef X
-#undef B
 }
 
 // ---- conjugate-gradient vector kernels on the finest level
@@ -345,7 +683,7 @@ __device__ __forceinline__ void cg_matvec_body(const MGLevel &L, const float *z,
                                                float *pc, float *q, const double *rz, int k,
                                                double *pq, const double *zq, int blk, int nblk)
 {
-    if (L.gate && *L.gate) return;
+    const int32_t gated = gate_load(L.gate);   // tested after the loads are issued
     __shared__ double red[CB / 64];
     // Fletcher-Reeves beta for a fixed preconditioner; with zq (z_k.q_{k-1})
     // the Polak-Ribiere beta of flexible CG, z_k.(r_k - r_{k-1}) / z_{k-1}.r_{k-1}
@@ -372,9 +710,11 @@ __device__ __forceinline__ void cg_matvec_body(const MGLevel &L, const float *z,
             qv = (w + e + s + nb) * pv - (w * pw + e * pe + s * ps + nb * pnn);
             acc += (double)pv * (double)qv;
         }
+        if (gated) return;
         pc[n] = pv;
         q[n] = qv;
     }
+    if (gated) return;
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -390,16 +730,19 @@ __device__ __forceinline__ void cg_update_body(int64_t nn, const float *p, const
                                                float *r, const double *rz, const double *pq,
                                                double *rr, const int32_t *gate, int blk, int nblk)
 {
-    if (gate && *gate) return;
+    const int32_t gated = gate_load(gate);   // tested after the loads are issued
     __shared__ double red[CB / 64];
     const float alpha = (*pq != 0.0) ? (float)(*rz / *pq) : 0.0f;
     double acc = 0.0;
     for (int64_t n = (int64_t)blk * CB + threadIdx.x; n < nn; n += (int64_t)nblk * CB) {
-        e[n] += alpha * p[n];
+        const float en = e[n] + alpha * p[n];
         const float v = r[n] - alpha * q[n];
+        if (gated) return;
+        e[n] = en;
         r[n] = v;
         acc += (double)v * (double)v;
     }
+    if (gated) return;
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -418,6 +761,16 @@ __global__ void __launch_bounds__(256) k_mg_down(MGLevel F, MGLevel C)
 __global__ void __launch_bounds__(256) k_mg_up(MGLevel F, MGLevel C, double *dot)
 {
     mg_up_body(F, C, dot, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(D2T) k_mg_down2(MGLevel F, MGLevel M, MGLevel C)
+{
+    mg_down2_body(F, M, C, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) k_mg_up2(MGLevel F, MGLevel M, MGLevel C)
+{
+    mg_up2_body(F, M, C, blockIdx.x, blockIdx.y);
 }
 
 __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
@@ -500,20 +853,40 @@ inline int cg_blocks(int64_t n)
 
 }  // namespace
 
-void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s)
+void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s, bool two_level)
 {
-    // down the grid levels
-    for (int l = 0; l < H.tail.first; ++l) {
-        const MGLevel &F = H.lv[l], &C = H.lv[l + 1];
-        dim3 g((C.nr + 1 + DTX - 1) / DTX, (C.nz + 1 + DTY - 1) / DTY);
-        hipLaunchKernelGGL(k_mg_down, g, dim3(256), 0, s, F, C);
+    // pairs (l, l + 1) of grid levels run in one two-level kernel, taken from
+    // the coarse end; the finest level has blocks enough to run alone
+    bool pair[MAX_LEVELS] = {};
+    if (two_level)
+        for (int l = H.tail.first - 2; l >= 1; l -= 2) pair[l] = true;
+    for (int l = 0; l < H.tail.first;) {
+        if (pair[l]) {
+            const MGLevel &F = H.lv[l], &M = H.lv[l + 1], &C = H.lv[l + 2];
+            dim3 g((C.nr + 1 + D2W - 1) / D2W, (C.nz + 1 + D2H - 1) / D2H);
+            hipLaunchKernelGGL(k_mg_down2, g, dim3(D2T), 0, s, F, M, C);
+            l += 2;
+        } else {
+            const MGLevel &F = H.lv[l], &C = H.lv[l + 1];
+            dim3 g((C.nr + 1 + DTX - 1) / DTX, (C.nz + 1 + DTY - 1) / DTY);
+            hipLaunchKernelGGL(k_mg_down, g, dim3(256), 0, s, F, C);
+            l += 1;
+        }
     }
     hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(TT, TT), H.tail_lds_bytes, s, H.tail,
                        H.tail.first == 0 ? dot : nullptr);
-    for (int l = H.tail.first - 1; l >= 0; --l) {
-        const MGLevel &F = H.lv[l], &C = H.lv[l + 1];
-        dim3 g((F.nr + 1 + UTX - 1) / UTX, (F.nz + 1 + UTY - 1) / UTY);
-        hipLaunchKernelGGL(k_mg_up, g, dim3(256), 0, s, F, C, l == 0 ? dot : nullptr);
+    for (int l = H.tail.first - 1; l >= 0;) {
+        if (l >= 1 && pair[l - 1]) {
+            const MGLevel &F = H.lv[l - 1], &M = H.lv[l], &C = H.lv[l + 1];
+            dim3 g((F.nr + 1 + UTX - 1) / UTX, (F.nz + 1 + UTY - 1) / UTY);
+            hipLaunchKernelGGL(k_mg_up2, g, dim3(256), 0, s, F, M, C);
+            l -= 2;
+        } else {
+            const MGLevel &F = H.lv[l], &C = H.lv[l + 1];
+            dim3 g((F.nr + 1 + UTX - 1) / UTX, (F.nz + 1 + UTY - 1) / UTY);
+            hipLaunchKernelGGL(k_mg_up, g, dim3(256), 0, s, F, C, l == 0 ? dot : nullptr);
+            l -= 1;
+        }
     }
 }
 

@@ -227,8 +227,16 @@ class Simulation:
         L.check(self.lib.pic_autotune(self.h, int(steps_per_trial), C.byref(t)), self.h)
         return t.as_dict()
 
-    def set_tuning(self, push_blocks, push_e_weight):
-        t = L.pic_tuning(push_blocks, push_e_weight, 0.0, 0)
+    def set_tuning(self, push_blocks=None, push_e_weight=None, mg_one_level=None):
+        """Apply launch choices; a field left None keeps its current value."""
+        t = L.pic_tuning()
+        L.check(self.lib.pic_get_tuning(self.h, C.byref(t)), self.h)
+        if push_blocks is not None:
+            t.push_blocks = int(push_blocks)
+        if push_e_weight is not None:
+            t.push_e_weight = float(push_e_weight)
+        if mg_one_level is not None:
+            t.mg_one_level = int(mg_one_level)
         L.check(self.lib.pic_set_tuning(self.h, C.byref(t)), self.h)
 
     def tuning(self):

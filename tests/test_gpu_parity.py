@@ -235,6 +235,59 @@ def test_sort_compacts_and_orders(prec):
         assert np.array_equal(np.sort(after["id"]), np.sort(before[s]["id"]))
 
 
+@pytest.mark.parametrize("preset", ["ec256x512_f32", "ec512x1024_f32"])
+def test_two_level_vcycle_matches_one_level(preset):
+    """Pairs of small grid levels run in one kernel (a tile with both
+    levels' halos) by default; every node is computed with the operations of
+    the one-kernel-per-level V-cycle (256x512 fuses levels 1-2, 512x1024
+    levels 2-3).  The compiler may contract multiply-adds differently in the
+    two kernels, so the comparison is to FP32 rounding: one CG iteration
+    (phi on the unknowns is then a multiple of one V-cycle's output) agrees
+    to 1e-5 of its maximum, where a wrong halo or index would be off by
+    O(1); full solves take the same iterations and agree to the tolerance."""
+    import torch
+    p = W.preset(preset).replace(poisson_rtol=1e-8, n_per_species=0)
+    br, bz, sig, _ = W.inputs(p, n=0)
+    say("case", preset)
+    kind = O.Oracle(p, br, bz, sig, None, capacity=(16, 16)).node_kind()
+    unk = kind == 0
+    rng = np.random.default_rng(5)
+    q = rng.normal(size=p.nodes) * 1e-12
+    qd = torch.tensor(q, dtype=torch.float64, device="cuda")
+    one_it, full = [], []
+    # fresh handles: a solve plans its iterations from the convergence rate
+    # the handle's earlier solves measured
+    # (a tolerance of 0.9 plans a single iteration)
+    for one in (0, 1):
+        for rtol in (0.9, 1e-8):
+            sim = gpu_sim(p.replace(poisson_rtol=rtol), br, bz, sig, None,
+                          capacity=(1024, 1024))
+            assert sim.tuning()["mg_one_level"] == 0
+            with pytest.raises(Exception):
+                sim.set_tuning(mg_one_level=2)
+            sim.set_tuning(mg_one_level=one)
+            assert sim.tuning()["mg_one_level"] == one
+            phi = torch.zeros(p.nodes, dtype=torch.float64, device="cuda")
+            status, st = sim.poisson_status(qd, -500.0, phi)
+            say("one level" if one else "two level", "rtol", rtol, status, st)
+            assert status == 0 and st["converged"]
+            if rtol > 0.5:
+                assert st["iterations"] == 1
+                one_it.append(phi.cpu().numpy())
+            else:
+                assert st["rel_res"] <= 1e-8
+                full.append((phi.cpu().numpy(), st["iterations"]))
+            sim.close()
+    scale = np.abs(one_it[1][unk]).max()
+    d1 = np.abs(one_it[0][unk] - one_it[1][unk]).max() / scale
+    say("one iteration: max diff / max", d1)
+    assert scale > 0 and d1 <= 1e-5
+    assert full[0][1] == full[1][1]
+    df = np.abs(full[0][0] - full[1][0]).max() / np.abs(full[1][0]).max()
+    say("full solve: max diff / max", df)
+    assert df <= 1e-7
+
+
 def test_poisson_standalone_matches_oracle():
     p = W.preset("ec256x512_f32").replace(poisson_rtol=1e-8, n_per_species=0)
     br, bz, sig, _ = W.inputs(p, n=0)
