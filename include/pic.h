@@ -317,6 +317,11 @@ typedef struct pic_tuning {
                                    1 runs one kernel per level.  Both apply
                                    the same operations to every node: results
                                    agree to FP32 rounding.                    */
+    int32_t pass_graphs;        /* field-solve passes: 0 (default) launches their
+                                   kernels directly; 1 captures a pass into a
+                                   hipGraph on first use and replays it (on
+                                   ROCm's graph launch, which enqueues node by
+                                   node, the direct launches measured faster). */
 } pic_tuning;
 
 pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out);

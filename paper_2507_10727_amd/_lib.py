@@ -135,7 +135,7 @@ EXPORTS = [
 class pic_tuning(C.Structure):
     _fields_ = [("push_blocks", C.c_int32), ("push_e_weight", C.c_double),
                 ("push_ms", C.c_double), ("trials", C.c_int32),
-                ("mg_one_level", C.c_int32)]
+                ("mg_one_level", C.c_int32), ("pass_graphs", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

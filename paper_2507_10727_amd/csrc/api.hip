@@ -70,7 +70,7 @@ struct pic_handle {
         hipGraphExec_t exec;
     };
     std::vector<PassGraph> graphs;
-    bool use_graphs = true;
+    bool use_graphs = false;        // replay each solve pass from a captured graph
     // learned preconditioner
     PcNet net;
     bool pc_on = false;
@@ -83,6 +83,10 @@ struct pic_handle {
     int push_blocks = 1024;
     double push_e_weight = 1.3;
     bool mg_one_level = false;      // V-cycle with one kernel per grid level
+    // pinned host block the field solve reads its status and inner residuals
+    // back into (a copy to pageable memory is staged and synchronous)
+    double *pinned = nullptr;
+    hipEvent_t rb_done = nullptr;   // recorded after the copies; the host spins on it
     int32_t host_flags = 0;
     bool timers_on = false;
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
@@ -527,15 +531,26 @@ struct SolveReadback {
 
 // With hist, also the inner iterations' squared residuals of the pass (the
 // FP32 residual starts at unit norm), in the same synchronization.
+constexpr size_t PINNED_BYTES = sizeof(SolveReadback) + MAX_PCG * sizeof(double);
+
 pic_status readback(pic_handle *h, SolveReadback *rb, double *hist = nullptr, int n_hist = 0)
 {
     static_assert(sizeof(SolveReadback) == 48, "readback layout");
-    HIPCHECK(h, hipMemcpyAsync(rb, &h->sc->res_rr, sizeof(SolveReadback), hipMemcpyDeviceToHost,
+    char *pin = (char *)h->pinned;
+    HIPCHECK(h, hipMemcpyAsync(pin, &h->sc->res_rr, sizeof(SolveReadback), hipMemcpyDeviceToHost,
                                h->stream));
     if (hist && n_hist > 0)
-        HIPCHECK(h, hipMemcpyAsync(hist, h->sc->pcg_rr, (size_t)n_hist * 8, hipMemcpyDeviceToHost,
-                                   h->stream));
-    HIPCHECK(h, hipStreamSynchronize(h->stream));
+        HIPCHECK(h, hipMemcpyAsync(pin + sizeof(SolveReadback), h->sc->pcg_rr, (size_t)n_hist * 8,
+                                   hipMemcpyDeviceToHost, h->stream));
+    // the solve's only synchronization sits on the step's critical path:
+    // poll for it rather than let the runtime block and be woken
+    HIPCHECK(h, hipEventRecord(h->rb_done, h->stream));
+    hipError_t q;
+    while ((q = hipEventQuery(h->rb_done)) == hipErrorNotReady) {
+    }
+    HIPCHECK(h, q);
+    memcpy(rb, pin, sizeof(SolveReadback));
+    if (hist && n_hist > 0) memcpy(hist, pin + sizeof(SolveReadback), (size_t)n_hist * 8);
     h->host_count[0] = rb->count[0];
     h->host_count[1] = rb->count[1];
     h->host_flags = rb->flags;
@@ -589,9 +604,9 @@ void drop_graphs(pic_handle *h)
     h->graphs.clear();
 }
 
-// The pass is replayed from a cached hipGraph per (buffers, iteration count,
-// preconditioner) when the stream allows capture; otherwise its kernels are
-// launched directly.
+// The pass's kernels are launched directly, or (pass_graphs tuning) replayed
+// from a cached hipGraph per (buffers, iteration count, preconditioner) when
+// the stream allows capture.
 template <typename Q>
 pic_status run_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_iter, int mode)
 {
@@ -1289,16 +1304,25 @@ pic_status pic_init(const pic_config *cfg, void *workspace_dev, int64_t workspac
     h->ts = (cfg->precision == PIC_F64) ? 8 : 4;
     h->cap[0] = cfg->capacity[0];
     h->cap[1] = cfg->capacity[1];
-    const char *ng = getenv("PIC_NO_GRAPHS");
-    h->use_graphs = !(ng && ng[0] == '1');
     h->pmode = cfg->poisson_mode;
     layout(*cfg, h->ws, h);
-    st = (h->prec == PIC_F64) ? init_typed<double>(h, init) : init_typed<float>(h, init);
+    if (hipHostMalloc((void **)&h->pinned, PINNED_BYTES) != hipSuccess) {
+        h->pinned = nullptr;
+        st = fail(h, PIC_EHIP, "cannot allocate %zu bytes of pinned host memory", PINNED_BYTES);
+    } else if (hipEventCreateWithFlags(&h->rb_done, hipEventDisableTiming) != hipSuccess) {
+        h->rb_done = nullptr;
+        st = fail(h, PIC_EHIP, "cannot create the readback event");
+    } else {
+        st = (h->prec == PIC_F64) ? init_typed<double>(h, init) : init_typed<float>(h, init);
+    }
     // the host arrays of the config are not kept
     h->cfg.sigma = nullptr;
     h->cfg.b_r = h->cfg.b_z = nullptr;
     if (st != PIC_OK) {
         g_init_error = h->err;
+        (void)hipStreamSynchronize(h->stream);
+        if (h->pinned) (void)hipHostFree(h->pinned);
+        if (h->rb_done) (void)hipEventDestroy(h->rb_done);
         delete h;
         return st;
     }
@@ -1752,11 +1776,17 @@ pic_status pic_set_tuning(pic_handle *h, const pic_tuning *t)
         return fail(h, PIC_EINVAL, "push_blocks in [2, 65536] and push_e_weight in (0, 100)");
     if (t->mg_one_level != 0 && t->mg_one_level != 1)
         return fail(h, PIC_EINVAL, "mg_one_level must be 0 or 1");
+    if (t->pass_graphs != 0 && t->pass_graphs != 1)
+        return fail(h, PIC_EINVAL, "pass_graphs must be 0 or 1");
     h->push_blocks = t->push_blocks;
     h->push_e_weight = t->push_e_weight;
     if (h->mg_one_level != (t->mg_one_level != 0)) {
         h->mg_one_level = t->mg_one_level != 0;
         drop_graphs(h);   // captured solves hold the other launch sequence
+    }
+    if (h->use_graphs != (t->pass_graphs != 0)) {
+        h->use_graphs = t->pass_graphs != 0;
+        drop_graphs(h);
     }
     return PIC_OK;
 }
@@ -1768,6 +1798,7 @@ pic_status pic_get_tuning(const pic_handle *h, pic_tuning *t)
     t->push_blocks = h->push_blocks;
     t->push_e_weight = h->push_e_weight;
     t->mg_one_level = h->mg_one_level ? 1 : 0;
+    t->pass_graphs = h->use_graphs ? 1 : 0;
     return PIC_OK;
 }
 
@@ -1792,7 +1823,8 @@ pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out)
         *ms = h->timers.push_ms / std::max<int64_t>(h->timers.push_launches, 1);
         return PIC_OK;
     };
-    pic_tuning best = {h->push_blocks, h->push_e_weight, 1e300, 0, h->mg_one_level ? 1 : 0};
+    pic_tuning best = {h->push_blocks, h->push_e_weight, 1e300, 0, h->mg_one_level ? 1 : 0,
+                       h->use_graphs ? 1 : 0};
     pic_status st = PIC_OK;
     // coordinate search: block count at the current weight, then the weight
     static const int blocks[] = {256, 512, 1024, 2048, 4096, 8192};
@@ -1834,6 +1866,8 @@ pic_status pic_free(pic_handle *h)
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    if (h->rb_done) (void)hipEventDestroy(h->rb_done);
     delete h;
     return PIC_OK;
 }

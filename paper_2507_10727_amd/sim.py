@@ -227,10 +227,13 @@ class Simulation:
         L.check(self.lib.pic_autotune(self.h, int(steps_per_trial), C.byref(t)), self.h)
         return t.as_dict()
 
-    def set_tuning(self, push_blocks=None, push_e_weight=None, mg_one_level=None):
+    def set_tuning(self, push_blocks=None, push_e_weight=None, mg_one_level=None,
+                   pass_graphs=None):
         """Apply launch choices; a field left None keeps its current value."""
         t = L.pic_tuning()
         L.check(self.lib.pic_get_tuning(self.h, C.byref(t)), self.h)
+        if pass_graphs is not None:
+            t.pass_graphs = int(pass_graphs)
         if push_blocks is not None:
             t.push_blocks = int(push_blocks)
         if push_e_weight is not None:

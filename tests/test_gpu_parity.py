@@ -257,7 +257,8 @@ def test_two_level_vcycle_matches_one_level(preset):
     one_it, full = [], []
     # fresh handles: a solve plans its iterations from the convergence rate
     # the handle's earlier solves measured
-    # (a tolerance of 0.9 plans a single iteration)
+    # (a tolerance of 0.9 plans a single iteration); the one-level runs also
+    # replay their passes from captured graphs (pass_graphs), solving twice
     for one in (0, 1):
         for rtol in (0.9, 1e-8):
             sim = gpu_sim(p.replace(poisson_rtol=rtol), br, bz, sig, None,
@@ -265,10 +266,19 @@ def test_two_level_vcycle_matches_one_level(preset):
             assert sim.tuning()["mg_one_level"] == 0
             with pytest.raises(Exception):
                 sim.set_tuning(mg_one_level=2)
-            sim.set_tuning(mg_one_level=one)
-            assert sim.tuning()["mg_one_level"] == one
+            sim.set_tuning(mg_one_level=one, pass_graphs=one)
+            assert sim.tuning()["mg_one_level"] == one and sim.tuning()["pass_graphs"] == one
             phi = torch.zeros(p.nodes, dtype=torch.float64, device="cuda")
             status, st = sim.poisson_status(qd, -500.0, phi)
+            if one and rtol < 0.5:
+                # a second solve of the same system replays the captured
+                # passes (the plan may differ: the first measured the rate)
+                phi2 = torch.zeros(p.nodes, dtype=torch.float64, device="cuda")
+                status2, st2 = sim.poisson_status(qd, -500.0, phi2)
+                assert status2 == 0 and st2["converged"] and st2["rel_res"] <= 1e-8
+                d2 = (phi2 - phi).abs().max().item() / phi.abs().max().item()
+                say("graph replay: max diff / max", d2)
+                assert d2 <= 1e-7
             say("one level" if one else "two level", "rtol", rtol, status, st)
             assert status == 0 and st["converged"]
             if rtol > 0.5:
