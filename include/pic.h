@@ -311,12 +311,15 @@ typedef struct pic_tuning {
     double push_e_weight;       /* default 1.3                                    */
     double push_ms;             /* autotune: mean particle-kernel time chosen     */
     int32_t trials;
-    int32_t mg_one_level;       /* multigrid V-cycle: 0 (default) runs pairs of
-                                   the small grid levels above the single-
-                                   workgroup coarse levels in one kernel each;
-                                   1 runs one kernel per level.  Both apply
-                                   the same operations to every node: results
-                                   agree to FP32 rounding.                    */
+    int32_t mg_one_level;       /* multigrid-preconditioned CG: 0 (default) runs
+                                   pairs of the small grid levels above the
+                                   single-workgroup coarse levels in one kernel
+                                   each, and fuses the CG vector updates into
+                                   the finest level's V-cycle kernels (p.q
+                                   from dots of z, A z and q by the symmetry
+                                   of A); 1 runs one kernel per level and
+                                   separate CG kernels.  The two agree to FP32
+                                   rounding.                                  */
     int32_t pass_graphs;        /* field-solve passes: 0 (default) launches their
                                    kernels directly; 1 captures a pass into a
                                    hipGraph on first use and replays it (on

@@ -289,6 +289,9 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     f.q32 = cv.take<float>(nodes * 4);
     f.p32[0] = cv.take<float>(nodes * 4);
     f.p32[1] = cv.take<float>(nodes * 4);
+    f.q32b = cv.take<float>(nodes * 4);
+    f.r32b = cv.take<float>(nodes * 4);
+    f.w32 = cv.take<float>(nodes * 4);
     auto shapes = mg_shapes(c);
     MGHier &H = f.mg;
     H.nlevels = (int)shapes.size();
@@ -508,6 +511,9 @@ pic_status setup_field(pic_handle *h)
                         H.tail_lds_bytes);
     }
     launch_zero(h->f.e32, nodes * 4, h->stream);
+    launch_zero(h->f.q32b, nodes * 4, h->stream);
+    launch_zero(h->f.r32b, nodes * 4, h->stream);
+    launch_zero(h->f.w32, nodes * 4, h->stream);
     launch_zero(h->f.p32[0], nodes * 4, h->stream);
     launch_zero(h->f.p32[1], nodes * 4, h->stream);
     launch_zero(h->f.q32, nodes * 4, h->stream);
@@ -586,6 +592,27 @@ void enqueue_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_it
     launch_cast_scale(f, h->sc, s);
     launch_zero_gated(h->sc->pcg_rz, sizeof(double) * 5 * (MAX_PCG + 2), f.gate, s);
     const double *zq = (mode == PIC_LEARNED) ? h->sc->pcg_zq : nullptr;
+    if (mode == PIC_MGCG && !h->mg_one_level && H.tail.first >= 1) {
+        // CG vector work fused into the finest level's V-cycle kernels
+        CgVecs v;
+        v.r[0] = H.lv[0].b;
+        v.r[1] = f.r32b;
+        v.q[0] = f.q32;
+        v.q[1] = f.q32b;
+        v.w = f.w32;
+        v.p = f.p32[0];
+        v.e = f.e32;
+        v.rz = h->sc->pcg_rz;
+        v.pq = h->sc->pcg_pq;
+        v.rr = h->sc->pcg_rr;
+        v.zq = h->sc->pcg_zq;
+        v.zaz = h->sc->pcg_ss;
+        for (int k = 0; k < n_iter; ++k) launch_mg_vcycle_cg(H, v, k, s, true);
+        launch_cg_update_last(H, v, n_iter - 1, s);
+        launch_update64(f, phi, h->sc, inv_2pi_eps0, s);
+        launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
+        return;
+    }
     enqueue_precond(h, mode, 0);
     for (int k = 0; k < n_iter; ++k) {
         launch_cg_matvec(H, H.lv[0].xu, f.p32[(k + 1) & 1], f.p32[k & 1], f.q32, h->sc->pcg_rz,

@@ -426,6 +426,24 @@ void launch_cg_update(const MGHier &H, const float *p, const float *q, float *e,
                       const double *rz, const double *pq, double *rr, hipStream_t s);
 int mg_tail_setup(MGHier &H);
 
+// Preconditioned CG fused into the finest level's V-cycle kernels.  The "up"
+// kernel of iteration k also forms w_k = A z_k and the dots r_k.z_k, z_k.w_k,
+// z_k.q_{k-1}; the next V-cycle's "down" kernel first applies the update of
+// iteration k on its tile (p_k = z_k + beta p_{k-1}, q_k = w_k + beta q_{k-1}
+// = A p_k, p_k.q_k = z.w + 2 beta z.q_{k-1} + beta^2 p_{k-1}.q_{k-1} by the
+// symmetry of A, alpha, e += alpha p_k, r_{k+1} = r_k - alpha q_k) and smooths
+// r_{k+1}.  r and q are double-buffered: a tile reads its halo's old values
+// while its owned nodes get the new ones.
+struct CgVecs {
+    float *r[2], *q[2], *w, *p, *e;
+    double *rz, *pq, *rr, *zq, *zaz;    // per-iteration scalars
+};
+// z = M r[k & 1] into lv[0].xu, with w and the dots; for k > 0 the down
+// kernel first applies update k - 1 (r[k & 1] = r_k from r[(k - 1) & 1])
+void launch_mg_vcycle_cg(const MGHier &H, const CgVecs &v, int k, hipStream_t s, bool two_level);
+// the last iteration's update (e += alpha p, ||r||^2), no V-cycle after it
+void launch_cg_update_last(const MGHier &H, const CgVecs &v, int k, hipStream_t s);
+
 // field.hip
 struct FieldDev {
     int32_t nr, nz;
@@ -436,6 +454,7 @@ struct FieldDev {
     double *phi0_prev;          // phi0 of the previous step (warm-start extrapolation)
     double *r64;                // FP64 residual
     float *e32, *q32, *p32[2];  // inner CG vectors (finest level)
+    float *q32b, *r32b, *w32;   // second q and r buffers, w = A z (CG fused into the V-cycle)
     MGHier mg;                  // r32 = mg.lv[0].b, z32 = mg.lv[0].xu
     const double *b_r, *b_z;    // static nodal B
     const double *vdep;         // node volumes for densities

@@ -399,6 +399,194 @@ __device__ __forceinline__ void mg_up2_body(const MGLevel &F, const MGLevel &M, 
     }
 }
 
+// ---- the finest level with the CG vector work fused in
+
+// scalars of CG iteration j (uniform over the grid): beta_j, alpha_j and
+// p_j.q_j from the dots of the V-cycle that produced z_j
+struct CgScalars {
+    float alpha, beta;
+    double pq;
+};
+__device__ __forceinline__ CgScalars cg_scalars(const CgVecs &v, int j)
+{
+    CgScalars c;
+    const double rz = v.rz[j];
+    const double bd = (j > 0 && v.rz[j - 1] != 0.0) ? rz / v.rz[j - 1] : 0.0;
+    c.pq = v.zaz[j] + (j > 0 ? 2.0 * bd * v.zq[j] + bd * bd * v.pq[j - 1] : 0.0);
+    c.beta = (float)bd;
+    c.alpha = (c.pq > 0.0) ? (float)(rz / c.pq) : 0.0f;
+    return c;
+}
+
+// Down on the finest level with the update of CG iteration j applied first:
+// the tile (halo included) forms q_j = w_j + beta q_{j-1} and r_{j+1} =
+// r_j - alpha q_j from r[j & 1], w, q[(j - 1) & 1]; owned nodes store
+// r[(j + 1) & 1], q[j & 1], p_j = z_j + beta p_{j-1} (in place), e += alpha
+// p_j and add r_{j+1}^2 to rr[j]; then pre-smoothing of r_{j+1} as in the
+// plain down kernel.  Block (0, 0) records p_j.q_j in pq[j].
+static_assert(MG_NU >= 1, "the owned-node pass reads sb before the smoothing's first barrier");
+__device__ __forceinline__ void mg_down_cg_body(const MGLevel &F, const MGLevel &C,
+                                                const CgVecs &v, int j, int bx, int by)
+{
+    __shared__ float sb[DLH][DLW], sx[DLH][DLW], sq[DLH][DLW];
+    __shared__ double red[4];
+    const int I0 = bx * DTX, J0 = by * DTY;
+    const int fi0 = 2 * I0 - DH, fj0 = 2 * J0 - DH;
+    const int ld = F.nr + 1;
+    const float *rold = v.r[j & 1], *qold = v.q[(j + 1) & 1];   // q_{j-1} (unused for j = 0)
+    float rl[DN], wl[DN], ql[DN];
+#pragma unroll
+    for (int u = 0; u < DN; ++u) {
+        const int t = threadIdx.x + 256 * u;
+        const int i = fi0 + t % DLW, jj = fj0 + t / DLW;
+        const bool un = t < DLW * DLH && mg_in(F, i, jj) && mg_unknown(F, i, jj);
+        const int64_t n = un ? (int64_t)jj * ld + i : 0;
+        rl[u] = rold[n];
+        wl[u] = v.w[n];
+        ql[u] = qold[n];
+    }
+    // owned nodes [2 I0, 2 I0 + 2 DTX) x [2 J0, 2 J0 + 2 DTY): z, p_{j-1}, e
+    constexpr int ON = (4 * DTX * DTY + 255) / 256;
+    float zl[ON], pl[ON], el[ON];
+#pragma unroll
+    for (int o = 0; o < ON; ++o) {
+        const int t = threadIdx.x + 256 * o;
+        const int i = 2 * I0 + t % (2 * DTX), jj = 2 * J0 + t / (2 * DTX);
+        const int64_t n = (i <= F.nr && jj <= F.nz) ? (int64_t)jj * ld + i : 0;
+        zl[o] = F.xu[n];
+        pl[o] = v.p[n];
+        el[o] = v.e[n];
+    }
+    const CgScalars cs = cg_scalars(v, j);
+#pragma unroll
+    for (int u = 0; u < DN; ++u) {
+        const int t = threadIdx.x + 256 * u;
+        if (t >= DLW * DLH) continue;
+        const int li = t % DLW, lj = t / DLW;
+        const int i = fi0 + li, jj = fj0 + lj;
+        const bool un = mg_in(F, i, jj) && mg_unknown(F, i, jj);
+        const float qv = j > 0 ? wl[u] + cs.beta * ql[u] : wl[u];
+        const float rn = rl[u] - cs.alpha * qv;
+        sb[lj][li] = un ? rn : 0.0f;
+        sx[lj][li] = un ? down_red(F, i, jj, rn) : 0.0f;
+        sq[lj][li] = un ? qv : 0.0f;
+    }
+    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int o = 0; o < ON; ++o) {
+        const int t = threadIdx.x + 256 * o;
+        const int i = 2 * I0 + t % (2 * DTX), jj = 2 * J0 + t / (2 * DTX);
+        if (t >= 4 * DTX * DTY || i > F.nr || jj > F.nz) continue;
+        const int64_t n = (int64_t)jj * ld + i;
+        const float rn = sb[jj - fj0][i - fi0];
+        const float pv = j > 0 ? zl[o] + cs.beta * pl[o] : zl[o];
+        v.p[n] = pv;
+        v.e[n] = el[o] + cs.alpha * pv;
+        v.q[j & 1][n] = sq[jj - fj0][i - fi0];
+        v.r[(j + 1) & 1][n] = rn;
+        acc += (double)rn * (double)rn;
+    }
+    if (bx == 0 && by == 0 && threadIdx.x == 0) v.pq[j] = cs.pq;
+    tile_down_smooth<DLW, DLH, 256>(F, fi0, fj0, sb, sx);
+    const int ldc = C.nr + 1;
+    for (int t = threadIdx.x; t < DTX * DTY; t += 256) {
+        const int I = I0 + t % DTX, J = J0 + t / DTX;
+        if (I > C.nr || J > C.nz) continue;
+        C.b[(int64_t)J * ldc + I] = mg_unknown(C, I, J) ? tile_restrict<DLW>(sb, 2 * I - fi0, 2 * J - fj0) : 0.0f;
+    }
+    for (int t = threadIdx.x; t < 4 * DTX * DTY; t += 256) {
+        const int i = 2 * I0 + t % (2 * DTX), jj = 2 * J0 + t / (2 * DTX);
+        if (i > F.nr || jj > F.nz) continue;
+        F.xd[(int64_t)jj * ld + i] = sx[jj - fj0][i - fi0];
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double s = red[0] + red[1] + red[2] + red[3];
+        if (s != 0.0) atomic_add_dev(&v.rr[j], s);
+    }
+}
+
+// Up on the finest level of CG iteration k (F.b = r_k): a tile with one more
+// halo node, so that after the sweeps z is exact on the owned nodes and their
+// neighbours; owned nodes store z (F.xu) and w = A z, and the block adds
+// r.z, z.w and z.q_{k-1} (k > 0) to rz[k], zaz[k], zq[k].
+constexpr int UH3 = UH + 1;
+constexpr int UCW = UTX + 2 * UH3, UCH = UTY + 2 * UH3;
+constexpr int UCN = (UCW * UCH + 255) / 256;
+
+__device__ __forceinline__ void mg_up_cg_body(const MGLevel &F, const MGLevel &C, const CgVecs &v,
+                                              int k, int bx, int by)
+{
+    __shared__ float sb[UCH][UCW], sx[UCH][UCW];
+    __shared__ double red[3][4];
+    const int i0 = bx * UTX, j0 = by * UTY;
+    const int fi0 = i0 - UH3, fj0 = j0 - UH3;
+    const int ld = F.nr + 1;
+    float bl[UCN], xl[UCN], c0[UCN], c1[UCN], c2[UCN], c3[UCN];
+    up_loads<UCW, UCH, 256, UCN>(F, C, fi0, fj0, bl, xl, c0, c1, c2, c3);
+    constexpr int ON = (UTX * UTY + 255) / 256;
+    const float *qold = v.q[(k + 1) & 1];   // q_{k-1} (unused for k = 0)
+    float ql[ON];
+#pragma unroll
+    for (int o = 0; o < ON; ++o) {
+        const int t = threadIdx.x + 256 * o;
+        const int i = i0 + t % UTX, jj = j0 + t / UTX;
+        ql[o] = qold[(i <= F.nr && jj <= F.nz) ? (int64_t)jj * ld + i : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < UCN; ++u) {
+        const int t = threadIdx.x + 256 * u;
+        if (t >= UCW * UCH) continue;
+        const int li = t % UCW, lj = t / UCW;
+        const int i = fi0 + li, jj = fj0 + lj;
+        const bool un = mg_in(F, i, jj) && mg_unknown(F, i, jj);
+        sb[lj][li] = un ? bl[u] : 0.0f;
+        sx[lj][li] = un ? xl[u] + mg_prolong_sel(i & 1, jj & 1, c0[u], c1[u], c2[u], c3[u]) : 0.0f;
+    }
+    __syncthreads();
+    tile_up_smooth<UCW, UCH, 256>(F, fi0, fj0, sb, sx);
+    double a_rz = 0.0, a_zaz = 0.0, a_zq = 0.0;
+#pragma unroll
+    for (int o = 0; o < ON; ++o) {
+        const int t = threadIdx.x + 256 * o;
+        const int i = i0 + t % UTX, jj = j0 + t / UTX;
+        if (i > F.nr || jj > F.nz) continue;
+        const int li = i - fi0, lj = jj - fj0;
+        const float z = sx[lj][li];
+        float w = 0.0f;
+        if (mg_unknown(F, i, jj)) {
+            float cw, ce, cs, cn;
+            mg_coup(F, i, jj, cw, ce, cs, cn);
+            w = (cw + ce + cs + cn) * z - (cw * sx[lj][li - 1] + ce * sx[lj][li + 1] +
+                                            cs * sx[lj - 1][li] + cn * sx[lj + 1][li]);
+        }
+        const int64_t n = (int64_t)jj * ld + i;
+        F.xu[n] = z;
+        v.w[n] = w;
+        a_rz += (double)z * (double)sb[lj][li];
+        a_zaz += (double)z * (double)w;
+        if (k > 0) a_zq += (double)z * (double)ql[o];
+    }
+    a_rz = wave_sum(a_rz);
+    a_zaz = wave_sum(a_zaz);
+    a_zq = wave_sum(a_zq);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = a_rz;
+        red[1][threadIdx.x >> 6] = a_zaz;
+        red[2][threadIdx.x >> 6] = a_zq;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const double s = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] +
+                         red[threadIdx.x][3];
+        double *dst = threadIdx.x == 0 ? &v.rz[k] : (threadIdx.x == 1 ? &v.zaz[k] : &v.zq[k]);
+        if (s != 0.0) atomic_add_dev(dst, s);
+    }
+}
+
 // Tail: every level from `first` down to the coarsest in one workgroup of
 // TT x TT threads, all in LDS.  Reads L[first].b, writes L[first].xu (and
 // sum(b * x) into dot if given).  Loops run flat over a level's nodes (or
@@ -753,6 +941,35 @@ __device__ __forceinline__ void cg_update_body(int64_t nn, const float *p, const
     }
 }
 
+// The update of the last CG iteration j of a pass (no V-cycle follows):
+// p_j, q_j, e += alpha p_j and ||r_{j+1}||^2 over all nodes.
+__device__ __forceinline__ void cg_update_last_body(const MGLevel &L, const CgVecs &v, int j,
+                                                    int blk, int nblk)
+{
+    __shared__ double red[CB / 64];
+    const CgScalars cs = cg_scalars(v, j);
+    const float *rold = v.r[j & 1], *qold = v.q[(j + 1) & 1];
+    const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
+    double acc = 0.0;
+    for (int64_t n = (int64_t)blk * CB + threadIdx.x; n < nn; n += (int64_t)nblk * CB) {
+        const float w = v.w[n], z = L.xu[n], qo = qold[n], po = v.p[n], en = v.e[n], ro = rold[n];
+        const float qv = j > 0 ? w + cs.beta * qo : w;
+        const float pv = j > 0 ? z + cs.beta * po : z;
+        v.e[n] = en + cs.alpha * pv;
+        const float rn = ro - cs.alpha * qv;
+        acc += (double)rn * (double)rn;
+    }
+    if (blk == 0 && threadIdx.x == 0) v.pq[j] = cs.pq;
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < CB / 64; ++w) s += red[w];
+        if (s != 0.0) atomic_add_dev(&v.rr[j], s);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_mg_down(MGLevel F, MGLevel C)
 {
     mg_down_body(F, C, blockIdx.x, blockIdx.y);
@@ -771,6 +988,21 @@ __global__ void __launch_bounds__(D2T) k_mg_down2(MGLevel F, MGLevel M, MGLevel 
 __global__ void __launch_bounds__(256) k_mg_up2(MGLevel F, MGLevel M, MGLevel C)
 {
     mg_up2_body(F, M, C, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) k_mg_down_cg(MGLevel F, MGLevel C, CgVecs v, int j)
+{
+    mg_down_cg_body(F, C, v, j, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) k_mg_up_cg(MGLevel F, MGLevel C, CgVecs v, int k)
+{
+    mg_up_cg_body(F, C, v, k, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(CB) k_cg_update_last(MGLevel L, CgVecs v, int j)
+{
+    cg_update_last_body(L, v, j, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(1024) k_mg_tail(MGTail T, double *dot)
@@ -853,14 +1085,22 @@ inline int cg_blocks(int64_t n)
 
 }  // namespace
 
-void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s, bool two_level)
+namespace {
+
+// Pairs (l, l + 1) of grid levels run in one two-level kernel, taken from the
+// coarse end; the finest level has blocks enough to run alone.
+void level_pairs(const MGHier &H, bool two_level, bool *pair)
 {
-    // pairs (l, l + 1) of grid levels run in one two-level kernel, taken from
-    // the coarse end; the finest level has blocks enough to run alone
-    bool pair[MAX_LEVELS] = {};
+    for (int l = 0; l < MAX_LEVELS; ++l) pair[l] = false;
     if (two_level)
         for (int l = H.tail.first - 2; l >= 1; l -= 2) pair[l] = true;
-    for (int l = 0; l < H.tail.first;) {
+}
+
+// down kernels from level `from`, the tail, up kernels back to level `to`
+void launch_levels(const MGHier &H, const bool *pair, int from, int to, double *dot,
+                   hipStream_t s)
+{
+    for (int l = from; l < H.tail.first;) {
         if (pair[l]) {
             const MGLevel &F = H.lv[l], &M = H.lv[l + 1], &C = H.lv[l + 2];
             dim3 g((C.nr + 1 + D2W - 1) / D2W, (C.nz + 1 + D2H - 1) / D2H);
@@ -875,8 +1115,8 @@ void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s, bool two_leve
     }
     hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(TT, TT), H.tail_lds_bytes, s, H.tail,
                        H.tail.first == 0 ? dot : nullptr);
-    for (int l = H.tail.first - 1; l >= 0;) {
-        if (l >= 1 && pair[l - 1]) {
+    for (int l = H.tail.first - 1; l >= to;) {
+        if (l >= 1 && pair[l - 1] && l - 1 >= to) {
             const MGLevel &F = H.lv[l - 1], &M = H.lv[l], &C = H.lv[l + 1];
             dim3 g((F.nr + 1 + UTX - 1) / UTX, (F.nz + 1 + UTY - 1) / UTY);
             hipLaunchKernelGGL(k_mg_up2, g, dim3(256), 0, s, F, M, C);
@@ -888,6 +1128,37 @@ void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s, bool two_leve
             l -= 1;
         }
     }
+}
+
+}  // namespace
+
+void launch_mg_vcycle(const MGHier &H, double *dot, hipStream_t s, bool two_level)
+{
+    bool pair[MAX_LEVELS];
+    level_pairs(H, two_level, pair);
+    launch_levels(H, pair, 0, 0, dot, s);
+}
+
+void launch_mg_vcycle_cg(const MGHier &H, const CgVecs &v, int k, hipStream_t s, bool two_level)
+{
+    bool pair[MAX_LEVELS];
+    level_pairs(H, two_level, pair);
+    MGLevel F = H.lv[0];
+    F.b = v.r[k & 1];
+    const MGLevel &C = H.lv[1];
+    dim3 gd((C.nr + 1 + DTX - 1) / DTX, (C.nz + 1 + DTY - 1) / DTY);
+    if (k == 0) hipLaunchKernelGGL(k_mg_down, gd, dim3(256), 0, s, F, C);
+    else hipLaunchKernelGGL(k_mg_down_cg, gd, dim3(256), 0, s, F, C, v, k - 1);
+    launch_levels(H, pair, 1, 1, nullptr, s);
+    dim3 gu((F.nr + 1 + UTX - 1) / UTX, (F.nz + 1 + UTY - 1) / UTY);
+    hipLaunchKernelGGL(k_mg_up_cg, gu, dim3(256), 0, s, F, C, v, k);
+}
+
+void launch_cg_update_last(const MGHier &H, const CgVecs &v, int k, hipStream_t s)
+{
+    const MGLevel &L = H.lv[0];
+    const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
+    hipLaunchKernelGGL(k_cg_update_last, dim3(cg_blocks(nn)), dim3(CB), 0, s, L, v, k);
 }
 
 void launch_cg_matvec(const MGHier &H, const float *z, const float *pp, float *pc, float *q,
