@@ -589,8 +589,8 @@ void enqueue_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_it
     FieldDev &f = h->f;
     const MGHier &H = f.mg;
     const double inv_2pi_eps0 = 1.0 / (2.0 * 3.14159265358979323846 * eps0());
-    launch_cast_scale(f, h->sc, s);
-    launch_zero_gated(h->sc->pcg_rz, sizeof(double) * 5 * (MAX_PCG + 2), f.gate, s);
+    // (the cast also clears the pass's CG accumulators: pcg_rz .. pcg_ss)
+    launch_cast_scale(f, h->sc, s, h->sc->pcg_rz, 5 * (MAX_PCG + 2));
     const double *zq = (mode == PIC_LEARNED) ? h->sc->pcg_zq : nullptr;
     if (mode == PIC_MGCG && !h->mg_one_level && H.tail.first >= 1) {
         // CG vector work fused into the finest level's V-cycle kernels
@@ -609,8 +609,8 @@ void enqueue_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_it
         v.zaz = h->sc->pcg_ss;
         for (int k = 0; k < n_iter; ++k) launch_mg_vcycle_cg(H, v, k, s, true);
         launch_cg_update_last(H, v, n_iter - 1, s);
-        launch_update64(f, phi, h->sc, inv_2pi_eps0, s);
-        launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
+        launch_update64(f, phi, h->sc, inv_2pi_eps0, s, true);
+        launch_residual64<Q>(f, phi, q0, q1, h->sc, s, false);
         return;
     }
     enqueue_precond(h, mode, 0);
@@ -621,8 +621,8 @@ void enqueue_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_it
                          &h->sc->pcg_pq[k], &h->sc->pcg_rr[k], s);
         if (k + 1 < n_iter) enqueue_precond(h, mode, k + 1);
     }
-    launch_update64(f, phi, h->sc, inv_2pi_eps0, s);
-    launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
+    launch_update64(f, phi, h->sc, inv_2pi_eps0, s, true);
+    launch_residual64<Q>(f, phi, q0, q1, h->sc, s, false);
 }
 
 void drop_graphs(pic_handle *h)
@@ -663,12 +663,13 @@ pic_status run_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_
     return PIC_OK;
 }
 
-// FP64-refined solve.  With the learned preconditioner, after pc_maxit of
-// its iterations without convergence, or a pass that does not lower the
+// FP64-refined solve (extrapolate: start from phi0 extrapolated from the last
+// two steps).  With the learned preconditioner, after pc_maxit of its
+// iterations without convergence, or a pass that does not lower the
 // residual, the remaining passes use the multigrid preconditioner.
 template <typename Q>
 pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_cathode,
-                 pic_poisson_stats *st, int mode)
+                 pic_poisson_stats *st, int mode, bool extrapolate = false)
 {
     hipStream_t s = h->stream;
     FieldDev &f = h->f;
@@ -679,8 +680,8 @@ pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_
         return fail(h, PIC_ESTATE, "the learned preconditioner has no weights");
     pic_status pe = PIC_OK;
     pic_poisson_stats S = {};
-    launch_set_dirichlet(f, phi, v_cathode, s);
-    launch_residual64<Q>(f, phi, q0, q1, h->sc, s);
+    launch_solve_prep(f, phi, extrapolate, v_cathode, h->sc, s);
+    launch_residual64<Q>(f, phi, q0, q1, h->sc, s, false);
     auto rate = [&]() -> double & {
         return mode == PIC_LEARNED ? h->rho_pc : (mode == PIC_CG ? h->rho_cg : h->rho);
     };
@@ -909,9 +910,10 @@ pic_status field_update(pic_handle *h)
     const pic_config &c = h->cfg;
     hipEvent_t ev[2];
     timer_begin(h, ev);
-    launch_extrapolate(h->f, 0, h->stream);
+    // the warm start (phi0 extrapolated from the last two steps) is applied
+    // by the solve's first kernel
     pic_status st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr,
-                              h->pmode);
+                              h->pmode, true);
     timer_end(h, 3, ev);
     if (st != PIC_OK) return st;
     timer_begin(h, ev);

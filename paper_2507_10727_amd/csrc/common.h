@@ -535,16 +535,25 @@ void launch_status_b(const BatchPlan &P, RunStatus *status_dev, hipStream_t s);
 
 void launch_zero(void *p, int64_t bytes, hipStream_t s);
 void launch_zero_gated(void *p, int64_t bytes, const int32_t *gate, hipStream_t s);
+// FP64 residual and its norms (zero: clear the accumulators first; false when
+// an earlier kernel of the sequence has)
 template <typename T>
 void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const T *q1,
-                       DevScalars *sc, hipStream_t s);
+                       DevScalars *sc, hipStream_t s, bool zero = true);
 // out = K phi on unknown nodes, 0 on Dirichlet nodes (FP64)
 void launch_apply_k64(const FieldDev &f, const double *phi, double *out, hipStream_t s);
-// r32 = r64 / ||r64|| (norm read on the device), e32 = 0
-void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s);
-// phi += e32 ||r64|| / (2 pi eps0) on unknown nodes
-void launch_update64(const FieldDev &f, double *phi, const DevScalars *sc, double inv_2pi_eps0,
-                     hipStream_t s);
+// r32 = r64 / ||r64|| (norm read on the device), e32 = 0, and nzero doubles
+// at zero cleared
+void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s, double *zero = nullptr,
+                       int64_t nzero = 0);
+// phi += e32 ||r64|| / (2 pi eps0) on unknown nodes; zero_res also clears
+// the residual accumulators for the residual that follows
+void launch_update64(const FieldDev &f, double *phi, DevScalars *sc, double inv_2pi_eps0,
+                     hipStream_t s, bool zero_res = false);
+// extrapolation of phi0 (when asked), Dirichlet values, cleared residual
+// accumulators: the start of a solve in one launch
+void launch_solve_prep(const FieldDev &f, double *phi, bool extrapolate, double v_cathode,
+                       DevScalars *sc, hipStream_t s);
 template <typename T>
 void launch_circuit(const FieldDev &f, const T *q0, const T *q1, DevScalars *sc, int circuit,
                     double v_fixed, double v_ext, double r_ext, double dt, double extra_dq,

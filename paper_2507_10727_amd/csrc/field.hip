@@ -137,13 +137,18 @@ __global__ void __launch_bounds__(FB) k_apply_k64(int32_t nr, int32_t nz, const 
     }
 }
 
+// also zeroes nzero doubles at zero (the pass's CG accumulators), which
+// nothing in this kernel reads
 __device__ __forceinline__ void cast_scale_body(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32,
-                             const int32_t *gate, int blk, int nblk)
+                             const int32_t *gate, int blk, int nblk, double *zero = nullptr,
+                             int64_t nzero = 0)
 {
     if (gate && *gate) return;
     const double rr = sc->res_rr;
     const double scale = (rr > 0.0) ? 1.0 / sqrt(rr) : 0.0;
     if (blk == 0 && threadIdx.x == 0) sc->res_rr0 = rr;
+    for (int64_t k = (int64_t)blk * FB + threadIdx.x; k < nzero; k += (int64_t)nblk * FB)
+        zero[k] = 0.0;
     for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB) {
         r32[n] = (float)(r64[n] * scale);
         e32[n] = 0.0f;
@@ -151,24 +156,29 @@ __device__ __forceinline__ void cast_scale_body(int64_t nn, const double *r64, D
 }
 
 __global__ void k_cast_scale(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32,
-                             const int32_t *gate)
+                             const int32_t *gate, double *zero, int64_t nzero)
 {
-    cast_scale_body(nn, r64, sc, r32, e32, gate, blockIdx.x, gridDim.x);
+    cast_scale_body(nn, r64, sc, r32, e32, gate, blockIdx.x, gridDim.x, zero, nzero);
 }
 
+// with zero_res, also zeroes the residual accumulators (res_rr, res_bb) for
+// the residual that follows; this kernel reads only res_rr0
 __device__ __forceinline__ void update64_body(int64_t nn, const uint8_t *kind, double *phi, const float *e32,
-                           const DevScalars *sc, double inv_2pi_eps0, const int32_t *gate, int blk, int nblk)
+                           const DevScalars *sc, double inv_2pi_eps0, const int32_t *gate, int blk, int nblk,
+                           double *zero_res = nullptr)
 {
     if (gate && *gate) return;
     const double scale = sqrt(sc->res_rr0) * inv_2pi_eps0;
+    if (zero_res && blk == 0 && threadIdx.x < 2) zero_res[threadIdx.x] = 0.0;
     for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB)
         if (kind[n] == 0) phi[n] += (double)e32[n] * scale;
 }
 
 __global__ void k_update64(int64_t nn, const uint8_t *kind, double *phi, const float *e32,
-                           const DevScalars *sc, double inv_2pi_eps0, const int32_t *gate)
+                           const DevScalars *sc, double inv_2pi_eps0, const int32_t *gate,
+                           double *zero_res)
 {
-    update64_body(nn, kind, phi, e32, sc, inv_2pi_eps0, gate, blockIdx.x, gridDim.x);
+    update64_body(nn, kind, phi, e32, sc, inv_2pi_eps0, gate, blockIdx.x, gridDim.x, zero_res);
 }
 
 // ---- circuit: induced cathode charge of phi0 and the cathode voltage update
@@ -295,6 +305,25 @@ __device__ __forceinline__ void set_dirichlet_body(int64_t nn, const uint8_t *ki
 __global__ void k_set_dirichlet(int64_t nn, const uint8_t *kind, double *phi, double vcat)
 {
     set_dirichlet_body(nn, kind, phi, vcat, blockIdx.x, gridDim.x);
+}
+
+// Start of a solve in one launch: the warm-start extrapolation of the
+// unknowns (when prev is given), the Dirichlet values, and zeroed residual
+// accumulators for the residual that follows.
+__global__ void k_solve_prep(int64_t nn, const uint8_t *kind, double *phi, double *prev,
+                             double vcat, double *zero_res)
+{
+    if (blockIdx.x == 0 && threadIdx.x < 2) zero_res[threadIdx.x] = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
+        const uint8_t k = kind[n];
+        if (prev) {
+            const double t = phi[n];
+            if (k == 0) phi[n] = 2.0 * t - prev[n];
+            prev[n] = t;
+        }
+        if (k == 1) phi[n] = vcat;
+        else if (k == 2) phi[n] = 0.0;
+    }
 }
 
 // Per-block partial diagnostics: sum Q_e, sum Q_i, max n_e, max n_i, max phi,
@@ -509,10 +538,10 @@ void launch_zero_gated(void *p, int64_t bytes, const int32_t *gate, hipStream_t 
 
 template <typename T>
 void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const T *q1,
-                       DevScalars *sc, hipStream_t s)
+                       DevScalars *sc, hipStream_t s, bool zero)
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
-    launch_zero_gated(&sc->res_rr, 2 * sizeof(double), f.gate, s);
+    if (zero) launch_zero_gated(&sc->res_rr, 2 * sizeof(double), f.gate, s);
     hipLaunchKernelGGL((k_residual64<T>), dim3(res_blocks(nn)), dim3(RB), 0, s, f.nr,
                        f.nz, f.ce64, f.cn64, f.kind, phi, q0, q1, f.r64, sc, f.gate);
 }
@@ -524,19 +553,28 @@ void launch_apply_k64(const FieldDev &f, const double *phi, double *out, hipStre
                        f.cn64, f.kind, phi, out);
 }
 
-void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s)
+void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s, double *zero,
+                       int64_t nzero)
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     hipLaunchKernelGGL(k_cast_scale, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.r64, sc,
-                       f.mg.lv[0].b, f.e32, f.gate);
+                       f.mg.lv[0].b, f.e32, f.gate, zero, nzero);
 }
 
-void launch_update64(const FieldDev &f, double *phi, const DevScalars *sc, double inv_2pi_eps0,
-                     hipStream_t s)
+void launch_update64(const FieldDev &f, double *phi, DevScalars *sc, double inv_2pi_eps0,
+                     hipStream_t s, bool zero_res)
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     hipLaunchKernelGGL(k_update64, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.kind, phi, f.e32,
-                       sc, inv_2pi_eps0, f.gate);
+                       sc, inv_2pi_eps0, f.gate, zero_res ? &sc->res_rr : nullptr);
+}
+
+void launch_solve_prep(const FieldDev &f, double *phi, bool extrapolate, double v_cathode,
+                       DevScalars *sc, hipStream_t s)
+{
+    const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
+    hipLaunchKernelGGL(k_solve_prep, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.kind, phi,
+                       extrapolate ? f.phi0_prev : nullptr, v_cathode, &sc->res_rr);
 }
 
 template <typename T>
@@ -592,9 +630,9 @@ void launch_count_live(const int32_t *key, const DevScalars *sc, int species,
 }
 
 template void launch_residual64<float>(const FieldDev &, const double *, const float *,
-                                       const float *, DevScalars *, hipStream_t);
+                                       const float *, DevScalars *, hipStream_t, bool);
 template void launch_residual64<double>(const FieldDev &, const double *, const double *,
-                                        const double *, DevScalars *, hipStream_t);
+                                        const double *, DevScalars *, hipStream_t, bool);
 template void launch_circuit<float>(const FieldDev &, const float *, const float *, DevScalars *,
                                     int, double, double, double, double, double, hipStream_t);
 template void launch_circuit<double>(const FieldDev &, const double *, const double *,
