@@ -603,8 +603,27 @@ constexpr int TN = TT * TT;
 struct TailLevel {
     int nr, nz, cath, ld;
     float dz, dr2dz;
+    float rld, rhalf;           // 1 / ld and 1 / (nr / 2), for the node index split
     float *x, *b;
 };
+
+// q = n / d for the small counts of a tail level (0 <= n < 2^22, 0 < d), from
+// the float reciprocal rd ~ 1 / d: the estimate is off by at most one, fixed
+// with full-rate 24-bit multiplies (a 32-bit division costs quarter-rate
+// multiplies, and the tail is instruction-bound on its one CU)
+__device__ __forceinline__ int tail_div(int n, int d, float rd)
+{
+    int q = (int)((float)n * rd);
+    const int r = n - __mul24(q, d);
+    q += (r >= d) ? 1 : 0;
+    q -= (r < 0) ? 1 : 0;
+    return q;
+}
+__device__ __forceinline__ void tail_ij(int n, const TailLevel &L, int &i, int &j)
+{
+    j = tail_div(n, L.ld, L.rld);
+    i = n - __mul24(j, L.ld);
+}
 
 // (the batched kernel reads the same fields from device memory into vector
 // registers: readfirstlane moves the uniform value to a scalar register)
@@ -628,6 +647,8 @@ __device__ __forceinline__ TailLevel tail_level(const MGTail &T, float *sm, int 
     v.ld = v.nr + 1;
     v.dz = in_sreg(T.L[l].dz);
     v.dr2dz = in_sreg(T.L[l].dr2dz);
+    v.rld = __builtin_amdgcn_rcpf((float)v.ld);
+    v.rhalf = __builtin_amdgcn_rcpf((float)(v.nr > 1 ? v.nr >> 1 : 1));
     v.x = sm + in_sreg(T.offx[l]);
     v.b = sm + in_sreg(T.offb[l]);
     return v;
@@ -652,40 +673,28 @@ __device__ __forceinline__ float tail_res(const TailLevel &L, int i, int j, int 
 
 // One colour c of a red-black sweep: nodes with (i + j + c) even.  A swept
 // level has even nr (it has a coarser level), so each row holds nr / 2 nodes
-// of a colour; a thread updates two per pass.
+// of a colour.  One node per pass: the workgroup's 16 waves hide the LDS
+// latency, and a second node per pass would only add instructions.
 __device__ __forceinline__ void tail_sweep(const TailLevel &L, int c, int tid)
 {
-    const int half = L.nr >> 1, cnt = half * L.nz;
-    for (int h0 = tid; h0 < cnt; h0 += 2 * TN) {
-        float xn[2], dg[2], bb[2];
-        int mm[2];
-        bool ok[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int h = h0 + u * TN;
-            const int hh = h < cnt ? h : 0;
-            const int j = (int)((uint32_t)hh / (uint32_t)half);
-            const int i = 2 * (hh - j * half) + ((j + c) & 1);
-            ok[u] = h < cnt && !(j == 0 && i < L.cath);
-            float w, e, s, n;
-            mg_coup_v(L.nr, L.nz, L.dz, L.dr2dz, i, j, w, e, s, n);
-            const int m = j * L.ld + i;
-            mm[u] = m;
-            xn[u] = w * L.x[m - (i > 0 ? 1 : 0)] + e * L.x[m + 1] +
-                    s * L.x[m - (j > 0 ? L.ld : 0)] + n * L.x[m + L.ld];
-            bb[u] = L.b[m];
-            dg[u] = w + e + s + n;
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-            if (ok[u]) L.x[mm[u]] = (bb[u] + xn[u]) * __builtin_amdgcn_rcpf(dg[u]);
+    const int half = L.nr >> 1, cnt = __mul24(half, L.nz);
+    for (int h = tid; h < cnt; h += TN) {
+        const int j = tail_div(h, half, L.rhalf);
+        const int i = 2 * (h - __mul24(j, half)) + ((j + c) & 1);
+        if (j == 0 && i < L.cath) continue;
+        float w, e, s, n;
+        mg_coup_v(L.nr, L.nz, L.dz, L.dr2dz, i, j, w, e, s, n);
+        const int m = __mul24(j, L.ld) + i;
+        const float o = w * L.x[m - (i > 0 ? 1 : 0)] + e * L.x[m + 1] +
+                        s * L.x[m - (j > 0 ? L.ld : 0)] + n * L.x[m + L.ld];
+        L.x[m] = (L.b[m] + o) * __builtin_amdgcn_rcpf(w + e + s + n);
     }
 }
 
 // Right-hand-side values per thread loaded up front, and the share of the
 // dense inverse held in registers (rows g + 32 r, columns lane + 32 m of a
-// 32-lane group g): inverses of up to 32 TDR unknowns arrive while the
-// levels above the coarsest are smoothed; larger ones are read when needed.
+// 32-lane group g): inverses of up to 32 TDR unknowns are prefetched,
+// larger ones read when needed.
 constexpr int TBN = MG_TAIL_NODES_MAX / TN;
 constexpr int TDR = 7;
 static_assert(TBN * TN == MG_TAIL_NODES_MAX, "tail rows per thread");
@@ -704,27 +713,6 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
         const int n = tid + TN * u;
         bl[u] = T.L[T.first].b[n < T.tmp_size ? n : 0];
     }
-    // loads complete in issue order: keep the right-hand side ahead of the
-    // inverse, so the first phase waits only for its own loads
-    asm volatile("" ::: "memory");
-    // issued unconditionally (a branch around them would make every later
-    // wait assume the worst case): an inverse too large for the registers
-    // reads the first right-hand-side word in their place
-    {
-        const float *ip = dense_regs ? T.inv : T.L[T.first].b;
-        const int32_t *mp = dense_regs ? T.map : (const int32_t *)T.L[T.first].b;
-#pragma unroll
-        for (int m = 0; m < TDR; ++m) {
-            const int c = lane + 32 * m;
-            const bool cv = dense_regs && c < T.ninv;
-            col[m] = mp[cv ? c : 0];
-#pragma unroll
-            for (int r = 0; r < TDR; ++r) {
-                const int a = g + 32 * r;
-                inv[r][m] = ip[(cv && a < T.ninv) ? (int64_t)a * T.ninv + c : 0];
-            }
-        }
-    }
     {
         const TailLevel L = tail_level(T, sm, T.first);
 #pragma unroll
@@ -738,6 +726,23 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
     }
     if (gated) return;   // uniform: the whole block leaves before its first barrier
     __syncthreads();
+    // the inverse's share, issued once every wave has its right-hand side
+    // (loads queue in order: ahead of them they would delay the first
+    // phase), arrives while the levels above the coarsest are smoothed;
+    // only the nb x nb blocks of 32 rows / columns the inverse has
+    const int nb = dense_regs ? (T.ninv + 31) >> 5 : 0;
+#pragma unroll
+    for (int m = 0; m < TDR; ++m) {
+        if (m >= nb) break;
+        const int c = lane + 32 * m;
+        col[m] = T.map[c < T.ninv ? c : 0];
+#pragma unroll
+        for (int r = 0; r < TDR; ++r) {
+            if (r >= nb) break;
+            const int a = g + 32 * r;
+            inv[r][m] = T.inv[(c < T.ninv && a < T.ninv) ? (int64_t)a * T.ninv + c : 0];
+        }
+    }
     // descend: x = 0, red-black sweep, residual, restriction
     for (int l = T.first; l < T.last; ++l) {
         const TailLevel L = tail_level(T, sm, l);
@@ -750,7 +755,7 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
         const int nn = L.ld * (L.nz + 1);
         for (int n = tid; n < nn; n += TN) {
             int i, j;
-            node_ij(n, L.ld, i, j);
+            tail_ij(n, L, i, j);
             tmp[n] = tail_unknown(L, i, j) ? tail_res(L, i, j, n) : 0.0f;
         }
         __syncthreads();
@@ -758,7 +763,7 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
         const int nc = C.ld * (C.nz + 1);
         for (int n = tid; n < nc; n += TN) {
             int I, J;
-            node_ij(n, C.ld, I, J);
+            tail_ij(n, C, I, J);
             float v = 0.0f;
             if (tail_unknown(C, I, J)) {
                 // full weighting of the fine residual; fine nodes 2I-1 / 2J-1
@@ -784,23 +789,34 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
         if (dense_regs) {
             float bq[TDR], acc[TDR];
 #pragma unroll
-            for (int m = 0; m < TDR; ++m) bq[m] = C.b[col[m]];
+            for (int m = 0; m < TDR; ++m) {
+                if (m >= nb) break;
+                bq[m] = C.b[col[m]];
+            }
 #pragma unroll
             for (int r = 0; r < TDR; ++r) {
+                if (r >= nb) break;
                 acc[r] = 0.0f;
 #pragma unroll
-                for (int m = 0; m < TDR; ++m)
+                for (int m = 0; m < TDR; ++m) {
+                    if (m >= nb) break;
                     if (lane + 32 * m < T.ninv) acc[r] += inv[r][m] * bq[m];
+                }
             }
             // the rows' shuffle steps interleaved: one LDS wait per step
 #pragma unroll
             for (int o = 16; o > 0; o >>= 1)
 #pragma unroll
-                for (int r = 0; r < TDR; ++r) acc[r] += __shfl_xor(acc[r], o, 32);
+                for (int r = 0; r < TDR; ++r) {
+                    if (r >= nb) break;
+                    acc[r] += __shfl_xor(acc[r], o, 32);
+                }
             // every lane holds the sums; lane g holds map[g + 32 r] = map[a]
 #pragma unroll
-            for (int r = 0; r < TDR; ++r)
+            for (int r = 0; r < TDR; ++r) {
+                if (r >= nb) break;
                 if (g + 32 * r < T.ninv && lane == g) C.x[col[r]] = acc[r];
+            }
         } else {
             for (int a0 = 0; a0 < T.ninv; a0 += TN / 32) {
                 const int a = a0 + g;
@@ -822,7 +838,7 @@ __device__ __forceinline__ void mg_tail_body(const MGTail &T, double *dot, float
         const int nn = L.ld * (L.nz + 1);
         for (int n = tid; n < nn; n += TN) {
             int i, j;
-            node_ij(n, L.ld, i, j);
+            tail_ij(n, L, i, j);
             if (tail_unknown(L, i, j)) {
                 // unknown fine nodes have i < nr, j < nz: the east / north
                 // coarse values exist where odd i / j reads them
