@@ -292,6 +292,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     f.q32b = cv.take<float>(nodes * 4);
     f.r32b = cv.take<float>(nodes * 4);
     f.w32 = cv.take<float>(nodes * 4);
+    f.cg_acc = cv.take<double>((int64_t)MAX_PCG * CG_ACC_PER_ITER * 8);
     auto shapes = mg_shapes(c);
     MGHier &H = f.mg;
     H.nlevels = (int)shapes.size();
@@ -589,11 +590,12 @@ void enqueue_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_it
     FieldDev &f = h->f;
     const MGHier &H = f.mg;
     const double inv_2pi_eps0 = 1.0 / (2.0 * 3.14159265358979323846 * eps0());
-    // (the cast also clears the pass's CG accumulators: pcg_rz .. pcg_ss)
-    launch_cast_scale(f, h->sc, s, h->sc->pcg_rz, 5 * (MAX_PCG + 2));
     const double *zq = (mode == PIC_LEARNED) ? h->sc->pcg_zq : nullptr;
     if (mode == PIC_MGCG && !h->mg_one_level && H.tail.first >= 1) {
-        // CG vector work fused into the finest level's V-cycle kernels
+        // CG vector work fused into the finest level's V-cycle kernels; the
+        // cast clears the pass's slotted dots, the FP64 update sums each
+        // iteration's ||r||^2 into pcg_rr for the readback
+        launch_cast_scale(f, h->sc, s, f.cg_acc, (int64_t)n_iter * CG_ACC_PER_ITER);
         CgVecs v;
         v.r[0] = H.lv[0].b;
         v.r[1] = f.r32b;
@@ -602,17 +604,16 @@ void enqueue_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_it
         v.w = f.w32;
         v.p = f.p32[0];
         v.e = f.e32;
-        v.rz = h->sc->pcg_rz;
+        v.acc = f.cg_acc;
         v.pq = h->sc->pcg_pq;
-        v.rr = h->sc->pcg_rr;
-        v.zq = h->sc->pcg_zq;
-        v.zaz = h->sc->pcg_ss;
         for (int k = 0; k < n_iter; ++k) launch_mg_vcycle_cg(H, v, k, s, true);
         launch_cg_update_last(H, v, n_iter - 1, s);
-        launch_update64(f, phi, h->sc, inv_2pi_eps0, s, true);
+        launch_update64(f, phi, h->sc, inv_2pi_eps0, s, true, n_iter);
         launch_residual64<Q>(f, phi, q0, q1, h->sc, s, false);
         return;
     }
+    // (the cast also clears the pass's CG accumulators: pcg_rz .. pcg_ss)
+    launch_cast_scale(f, h->sc, s, h->sc->pcg_rz, 5 * (MAX_PCG + 2));
     enqueue_precond(h, mode, 0);
     for (int k = 0; k < n_iter; ++k) {
         launch_cg_matvec(H, H.lv[0].xu, f.p32[(k + 1) & 1], f.p32[k & 1], f.q32, h->sc->pcg_rz,

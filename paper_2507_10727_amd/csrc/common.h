@@ -26,6 +26,12 @@ constexpr int MAX_LEVELS = 16;
 constexpr int MG_TAIL_LDS_MAX = 128 * 1024;        // dynamic LDS of the coarse-level kernels
 constexpr int MG_TAIL_NODES_MAX = 4096;            // nodes of the first level of that kernel
 constexpr int MAX_PCG = 512;
+// Sums that hundreds of blocks finishing together accumulate with FP64
+// atomics are spread over ACC_SLOTS partial sums, a block adding to slot
+// (block mod ACC_SLOTS), each slot on its own 64-byte line: atomics of every
+// block to one address serialize and hold the kernel's completion by
+// microseconds.
+constexpr int ACC_SLOTS = 16, ACC_STRIDE = 8;
 
 enum : int32_t { FLAG_CAPACITY = 1, FLAG_CHILD_OVERFLOW = 2, FLAG_NAN = 4 };
 
@@ -434,9 +440,19 @@ int mg_tail_setup(MGHier &H);
 // symmetry of A, alpha, e += alpha p_k, r_{k+1} = r_k - alpha q_k) and smooths
 // r_{k+1}.  r and q are double-buffered: a tile reads its halo's old values
 // while its owned nodes get the new ones.
+// Each dot product is accumulated in CG_SLOTS partial sums (ACC_SLOTS).
+// Iteration k's quantity m (0 r.z, 1 z.w, 2 z.q_{k-1}, 3 ||r_{k+1}||^2) sits
+// at acc + cg_acc_at(k, m, slot).
+constexpr int CG_SLOTS = ACC_SLOTS, CG_SLOT_STRIDE = ACC_STRIDE;
+constexpr int CG_ACC_PER_ITER = 4 * CG_SLOTS * CG_SLOT_STRIDE;
+__host__ __device__ constexpr int cg_acc_at(int k, int m, int slot)
+{
+    return (k * 4 + m) * CG_SLOTS * CG_SLOT_STRIDE + slot * CG_SLOT_STRIDE;
+}
 struct CgVecs {
     float *r[2], *q[2], *w, *p, *e;
-    double *rz, *pq, *rr, *zq, *zaz;    // per-iteration scalars
+    double *acc;                        // slotted dots, cleared per pass
+    double *pq;                         // p_k.q_k per iteration
 };
 // z = M r[k & 1] into lv[0].xu, with w and the dots; for k > 0 the down
 // kernel first applies update k - 1 (r[k & 1] = r_k from r[(k - 1) & 1])
@@ -455,6 +471,7 @@ struct FieldDev {
     double *r64;                // FP64 residual
     float *e32, *q32, *p32[2];  // inner CG vectors (finest level)
     float *q32b, *r32b, *w32;   // second q and r buffers, w = A z (CG fused into the V-cycle)
+    double *cg_acc;             // slotted dots of the fused CG (MAX_PCG iterations)
     MGHier mg;                  // r32 = mg.lv[0].b, z32 = mg.lv[0].xu
     const double *b_r, *b_z;    // static nodal B
     const double *vdep;         // node volumes for densities
@@ -547,9 +564,11 @@ void launch_apply_k64(const FieldDev &f, const double *phi, double *out, hipStre
 void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s, double *zero = nullptr,
                        int64_t nzero = 0);
 // phi += e32 ||r64|| / (2 pi eps0) on unknown nodes; zero_res also clears
-// the residual accumulators for the residual that follows
+// the residual accumulators for the residual that follows; with cg_iters > 0
+// it also sums the fused CG's slotted ||r||^2 of each iteration into
+// sc->pcg_rr
 void launch_update64(const FieldDev &f, double *phi, DevScalars *sc, double inv_2pi_eps0,
-                     hipStream_t s, bool zero_res = false);
+                     hipStream_t s, bool zero_res = false, int cg_iters = 0);
 // extrapolation of phi0 (when asked), Dirichlet values, cleared residual
 // accumulators: the start of a solve in one launch
 void launch_solve_prep(const FieldDev &f, double *phi, bool extrapolate, double v_cathode,

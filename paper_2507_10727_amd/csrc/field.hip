@@ -165,20 +165,28 @@ __global__ void k_cast_scale(int64_t nn, const double *r64, DevScalars *sc, floa
 // the residual that follows; this kernel reads only res_rr0
 __device__ __forceinline__ void update64_body(int64_t nn, const uint8_t *kind, double *phi, const float *e32,
                            const DevScalars *sc, double inv_2pi_eps0, const int32_t *gate, int blk, int nblk,
-                           double *zero_res = nullptr)
+                           double *zero_res = nullptr, const double *cg_acc = nullptr,
+                           double *rr_out = nullptr, int cg_iters = 0)
 {
     if (gate && *gate) return;
     const double scale = sqrt(sc->res_rr0) * inv_2pi_eps0;
     if (zero_res && blk == 0 && threadIdx.x < 2) zero_res[threadIdx.x] = 0.0;
+    if (blk == 0)
+        for (int k = threadIdx.x; k < cg_iters; k += FB) {
+            double a = 0.0;
+            for (int sl = 0; sl < CG_SLOTS; ++sl) a += cg_acc[cg_acc_at(k, 3, sl)];
+            rr_out[k] = a;
+        }
     for (int64_t n = (int64_t)blk * FB + threadIdx.x; n < nn; n += (int64_t)nblk * FB)
         if (kind[n] == 0) phi[n] += (double)e32[n] * scale;
 }
 
 __global__ void k_update64(int64_t nn, const uint8_t *kind, double *phi, const float *e32,
                            const DevScalars *sc, double inv_2pi_eps0, const int32_t *gate,
-                           double *zero_res)
+                           double *zero_res, const double *cg_acc, double *rr_out, int cg_iters)
 {
-    update64_body(nn, kind, phi, e32, sc, inv_2pi_eps0, gate, blockIdx.x, gridDim.x, zero_res);
+    update64_body(nn, kind, phi, e32, sc, inv_2pi_eps0, gate, blockIdx.x, gridDim.x, zero_res,
+                  cg_acc, rr_out, cg_iters);
 }
 
 // ---- circuit: induced cathode charge of phi0 and the cathode voltage update
@@ -562,11 +570,12 @@ void launch_cast_scale(const FieldDev &f, DevScalars *sc, hipStream_t s, double 
 }
 
 void launch_update64(const FieldDev &f, double *phi, DevScalars *sc, double inv_2pi_eps0,
-                     hipStream_t s, bool zero_res)
+                     hipStream_t s, bool zero_res, int cg_iters)
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     hipLaunchKernelGGL(k_update64, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.kind, phi, f.e32,
-                       sc, inv_2pi_eps0, f.gate, zero_res ? &sc->res_rr : nullptr);
+                       sc, inv_2pi_eps0, f.gate, zero_res ? &sc->res_rr : nullptr, f.cg_acc,
+                       sc->pcg_rr, cg_iters);
 }
 
 void launch_solve_prep(const FieldDev &f, double *phi, bool extrapolate, double v_cathode,

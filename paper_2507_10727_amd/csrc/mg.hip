@@ -401,6 +401,11 @@ __device__ __forceinline__ void mg_up2_body(const MGLevel &F, const MGLevel &M, 
 
 // ---- the finest level with the CG vector work fused in
 
+__device__ __forceinline__ double ld_vec(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // scalars of CG iteration j (uniform over the grid): beta_j, alpha_j and
 // p_j.q_j from the dots of the V-cycle that produced z_j
 struct CgScalars {
@@ -409,10 +414,27 @@ struct CgScalars {
 };
 __device__ __forceinline__ CgScalars cg_scalars(const CgVecs &v, int j)
 {
+    // the slotted dots: lane l reads slot l mod CG_SLOTS of each (vector
+    // loads, which queue with the kernel's other loads; scalar loads of
+    // values the previous kernel wrote miss the scalar cache one after
+    // another), summed over the slots by a butterfly that leaves the same
+    // sums in every lane; index j - 1 is clamped and its terms selected away
+    // for j = 0
+    const int sl = threadIdx.x & (CG_SLOTS - 1);
+    const int jm = j > 0 ? j - 1 : 0;
+    double rz = ld_vec(&v.acc[cg_acc_at(j, 0, sl)]), rzm = ld_vec(&v.acc[cg_acc_at(jm, 0, sl)]);
+    double zaz = ld_vec(&v.acc[cg_acc_at(j, 1, sl)]), zq = ld_vec(&v.acc[cg_acc_at(j, 2, sl)]);
+    const double pqm = ld_vec(&v.pq[jm]);
+#pragma unroll
+    for (int o = CG_SLOTS / 2; o > 0; o >>= 1) {
+        rz += __shfl_xor(rz, o, CG_SLOTS);
+        rzm += __shfl_xor(rzm, o, CG_SLOTS);
+        zaz += __shfl_xor(zaz, o, CG_SLOTS);
+        zq += __shfl_xor(zq, o, CG_SLOTS);
+    }
     CgScalars c;
-    const double rz = v.rz[j];
-    const double bd = (j > 0 && v.rz[j - 1] != 0.0) ? rz / v.rz[j - 1] : 0.0;
-    c.pq = v.zaz[j] + (j > 0 ? 2.0 * bd * v.zq[j] + bd * bd * v.pq[j - 1] : 0.0);
+    const double bd = (j > 0 && rzm != 0.0) ? rz / rzm : 0.0;
+    c.pq = zaz + (j > 0 ? 2.0 * bd * zq + bd * bd * pqm : 0.0);
     c.beta = (float)bd;
     c.alpha = (c.pq > 0.0) ? (float)(rz / c.pq) : 0.0f;
     return c;
@@ -422,8 +444,9 @@ __device__ __forceinline__ CgScalars cg_scalars(const CgVecs &v, int j)
 // the tile (halo included) forms q_j = w_j + beta q_{j-1} and r_{j+1} =
 // r_j - alpha q_j from r[j & 1], w, q[(j - 1) & 1]; owned nodes store
 // r[(j + 1) & 1], q[j & 1], p_j = z_j + beta p_{j-1} (in place), e += alpha
-// p_j and add r_{j+1}^2 to rr[j]; then pre-smoothing of r_{j+1} as in the
-// plain down kernel.  Block (0, 0) records p_j.q_j in pq[j].
+// p_j and add r_{j+1}^2 to their slot of ||r_{j+1}||^2; then pre-smoothing
+// of r_{j+1} as in the plain down kernel.  Block (0, 0) records p_j.q_j in
+// pq[j].
 static_assert(MG_NU >= 1, "the owned-node pass reads sb before the smoothing's first barrier");
 __device__ __forceinline__ void mg_down_cg_body(const MGLevel &F, const MGLevel &C,
                                                 const CgVecs &v, int j, int bx, int by)
@@ -457,6 +480,8 @@ __device__ __forceinline__ void mg_down_cg_body(const MGLevel &F, const MGLevel 
         pl[o] = v.p[n];
         el[o] = v.e[n];
     }
+    // issued after the tile's loads: they complete in order, so the scalars'
+    // wait is the tile's
     const CgScalars cs = cg_scalars(v, j);
 #pragma unroll
     for (int u = 0; u < DN; ++u) {
@@ -505,14 +530,15 @@ __device__ __forceinline__ void mg_down_cg_body(const MGLevel &F, const MGLevel 
     __syncthreads();
     if (threadIdx.x == 0) {
         const double s = red[0] + red[1] + red[2] + red[3];
-        if (s != 0.0) atomic_add_dev(&v.rr[j], s);
+        const int sl = (by * (int)gridDim.x + bx) & (CG_SLOTS - 1);
+        if (s != 0.0) atomic_add_dev(&v.acc[cg_acc_at(j, 3, sl)], s);
     }
 }
 
 // Up on the finest level of CG iteration k (F.b = r_k): a tile with one more
 // halo node, so that after the sweeps z is exact on the owned nodes and their
 // neighbours; owned nodes store z (F.xu) and w = A z, and the block adds
-// r.z, z.w and z.q_{k-1} (k > 0) to rz[k], zaz[k], zq[k].
+// r.z, z.w and z.q_{k-1} (k > 0) to its slot of iteration k's dots.
 constexpr int UH3 = UH + 1;
 constexpr int UCW = UTX + 2 * UH3, UCH = UTY + 2 * UH3;
 constexpr int UCN = (UCW * UCH + 255) / 256;
@@ -582,8 +608,8 @@ __device__ __forceinline__ void mg_up_cg_body(const MGLevel &F, const MGLevel &C
     if (threadIdx.x < 3) {
         const double s = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] +
                          red[threadIdx.x][3];
-        double *dst = threadIdx.x == 0 ? &v.rz[k] : (threadIdx.x == 1 ? &v.zaz[k] : &v.zq[k]);
-        if (s != 0.0) atomic_add_dev(dst, s);
+        const int sl = (by * (int)gridDim.x + bx) & (CG_SLOTS - 1);
+        if (s != 0.0) atomic_add_dev(&v.acc[cg_acc_at(k, threadIdx.x, sl)], s);
     }
 }
 
@@ -982,7 +1008,7 @@ __device__ __forceinline__ void cg_update_last_body(const MGLevel &L, const CgVe
     if (threadIdx.x == 0) {
         double s = 0.0;
         for (int w = 0; w < CB / 64; ++w) s += red[w];
-        if (s != 0.0) atomic_add_dev(&v.rr[j], s);
+        if (s != 0.0) atomic_add_dev(&v.acc[cg_acc_at(j, 3, blk & (CG_SLOTS - 1))], s);
     }
 }
 
