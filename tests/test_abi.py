@@ -78,6 +78,21 @@ def test_fp32_grid_limit_of_packed_positions():
     assert lib.pic_query_workspace(C.byref(cfg), C.byref(n)) == 0
 
 
+def test_coarse_level_node_limit():
+    # a grid that cannot coarsen (2 cells in z) whose cathode covers the
+    # first row: few unknowns, but the one-workgroup coarse solve would start
+    # at a level of (nr + 1) x 3 nodes, accepted up to 4096
+    lib = L.load()
+    n = C.c_int64()
+    lr = W.preset("small_mc64_f64").lr
+    for nr, ok in ((1300, True), (1500, False)):
+        cfg, keep = _cfg(nr=nr, nz=2, cathode_rmax=lr)
+        st = lib.pic_query_workspace(C.byref(cfg), C.byref(n))
+        assert (st == 0) == ok, (nr, st)
+        if not ok:
+            assert st == L.PIC_EINVAL and b"nodes" in lib.pic_last_error(None)
+
+
 def test_init_rejects_missing_workspace():
     lib = L.load()
     cfg, keep = _cfg()
