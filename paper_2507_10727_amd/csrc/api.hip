@@ -538,16 +538,21 @@ struct SolveReadback {
 
 // With hist, also the inner iterations' squared residuals of the pass (the
 // FP32 residual starts at unit norm), in the same synchronization.
-constexpr size_t PINNED_BYTES = sizeof(SolveReadback) + MAX_PCG * sizeof(double);
+constexpr size_t PINNED_BYTES =
+    sizeof(SolveReadback) + (RES_SLOT_WORDS + MAX_PCG) * sizeof(double);
 
 pic_status readback(pic_handle *h, SolveReadback *rb, double *hist = nullptr, int n_hist = 0)
 {
     static_assert(sizeof(SolveReadback) == 48, "readback layout");
     char *pin = (char *)h->pinned;
+    double *slots = (double *)(pin + sizeof(SolveReadback));
+    char *hist_pin = pin + sizeof(SolveReadback) + RES_SLOT_WORDS * sizeof(double);
     HIPCHECK(h, hipMemcpyAsync(pin, &h->sc->res_rr, sizeof(SolveReadback), hipMemcpyDeviceToHost,
                                h->stream));
+    HIPCHECK(h, hipMemcpyAsync(slots, h->sc->res_slots, RES_SLOT_WORDS * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
     if (hist && n_hist > 0)
-        HIPCHECK(h, hipMemcpyAsync(pin + sizeof(SolveReadback), h->sc->pcg_rr, (size_t)n_hist * 8,
+        HIPCHECK(h, hipMemcpyAsync(hist_pin, h->sc->pcg_rr, (size_t)n_hist * 8,
                                    hipMemcpyDeviceToHost, h->stream));
     // the solve's only synchronization sits on the step's critical path:
     // poll for it rather than let the runtime block and be woken
@@ -557,7 +562,13 @@ pic_status readback(pic_handle *h, SolveReadback *rb, double *hist = nullptr, in
     }
     HIPCHECK(h, q);
     memcpy(rb, pin, sizeof(SolveReadback));
-    if (hist && n_hist > 0) memcpy(hist, pin + sizeof(SolveReadback), (size_t)n_hist * 8);
+    // the residual norms are kept in slots (summed in slot order)
+    rb->rr = rb->bb = 0.0;
+    for (int k = 0; k < ACC_SLOTS; ++k) {
+        rb->rr += slots[k * ACC_STRIDE];
+        rb->bb += slots[(ACC_SLOTS + k) * ACC_STRIDE];
+    }
+    if (hist && n_hist > 0) memcpy(hist, hist_pin, (size_t)n_hist * 8);
     h->host_count[0] = rb->count[0];
     h->host_count[1] = rb->count[1];
     h->host_flags = rb->flags;

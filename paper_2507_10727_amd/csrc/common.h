@@ -67,7 +67,11 @@ struct DevScalars {
     // device-controlled solve of a captured step: done flag (gates the pass
     // kernels), passes and iterations run
     int32_t solve_done, solve_passes, solve_iters, solve_pad;
+    // a single run's FP64 residual norms^2 (||r||^2, ||b||^2) in ACC_SLOTS
+    // slots each, summed by their readers (the cast kernel, the host)
+    double res_slots[2 * ACC_SLOTS * ACC_STRIDE];
 };
+constexpr int RES_SLOT_WORDS = 2 * ACC_SLOTS * ACC_STRIDE;
 
 // Particle arrays of one species (structure of arrays).
 //

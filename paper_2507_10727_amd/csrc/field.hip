@@ -75,7 +75,8 @@ __device__ __forceinline__ void residual64_body(int32_t nr, int32_t nz, const do
                                                    const double *cn, const uint8_t *kind,
                                                    const double *phi, const T *q0, const T *q1,
                                                    double *r64, DevScalars *sc,
-                                                   const int32_t *gate, int blk, int nblk)
+                                                   const int32_t *gate, int blk, int nblk,
+                                                   bool slotted = false)
 {
     if (gate && *gate) return;
     __shared__ double buf[RB / 64];
@@ -101,8 +102,15 @@ __device__ __forceinline__ void residual64_body(int32_t nr, int32_t nz, const do
     const double a = block_sum(rr, buf);
     const double b = block_sum(bb, buf);
     if (threadIdx.x == 0) {
-        if (a != 0.0) atomic_add_dev(&sc->res_rr, a);
-        if (b != 0.0) atomic_add_dev(&sc->res_bb, b);
+        if (slotted) {
+            // (blocks finishing together would serialize on one address)
+            const int sl = (blk & (ACC_SLOTS - 1)) * ACC_STRIDE;
+            if (a != 0.0) atomic_add_dev(&sc->res_slots[sl], a);
+            if (b != 0.0) atomic_add_dev(&sc->res_slots[ACC_SLOTS * ACC_STRIDE + sl], b);
+        } else {
+            if (a != 0.0) atomic_add_dev(&sc->res_rr, a);
+            if (b != 0.0) atomic_add_dev(&sc->res_bb, b);
+        }
     }
 }
 
@@ -113,7 +121,8 @@ __global__ void __launch_bounds__(RB) k_residual64(int32_t nr, int32_t nz, const
                                                    double *r64, DevScalars *sc,
                                                    const int32_t *gate)
 {
-    residual64_body<T>(nr, nz, ce, cn, kind, phi, q0, q1, r64, sc, gate, blockIdx.x, gridDim.x);
+    residual64_body<T>(nr, nz, ce, cn, kind, phi, q0, q1, r64, sc, gate, blockIdx.x, gridDim.x,
+                       true);
 }
 
 // out = K phi on unknown nodes (charge form, C), 0 on Dirichlet nodes
@@ -141,10 +150,18 @@ __global__ void __launch_bounds__(FB) k_apply_k64(int32_t nr, int32_t nz, const 
 // nothing in this kernel reads
 __device__ __forceinline__ void cast_scale_body(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32,
                              const int32_t *gate, int blk, int nblk, double *zero = nullptr,
-                             int64_t nzero = 0)
+                             int64_t nzero = 0, bool slotted = false)
 {
     if (gate && *gate) return;
-    const double rr = sc->res_rr;
+    double rr;
+    if (slotted) {
+        // the residual's slots, lane l reading slot l mod ACC_SLOTS, summed
+        // by a butterfly that leaves the same sum in every lane
+        rr = sc->res_slots[(threadIdx.x & (ACC_SLOTS - 1)) * ACC_STRIDE];
+        for (int o = ACC_SLOTS / 2; o > 0; o >>= 1) rr += __shfl_xor(rr, o, ACC_SLOTS);
+    } else {
+        rr = sc->res_rr;
+    }
     const double scale = (rr > 0.0) ? 1.0 / sqrt(rr) : 0.0;
     if (blk == 0 && threadIdx.x == 0) sc->res_rr0 = rr;
     for (int64_t k = (int64_t)blk * FB + threadIdx.x; k < nzero; k += (int64_t)nblk * FB)
@@ -158,7 +175,7 @@ __device__ __forceinline__ void cast_scale_body(int64_t nn, const double *r64, D
 __global__ void k_cast_scale(int64_t nn, const double *r64, DevScalars *sc, float *r32, float *e32,
                              const int32_t *gate, double *zero, int64_t nzero)
 {
-    cast_scale_body(nn, r64, sc, r32, e32, gate, blockIdx.x, gridDim.x, zero, nzero);
+    cast_scale_body(nn, r64, sc, r32, e32, gate, blockIdx.x, gridDim.x, zero, nzero, true);
 }
 
 // with zero_res, also zeroes the residual accumulators (res_rr, res_bb) for
@@ -170,7 +187,8 @@ __device__ __forceinline__ void update64_body(int64_t nn, const uint8_t *kind, d
 {
     if (gate && *gate) return;
     const double scale = sqrt(sc->res_rr0) * inv_2pi_eps0;
-    if (zero_res && blk == 0 && threadIdx.x < 2) zero_res[threadIdx.x] = 0.0;
+    if (zero_res && blk == 0)
+        for (int k = threadIdx.x; k < RES_SLOT_WORDS; k += FB) zero_res[k] = 0.0;
     if (blk == 0)
         for (int k = threadIdx.x; k < cg_iters; k += FB) {
             double a = 0.0;
@@ -321,7 +339,8 @@ __global__ void k_set_dirichlet(int64_t nn, const uint8_t *kind, double *phi, do
 __global__ void k_solve_prep(int64_t nn, const uint8_t *kind, double *phi, double *prev,
                              double vcat, double *zero_res)
 {
-    if (blockIdx.x == 0 && threadIdx.x < 2) zero_res[threadIdx.x] = 0.0;
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < RES_SLOT_WORDS; k += FB) zero_res[k] = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * FB + threadIdx.x; n < nn; n += (int64_t)gridDim.x * FB) {
         const uint8_t k = kind[n];
         if (prev) {
@@ -549,7 +568,7 @@ void launch_residual64(const FieldDev &f, const double *phi, const T *q0, const 
                        DevScalars *sc, hipStream_t s, bool zero)
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
-    if (zero) launch_zero_gated(&sc->res_rr, 2 * sizeof(double), f.gate, s);
+    if (zero) launch_zero_gated(sc->res_slots, RES_SLOT_WORDS * sizeof(double), f.gate, s);
     hipLaunchKernelGGL((k_residual64<T>), dim3(res_blocks(nn)), dim3(RB), 0, s, f.nr,
                        f.nz, f.ce64, f.cn64, f.kind, phi, q0, q1, f.r64, sc, f.gate);
 }
@@ -574,7 +593,7 @@ void launch_update64(const FieldDev &f, double *phi, DevScalars *sc, double inv_
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     hipLaunchKernelGGL(k_update64, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.kind, phi, f.e32,
-                       sc, inv_2pi_eps0, f.gate, zero_res ? &sc->res_rr : nullptr, f.cg_acc,
+                       sc, inv_2pi_eps0, f.gate, zero_res ? sc->res_slots : nullptr, f.cg_acc,
                        sc->pcg_rr, cg_iters);
 }
 
@@ -583,7 +602,7 @@ void launch_solve_prep(const FieldDev &f, double *phi, bool extrapolate, double 
 {
     const int64_t nn = (int64_t)(f.nr + 1) * (f.nz + 1);
     hipLaunchKernelGGL(k_solve_prep, dim3(blocks_for(nn)), dim3(FB), 0, s, nn, f.kind, phi,
-                       extrapolate ? f.phi0_prev : nullptr, v_cathode, &sc->res_rr);
+                       extrapolate ? f.phi0_prev : nullptr, v_cathode, sc->res_slots);
 }
 
 template <typename T>
