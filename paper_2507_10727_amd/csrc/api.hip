@@ -77,9 +77,11 @@ struct pic_handle {
     int pmode = PIC_MGCG;
     int64_t n_unknown = 0;
     double rho_pc = 0.5, rho_cg = 0.9;
+    RunSolve *rsolve = nullptr;     // descriptor of the batched field update
+    char *part_desc = nullptr;      // RunParticles for each pair of current particle
+                                    // buffers (an ensemble's one-launch particle kernels)
     // launch shape of the particle kernel (autotuned): total blocks and the
     // weight of an electron against an ion when splitting them
-    RunSolve *rsolve = nullptr;     // descriptor of the batched field update
     int push_blocks = 1024;
     double push_e_weight = 1.3;
     bool mg_one_level = false;      // V-cycle with one kernel per grid level
@@ -221,6 +223,9 @@ pic_status validate(const pic_config *c, pic_handle *h)
     return PIC_OK;
 }
 
+constexpr int64_t PART_DESC_BYTES =
+    ((int64_t)std::max(sizeof(RunParticles<float>), sizeof(RunParticles<double>)) + 255) & ~255;
+
 // Workspace layout.  With base == nullptr only the size is computed.
 struct Carver {
     char *base;
@@ -336,6 +341,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     double *dpart = cv.take<double>((int64_t)dblocks * 6 * 8);
     unsigned long long *live = cv.take<unsigned long long>(2 * 8);
     RunSolve *rsolve = cv.take<RunSolve>(sizeof(RunSolve));
+    char *part_desc = cv.take<char>(4 * PART_DESC_BYTES);
     // learned preconditioner: network, Adam state and activations
     const bool pc_on = c.pc_batch > 0 || c.poisson_mode == PIC_LEARNED;
     PcNet net;
@@ -346,6 +352,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     }
     if (h) {
         h->rsolve = rsolve;
+        h->part_desc = part_desc;
         h->pc_on = pc_on;
         if (pc_on) {
             h->net = net;
@@ -942,17 +949,11 @@ pic_status field_update(pic_handle *h)
 // (gather, Boris, walls, candidate queues, deposit), events (collisions,
 // emission), children (ids, append, deposit), finalize (counts).
 template <typename T>
-void particle_phase(pic_handle *h)
+EventParams<T> event_params(const pic_handle *h)
 {
     const pic_config &c = h->cfg;
-    const int64_t nodes = (int64_t)(c.nr + 1) * (c.nz + 1);
-    launch_begin_step(h->sc, h->q[0], h->q[1], nodes, (int)sizeof(T), h->stream);
-    hipEvent_t ev[2];
-    timer_begin(h, ev);
-    launch_push_h<T>(h, 0);
-    timer_end(h, 0, ev);
-    timer_begin(h, ev);
     EventParams<T> E;
+    memset(&E, 0, sizeof(E));
     for (int s = 0; s < 2; ++s) E.sp[s] = species_dev<T>(h->buf[s][h->cur[s]]);
     E.cold = (const PushCold<T> *)h->cold;
     E.sc = h->sc;
@@ -963,8 +964,15 @@ void particle_phase(pic_handle *h)
     E.key0 = (uint32_t)(c.seed & 0xffffffffu);
     E.key1 = (uint32_t)(c.seed >> 32);
     E.run = c.run;
-    launch_events<T>(E, h->stream);
+    return E;
+}
+
+template <typename T>
+ChildParams<T> child_params(const pic_handle *h)
+{
+    const pic_config &c = h->cfg;
     ChildParams<T> C;
+    memset(&C, 0, sizeof(C));
     for (int s = 0; s < 2; ++s) {
         C.sp[s] = species_dev<T>(h->buf[s][h->cur[s]]);
         C.cap[s] = h->cap[s];
@@ -975,9 +983,31 @@ void particle_phase(pic_handle *h)
     C.child = (const Child<T> *)h->child;
     C.child_cap = h->child_cap;
     C.nr = c.nr;
-    launch_children<T>(C, h->stream);
+    return C;
+}
+
+template <typename T>
+void particle_events(pic_handle *h)
+{
+    hipEvent_t ev[2];
+    timer_begin(h, ev);
+    launch_events<T>(event_params<T>(h), h->stream);
+    launch_children<T>(child_params<T>(h), h->stream);
     launch_finalize_step(h->sc, h->cap, h->stream);
     timer_end(h, 1, ev);
+}
+
+template <typename T>
+void particle_phase(pic_handle *h)
+{
+    const pic_config &c = h->cfg;
+    const int64_t nodes = (int64_t)(c.nr + 1) * (c.nz + 1);
+    launch_begin_step(h->sc, h->q[0], h->q[1], nodes, (int)sizeof(T), h->stream);
+    hipEvent_t ev[2];
+    timer_begin(h, ev);
+    launch_push_h<T>(h, 0);
+    timer_end(h, 0, ev);
+    particle_events<T>(h);
 }
 
 template <typename T>
@@ -1008,13 +1038,6 @@ pic_status step_one(pic_handle *h)
 // ---- a step with no host synchronization (for graph capture) ---------------
 
 // The particle part of a step (the ensemble batches the field update).
-template <typename T>
-void step_enqueue(pic_handle *h, bool do_sort)
-{
-    if (do_sort) sort_all<T>(h);
-    particle_phase<T>(h);
-}
-
 template <typename T>
 pic_status init_typed(pic_handle *h, const pic_species_host *init)
 {
@@ -1173,8 +1196,91 @@ void drop_ensemble_graphs(pic_ensemble *e)
     e->graphs.clear();
 }
 
-// Capture one step of every run, each run on one of the ensemble's streams
-// (round robin), with the status copy of each run at its end.
+// A run's RunParticles for the four pairs of current particle buffers, into
+// its workspace.
+template <typename T>
+bool upload_run_particles(pic_handle *h)
+{
+    const int cur0 = h->cur[0], cur1 = h->cur[1];
+    bool up = true;
+    for (int k = 0; k < 4; ++k) {
+        h->cur[0] = k & 1;
+        h->cur[1] = k >> 1;
+        RunParticles<T> D;
+        memset(&D, 0, sizeof(D));
+        D.push = push_params<T>(h, 0);
+        D.ev = event_params<T>(h);
+        D.ch = child_params<T>(h);
+        up &= hipMemcpy(h->part_desc + k * PART_DESC_BYTES, &D, sizeof(D),
+                        hipMemcpyHostToDevice) == hipSuccess;
+    }
+    h->cur[0] = cur0;
+    h->cur[1] = cur1;
+    return up;
+}
+
+// Particle phase of the runs of batch b of an ensemble, one launch per
+// kernel (begin, push, events, children, finalize), each block reading its
+// run's descriptor for the run's current particle buffers.  A batch that
+// mixes schemes pushes run by run.
+template <typename T>
+void particle_phase_b(pic_ensemble *e, size_t b)
+{
+    const size_t r0 = b * MAX_BATCH;
+    const size_t r1 = std::min(e->runs.size(), r0 + MAX_BATCH);
+    const int n = (int)(r1 - r0);
+    PartBatch<T> Bb, Bp, Be, Bc;
+    for (PartBatch<T> *B : {&Bb, &Bp, &Be, &Bc}) memset(B, 0, sizeof(*B));
+    int ob = 0, op = 0, oe = 0, oc = 0;
+    bool one_scheme = true;
+    for (int k = 0; k < n; ++k) {
+        pic_handle *h = e->runs[r0 + k];
+        one_scheme &= h->cfg.scheme == e->runs[r0]->cfg.scheme;
+        const RunParticles<T> *d =
+            (const RunParticles<T> *)(h->part_desc + (h->cur[0] + 2 * h->cur[1]) * PART_DESC_BYTES);
+        Bb.p[k] = d;
+        Bb.off[k] = ob;
+        ob += begin_b_blocks((int64_t)(h->cfg.nr + 1) * (h->cfg.nz + 1), (int)sizeof(T));
+        Bp.off[k] = op;
+        int be, nb;
+        push_grid(h, &be, &nb);
+        Bp.aux[k] = be;
+        op += nb;
+        Be.off[k] = oe;
+        oe += EVENTS_B_BLOCKS;
+        Bc.off[k] = oc;
+        oc += children_b_blocks(h->child_cap);
+    }
+    Bb.off[n] = ob;
+    Bb.nruns = n;
+    for (PartBatch<T> *B : {&Bp, &Be, &Bc}) {
+        for (int k = 0; k < n; ++k) B->p[k] = Bb.p[k];
+        B->nruns = n;
+    }
+    Bp.off[n] = op;
+    Be.off[n] = oe;
+    Bc.off[n] = oc;
+    launch_begin_b<T>(Bb, e->s0);
+    if (one_scheme) {
+        launch_push_b<T>(Bp, e->runs[r0]->cfg.scheme, e->s0);
+    } else {
+        for (size_t r = r0; r < r1; ++r) {
+            pic_handle *h = e->runs[r];
+            hipStream_t saved = h->stream;
+            h->stream = e->s0;
+            launch_push_h<T>(h, 0);
+            h->stream = saved;
+        }
+    }
+    launch_events_b<T>(Be, e->s0);
+    launch_children_b<T>(Bc, e->s0);
+    launch_finalize_b<T>(Bb, e->s0);
+}
+
+// Capture one step of every run: in a sort step the per-run sorts on the
+// ensemble's streams (round robin), then for each batch of up to MAX_BATCH
+// runs one launch per particle kernel, the batched field update and a status
+// copy per run.
 pic_status capture_ensemble(pic_ensemble *e, bool do_sort, hipGraphExec_t *out)
 {
     const int ns = (int)e->streams.size();
@@ -1197,19 +1303,30 @@ pic_status capture_ensemble(pic_ensemble *e, bool do_sort, hipGraphExec_t *out)
     };
     const int plan[3] = {iters(std::max(0.5 * rtol / rel0, 1e-6)), iters(1e-6), iters(1e-6)};
     EHIPCHECK(e, hipStreamBeginCapture(e->s0, hipStreamCaptureModeThreadLocal));
-    (void)hipEventRecord(e->events[0], e->s0);
-    for (int k = 0; k < ns; ++k) (void)hipStreamWaitEvent(e->streams[k], e->events[0], 0);
-    for (size_t r = 0; r < e->runs.size(); ++r) {
-        pic_handle *h = e->runs[r];
-        hipStream_t saved = h->stream;
-        h->stream = e->streams[r % ns];
-        if (h->prec == PIC_F64) step_enqueue<double>(h, do_sort);
-        else step_enqueue<float>(h, do_sort);
-        h->stream = saved;
+    auto join = [&]() {
+        for (int k = 0; k < ns; ++k) {
+            (void)hipEventRecord(e->events[1 + k], e->streams[k]);
+            (void)hipStreamWaitEvent(e->s0, e->events[1 + k], 0);
+        }
+    };
+    // the sorts of a sort step, per run
+    if (do_sort) {
+        (void)hipEventRecord(e->events[0], e->s0);
+        for (int k = 0; k < ns; ++k) (void)hipStreamWaitEvent(e->streams[k], e->events[0], 0);
+        for (size_t r = 0; r < e->runs.size(); ++r) {
+            pic_handle *h = e->runs[r];
+            hipStream_t saved = h->stream;
+            h->stream = e->streams[r % ns];
+            if (h->prec == PIC_F64) sort_all<double>(h);
+            else sort_all<float>(h);
+            h->stream = saved;
+        }
+        join();
     }
-    for (int k = 0; k < ns; ++k) {
-        (void)hipEventRecord(e->events[1 + k], e->streams[k]);
-        (void)hipStreamWaitEvent(e->s0, e->events[1 + k], 0);
+    // particle phase of every run: one launch per kernel for a batch of runs
+    for (size_t b = 0; b < e->plans.size(); ++b) {
+        if (e->runs[0]->prec == PIC_F64) particle_phase_b<double>(e, b);
+        else particle_phase_b<float>(e, b);
     }
     // field update of every run, batched: extrapolated warm start, FP64
     // residual, up to three device-gated multigrid-PCG passes, circuit,
@@ -1750,6 +1867,17 @@ pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *str
         if (hipMemcpy(h->rsolve, &R, sizeof(R), hipMemcpyHostToDevice) != hipSuccess) {
             pic_ensemble_free(e);
             return efail(nullptr, PIC_EHIP, "cannot upload the run descriptors");
+        }
+        // particle-kernel parameters for each pair of current buffers
+        if (h->part_desc + 4 * PART_DESC_BYTES > h->ws + h->ws_bytes) {
+            pic_ensemble_free(e);
+            return efail(nullptr, PIC_EINVAL, "run %d: no room for the particle descriptors", r);
+        }
+        const bool up = h->prec == PIC_F64 ? upload_run_particles<double>(h)
+                                           : upload_run_particles<float>(h);
+        if (!up) {
+            pic_ensemble_free(e);
+            return efail(nullptr, PIC_EHIP, "cannot upload the particle descriptors");
         }
         BatchPlan &P = e->plans[r / MAX_BATCH];
         P.dev[P.nruns] = h->rsolve;

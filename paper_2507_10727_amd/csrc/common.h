@@ -26,6 +26,7 @@ constexpr int MAX_LEVELS = 16;
 constexpr int MG_TAIL_LDS_MAX = 128 * 1024;        // dynamic LDS of the coarse-level kernels
 constexpr int MG_TAIL_NODES_MAX = 4096;            // nodes of the first level of that kernel
 constexpr int MAX_PCG = 512;
+constexpr int MAX_BATCH = 64;
 // Sums that hundreds of blocks finishing together accumulate with FP64
 // atomics are spread over ACC_SLOTS partial sums, a block adding to slot
 // (block mod ACC_SLOTS), each slot on its own 64-byte line: atomics of every
@@ -235,6 +236,26 @@ struct ChildParams {
     int32_t nr;
 };
 
+// A run's particle-kernel parameters for one pair of current particle
+// buffers; an ensemble keeps the four pairs in each run's workspace.
+template <typename T>
+struct RunParticles {
+    PushParams<T> push;
+    EventParams<T> ev;
+    ChildParams<T> ch;
+};
+
+// One launch of a particle kernel for up to MAX_BATCH runs: each run's
+// descriptor, its first block (a block finds its run by binary search over
+// off) and, for the push, its electron blocks (aux).
+template <typename T>
+struct PartBatch {
+    const RunParticles<T> *p[MAX_BATCH];
+    int32_t off[MAX_BATCH + 1];
+    int32_t aux[MAX_BATCH];
+    int32_t nruns;
+};
+
 // ---------------------------------------------------------------- Philox --
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 products of counter words 0 and 2 with the round multipliers,
@@ -334,6 +355,20 @@ __device__ __forceinline__ void atomic_add_dev(double *p, double v) { unsafeAtom
 // particles.hip
 template <typename T>
 void launch_push(const PushParams<T> &p, int scheme, int nblocks, hipStream_t s);
+template <typename T>
+void launch_push_b(const PartBatch<T> &b, int scheme, hipStream_t s);
+template <typename T>
+void launch_begin_b(const PartBatch<T> &b, hipStream_t s);
+template <typename T>
+void launch_events_b(const PartBatch<T> &b, hipStream_t s);
+template <typename T>
+void launch_children_b(const PartBatch<T> &b, hipStream_t s);
+template <typename T>
+void launch_finalize_b(const PartBatch<T> &b, hipStream_t s);
+// blocks per run of the batched begin, event and child kernels
+int begin_b_blocks(int64_t nodes, int elem_bytes);
+constexpr int EVENTS_B_BLOCKS = 128;
+int children_b_blocks(int32_t child_cap);
 template <typename T>
 void launch_events(const EventParams<T> &p, hipStream_t s);
 template <typename T>
@@ -483,7 +518,6 @@ struct FieldDev {
 };
 
 // ---- batched field update of an ensemble ------------------------------------
-constexpr int MAX_BATCH = 64;
 
 // Per-run descriptor in the run's workspace: the field state, the charge,
 // the gather fields and the constants of the solve and the circuit; gates

@@ -427,8 +427,10 @@ __device__ __forceinline__ void stream_store(int4 *p, const int4 &v) { stream_st
 __device__ __forceinline__ void stream_store(float4 *p, const float4 &v) { stream_store_v<float4, float>(p, v); }
 __device__ __forceinline__ void stream_store(double4 *p, const double4 &v) { stream_store_v<double4, double>(p, v); }
 
+// The particle kernel's work for block bid of the nb blocks given to one
+// run, of which the first nblk_e push electrons and the rest ions.
 template <typename T, int SCHEME>
-__global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
+__device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb, int nblk_e)
 {
     using T4 = typename Vec4<T>::type;
     constexpr int NW = PUSH_THREADS / 64;
@@ -440,9 +442,9 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     T *const tile = lds_q + wid * WAVE_NODES;
-    const int s = ((int)blockIdx.x < P.nblk_e) ? 0 : 1;
-    const int blk = s ? (int)blockIdx.x - P.nblk_e : (int)blockIdx.x;
-    const int nblk = s ? (int)gridDim.x - P.nblk_e : P.nblk_e;
+    const int s = (bid < nblk_e) ? 0 : 1;
+    const int blk = s ? bid - nblk_e : bid;
+    const int nblk = s ? nb - nblk_e : nblk_e;
     int32_t *__restrict__ KEY = P.sp[s].key;
     T *__restrict__ FR = P.sp[s].fr;
     T *__restrict__ FZ = P.sp[s].fz;
@@ -740,6 +742,37 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
     }
 }
 
+template <typename T, int SCHEME>
+__global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
+{
+    push_body<T, SCHEME>(P, (int)blockIdx.x, (int)gridDim.x, P.nblk_e);
+}
+
+// Run of block b in a batched launch: the last run whose first block is at
+// most b.
+template <typename T>
+__device__ inline int batch_run(const PartBatch<T> &B, int b)
+{
+    int lo = 0, hi = B.nruns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The particle kernel of every run of an ensemble in one launch: a block
+// finds its run from the block offsets and reads the run's parameters from
+// the run's descriptor in device memory.
+template <typename T, int SCHEME>
+__global__ void __launch_bounds__(PUSH_THREADS) k_push_b(PartBatch<T> B)
+{
+    const int b = (int)blockIdx.x;
+    const int r = batch_run(B, b);
+    push_body<T, SCHEME>(B.p[r]->push, b - B.off[r], B.off[r + 1] - B.off[r], B.aux[r]);
+}
+
 // ---------------------------------------------------------------------------
 // Events of the step: collisions of the null-collision candidates (queue of
 // electron slots) and secondary emission of the ions absorbed on the cathode
@@ -748,7 +781,7 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push(PushParams<T> P)
 // order does not matter.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_events(EventParams<T> P)
+__device__ void events_body(const EventParams<T> P, int bid, int nb)
 {
     const PushCold<T> *C = P.cold;
     DevScalars *sc = P.sc;
@@ -758,7 +791,7 @@ __global__ void __launch_bounds__(256) k_events(EventParams<T> P)
     unsigned int coll[3] = {0u, 0u, 0u}, see = 0u;
     double dq = 0.0;
     const uint32_t w_e = P.run << 8, w_i = (P.run << 8) | (1u << 4);
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nm + ns; e += gridDim.x * blockDim.x) {
+    for (int e = bid * blockDim.x + threadIdx.x; e < nm + ns; e += nb * blockDim.x) {
         if (e < nm) {
             const int p = P.mcc_q[e].x;
             const SpeciesDev<T> S = P.sp[0];
@@ -793,16 +826,45 @@ __global__ void __launch_bounds__(256) k_events(EventParams<T> P)
         if (coll[q]) atomicAdd(&sc->n_coll[q], (unsigned long long)coll[q]);
     if (see) atomicAdd(&sc->n_see, (unsigned long long)see);
     if (dq != 0.0) atomic_add_dev(&sc->dq_conv, dq);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         sc->n_cand = (unsigned long long)nm;
         if (sc->n_mcc_q > P.ev_cap || sc->n_see_q > P.ev_cap) atomicOr(&sc->flags, FLAG_CHILD_OVERFLOW);
     }
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) k_events(EventParams<T> P)
+{
+    events_body<T>(P, (int)blockIdx.x, (int)gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_events_b(PartBatch<T> B)
+{
+    const int b = (int)blockIdx.x;
+    const int r = batch_run(B, b);
+    events_body<T>(B.p[r]->ev, b - B.off[r], B.off[r + 1] - B.off[r]);
+}
+
+template <typename T>
 void launch_events(const EventParams<T> &p, hipStream_t s)
 {
     hipLaunchKernelGGL((k_events<T>), dim3(256), dim3(256), 0, s, p);
+}
+
+template <typename T>
+void launch_events_b(const PartBatch<T> &b, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_events_b<T>), dim3(b.off[b.nruns]), dim3(256), 0, s, b);
+}
+
+template <typename T>
+void launch_push_b(const PartBatch<T> &b, int scheme, hipStream_t s)
+{
+    if (scheme == PIC_EC)
+        hipLaunchKernelGGL((k_push_b<T, PIC_EC>), dim3(b.off[b.nruns]), dim3(PUSH_THREADS), 0, s, b);
+    else
+        hipLaunchKernelGGL((k_push_b<T, PIC_MC>), dim3(b.off[b.nruns]), dim3(PUSH_THREADS), 0, s, b);
 }
 
 template <typename T>
@@ -822,13 +884,12 @@ void launch_push(const PushParams<T> &p, int scheme, int nblocks, hipStream_t s)
 // next_id[s] + rank; its charge is deposited with global atomics.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) k_children(ChildParams<T> P)
+__device__ void children_body(const ChildParams<T> P, int bid, int nb, unsigned long long *tk,
+                              int *ts)
 {
-    __shared__ unsigned long long tk[256];
-    __shared__ int ts[256];
     const int n = min(P.sc->n_child, P.child_cap);
     const int ldn = P.nr + 1;
-    for (int base = blockIdx.x * 256; base < n; base += gridDim.x * 256) {
+    for (int base = bid * 256; base < n; base += nb * 256) {
         const int c = base + threadIdx.x;
         unsigned long long my = ~0ull;
         int ms = -1;
@@ -873,6 +934,24 @@ __global__ void __launch_bounds__(256) k_children(ChildParams<T> P)
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) k_children(ChildParams<T> P)
+{
+    __shared__ unsigned long long tk[256];
+    __shared__ int ts[256];
+    children_body<T>(P, (int)blockIdx.x, (int)gridDim.x, tk, ts);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_children_b(PartBatch<T> B)
+{
+    __shared__ unsigned long long tk[256];
+    __shared__ int ts[256];
+    const int b = (int)blockIdx.x;
+    const int r = batch_run(B, b);
+    children_body<T>(B.p[r]->ch, b - B.off[r], B.off[r + 1] - B.off[r], tk, ts);
+}
+
+template <typename T>
 void launch_children(const ChildParams<T> &p, hipStream_t s)
 {
     int blocks = (p.child_cap + 255) / 256;
@@ -880,11 +959,21 @@ void launch_children(const ChildParams<T> &p, hipStream_t s)
     hipLaunchKernelGGL((k_children<T>), dim3(blocks), dim3(256), 0, s, p);
 }
 
+int children_b_blocks(int32_t child_cap)
+{
+    return std::max(1, std::min(64, (child_cap + 255) / 256));
+}
+
+template <typename T>
+void launch_children_b(const PartBatch<T> &b, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_children_b<T>), dim3(b.off[b.nruns]), dim3(256), 0, s, b);
+}
+
 // Counts and id counters advance by the children of the step; the step
 // counter advances.
-__global__ void k_finalize_step(DevScalars *sc, int64_t cap0, int64_t cap1)
+__device__ void finalize_body(DevScalars *sc, int64_t cap0, int64_t cap1)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const int64_t cap[2] = {cap0, cap1};
     for (int s = 0; s < 2; ++s) {
         int64_t c = sc->count[s] + sc->n_child_s[s];
@@ -900,20 +989,43 @@ __global__ void k_finalize_step(DevScalars *sc, int64_t cap0, int64_t cap1)
     sc->step += 1;
 }
 
+__global__ void k_finalize_step(DevScalars *sc, int64_t cap0, int64_t cap1)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    finalize_body(sc, cap0, cap1);
+}
+
+// one thread per run
+template <typename T>
+__global__ void k_finalize_b(PartBatch<T> B)
+{
+    const int r = (int)threadIdx.x;
+    if (r >= B.nruns) return;
+    const ChildParams<T> &C = B.p[r]->ch;
+    finalize_body(C.sc, C.cap[0], C.cap[1]);
+}
+
 void launch_finalize_step(DevScalars *sc, const int64_t cap[2], hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize_step, dim3(1), dim3(64), 0, s, sc, cap[0], cap[1]);
 }
 
-// Zero the deposit targets and the per-step tallies.
-__global__ void k_begin_step(DevScalars *sc, uint32_t *q0, uint32_t *q1, int64_t words)
+template <typename T>
+void launch_finalize_b(const PartBatch<T> &b, hipStream_t s)
 {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < words;
-         k += (int64_t)gridDim.x * blockDim.x) {
+    hipLaunchKernelGGL((k_finalize_b<T>), dim3(1), dim3(MAX_BATCH), 0, s, b);
+}
+
+// Zero the deposit targets and the per-step tallies.
+__device__ void begin_body(DevScalars *sc, uint32_t *q0, uint32_t *q1, int64_t words, int bid,
+                           int nb)
+{
+    for (int64_t k = (int64_t)bid * blockDim.x + threadIdx.x; k < words;
+         k += (int64_t)nb * blockDim.x) {
         q0[k] = 0u;
         q1[k] = 0u;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         sc->dq_conv = 0.0;
         sc->ke[0] = sc->ke[1] = 0.0;
         sc->pz[0] = sc->pz[1] = 0.0;
@@ -924,6 +1036,34 @@ __global__ void k_begin_step(DevScalars *sc, uint32_t *q0, uint32_t *q1, int64_t
         sc->n_see = 0;
         sc->deposit_fallback = 0;
     }
+}
+
+__global__ void k_begin_step(DevScalars *sc, uint32_t *q0, uint32_t *q1, int64_t words)
+{
+    begin_body(sc, q0, q1, words, (int)blockIdx.x, (int)gridDim.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_begin_b(PartBatch<T> B)
+{
+    const int b = (int)blockIdx.x;
+    const int r = batch_run(B, b);
+    const PushParams<T> &P = B.p[r]->push;
+    const int64_t words = (int64_t)(P.nr + 1) * (P.nz + 1) * (int64_t)(sizeof(T) / 4);
+    begin_body(P.sc, (uint32_t *)P.q[0], (uint32_t *)P.q[1], words, b - B.off[r],
+               B.off[r + 1] - B.off[r]);
+}
+
+int begin_b_blocks(int64_t nodes, int elem_bytes)
+{
+    const int64_t words = nodes * elem_bytes / 4;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(512, (words + 255) / 256));
+}
+
+template <typename T>
+void launch_begin_b(const PartBatch<T> &b, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_begin_b<T>), dim3(b.off[b.nruns]), dim3(256), 0, s, b);
 }
 
 void launch_begin_step(DevScalars *sc, void *q0, void *q1, int64_t nodes, int elem_bytes,
@@ -979,6 +1119,16 @@ void launch_load(SpeciesDev<T> sp, int64_t offset, const double *r, const double
 
 template void launch_push<float>(const PushParams<float> &, int, int, hipStream_t);
 template void launch_push<double>(const PushParams<double> &, int, int, hipStream_t);
+template void launch_push_b<float>(const PartBatch<float> &, int, hipStream_t);
+template void launch_push_b<double>(const PartBatch<double> &, int, hipStream_t);
+template void launch_begin_b<float>(const PartBatch<float> &, hipStream_t);
+template void launch_begin_b<double>(const PartBatch<double> &, hipStream_t);
+template void launch_events_b<float>(const PartBatch<float> &, hipStream_t);
+template void launch_events_b<double>(const PartBatch<double> &, hipStream_t);
+template void launch_children_b<float>(const PartBatch<float> &, hipStream_t);
+template void launch_children_b<double>(const PartBatch<double> &, hipStream_t);
+template void launch_finalize_b<float>(const PartBatch<float> &, hipStream_t);
+template void launch_finalize_b<double>(const PartBatch<double> &, hipStream_t);
 template void launch_events<float>(const EventParams<float> &, hipStream_t);
 template void launch_events<double>(const EventParams<double> &, hipStream_t);
 template void launch_children<float>(const ChildParams<float> &, hipStream_t);
