@@ -1165,6 +1165,7 @@ struct pic_ensemble {
         hipGraphExec_t exec;
     };
     std::vector<G> graphs;
+    hipGraphExec_t pass_exec = nullptr; // a further solve pass (runs not yet converged)
     std::vector<int64_t> captured;      // particles per run when the graphs were captured
     std::string err;
 };
@@ -1194,6 +1195,8 @@ void drop_ensemble_graphs(pic_ensemble *e)
 {
     for (auto &g : e->graphs) (void)hipGraphExecDestroy(g.exec);
     e->graphs.clear();
+    if (e->pass_exec) (void)hipGraphExecDestroy(e->pass_exec);
+    e->pass_exec = nullptr;
 }
 
 // A run's RunParticles for the four pairs of current particle buffers, into
@@ -1277,6 +1280,48 @@ void particle_phase_b(pic_ensemble *e, size_t b)
     launch_finalize_b<T>(Bb, e->s0);
 }
 
+// One device-gated multigrid-PCG pass of n iterations for the runs of batch
+// b that have not converged, then circuit and gather fields of the runs
+// converged and not yet finished (the status copy marks them finished).
+void enqueue_pass_b(pic_ensemble *e, size_t b, int n, hipStream_t s)
+{
+    const BatchPlan &P = e->plans[b];
+    launch_nodes_b(P, BATCH_CAST_SCALE, s);
+    launch_scalars_b(P, BATCH_ZERO_PCG_GATED, 0, s);
+    launch_mg_vcycle_b(P, 0, s);
+    for (int k = 0; k < n; ++k) {
+        launch_cg_matvec_b(P, k, s);
+        launch_cg_update_b(P, k, s);
+        if (k + 1 < n) launch_mg_vcycle_b(P, k + 1, s);
+    }
+    launch_nodes_b(P, BATCH_UPDATE64, s);
+    launch_scalars_b(P, BATCH_ZERO_RES_GATED, 0, s);
+    launch_residual64_b(P, 1, s);
+    launch_scalars_b(P, BATCH_SOLVE_GATE, n, s);
+    launch_circuit_b(P, s);
+    launch_nodes_b(P, BATCH_FIELD_PREP, s);
+    launch_status_b(P, e->status_dev + b * MAX_BATCH, s);
+}
+
+// The further pass of an ensemble step, launched only when a run has not
+// converged after the step's first pass.
+pic_status capture_pass(pic_ensemble *e, int n)
+{
+    EHIPCHECK(e, hipStreamBeginCapture(e->s0, hipStreamCaptureModeThreadLocal));
+    for (size_t b = 0; b < e->plans.size(); ++b) enqueue_pass_b(e, b, n, e->s0);
+    hipGraph_t graph;
+    const hipError_t ec = hipStreamEndCapture(e->s0, &graph);
+    if (ec != hipSuccess)
+        return efail(e, PIC_EHIP, "capture of the ensemble pass failed: %s", hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&e->pass_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        e->pass_exec = nullptr;
+        return efail(e, PIC_EHIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    return PIC_OK;
+}
+
 // Capture one step of every run: in a sort step the per-run sorts on the
 // ensemble's streams (round robin), then for each batch of up to MAX_BATCH
 // runs one launch per particle kernel, the batched field update and a status
@@ -1301,7 +1346,11 @@ pic_status capture_ensemble(pic_ensemble *e, bool do_sort, hipGraphExec_t *out)
         const int n = (int)std::ceil(std::log(target) / std::log(rho));
         return std::max(1, std::min(n, 64));
     };
-    const int plan[3] = {iters(std::max(0.5 * rtol / rel0, 1e-6)), iters(1e-6), iters(1e-6)};
+    const int plan[2] = {iters(std::max(0.5 * rtol / rel0, 1e-6)), iters(1e-6)};
+    if (!e->pass_exec) {
+        pic_status st = capture_pass(e, plan[1]);
+        if (st != PIC_OK) return st;
+    }
     EHIPCHECK(e, hipStreamBeginCapture(e->s0, hipStreamCaptureModeThreadLocal));
     auto join = [&]() {
         for (int k = 0; k < ns; ++k) {
@@ -1329,8 +1378,8 @@ pic_status capture_ensemble(pic_ensemble *e, bool do_sort, hipGraphExec_t *out)
         else particle_phase_b<float>(e, b);
     }
     // field update of every run, batched: extrapolated warm start, FP64
-    // residual, up to three device-gated multigrid-PCG passes, circuit,
-    // gather fields, status
+    // residual, the first device-gated multigrid-PCG pass, then circuit,
+    // gather fields and status of the runs it converged
     hipStream_t s = e->s0;
     for (size_t b = 0; b < e->plans.size(); ++b) {
         const BatchPlan &P = e->plans[b];
@@ -1340,24 +1389,7 @@ pic_status capture_ensemble(pic_ensemble *e, bool do_sort, hipGraphExec_t *out)
         launch_residual64_b(P, 0, s);
         launch_scalars_b(P, BATCH_SOLVE_INIT, 0, s);
         launch_nodes_b(P, BATCH_ZERO_IF_EMPTY, s);
-        for (int p = 0; p < 3; ++p) {
-            const int n = plan[p];
-            launch_nodes_b(P, BATCH_CAST_SCALE, s);
-            launch_scalars_b(P, BATCH_ZERO_PCG_GATED, 0, s);
-            launch_mg_vcycle_b(P, 0, s);
-            for (int k = 0; k < n; ++k) {
-                launch_cg_matvec_b(P, k, s);
-                launch_cg_update_b(P, k, s);
-                if (k + 1 < n) launch_mg_vcycle_b(P, k + 1, s);
-            }
-            launch_nodes_b(P, BATCH_UPDATE64, s);
-            launch_scalars_b(P, BATCH_ZERO_RES_GATED, 0, s);
-            launch_residual64_b(P, 1, s);
-            launch_scalars_b(P, BATCH_SOLVE_GATE, n, s);
-        }
-        launch_circuit_b(P, s);
-        launch_nodes_b(P, BATCH_FIELD_PREP, s);
-        launch_status_b(P, e->status_dev + b * MAX_BATCH, s);
+        enqueue_pass_b(e, b, plan[0], s);
     }
     hipGraph_t graph;
     const hipError_t ec = hipStreamEndCapture(e->s0, &graph);
@@ -1394,6 +1426,15 @@ pic_status ensemble_step(pic_ensemble *e)
     for (pic_handle *h : e->runs) EHIPCHECK(e, hipStreamSynchronize(h->stream));
     EHIPCHECK(e, hipGraphLaunch(exec, e->s0));
     EHIPCHECK(e, hipStreamSynchronize(e->s0));
+    // up to two further passes while some run has not converged
+    for (int p = 1; p < 3; ++p) {
+        bool open = false;
+        for (size_t r = 0; r < e->runs.size(); ++r)
+            open |= e->status[(r / MAX_BATCH) * MAX_BATCH + r % MAX_BATCH].solve_done == 0;
+        if (!open) break;
+        EHIPCHECK(e, hipGraphLaunch(e->pass_exec, e->s0));
+        EHIPCHECK(e, hipStreamSynchronize(e->s0));
+    }
     bool drift = false;
     for (size_t r = 0; r < e->runs.size(); ++r) {
         pic_handle *h = e->runs[r];

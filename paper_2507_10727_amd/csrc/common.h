@@ -67,7 +67,8 @@ struct DevScalars {
     double pcg_ss[MAX_PCG + 2];     // sum r^2 of each learned-preconditioner input
     // device-controlled solve of a captured step: done flag (gates the pass
     // kernels), passes and iterations run
-    int32_t solve_done, solve_passes, solve_iters, solve_pad;
+    int32_t solve_done, solve_passes, solve_iters;
+    int32_t post_done;          // ensembles: circuit and gather fields done this step
     // a single run's FP64 residual norms^2 (||r||^2, ||b||^2) in ACC_SLOTS
     // slots each, summed by their readers (the cast kernel, the host)
     double res_slots[2 * ACC_SLOTS * ACC_STRIDE];

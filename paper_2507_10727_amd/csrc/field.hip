@@ -437,6 +437,8 @@ __global__ void __launch_bounds__(FB) k_nodes_b(BatchArgs a)
             update64_body(nn, f.kind, f.phi0, f.e32, R.sc, R.inv_2pi_eps0, f.gate, blk, nblk);
             break;
         default:
+            // runs whose solve has converged and whose step is not finished
+            if (!R.sc->solve_done || R.sc->post_done) return;
             field_prep_body<T>(f.nr, f.nz, f.dr, f.dz, f.phi, f.phi0, f.phi_l, f.b_r, f.b_z,
                                (typename Vec4<T>::type *)R.node, R.sc, R.scheme, 0, blk, nblk);
             break;
@@ -460,6 +462,7 @@ __global__ void k_scalars_b(BatchArgs a)
             if (threadIdx.x == 0) {
                 const double rr = sc->res_rr, bb = sc->res_bb;
                 sc->solve_done = (bb == 0.0 || rr <= R.rtol2 * bb) ? 1 : 0;
+                sc->post_done = 0;
                 sc->solve_passes = 0;
                 sc->solve_iters = 0;
             }
@@ -495,6 +498,7 @@ __global__ void k_circuit_b(BatchArgs a)
 {
     const RunSolve &R = *a.run[blockIdx.x];
     const FieldDev &f = R.f;
+    if (!R.sc->solve_done || R.sc->post_done) return;
     circuit_body<T>(f.nr, f.ce64, f.cn64, f.kind, f.phi0, (const T *)R.q0, (const T *)R.q1, R.sc,
                     R.circuit, R.v_fixed, R.v_ext, R.r_ext, R.dt, R.extra_dq, 0, 1);
 }
@@ -503,7 +507,8 @@ __global__ void k_status_b(BatchArgs a, RunStatus *out)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.nruns) return;
-    const DevScalars *sc = a.run[r]->sc;
+    DevScalars *sc = a.run[r]->sc;
+    if (sc->solve_done) sc->post_done = 1;
     RunStatus s;
     s.rr = sc->res_rr;
     s.bb = sc->res_bb;

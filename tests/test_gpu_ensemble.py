@@ -17,9 +17,9 @@ from paper_2507_10727_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def sweep(n_runs, scale, sort_every=3):
+def sweep(n_runs, scale, sort_every=3, rtol=1e-8):
     ps = W.ensemble_problems(n_runs=n_runs, scale=scale)
-    return [p.replace(sort_every=sort_every, poisson_rtol=1e-8) for p in ps]
+    return [p.replace(sort_every=sort_every, poisson_rtol=rtol) for p in ps]
 
 
 def make(ps):
@@ -30,16 +30,25 @@ def make(ps):
     return sims
 
 
-def test_ensemble_equals_sequential():
+@pytest.mark.parametrize("rtol", [1e-8, 1e-11])
+def test_ensemble_equals_sequential(rtol):
+    """At 1e-11 the first solve pass of a step leaves runs short of the
+    tolerance, so the ensemble's further-pass graph runs as well."""
     from paper_2507_10727_amd.sim import Ensemble
-    ps = sweep(5, 0.05)
-    say("case ensemble", [(p.nr, p.n_per_species, p.gamma_i, p.r_ext) for p in ps])
+    ps = sweep(5, 0.05, rtol=rtol)
+    say("case ensemble rtol", rtol, [(p.nr, p.n_per_species, p.gamma_i, p.r_ext) for p in ps])
     alone = make(ps)
     for s in alone:
         s.step(7)
     batch = make(ps)
     ens = Ensemble(batch, nstreams=3)
-    ens.step(7)
+    passes = []
+    for _ in range(7):
+        ens.step(1)
+        passes += [b.diag()["poisson"]["outer"] for b in batch]
+    say("solve passes per run and step", passes)
+    if rtol < 1e-10:
+        assert max(passes) >= 2
     for k, (a, b) in enumerate(zip(alone, batch)):
         da, db = a.diag(), b.diag()
         say(f"run {k}: counts {da['count']} / {db['count']}, coll {da['n_coll']} / {db['n_coll']}, "
@@ -49,7 +58,7 @@ def test_ensemble_equals_sequential():
         assert da["count"] == db["count"]
         assert da["n_coll"] == db["n_coll"] and da["n_see"] == db["n_see"]
         assert da["n_abs"] == db["n_abs"]
-        assert db["poisson"]["converged"] == 1 and db["poisson"]["rel_res"] <= 1e-8
+        assert db["poisson"]["converged"] == 1 and db["poisson"]["rel_res"] <= rtol
         assert abs(da["vc"] - db["vc"]) <= 1e-6 * abs(da["vc"])
         fa, fb = a.fields_host(), b.fields_host()
         assert np.abs(fa["phi"] - fb["phi"]).max() <= 1e-6 * np.abs(fa["phi"]).max()
