@@ -30,25 +30,7 @@ def make(ps):
     return sims
 
 
-@pytest.mark.parametrize("rtol", [1e-8, 1e-11])
-def test_ensemble_equals_sequential(rtol):
-    """At 1e-11 the first solve pass of a step leaves runs short of the
-    tolerance, so the ensemble's further-pass graph runs as well."""
-    from paper_2507_10727_amd.sim import Ensemble
-    ps = sweep(5, 0.05, rtol=rtol)
-    say("case ensemble rtol", rtol, [(p.nr, p.n_per_species, p.gamma_i, p.r_ext) for p in ps])
-    alone = make(ps)
-    for s in alone:
-        s.step(7)
-    batch = make(ps)
-    ens = Ensemble(batch, nstreams=3)
-    passes = []
-    for _ in range(7):
-        ens.step(1)
-        passes += [b.diag()["poisson"]["outer"] for b in batch]
-    say("solve passes per run and step", passes)
-    if rtol < 1e-10:
-        assert max(passes) >= 2
+def assert_same(ps, alone, batch, rtol):
     for k, (a, b) in enumerate(zip(alone, batch)):
         da, db = a.diag(), b.diag()
         say(f"run {k}: counts {da['count']} / {db['count']}, coll {da['n_coll']} / {db['n_coll']}, "
@@ -71,10 +53,49 @@ def test_ensemble_equals_sequential(rtol):
             assert np.abs(pa["z"][ia] - pb["z"][ib]).max() <= 1e-5 * dr
             same_cell = np.mean(pa["key"][ia] == pb["key"][ib])
             assert same_cell >= 1 - 1e-4
+
+
+@pytest.mark.parametrize("rtol", [1e-8, 1e-11])
+def test_ensemble_equals_sequential(rtol):
+    """At 1e-11 the first solve pass of a step leaves runs short of the
+    tolerance, so the ensemble's further-pass graph runs as well."""
+    from paper_2507_10727_amd.sim import Ensemble
+    ps = sweep(5, 0.05, rtol=rtol)
+    say("case ensemble rtol", rtol, [(p.nr, p.n_per_species, p.gamma_i, p.r_ext) for p in ps])
+    alone = make(ps)
+    for s in alone:
+        s.step(7)
+    batch = make(ps)
+    ens = Ensemble(batch, nstreams=3)
+    passes = []
+    for _ in range(7):
+        ens.step(1)
+        passes += [b.diag()["poisson"]["outer"] for b in batch]
+    say("solve passes per run and step", passes)
+    if rtol < 1e-10:
+        assert max(passes) >= 2
+    assert_same(ps, alone, batch, rtol)
     ens.close()
     # the runs stay usable on their own afterwards
     batch[0].step(1)
     assert batch[0].diag()["step"] == 8
+
+
+def test_ensemble_mixed_schemes_f64():
+    """FP64 state (the double forms of the batched particle kernels) and a
+    batch mixing EC- and MC-PIC runs, whose pushes are launched run by run."""
+    from paper_2507_10727_amd.sim import Ensemble
+    ps = [p.replace(precision=W.F64, scheme=(W.MC_PIC if k % 2 else W.EC_PIC))
+          for k, p in enumerate(sweep(4, 0.02))]
+    say("case ensemble f64 mixed", [(p.nr, p.n_per_species, p.scheme) for p in ps])
+    alone = make(ps)
+    for s in alone:
+        s.step(7)
+    batch = make(ps)
+    ens = Ensemble(batch, nstreams=2)
+    ens.step(7)
+    assert_same(ps, alone, batch, 1e-8)
+    ens.close()
 
 
 def test_ensemble_rejects_mixed_sort_interval():
