@@ -1286,13 +1286,21 @@ void particle_phase_b(pic_ensemble *e, size_t b)
 void enqueue_pass_b(pic_ensemble *e, size_t b, int n, hipStream_t s)
 {
     const BatchPlan &P = e->plans[b];
-    launch_nodes_b(P, BATCH_CAST_SCALE, s);
-    launch_scalars_b(P, BATCH_ZERO_PCG_GATED, 0, s);
-    launch_mg_vcycle_b(P, 0, s);
-    for (int k = 0; k < n; ++k) {
-        launch_cg_matvec_b(P, k, s);
-        launch_cg_update_b(P, k, s);
-        if (k + 1 < n) launch_mg_vcycle_b(P, k + 1, s);
+    if (batch_fused_cg(P)) {
+        // CG vector work in the finest level's V-cycle kernels (the cast
+        // clears the pass's slotted dots)
+        launch_nodes_b(P, BATCH_CAST_SCALE_CG, s, n);
+        for (int k = 0; k < n; ++k) launch_mg_vcycle_cg_b(P, k, s);
+        launch_cg_update_last_b(P, n - 1, s);
+    } else {
+        launch_nodes_b(P, BATCH_CAST_SCALE, s);
+        launch_scalars_b(P, BATCH_ZERO_PCG_GATED, 0, s);
+        launch_mg_vcycle_b(P, 0, s);
+        for (int k = 0; k < n; ++k) {
+            launch_cg_matvec_b(P, k, s);
+            launch_cg_update_b(P, k, s);
+            if (k + 1 < n) launch_mg_vcycle_b(P, k + 1, s);
+        }
     }
     launch_nodes_b(P, BATCH_UPDATE64, s);
     launch_scalars_b(P, BATCH_ZERO_RES_GATED, 0, s);
@@ -1901,6 +1909,15 @@ pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *str
         R.inv_2pi_eps0 = inv_2pi_eps0;
         R.circuit = c.circuit;
         R.scheme = c.scheme;
+        R.cg.r[0] = h->f.mg.lv[0].b;
+        R.cg.r[1] = h->f.r32b;
+        R.cg.q[0] = h->f.q32;
+        R.cg.q[1] = h->f.q32b;
+        R.cg.w = h->f.w32;
+        R.cg.p = h->f.p32[0];
+        R.cg.e = h->f.e32;
+        R.cg.acc = h->f.cg_acc;
+        R.cg.pq = h->sc->pcg_pq;
         if ((const char *)h->rsolve + sizeof(RunSolve) > h->ws + h->ws_bytes) {
             pic_ensemble_free(e);
             return efail(nullptr, PIC_EINVAL, "run %d: no room for the run descriptor", r);

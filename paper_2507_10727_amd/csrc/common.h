@@ -531,6 +531,7 @@ struct RunSolve {
     double rtol2;
     double v_fixed, v_ext, r_ext, dt, extra_dq, inv_2pi_eps0;
     int32_t circuit, scheme;
+    CgVecs cg;                  // the run's CG vectors of the fused V-cycle
 };
 
 // Kernel argument of a batched launch: the runs and the first block of each.
@@ -564,13 +565,19 @@ struct BatchPlan {
 void launch_mg_vcycle_b(const BatchPlan &P, int k, hipStream_t s);
 void launch_cg_matvec_b(const BatchPlan &P, int k, hipStream_t s);
 void launch_cg_update_b(const BatchPlan &P, int k, hipStream_t s);
+// the fused forms (CG vector work in the finest level's V-cycle kernels) for
+// batches whose every run has a finest level outside the coarse tail
+bool batch_fused_cg(const BatchPlan &P);
+void launch_mg_vcycle_cg_b(const BatchPlan &P, int k, hipStream_t s);
+void launch_cg_update_last_b(const BatchPlan &P, int k, hipStream_t s);
 // node-wise field operations of every run (op: BATCH_*), gated ones skip
-// runs whose solve is done
+// runs whose solve is done; BATCH_CAST_SCALE_CG also clears the slotted dots
+// of n_iter fused CG iterations
 enum : int32_t {
     BATCH_EXTRAPOLATE = 0, BATCH_SET_DIRICHLET = 1, BATCH_ZERO_IF_EMPTY = 2,
-    BATCH_CAST_SCALE = 3, BATCH_UPDATE64 = 4, BATCH_FIELD_PREP = 5
+    BATCH_CAST_SCALE = 3, BATCH_UPDATE64 = 4, BATCH_FIELD_PREP = 5, BATCH_CAST_SCALE_CG = 6
 };
-void launch_nodes_b(const BatchPlan &P, int op, hipStream_t s);
+void launch_nodes_b(const BatchPlan &P, int op, hipStream_t s, int n_iter = 0);
 // per-run scalar operations (one block per run)
 enum : int32_t {
     BATCH_ZERO_RES = 0, BATCH_ZERO_RES_GATED = 1, BATCH_SOLVE_INIT = 2, BATCH_SOLVE_GATE = 3,

@@ -436,6 +436,10 @@ __global__ void __launch_bounds__(FB) k_nodes_b(BatchArgs a)
         case BATCH_UPDATE64:
             update64_body(nn, f.kind, f.phi0, f.e32, R.sc, R.inv_2pi_eps0, f.gate, blk, nblk);
             break;
+        case BATCH_CAST_SCALE_CG:
+            cast_scale_body(nn, f.r64, R.sc, f.mg.lv[0].b, f.e32, f.gate, blk, nblk, R.cg.acc,
+                            (int64_t)a.n_iter * CG_ACC_PER_ITER);
+            break;
         default:
             // runs whose solve has converged and whose step is not finished
             if (!R.sc->solve_done || R.sc->post_done) return;
@@ -671,9 +675,10 @@ template void launch_circuit<float>(const FieldDev &, const float *, const float
 template void launch_circuit<double>(const FieldDev &, const double *, const double *,
                                      DevScalars *, int, double, double, double, double, double,
                                      hipStream_t);
-void launch_nodes_b(const BatchPlan &P, int op, hipStream_t s)
+void launch_nodes_b(const BatchPlan &P, int op, hipStream_t s, int n_iter)
 {
-    const BatchArgs a = node_args(P, op);
+    BatchArgs a = node_args(P, op);
+    a.n_iter = n_iter;
     if (P.prec == PIC_F64)
         hipLaunchKernelGGL(k_nodes_b<double>, dim3(a.off[P.nruns]), dim3(FB), 0, s, a);
     else

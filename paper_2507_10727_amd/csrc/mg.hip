@@ -482,7 +482,9 @@ __device__ __forceinline__ void mg_down_cg_body(const MGLevel &F, const MGLevel 
     }
     // issued after the tile's loads: they complete in order, so the scalars'
     // wait is the tile's
+    const int32_t gated = gate_load(F.gate);
     const CgScalars cs = cg_scalars(v, j);
+    if (gated) return;   // uniform: the whole block leaves before its first barrier
 #pragma unroll
     for (int u = 0; u < DN; ++u) {
         const int t = threadIdx.x + 256 * u;
@@ -562,6 +564,8 @@ __device__ __forceinline__ void mg_up_cg_body(const MGLevel &F, const MGLevel &C
         const int i = i0 + t % UTX, jj = j0 + t / UTX;
         ql[o] = qold[(i <= F.nr && jj <= F.nz) ? (int64_t)jj * ld + i : 0];
     }
+    const int32_t gated = gate_load(F.gate);
+    if (gated) return;   // uniform: the whole block leaves before its first barrier
 #pragma unroll
     for (int u = 0; u < UCN; ++u) {
         const int t = threadIdx.x + 256 * u;
@@ -989,7 +993,9 @@ __device__ __forceinline__ void cg_update_last_body(const MGLevel &L, const CgVe
                                                     int blk, int nblk)
 {
     __shared__ double red[CB / 64];
+    const int32_t gated = gate_load(L.gate);
     const CgScalars cs = cg_scalars(v, j);
+    if (gated) return;   // uniform: the whole block leaves before its first barrier
     const float *rold = v.r[j & 1], *qold = v.q[(j + 1) & 1];
     const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
     double acc = 0.0;
@@ -1094,6 +1100,36 @@ __global__ void __launch_bounds__(1024) k_mg_tail_b(BatchArgs a)
     extern __shared__ float sm[];
     const RunSolve &R = *a.run[blockIdx.x];
     mg_tail_body(R.f.mg.tail, R.f.mg.tail.first == 0 ? &R.sc->pcg_rz[a.k] : nullptr, sm);
+}
+
+// fused forms: F.b of the finest level is r[k & 1] of the run's CG vectors
+// (r[0] is the level's own b, so iteration 0 goes down with k_mg_down_b)
+__global__ void __launch_bounds__(256) k_mg_down_cg_b(BatchArgs a)
+{
+    const int r = batch_run(a);
+    const RunSolve &R = *a.run[r];
+    MGLevel F = R.f.mg.lv[0];
+    F.b = R.cg.r[a.k & 1];
+    const MGLevel &C = R.f.mg.lv[1];
+    const int lb = blockIdx.x - a.off[r], tx = (C.nr + 1 + DTX - 1) / DTX;
+    mg_down_cg_body(F, C, R.cg, a.k - 1, lb % tx, lb / tx);
+}
+
+__global__ void __launch_bounds__(256) k_mg_up_cg_b(BatchArgs a)
+{
+    const int r = batch_run(a);
+    const RunSolve &R = *a.run[r];
+    MGLevel F = R.f.mg.lv[0];
+    F.b = R.cg.r[a.k & 1];
+    const int lb = blockIdx.x - a.off[r], tx = (F.nr + 1 + UTX - 1) / UTX;
+    mg_up_cg_body(F, R.f.mg.lv[1], R.cg, a.k, lb % tx, lb / tx);
+}
+
+__global__ void __launch_bounds__(CB) k_cg_update_last_b(BatchArgs a)
+{
+    const int r = batch_run(a);
+    const RunSolve &R = *a.run[r];
+    cg_update_last_body(R.f.mg.lv[0], R.cg, a.k, blockIdx.x - a.off[r], a.off[r + 1] - a.off[r]);
 }
 
 __global__ void __launch_bounds__(CB) k_cg_matvec_b(BatchArgs a)
@@ -1270,6 +1306,73 @@ void launch_mg_vcycle_b(const BatchPlan &P, int k, hipStream_t s)
         if (a.off[P.nruns] > 0)
             hipLaunchKernelGGL(k_mg_up_b, dim3(a.off[P.nruns]), dim3(256), 0, s, a);
     }
+}
+
+bool batch_fused_cg(const BatchPlan &P)
+{
+    for (int r = 0; r < P.nruns; ++r)
+        if (P.host[r].tail.first < 1) return false;
+    return true;
+}
+
+// The middle levels (1 .. first - 1 of each run) one kernel per level, as in
+// the unfused V-cycle; the finest level's down and up kernels carry the CG
+// vector work of iterations k - 1 and k.
+void launch_mg_vcycle_cg_b(const BatchPlan &P, int k, hipStream_t s)
+{
+    BatchArgs a = batch_args(P);
+    a.k = k;
+    int lmax = 0, tail_lds = 0;
+    for (int r = 0; r < P.nruns; ++r) {
+        lmax = std::max(lmax, (int)P.host[r].tail.first);
+        tail_lds = std::max(tail_lds, (int)P.host[r].tail_lds_bytes);
+    }
+    for (int r = 0; r < P.nruns; ++r) {
+        const MGLevel &C = P.host[r].lv[1];
+        a.off[r + 1] = a.off[r] + ((C.nr + 1 + DTX - 1) / DTX) * ((C.nz + 1 + DTY - 1) / DTY);
+    }
+    if (k == 0) hipLaunchKernelGGL(k_mg_down_b, dim3(a.off[P.nruns]), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_mg_down_cg_b, dim3(a.off[P.nruns]), dim3(256), 0, s, a);
+    for (int l = 1; l < lmax; ++l) {
+        a.level = l;
+        for (int r = 0; r < P.nruns; ++r) {
+            const MGHier &H = P.host[r];
+            int nb = 0;
+            if (l < H.tail.first)
+                nb = ((H.lv[l + 1].nr + 1 + DTX - 1) / DTX) * ((H.lv[l + 1].nz + 1 + DTY - 1) / DTY);
+            a.off[r + 1] = a.off[r] + nb;
+        }
+        if (a.off[P.nruns] > 0)
+            hipLaunchKernelGGL(k_mg_down_b, dim3(a.off[P.nruns]), dim3(256), 0, s, a);
+    }
+    for (int r = 0; r <= P.nruns; ++r) a.off[r] = r;
+    hipLaunchKernelGGL(k_mg_tail_b, dim3(P.nruns), dim3(TT, TT), tail_lds, s, a);
+    for (int l = lmax - 1; l >= 1; --l) {
+        a.level = l;
+        for (int r = 0; r < P.nruns; ++r) {
+            const MGHier &H = P.host[r];
+            int nb = 0;
+            if (l < H.tail.first)
+                nb = ((H.lv[l].nr + 1 + UTX - 1) / UTX) * ((H.lv[l].nz + 1 + UTY - 1) / UTY);
+            a.off[r + 1] = a.off[r] + nb;
+        }
+        if (a.off[P.nruns] > 0)
+            hipLaunchKernelGGL(k_mg_up_b, dim3(a.off[P.nruns]), dim3(256), 0, s, a);
+    }
+    for (int r = 0; r < P.nruns; ++r) {
+        const MGLevel &F = P.host[r].lv[0];
+        a.off[r + 1] = a.off[r] + ((F.nr + 1 + UTX - 1) / UTX) * ((F.nz + 1 + UTY - 1) / UTY);
+    }
+    hipLaunchKernelGGL(k_mg_up_cg_b, dim3(a.off[P.nruns]), dim3(256), 0, s, a);
+}
+
+void launch_cg_update_last_b(const BatchPlan &P, int k, hipStream_t s)
+{
+    BatchArgs a = batch_args(P);
+    a.k = k;
+    for (int r = 0; r < P.nruns; ++r)
+        a.off[r + 1] = a.off[r] + cg_blocks((int64_t)(P.host[r].lv[0].nr + 1) * (P.host[r].lv[0].nz + 1));
+    hipLaunchKernelGGL(k_cg_update_last_b, dim3(a.off[P.nruns]), dim3(CB), 0, s, a);
 }
 
 void launch_cg_matvec_b(const BatchPlan &P, int k, hipStream_t s)
