@@ -98,6 +98,33 @@ def test_ensemble_mixed_schemes_f64():
     ens.close()
 
 
+def test_ensemble_of_two_batches():
+    """66 runs: two batches of the batched kernels (64 + 2 runs), each with
+    its own particle launches, solve passes and status block; runs of both
+    batches equal the same runs advanced alone."""
+    from paper_2507_10727_amd.sim import Ensemble
+    ps = sweep(66, 0.01)
+    say("case ensemble 66 runs", sum(p.n_per_species for p in ps))
+    batch = make(ps)
+    ens = Ensemble(batch, nstreams=4)
+    ens.step(3)
+    check = [0, 63, 64, 65]
+    alone = make([ps[k] for k in check])
+    for s in alone:
+        s.step(3)
+    for a, k in zip(alone, check):
+        da, db = a.diag(), batch[k].diag()
+        say(f"run {k}: counts {da['count']} / {db['count']}, solve {db['poisson']}")
+        assert da["step"] == db["step"] == 3
+        assert da["count"] == db["count"]
+        assert da["n_coll"] == db["n_coll"] and da["n_see"] == db["n_see"]
+        assert db["poisson"]["converged"] == 1
+        assert abs(da["vc"] - db["vc"]) <= 1e-6 * abs(da["vc"])
+        fa, fb = a.fields_host(), batch[k].fields_host()
+        assert np.abs(fa["phi"] - fb["phi"]).max() <= 1e-6 * np.abs(fa["phi"]).max()
+    ens.close()
+
+
 def test_ensemble_rejects_mixed_sort_interval():
     from paper_2507_10727_amd.sim import Ensemble
     ps = sweep(2, 0.02)
