@@ -335,19 +335,23 @@ pic_status pic_get_tuning(const pic_handle *h, pic_tuning *t);
  * Many runs (each created by pic_init, with its own grid, particles,
  * secondary yield and circuit; Section 4's study varies the yield and the
  * external resistance) advance together: one step of every run is captured
- * once into a hipGraph, its runs spread over nstreams streams, and replayed
- * each step as a single launch, with one synchronization per step for the
- * runs' status.  Inside the graph each field solve is multigrid-
- * preconditioned and controlled on the device (its passes stop once the
- * FP64 residual meets poisson_rtol, at most three passes), so a run advances
- * exactly as pic_step would to within the solve tolerance.  The runs must
- * share sort_every and have timers off; creation cell-sorts every run so
- * that all share one sort phase.  Runs are not used through other calls
- * while pic_ensemble_step runs.  The library owns the
- * streams, graphs and a small pinned status buffer; stream (nullable) is
- * where the graph launches.  Errors of pic_ensemble_step name the run:
- * PIC_ECAPACITY, PIC_ENOCONV, PIC_EHIP.  Each run's descriptor of the
- * batched solve is written into its own workspace at creation. */
+ * once into a hipGraph and replayed each step as a single launch, with one
+ * synchronization per step for the runs' status.  Each kernel of the step
+ * runs once for a batch of up to 64 runs (a block finds its run from block
+ * offsets); the sorts of a sort step run per run, spread over nstreams
+ * streams.  Each field solve is multigrid-preconditioned and controlled on
+ * the device: the step's graph holds its first pass, and while the status
+ * shows a run short of poisson_rtol a captured one-pass graph runs again
+ * (at most two more passes) for the runs not yet converged, so a run
+ * advances exactly as pic_step would to within the solve tolerance.  The
+ * runs must share sort_every and the state precision and have timers off;
+ * creation cell-sorts every run so that all share one sort phase.  Runs are
+ * not used through other calls while pic_ensemble_step runs.  The library
+ * owns the streams, graphs and a small pinned status buffer; stream
+ * (nullable) is where the graphs launch.  Errors of pic_ensemble_step name
+ * the run: PIC_ECAPACITY, PIC_ENOCONV, PIC_EHIP.  Each run's descriptors
+ * (of the batched solve and of its particle kernels) are written into its
+ * own workspace at creation. */
 pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *stream,
                                int32_t nstreams, pic_ensemble **out);
 pic_status pic_ensemble_step(pic_ensemble *e, int32_t nsteps);
