@@ -133,6 +133,59 @@ def poisson_bench(train_seconds=60.0, reps=6):
     return out
 
 
+def gather_forms_bench(workload, steps=100, warmup=20, box_steps=4000, box_every=40):
+    """Both gather forms of the paper (Section 2).  Throughput: the bench
+    workload's full step with each form (EC-PIC is the headline value, MC-PIC
+    the same discharge with the nodal-field gather).  Energy: the closed
+    thermal box (workloads.thermal_box) at the workload's grid, cell and
+    particle count, where the cell is three Debye lengths: EC-PIC's total
+    energy stays bounded, MC-PIC heats (finite-grid instability)."""
+    import numpy as np
+    import torch
+    from paper_2507_10727_amd import workloads as W
+    from paper_2507_10727_amd.sim import Simulation
+    base = W.preset(workload)
+    out = {}
+    for name, scheme in (("ec", W.EC_PIC), ("mc", W.MC_PIC)):
+        p = base.replace(scheme=scheme)
+        br, bz, sig, parts = W.inputs(p)
+        sim = Simulation(p, br, bz, sig, parts)
+        sim.step(warmup)
+        d0 = sim.diag()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        d1 = sim.diag()
+        sim.close()
+        del sim, parts
+        n = 0.5 * (sum(d0["count"]) + sum(d1["count"]))
+        res = {"particle_steps_per_s": n * steps / wall, "ms_per_step": wall / steps * 1e3}
+        ppc = max(1, base.n_per_species // (base.nr * base.nz))
+        bp, bparts = W.thermal_box(base.nr, base.nz, base.dr, ppc, scheme, base.precision)
+        bbr, bbz = W.magnetron_field(bp)
+        sim = Simulation(bp, bbr, bbz, W.cross_sections(bp.e_exc, bp.e_iz), bparts)
+        ke, tot = [], []
+        for _ in range(box_steps // box_every):
+            sim.step(box_every)
+            d = sim.diag()
+            ke.append(d["ke"][0])
+            tot.append(d["ke"][0] + d["w_field"])
+        sim.close()
+        del sim, bparts
+        ke, tot = np.array(ke), np.array(tot)
+        m = max(1, len(ke) // 20)
+        res["box"] = {"grid": f"{bp.nr}x{bp.nz}", "particles_per_species": bp.n_per_species,
+                      "density_m3": bp.density, "dt_s": bp.dt, "steps": box_steps,
+                      "total_energy_drift_max": float(np.abs(tot - tot[0]).max() / tot[0]),
+                      "electron_ke_growth": float(ke[-m:].mean() / ke[:m].mean() - 1.0)}
+        out[name] = res
+        torch.cuda.empty_cache()
+        log(f"[bench] gather form {name}: {res}")
+    return out
+
+
 def ensemble_bench(n_runs=64, steps=10, scale=1.0):
     """The yield / resistance sweep (workloads.ensemble_problems): the runs
     advanced one after another through pic_step, then the same runs advanced
@@ -218,6 +271,8 @@ def main():
     ap.add_argument("--poisson-only", action="store_true",
                     help="only the field-solve comparison (prints its JSON)")
     ap.add_argument("--train-seconds", type=float, default=60.0)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the EC-PIC / MC-PIC throughput and energy comparison")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the batched sweep of 64 runs")
     ap.add_argument("--ensemble-only", action="store_true",
@@ -264,7 +319,8 @@ def main():
     log(f"[bench] init {time.perf_counter() - t0:.1f} s; warmup {args.warmup} steps")
     sim.step(args.warmup)
     d0 = sim.diag()
-    sim.lib.pic_enable_timers(sim.h, 1)
+    # the timed steps time the particle kernel alone (two HIP events a step)
+    sim.lib.pic_enable_timers(sim.h, 2)
     sim.timers(reset=True)
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
@@ -274,6 +330,14 @@ def main():
     wall = time.perf_counter() - t0
     tm = sim.timers(reset=True)
     d1 = sim.diag()
+    # phase breakdown from further steps with every phase timed (the events
+    # around each phase cost time of their own, so they stay out of the
+    # timed steps); one cell sort falls in every sort_every steps
+    n_ph = max(p.sort_every, 20)
+    sim.lib.pic_enable_timers(sim.h, 1)
+    sim.step(n_ph)
+    tm_all = sim.timers(reset=True)
+    sim.lib.pic_enable_timers(sim.h, 0)
     n0 = d0["count"][0] + d0["count"][1]
     n1 = d1["count"][0] + d1["count"][1]
     nmean = 0.5 * (n0 + n1)
@@ -289,8 +353,9 @@ def main():
             "kernel": "k_push (gather+Boris+walls+SEE+MCC+deposit)",
             "avg_ms": push_avg_ms, "launches": tm["push_launches"],
             "algorithmic_bytes_per_launch": algo_bytes}
-    phases = {k: tm[k] / args.steps for k in ("push_ms", "children_ms", "sort_ms", "poisson_ms",
-                                              "circuit_ms", "field_ms")}
+    phases = {k: tm_all[k] / n_ph for k in ("push_ms", "children_ms", "sort_ms", "poisson_ms",
+                                            "circuit_ms", "field_ms")}
+    phases["steps"] = n_ph
     log(f"[bench] {value:.3e} particle-steps/s, {wall / args.steps * 1e3:.3f} ms/step, "
         f"push {push_avg_ms:.3f} ms ({achieved:.0f} GB/s algorithmic)")
     log(f"[bench] last field solve: {d1['poisson']}")
@@ -302,6 +367,10 @@ def main():
     if not args.no_poisson:
         log("[bench] poisson 512x1024")
         poisson = poisson_bench(args.train_seconds)
+    forms = None
+    if not args.no_forms:
+        log("[bench] gather forms (EC-PIC / MC-PIC)")
+        forms = gather_forms_bench(args.workload)
     ensemble = None
     if not args.no_ensemble:
         log(f"[bench] ensemble of {args.ensemble_runs} runs")
@@ -328,6 +397,7 @@ def main():
         "cpu_baseline": cpu,
         "phase_ms_per_step": phases,
         "poisson": poisson,
+        "gather_forms": forms,
         "ensemble": ensemble,
         "diag": {"vc": d1["vc"], "i_cathode": d1["i_cathode"], "n_coll": d1["n_coll"],
                  "deposit_fallback": d1["deposit_fallback"], "count": d1["count"]},

@@ -249,8 +249,11 @@ pic_status pic_compact(pic_handle *h);
 pic_status pic_get_state(const pic_handle *h, pic_scalar_state *out);
 pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in);
 
-/* Enable (1) or disable (0) per-phase HIP-event timing; pic_get_timers
- * returns the sums since the last reset and resets when reset != 0. */
+/* Per-phase HIP-event timing: on = 0 off, 1 every phase (particle kernel,
+ * events and children, sort, field solve, circuit, field preparation), 2 the
+ * particle kernel alone (two events per step instead of ten or more; the other
+ * sums stay zero); other values give PIC_EINVAL.  pic_get_timers returns the
+ * sums since the last reset and resets when reset != 0. */
 pic_status pic_enable_timers(pic_handle *h, int32_t on);
 pic_status pic_get_timers(pic_handle *h, pic_timers *out, int32_t reset);
 

@@ -91,6 +91,7 @@ struct pic_handle {
     hipEvent_t rb_done = nullptr;   // recorded after the copies; the host spins on it
     int32_t host_flags = 0;
     bool timers_on = false;
+    bool timers_push_only = false;  // time the particle kernel alone
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> free_events;
     pic_timers timers = {};
@@ -397,9 +398,10 @@ const int32_t *live_key_words(const pic_handle *h, int s)
 }
 
 // ---- timers
-void timer_begin(pic_handle *h, hipEvent_t *a)
+void timer_begin(pic_handle *h, hipEvent_t *a, int phase)
 {
-    if (!h->timers_on) return;
+    a[0] = a[1] = nullptr;
+    if (!h->timers_on || (h->timers_push_only && phase != 0)) return;
     hipEvent_t e0, e1;
     if (!h->free_events.empty()) {
         e0 = h->free_events.back().first;
@@ -416,7 +418,7 @@ void timer_begin(pic_handle *h, hipEvent_t *a)
 
 void timer_end(pic_handle *h, int phase, hipEvent_t *a)
 {
-    if (!h->timers_on) return;
+    if (!a[0]) return;
     (void)hipEventRecord(a[1], h->stream);
     h->pending.emplace_back(phase, a[0], a[1]);
 }
@@ -893,7 +895,7 @@ template <typename T>
 void sort_all(pic_handle *h)
 {
     hipEvent_t ev[2];
-    timer_begin(h, ev);
+    timer_begin(h, ev, 2);
     sort_species<T>(h, 0);
     sort_species<T>(h, 1);
     timer_end(h, 2, ev);
@@ -928,18 +930,18 @@ pic_status field_update(pic_handle *h)
 {
     const pic_config &c = h->cfg;
     hipEvent_t ev[2];
-    timer_begin(h, ev);
+    timer_begin(h, ev, 3);
     // the warm start (phi0 extrapolated from the last two steps) is applied
     // by the solve's first kernel
     pic_status st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr,
                               h->pmode, true);
     timer_end(h, 3, ev);
     if (st != PIC_OK) return st;
-    timer_begin(h, ev);
+    timer_begin(h, ev, 4);
     launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, c.circuit, c.v_fixed,
                       c.v_ext, c.r_ext, c.dt, c.extra_current * c.dt, h->stream);
     timer_end(h, 4, ev);
-    timer_begin(h, ev);
+    timer_begin(h, ev, 5);
     launch_field_prep<T>(h->f, (typename Vec4<T>::type *)h->node, h->sc, c.scheme, 0, h->stream);
     timer_end(h, 5, ev);
     return PIC_OK;
@@ -990,7 +992,7 @@ template <typename T>
 void particle_events(pic_handle *h)
 {
     hipEvent_t ev[2];
-    timer_begin(h, ev);
+    timer_begin(h, ev, 1);
     launch_events<T>(event_params<T>(h), h->stream);
     launch_children<T>(child_params<T>(h), h->stream);
     launch_finalize_step(h->sc, h->cap, h->stream);
@@ -1004,7 +1006,7 @@ void particle_phase(pic_handle *h)
     const int64_t nodes = (int64_t)(c.nr + 1) * (c.nz + 1);
     launch_begin_step(h->sc, h->q[0], h->q[1], nodes, (int)sizeof(T), h->stream);
     hipEvent_t ev[2];
-    timer_begin(h, ev);
+    timer_begin(h, ev, 0);
     launch_push_h<T>(h, 0);
     timer_end(h, 0, ev);
     particle_events<T>(h);
@@ -1554,7 +1556,7 @@ pic_status pic_poisson(pic_handle *h, const double *q_dev, double v_cathode, dou
     if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
     if (!q_dev || !phi_dev) return fail(h, PIC_EINVAL, "q_dev and phi_dev are required");
     hipEvent_t ev[2];
-    timer_begin(h, ev);
+    timer_begin(h, ev, 3);
     pic_status st = solve<double>(h, phi_dev, q_dev, (const double *)nullptr, v_cathode, stats,
                                   h->pmode);
     timer_end(h, 3, ev);
@@ -1720,7 +1722,9 @@ pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in)
 pic_status pic_enable_timers(pic_handle *h, int32_t on)
 {
     if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (on < 0 || on > 2) return fail(h, PIC_EINVAL, "timer mode %d outside 0..2", (int)on);
     h->timers_on = on != 0;
+    h->timers_push_only = on == 2;
     return PIC_OK;
 }
 
@@ -2033,11 +2037,12 @@ pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out)
 {
     if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
     if (steps_per_trial < 1) return fail(h, PIC_EINVAL, "steps_per_trial < 1");
-    const bool was_on = h->timers_on;
+    const bool was_on = h->timers_on, was_push_only = h->timers_push_only;
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     timers_collect(h);
     const pic_timers saved = h->timers;
     h->timers_on = true;
+    h->timers_push_only = true;
     // one trial: the mean device time of the particle kernel over the steps
     auto trial = [&](int blocks, double w, double *ms) -> pic_status {
         h->push_blocks = blocks;
@@ -2077,6 +2082,7 @@ pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out)
     h->push_e_weight = best.push_e_weight;
     h->timers = saved;
     h->timers_on = was_on;
+    h->timers_push_only = was_push_only;
     if (st != PIC_OK) return st;
     best.trials = (int32_t)(sizeof(blocks) / sizeof(blocks[0]) + sizeof(weights) / sizeof(weights[0]));
     if (out) *out = best;

@@ -349,6 +349,33 @@ def load_uniform(p: Problem, n: Optional[int] = None, seed_offset: int = 0):
     return out
 
 
+def thermal_box(nr: int, nz: int, cell: float, ppc: int, scheme: int, precision: int = F32,
+                seed: int = 99):
+    """Closed box for the EC-/MC-PIC energy comparison (Sections 2 and 5):
+    nr x nz cells of size `cell`, the cell three Debye lengths at Te = 2 eV
+    (density set to match), dt = 0.1 / w_pe, reflecting grounded walls, no
+    collisions, emission or magnetic field, frozen cold ions, electrons
+    started on the ions' positions (quiet, neutral); ppc particles per species
+    per cell.  Returns (problem, [electrons, ions])."""
+    eps0 = 8.8541878128e-12
+    te = 2.0
+    lam = cell / 3.0
+    n0 = eps0 * te / (E_CHARGE * lam * lam)
+    wpe = math.sqrt(n0 * E_CHARGE * E_CHARGE / (eps0 * M_E))
+    p = Problem(name=f"box{nr}x{nz}", nr=nr, nz=nz, lr=nr * cell, lz=nz * cell,
+                circuit=FIXED_V, v_fixed=0.0, v_ext=0.0, mcc_on=0, see_on=0, frozen_ions=1,
+                wall_bc=(REFLECT, REFLECT, REFLECT), gamma_i=0.0, b_peak=0.0, scheme=scheme,
+                precision=precision, dt=0.1 / wpe, density=n0, n_per_species=nr * nz * ppc,
+                te_ev=te, ti_ev=0.0, seed=seed)
+    el, io = load_uniform(p)
+    io.vr[:] = 0.0
+    io.vt[:] = 0.0
+    io.vz[:] = 0.0
+    el.r[:] = io.r
+    el.z[:] = io.z
+    return p, [el, io]
+
+
 def inputs(p: Problem, n: Optional[int] = None):
     """Everything a run needs: (B_r, B_z, sigma table, [electrons, ions])."""
     br, bz = magnetron_field(p)
