@@ -340,9 +340,10 @@ pic_status pic_get_tuning(const pic_handle *h, pic_tuning *t);
  * external resistance) advance together: one step of every run is captured
  * once into a hipGraph and replayed each step as a single launch, with one
  * synchronization per step for the runs' status.  Each kernel of the step
- * runs once for a batch of up to 64 runs (a block finds its run from block
- * offsets); the sorts of a sort step run per run, spread over nstreams
- * streams.  Each field solve is multigrid-preconditioned and controlled on
+ * (the cell sort of a sort step included) runs once for a batch of up to 64
+ * runs, a block finding its run from block offsets, so the step is one
+ * stream's work; nstreams (1..16) is accepted and the streams are created,
+ * but they no longer change the step.  Each field solve is multigrid-preconditioned and controlled on
  * the device: the step's graph holds its first pass, and while the status
  * shows a run short of poisson_rtol a captured one-pass graph runs again
  * (at most two more passes) for the runs not yet converged, so a run

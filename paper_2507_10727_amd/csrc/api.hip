@@ -1216,12 +1216,49 @@ bool upload_run_particles(pic_handle *h)
         D.push = push_params<T>(h, 0);
         D.ev = event_params<T>(h);
         D.ch = child_params<T>(h);
+        for (int sp = 0; sp < 2; ++sp) {
+            SortJob<T> &J = D.sort[sp];
+            J.src = species_dev<T>(h->buf[sp][h->cur[sp]]);
+            J.dst = species_dev<T>(h->buf[sp][1 - h->cur[sp]]);
+            J.sc = h->sc;
+            J.hist = h->hist;
+            J.block_sums = h->block_sums;
+            J.nr = h->cfg.nr;
+            J.nbins = h->cfg.nr * h->cfg.nz;
+        }
         up &= hipMemcpy(h->part_desc + k * PART_DESC_BYTES, &D, sizeof(D),
                         hipMemcpyHostToDevice) == hipSuccess;
     }
     h->cur[0] = cur0;
     h->cur[1] = cur1;
     return up;
+}
+
+// Cell sort of both species of the runs of batch b, from their current
+// buffers (the descriptor of the runs' current pair).
+template <typename T>
+void sort_b(pic_ensemble *e, size_t b)
+{
+    const size_t r0 = b * MAX_BATCH;
+    const size_t r1 = std::min(e->runs.size(), r0 + MAX_BATCH);
+    const int n = (int)(r1 - r0);
+    SortBatch<T> B;
+    memset(&B, 0, sizeof(B));
+    B.nruns = n;
+    int64_t cap[2][MAX_BATCH];
+    for (int k = 0; k < n; ++k) {
+        pic_handle *h = e->runs[r0 + k];
+        const RunParticles<T> *d =
+            (const RunParticles<T> *)(h->part_desc + (h->cur[0] + 2 * h->cur[1]) * PART_DESC_BYTES);
+        B.job[k] = d->sort;
+        B.nbins[k] = h->cfg.nr * h->cfg.nz;
+        cap[0][k] = h->cap[0];
+        cap[1][k] = h->cap[1];
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+        B.species = sp;
+        launch_sort_b<T>(B, cap[sp], e->s0);
+    }
 }
 
 // Particle phase of the runs of batch b of an ensemble, one launch per
@@ -1332,13 +1369,11 @@ pic_status capture_pass(pic_ensemble *e, int n)
     return PIC_OK;
 }
 
-// Capture one step of every run: in a sort step the per-run sorts on the
-// ensemble's streams (round robin), then for each batch of up to MAX_BATCH
-// runs one launch per particle kernel, the batched field update and a status
-// copy per run.
+// Capture one step of every run: for each batch of up to MAX_BATCH runs one
+// launch per kernel (in a sort step the cell sort of each species first),
+// the batched field update and a status copy per run.
 pic_status capture_ensemble(pic_ensemble *e, bool do_sort, hipGraphExec_t *out)
 {
-    const int ns = (int)e->streams.size();
     std::vector<int> cur0, cur1, since;
     for (pic_handle *h : e->runs) {
         cur0.push_back(h->cur[0]);
@@ -1362,25 +1397,18 @@ pic_status capture_ensemble(pic_ensemble *e, bool do_sort, hipGraphExec_t *out)
         if (st != PIC_OK) return st;
     }
     EHIPCHECK(e, hipStreamBeginCapture(e->s0, hipStreamCaptureModeThreadLocal));
-    auto join = [&]() {
-        for (int k = 0; k < ns; ++k) {
-            (void)hipEventRecord(e->events[1 + k], e->streams[k]);
-            (void)hipStreamWaitEvent(e->s0, e->events[1 + k], 0);
-        }
-    };
-    // the sorts of a sort step, per run
+    // the sorts of a sort step: each species of every run of a batch, one
+    // launch per kernel; then every run's current buffers flip
     if (do_sort) {
-        (void)hipEventRecord(e->events[0], e->s0);
-        for (int k = 0; k < ns; ++k) (void)hipStreamWaitEvent(e->streams[k], e->events[0], 0);
-        for (size_t r = 0; r < e->runs.size(); ++r) {
-            pic_handle *h = e->runs[r];
-            hipStream_t saved = h->stream;
-            h->stream = e->streams[r % ns];
-            if (h->prec == PIC_F64) sort_all<double>(h);
-            else sort_all<float>(h);
-            h->stream = saved;
+        for (size_t b = 0; b < e->plans.size(); ++b) {
+            if (e->runs[0]->prec == PIC_F64) sort_b<double>(e, b);
+            else sort_b<float>(e, b);
         }
-        join();
+        for (pic_handle *h : e->runs) {
+            h->cur[0] = 1 - h->cur[0];
+            h->cur[1] = 1 - h->cur[1];
+            h->steps_since_sort = 0;
+        }
     }
     // particle phase of every run: one launch per kernel for a batch of runs
     for (size_t b = 0; b < e->plans.size(); ++b) {

@@ -237,6 +237,17 @@ struct ChildParams {
     int32_t nr;
 };
 
+// The cell sort of one species of a run: from the current buffer (src) into
+// the other (dst), with the run's bin counts and tile sums (shared by its two
+// species, which sort one after the other).
+template <typename T>
+struct SortJob {
+    SpeciesDev<T> src, dst;
+    DevScalars *sc;
+    int32_t *hist, *block_sums;
+    int32_t nr, nbins;
+};
+
 // A run's particle-kernel parameters for one pair of current particle
 // buffers; an ensemble keeps the four pairs in each run's workspace.
 template <typename T>
@@ -244,6 +255,18 @@ struct RunParticles {
     PushParams<T> push;
     EventParams<T> ev;
     ChildParams<T> ch;
+    SortJob<T> sort[2];         // per species
+};
+
+// The sort of one species in every run of a batch, one launch per kernel:
+// job[r] points at run r's two SortJobs; off holds each run's first block
+// (set per kernel by the launcher), nbins each run's bin count.
+template <typename T>
+struct SortBatch {
+    const SortJob<T> *job[MAX_BATCH];
+    int32_t off[MAX_BATCH + 1];
+    int32_t nbins[MAX_BATCH];
+    int32_t nruns, species;
 };
 
 // One launch of a particle kernel for up to MAX_BATCH runs: each run's
@@ -383,6 +406,9 @@ void launch_load(SpeciesDev<T> sp, int64_t offset, const double *r, const double
                  int64_t n, int32_t nr, int32_t nz, double dr, double dz, hipStream_t s);
 
 // sort.hip
+// cap[r]: run r's capacity of the species (sets its blocks)
+template <typename T>
+void launch_sort_b(SortBatch<T> b, const int64_t *cap, hipStream_t s);
 template <typename T>
 void launch_sort(SpeciesDev<T> src, SpeciesDev<T> dst, DevScalars *sc, int species,
                  int32_t *hist, int32_t *block_sums, int32_t nr, int32_t nz, int64_t cap,

@@ -69,16 +69,16 @@ __device__ __forceinline__ int chunk_min_bin(const int *bins, int *red)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_sort_hist(SpeciesDev<T> S, const DevScalars *sc,
-                                                    int species, int32_t nr, int32_t *hist)
+__device__ __forceinline__ void sort_hist_body(const SpeciesDev<T> &S, const DevScalars *sc,
+                                               int species, int32_t nr, int32_t *hist, int bid,
+                                               int nb)
 {
     __shared__ int cnt[SORT_WIN];
     __shared__ int red[4];
     const int64_t n = sc->count[species];
     const int lane = threadIdx.x & 63;
     for (int q = threadIdx.x; q < SORT_WIN; q += 256) cnt[q] = 0;
-    for (int64_t base = (int64_t)blockIdx.x * SORT_CHUNK; base < n;
-         base += (int64_t)gridDim.x * SORT_CHUNK) {
+    for (int64_t base = (int64_t)bid * SORT_CHUNK; base < n; base += (int64_t)nb * SORT_CHUNK) {
         int bins[SORT_PER_THREAD];
 #pragma unroll
         for (int m = 0; m < SORT_PER_THREAD; ++m) {
@@ -110,12 +110,20 @@ __global__ void __launch_bounds__(256) k_sort_hist(SpeciesDev<T> S, const DevSca
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_sort_hist(SpeciesDev<T> S, const DevScalars *sc,
+                                                    int species, int32_t nr, int32_t *hist)
+{
+    sort_hist_body(S, sc, species, nr, hist, (int)blockIdx.x, (int)gridDim.x);
+}
+
 // Exclusive scan of hist[0, nbins) in three passes (tile sums, scan of the
 // tile sums in one block, tile scans with offsets).
-__global__ void k_scan_tiles(const int32_t *in, int32_t nbins, int32_t *tile_sums)
+__device__ __forceinline__ void scan_tiles_body(const int32_t *in, int32_t nbins,
+                                                int32_t *tile_sums, int tile)
 {
     __shared__ int32_t part[SCAN_TILE / 64];
-    const int t0 = blockIdx.x * SCAN_TILE;
+    const int t0 = tile * SCAN_TILE;
     int v = 0;
     for (int q = threadIdx.x; q < SCAN_TILE; q += blockDim.x) {
         const int b = t0 + q;
@@ -127,11 +135,17 @@ __global__ void k_scan_tiles(const int32_t *in, int32_t nbins, int32_t *tile_sum
     if (threadIdx.x == 0) {
         int s = 0;
         for (int w = 0; w < (int)(blockDim.x / 64); ++w) s += part[w];
-        tile_sums[blockIdx.x] = s;
+        tile_sums[tile] = s;
     }
 }
 
-__global__ void k_scan_top(int32_t *tile_sums, int32_t ntiles, DevScalars *sc, int species)
+__global__ void k_scan_tiles(const int32_t *in, int32_t nbins, int32_t *tile_sums)
+{
+    scan_tiles_body(in, nbins, tile_sums, (int)blockIdx.x);
+}
+
+__device__ __forceinline__ void scan_top_body(int32_t *tile_sums, int32_t ntiles, DevScalars *sc,
+                                              int species)
 {
     // one block of 1024 threads, ntiles <= 1024 * 64 handled by a serial loop per thread
     __shared__ int32_t buf[1024];
@@ -163,11 +177,17 @@ __global__ void k_scan_top(int32_t *tile_sums, int32_t ntiles, DevScalars *sc, i
     if (threadIdx.x == 1023) sc->sort_total[species] = buf[1023];
 }
 
-__global__ void k_scan_down(int32_t *data, int32_t nbins, const int32_t *tile_offsets)
+__global__ void k_scan_top(int32_t *tile_sums, int32_t ntiles, DevScalars *sc, int species)
+{
+    scan_top_body(tile_sums, ntiles, sc, species);
+}
+
+__device__ __forceinline__ void scan_down_body(int32_t *data, int32_t nbins,
+                                               const int32_t *tile_offsets, int tile)
 {
     // one block of SCAN_TILE threads per tile
     __shared__ int32_t buf[SCAN_TILE];
-    const int b = blockIdx.x * SCAN_TILE + threadIdx.x;
+    const int b = tile * SCAN_TILE + threadIdx.x;
     const int v = (b < nbins) ? data[b] : 0;
     buf[threadIdx.x] = v;
     __syncthreads();
@@ -177,7 +197,12 @@ __global__ void k_scan_down(int32_t *data, int32_t nbins, const int32_t *tile_of
         buf[threadIdx.x] += a;
         __syncthreads();
     }
-    if (b < nbins) data[b] = tile_offsets[blockIdx.x] + buf[threadIdx.x] - v;
+    if (b < nbins) data[b] = tile_offsets[tile] + buf[threadIdx.x] - v;
+}
+
+__global__ void k_scan_down(int32_t *data, int32_t nbins, const int32_t *tile_offsets)
+{
+    scan_down_body(data, nbins, tile_offsets, (int)blockIdx.x);
 }
 
 template <typename T>
@@ -200,9 +225,10 @@ __device__ __forceinline__ void copy_slot(const SpeciesDev<T> &src, const Specie
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_sort_scatter(SpeciesDev<T> src, SpeciesDev<T> dst,
-                                                       const DevScalars *sc, int species,
-                                                       int32_t nr, int32_t *off)
+__device__ __forceinline__ void sort_scatter_body(const SpeciesDev<T> &src,
+                                                  const SpeciesDev<T> &dst, const DevScalars *sc,
+                                                  int species, int32_t nr, int32_t *off, int bid,
+                                                  int nb)
 {
     __shared__ int cnt[SORT_WIN];     // counts, then the chunk's first slot per bin
     __shared__ int rk[SORT_WIN];      // slots of the bin handed out so far
@@ -210,8 +236,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(SpeciesDev<T> src, Species
     const int64_t n = sc->count[species];
     const int lane = threadIdx.x & 63;
     for (int q = threadIdx.x; q < SORT_WIN; q += 256) cnt[q] = 0;
-    for (int64_t base = (int64_t)blockIdx.x * SORT_CHUNK; base < n;
-         base += (int64_t)gridDim.x * SORT_CHUNK) {
+    for (int64_t base = (int64_t)bid * SORT_CHUNK; base < n; base += (int64_t)nb * SORT_CHUNK) {
         int bins[SORT_PER_THREAD];
 #pragma unroll
         for (int m = 0; m < SORT_PER_THREAD; ++m) {
@@ -257,12 +282,122 @@ __global__ void __launch_bounds__(256) k_sort_scatter(SpeciesDev<T> src, Species
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_sort_scatter(SpeciesDev<T> src, SpeciesDev<T> dst,
+                                                       const DevScalars *sc, int species,
+                                                       int32_t nr, int32_t *off)
+{
+    sort_scatter_body(src, dst, sc, species, nr, off, (int)blockIdx.x, (int)gridDim.x);
+}
+
 __global__ void k_sort_finish(DevScalars *sc, int species)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) sc->count[species] = sc->sort_total[species];
 }
 
+// ---- batched forms: the sort of one species in every run of a batch, one
+// launch per kernel; a block finds its run from the block offsets
+template <typename T>
+__device__ __forceinline__ int sort_run(const SortBatch<T> &B, int b)
+{
+    int lo = 0, hi = B.nruns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sort_zero_b(SortBatch<T> B)
+{
+    const int b = (int)blockIdx.x, r = sort_run(B, b);
+    const SortJob<T> &J = B.job[r][B.species];
+    const int nb = B.off[r + 1] - B.off[r];
+    for (int q = (b - B.off[r]) * 256 + threadIdx.x; q < J.nbins; q += nb * 256) J.hist[q] = 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sort_hist_b(SortBatch<T> B)
+{
+    const int b = (int)blockIdx.x, r = sort_run(B, b);
+    const SortJob<T> &J = B.job[r][B.species];
+    sort_hist_body(J.src, J.sc, B.species, J.nr, J.hist, b - B.off[r], B.off[r + 1] - B.off[r]);
+}
+
+template <typename T>
+__global__ void k_scan_tiles_b(SortBatch<T> B)
+{
+    const int b = (int)blockIdx.x, r = sort_run(B, b);
+    const SortJob<T> &J = B.job[r][B.species];
+    scan_tiles_body(J.hist, J.nbins, J.block_sums, b - B.off[r]);
+}
+
+// one block per run
+template <typename T>
+__global__ void __launch_bounds__(1024) k_scan_top_b(SortBatch<T> B)
+{
+    const SortJob<T> &J = B.job[blockIdx.x][B.species];
+    scan_top_body(J.block_sums, (J.nbins + SCAN_TILE - 1) / SCAN_TILE, J.sc, B.species);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_TILE) k_scan_down_b(SortBatch<T> B)
+{
+    const int b = (int)blockIdx.x, r = sort_run(B, b);
+    const SortJob<T> &J = B.job[r][B.species];
+    scan_down_body(J.hist, J.nbins, J.block_sums, b - B.off[r]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sort_scatter_b(SortBatch<T> B)
+{
+    const int b = (int)blockIdx.x, r = sort_run(B, b);
+    const SortJob<T> &J = B.job[r][B.species];
+    sort_scatter_body(J.src, J.dst, J.sc, B.species, J.nr, J.hist, b - B.off[r],
+                      B.off[r + 1] - B.off[r]);
+}
+
+// one thread per run
+template <typename T>
+__global__ void k_sort_finish_b(SortBatch<T> B)
+{
+    const int r = (int)threadIdx.x;
+    if (r >= B.nruns) return;
+    DevScalars *sc = B.job[r][B.species].sc;
+    sc->count[B.species] = sc->sort_total[B.species];
+}
+
 }  // namespace
+
+int sort_blocks(int64_t cap)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (cap + SORT_CHUNK - 1) / SORT_CHUNK));
+}
+
+template <typename T>
+void launch_sort_b(SortBatch<T> B, const int64_t *cap, hipStream_t s)
+{
+    const int n = B.nruns;
+    auto offsets = [&](auto blocks_of) {
+        B.off[0] = 0;
+        for (int r = 0; r < n; ++r) B.off[r + 1] = B.off[r] + blocks_of(r);
+        return B.off[n];
+    };
+    auto ntiles = [&](int r) { return (B.nbins[r] + SCAN_TILE - 1) / SCAN_TILE; };
+    int g = offsets([&](int r) { return std::max(1, std::min(256, (B.nbins[r] + 255) / 256)); });
+    hipLaunchKernelGGL((k_sort_zero_b<T>), dim3(g), dim3(256), 0, s, B);
+    g = offsets([&](int r) { return sort_blocks(cap[r]); });
+    hipLaunchKernelGGL((k_sort_hist_b<T>), dim3(g), dim3(256), 0, s, B);
+    const SortBatch<T> Bh = B;
+    g = offsets(ntiles);
+    hipLaunchKernelGGL((k_scan_tiles_b<T>), dim3(g), dim3(256), 0, s, B);
+    hipLaunchKernelGGL((k_scan_top_b<T>), dim3(n), dim3(1024), 0, s, B);
+    hipLaunchKernelGGL((k_scan_down_b<T>), dim3(g), dim3(SCAN_TILE), 0, s, B);
+    hipLaunchKernelGGL((k_sort_scatter_b<T>), dim3(Bh.off[n]), dim3(256), 0, s, Bh);
+    hipLaunchKernelGGL((k_sort_finish_b<T>), dim3(1), dim3(MAX_BATCH), 0, s, B);
+}
 
 template <typename T>
 void launch_sort(SpeciesDev<T> src, SpeciesDev<T> dst, DevScalars *sc, int species,
@@ -272,9 +407,7 @@ void launch_sort(SpeciesDev<T> src, SpeciesDev<T> dst, DevScalars *sc, int speci
     const int32_t nbins = nr * nz;
     const int ntiles = (nbins + SCAN_TILE - 1) / SCAN_TILE;
     launch_zero(hist, (int64_t)nbins * 4, s);
-    int blocks = (int)((cap + SORT_CHUNK - 1) / SORT_CHUNK);
-    if (blocks > 1024) blocks = 1024;
-    if (blocks < 1) blocks = 1;
+    const int blocks = sort_blocks(cap);
     hipLaunchKernelGGL((k_sort_hist<T>), dim3(blocks), dim3(256), 0, s, src, sc, species, nr, hist);
     hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, s, hist, nbins, block_sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, block_sums, ntiles, sc, species);
@@ -288,5 +421,7 @@ template void launch_sort<float>(SpeciesDev<float>, SpeciesDev<float>, DevScalar
                                  int32_t *, int32_t *, int32_t, int32_t, int64_t, hipStream_t);
 template void launch_sort<double>(SpeciesDev<double>, SpeciesDev<double>, DevScalars *, int,
                                   int32_t *, int32_t *, int32_t, int32_t, int64_t, hipStream_t);
+template void launch_sort_b<float>(SortBatch<float>, const int64_t *, hipStream_t);
+template void launch_sort_b<double>(SortBatch<double>, const int64_t *, hipStream_t);
 
 }  // namespace pic
