@@ -323,3 +323,38 @@ def test_poisson_standalone_matches_oracle():
     kp = o.apply_k(np.where(kind != 0, g, 0.0))  # Dirichlet part of K phi
     b = q - kp
     assert np.linalg.norm(r[kind == 0]) <= 1e-8 * np.linalg.norm(b[kind == 0]) * 1.0001
+
+
+def test_timer_modes():
+    """pic_enable_timers: mode 1 times every phase, mode 2 the particle kernel
+    alone (one launch a step), other modes are rejected; timing changes no
+    result."""
+    from paper_2507_10727_amd import _lib as L
+    p = W.scaled(W.preset("small_mc64_f64"), 20_000).replace(sort_every=4)
+    br, bz, sig, parts = W.inputs(p)
+    say("case timer modes")
+    sims = [gpu_sim(p, br, bz, sig, [x.copy() for x in parts]) for _ in range(2)]
+    a, b = sims
+    b.lib.pic_enable_timers(b.h, 2)
+    b.timers(reset=True)
+    a.step(8)
+    b.step(8)
+    t2 = b.timers(reset=True)
+    assert t2["push_launches"] == 8 and t2["push_ms"] > 0.0
+    assert t2["poisson_ms"] == 0.0 and t2["sort_ms"] == 0.0 and t2["children_ms"] == 0.0
+    b.lib.pic_enable_timers(b.h, 1)
+    b.step(4)
+    t1 = b.timers(reset=True)
+    assert t1["push_launches"] == 4 and t1["poisson_ms"] > 0.0 and t1["sort_launches"] == 1
+    a.step(4)
+    assert b.lib.pic_enable_timers(b.h, 3) == L.PIC_EINVAL
+    # (deposit atomics make runs differ by rounding only)
+    da, db = a.diag(), b.diag()
+    assert da["count"] == db["count"]
+    assert abs(da["vc"] - db["vc"]) <= 1e-9 * abs(da["vc"])
+    for s in range(2):
+        pa, pb = a.particles(s), b.particles(s)
+        ia, ib = np.argsort(pa["id"]), np.argsort(pb["id"])
+        assert np.abs(pa["r"][ia] - pb["r"][ib]).max() <= 1e-9 * p.dr
+    for x in sims:
+        x.close()
