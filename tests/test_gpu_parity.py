@@ -130,17 +130,21 @@ def test_f32_single_step(scheme):
     assert abs(d_g["n_cand"] - d_o["n_cand"]) <= 2
 
 
-def test_f32_full_size_sampled():
-    """The benchmark workload at its full size and launch shape (256x512 cells,
-    1e7 electrons + 1e7 Ar+, FP32, default blocks): one GPU step of all
-    particles, and a random sample of 20000 per species advanced by the
-    oracle from the same state and fields.  A particle's push, wall handling
-    and collision depend only on its own state, its random stream (id, step)
-    and the fields before the step, so the sampled particles are compared
-    one by one; children (whose ids follow the global order) are left out."""
-    p = W.preset("ec256x512_f32")
+@pytest.mark.parametrize("name,scheme", [("ec256x512_f32", W.EC_PIC),
+                                         ("ec256x512_f32", W.MC_PIC),
+                                         ("ec512x1024_f32", W.EC_PIC)])
+def test_f32_full_size_sampled(name, scheme):
+    """The FP32 workloads at full size and launch shape (256x512 cells with
+    1e7 electrons + 1e7 Ar+, the benchmark's, in both gather forms; 512x1024
+    cells with 5e7 + 5e7; default blocks): one GPU step of all particles, and
+    a random sample of 20000 per species advanced by the oracle from the same
+    state and fields.  A particle's push, wall handling and collision depend
+    only on its own state, its random stream (id, step) and the fields before
+    the step, so the sampled particles are compared one by one; children
+    (whose ids follow the global order) are left out."""
+    p = W.preset(name).replace(scheme=scheme)
     br, bz, sig, parts = W.inputs(p)
-    say("case f32 full size", p.name, p.n_per_species)
+    say("case f32 full size", p.name, p.n_per_species, "scheme", scheme)
     sim = gpu_sim(p, br, bz, sig, parts)
     del parts
     sim.step(2)
