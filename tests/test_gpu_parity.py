@@ -362,3 +362,52 @@ def test_timer_modes():
         assert np.abs(pa["r"][ia] - pb["r"][ib]).max() <= 1e-9 * p.dr
     for x in sims:
         x.close()
+
+
+def test_f32_long_run_statistics():
+    """A long run in FP32 state against the same run in FP64 state (whose
+    steps match the oracle's element by element, see the 200-step test): the
+    trajectories part by rounding, so the comparison is statistical.  The
+    discharge of the benchmark workload on a 64x128-cell cut (1 x 2 cm, 5e5
+    + 5e5 particles, EC-PIC) for 2000 steps; over the last 1000 steps the
+    means of the particle counts, kinetic energies, peak densities (of each
+    species' charge summed over blocks of 8 x 8 nodes: a single node's
+    density near the axis, where node volumes are smallest, is mostly
+    sampling noise), peak potential and cathode voltage, and the collisions
+    counted, agree within 5%."""
+    def block_peak(q, p):
+        g = np.abs(q).reshape(p.nz + 1, p.nr + 1)[:p.nz, :p.nr]
+        b = g.reshape(p.nz // 8, 8, p.nr // 8, 8).sum(axis=(1, 3))
+        r0 = np.maximum(np.arange(0, p.nr, 8) - 0.5, 0.0) * p.dr
+        r1 = (np.arange(0, p.nr, 8) + 7.5) * p.dr
+        vol = np.pi * (r1 ** 2 - r0 ** 2) * 8 * p.dz
+        return (b / vol[None, :]).max() / 1.602176634e-19
+
+    base = W.preset("ec256x512_f32").replace(nr=64, nz=128, lr=0.01, lz=0.02,
+                                            n_per_species=500_000)
+    say("case long run FP32 vs FP64", base.nr, base.nz, base.n_per_species)
+    series = {}
+    for prec in (W.F64, W.F32):
+        p = base.replace(precision=prec)
+        br, bz, sig, parts = W.inputs(p)
+        sim = gpu_sim(p, br, bz, sig, parts)
+        rows, coll = [], np.zeros(3)
+        for k in range(20):
+            sim.step(100)
+            d = sim.diag()
+            if k >= 10:
+                f = sim.fields_host()
+                rows.append([d["count"][0], d["count"][1], d["ke"][0], d["ke"][1],
+                             block_peak(f["q_e"], p), block_peak(f["q_i"], p), d["phi_max"],
+                             d["vc"]])
+                coll += np.array(d["n_coll"], dtype=np.float64)
+        sim.close()
+        series[prec] = (np.mean(np.array(rows), axis=0), coll)
+    names = ["n_e", "n_i", "ke_e", "ke_i", "n_peak_e", "n_peak_i", "phi_max", "vc"]
+    m64, c64 = series[W.F64]
+    m32, c32 = series[W.F32]
+    for nm, a, b in zip(names, m64, m32):
+        say(f"  {nm}: f64 {a:.6g} f32 {b:.6g} rel {abs(b - a) / abs(a):.2e}")
+        assert abs(b - a) <= 0.05 * abs(a), nm
+    say("  collisions", c64, c32)
+    assert np.all(np.abs(c32 - c64) <= 0.05 * c64 + 10)
