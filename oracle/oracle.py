@@ -61,7 +61,8 @@ class Diag(C.Structure):
                 ("n_abs", (C.c_int64 * 5) * 2), ("n_cand", C.c_int64),
                 ("n_coll", C.c_int64 * 3), ("n_see", C.c_int64),
                 ("n_child", C.c_int64 * 2), ("poisson_iters", C.c_int64),
-                ("poisson_res", C.c_double)]
+                ("poisson_res", C.c_double), ("n_peak", C.c_double * 2),
+                ("phi_max", C.c_double), ("i_cathode", C.c_double)]
 
     def as_dict(self):
         return {
@@ -70,7 +71,8 @@ class Diag(C.Structure):
             "n_abs": [tuple(self.n_abs[s]) for s in range(2)],
             "n_cand": self.n_cand, "n_coll": tuple(self.n_coll), "n_see": self.n_see,
             "n_child": tuple(self.n_child), "poisson_iters": self.poisson_iters,
-            "poisson_res": self.poisson_res,
+            "poisson_res": self.poisson_res, "n_peak": tuple(self.n_peak),
+            "phi_max": self.phi_max, "i_cathode": self.i_cathode,
         }
 
 
@@ -108,6 +110,17 @@ def lib():
         L.orc_gather.argtypes = [C.POINTER(Problem), _dp, _dp, _dp, C.c_int64, _dp, _dp, _dp, _dp]
         L.orc_nu_tables.argtypes = [C.POINTER(Problem), _dp, C.POINTER(C.c_uint64)]
         L.orc_nu_tables.restype = C.c_double
+        L.orc_node_volumes.argtypes = [C.POINTER(Problem), _dp]
+        L.orc_capacitance.argtypes = [C.POINTER(Problem), _dp]
+        L.orc_capacitance.restype = C.c_double
+        L.orc_induced_charge.argtypes = [C.POINTER(Problem), _dp, _dp]
+        L.orc_induced_charge.restype = C.c_double
+        L.orc_mcc_select.argtypes = [C.POINTER(Problem), _dp, C.c_double, C.c_uint64, C.c_uint32,
+                                     C.c_int64, C.c_double, C.c_double, C.c_double,
+                                     C.POINTER(C.c_double)]
+        L.orc_mcc_select.restype = C.c_int
+        L.orc_mcc_select_many.argtypes = [C.POINTER(Problem), C.c_int64, C.c_int64, _up, _dp, _dp,
+                                          _dp, C.POINTER(C.c_int32), _dp]
         L.orc_init.argtypes = [C.POINTER(Problem), C.POINTER(Species), C.POINTER(State),
                                _dp, _dp, _dp, _dp, _dp]
         L.orc_init.restype = C.c_int
@@ -290,6 +303,33 @@ class Oracle:
         out = [np.zeros(n) for _ in range(4)]
         lib().orc_gather(C.byref(self.P), _d(phi), _d(r), _d(z), n, *(_d(o) for o in out))
         return out
+
+    def node_volumes(self):
+        v = np.zeros(self.prob.nodes)
+        lib().orc_node_volumes(C.byref(self.P), _d(v))
+        return v
+
+    def capacitance(self, phi_l):
+        phi_l = np.ascontiguousarray(phi_l, np.float64)
+        return lib().orc_capacitance(C.byref(self.P), _d(phi_l))
+
+    def induced_charge(self, phi0, q_node):
+        phi0 = np.ascontiguousarray(phi0, np.float64)
+        q_node = np.ascontiguousarray(q_node, np.float64)
+        return lib().orc_induced_charge(C.byref(self.P), _d(phi0), _d(q_node))
+
+    def mcc_select(self, ids, step, vr, vt, vz):
+        """The oracle's null-collision decision for each electron (ids, velocities
+        after the push): codes -2 not a candidate, -1 null, 0/1/2 process, and the
+        relative margin of the deciding floating-point comparisons."""
+        ids = np.ascontiguousarray(ids, np.uint32)
+        vr, vt, vz = (np.ascontiguousarray(a, np.float64) for a in (vr, vt, vz))
+        n = ids.shape[0]
+        code = np.zeros(n, np.int32)
+        margin = np.zeros(n)
+        lib().orc_mcc_select_many(C.byref(self.P), int(step), n, _u(ids), _d(vr), _d(vt), _d(vz),
+                                  code.ctypes.data_as(C.POINTER(C.c_int32)), _d(margin))
+        return code, margin
 
     def nu_tables(self):
         nu = np.zeros((3, self.sigma.shape[1]))

@@ -304,6 +304,24 @@ void orc_nodal_e(const orc_problem *p, const double *phi, double *er, double *ez
         }
 }
 
+/* Node volumes: a tent weight S_i(r) S_j(z) integrated over the cylinder.
+ * In r, the integral of 2 pi r S_i(r) dr is pi dr^2 / 3 on the axis,
+ * 2 pi r_i dr inside and pi dr R - pi dr^2 / 3 at the outer wall; in z it is
+ * dz inside and dz / 2 on the two z walls. */
+void orc_node_volumes(const orc_problem *p, double *vol)
+{
+    const double dr = p->lr / p->nr, dz = p->lz / p->nz;
+    for (int j = 0; j <= p->nz; ++j)
+        for (int i = 0; i <= p->nr; ++i) {
+            double a;
+            if (i == 0) a = PI * dr * dr / 3.0;
+            else if (i == p->nr) a = PI * dr * p->lr - PI * dr * dr / 3.0;
+            else a = 2.0 * PI * (i * dr) * dr;
+            double h = (j == 0 || j == p->nz) ? 0.5 * dz : dz;
+            vol[IDX(p, i, j)] = a * h;
+        }
+}
+
 /* Cell and in-cell fraction of a position: i = floor(r/dr) kept in
  * [0, nr-1], f = r/dr - i (likewise in z). */
 static void locate(const orc_problem *p, double r, double z, int *i, int *j, double *fr, double *fz)
@@ -410,6 +428,53 @@ static double interp(const double *row, int n, double de, double e)
     return (1.0 - f) * row[k] + f * row[k + 1];
 }
 
+/* Null-collision selection (one electron, after its push): it is a
+ * candidate iff the first word of its collision draw is below
+ * floor(P_null 2^32) (an integer test); a candidate's process follows from
+ * R = U24(u1) nu_max against the cumulative frequencies nu_el, + nu_ex,
+ * + nu_iz at its energy; a selected inelastic process below its threshold,
+ * and anything beyond the sum, is a null collision. */
+int orc_mcc_select(const orc_problem *p, const double *nu, double numax, uint64_t t_null,
+                   uint32_t id, int64_t step, double vr, double vt, double vz, double *margin)
+{
+    uint32_t u[4];
+    draw(p, id, 0, PUR_MCC, step, u);
+    if (margin) *margin = 0.0;
+    if ((uint64_t)u[0] >= t_null) return -2;
+    const double *nel = nu, *nex = nu + p->n_table, *niz = nu + 2 * p->n_table;
+    double e = 0.5 * p->m[0] * (vr * vr + vt * vt + vz * vz) / QE;
+    double c1 = interp(nel, p->n_table, p->de_table, e);
+    double c2 = c1 + interp(nex, p->n_table, p->de_table, e);
+    double c3 = c2 + interp(niz, p->n_table, p->de_table, e);
+    double rsel = u24(u[1]) * numax;
+    int proc = -1;
+    if (rsel < c1) proc = 0;
+    else if (rsel < c2) proc = (e >= p->e_exc) ? 1 : -1;
+    else if (rsel < c3) proc = (e >= p->e_iz) ? 2 : -1;
+    if (margin) {
+        double m = fabs(rsel - c1) / numax;
+        m = fmin(m, fabs(rsel - c2) / numax);
+        m = fmin(m, fabs(rsel - c3) / numax);
+        m = fmin(m, fabs(e - p->e_exc) / p->e_exc);
+        m = fmin(m, fabs(e - p->e_iz) / p->e_iz);
+        *margin = m;
+    }
+    return proc;
+}
+
+void orc_mcc_select_many(const orc_problem *p, int64_t step, int64_t n, const uint32_t *id,
+                         const double *vr, const double *vt, const double *vz, int32_t *codes,
+                         double *margins)
+{
+    double *nu = malloc(sizeof(double) * 3 * p->n_table);
+    uint64_t t_null = 0;
+    double numax = orc_nu_tables(p, nu, &t_null);
+    for (int64_t k = 0; k < n; ++k)
+        codes[k] = orc_mcc_select(p, nu, numax, t_null, id[k], step, vr[k], vt[k], vz[k],
+                                  margins ? &margins[k] : NULL);
+    free(nu);
+}
+
 /* Isotropic unit vector from two uniforms: cos(chi) = 1 - 2U, azimuth 2 pi U'. */
 static void iso_dir(uint32_t ua, uint32_t ub, double d[3])
 {
@@ -462,7 +527,7 @@ static uint64_t child_key(int parent_species, uint32_t parent_id, int kind)
  * Q_c0 = sum over cathode nodes of (K phi0 - Q).  Charge conservation with a
  * backward-Euler resistor current (V_ext - V_c)/R:
  *     Q_c0 + C V^{n+1} = Q_c^n + dQ_conv + dt (V_ext - V^{n+1}) / R.      */
-static double induced_charge(const orc_problem *p, const double *phi0, const double *q_node)
+double orc_induced_charge(const orc_problem *p, const double *phi0, const double *q_node)
 {
     int64_t nn = (int64_t)(p->nr + 1) * (p->nz + 1);
     double *kp = malloc(sizeof(double) * nn);
@@ -474,7 +539,7 @@ static double induced_charge(const orc_problem *p, const double *phi0, const dou
     return s;
 }
 
-static double capacitance(const orc_problem *p, const double *phi_l)
+double orc_capacitance(const orc_problem *p, const double *phi_l)
 {
     int64_t nn = (int64_t)(p->nr + 1) * (p->nz + 1);
     double *kp = malloc(sizeof(double) * nn);
@@ -509,9 +574,9 @@ int orc_init(const orc_problem *p, orc_species sp[2], orc_state *st,
     memset(phi0, 0, sizeof(double) * nn);
     if (orc_solve(p, qt, 0.0, phi0, p->poisson_rtol, p->poisson_maxit, &it, &res)) rc = -4;
     st->step = 0;
-    st->cap_c = capacitance(p, phi_l);
+    st->cap_c = orc_capacitance(p, phi_l);
     st->vc = (p->circuit == 1) ? p->v_ext : p->v_fixed;
-    st->qc = induced_charge(p, phi0, qt) + st->cap_c * st->vc;
+    st->qc = orc_induced_charge(p, phi0, qt) + st->cap_c * st->vc;
     for (int64_t n = 0; n < nn; ++n) phi[n] = phi0[n] + st->vc * phi_l[n];
     for (int s = 0; s < 2; ++s) {
         uint32_t mx = 0;
@@ -639,26 +704,18 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
     if (p->mcc_on) {
         orc_species *S = &sp[0];
         const double me = p->m[0];
-        const double *nel = nu, *nex = nu + p->n_table, *niz = nu + 2 * p->n_table;
         for (int64_t k = 0; k < n_pre[0]; ++k) {
             if (dead[0][k]) continue;
-            uint32_t u[4];
-            draw(p, S->id[k], 0, PUR_MCC, st->step, u);
-            if ((uint64_t)u[0] >= t_null) continue;
-            d->n_cand++;
             double vx = S->vr[k], vy = S->vt[k], vz = S->vz[k];
-            double v2 = vx * vx + vy * vy + vz * vz;
-            double e = 0.5 * me * v2 / QE;
-            double c1 = interp(nel, p->n_table, p->de_table, e);
-            double c2 = c1 + interp(nex, p->n_table, p->de_table, e);
-            double c3 = c2 + interp(niz, p->n_table, p->de_table, e);
-            double rsel = u24(u[1]) * numax;
-            int proc = -1;
-            if (rsel < c1) proc = 0;
-            else if (rsel < c2) proc = (e >= p->e_exc) ? 1 : -1;
-            else if (rsel < c3) proc = (e >= p->e_iz) ? 2 : -1;
+            int proc = orc_mcc_select(p, nu, numax, t_null, S->id[k], st->step, vx, vy, vz, NULL);
+            if (proc == -2) continue;
+            d->n_cand++;
             if (proc < 0) continue;
             d->n_coll[proc]++;
+            uint32_t u[4];
+            draw(p, S->id[k], 0, PUR_MCC, st->step, u);
+            double v2 = vx * vx + vy * vy + vz * vz;
+            double e = 0.5 * me * v2 / QE;
             double dn[3];
             iso_dir(u[2], u[3], dn);
             double enew;
@@ -730,6 +787,17 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
     /* deposit */
     deposit_all(p, sp, q_e, q_i);
     for (int64_t n = 0; n < nn; ++n) { d->q_dep[0] += q_e[n]; d->q_dep[1] += q_i[n]; }
+    {
+        /* peak density of each species: node charge over (q_s times the node volume) */
+        double *vol = malloc(sizeof(double) * nn);
+        orc_node_volumes(p, vol);
+        d->n_peak[0] = d->n_peak[1] = -HUGE_VAL;
+        for (int64_t n = 0; n < nn; ++n) {
+            d->n_peak[0] = fmax(d->n_peak[0], q_e[n] / (p->q[0] * vol[n]));
+            d->n_peak[1] = fmax(d->n_peak[1], q_i[n] / (p->q[1] * vol[n]));
+        }
+        free(vol);
+    }
 
     /* field solve and circuit */
     d->dq_conv = dq;
@@ -738,7 +806,7 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
         for (int64_t n = 0; n < nn; ++n) qt[n] = q_e[n] + q_i[n];
         if (orc_solve(p, qt, 0.0, phi0, p->poisson_rtol, p->poisson_maxit,
                       &d->poisson_iters, &d->poisson_res)) rc = rc ? rc : -4;
-        double qc0 = induced_charge(p, phi0, qt);
+        double qc0 = orc_induced_charge(p, phi0, qt);
         d->qc0 = qc0;
         double v;
         if (p->circuit == 1)
@@ -750,6 +818,9 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
         for (int64_t n = 0; n < nn; ++n) phi[n] = phi0[n] + v * phi_l[n];
         free(qt);
     }
+    d->i_cathode = dq / dt;
+    d->phi_max = -HUGE_VAL;
+    for (int64_t n = 0; n < nn; ++n) d->phi_max = fmax(d->phi_max, phi[n]);
     st->step++;
     free(ern); free(ezn); free(nu);
     return rc;

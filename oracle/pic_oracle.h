@@ -78,6 +78,9 @@ typedef struct orc_diag {
     int64_t n_child[2];
     int64_t poisson_iters;
     double poisson_res;
+    double n_peak[2];          /* max over nodes of Q_s / (q_s V_node) after the deposit */
+    double phi_max;            /* max over nodes of the new phi             */
+    double i_cathode;          /* dq_conv / dt                              */
 } orc_diag;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
@@ -91,6 +94,13 @@ int  orc_solve(const orc_problem *p, const double *q_node, double v_cathode,
                double *phi, double rtol, int maxit, int64_t *iters, double *rel_res);
 double orc_field_energy(const orc_problem *p, const double *phi);
 void orc_nodal_e(const orc_problem *p, const double *phi, double *er, double *ez);
+/* Node volumes of the density diagnostic: the volume a tent weight of node
+ * (i,j) integrates to over the cylinder (linear-in-r weighting). */
+void orc_node_volumes(const orc_problem *p, double *vol);
+/* Circuit pieces: capacitance sum over cathode nodes of (K phi_L), and the
+ * induced cathode charge sum over cathode nodes of (K phi0 - Q). */
+double orc_capacitance(const orc_problem *p, const double *phi_l);
+double orc_induced_charge(const orc_problem *p, const double *phi0, const double *q_node);
 
 /* Particle-grid pieces. */
 void orc_deposit(const orc_problem *p, const double *r, const double *z, int64_t n,
@@ -100,6 +110,19 @@ void orc_gather(const orc_problem *p, const double *phi, const double *r, const 
 
 /* Collision tables: nu[3][n_table] (1/s), returns nu_max; *t_null = floor(P_null 2^32). */
 double orc_nu_tables(const orc_problem *p, double *nu, uint64_t *t_null);
+
+/* The null-collision decision of one electron with velocity v (after the
+ * push) at step `step`: -2 not a candidate, -1 null collision, 0 elastic,
+ * 1 excitation, 2 ionization.  *margin (nullable) receives the smallest
+ * relative distance of the floating-point comparisons that decide the
+ * process: |R - cumulative nu_k| / nu_max and |E - E_threshold| / E_threshold
+ * (0 when the electron is not a candidate: that test is an integer one). */
+int orc_mcc_select(const orc_problem *p, const double *nu, double numax, uint64_t t_null,
+                   uint32_t id, int64_t step, double vr, double vt, double vz, double *margin);
+/* orc_mcc_select for n electrons (codes[k], margins[k] nullable). */
+void orc_mcc_select_many(const orc_problem *p, int64_t step, int64_t n, const uint32_t *id,
+                         const double *vr, const double *vt, const double *vz, int32_t *codes,
+                         double *margins);
 
 /* Whole-run drivers. phi, phi0, phi_l and q_node[2] are node arrays. */
 int orc_init(const orc_problem *p, orc_species sp[2], orc_state *st,

@@ -14,6 +14,7 @@ import math
 
 import numpy as np
 import pytest
+from tol import approx
 from scipy.signal import correlate2d
 
 from oracle import cnn_oracle as N
@@ -154,7 +155,7 @@ def test_loss_is_half_for_zero_output():
     ci, co = N.CONVS[-1]
     theta[-(ci * co * 9 + co):] = 0.0
     L, g = N.loss_and_grad(theta, 1.0, bs, phis, kind, p.nr, p.nz, apply_a)
-    assert L == pytest.approx(0.5, abs=1e-13)
+    assert L == approx(0.5, abs=1e-13)
 
 
 def test_adam_first_step_closed_form():

@@ -15,6 +15,7 @@ import math
 
 import numpy as np
 import pytest
+from tol import approx
 
 from oracle import oracle as O
 from oracle_helpers import empty, make_oracle, species, zero_field_problem
@@ -66,7 +67,7 @@ def test_mcc_counts_binomial():
         sd = math.sqrt(n * prob * (1 - prob))
         assert abs(d["n_coll"][j] - mean) < 5 * sd + 1, (j, d["n_coll"][j], mean)
         # small-probability limit: ~ N n sigma v dt
-        assert mean == pytest.approx(n * ng * sig[j] * v * p.dt, rel=2 * numax * p.dt)
+        assert mean == approx(n * ng * sig[j] * v * p.dt, rel=2 * numax * p.dt)
     assert d["n_child"] == (d["n_coll"][2], d["n_coll"][2])
 
 
@@ -116,6 +117,13 @@ def test_mcc_decisions_bruteforce():
     assert not mism, mism[:10]
     assert len(got) == n
     assert sum(v == "iz" for v in expect.values()) == d["n_coll"][2] > 0
+    # the oracle's decision function on the beam's velocities gives the same
+    # outcomes (speed is unchanged by the field-free push), with positive
+    # margins
+    code, margin = o.mcc_select(beam.id, 0, beam.vr, beam.vt, beam.vz)
+    names = {-2: "none", -1: "none", 0: "el", 1: "ex", 2: "iz"}
+    assert [names[int(c)] for c in code] == [expect[pid] for pid in range(n)]
+    assert (margin[code >= -1] > 0).all() and (margin[code == -2] == 0).all()
 
 
 def test_collision_energetics():
@@ -148,10 +156,10 @@ def test_collision_energetics():
     # elastic: 0 <= loss fraction <= 4 m/M and mean 2 m/M
     el = (frac > 1e-12) & (frac <= 4 * ME / m_ar * 1.0001) & ~ex
     assert el.sum() > 1000
-    assert frac[el].mean() == pytest.approx(2 * ME / m_ar, rel=0.1)
+    assert frac[el].mean() == approx(2 * ME / m_ar, rel=0.1)
     # new ions: Maxwellian at the gas temperature
     vt = math.sqrt(KB * p.t_gas / (m_ar - ME))
-    assert np.std(ion["vr"]) == pytest.approx(vt, rel=0.15)
+    assert np.std(ion["vr"]) == approx(vt, rel=0.15)
 
 
 def test_secondary_emission():
@@ -180,7 +188,7 @@ def test_secondary_emission():
     rr = r - 1e4 * 0 * p.dt  # radial position unchanged (v_r = 0)
     assert np.allclose(e["r"], rr[emit], rtol=0, atol=1e-18)
     # cathode charge: N_hit q_i w + N_see e w_e
-    assert d["dq_conv"] == pytest.approx(n * QE + nsee * QE, rel=1e-12)
+    assert d["dq_conv"] == approx(n * QE + nsee * QE, rel=1e-12)
 
 
 def test_circuit_relaxation():
@@ -195,7 +203,7 @@ def test_circuit_relaxation():
     for n in range(1, 40):
         o.step()
         expect = vstar + (v0 - vstar) * a ** n
-        assert o.state.vc == pytest.approx(expect, rel=1e-12, abs=1e-12)
+        assert o.state.vc == approx(expect, rel=1e-12, abs=1e-12)
     assert 0.05 < a < 0.95
 
 

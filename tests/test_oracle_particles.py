@@ -12,6 +12,7 @@ import math
 
 import numpy as np
 import pytest
+from tol import approx
 
 from oracle_helpers import empty, make_oracle, species, zero_field_problem
 from paper_2507_10727_amd import workloads as W
@@ -29,7 +30,7 @@ def test_deposit_total_charge():
     r = p.lr * np.sqrt(rng.random(n))
     z = p.lz * rng.random(n)
     q = o.deposit(r, z, -3.7e-14)
-    assert q.sum() == pytest.approx(-3.7e-14 * n, rel=1e-13)
+    assert q.sum() == approx(-3.7e-14 * n, rel=1e-13)
 
 
 def test_deposit_single_particle_weights():
@@ -38,7 +39,7 @@ def test_deposit_single_particle_weights():
     q = o.deposit([2.25e-3], [3.5e-3], 1.0).reshape(9, 9)  # (j, i)
     expect = {(3, 2): 0.75 * 0.5, (3, 3): 0.25 * 0.5, (4, 2): 0.75 * 0.5, (4, 3): 0.25 * 0.5}
     for (j, i), v in expect.items():
-        assert q[j, i] == pytest.approx(v, rel=1e-14)
+        assert q[j, i] == approx(v, rel=1e-14)
     assert np.count_nonzero(q) == 4
 
 
@@ -135,8 +136,8 @@ def test_mc_momentum_identity():
     er, ez, _, _ = o.gather(phi, r, z)
     qn = o.deposit(r, z, 1.0)
     ern, ezn = o.nodal_e(phi)
-    assert er.sum() == pytest.approx((qn * ern).sum(), rel=1e-11)
-    assert ez.sum() == pytest.approx((qn * ezn).sum(), rel=1e-11)
+    assert er.sum() == approx((qn * ern).sum(), rel=1e-11)
+    assert ez.sum() == approx((qn * ezn).sum(), rel=1e-11)
 
 
 # ------------------------------------------------------------------- push ---
@@ -194,7 +195,7 @@ def test_boris_gyration_discrete_orbit():
     xs = np.array(xs)
     ctr = xs.mean(axis=0)
     rad = np.hypot(*(xs - ctr).T).mean()
-    assert rad == pytest.approx(rl * math.sqrt(1 + (wc * p.dt / 2) ** 2), rel=2e-3)
+    assert rad == approx(rl * math.sqrt(1 + (wc * p.dt / 2) ** 2), rel=2e-3)
 
 
 def test_straight_line_through_axis():
@@ -223,4 +224,4 @@ def test_exb_drift():
     n = np.arange(steps)
     A = np.stack([np.ones(steps), np.cos(theta * n), np.sin(theta * n)], axis=1)
     coef, *_ = np.linalg.lstsq(A, out["vt"], rcond=None)
-    assert coef[0] == pytest.approx(-e0 / b0, rel=1e-3)
+    assert coef[0] == approx(-e0 / b0, rel=1e-3)

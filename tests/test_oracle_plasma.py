@@ -11,6 +11,7 @@ import math
 
 import numpy as np
 import pytest
+from tol import approx
 from scipy.special import j0, j1, jn_zeros
 
 from oracle_helpers import make_oracle, species
@@ -61,7 +62,7 @@ def test_cold_plasma_frequency():
         if best is None or err < best:
             best, wbest = err, om
     expect = 2.0 / dt * math.asin(wpe * dt / 2)
-    assert wbest == pytest.approx(expect, rel=0.02)
+    assert wbest == approx(expect, rel=0.02)
 
 
 def _thermal_box(scheme, steps):

@@ -11,6 +11,7 @@ import math
 
 import numpy as np
 import pytest
+from tol import approx
 from scipy import fft as sfft
 from scipy.linalg import solve_banded
 from scipy.special import j0, jn_zeros
@@ -52,11 +53,11 @@ def test_face_areas_tile_domain():
     # axial faces at each z_{j+1/2} tile the disk pi R^2
     for j in range(p.nz):
         area = cn[j].sum() * p.dz / EPS0
-        assert area == pytest.approx(math.pi * p.lr ** 2, rel=1e-13)
+        assert area == approx(math.pi * p.lr ** 2, rel=1e-13)
     # radial faces at each r_{i+1/2} tile the side 2 pi r L
     for i in range(p.nr):
         area = ce[:, i].sum() * p.dr / EPS0
-        assert area == pytest.approx(2 * math.pi * (i + 0.5) * p.dr * p.lz, rel=1e-13)
+        assert area == approx(2 * math.pi * (i + 0.5) * p.dr * p.lz, rel=1e-13)
 
 
 def test_gauss_law_total_charge():
@@ -70,7 +71,7 @@ def test_gauss_law_total_charge():
     assert rc == 0
     kp = o.apply_k(phi)
     induced = kp[kind != 0].sum()
-    assert induced == pytest.approx(-q.sum(), rel=1e-10)
+    assert induced == approx(-q.sum(), rel=1e-10)
 
 
 def dst_solve(o, q):
