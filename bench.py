@@ -266,6 +266,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ec256x512_f32")
+    ap.add_argument("--solver", choices=("direct", "mgcg"), default="direct",
+                    help="field solve of the timed steps: the direct sine-transform solve "
+                         "(default) or multigrid-preconditioned CG")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-poisson", action="store_true")
     ap.add_argument("--poisson-only", action="store_true",
@@ -309,7 +312,8 @@ def main():
         torch.cuda.empty_cache()
         log("[bench] copy calibration: 3 x 1 GiB device copies")
 
-    p = W.preset(args.workload)
+    p = W.preset(args.workload).replace(
+        poisson_mode=W.POISSON_DIRECT if args.solver == "direct" else W.POISSON_MGCG)
     log(f"[bench] generating {args.workload}: {p.nr}x{p.nz} cells, {p.n_per_species} per species")
     br, bz, sig, parts = W.inputs(p)
     log("[bench] init on GPU")
@@ -392,7 +396,8 @@ def main():
                    "scheme": "EC-PIC" if p.scheme == W.EC_PIC else "MC-PIC",
                    "density_m3": p.density, "pressure_mtorr": p.p_gas / W.TORR * 1e3,
                    "circuit": f"{p.v_ext} V through {p.r_ext} ohm", "dt_s": p.dt,
-                   "poisson_rtol": p.poisson_rtol, "sort_every": p.sort_every},
+                   "poisson_rtol": p.poisson_rtol, "sort_every": p.sort_every,
+                   "field_solve": args.solver},
         "roofline": roof,
         "cpu_baseline": cpu,
         "phase_ms_per_step": phases,

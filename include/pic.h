@@ -59,8 +59,11 @@ enum { PIC_MC = 0, PIC_EC = 1 };              /* field-gather scheme (Section 2)
 enum { PIC_F32 = 0, PIC_F64 = 1 };            /* particle-state precision        */
 enum { PIC_FIXED_V = 0, PIC_RESISTOR = 1 };   /* cathode circuit (Sections 3-4)  */
 enum { PIC_ABSORB = 0, PIC_REFLECT = 1 };     /* particle wall condition         */
-enum { PIC_MGCG = 0, PIC_LEARNED = 1, PIC_CG = 2 }; /* field-solve preconditioner:
-                                   multigrid, learned network, none       */
+enum { PIC_MGCG = 0, PIC_LEARNED = 1, PIC_CG = 2, PIC_DIRECT = 3 };
+                                /* field solve: CG preconditioned by multigrid,
+                                   by the learned network, or by nothing; or
+                                   the direct sine-transform solve (needs a
+                                   cathode covering the z = 0 row)         */
 
 typedef struct pic_handle pic_handle;         /* opaque, library-owned */
 typedef struct pic_ensemble pic_ensemble;     /* opaque, library-owned */

@@ -140,7 +140,7 @@ class pic_tuning(C.Structure):
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
-PIC_MGCG, PIC_LEARNED, PIC_CG = 0, 1, 2
+PIC_MGCG, PIC_LEARNED, PIC_CG, PIC_DIRECT = 0, 1, 2, 3
 
 _lib = None
 

@@ -77,6 +77,8 @@ struct pic_handle {
     int pmode = PIC_MGCG;
     int64_t n_unknown = 0;
     double rho_pc = 0.5, rho_cg = 0.9;
+    FastSolve fs = {};              // direct sine-transform solve (PIC_DIRECT)
+    bool fs_on = false;
     RunSolve *rsolve = nullptr;     // descriptor of the batched field update
     char *part_desc = nullptr;      // RunParticles for each pair of current particle
                                     // buffers (an ensemble's one-launch particle kernels)
@@ -198,8 +200,17 @@ pic_status validate(const pic_config *c, pic_handle *h)
     if (c->sort_every < 1) return fail(h, PIC_EINVAL, "sort_every must be >= 1");
     if (!(c->poisson_rtol > 0) || c->poisson_maxit < 1 || c->poisson_maxit > MAX_PCG)
         return fail(h, PIC_EINVAL, "poisson_rtol > 0 and 1 <= poisson_maxit <= %d required", MAX_PCG);
-    if (c->poisson_mode != PIC_MGCG && c->poisson_mode != PIC_LEARNED && c->poisson_mode != PIC_CG)
-        return fail(h, PIC_EINVAL, "poisson_mode must be PIC_MGCG, PIC_LEARNED or PIC_CG");
+    if (c->poisson_mode != PIC_MGCG && c->poisson_mode != PIC_LEARNED &&
+        c->poisson_mode != PIC_CG && c->poisson_mode != PIC_DIRECT)
+        return fail(h, PIC_EINVAL, "poisson_mode must be PIC_MGCG, PIC_LEARNED, PIC_CG or PIC_DIRECT");
+    if (c->poisson_mode == PIC_DIRECT) {
+        if (host_node_kind(c->nr, c->nz, c->lr, c->cathode_rmax, c->nr - 1, 0) != 1)
+            return fail(h, PIC_EINVAL,
+                        "PIC_DIRECT needs the cathode to cover the z = 0 row (cathode_rmax > "
+                        "(nr - 1) dr): with a Neumann block the field equation does not separate");
+        if (c->nr > 1024 || c->nz > 2048)
+            return fail(h, PIC_EINVAL, "PIC_DIRECT supports at most 1024 x 2048 cells");
+    }
     if (c->pc_batch < 0 || c->pc_batch > 64)
         return fail(h, PIC_EINVAL, "pc_batch outside [0, 64]");
     if (c->pc_maxit < 0 || c->pc_maxit > MAX_PCG)
@@ -343,6 +354,18 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     unsigned long long *live = cv.take<unsigned long long>(2 * 8);
     RunSolve *rsolve = cv.take<RunSolve>(sizeof(RunSolve));
     char *part_desc = cv.take<char>(4 * PART_DESC_BYTES);
+    // direct solve: sine transform, right-hand side and its transform, tables
+    FastSolve fs = {};
+    const bool fs_on = c.poisson_mode == PIC_DIRECT;
+    if (fs_on) {
+        const int64_t Mp = fs_pad(c.nz - 1), Np = fs_pad(c.nr);
+        fs.S = cv.take<double>(Mp * Mp * 8);
+        fs.b = cv.take<double>(Mp * Np * 8);
+        fs.bh = cv.take<double>(Mp * Np * 8);
+        fs.ce1 = cv.take<double>(Np * 8);
+        fs.cn1 = cv.take<double>(Np * 8);
+        fs.lam = cv.take<double>(Mp * 8);
+    }
     // learned preconditioner: network, Adam state and activations
     const bool pc_on = c.pc_batch > 0 || c.poisson_mode == PIC_LEARNED;
     PcNet net;
@@ -352,6 +375,8 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
         pc_base = cv.take<char>(pc_bytes(net));
     }
     if (h) {
+        h->fs = fs;
+        h->fs_on = fs_on;
         h->rsolve = rsolve;
         h->part_desc = part_desc;
         h->pc_on = pc_on;
@@ -519,6 +544,19 @@ pic_status setup_field(pic_handle *h)
         if (mg_tail_setup(H) != 0)
             return fail(h, PIC_EHIP, "cannot reserve %d bytes of LDS for the coarse levels",
                         H.tail_lds_bytes);
+    }
+    if (h->fs_on) {
+        if (!fs_separable(c.nr, c.nz, ce.data(), cn.data(), kind.data()))
+            return fail(h, PIC_EINVAL, "the field equation of this grid does not separate");
+        const int Mp = fs_pad(c.nz - 1), Np = fs_pad(c.nr);
+        std::vector<double> S((size_t)Mp * Mp), ce1(Np, 0.0), cn1(Np, 0.0), lam(Mp);
+        fs_tables(c.nr, c.nz, ce.data(), cn.data(), S.data(), ce1.data(), cn1.data(), lam.data());
+        HIPCHECK(h, hipMemcpy((void *)h->fs.S, S.data(), S.size() * 8, hipMemcpyHostToDevice));
+        HIPCHECK(h, hipMemcpy((void *)h->fs.ce1, ce1.data(), Np * 8, hipMemcpyHostToDevice));
+        HIPCHECK(h, hipMemcpy((void *)h->fs.cn1, cn1.data(), Np * 8, hipMemcpyHostToDevice));
+        HIPCHECK(h, hipMemcpy((void *)h->fs.lam, lam.data(), Mp * 8, hipMemcpyHostToDevice));
+        launch_zero(h->fs.b, (int64_t)Mp * Np * 8, h->stream);
+        launch_zero(h->fs.bh, (int64_t)Mp * Np * 8, h->stream);
     }
     launch_zero(h->f.e32, nodes * 4, h->stream);
     launch_zero(h->f.q32b, nodes * 4, h->stream);
@@ -690,7 +728,7 @@ pic_status run_pass(pic_handle *h, double *phi, const Q *q0, const Q *q1, int n_
 // residual, the remaining passes use the multigrid preconditioner.
 template <typename Q>
 pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_cathode,
-                 pic_poisson_stats *st, int mode, bool extrapolate = false)
+                 pic_poisson_stats *st, int mode, bool extrapolate = false, bool sync = true)
 {
     hipStream_t s = h->stream;
     FieldDev &f = h->f;
@@ -702,6 +740,40 @@ pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_
     pic_status pe = PIC_OK;
     pic_poisson_stats S = {};
     launch_solve_prep(f, phi, extrapolate, v_cathode, h->sc, s);
+    if (mode == PIC_DIRECT) {
+        // residual correction with the direct FP64 solve: r = b - K phi,
+        // phi += K^-1 r, and the FP64 residual of the result; a step's solve
+        // keeps the norms on the device (checked there by launch_solve_check),
+        // a synchronous one corrects again while short of the tolerance
+        launch_residual64<Q>(f, phi, q0, q1, h->sc, s, false);
+        launch_fast_solve(h->fs, f, phi, h->sc, s);
+        launch_residual64<Q>(f, phi, q0, q1, h->sc, s, false);
+        S.outer = 1;
+        if (!sync) {
+            launch_solve_check(h->sc, rtol * rtol, s);
+            S.converged = -1;           // known at the next synchronization
+            h->last = S;
+            return PIC_OK;
+        }
+        for (;;) {
+            SolveReadback rb;
+            pe = readback(h, &rb);
+            if (pe != PIC_OK) return pe;
+            S.rel_res = rb.bb > 0.0 ? std::sqrt(rb.rr / rb.bb) : 0.0;
+            S.converged = (std::isfinite(S.rel_res) && S.rel_res <= rtol) ? 1 : 0;
+            if (S.converged || !std::isfinite(S.rel_res) || S.outer == 3) break;
+            launch_fast_solve(h->fs, f, phi, h->sc, s);
+            launch_residual64<Q>(f, phi, q0, q1, h->sc, s, false);
+            S.outer++;
+        }
+        h->last = S;
+        if (st) *st = S;
+        if (!std::isfinite(S.rel_res)) return fail(h, PIC_ENAN, "non-finite residual in the field solve");
+        if (!S.converged)
+            return fail(h, PIC_ENOCONV, "direct field solve left relative residual %.3e (target %.1e)",
+                        S.rel_res, rtol);
+        return PIC_OK;
+    }
     launch_residual64<Q>(f, phi, q0, q1, h->sc, s, false);
     auto rate = [&]() -> double & {
         return mode == PIC_LEARNED ? h->rho_pc : (mode == PIC_CG ? h->rho_cg : h->rho);
@@ -828,7 +900,7 @@ PushParams<T> push_params(pic_handle *h, int deposit_only)
         P.q[s] = (T *)h->q[s];
         P.hqm[s] = (T)(0.5 * c.q[s] / c.m[s] * c.dt);
         P.qw[s] = (T)(c.q[s] * c.w[s]);
-        P.mw[s] = (float)(c.m[s] * c.w[s]);
+        P.mw[s] = c.m[s] * c.w[s];
     }
     P.node = (const typename Vec4<T>::type *)h->node;
     P.sc = h->sc;
@@ -920,8 +992,16 @@ pic_status check_flags(pic_handle *h)
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     h->host_count[0] = counts[0];
     h->host_count[1] = counts[1];
+    h->host_flags = flags;
     if (flags & (FLAG_CAPACITY | FLAG_CHILD_OVERFLOW))
         return fail(h, PIC_ECAPACITY, "particle capacity exceeded (flags %d)", flags);
+    if (flags & FLAG_NOCONV) {
+        // reported once: cleared on the device
+        const int32_t keep = flags & ~FLAG_NOCONV;
+        HIPCHECK(h, hipMemcpyAsync(&h->sc->flags, &keep, 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHECK(h, hipStreamSynchronize(h->stream));
+        return fail(h, PIC_ENOCONV, "a direct field solve missed its residual tolerance");
+    }
     return PIC_OK;
 }
 
@@ -934,7 +1014,7 @@ pic_status field_update(pic_handle *h)
     // the warm start (phi0 extrapolated from the last two steps) is applied
     // by the solve's first kernel
     pic_status st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr,
-                              h->pmode, true);
+                              h->pmode, true, h->pmode != PIC_DIRECT);
     timer_end(h, 3, ev);
     if (st != PIC_OK) return st;
     timer_begin(h, ev, 4);
@@ -1030,7 +1110,9 @@ pic_status step_one(pic_handle *h)
         }
     }
     if (c.field_solve) {
-        if (h->host_flags & (FLAG_CAPACITY | FLAG_CHILD_OVERFLOW))
+        // (the direct solve does not synchronize: pic_step checks the flags
+        // once at the end of the call)
+        if (h->pmode != PIC_DIRECT && (h->host_flags & (FLAG_CAPACITY | FLAG_CHILD_OVERFLOW)))
             return fail(h, PIC_ECAPACITY, "particle capacity exceeded (flags %d)", h->host_flags);
         return PIC_OK;
     }
@@ -1110,7 +1192,8 @@ pic_status init_typed(pic_handle *h, const pic_species_host *init)
     // phi_L: cathode at 1 V, no charge
     launch_begin_step(h->sc, h->q[0], h->q[1], nodes, (int)sizeof(T), s);
     launch_zero(h->f.phi_l, nodes * 8, s);
-    st = solve<T>(h, h->f.phi_l, (const T *)h->q[0], (const T *)h->q[1], 1.0, nullptr, PIC_MGCG);
+    const int init_mode = (h->pmode == PIC_DIRECT) ? PIC_DIRECT : PIC_MGCG;
+    st = solve<T>(h, h->f.phi_l, (const T *)h->q[0], (const T *)h->q[1], 1.0, nullptr, init_mode);
     if (st != PIC_OK) return st;
     // capacitance C = sum over cathode nodes of (K phi_L)
     {
@@ -1135,7 +1218,7 @@ pic_status init_typed(pic_handle *h, const pic_species_host *init)
     launch_zero(h->f.phi0, nodes * 8, s);
     if (c.field_solve) {
         st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr,
-                      PIC_MGCG);
+                      init_mode);
         if (st != PIC_OK) return st;
     }
     launch_extrapolate(h->f, 1, s);
@@ -1575,6 +1658,9 @@ pic_status pic_step(pic_handle *h, int32_t nsteps)
         pic_status st = (h->prec == PIC_F64) ? step_one<double>(h) : step_one<float>(h);
         if (st != PIC_OK) return st;
     }
+    // with the direct solve no step synchronized: capacity, overflow and
+    // solve flags of all the call's steps are read here, once
+    if (nsteps > 0 && h->cfg.field_solve && h->pmode == PIC_DIRECT) return check_flags(h);
     return PIC_OK;
 }
 
@@ -1647,6 +1733,16 @@ pic_status pic_diag(pic_handle *h, pic_diag_out *out)
     out->n_see = (int64_t)sc.n_see;
     out->deposit_fallback = (int64_t)sc.deposit_fallback;
     out->poisson = h->last;
+    if (h->last.converged == -1) {
+        // a step's direct solve: its FP64 residual norms are still on the device
+        double rr = 0.0, bb = 0.0;
+        for (int k = 0; k < ACC_SLOTS; ++k) {
+            rr += sc.res_slots[k * ACC_STRIDE];
+            bb += sc.res_slots[(ACC_SLOTS + k) * ACC_STRIDE];
+        }
+        out->poisson.rel_res = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+        out->poisson.converged = out->poisson.rel_res <= c.poisson_rtol ? 1 : 0;
+    }
     out->flags = sc.flags;
     if (!std::isfinite(w) || !std::isfinite(sc.ke[0]) || !std::isfinite(sc.ke[1]))
         out->flags |= FLAG_NAN;
@@ -1859,10 +1955,12 @@ pic_status pic_pc_apply(pic_handle *h, const double *r_dev, double *z_dev)
 pic_status pic_set_poisson_mode(pic_handle *h, int32_t mode)
 {
     if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
-    if (mode != PIC_MGCG && mode != PIC_LEARNED && mode != PIC_CG)
-        return fail(h, PIC_EINVAL, "mode must be PIC_MGCG, PIC_LEARNED or PIC_CG");
+    if (mode != PIC_MGCG && mode != PIC_LEARNED && mode != PIC_CG && mode != PIC_DIRECT)
+        return fail(h, PIC_EINVAL, "mode must be PIC_MGCG, PIC_LEARNED, PIC_CG or PIC_DIRECT");
     if (mode == PIC_LEARNED && !h->pc_on)
         return fail(h, PIC_ESTATE, "no learned-preconditioner buffers (pc_batch = 0)");
+    if (mode == PIC_DIRECT && !h->fs_on)
+        return fail(h, PIC_ESTATE, "no direct-solve buffers (created with another poisson_mode)");
     h->pmode = mode;
     return PIC_OK;
 }

@@ -732,14 +732,17 @@ __global__ void __launch_bounds__(EB) k_pc_loss(const float *net, const float *t
     block_add(acc, loss);
 }
 
+// Adam (Kingma and Ba) with bias-corrected moments; a1 = 1 - beta1 and
+// a2 = 1 - beta2 are passed rounded from their exact values (1 - 0.999f is
+// 1.3e-5 off 0.001), c1 = 1 - beta1^t and c2 = 1 - beta2^t likewise.
 __global__ void k_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1,
-                       float b2, float eps, float c1, float c2)
+                       float b2, float a1, float a2, float eps, float c1, float c2)
 {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
         const float gt = g[t];
-        const float mt = b1 * m[t] + (1.0f - b1) * gt;
-        const float vt = b2 * v[t] + (1.0f - b2) * gt * gt;
+        const float mt = b1 * m[t] + a1 * gt;
+        const float vt = b2 * v[t] + a2 * gt * gt;
         m[t] = mt;
         v[t] = vt;
         w[t] -= lr * (mt / c1) / (sqrtf(vt / c2) + eps);
@@ -1237,12 +1240,14 @@ void pc_train_enqueue(PcNet &n, const MGLevel &L, int64_t n_unknown, const doubl
     backward(n, B, s);
     if (lr > 0.0f) {
         n.adam_t++;
-        const float b1 = 0.9f, b2 = 0.999f;
-        const float c1 = 1.0f - std::pow(b1, (float)n.adam_t);
-        const float c2 = 1.0f - std::pow(b2, (float)n.adam_t);
+        // beta1 = 0.9, beta2 = 0.999; 1 - beta and the bias corrections
+        // 1 - beta^t in FP64, then rounded (in FP32, 1 - 0.999f^t cancels)
+        const double B1 = 0.9, B2 = 0.999;
+        const float c1 = (float)(1.0 - std::pow(B1, (double)n.adam_t));
+        const float c2 = (float)(1.0 - std::pow(B2, (double)n.adam_t));
         hipLaunchKernelGGL(k_adam, dim3(eblocks(n.n_master)), dim3(EB), 0, s, n.master,
-                           (const float *)n.grad, n.adam_m, n.adam_v, n.n_master, lr, b1, b2, 1e-8f,
-                           c1, c2);
+                           (const float *)n.grad, n.adam_m, n.adam_v, n.n_master, lr, (float)B1,
+                           (float)B2, (float)(1.0 - B1), (float)(1.0 - B2), 1e-8f, c1, c2);
         pc_pack(n, s);
     }
 }

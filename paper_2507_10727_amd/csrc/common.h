@@ -34,7 +34,7 @@ constexpr int MAX_BATCH = 64;
 // microseconds.
 constexpr int ACC_SLOTS = 16, ACC_STRIDE = 8;
 
-enum : int32_t { FLAG_CAPACITY = 1, FLAG_CHILD_OVERFLOW = 2, FLAG_NAN = 4 };
+enum : int32_t { FLAG_CAPACITY = 1, FLAG_CHILD_OVERFLOW = 2, FLAG_NAN = 4, FLAG_NOCONV = 8 };
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
@@ -206,7 +206,7 @@ struct PushParams {
     T dr, inv_dr, inv_dz, dt;
     T hqm[2];                   // q dt / (2 m)
     T qw[2];                    // q w (C per macroparticle)
-    float mw[2];                // m w (kg per macroparticle), diagnostics
+    double mw[2];               // m w (kg per macroparticle), diagnostics
     int32_t frozen_ions, mcc_on, see_on;
     int32_t any_reflect;        // some wall reflects (test configurations)
     int32_t deposit_only;       // 1: only deposit the current positions
@@ -543,6 +543,31 @@ struct FieldDev {
     const double *vdep;         // node volumes for densities
     const int32_t *gate;        // when set and nonzero, the solve's kernels return at once
 };
+
+// ---- direct solve of the separable field equation (fastsolve.hip) -----------
+// Buffers of the sine-transform solve: S (Mp x Mp, the orthonormal sine
+// transform over the nz - 1 unknown rows, zero padded to a multiple of 32),
+// the right-hand side b and its transform bh (Mp x Np, Np = nr padded), the
+// radial and axial couplings of an interior row and the eigenvalues of
+// tridiag(-1, 2, -1).
+struct FastSolve {
+    const double *S;
+    double *b, *bh;
+    const double *ce1, *cn1, *lam;
+};
+int fs_pad(int n);
+// true when the unknowns are exactly i < nr, 0 < j < nz and the couplings
+// are the same on every row (the cathode covers the z = 0 row)
+bool fs_separable(int nr, int nz, const double *ce, const double *cn, const uint8_t *kind);
+void fs_tables(int nr, int nz, const double *ce, const double *cn, double *S, double *ce1,
+               double *cn1, double *lam);
+// phi += K^-1 r on the unknown nodes, r = f.r64 the FP64 residual of phi
+// (written by launch_residual64); also clears sc->res_slots for the residual
+// check that follows
+void launch_fast_solve(const FastSolve &F, const FieldDev &f, double *phi, DevScalars *sc,
+                       hipStream_t s);
+// after a residual: flag FLAG_NOCONV when ||r||^2 > rtol2 ||b||^2 (slotted norms)
+void launch_solve_check(DevScalars *sc, double rtol2, hipStream_t s);
 
 // ---- batched field update of an ensemble ------------------------------------
 

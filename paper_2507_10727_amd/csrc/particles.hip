@@ -709,7 +709,7 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
     }
 
     // ---- block totals of the diagnostics, one atomic per quantity
-    const double mw = (double)P.mw[s];
+    const double mw = P.mw[s];
     double dv[3] = {wave_sum(0.5 * mw * t.ke), wave_sum(mw * t.pz), wave_sum(t.dq)};
     unsigned long long c[10] = {t.abs1, t.abs2, t.abs3, t.abs4, 0, 0, 0, 0, 0, t.fb};
 #pragma unroll

@@ -47,6 +47,7 @@ REFLECT = 1
 POISSON_MGCG = 0       # field-solve preconditioner: multigrid
 POISSON_LEARNED = 1    # learned network (flexible CG)
 POISSON_CG = 2         # none
+POISSON_DIRECT = 3     # direct sine-transform solve (cathode covering z = 0)
 
 
 @dataclasses.dataclass
@@ -93,7 +94,7 @@ class Problem:
     field_solve: int = 1
     extra_current: float = 0.0
     capacity_factor: float = 1.5
-    poisson_mode: int = 0       # 0 multigrid, 1 learned network, 2 none (plain CG)
+    poisson_mode: int = 0       # 0 multigrid, 1 learned network, 2 none (plain CG), 3 direct
     pc_batch: int = 0           # training batch of the learned preconditioner
     pc_maxit: int = 0           # learned iterations before the multigrid fallback
     weight: Optional[float] = None  # macroparticle weight; default n*V/N
@@ -173,6 +174,9 @@ def preset(name: str) -> Problem:
     small_mc64_f64   : 64x64 cells over 2x2 cm, 2e5 e- + 2e5 Ar+, n = 1e15,
                        MC-PIC, FP64 state, cathode fixed at -400 V, 5 mTorr,
                        peak B 0.03 T, 200 steps (the small parity case).
+    All three solve the field with the direct sine-transform solve (their
+    cathode covers the z = 0 row); replace(poisson_mode=...) selects the
+    conjugate-gradient solves.
     ec256x512_f32    : 256x512 cells over 4x8 cm, 1e7 + 1e7, n = 1e16,
                        EC-PIC, FP32 state, -500 V through 100 ohm, 10 mTorr,
                        peak B 0.05 T (the throughput case; mc256x512_f32 is
@@ -181,7 +185,7 @@ def preset(name: str) -> Problem:
                        20 mTorr, -500 V through 10/100 ohm (high-density case).
     """
     if name == "small_mc64_f64":
-        return Problem(name=name)
+        return Problem(name=name, poisson_mode=POISSON_DIRECT)
     if name in ("ec256x512_f32", "mc256x512_f32"):
         return Problem(
             name=name, nr=256, nz=512, lr=0.04, lz=0.08,
@@ -189,7 +193,7 @@ def preset(name: str) -> Problem:
             circuit=RESISTOR, v_ext=-500.0, v_fixed=-500.0, r_ext=100.0,
             p_gas=10e-3 * TORR, b_peak=0.05, density=1e16,
             n_per_species=10_000_000, steps=20000, seed=250710728,
-            capacity_factor=1.25)
+            capacity_factor=1.25, poisson_mode=POISSON_DIRECT)
     if name in ("ec512x1024_f32", "mc512x1024_f32"):
         return Problem(
             name=name, nr=512, nz=1024, lr=0.05, lz=0.10,
@@ -197,7 +201,7 @@ def preset(name: str) -> Problem:
             circuit=RESISTOR, v_ext=-500.0, v_fixed=-500.0, r_ext=100.0,
             p_gas=20e-3 * TORR, b_peak=0.05, density=1e17,
             n_per_species=50_000_000, steps=20000, seed=250710729,
-            capacity_factor=1.1)
+            capacity_factor=1.1, poisson_mode=POISSON_DIRECT)
     raise KeyError(name)
 
 

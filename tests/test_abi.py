@@ -31,10 +31,26 @@ def test_library_exports_all_symbols():
 
 
 def _cfg(**kw):
+    kw = {"poisson_mode": W.POISSON_MGCG, **kw}
     p = W.preset("small_mc64_f64").replace(**kw)
     br, bz = W.magnetron_field(p)
     sig = W.cross_sections()
     return make_config(p, br, bz, sig)
+
+
+def test_direct_mode_accepted_and_sized():
+    """PIC_DIRECT adds the sine transform (Mp^2 doubles) and two transform
+    buffers (Mp Np doubles) to the workspace; Mp, Np are the unknown rows
+    and columns padded to multiples of 32."""
+    lib = L.load()
+    n0, n1 = C.c_int64(), C.c_int64()
+    cfg, keep = _cfg()
+    assert lib.pic_query_workspace(C.byref(cfg), C.byref(n0)) == 0
+    cfg, keep = _cfg(poisson_mode=W.POISSON_DIRECT)
+    assert lib.pic_query_workspace(C.byref(cfg), C.byref(n1)) == 0
+    mp, np_ = 64, 64
+    extra = 8 * (mp * mp + 2 * mp * np_ + 2 * np_ + mp)
+    assert extra <= n1.value - n0.value <= extra + 6 * 256
 
 
 def test_query_workspace_sizes():
@@ -55,6 +71,9 @@ def test_query_workspace_sizes():
     dict(nr=101, nz=101), dict(poisson_mode=5), dict(pc_batch=-1), dict(pc_batch=65),
     dict(pc_maxit=-1), dict(pc_maxit=100000),
     dict(precision=W.F32, nr=2048), dict(precision=W.F32, nz=2048),
+    # the direct solve needs the cathode over the whole z = 0 row
+    dict(poisson_mode=W.POISSON_DIRECT, cathode_rmax=0.85 * 0.02),
+    dict(poisson_mode=W.POISSON_DIRECT, nr=2048, nz=64, lr=0.64),
 ])
 def test_invalid_configs_rejected(bad):
     lib = L.load()

@@ -10,7 +10,7 @@ emission, ids) are the same.
 import numpy as np
 import pytest
 
-from gpu_helpers import gpu_sim, say
+from gpu_helpers import check_sample, gpu_sim, sample_oracle, say
 from paper_2507_10727_amd import _lib as L
 from paper_2507_10727_amd import workloads as W
 
@@ -122,6 +122,34 @@ def test_ensemble_of_two_batches():
         assert abs(da["vc"] - db["vc"]) <= 1e-6 * abs(da["vc"])
         fa, fb = a.fields_host(), batch[k].fields_host()
         assert np.abs(fa["phi"] - fb["phi"]).max() <= 1e-6 * np.abs(fa["phi"]).max()
+    ens.close()
+
+
+def test_ensemble_runs_match_oracle():
+    """A 64-run ensemble of the yield / resistance sweep (particles scaled to
+    2%): after two ensemble steps, a sample of runs 0, 31 and 63 (random
+    streams run = 0, 31, 63; different grids, yields and resistances) is
+    advanced by the oracle from each run's state and fields and compared one
+    by one with the ensemble's next step."""
+    from paper_2507_10727_amd.sim import Ensemble
+    ps = sweep(64, 0.02)
+    ins = [W.inputs(p) for p in ps]
+    batch = [gpu_sim(p, br, bz, sig, parts) for p, (br, bz, sig, parts) in zip(ps, ins)]
+    ens = Ensemble(batch, nstreams=1)
+    ens.step(2)
+    picks = [0, 31, 63]
+    orc = {}
+    for k in picks:
+        br, bz, sig, _ = ins[k]
+        orc[k] = sample_oracle(ps[k], br, bz, sig, batch[k], 5000, 100 + k)
+    ens.step(1)
+    for k in picks:
+        o, ids = orc[k]
+        o.step()
+        p = ps[k]
+        say(f"run {k}: {p.nr}x{p.nz}, gamma {p.gamma_i}, R {p.r_ext}, run field {p.run}")
+        check_sample(p, batch[k], o, ids)
+        assert batch[k].diag()["step"] == 3
     ens.close()
 
 

@@ -10,8 +10,9 @@ import math
 
 import numpy as np
 import pytest
+from tol import approx
 
-from gpu_helpers import compare_particles, gpu_sim, say
+from gpu_helpers import check_mcc_decisions, compare_particles, gpu_sim, say, twin
 from oracle import oracle as O
 from oracle_helpers import empty, species
 from paper_2507_10727_amd import workloads as W
@@ -56,8 +57,11 @@ def test_collisions_match_oracle(precision):
     o.phi[:] = 0.0
     sim.set_phi(np.zeros(nn))
     for step in range(3):
-        if precision == W.F32 and step > 0:
-            # FP32 is compared one step at a time from the GPU's own state
+        pushed = None
+        if precision == W.F32:
+            # FP32 is compared one step at a time from the GPU's own state;
+            # a twin without collisions gives the GPU's pushed velocities,
+            # on which the oracle's decision function is evaluated
             st = sim.get_state()
             parts = []
             for s_ in range(2):
@@ -68,20 +72,31 @@ def test_collisions_match_oracle(precision):
             o.phi[:] = 0.0
             o.state.step = st["step"]
             o.state.next_id[0], o.state.next_id[1] = st["next_id"]
+            pushed = twin(sim, p.replace(mcc_on=0), b[0], b[1], sig, cap)
+            pushed.step(1)
         d_o = o.step()
         sim.step(1)
         d_g = sim.diag()
         say("step", step, "oracle", d_o["n_cand"], d_o["n_coll"], "gpu", d_g["n_cand"], d_g["n_coll"])
-        tol = 1e-12 if precision == W.F64 else 2e-5
-        slack = 0 if precision == W.F64 else 3
-        assert abs(d_g["n_cand"] - d_o["n_cand"]) <= slack
-        for j in range(3):
-            assert abs(d_g["n_coll"][j] - d_o["n_coll"][j]) <= slack
-        for s in range(2):
-            ep, ev, only = compare_particles(p, sim.particles(s), o.particles(s), s, tol,
-                                             max_mismatch=2 * slack)
-            say("  species", s, "pos", ep, "vel", ev, "only-one-side", only)
-            assert ep < tol and ev < tol
+        if precision == W.F64:
+            assert d_g["n_cand"] == d_o["n_cand"] and d_g["n_coll"] == d_o["n_coll"]
+            for s in range(2):
+                ep, ev, only = compare_particles(p, sim.particles(s), o.particles(s), s, 1e-12)
+                say("  species", s, "pos", ep, "vel", ev, "only-one-side", only)
+                assert ep < 1e-12 and ev < 1e-12 and only == 0
+            continue
+        ncand, ncoll, n_band = check_mcc_decisions(o, sim.particles(0), pushed.particles(0),
+                                                   st["next_id"][0], st["step"])
+        assert d_g["n_cand"] == ncand == d_o["n_cand"]
+        assert list(d_g["n_coll"]) == ncoll
+        pushed.close()
+        if n_band == 0:
+            # same decisions: every particle, new ones included, by id
+            assert d_g["n_coll"] == d_o["n_coll"]
+            for s in range(2):
+                ep, ev, only = compare_particles(p, sim.particles(s), o.particles(s), s, 2e-5)
+                say("  species", s, "pos", ep, "vel", ev, "only-one-side", only)
+                assert ep < 2e-5 and ev < 2e-5 and only == 0
     assert d_o["n_coll"][2] > 0 and o.count(1) > 0
 
 
@@ -108,7 +123,7 @@ def test_emission_matches_oracle():
         say("step", step, d_o["n_see"], d_g["n_see"], d_o["dq_conv"], d_g["dq_conv"])
         assert d_g["n_see"] == d_o["n_see"]
         assert d_g["n_abs"][1][1] == d_o["n_abs"][1][1]
-        assert d_g["dq_conv"] == pytest.approx(d_o["dq_conv"], rel=1e-12, abs=1e-25)
+        assert d_g["dq_conv"] == approx(d_o["dq_conv"], rel=1e-12, abs=1e-25)
         for s in range(2):
             ep, ev, only = compare_particles(p, sim.particles(s), o.particles(s), s, 1e-12)
             assert ep < 1e-12 and ev < 1e-12 and only == 0

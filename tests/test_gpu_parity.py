@@ -4,15 +4,20 @@ Particles are compared by id: positions relative to the cell size,
 velocities relative to (v_th,s + |v|); fields relative to their maximum.
 FP64 runs must agree to 1e-12, FP32 runs to 1e-5; integer decisions (which
 particles are absorbed, collide, emit; the ids of new particles) must be
-identical, except for draws whose floating-point comparison falls within
-round-off of its threshold (counted, and bounded by a handful).
+identical.  In FP32 the oracle's decision is taken on the GPU's own
+pre-decision values (collisions: the velocity after the push, from a twin
+run without collisions; cells and walls: the positions), and a different
+outcome is allowed only where that value lies within 4 units in the last
+place of its threshold; such cases are counted and reported.
 """
 import math
 
 import numpy as np
 import pytest
+from tol import approx
 
-from gpu_helpers import to_species, compare_particles, gpu_sim, oracle_from_gpu, say
+from gpu_helpers import (to_species, compare_particles, gpu_sim, oracle_from_gpu, say, twin,
+                         check_mcc_decisions, check_wall_decisions, sample_oracle, check_sample)
 from oracle import oracle as O
 from paper_2507_10727_amd import workloads as W
 
@@ -59,9 +64,28 @@ def test_f64_single_step(scheme):
     assert d_g["n_coll"] == d_o["n_coll"] and d_g["n_cand"] == d_o["n_cand"]
     assert d_g["n_see"] == d_o["n_see"]
     assert [tuple(x) for x in d_g["n_abs"]] == [tuple(x) for x in d_o["n_abs"]]
-    assert d_g["dq_conv"] == pytest.approx(d_o["dq_conv"], rel=1e-12, abs=1e-30)
-    assert d_g["ke"][0] == pytest.approx(d_o["ke"][0], rel=1e-12)
-    assert d_g["w_field"] == pytest.approx(d_o["w_field"], rel=1e-11)
+    assert d_g["dq_conv"] == approx(d_o["dq_conv"], rel=1e-12, abs=1e-30)
+    assert d_g["ke"][0] == approx(d_o["ke"][0], rel=1e-12)
+    # pic_diag's field energy is that of the current (new) potential
+    assert d_g["w_field"] == approx(o.field_energy(o.phi), rel=1e-11)
+    _diag_close(p, d_g, d_o, 1e-12)
+
+
+def _diag_close(p, d_g, d_o, tol):
+    """The observables of the step: peak density of each species, peak
+    potential, cathode current, axial momentum and kinetic energy."""
+    sp = p.species()
+    for s in range(2):
+        say(f"  n_peak[{s}] gpu {d_g['n_peak'][s]:.15e} oracle {d_o['n_peak'][s]:.15e}")
+        assert d_g["n_peak"][s] == approx(d_o["n_peak"][s], rel=tol)
+        # momentum sums cancel: compared against the scale of its terms
+        vt = math.sqrt((p.te_ev if s == 0 else p.ti_ev) * 1.602176634e-19 / sp[s][1])
+        scale = sp[s][1] * sp[s][2] * vt * max(d_g["count"][s], 1)
+        assert abs(d_g["pz"][s] - d_o["pz"][s]) <= tol * scale, (s, d_g["pz"][s], d_o["pz"][s])
+        assert d_g["ke"][s] == approx(d_o["ke"][s], rel=tol)
+    say(f"  phi_max gpu {d_g['phi_max']:.15e} oracle {d_o['phi_max']:.15e}")
+    assert d_g["phi_max"] == approx(d_o["phi_max"], rel=tol, abs=tol * abs(p.v_ext or p.v_fixed))
+    assert d_g["i_cathode"] == approx(d_o["i_cathode"], rel=max(tol, 1e-12), abs=1e-30)
 
 
 def test_f64_small_config_200_steps():
@@ -97,93 +121,134 @@ def test_f64_small_config_200_steps():
     assert st["next_id"] == (o.state.next_id[0], o.state.next_id[1])
 
 
-@pytest.mark.parametrize("scheme", [W.EC_PIC, W.MC_PIC])
-def test_f32_single_step(scheme):
-    p = W.preset("ec256x512_f32").replace(scheme=scheme)
+def _by_id(d, ids):
+    o = np.argsort(d["id"])
+    k = o[np.searchsorted(d["id"][o], ids)]
+    assert np.array_equal(d["id"][k], ids)
+    return {n: v[k] for n, v in d.items()}
+
+
+@pytest.mark.parametrize("scheme,run", [(W.EC_PIC, 0), (W.MC_PIC, 3)])
+def test_f32_single_step(scheme, run):
+    """One FP32 step of the benchmark discharge (256x512, scaled to 4e5 + 4e5
+    particles) against the oracle started from the GPU's own state and
+    potential, in both gather forms and in the random stream of ensemble run
+    `run`.  Decisions follow the parity protocol: the oracle's collision
+    decision (orc_mcc_select) is evaluated on the GPU's own pushed
+    velocities (a twin run without collisions from a bitwise copy of the
+    state) and must equal the GPU's outcome; an absorption decided
+    differently must lie within 4 quanta of the FP32 position word of a wall;
+    either kind of difference is allowed only inside that band."""
+    p = W.preset("ec256x512_f32").replace(scheme=scheme, run=run)
     p = W.scaled(p, 400_000)
     br, bz, sig, parts = W.inputs(p)
-    say("case f32 single step", p.name, scheme)
+    say("case f32 single step", p.name, "scheme", scheme, "run", run)
     sim = gpu_sim(p, br, bz, sig, parts)
-    # the oracle starts from the GPU's own (FP32) state and fields
+    pushed = twin(sim, p.replace(mcc_on=0), br, bz, sig, p.capacity())
+    before = [sim.particles(s) for s in range(2)]
     o = oracle_from_gpu(p, br, bz, sig, sim, rtol=1e-11)
     o.init()
     f = sim.fields_host()
     o.phi[:] = f["phi"]
     o.phi0[:] = f["phi0"]
     st = sim.get_state()
+    o.state.step = st["step"]
     o.state.vc, o.state.qc = st["vc"], st["qc"]
     sim.step(1)
+    pushed.step(1)
     d_o = o.step()
     d_g = sim.diag()
+    ga = [sim.particles(s) for s in range(2)]
+    gb = [pushed.particles(s) for s in range(2)]
+    oa = [o.particles(s) for s in range(2)]
+    n_wall = sum(check_wall_decisions(p, ga[s], oa[s], np.sort(before[s]["id"])) for s in range(2))
+    ncand, ncoll, n_band = check_mcc_decisions(o, ga[0], gb[0], st["next_id"][0], st["step"])
+    assert d_g["n_cand"] == ncand and list(d_g["n_coll"]) == ncoll
+    say("band cases: walls", n_wall, "collisions", n_band)
+    # values: particles whose oracle collision decision on the GPU's pushed
+    # velocity sits within the FP32 tolerance of a threshold are left out
+    # of the value comparison (the oracle decides on its own FP64 push)
+    ids_e = np.sort(gb[0]["id"][gb[0]["id"] < st["next_id"][0]])
+    pb = _by_id(gb[0], ids_e)
+    _, margin = o.mcc_select(ids_e, st["step"], pb["vr"], pb["vt"], pb["vz"])
+    near = set(ids_e[(margin > 0) & (margin < 1e-5)].tolist())
+    say("electrons within 1e-5 of a collision threshold:", len(near))
     for s in range(2):
-        ep, ev, only = compare_particles(p, sim.particles(s), o.particles(s), s, 1e-5,
-                                         max_mismatch=4)
-        say("species", s, "pos", ep, "vel", ev, "mismatch", only)
-        assert ep < 1e-5 and ev < 1e-5
+        g, r = ga[s], oa[s]
+        if near or n_wall:
+            keep = np.intersect1d(g["id"], r["id"])
+            keep = keep[~np.isin(keep, list(near))] if s == 0 else keep
+            keep = keep[keep < st["next_id"][s]]
+            g = {k: v[np.isin(g["id"], keep)] for k, v in g.items()}
+            r = {k: v[np.isin(r["id"], keep)] for k, v in r.items()}
+        ep, ev, only = compare_particles(p, g, r, s, 1e-5)
+        say("species", s, "pos", ep, "vel", ev, "one side only", only)
+        assert ep < 1e-5 and ev < 1e-5 and only == 0
     f = sim.fields_host()
     ephi = np.abs(f["phi"] - o.phi).max() / np.abs(o.phi).max()
     say("phi", ephi, "vc", d_g["vc"], o.state.vc)
     assert ephi < 1e-5
-    assert d_g["vc"] == pytest.approx(o.state.vc, rel=1e-5)
-    for j in range(3):
-        assert abs(d_g["n_coll"][j] - d_o["n_coll"][j]) <= 2
-    assert abs(d_g["n_cand"] - d_o["n_cand"]) <= 2
+    assert d_g["vc"] == approx(o.state.vc, rel=1e-5)
+    if not (n_wall or n_band or near):
+        assert d_g["n_coll"] == d_o["n_coll"] and d_g["n_cand"] == d_o["n_cand"]
+        assert d_g["n_see"] == d_o["n_see"]
+        assert [tuple(x) for x in d_g["n_abs"]] == [tuple(x) for x in d_o["n_abs"]]
+        _diag_close(p, d_g, d_o, 1e-5)
+    sim.close()
+    pushed.close()
 
 
-@pytest.mark.parametrize("name,scheme", [("ec256x512_f32", W.EC_PIC),
-                                         ("ec256x512_f32", W.MC_PIC),
-                                         ("ec512x1024_f32", W.EC_PIC)])
-def test_f32_full_size_sampled(name, scheme):
-    """The FP32 workloads at full size and launch shape (256x512 cells with
-    1e7 electrons + 1e7 Ar+, the benchmark's, in both gather forms; 512x1024
-    cells with 5e7 + 5e7; default blocks): one GPU step of all particles, and
-    a random sample of 20000 per species advanced by the oracle from the same
-    state and fields.  A particle's push, wall handling and collision depend
-    only on its own state, its random stream (id, step) and the fields before
-    the step, so the sampled particles are compared one by one; children
-    (whose ids follow the global order) are left out."""
-    p = W.preset(name).replace(scheme=scheme)
+def test_f32_full_size_collision_decisions():
+    """The benchmark workload at full size (256x512, 1e7 + 1e7, EC-PIC,
+    ensemble stream run = 5): every null-collision decision of the step,
+    for all 1e7 electrons, checked against the oracle's decision function
+    on the GPU's own pushed velocities (twin run without collisions)."""
+    p = W.preset("ec256x512_f32").replace(run=5)
     br, bz, sig, parts = W.inputs(p)
-    say("case f32 full size", p.name, p.n_per_species, "scheme", scheme)
+    say("case f32 full-size collision decisions", p.n_per_species)
     sim = gpu_sim(p, br, bz, sig, parts)
     del parts
     sim.step(2)
-    f = sim.fields_host()
+    pushed = twin(sim, p.replace(mcc_on=0), br, bz, sig, p.capacity())
     st = sim.get_state()
-    rng = np.random.default_rng(11)
-    sample, ids = [], []
-    for s in range(2):
-        g = sim.particles(s)
-        pick = np.sort(rng.choice(g["id"].shape[0], 20000, replace=False))
-        sample.append(to_species({k: g[k][pick] for k in ("r", "z", "vr", "vt", "vz", "id")}))
-        ids.append(g["id"][pick])
-    o = O.Oracle(p, br, bz, sig, sample, capacity=(40000, 40000), rtol=1e-11)
-    o.init()
-    o.phi[:] = f["phi"]
-    o.phi0[:] = f["phi0"]
-    o.set_state(step=st["step"], vc=st["vc"])
-    o.state.qc = st["qc"]
+    sim.step(1)
+    pushed.step(1)
+    d_g = sim.diag()
+    o = O.Oracle(p, br, bz, sig, None, capacity=(16, 16))
+    ncand, ncoll, n_band = check_mcc_decisions(o, sim.particles(0), pushed.particles(0),
+                                               st["next_id"][0], st["step"])
+    assert d_g["n_cand"] == ncand and list(d_g["n_coll"]) == ncoll
+    assert ncand > 100
+    sim.close()
+    pushed.close()
+
+
+@pytest.mark.parametrize("name,scheme,run", [("ec256x512_f32", W.EC_PIC, 0),
+                                             ("ec256x512_f32", W.MC_PIC, 3),
+                                             ("ec512x1024_f32", W.EC_PIC, 0),
+                                             ("ec512x1024_f32", W.MC_PIC, 7)])
+def test_f32_full_size_sampled(name, scheme, run):
+    """The FP32 workloads at full size and launch shape (256x512 cells with
+    1e7 electrons + 1e7 Ar+, the benchmark's; 512x1024 cells with 5e7 +
+    5e7; both gather forms; default blocks; streams of runs 0, 3 and 7):
+    one GPU step of all particles, and a random sample of 20000 per species
+    advanced by the oracle from the same state and fields.  A particle's
+    push, wall handling and collision depend only on its own state, its
+    random stream (id, step) and the fields before the step, so the sampled
+    particles are compared one by one; children (whose ids follow the
+    global order) are left out.  Cells and absorptions must agree except
+    within 4 quanta of the FP32 position word of a cell face or wall."""
+    p = W.preset(name).replace(scheme=scheme, run=run)
+    br, bz, sig, parts = W.inputs(p)
+    say("case f32 full size", p.name, p.n_per_species, "scheme", scheme, "run", run)
+    sim = gpu_sim(p, br, bz, sig, parts)
+    del parts
+    sim.step(2)
+    o, ids = sample_oracle(p, br, bz, sig, sim, 20000, 11 + run)
     sim.step(1)
     o.step()
-    for s in range(2):
-        g = sim.particles(s)
-        keep = np.isin(g["id"], ids[s])
-        g = {k: v[keep] for k, v in g.items()}
-        r = o.particles(s)
-        keep = np.isin(r["id"], ids[s])
-        r = {k: v[keep] for k, v in r.items()}
-        ep, ev, only = compare_particles(p, g, r, s, 1e-5)
-        say("species", s, "sample", len(ids[s]), "kept", g["id"].shape[0], "pos", ep, "vel", ev)
-        assert only == 0 and ep < 1e-5 and ev < 1e-5
-        assert g["id"].shape[0] > 0.99 * len(ids[s])
-        # cells: identical except where FP32 and FP64 land on opposite
-        # sides of a cell edge
-        gi, ri = np.argsort(g["id"]), np.argsort(r["id"])
-        oi = np.floor(r["r"][ri] / p.dr).astype(np.int64)
-        oj = np.floor(r["z"][ri] / p.dz).astype(np.int64)
-        same = np.mean((g["i"][gi] == oi) & (g["j"][gi] == oj))
-        say("species", s, "same cell", same)
-        assert same >= 1 - 1e-3
+    say("band cases", check_sample(p, sim, o, ids))
+    sim.close()
 
 
 def test_deposit_total_charge_f32_f64():
@@ -196,7 +261,7 @@ def test_deposit_total_charge_f32_f64():
         sim.step(2)
         d = sim.diag()
         for s in range(2):
-            assert d["q_dep"][s] == pytest.approx(d["q_expect"][s], rel=tol)
+            assert d["q_dep"][s] == approx(d["q_expect"][s], rel=tol)
 
 
 def test_empty_and_ragged():
@@ -250,7 +315,8 @@ def test_two_level_vcycle_matches_one_level(preset):
     to 1e-5 of its maximum, where a wrong halo or index would be off by
     O(1); full solves take the same iterations and agree to the tolerance."""
     import torch
-    p = W.preset(preset).replace(poisson_rtol=1e-8, n_per_species=0)
+    p = W.preset(preset).replace(poisson_rtol=1e-8, n_per_species=0,
+                                 poisson_mode=W.POISSON_MGCG)
     br, bz, sig, _ = W.inputs(p, n=0)
     say("case", preset)
     kind = O.Oracle(p, br, bz, sig, None, capacity=(16, 16)).node_kind()
@@ -303,9 +369,10 @@ def test_two_level_vcycle_matches_one_level(preset):
 
 
 def test_poisson_standalone_matches_oracle():
-    p = W.preset("ec256x512_f32").replace(poisson_rtol=1e-8, n_per_species=0)
+    p = W.preset("ec256x512_f32").replace(poisson_rtol=1e-8, n_per_species=0,
+                                          poisson_mode=W.POISSON_MGCG)
     br, bz, sig, _ = W.inputs(p, n=0)
-    say("case poisson 256x512")
+    say("case poisson 256x512 (multigrid-preconditioned CG)")
     import torch
     sim = gpu_sim(p, br, bz, sig, None, capacity=(1024, 1024))
     o = O.Oracle(p, br, bz, sig, None, capacity=(16, 16))

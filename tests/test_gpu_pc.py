@@ -226,6 +226,37 @@ def train(sim, p, o, kind, rng, n_pairs=48, steps=150, batch=4, lr=1e-3, seed=7)
     return losses
 
 
+def test_adam_matches_oracle():
+    """Two Adam steps of the GPU (k_adam, FP32 master weights and moments)
+    against the oracle's adam_step fed the GPU's own gradients: the updated
+    weights agree to FP32 rounding of the weights and of the step."""
+    p = problem()
+    say("case pc adam", p.nr, p.nz)
+    sim, o, kind, apply_a = setup(p)
+    rng = np.random.default_rng(23)
+    qs, phis = solved_pairs(p, o, kind, rng, 2)
+    theta = random_theta(8)
+    scale = output_scale(p, kind, qs, phis)
+    sim.pc_set_weights(theta.astype(np.float32), scale)
+    state = {"t": 0, "m": np.zeros_like(theta), "v": np.zeros_like(theta)}
+    ref = theta.copy()
+    for k, lr in enumerate((1e-3, 3e-4)):
+        before, _ = sim.pc_get_weights()
+        _, g = sim.pc_train_step(dev(np.stack(qs)), dev(np.stack(phis)), lr, want_grad=True)
+        after, _ = sim.pc_get_weights()
+        ref = N.adam_step(before.astype(np.float64), g.astype(np.float64), state, lr)
+        step = np.abs(ref - before)
+        err = np.abs(after.astype(np.float64) - ref)
+        # FP32 weights and moments: rounding of the stored weight, and of a
+        # step of at most lr whose moment sums may cancel
+        bound = 4 * np.finfo(np.float32).eps * (np.abs(ref) + lr)
+        say(f"adam step {k}: max |step| {step.max():.3e}, max err {err.max():.3e}, "
+            f"worst err / bound {(err / bound).max():.3f}")
+        assert np.all(err <= bound)
+        assert step.max() > 0.5 * lr
+    sim.close()
+
+
 def test_training_lowers_loss():
     p = problem()
     say("case pc training", p.nr, p.nz)
@@ -302,7 +333,8 @@ def test_timestep_with_learned_preconditioner():
     """A plasma run whose field solves use the learned preconditioner gives
     the multigrid run's potential and particle counts."""
     p = W.preset("small_mc64_f64").replace(n_per_species=20000, steps=3, pc_batch=4,
-                                           poisson_rtol=1e-9, poisson_maxit=512)
+                                           poisson_rtol=1e-9, poisson_maxit=512,
+                                           poisson_mode=W.POISSON_MGCG)
     say("case pc timestep", p.name)
     br, bz, sig, parts = W.inputs(p)
     sims = {}
