@@ -228,6 +228,27 @@ pic_status pic_step(pic_handle *h, int32_t nsteps);
 pic_status pic_poisson(pic_handle *h, const double *q_dev, double v_cathode, double *phi_dev,
                        pic_poisson_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * direct solve of pic_poisson (PIC_DIRECT) whose temporaries -- the FP64
+ * residual, the two transform buffers and the residual norms -- live in a
+ * static device array of the library instead of the handle's workspace.
+ * Same arguments and results as pic_poisson: q_dev node charge (C, FP64),
+ * phi_dev the initial guess on entry (Dirichlet entries overwritten) and
+ * the solution on exit, both (nr+1)(nz+1) device doubles owned by the
+ * caller; stats (host, nullable).  The handle must have been created with
+ * poisson_mode = PIC_DIRECT (else PIC_ESTATE) and its device must be
+ * current (else PIC_EINVAL).  The array holds 32 MiB per GPU (kept until
+ * the process ends); a grid whose solve needs more -- (nr+1)(nz+1) + 2 Mp Np
+ * doubles plus 24 KiB, Mp and Np the unknown rows and columns rounded up to
+ * 32, e.g. 512 x 1024 cells fit, 1024 x 2048 do not -- gives PIC_EINVAL.
+ * It calls no hipMalloc / hipFree and synchronizes the handle's stream.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one
+ * GPU (other threads, other streams) race and must be serialized by the
+ * caller.  Errors: PIC_ENOCONV (stats filled), PIC_EHIP. */
+pic_status pic_poisson_static(pic_handle *h, const double *q_dev, double v_cathode,
+                              double *phi_dev, pic_poisson_stats *stats);
+
 /* out_dev = K phi_dev: the charge-form field operator of the solve (C per V;
  * Section 3's Gauss's law over each node's control volume) on unknown nodes,
  * 0 on Dirichlet nodes; phi_dev's Dirichlet entries are used as given.  FP64

@@ -128,7 +128,7 @@ EXPORTS = [
     "pic_pc_param_count", "pic_pc_set_weights", "pic_pc_get_weights", "pic_pc_train_step",
     "pic_pc_apply", "pic_set_poisson_mode", "pic_apply_operator",
     "pic_ensemble_create", "pic_ensemble_step", "pic_ensemble_free", "pic_ensemble_last_error",
-    "pic_autotune", "pic_set_tuning", "pic_get_tuning",
+    "pic_autotune", "pic_set_tuning", "pic_get_tuning", "pic_poisson_static",
 ]
 
 
@@ -161,6 +161,8 @@ def load():
     L.pic_step.argtypes = [H, C.c_int32]
     L.pic_poisson.argtypes = [H, C.c_void_p, C.c_double, C.c_void_p,
                               C.POINTER(pic_poisson_stats)]
+    L.pic_poisson_static.argtypes = [H, C.c_void_p, C.c_double, C.c_void_p,
+                                     C.POINTER(pic_poisson_stats)]
     L.pic_diag.argtypes = [H, C.POINTER(pic_diag_out)]
     L.pic_particles.argtypes = [H, C.c_int32, C.POINTER(pic_particle_view)]
     L.pic_fields.argtypes = [H, C.POINTER(pic_field_view)]

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -36,6 +37,7 @@ struct pic_handle {
     pic_config cfg;
     std::string err;
     hipStream_t stream = nullptr;
+    int device = 0;                 // the GPU current at pic_init
     char *ws = nullptr;
     int64_t ws_bytes = 0;
     int prec = PIC_F32;
@@ -1591,6 +1593,49 @@ pic_status ensemble_step(pic_ensemble *e)
 
 }  // namespace
 
+// ---- scratch of pic_poisson_static ------------------------------------------
+// A file-scope device array: each GPU the library runs on holds its own copy
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): the device
+// address of each GPU's copy comes from hipGetSymbolAddress, taken once per
+// device with that device current, and only that pointer is used.
+constexpr int64_t STATIC_SCRATCH_BYTES = 32ll << 20;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+char *g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch (nullptr on failure).
+hipError_t scratch_of_device(int dev, char **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = (char *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+// Bytes of scratch a direct solve of the handle's grid takes: scalar block
+// (the residual norms' slots), the FP64 residual, the transform buffers.
+int64_t static_scratch_bytes(const pic_handle *h)
+{
+    const int64_t nodes = (int64_t)(h->cfg.nr + 1) * (h->cfg.nz + 1);
+    const int64_t Mp = fs_pad(h->cfg.nz - 1), Np = fs_pad(h->cfg.nr);
+    auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    return up(sizeof(DevScalars)) + up(nodes * 8) + 2 * up(Mp * Np * 8);
+}
+
+}  // namespace
+
 extern "C" {
 
 pic_status pic_query_workspace(const pic_config *cfg, int64_t *bytes)
@@ -1618,6 +1663,7 @@ pic_status pic_init(const pic_config *cfg, void *workspace_dev, int64_t workspac
     pic_handle *h = new pic_handle();
     h->cfg = *cfg;
     h->stream = (hipStream_t)stream;
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
     h->ws = (char *)workspace_dev;
     h->ws_bytes = workspace_bytes;
     h->prec = cfg->precision;
@@ -1675,6 +1721,69 @@ pic_status pic_poisson(pic_handle *h, const double *q_dev, double v_cathode, dou
                                   h->pmode);
     timer_end(h, 3, ev);
     return st;
+}
+
+pic_status pic_poisson_static(pic_handle *h, const double *q_dev, double v_cathode,
+                              double *phi_dev, pic_poisson_stats *stats)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (!q_dev || !phi_dev) return fail(h, PIC_EINVAL, "q_dev and phi_dev are required");
+    if (!h->fs_on)
+        return fail(h, PIC_ESTATE, "pic_poisson_static needs a handle created with PIC_DIRECT");
+    const int64_t need = static_scratch_bytes(h);
+    if (need > STATIC_SCRATCH_BYTES)
+        return fail(h, PIC_EINVAL,
+                    "grid %d x %d needs %lld bytes of scratch, above the %lld of "
+                    "pic_poisson_static",
+                    h->cfg.nr, h->cfg.nz, (long long)need, (long long)STATIC_SCRATCH_BYTES);
+    int dev = -1;
+    HIPCHECK(h, hipGetDevice(&dev));
+    if (dev != h->device)
+        return fail(h, PIC_EINVAL, "device %d is current; the handle lives on device %d", dev,
+                    h->device);
+    char *base = nullptr;
+    HIPCHECK(h, scratch_of_device(dev, &base));
+    // the solve's temporaries in the scratch; the handle gives the operator
+    // and the transform tables
+    auto up = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    const int64_t nodes = (int64_t)(h->cfg.nr + 1) * (h->cfg.nz + 1);
+    const int64_t Mp = fs_pad(h->cfg.nz - 1), Np = fs_pad(h->cfg.nr);
+    DevScalars *ssc = (DevScalars *)base;
+    FieldDev f = h->f;
+    f.r64 = (double *)(base + up(sizeof(DevScalars)));
+    FastSolve F = h->fs;
+    F.b = (double *)((char *)f.r64 + up(nodes * 8));
+    F.bh = (double *)((char *)F.b + up(Mp * Np * 8));
+    hipStream_t s = h->stream;
+    const double rtol = h->cfg.poisson_rtol;
+    pic_poisson_stats S = {};
+    // Dirichlet values and cleared norms, FP64 residual, then corrections
+    // (as pic_poisson with PIC_DIRECT)
+    launch_solve_prep(f, phi_dev, false, v_cathode, ssc, s);
+    launch_residual64<double>(f, phi_dev, q_dev, nullptr, ssc, s, false);
+    double *pin = (double *)h->pinned;
+    for (;;) {
+        launch_fast_solve(F, f, phi_dev, ssc, s);
+        launch_residual64<double>(f, phi_dev, q_dev, nullptr, ssc, s, false);
+        S.outer++;
+        HIPCHECK(h, hipMemcpyAsync(pin, ssc->res_slots, RES_SLOT_WORDS * sizeof(double),
+                                   hipMemcpyDeviceToHost, s));
+        HIPCHECK(h, hipStreamSynchronize(s));
+        double rr = 0.0, bb = 0.0;
+        for (int k = 0; k < ACC_SLOTS; ++k) {
+            rr += pin[k * ACC_STRIDE];
+            bb += pin[(ACC_SLOTS + k) * ACC_STRIDE];
+        }
+        S.rel_res = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+        S.converged = (std::isfinite(S.rel_res) && S.rel_res <= rtol) ? 1 : 0;
+        if (S.converged || !std::isfinite(S.rel_res) || S.outer == 3) break;
+    }
+    if (stats) *stats = S;
+    if (!std::isfinite(S.rel_res)) return fail(h, PIC_ENAN, "non-finite residual in the field solve");
+    if (!S.converged)
+        return fail(h, PIC_ENOCONV, "direct field solve left relative residual %.3e (target %.1e)",
+                    S.rel_res, rtol);
+    return PIC_OK;
 }
 
 pic_status pic_diag(pic_handle *h, pic_diag_out *out)

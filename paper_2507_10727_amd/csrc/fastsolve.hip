@@ -108,19 +108,20 @@ __global__ void __launch_bounds__(256) k_gemm_f64(const double *__restrict__ A, 
 
 // Right-hand side of the correction equation on the unknown block:
 // B[j-1][i] = r(i, j), the FP64 residual of the current potential, for
-// i < nr, 1 <= j < nz (the padding of B stays zero).  Also clears the
-// residual norms' slots for the check that follows the correction.
+// i < nr, 1 <= j < nz, and zero on the rest of the padded Mp x ldb block
+// (so nothing earlier left in B matters).  Also clears the residual norms'
+// slots for the check that follows the correction.
 __global__ void k_fs_rhs(int32_t nr, int32_t nz, const double *__restrict__ r64,
-                         double *__restrict__ Bm, int ldb, double *__restrict__ res_slots)
+                         double *__restrict__ Bm, int ldb, int Mp, double *__restrict__ res_slots)
 {
     if (blockIdx.x == 0)
         for (int k = threadIdx.x; k < RES_SLOT_WORDS; k += blockDim.x) res_slots[k] = 0.0;
     const int ld = nr + 1;
-    const int64_t total = (int64_t)(nz - 1) * nr;
+    const int64_t total = (int64_t)Mp * ldb;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const int jm = (int)(t / nr), i = (int)(t - (int64_t)jm * nr);
-        Bm[(int64_t)jm * ldb + i] = r64[(int64_t)(jm + 1) * ld + i];
+        const int jm = (int)(t / ldb), i = (int)(t - (int64_t)jm * ldb);
+        Bm[t] = (jm < nz - 1 && i < nr) ? r64[(int64_t)(jm + 1) * ld + i] : 0.0;
     }
 }
 
@@ -241,10 +242,10 @@ void launch_fast_solve(const FastSolve &F, const FieldDev &f, double *phi, DevSc
 {
     const int nr = f.nr, nz = f.nz;
     const int M = nz - 1, Mp = fs_pad(M), Np = fs_pad(nr);
-    const int64_t total = (int64_t)M * nr;
+    const int64_t total = (int64_t)Mp * Np;
     const int rb = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (total + 255) / 256));
     hipLaunchKernelGGL(k_fs_rhs, dim3(rb), dim3(256), 0, s, nr, nz, (const double *)f.r64, F.b,
-                       Np, sc->res_slots);
+                       Np, Mp, sc->res_slots);
     hipLaunchKernelGGL(k_gemm_f64, dim3(Np / GT, Mp / GT), dim3(256), 0, s, F.S, Mp, F.b, Np,
                        F.bh, Np, Mp, 0, M, nr, 0);
     int pt = 64;

@@ -157,6 +157,15 @@ class Simulation:
         L.check(status, self.h)
         return st.as_dict()
 
+    def poisson_static(self, q, v_cathode, phi):
+        """pic_poisson_static: the direct solve with the library's static
+        scratch (allocates nothing); returns (status, stats)."""
+        self.torch.cuda.synchronize(self.device)
+        st = L.pic_poisson_stats()
+        status = self.lib.pic_poisson_static(self.h, C.c_void_p(q.data_ptr()), float(v_cathode),
+                                             C.c_void_p(phi.data_ptr()), C.byref(st))
+        return status, st.as_dict()
+
     def poisson_status(self, q, v_cathode, phi):
         self.torch.cuda.synchronize(self.device)
         st = L.pic_poisson_stats()
