@@ -42,6 +42,7 @@ class Problem(C.Structure):
         ("field_solve", C.c_int32),
         ("extra_current", C.c_double),
         ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int32),
+        ("gamma_e", C.c_double), ("n_meta", C.c_double), ("e_iz_meta", C.c_double),
     ]
 
 
@@ -59,10 +60,11 @@ class Diag(C.Structure):
     _fields_ = [("ke", C.c_double * 2), ("pz", C.c_double * 2), ("w_field", C.c_double),
                 ("q_dep", C.c_double * 2), ("dq_conv", C.c_double), ("qc0", C.c_double),
                 ("n_abs", (C.c_int64 * 5) * 2), ("n_cand", C.c_int64),
-                ("n_coll", C.c_int64 * 3), ("n_see", C.c_int64),
+                ("n_coll", C.c_int64 * 4), ("n_see", C.c_int64),
                 ("n_child", C.c_int64 * 2), ("poisson_iters", C.c_int64),
                 ("poisson_res", C.c_double), ("n_peak", C.c_double * 2),
-                ("phi_max", C.c_double), ("i_cathode", C.c_double)]
+                ("phi_max", C.c_double), ("i_cathode", C.c_double),
+                ("n_see_e", C.c_int64)]
 
     def as_dict(self):
         return {
@@ -72,7 +74,7 @@ class Diag(C.Structure):
             "n_cand": self.n_cand, "n_coll": tuple(self.n_coll), "n_see": self.n_see,
             "n_child": tuple(self.n_child), "poisson_iters": self.poisson_iters,
             "poisson_res": self.poisson_res, "n_peak": tuple(self.n_peak),
-            "phi_max": self.phi_max, "i_cathode": self.i_cathode,
+            "phi_max": self.phi_max, "i_cathode": self.i_cathode, "n_see_e": self.n_see_e,
         }
 
 
@@ -169,6 +171,9 @@ class Oracle:
         P.circuit = prob.circuit
         P.v_fixed, P.v_ext, P.r_ext = prob.v_fixed, prob.v_ext, prob.r_ext
         P.gamma_i = prob.gamma_i
+        P.gamma_e = prob.gamma_e
+        P.n_meta = prob.n_meta
+        P.e_iz_meta = prob.e_iz_meta
         P.p_gas, P.t_gas = prob.p_gas, prob.t_gas
         P.e_exc, P.e_iz = prob.e_exc, prob.e_iz
         P.sigma = _d(self.sigma)
@@ -332,7 +337,7 @@ class Oracle:
         return code, margin
 
     def nu_tables(self):
-        nu = np.zeros((3, self.sigma.shape[1]))
+        nu = np.zeros((4, self.sigma.shape[1]))
         t = C.c_uint64()
         numax = lib().orc_nu_tables(C.byref(self.P), _d(nu), C.byref(t))
         return nu, numax, t.value

@@ -393,7 +393,7 @@ void orc_gather(const orc_problem *p, const double *phi, const double *r, const 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Null-collision Monte Carlo (Section 3, processes (1a)-(1c)).              */
+/* Null-collision Monte Carlo (Section 3, processes (1a)-(1d)).              */
 /* nu_j(E) = n_g sigma_j(E) sqrt(2 e E / m_e) on the table's energies;       */
 /* nu_max = max over table energies of the summed frequency (an upper bound   */
 /* of the piecewise-linear interpolant); P_null = 1 - exp(-nu_max dt).        */
@@ -406,8 +406,11 @@ double orc_nu_tables(const orc_problem *p, double *nu, uint64_t *t_null)
         double e = k * p->de_table;
         double v = sqrt(2.0 * QE * e / p->m[0]);
         double sum = 0.0;
-        for (int c = 0; c < 3; ++c) {
-            nu[c * p->n_table + k] = ng * p->sigma[c * p->n_table + k] * v;
+        for (int c = 0; c < 4; ++c) {
+            /* processes (1a)-(1c) collide with ground-state argon, (1d) with
+             * the static metastable density */
+            double target = (c < 3) ? ng : p->n_meta;
+            nu[c * p->n_table + k] = target * p->sigma[c * p->n_table + k] * v;
             sum += nu[c * p->n_table + k];
         }
         if (sum > numax) numax = sum;
@@ -442,21 +445,28 @@ int orc_mcc_select(const orc_problem *p, const double *nu, double numax, uint64_
     if (margin) *margin = 0.0;
     if ((uint64_t)u[0] >= t_null) return -2;
     const double *nel = nu, *nex = nu + p->n_table, *niz = nu + 2 * p->n_table;
+    const double *nmi = nu + 3 * p->n_table;
     double e = 0.5 * p->m[0] * (vr * vr + vt * vt + vz * vz) / QE;
     double c1 = interp(nel, p->n_table, p->de_table, e);
     double c2 = c1 + interp(nex, p->n_table, p->de_table, e);
     double c3 = c2 + interp(niz, p->n_table, p->de_table, e);
+    double c4 = c3 + interp(nmi, p->n_table, p->de_table, e);
     double rsel = u24(u[1]) * numax;
     int proc = -1;
     if (rsel < c1) proc = 0;
     else if (rsel < c2) proc = (e >= p->e_exc) ? 1 : -1;
     else if (rsel < c3) proc = (e >= p->e_iz) ? 2 : -1;
+    else if (rsel < c4) proc = (e >= p->e_iz_meta) ? 3 : -1;
     if (margin) {
         double m = fabs(rsel - c1) / numax;
         m = fmin(m, fabs(rsel - c2) / numax);
         m = fmin(m, fabs(rsel - c3) / numax);
         m = fmin(m, fabs(e - p->e_exc) / p->e_exc);
         m = fmin(m, fabs(e - p->e_iz) / p->e_iz);
+        if (p->n_meta > 0.0) {
+            m = fmin(m, fabs(rsel - c4) / numax);
+            m = fmin(m, fabs(e - p->e_iz_meta) / p->e_iz_meta);
+        }
         *margin = m;
     }
     return proc;
@@ -466,7 +476,7 @@ void orc_mcc_select_many(const orc_problem *p, int64_t step, int64_t n, const ui
                          const double *vr, const double *vt, const double *vz, int32_t *codes,
                          double *margins)
 {
-    double *nu = malloc(sizeof(double) * 3 * p->n_table);
+    double *nu = malloc(sizeof(double) * 4 * p->n_table);
     uint64_t t_null = 0;
     double numax = orc_nu_tables(p, nu, &t_null);
     for (int64_t k = 0; k < n; ++k)
@@ -613,12 +623,20 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
     orc_nodal_e(p, phi, ern, ezn);
     d->w_field = orc_field_energy(p, phi);
 
-    double *nu = malloc(sizeof(double) * 3 * p->n_table);
+    double *nu = malloc(sizeof(double) * 4 * p->n_table);
     uint64_t t_null = 0;
     double numax = orc_nu_tables(p, nu, &t_null);
-    double see_p = p->gamma_i * p->w[1] / p->w[0];
-    if (see_p > 1.0) see_p = 1.0;
-    uint64_t t_see = (uint64_t)floor(see_p * 4294967296.0);
+    /* emission probability per absorbed particle of species s: yield times
+     * the weight ratio (one electron of weight w_e carries gamma w_s of
+     * emitted charge), capped at 1 */
+    uint64_t t_see[2];
+    for (int s = 0; s < 2; ++s) {
+        double g = (s == 0) ? p->gamma_e : p->gamma_i;
+        double see_p = g * p->w[s] / p->w[0];
+        if (see_p > 1.0) see_p = 1.0;
+        if (see_p < 0.0) see_p = 0.0;
+        t_see[s] = (uint64_t)floor(see_p * 4294967296.0);
+    }
 
     child_list kids = {0, 0, 0};
     double dq = p->extra_current * dt;
@@ -685,14 +703,18 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
                 d->n_abs[s][fate]++;
                 if (fate == 1) {
                     dq += p->q[s] * p->w[s];
-                    if (s == 1 && p->see_on) {
+                    /* secondary emission (Section 3): ions with yield
+                     * gamma_i, electrons with gamma_e, independently; the
+                     * secondary is an electron at rest at (r', 0) */
+                    if (p->see_on && t_see[s] > 0) {
                         uint32_t u[4];
-                        draw(p, S->id[k], 1, PUR_SEE, st->step, u);
-                        if ((uint64_t)u[0] < t_see) {
-                            child c = {child_key(1, S->id[k], 0), 0, r1, 0.0, 0.0, 0.0, 0.0};
+                        draw(p, S->id[k], s, PUR_SEE, st->step, u);
+                        if ((uint64_t)u[0] < t_see[s]) {
+                            child c = {child_key(s, S->id[k], 0), 0, r1, 0.0, 0.0, 0.0, 0.0};
                             push_child(&kids, c);
                             dq -= p->q[0] * p->w[0];
-                            d->n_see++;
+                            if (s == 1) d->n_see++;
+                            else d->n_see_e++;
                         }
                     }
                 }
@@ -727,10 +749,11 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
             } else if (proc == 1) {
                 enew = e - p->e_exc;
             } else {
-                /* ionization: remaining energy split uniformly between the
-                 * scattered and the ejected electron; a new ion at rest-frame
-                 * gas temperature appears at the same place. */
-                double erem = e - p->e_iz;
+                /* ionization from the ground state (2) or from the metastable
+                 * (3): the remaining energy is split uniformly between the
+                 * scattered and the ejected electron; a new ion with the gas
+                 * temperature appears at the same place. */
+                double erem = e - ((proc == 2) ? p->e_iz : p->e_iz_meta);
                 uint32_t ua[4], ub[4];
                 draw(p, S->id[k], 0, PUR_IZ, st->step, ua);
                 draw(p, S->id[k], 0, PUR_ION, st->step, ub);

@@ -39,7 +39,9 @@ typedef struct orc_problem {
     double gamma_i;            /* ion-induced secondary electron yield      */
     double p_gas, t_gas;       /* argon pressure (Pa) and temperature (K)   */
     double e_exc, e_iz;        /* excitation / ionization thresholds (eV)   */
-    const double *sigma;       /* [3][n_table] cross sections (m^2)         */
+    const double *sigma;       /* [4][n_table] cross sections (m^2): elastic,
+                                  excitation, ionization from the ground
+                                  state, ionization from the metastable    */
     int32_t n_table;
     double de_table;           /* table spacing (eV), E_k = k*de            */
     const double *b_r, *b_z;   /* nodal static B (T), index j*(nr+1)+i      */
@@ -51,6 +53,9 @@ typedef struct orc_problem {
     double extra_current;      /* synthetic current into the cathode (A)    */
     double poisson_rtol;
     int32_t poisson_maxit;
+    double gamma_e;            /* electron-induced secondary electron yield */
+    double n_meta;             /* static Ar* (metastable) density (m^-3)    */
+    double e_iz_meta;          /* ionization threshold from Ar* (eV)        */
 } orc_problem;
 
 typedef struct orc_species {
@@ -73,14 +78,16 @@ typedef struct orc_diag {
     double dq_conv;            /* charge delivered to the cathode this step */
     double qc0;                /* induced cathode charge of phi0            */
     int64_t n_abs[2][5];       /* absorbed per species by wall code 1..4    */
-    int64_t n_cand, n_coll[3]; /* null-collision candidates; el, ex, iz     */
-    int64_t n_see;
+    int64_t n_cand, n_coll[4]; /* null-collision candidates; el, ex, iz,
+                                  iz from Ar*                              */
+    int64_t n_see;             /* ion-induced secondary electrons          */
     int64_t n_child[2];
     int64_t poisson_iters;
     double poisson_res;
     double n_peak[2];          /* max over nodes of Q_s / (q_s V_node) after the deposit */
     double phi_max;            /* max over nodes of the new phi             */
     double i_cathode;          /* dq_conv / dt                              */
+    int64_t n_see_e;           /* electron-induced secondary electrons      */
 } orc_diag;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
@@ -108,12 +115,12 @@ void orc_deposit(const orc_problem *p, const double *r, const double *z, int64_t
 void orc_gather(const orc_problem *p, const double *phi, const double *r, const double *z,
                 int64_t n, double *er, double *ez, double *br, double *bz);
 
-/* Collision tables: nu[3][n_table] (1/s), returns nu_max; *t_null = floor(P_null 2^32). */
+/* Collision tables: nu[4][n_table] (1/s), returns nu_max; *t_null = floor(P_null 2^32). */
 double orc_nu_tables(const orc_problem *p, double *nu, uint64_t *t_null);
 
 /* The null-collision decision of one electron with velocity v (after the
  * push) at step `step`: -2 not a candidate, -1 null collision, 0 elastic,
- * 1 excitation, 2 ionization.  *margin (nullable) receives the smallest
+ * 1 excitation, 2 ionization from the ground state, 3 from the metastable.  *margin (nullable) receives the smallest
  * relative distance of the floating-point comparisons that decide the
  * process: |R - cumulative nu_k| / nu_max and |E - E_threshold| / E_threshold
  * (0 when the electron is not a candidate: that test is an integer one). */

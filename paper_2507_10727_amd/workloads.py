@@ -72,6 +72,9 @@ class Problem:
     v_ext: float = -400.0
     r_ext: float = 100.0
     gamma_i: float = 0.1
+    gamma_e: float = 0.0        # electron-induced yield (Section 3: 0.1)
+    n_meta: float = 0.0         # static Ar* density (Section 3: 2.5e17 m^-3)
+    e_iz_meta: float = 4.20     # ionization threshold from Ar* (eV)
     p_gas: float = 5e-3 * TORR
     t_gas: float = 300.0
     e_exc: float = 11.5
@@ -292,23 +295,27 @@ N_TABLE = 20001
 DE_TABLE = 0.05  # eV
 
 
-def cross_sections(e_exc=11.5, e_iz=15.76, n=N_TABLE, de=DE_TABLE):
+def cross_sections(e_exc=11.5, e_iz=15.76, n=N_TABLE, de=DE_TABLE, e_iz_meta=4.20):
     """Tabulated cross sections (m^2) at E_k = k*de eV, k = 0..n-1.
 
-    Rows: elastic, excitation, ionization.  Smooth analytic forms in the
-    magnitude range of e-Ar data: an elastic curve peaking near 10-15 eV, a
-    Thomson-like excitation and a Lotz ionization.  Both inelastic forms vanish
-    at and below threshold.
+    Rows: elastic, excitation, ionization from the ground state, ionization
+    from the metastable Ar* (Section 3's processes (1a)-(1d)).  Smooth
+    analytic forms in the magnitude range of e-Ar data: an elastic curve
+    peaking near 10-15 eV, a Thomson-like excitation and Lotz ionization
+    (ground state: 6 outer electrons at 15.76 eV; metastable: the one excited
+    electron at 4.20 eV).  The inelastic forms vanish at and below threshold.
     """
     e = np.arange(n, dtype=np.float64) * de
     el = 1.5e-19 * (e / 12.0) ** 1.2 / (1.0 + (e / 12.0) ** 2.2) + 2.0e-21
     el = el + 1.0e-20 / (1.0 + e)  # low-energy floor
     x = np.where(e > e_exc, e / e_exc, 1.0)
     ex = np.where(e > e_exc, 3.0e-20 * np.log(x) / x, 0.0)
-    # Lotz: sigma = a q ln(E/I) / (E I), a = 4.5e-18 eV^2 m^2, q = 6
+    # Lotz: sigma = a q ln(E/I) / (E I), a = 4.5e-18 eV^2 m^2, q outer electrons
     y = np.where(e > e_iz, e, e_iz)
     iz = np.where(e > e_iz, 4.5e-18 * 6.0 * np.log(y / e_iz) / (y * e_iz), 0.0)
-    return np.ascontiguousarray(np.stack([el, ex, iz]))
+    ym = np.where(e > e_iz_meta, e, e_iz_meta)
+    izm = np.where(e > e_iz_meta, 4.5e-18 * 1.0 * np.log(ym / e_iz_meta) / (ym * e_iz_meta), 0.0)
+    return np.ascontiguousarray(np.stack([el, ex, iz, izm]))
 
 
 # ---------------------------------------------------------------------------
@@ -383,6 +390,6 @@ def thermal_box(nr: int, nz: int, cell: float, ppc: int, scheme: int, precision:
 def inputs(p: Problem, n: Optional[int] = None):
     """Everything a run needs: (B_r, B_z, sigma table, [electrons, ions])."""
     br, bz = magnetron_field(p)
-    sig = cross_sections(p.e_exc, p.e_iz)
+    sig = cross_sections(p.e_exc, p.e_iz, e_iz_meta=p.e_iz_meta)
     parts = load_uniform(p, n)
     return br, bz, sig, parts

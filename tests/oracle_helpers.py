@@ -19,7 +19,7 @@ def make_oracle(p, parts=None, b=None, capacity=None, sigma=None):
         bz = np.zeros(nn)
     else:
         br, bz = b
-    sig = W.cross_sections(p.e_exc, p.e_iz) if sigma is None else sigma
+    sig = W.cross_sections(p.e_exc, p.e_iz, e_iz_meta=p.e_iz_meta) if sigma is None else sigma
     if parts is None:
         parts = [W.SpeciesArrays(*(np.zeros(0) for _ in range(5)), np.zeros(0, np.uint32))
                  for _ in range(2)]

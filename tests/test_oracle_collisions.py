@@ -232,3 +232,129 @@ def test_restart_bitexact():
         for k in x:
             assert np.array_equal(x[k], y[k]), (s, k)
     assert np.array_equal(a.phi, c.phi)
+
+
+# ---- Section 3's electron-induced emission and metastable ionization (1d)
+
+def test_electron_induced_emission():
+    """Electrons absorbed on the cathode emit with yield gamma_e, independently
+    of the ion-induced yield: emitted = Bernoulli per hit from the published
+    generator (species 0 stream), secondaries at rest on z = 0 under their
+    parent, ids in (parent species, parent id) order (electron parents
+    first), and the cathode tally nets the absorbed and emitted charge."""
+    n = 20000
+    ge, gi = 0.3, 0.1
+    p = _beam_problem(gamma_i=gi, gamma_e=ge, see_on=1, frozen_ions=0, mcc_on=0, nr=16, nz=16)
+    rng = np.random.default_rng(15)
+    re_ = 0.018 * rng.random(n)
+    ri = 0.018 * rng.random(n)
+    elec = species(re_, 1e-9, 0.0, 0.0, -1e6)
+    ions = species(ri, 1e-9, 0.0, 0.0, -1e4)
+    o = make_oracle(p, [elec, ions], capacity=(4 * n, n))
+    o.init()
+    o.phi[:] = 0
+    d = o.step()
+    assert d["n_abs"][0][1] == n and d["n_abs"][1][1] == n
+    key = [p.seed & 0xffffffff, p.seed >> 32]
+    thr_e = math.floor(ge * 2**32)
+    thr_i = math.floor(gi * 2**32)
+    emit_e = [pid for pid in range(n) if int(O.philox([pid, (0 << 4) | 3, 0, 0], key)[0]) < thr_e]
+    emit_i = [pid for pid in range(n) if int(O.philox([pid, (1 << 4) | 3, 0, 0], key)[0]) < thr_i]
+    assert d["n_see_e"] == len(emit_e) and d["n_see"] == len(emit_i)
+    assert abs(len(emit_e) - n * ge) < 5 * math.sqrt(n * ge * (1 - ge))
+    e = o.particles(0)
+    # ids: consecutive from next_id (= n), electron parents first, then ions
+    assert list(e["id"]) == list(range(n, n + len(emit_e) + len(emit_i)))
+    assert np.allclose(e["r"], np.concatenate([re_[emit_e], ri[emit_i]]), rtol=0, atol=1e-18)
+    assert (e["z"] == 0).all() and (e["vr"] == 0).all() and (e["vt"] == 0).all() and (e["vz"] == 0).all()
+    w = p.species()[0][2]
+    expect = (-n + len(emit_e)) * QE * w + (n + len(emit_i)) * QE * w
+    assert d["dq_conv"] == approx(expect, rel=1e-12)
+
+
+def _beam_meta(n, e0, seed, **kw):
+    base = dict(dt=2e-9, p_gas=30e-3 * W.TORR, n_meta=5e19,
+                wall_bc=(W.REFLECT, W.REFLECT, W.REFLECT))
+    base.update(kw)
+    p = _beam_problem(**base)
+    beam = _beam(n, e0, seed=seed)
+    o = make_oracle(p, [beam, empty()], capacity=(3 * n, 2 * n))
+    o.init()
+    o.phi[:] = 0
+    return p, beam, o
+
+
+def test_metastable_ionization_counts_binomial():
+    """Below the excitation threshold (8 eV) only elastic scattering and
+    ionization from Ar* (4.20 eV) can happen: per-process counts ~
+    Binomial(N, P_null nu_j / nu_max), nu_1d = n_meta sigma_1d v."""
+    e0 = 8.0
+    n = 200_000
+    p, beam, o = _beam_meta(n, e0, 16, dt=2e-10)
+    d = o.step()
+    nu, numax, tnull = o.nu_tables()
+    k = int(round(e0 / 0.05))
+    pnull = tnull / 2**32
+    assert d["n_coll"][1] == 0 and d["n_coll"][2] == 0
+    v = math.sqrt(2 * QE * e0 / ME)
+    assert nu[3, k] == approx(p.n_meta * o.sigma[3, k] * v, rel=1e-12)
+    for j in (0, 3):
+        prob = pnull * nu[j, k] / numax
+        mean, sd = n * prob, math.sqrt(n * prob * (1 - prob))
+        assert abs(d["n_coll"][j] - mean) < 5 * sd + 1, (j, d["n_coll"][j], mean)
+    assert d["n_coll"][3] > 100
+    assert d["n_child"] == (d["n_coll"][3], d["n_coll"][3])
+
+
+def test_metastable_ionization_energetics():
+    """Each (1d) event removes exactly 4.20 eV: the scattered and the ejected
+    electron share E - 4.20 (uniform split), the new ion sits at the parent's
+    position."""
+    e0 = 9.0
+    n = 50_000
+    p, beam, o = _beam_meta(n, e0, 17, n_meta=3e20)
+    d = o.step()
+    a = o.particles(0)
+    ion = o.particles(1)
+    assert d["n_coll"][3] > 1000 and d["n_coll"][2] == 0
+    e = _energy(a)
+    old = a["id"] < n
+    new = ~old
+    # the ejected electron of parent p is the k-th child: ids follow parent order
+    parents = np.array(sorted(pid for pid in a["id"][old]
+                              if abs(e0 - e[np.flatnonzero(a["id"] == pid)[0]]) > 1.0))
+    assert parents.size == d["n_coll"][3] == new.sum() == ion["id"].shape[0]
+    ej = e[new][np.argsort(a["id"][new])]
+    sc = np.array([e[np.flatnonzero(a["id"] == pid)[0]] for pid in parents])
+    assert np.allclose(sc + ej, e0 - 4.20, rtol=0, atol=1e-12 * e0)
+    # (the collision follows the push: the parent's position after the step)
+    pos = {int(i): (r, z) for i, r, z in zip(a["id"], a["r"], a["z"])}
+    ir = np.array([pos[int(pid)][0] for pid in parents])
+    iz = np.array([pos[int(pid)][1] for pid in parents])
+    io = np.argsort(ion["id"])
+    assert np.array_equal(ion["r"][io], ir) and np.array_equal(ion["z"][io], iz)
+
+
+def test_mcc_decisions_bruteforce_with_metastable():
+    """With Ar* present, a 40 eV beam's decisions re-derived from the
+    generator: R = U24(u1) nu_max against nu_el, + nu_ex, + nu_iz, + nu_1d."""
+    e0 = 40.0
+    n = 3000
+    p, beam, o = _beam_meta(n, e0, 18, n_meta=3e20)
+    nu, numax, tnull = o.nu_tables()
+    k = int(round(e0 / 0.05))
+    c = np.cumsum(nu[:, k])
+    key = [p.seed & 0xffffffff, p.seed >> 32]
+    expect = []
+    for pid in range(n):
+        u = O.philox([pid, 0, 0, 0], key)
+        if int(u[0]) >= tnull:
+            expect.append(-2)
+            continue
+        x = (int(u[1]) >> 8) / 2**24 * numax
+        expect.append(next((j for j in range(4) if x < c[j]), -1))
+    code, margin = o.mcc_select(beam.id, 0, beam.vr, beam.vt, beam.vz)
+    assert list(code) == expect
+    assert sum(1 for x in expect if x == 3) > 20
+    d = o.step()
+    assert list(d["n_coll"]) == [expect.count(j) for j in range(4)]
