@@ -83,9 +83,10 @@ typedef struct pic_config {
     double gamma_i;             /* ion-induced secondary electron yield           */
     double p_gas, t_gas;        /* argon pressure (Pa), temperature (K)           */
     double e_exc, e_iz;         /* excitation, ionization thresholds (eV)         */
-    const double *sigma;        /* host [3][n_table]: elastic, excitation,
-                                   ionization cross sections (m^2) at
-                                   E_k = k * de_table eV                          */
+    const double *sigma;        /* host [4][n_table]: elastic, excitation,
+                                   ionization from the ground state and from
+                                   the metastable Ar* (Section 3's (1a)-(1d)),
+                                   cross sections (m^2) at E_k = k * de_table eV */
     int32_t n_table;            /* >= 2                                           */
     double de_table;            /* eV                                             */
     const double *b_r, *b_z;    /* host nodal static magnetic field (T)           */
@@ -108,6 +109,11 @@ typedef struct pic_config {
     int32_t pc_maxit;           /* cap on learned-preconditioner iterations per
                                    solve before the multigrid fallback
                                    (0: poisson_maxit)                             */
+    double gamma_e;             /* electron-induced secondary electron yield
+                                   (Section 3: 0.1, independent of gamma_i)      */
+    double n_meta;              /* static metastable Ar* density (m^-3), the
+                                   target of process (1d) (Section 3: 2.5e17)    */
+    double e_iz_meta;           /* ionization threshold from Ar* (eV, 4.20)      */
 } pic_config;
 
 /* Initial particles of one species (host, FP64, absolute positions).
@@ -176,13 +182,15 @@ typedef struct pic_diag_out {
     double phi_max;             /* max over nodes of phi                          */
     int64_t n_abs[2][5];        /* absorbed in the last step by wall code 1..4:
                                    cathode, Neumann block, outer r, anode        */
-    int64_t n_cand, n_coll[3];  /* null-collision candidates; el, ex, iz          */
-    int64_t n_see;
+    int64_t n_cand, n_coll[4];  /* null-collision candidates; el, ex, iz, iz from
+                                   the metastable                               */
+    int64_t n_see;              /* ion-induced secondary electrons               */
     int64_t n_child[2];
     int64_t deposit_fallback;   /* wavefront chunks (256 particles) whose charge
                                    did not fit the LDS tile (global atomics)      */
     pic_poisson_stats poisson;  /* last field solve                               */
     int32_t flags;              /* bit 0 capacity, bit 1 child overflow, bit 2 NaN */
+    int64_t n_see_e;            /* electron-induced secondary electrons          */
 } pic_diag_out;
 
 /* Scalar state for checkpoint/resume (particle and field arrays are read and

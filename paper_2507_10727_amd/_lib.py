@@ -49,6 +49,7 @@ class pic_config(C.Structure):
         ("field_solve", C.c_int32),
         ("extra_current", C.c_double),
         ("pc_batch", C.c_int32), ("pc_maxit", C.c_int32),
+        ("gamma_e", C.c_double), ("n_meta", C.c_double), ("e_iz_meta", C.c_double),
     ]
 
 
@@ -87,9 +88,10 @@ class pic_diag_out(C.Structure):
         ("vc", C.c_double), ("qc", C.c_double), ("cap_c", C.c_double),
         ("n_peak", C.c_double * 2), ("phi_max", C.c_double),
         ("n_abs", (C.c_int64 * 5) * 2),
-        ("n_cand", C.c_int64), ("n_coll", C.c_int64 * 3), ("n_see", C.c_int64),
+        ("n_cand", C.c_int64), ("n_coll", C.c_int64 * 4), ("n_see", C.c_int64),
         ("n_child", C.c_int64 * 2), ("deposit_fallback", C.c_int64),
         ("poisson", pic_poisson_stats), ("flags", C.c_int32),
+        ("n_see_e", C.c_int64),
     ]
 
     def as_dict(self):

@@ -61,7 +61,7 @@ struct pic_handle {
     unsigned long long *live = nullptr;
     std::vector<LevelShape> levels;
     double numax = 0.0;
-    unsigned long long t_null = 0, t_see = 0;
+    unsigned long long t_null = 0, t_see[2] = {0, 0};
     int64_t host_count[2] = {0, 0};
     int steps_since_sort = 0;
     pic_poisson_stats last = {};
@@ -219,6 +219,8 @@ pic_status validate(const pic_config *c, pic_handle *h)
         return fail(h, PIC_EINVAL, "pc_maxit outside [0, %d]", MAX_PCG);
     if (c->gamma_i < 0 || c->p_gas < 0 || !(c->t_gas > 0))
         return fail(h, PIC_EINVAL, "gamma_i, p_gas >= 0 and t_gas > 0 required");
+    if (!(c->gamma_e >= 0) || !(c->n_meta >= 0) || !(c->e_iz_meta > 0))
+        return fail(h, PIC_EINVAL, "gamma_e, n_meta >= 0 and e_iz_meta > 0 required");
     for (int k = 0; k < 3; ++k)
         if (c->wall_bc[k] != PIC_ABSORB && c->wall_bc[k] != PIC_REFLECT)
             return fail(h, PIC_EINVAL, "bad wall_bc[%d]", k);
@@ -282,7 +284,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     void *q1 = cv.take<char>(nodes * ts);
     const size_t child_bytes = (ts == 8) ? sizeof(Child<double>) : sizeof(Child<float>);
     void *child = cv.take<char>((int64_t)child_cap * child_bytes);
-    void *nu = cv.take<char>((int64_t)3 * c.n_table * ts);
+    void *nu = cv.take<char>((int64_t)4 * c.n_table * ts);
     void *cold = cv.take<char>(sizeof(PushCold<double>));
     const int64_t ev_cap = std::max<int64_t>(1024, std::max(cap0, cap1));
     int2 *mcc_q = cv.take<int2>(ev_cap * 8);
@@ -877,13 +879,15 @@ PushCold<T> push_cold(pic_handle *h)
     C.n_table = c.n_table;
     C.inv_de = (T)(1.0 / c.de_table);
     C.numax = (T)h->numax;
-    C.t_see = h->t_see;
+    C.t_see[0] = h->t_see[0];
+    C.t_see[1] = h->t_see[1];
     const double qe = 1.602176634e-19;
     C.e_of_v2 = (T)(0.5 * c.m[0] / qe);
     C.v2_of_e = (T)(2.0 * qe / c.m[0]);
     C.two_m_over_M = (T)(2.0 * c.m[0] / c.m[1]);
     C.e_exc = (T)c.e_exc;
     C.e_iz = (T)c.e_iz;
+    C.e_iz_meta = (T)c.e_iz_meta;
     C.sig_ion = (T)std::sqrt(1.380649e-23 * c.t_gas / c.m[1]);
     for (int s = 0; s < 2; ++s) C.qw64[s] = c.q[s] * c.w[s];
     for (int k = 0; k < 3; ++k) C.wall_bc[k] = c.wall_bc[k];
@@ -919,7 +923,7 @@ PushParams<T> push_params(pic_handle *h, int deposit_only)
     P.dt = (T)c.dt;
     P.frozen_ions = c.frozen_ions;
     P.mcc_on = c.mcc_on;
-    P.see_on = c.see_on;
+    for (int s = 0; s < 2; ++s) P.emit[s] = (c.see_on && h->t_see[s] > 0) ? 1 : 0;
     P.any_reflect = (c.wall_bc[0] == PIC_REFLECT || c.wall_bc[1] == PIC_REFLECT ||
                      c.wall_bc[2] == PIC_REFLECT) ? 1 : 0;
     P.deposit_only = deposit_only;
@@ -1130,9 +1134,10 @@ pic_status init_typed(pic_handle *h, const pic_species_host *init)
     const pic_config &c = h->cfg;
     hipStream_t s = h->stream;
     // collision tables
-    std::vector<double> nu((size_t)3 * c.n_table);
+    std::vector<double> nu((size_t)4 * c.n_table);
     h->numax = host_nu_tables(c, nu.data(), &h->t_null);
-    h->t_see = host_see_threshold(c);
+    h->t_see[0] = host_see_threshold(c, 0);
+    h->t_see[1] = host_see_threshold(c, 1);
     std::vector<T> nut(nu.begin(), nu.end());
     HIPCHECK(h, hipMemcpy(h->nu, nut.data(), nut.size() * sizeof(T), hipMemcpyHostToDevice));
     pic_status st = setup_field(h);
@@ -1838,8 +1843,9 @@ pic_status pic_diag(pic_handle *h, pic_diag_out *out)
     out->qc = sc.qc;
     out->cap_c = sc.cap_c;
     out->n_cand = (int64_t)sc.n_cand;
-    for (int k = 0; k < 3; ++k) out->n_coll[k] = (int64_t)sc.n_coll[k];
+    for (int k = 0; k < 4; ++k) out->n_coll[k] = (int64_t)sc.n_coll[k];
     out->n_see = (int64_t)sc.n_see;
+    out->n_see_e = (int64_t)sc.n_see_e;
     out->deposit_fallback = (int64_t)sc.deposit_fallback;
     out->poisson = h->last;
     if (h->last.converged == -1) {

@@ -56,7 +56,7 @@ struct DevScalars {
     double dq_conv;             // charge into the cathode this step
     double ke[2], pz[2];
     unsigned long long n_abs[2][5];
-    unsigned long long n_cand, n_coll[3], n_see;
+    unsigned long long n_cand, n_coll[4], n_see, n_see_e;
     unsigned long long deposit_fallback;
     double vc, qc, cap_c, qc0;
     // sort
@@ -179,14 +179,15 @@ template <typename T>
 struct PushCold {
     Child<T> *child;
     int32_t child_cap;
-    const T *nu;                // [3][n_table] collision frequencies (1/s)
+    const T *nu;                // [4][n_table] collision frequencies (1/s)
     int32_t n_table;
     T inv_de, numax;
-    unsigned long long t_see;
+    unsigned long long t_see[2];  // emission thresholds per absorbed species
     T e_of_v2;                  // m_e / (2 e): eV per (m/s)^2
     T v2_of_e;                  // 2 e / m_e
     T two_m_over_M;             // elastic energy-loss factor 2 m_e / M
-    T e_exc, e_iz, sig_ion;     // thresholds (eV); ion thermal speed sqrt(kT/M)
+    T e_exc, e_iz, e_iz_meta;   // thresholds (eV): excitation, ionization (1c), (1d)
+    T sig_ion;                  // new-ion thermal speed sqrt(kT/M)
     double qw64[2];             // q w in FP64 for the cathode tally
     int32_t wall_bc[3];
     T cathode_rmax;
@@ -207,7 +208,8 @@ struct PushParams {
     T hqm[2];                   // q dt / (2 m)
     T qw[2];                    // q w (C per macroparticle)
     double mw[2];               // m w (kg per macroparticle), diagnostics
-    int32_t frozen_ions, mcc_on, see_on;
+    int32_t frozen_ions, mcc_on;
+    int32_t emit[2];            // absorbed particles of the species may emit
     int32_t any_reflect;        // some wall reflects (test configurations)
     int32_t deposit_only;       // 1: only deposit the current positions
     uint32_t key0, key1, run;
@@ -689,7 +691,7 @@ void launch_extrapolate(const FieldDev &f, int first, hipStream_t s);
 
 // host_tables.cpp (FP64 host arithmetic, built without FMA contraction)
 double host_nu_tables(const pic_config &c, double *nu, unsigned long long *t_null);
-unsigned long long host_see_threshold(const pic_config &c);
+unsigned long long host_see_threshold(const pic_config &c, int species);
 void host_couplings(int nr, int nz, double lr, double lz, double scale, double *ce, double *cn);
 int host_node_kind(int nr, int nz, double lr, double cathode_rmax, int i, int j);
 int host_dense_inverse(int n, double *a);   // in place, returns 0 on success

@@ -17,8 +17,9 @@ constexpr double kPi = 3.14159265358979323846;
 }  // namespace
 
 // Null-collision tables (Section 3's processes (1a)-(1c) against a static
-// argon background of density n_g = p / (k_B T)):
-//   nu_c(E_k) = n_g sigma_c(E_k) v(E_k),  v = sqrt(2 e E / m_e),
+// argon background of density n_g = p / (k_B T), (1d) against the static
+// metastable density n_meta):
+//   nu_c(E_k) = n_c sigma_c(E_k) v(E_k),  v = sqrt(2 e E / m_e),
 //   nu_max   = max_k sum_c nu_c(E_k)  (bounds the piecewise-linear interpolant),
 //   t_null   = floor((1 - exp(-nu_max dt)) 2^32)  (candidate iff u0 < t_null).
 double host_nu_tables(const pic_config &c, double *nu, unsigned long long *t_null)
@@ -29,8 +30,9 @@ double host_nu_tables(const pic_config &c, double *nu, unsigned long long *t_nul
         const double e = k * c.de_table;
         const double v = std::sqrt(2.0 * kQe * e / c.m[0]);
         double sum = 0.0;
-        for (int p = 0; p < 3; ++p) {
-            nu[p * c.n_table + k] = ng * c.sigma[p * c.n_table + k] * v;
+        for (int p = 0; p < 4; ++p) {
+            const double target = (p < 3) ? ng : c.n_meta;
+            nu[p * c.n_table + k] = target * c.sigma[p * c.n_table + k] * v;
             sum += nu[p * c.n_table + k];
         }
         if (sum > numax) numax = sum;
@@ -40,11 +42,12 @@ double host_nu_tables(const pic_config &c, double *nu, unsigned long long *t_nul
     return numax;
 }
 
-// Emission threshold: an absorbed ion emits one electron iff its draw
-// u0 < floor(min(1, gamma w_i / w_e) 2^32).
-unsigned long long host_see_threshold(const pic_config &c)
+// Emission threshold: an absorbed particle of species s (yield gamma_e for
+// electrons, gamma_i for ions) emits one electron iff its draw
+// u0 < floor(min(1, gamma w_s / w_e) 2^32).
+unsigned long long host_see_threshold(const pic_config &c, int species)
 {
-    double p = c.gamma_i * c.w[1] / c.w[0];
+    double p = (species == 0 ? c.gamma_e : c.gamma_i) * c.w[species] / c.w[0];
     if (p > 1.0) p = 1.0;
     if (p < 0.0) p = 0.0;
     return (unsigned long long)std::floor(p * 4294967296.0);

@@ -230,14 +230,16 @@ __device__ __forceinline__ int advance(const PushParams<T> &P, T hqm,
     return fate;
 }
 
-// Ionization products of one collision.  Returns the scattered electron's energy; records the ejected electron and
-// the new ion as children.
+// Ionization products of one collision (from the ground state or from the
+// metastable: `threshold` is 15.76 or 4.20 eV).  Returns the scattered
+// electron's energy; records the ejected electron and the new ion as
+// children.
 template <typename T>
 __device__ __forceinline__ T ionize(const PushCold<T> *C, DevScalars *sc, uint32_t id,
                                  uint32_t word1, uint32_t step, uint32_t key0, uint32_t key1,
-                                 int i, int j, T fr, T fz, T e)
+                                 int i, int j, T fr, T fz, T e, T threshold)
 {
-    const T erem = e - C->e_iz;
+    const T erem = e - threshold;
     const uint4 ua = philox4x32_10(make_uint4(id, word1 | PURPOSE_IZ, step, 0u), key0, key1);
     const uint4 ub = philox4x32_10(make_uint4(id, word1 | PURPOSE_ION, step, 0u), key0, key1);
     const T eej = u24<T>(ua.x) * erem;
@@ -274,11 +276,13 @@ __device__ __forceinline__ void scatter(const PushCold<T> *C, DevScalars *sc, ui
     const T c1 = interp_row(C->nu, kk, f);
     const T c2 = c1 + interp_row(C->nu + nt, kk, f);
     const T c3 = c2 + interp_row(C->nu + 2 * nt, kk, f);
+    const T c4 = c3 + interp_row(C->nu + 3 * nt, kk, f);
     const T rsel = u24<T>(u.y) * C->numax;
     int proc = -1;
     if (rsel < c1) proc = 0;
     else if (rsel < c2) proc = (e >= C->e_exc) ? 1 : -1;
     else if (rsel < c3) proc = (e >= C->e_iz) ? 2 : -1;
+    else if (rsel < c4) proc = (e >= C->e_iz_meta) ? 3 : -1;
     if (proc < 0) return;
     counts[proc]++;
     T d0, d1, d2;
@@ -291,7 +295,8 @@ __device__ __forceinline__ void scatter(const PushCold<T> *C, DevScalars *sc, ui
     } else if (proc == 1) {
         enew = e - C->e_exc;
     } else {
-        enew = ionize(C, sc, id, word1, step, key0, key1, i, j, fr, fz, e);
+        enew = ionize(C, sc, id, word1, step, key0, key1, i, j, fr, fz, e,
+                      proc == 2 ? C->e_iz : C->e_iz_meta);
     }
     const T vn = sqrt(C->v2_of_e * enew);
     v[0] = vn * d0;
@@ -459,7 +464,7 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
     const T hqm = P.hqm[s], qw = P.qw[s];
     const bool frozen = P.deposit_only || ((s == 1) && P.frozen_ions);
     const bool collide_on = (s == 0) && P.mcc_on && !P.deposit_only;
-    const bool emit = (s == 1) && P.see_on;
+    const bool emit = P.emit[s] != 0;
     const uint32_t word1 = (P.run << 8) | ((uint32_t)s << 4);
     T *__restrict__ Q = P.q[s];
     Tally t;
@@ -552,9 +557,11 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
                     if (fate == 1) {
                         ++t.abs1;
                         t.dq += P.cold->qw64[s];
-                        // emission is decided in the event kernel
+                        // emission is decided in the event kernel; the
+                        // entry's slot carries the species in bit 31
                         if (emit)
-                            enqueue(P.see_q, &P.sc->n_see_q, P.ev_cap, (int)(p0 + k),
+                            enqueue(P.see_q, &P.sc->n_see_q, P.ev_cap,
+                                    (int)((uint32_t)(p0 + k) | ((uint32_t)s << 31)),
                                     see_aux<T>(i, fr[k]));
                     } else if (fate == 2) {
                         ++t.abs2;
@@ -788,9 +795,9 @@ __device__ void events_body(const EventParams<T> P, int bid, int nb)
     const uint32_t step = (uint32_t)sc->step;
     const int nm = min(sc->n_mcc_q, P.ev_cap);
     const int ns = min(sc->n_see_q, P.ev_cap);
-    unsigned int coll[3] = {0u, 0u, 0u}, see = 0u;
+    unsigned int coll[4] = {0u, 0u, 0u, 0u}, see[2] = {0u, 0u};
     double dq = 0.0;
-    const uint32_t w_e = P.run << 8, w_i = (P.run << 8) | (1u << 4);
+    const uint32_t w_e = P.run << 8;
     for (int e = bid * blockDim.x + threadIdx.x; e < nm + ns; e += nb * blockDim.x) {
         if (e < nm) {
             const int p = P.mcc_q[e].x;
@@ -807,24 +814,29 @@ __device__ void events_body(const EventParams<T> P, int bid, int nb)
             S.vt[p] = v[1];
             S.vz[p] = v[2];
         } else {
-            const int2 q = P.see_q[e - nm];
-            const uint32_t pid = P.sp[1].id[q.x];
-            const uint4 u = philox4x32_10(make_uint4(pid, w_i | PURPOSE_SEE, step, 0u), P.key0, P.key1);
-            if ((unsigned long long)u.x < C->t_see) {
-                ++see;
+            // an absorbed cathode hit of either species (bit 31 of the slot)
+            int2 q = P.see_q[e - nm];
+            const int s = (int)((uint32_t)q.x >> 31);
+            q.x = (int)((uint32_t)q.x & 0x7fffffffu);
+            const uint32_t pid = P.sp[s].id[q.x];
+            const uint32_t word = (P.run << 8) | ((uint32_t)s << 4) | PURPOSE_SEE;
+            const uint4 u = philox4x32_10(make_uint4(pid, word, step, 0u), P.key0, P.key1);
+            if ((unsigned long long)u.x < C->t_see[s]) {
+                ++see[s];
                 dq -= C->qw64[0];
                 int ie;
                 T fe;
-                see_impact(P.sp[1], q, ie, fe);
+                see_impact(P.sp[s], q, ie, fe);
                 if (ie > P.nr - 1) { ie = P.nr - 1; fe = near_one<T>(); }
                 if (ie < 0) { ie = 0; fe = (T)0; }
-                record_child(C, sc, 1, pid, 0, 0, ie, 0, fe, (T)0, (T)0, (T)0, (T)0);
+                record_child(C, sc, s, pid, 0, 0, ie, 0, fe, (T)0, (T)0, (T)0, (T)0);
             }
         }
     }
-    for (int q = 0; q < 3; ++q)
+    for (int q = 0; q < 4; ++q)
         if (coll[q]) atomicAdd(&sc->n_coll[q], (unsigned long long)coll[q]);
-    if (see) atomicAdd(&sc->n_see, (unsigned long long)see);
+    if (see[1]) atomicAdd(&sc->n_see, (unsigned long long)see[1]);
+    if (see[0]) atomicAdd(&sc->n_see_e, (unsigned long long)see[0]);
     if (dq != 0.0) atomic_add_dev(&sc->dq_conv, dq);
     if (bid == 0 && threadIdx.x == 0) {
         sc->n_cand = (unsigned long long)nm;
@@ -1032,8 +1044,9 @@ __device__ void begin_body(DevScalars *sc, uint32_t *q0, uint32_t *q1, int64_t w
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 5; ++b) sc->n_abs[a][b] = 0;
         sc->n_cand = 0;
-        sc->n_coll[0] = sc->n_coll[1] = sc->n_coll[2] = 0;
+        sc->n_coll[0] = sc->n_coll[1] = sc->n_coll[2] = sc->n_coll[3] = 0;
         sc->n_see = 0;
+        sc->n_see_e = 0;
         sc->deposit_fallback = 0;
     }
 }

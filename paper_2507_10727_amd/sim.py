@@ -17,6 +17,9 @@ from . import workloads as W
 def make_config(prob: W.Problem, b_r, b_z, sigma, de_table=W.DE_TABLE, capacity=None):
     """pic_config from a Problem; returns (config, keep-alive arrays)."""
     sig = np.ascontiguousarray(sigma, np.float64)
+    if sig.ndim != 2 or sig.shape[0] != 4:
+        raise ValueError("sigma must hold 4 rows: elastic, excitation, ionization from the "
+                         "ground state and from the metastable")
     br = np.ascontiguousarray(b_r, np.float64)
     bz = np.ascontiguousarray(b_z, np.float64)
     c = L.pic_config()
@@ -27,6 +30,9 @@ def make_config(prob: W.Problem, b_r, b_z, sigma, de_table=W.DE_TABLE, capacity=
     c.circuit = prob.circuit
     c.v_fixed, c.v_ext, c.r_ext = prob.v_fixed, prob.v_ext, prob.r_ext
     c.gamma_i = prob.gamma_i
+    c.gamma_e = prob.gamma_e
+    c.n_meta = prob.n_meta
+    c.e_iz_meta = prob.e_iz_meta
     c.p_gas, c.t_gas = prob.p_gas, prob.t_gas
     c.e_exc, c.e_iz = prob.e_exc, prob.e_iz
     c.sigma = sig.ctypes.data_as(C.POINTER(C.c_double))

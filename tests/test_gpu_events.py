@@ -33,18 +33,22 @@ def _beam(n, e0, seed):
     return species(r, z, v * d[0], v * d[1], v * d[2])
 
 
-@pytest.mark.parametrize("precision", [W.F64, W.F32])
-def test_collisions_match_oracle(precision):
+@pytest.mark.parametrize("precision,n_meta", [(W.F64, 0.0), (W.F32, 0.0), (W.F64, 3e20),
+                                              (W.F32, 3e20)])
+def test_collisions_match_oracle(precision, n_meta):
+    """A 40 eV beam; with n_meta > 0 all four processes of Section 3 occur,
+    (1d) against a (test-sized) metastable density."""
     n = 20000
     p = W.Problem(name="beam", nr=16, nz=16, lr=0.02, lz=0.02, dt=2e-9, precision=precision,
                   p_gas=30e-3 * W.TORR, field_solve=0, see_on=0, frozen_ions=1, v_fixed=0.0,
-                  weight=1.0, wall_bc=(W.REFLECT, W.REFLECT, W.REFLECT), poisson_rtol=1e-13)
+                  weight=1.0, wall_bc=(W.REFLECT, W.REFLECT, W.REFLECT), poisson_rtol=1e-13,
+                  n_meta=n_meta)
     nn = p.nodes
     b = (np.zeros(nn), np.zeros(nn))
     sig = W.cross_sections()
     beam = _beam(n, 40.0, 21)
     cap = (3 * n, 2 * n)
-    say("case collisions", precision)
+    say("case collisions", precision, "n_meta", n_meta)
     sim = gpu_sim(p, b[0], b[1], sig, [beam.copy(), empty()], capacity=cap)
     if precision == W.F32:
         # the oracle starts from the GPU's FP32 state
@@ -98,6 +102,8 @@ def test_collisions_match_oracle(precision):
                 say("  species", s, "pos", ep, "vel", ev, "only-one-side", only)
                 assert ep < 2e-5 and ev < 2e-5 and only == 0
     assert d_o["n_coll"][2] > 0 and o.count(1) > 0
+    if n_meta > 0:
+        assert d_o["n_coll"][3] > 0
 
 
 def test_emission_matches_oracle():
@@ -128,3 +134,41 @@ def test_emission_matches_oracle():
             ep, ev, only = compare_particles(p, sim.particles(s), o.particles(s), s, 1e-12)
             assert ep < 1e-12 and ev < 1e-12 and only == 0
     assert o.count(0) > 1000
+
+
+def test_electron_emission_matches_oracle():
+    """Electrons and ions absorbed on the cathode, both emitting (yields 0.3
+    and 0.1, independent draws of each species' stream), FP64: the emitted
+    electrons -- at rest under their parents, ids in (parent species, parent
+    id) order -- and the cathode tally match the oracle by id."""
+    n = 20000
+    p = W.Problem(name="see_e", nr=16, nz=16, lr=0.02, lz=0.02, gamma_i=0.1, gamma_e=0.3,
+                  see_on=1, mcc_on=0, field_solve=0, v_fixed=0.0, weight=1.0,
+                  poisson_rtol=1e-13)
+    nn = p.nodes
+    rng = np.random.default_rng(24)
+    elec = species(0.019 * rng.random(n), 1e-9 + 2e-5 * rng.random(n), 0.0, 0.0, -2e6)
+    ions = species(0.019 * rng.random(n), 1e-9 + 3e-7 * rng.random(n), 0.0, 0.0, -2e4)
+    sig = W.cross_sections()
+    cap = (3 * n, n)
+    say("case electron-induced emission")
+    sim = gpu_sim(p, np.zeros(nn), np.zeros(nn), sig, [elec.copy(), ions.copy()], capacity=cap)
+    o = O.Oracle(p, np.zeros(nn), np.zeros(nn), sig, [elec.copy(), ions.copy()], capacity=cap)
+    o.init()
+    o.phi[:] = 0.0
+    sim.set_phi(np.zeros(nn))
+    total = 0
+    for step in range(3):
+        d_o = o.step()
+        sim.step(1)
+        d_g = sim.diag()
+        total += d_g["n_see_e"]
+        say("step", step, "see_e", d_o["n_see_e"], d_g["n_see_e"], "see_i", d_o["n_see"],
+            d_g["n_see"], d_o["dq_conv"], d_g["dq_conv"])
+        assert d_g["n_see_e"] == d_o["n_see_e"] and d_g["n_see"] == d_o["n_see"]
+        assert [tuple(x) for x in d_g["n_abs"]] == [tuple(x) for x in d_o["n_abs"]]
+        assert d_g["dq_conv"] == approx(d_o["dq_conv"], rel=1e-12, abs=1e-25)
+        for s in range(2):
+            ep, ev, only = compare_particles(p, sim.particles(s), o.particles(s), s, 1e-12)
+            assert ep < 1e-12 and ev < 1e-12 and only == 0
+    assert o.count(0) > 1000 and total > 1000

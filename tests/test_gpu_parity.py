@@ -102,7 +102,7 @@ def test_f64_small_config_200_steps():
     sim = gpu_sim(p, br, bz, sig, [x.copy() for x in parts])
     o = O.Oracle(p, br, bz, sig, [x.copy() for x in parts])
     o.init()
-    tot_o = {"n_coll": np.zeros(3, np.int64), "n_see": 0}
+    tot_o = {"n_coll": np.zeros(4, np.int64), "n_see": 0}
     for k in range(1, 201):
         sim.step(1)
         d = o.step()
@@ -458,7 +458,7 @@ def test_f32_long_run_statistics():
         p = base.replace(precision=prec)
         br, bz, sig, parts = W.inputs(p)
         sim = gpu_sim(p, br, bz, sig, parts)
-        rows, coll = [], np.zeros(3)
+        rows, coll = [], np.zeros(4)
         for k in range(20):
             sim.step(100)
             d = sim.diag()
