@@ -17,6 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pic_oracle.c")
 LIB = os.path.join(HERE, "liborc.so")
+LIB_OMP = os.path.join(HERE, "liborc_omp.so")
 
 _dp = C.POINTER(C.c_double)
 _up = C.POINTER(C.c_uint32)
@@ -82,21 +83,37 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (always rebuilds when ``force``)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call([
-            "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-            "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (always rebuilds when ``force``): the serial
+    library liborc.so, and liborc_omp.so with OpenMP over the particle loops
+    (the multi-core timing build)."""
+    for out, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+            tmp = out + ".tmp"
+            subprocess.check_call([
+                "gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+                "-fPIC", "-shared", *extra, "-o", tmp, SRC, "-lm"])
+            os.replace(tmp, out)
     return LIB
+
+
+def use_openmp(on: bool = True):
+    """Select the OpenMP build for the oracle runs that follow (timing only;
+    the parity tests use the serial build).  Must be called before the first
+    use of the oracle in the process."""
+    global _which
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _which = LIB_OMP if on else LIB
+
+
+_which = None
 
 
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(_which or LIB)
         L.orc_philox4x32_10.argtypes = [_up, _up, _up]
         L.orc_node_kind.argtypes = [C.POINTER(Problem), C.c_int, C.c_int]
         L.orc_node_kind.restype = C.c_int

@@ -21,6 +21,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* CODATA 2018 */
 static const double EPS0 = 8.8541878128e-12;
@@ -518,6 +521,43 @@ static void push_child(child_list *l, child c)
     l->a[l->n++] = c;
 }
 
+/* Built with -fopenmp (the timing build), the particle loops run on all
+ * cores: each thread takes one contiguous range of particles (static
+ * schedule) and keeps its own sums, counters and new particles, which are
+ * combined in thread order afterwards.  For a given thread count the result
+ * is therefore deterministic; with one thread it is the serial loop. */
+typedef struct thread_acc {
+    double ke, pz, dq;
+    int64_t n_abs[5], n_see, n_see_e, n_cand, n_coll[4];
+    child_list kids;
+} thread_acc;
+
+static int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static int orc_thread_id(void)
+{
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
+static void append_children(child_list *to, child_list *from)
+{
+    for (int64_t c = 0; c < from->n; ++c) push_child(to, from->a[c]);
+    free(from->a);
+    from->a = NULL;
+    from->n = from->cap = 0;
+}
+
 static int child_cmp(const void *a, const void *b)
 {
     uint64_t x = ((const child *)a)->key, y = ((const child *)b)->key;
@@ -561,13 +601,37 @@ double orc_capacitance(const orc_problem *p, const double *phi_l)
     return s;
 }
 
-static void deposit_all(const orc_problem *p, orc_species sp[2], double *q_e, double *q_i)
+/* Both species' deposit.  The timing build (-fopenmp) gives each thread a
+ * contiguous range of particles and its own node array, and adds the arrays
+ * in thread order (deterministic for a given thread count; the serial build
+ * is the plain loop). */
+static void deposit_species(const orc_problem *p, const orc_species *S, double qw, double *q)
 {
     int64_t nn = (int64_t)(p->nr + 1) * (p->nz + 1);
-    memset(q_e, 0, sizeof(double) * nn);
-    memset(q_i, 0, sizeof(double) * nn);
-    orc_deposit(p, sp[0].r, sp[0].z, sp[0].n, p->q[0] * p->w[0], q_e);
-    orc_deposit(p, sp[1].r, sp[1].z, sp[1].n, p->q[1] * p->w[1], q_i);
+    const int nthr = orc_threads();
+    memset(q, 0, sizeof(double) * nn);
+    if (nthr == 1) {
+        orc_deposit(p, S->r, S->z, S->n, qw, q);
+        return;
+    }
+    double *part = calloc((size_t)nthr * nn, sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        const int t = orc_thread_id();
+        const int64_t lo = S->n * t / nthr, hi = S->n * (t + 1) / nthr;
+        orc_deposit(p, S->r + lo, S->z + lo, hi - lo, qw, part + (size_t)t * nn);
+    }
+    for (int t = 0; t < nthr; ++t)
+        for (int64_t n = 0; n < nn; ++n) q[n] += part[(size_t)t * nn + n];
+    free(part);
+}
+
+static void deposit_all(const orc_problem *p, orc_species sp[2], double *q_e, double *q_i)
+{
+    deposit_species(p, &sp[0], p->q[0] * p->w[0], q_e);
+    deposit_species(p, &sp[1], p->q[1] * p->w[1], q_i);
 }
 
 int orc_init(const orc_problem *p, orc_species sp[2], orc_state *st,
@@ -643,16 +707,27 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
     char *dead[2];
     int64_t n_pre[2];
 
+    const int nthr = orc_threads();
+    thread_acc *acc = calloc(nthr, sizeof(thread_acc));
     for (int s = 0; s < 2; ++s) {
         orc_species *S = &sp[s];
         n_pre[s] = S->n;
         dead[s] = calloc(S->n > 0 ? S->n : 1, 1);
         double qm = p->q[s] / p->m[s];
-        for (int64_t k = 0; k < S->n; ++k) {
+        for (int t = 0; t < nthr; ++t) {
+            acc[t].ke = acc[t].pz = acc[t].dq = 0.0;
+        }
+        acc[0].dq = dq;   /* the serial build sums in exactly the loop order */
+        const int64_t ns = S->n;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+        for (int64_t k = 0; k < ns; ++k) {
+            thread_acc *a = &acc[orc_thread_id()];
             if (s == 1 && p->frozen_ions) {
                 double v2 = S->vr[k] * S->vr[k] + S->vt[k] * S->vt[k] + S->vz[k] * S->vz[k];
-                d->ke[s] += 0.5 * p->m[s] * p->w[s] * v2;
-                d->pz[s] += p->m[s] * p->w[s] * S->vz[k];
+                a->ke += 0.5 * p->m[s] * p->w[s] * v2;
+                a->pz += p->m[s] * p->w[s] * S->vz[k];
                 continue;
             }
             double er, ez, br, bz;
@@ -672,8 +747,8 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
             double qy = my + (pz * sx - px * sz);
             double qz = mz + (px * sy - py * sx);
             double nx = qx + h * er, ny = qy, nz = qz + h * ez;
-            d->ke[s] += 0.5 * p->m[s] * p->w[s] * (vx * nx + vy * ny + vz * nz);
-            d->pz[s] += p->m[s] * p->w[s] * nz;
+            a->ke += 0.5 * p->m[s] * p->w[s] * (vx * nx + vy * ny + vz * nz);
+            a->pz += p->m[s] * p->w[s] * nz;
             /* drift and rotation into the new meridional plane */
             double x1 = S->r[k] + nx * dt, y1 = ny * dt, z1 = S->z[k] + nz * dt;
             double r1 = sqrt(x1 * x1 + y1 * y1);
@@ -700,9 +775,9 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
             S->r[k] = r1; S->z[k] = z1; S->vr[k] = vr1; S->vt[k] = vt1; S->vz[k] = vz1;
             if (fate) {
                 dead[s][k] = 1;
-                d->n_abs[s][fate]++;
+                a->n_abs[fate]++;
                 if (fate == 1) {
-                    dq += p->q[s] * p->w[s];
+                    a->dq += p->q[s] * p->w[s];
                     /* secondary emission (Section 3): ions with yield
                      * gamma_i, electrons with gamma_e, independently; the
                      * secondary is an electron at rest at (r', 0) */
@@ -711,14 +786,26 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
                         draw(p, S->id[k], s, PUR_SEE, st->step, u);
                         if ((uint64_t)u[0] < t_see[s]) {
                             child c = {child_key(s, S->id[k], 0), 0, r1, 0.0, 0.0, 0.0, 0.0};
-                            push_child(&kids, c);
-                            dq -= p->q[0] * p->w[0];
-                            if (s == 1) d->n_see++;
-                            else d->n_see_e++;
+                            push_child(&a->kids, c);
+                            a->dq -= p->q[0] * p->w[0];
+                            if (s == 1) a->n_see++;
+                            else a->n_see_e++;
                         }
                     }
                 }
             }
+        }
+        /* combine the threads' results in thread order */
+        dq = 0.0;
+        for (int t = 0; t < nthr; ++t) {
+            d->ke[s] += acc[t].ke;
+            d->pz[s] += acc[t].pz;
+            dq += acc[t].dq;
+            for (int f = 0; f < 5; ++f) { d->n_abs[s][f] += acc[t].n_abs[f]; acc[t].n_abs[f] = 0; }
+            d->n_see += acc[t].n_see;
+            d->n_see_e += acc[t].n_see_e;
+            acc[t].n_see = acc[t].n_see_e = 0;
+            append_children(&kids, &acc[t].kids);
         }
     }
 
@@ -726,14 +813,19 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
     if (p->mcc_on) {
         orc_species *S = &sp[0];
         const double me = p->m[0];
-        for (int64_t k = 0; k < n_pre[0]; ++k) {
+        const int64_t ne = n_pre[0];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+        for (int64_t k = 0; k < ne; ++k) {
+            thread_acc *a = &acc[orc_thread_id()];
             if (dead[0][k]) continue;
             double vx = S->vr[k], vy = S->vt[k], vz = S->vz[k];
             int proc = orc_mcc_select(p, nu, numax, t_null, S->id[k], st->step, vx, vy, vz, NULL);
             if (proc == -2) continue;
-            d->n_cand++;
+            a->n_cand++;
             if (proc < 0) continue;
-            d->n_coll[proc]++;
+            a->n_coll[proc]++;
             uint32_t u[4];
             draw(p, S->id[k], 0, PUR_MCC, st->step, u);
             double v2 = vx * vx + vy * vy + vz * vz;
@@ -764,20 +856,26 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
                 double vej = sqrt(2.0 * QE * eej / me);
                 child ce = {child_key(0, S->id[k], 0), 0, S->r[k], S->z[k],
                             vej * de_[0], vej * de_[1], vej * de_[2]};
-                push_child(&kids, ce);
+                push_child(&a->kids, ce);
                 double sig = sqrt(KB * p->t_gas / p->m[1]);
                 double a0 = sqrt(-2.0 * log(u_open(ub[0]))), p0 = 2.0 * PI * u24(ub[1]);
                 double a1 = sqrt(-2.0 * log(u_open(ub[2]))), p1 = 2.0 * PI * u24(ub[3]);
                 child ci = {child_key(0, S->id[k], 1), 1, S->r[k], S->z[k],
                             sig * a0 * cos(p0), sig * a0 * sin(p0), sig * a1 * cos(p1)};
-                push_child(&kids, ci);
+                push_child(&a->kids, ci);
             }
             double vnew = sqrt(2.0 * QE * enew / me);
             S->vr[k] = vnew * dn[0];
             S->vt[k] = vnew * dn[1];
             S->vz[k] = vnew * dn[2];
         }
+        for (int t = 0; t < nthr; ++t) {
+            d->n_cand += acc[t].n_cand;
+            for (int c = 0; c < 4; ++c) d->n_coll[c] += acc[t].n_coll[c];
+            append_children(&kids, &acc[t].kids);
+        }
     }
+    free(acc);
 
     /* remove absorbed particles, keeping order */
     for (int s = 0; s < 2; ++s) {
