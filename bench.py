@@ -52,22 +52,63 @@ def traffic_from_profile(workload):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(prob, br, bz, sig, parts, max_seconds=40.0):
-    """The FP64 oracle as it stands, single thread, one full step of the same
-    workload (all particles), on this host."""
-    from oracle import oracle as O
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def _time_oracle(O, prob, br, bz, sig, parts, budget_s, max_steps):
+    """Whole oracle steps (push, walls, MCC, deposit, field solve, circuit)
+    until about budget_s seconds have been spent; init is not timed."""
     o = O.Oracle(prob, br, bz, sig, parts, capacity=(parts[0].n + 4096, parts[1].n + 4096))
     t0 = time.perf_counter()
     o.init()
     t_init = time.perf_counter() - t0
-    n = o.count(0) + o.count(1)
-    t0 = time.perf_counter()
-    o.step()
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 full step of {prob.name} ({n} particles, FP64, single thread; "
-                      f"init excluded, {t_init:.1f} s)",
-            "seconds": dt}
+    steps, work, spent = 0, 0, 0.0
+    while steps < max_steps and spent < budget_s:
+        n = o.count(0) + o.count(1)
+        t0 = time.perf_counter()
+        o.step()
+        spent += time.perf_counter() - t0
+        work += n
+        steps += 1
+    del o
+    return {"value": work / spent, "steps": steps, "seconds": spent, "init_seconds": t_init,
+            "particle_steps": work}
+
+
+def cpu_baseline(prob, br, bz, sig, parts, budget_s=12.0, max_steps=64):
+    """The FP64 oracle as it stands, timed on this host's cores over whole
+    steps of the same workload: once with its serial build and once with its
+    OpenMP build (particle loops and deposit on every thread the process may
+    use, per-thread tallies combined in a fixed order).  The reported value
+    is the multi-core one."""
+    from oracle import oracle as O
+    O.use_openmp(False)
+    serial = _time_oracle(O, prob, br, bz, sig, parts, budget_s, max_steps)
+    log(f"[bench] cpu serial: {serial['value']:.3e} particle-steps/s over {serial['steps']} steps")
+    O.use_openmp(True)
+    threads = O.thread_count()
+    par = _time_oracle(O, prob, br, bz, sig, parts, budget_s, max_steps)
+    O.use_openmp(False)
+    n = parts[0].n + parts[1].n
+    return {"value": par["value"], "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{par['steps']} whole steps of {prob.name} from its initial load "
+                      f"({n} particles, FP64, {threads} OpenMP threads; init excluded); "
+                      f"serial build: {serial['steps']} steps on 1 thread",
+            "seconds": par["seconds"], "serial": serial, "openmp": par, **cpu_info()}
 
 
 def poisson_bench(train_seconds=60.0, reps=6):
@@ -381,9 +422,10 @@ def main():
         ensemble = ensemble_bench(args.ensemble_runs)
     cpu = None
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle, 1 step)")
+        log("[bench] cpu baseline (oracle: serial build, then OpenMP build)")
         cpu = cpu_baseline(p, br, bz, sig, parts)
-        log(f"[bench] cpu {cpu['value']:.3e} particle-steps/s in {cpu['seconds']:.1f} s")
+        log(f"[bench] cpu {cpu['value']:.3e} particle-steps/s on {cpu['cores']} threads "
+            f"in {cpu['seconds']:.1f} s")
 
     line = {
         "metric": "particle-steps/s (gather+push+MCC+deposit); Poisson ms learned-PC vs MG-CG @1e-8",

@@ -98,12 +98,18 @@ def build(force: bool = False) -> str:
 
 def use_openmp(on: bool = True):
     """Select the OpenMP build for the oracle runs that follow (timing only;
-    the parity tests use the serial build).  Must be called before the first
-    use of the oracle in the process."""
-    global _which
-    if _lib is not None:
-        raise RuntimeError("the oracle library is already loaded")
-    _which = LIB_OMP if on else LIB
+    the parity tests use the serial build).  Oracle objects made before the
+    switch must not be used after it."""
+    global _which, _lib
+    want = LIB_OMP if on else LIB
+    if (_which or LIB) != want:
+        _lib = None
+    _which = want
+
+
+def thread_count() -> int:
+    """Threads the loaded build runs its particle loops on."""
+    return int(lib().orc_thread_count())
 
 
 _which = None

@@ -171,6 +171,54 @@ double orc_field_energy(const orc_problem *p, const double *phi)
     return w;
 }
 
+static int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+int orc_thread_count(void)
+{
+    return orc_threads();
+}
+
+static int orc_thread_id(void)
+{
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
+/* Sums taken over [0, nn) in the solver: each thread sums one contiguous
+ * range in order, and the per-thread partial sums are added in thread
+ * order.  Deterministic for a given thread count; with one thread it is the
+ * plain loop. */
+#define THREAD_RANGE(nn, lo, hi)                                              \
+    const int nthr_ = omp_team_size();                                        \
+    const int t_ = orc_thread_id();                                           \
+    const int64_t lo = (nn) * t_ / nthr_, hi = (nn) * (t_ + 1) / nthr_
+
+static int omp_team_size(void)
+{
+#ifdef _OPENMP
+    return omp_get_num_threads();
+#else
+    return 1;
+#endif
+}
+
+static double sum_parts(const double *part, int nthr, int stride, int k)
+{
+    double s = 0.0;
+    for (int t = 0; t < nthr; ++t) s += part[t * stride + k];
+    return s;
+}
+
 /* Solve for phi with cathode nodes at v_cathode, grounded nodes at 0 and the
  * unknown rows satisfying (K phi)_u = Q_u.  Jacobi-preconditioned conjugate
  * gradients on the unknowns, warm-started from phi, until
@@ -218,6 +266,7 @@ int orc_solve(const orc_problem *p, const double *q_node, double v_cathode,
      * the matrix K_uu.  The differences are formed before scaling, which keeps
      * round-off small for smooth potentials. */
 #define APPLY(x, y)                                                          \
+    _Pragma("omp parallel for schedule(static)")                              \
     for (int jj = 0; jj <= nz; ++jj)                                          \
         for (int ii = 0; ii <= nr; ++ii) {                                    \
             int64_t m = IDX(p, ii, jj);                                       \
@@ -230,9 +279,16 @@ int orc_solve(const orc_problem *p, const double *q_node, double v_cathode,
             y[m] = acc;                                                       \
         }
 
-    double bnorm = 0.0;
-    for (int64_t n = 0; n < nn; ++n) bnorm += b[n] * b[n];
-    bnorm = sqrt(bnorm);
+    const int nthr = orc_threads();
+    double *part = calloc((size_t)nthr * 2, sizeof(double));
+#pragma omp parallel num_threads(nthr)
+    {
+        THREAD_RANGE(nn, lo, hi);
+        double s = 0.0;
+        for (int64_t n = lo; n < hi; ++n) s += b[n] * b[n];
+        part[2 * t_] = s;
+    }
+    double bnorm = sqrt(sum_parts(part, nthr, 2, 0));
     int status = 0;
     int64_t it = 0;
     double res = 0.0;
@@ -245,14 +301,21 @@ int orc_solve(const orc_problem *p, const double *q_node, double v_cathode,
         double last = HUGE_VAL;
         for (int restart = 0;; ++restart) {
             APPLY(phi, q);
-            double rz = 0.0, rr = 0.0;
-            for (int64_t n = 0; n < nn; ++n) {
-                r[n] = (kind[n] == 0) ? q_node[n] - q[n] : 0.0;
-                z[n] = (kind[n] == 0) ? r[n] / dg[n] : 0.0;
-                d[n] = z[n];
-                rz += r[n] * z[n];
-                rr += r[n] * r[n];
+#pragma omp parallel num_threads(nthr)
+            {
+                THREAD_RANGE(nn, lo, hi);
+                double s_rz = 0.0, s_rr = 0.0;
+                for (int64_t n = lo; n < hi; ++n) {
+                    r[n] = (kind[n] == 0) ? q_node[n] - q[n] : 0.0;
+                    z[n] = (kind[n] == 0) ? r[n] / dg[n] : 0.0;
+                    d[n] = z[n];
+                    s_rz += r[n] * z[n];
+                    s_rr += r[n] * r[n];
+                }
+                part[2 * t_] = s_rz;
+                part[2 * t_ + 1] = s_rr;
             }
+            double rz = sum_parts(part, nthr, 2, 0), rr = sum_parts(part, nthr, 2, 1);
             res = sqrt(rr) / bnorm;
             /* stop when converged, out of iterations, or when a restart no
              * longer reduces the true residual (round-off floor) */
@@ -261,21 +324,34 @@ int orc_solve(const orc_problem *p, const double *q_node, double v_cathode,
             double rec = res;
             while (rec > 0.5 * rtol && it < maxit) {
                 APPLY(d, q);
-                double dq = 0.0;
-                for (int64_t n = 0; n < nn; ++n) dq += d[n] * q[n];
-                double alpha = rz / dq;
-                double rz_new = 0.0;
-                rr = 0.0;
-                for (int64_t n = 0; n < nn; ++n) {
-                    if (kind[n] != 0) continue;
-                    phi[n] += alpha * d[n];
-                    r[n] -= alpha * q[n];
-                    z[n] = r[n] / dg[n];
-                    rz_new += r[n] * z[n];
-                    rr += r[n] * r[n];
+#pragma omp parallel num_threads(nthr)
+                {
+                    THREAD_RANGE(nn, lo, hi);
+                    double s = 0.0;
+                    for (int64_t n = lo; n < hi; ++n) s += d[n] * q[n];
+                    part[2 * t_] = s;
                 }
+                double alpha = rz / sum_parts(part, nthr, 2, 0);
+#pragma omp parallel num_threads(nthr)
+                {
+                    THREAD_RANGE(nn, lo, hi);
+                    double s_rz = 0.0, s_rr = 0.0;
+                    for (int64_t n = lo; n < hi; ++n) {
+                        if (kind[n] != 0) continue;
+                        phi[n] += alpha * d[n];
+                        r[n] -= alpha * q[n];
+                        z[n] = r[n] / dg[n];
+                        s_rz += r[n] * z[n];
+                        s_rr += r[n] * r[n];
+                    }
+                    part[2 * t_] = s_rz;
+                    part[2 * t_ + 1] = s_rr;
+                }
+                double rz_new = sum_parts(part, nthr, 2, 0);
+                rr = sum_parts(part, nthr, 2, 1);
                 double beta = rz_new / rz;
                 rz = rz_new;
+#pragma omp parallel for schedule(static) num_threads(nthr)
                 for (int64_t n = 0; n < nn; ++n) d[n] = z[n] + beta * d[n];
                 ++it;
                 rec = sqrt(rr) / bnorm;
@@ -287,6 +363,7 @@ int orc_solve(const orc_problem *p, const double *q_node, double v_cathode,
     if (iters) *iters = it;
     if (rel_res) *rel_res = res;
     free(ce); free(cn); free(b); free(r); free(z); free(d); free(q); free(dg); free(kind);
+    free(part);
     return status;
 }
 
@@ -532,23 +609,7 @@ typedef struct thread_acc {
     child_list kids;
 } thread_acc;
 
-static int orc_threads(void)
-{
-#ifdef _OPENMP
-    return omp_get_max_threads();
-#else
-    return 1;
-#endif
-}
 
-static int orc_thread_id(void)
-{
-#ifdef _OPENMP
-    return omp_get_thread_num();
-#else
-    return 0;
-#endif
-}
 
 static void append_children(child_list *to, child_list *from)
 {

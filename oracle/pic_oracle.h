@@ -132,6 +132,10 @@ void orc_mcc_select_many(const orc_problem *p, int64_t step, int64_t n, const ui
                          double *margins);
 
 /* Whole-run drivers. phi, phi0, phi_l and q_node[2] are node arrays. */
+/* Threads the particle loops use: 1 in the serial build, the OpenMP team
+ * size in the multi-core timing build. */
+int orc_thread_count(void);
+
 int orc_init(const orc_problem *p, orc_species sp[2], orc_state *st,
              double *phi, double *phi0, double *phi_l, double *q_e, double *q_i);
 int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
