@@ -478,3 +478,55 @@ def test_f32_long_run_statistics():
         assert abs(b - a) <= 0.05 * abs(a), nm
     say("  collisions", c64, c32)
     assert np.all(np.abs(c32 - c64) <= 0.05 * c64 + 10)
+
+
+@pytest.mark.parametrize("prec", [W.F64, W.F32])
+def test_long_run_statistics_against_oracle(prec):
+    """The small discharge (64 x 64 cells, 1e5 + 1e5 particles, cathode at
+    -400 V) for 20000 steps on the GPU, against the oracle's run of the same
+    inputs (tests/golden/long_run_small64.json, written by
+    tests/golden/make_long_run.py from the oracle alone).  The trajectories
+    part by round-off long before the end, so the comparison is statistical:
+    over the last 25% of the steps the mean cathode current, the mean peak
+    densities of both species (8 x 8-node blocks), the mean peak potential and
+    the live counts agree within 5% (the current within 5% or three standard
+    errors of its mean, whichever is larger)."""
+    import json
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    import make_long_run as G
+    with open(G.OUT) as f:
+        ref = json.load(f)
+    p = G.problem().replace(precision=prec)
+    br, bz, sig, parts = W.inputs(p)
+    say("case long run against the oracle", prec, p.steps)
+    sim = gpu_sim(p, br, bz, sig, parts, capacity=(4 * G.N_PER_SPECIES, 4 * G.N_PER_SPECIES))
+    lo, hi = G.stats_window(p)
+    sim.step(lo)
+    cur, ne, ni, phim, cnt = [], [], [], [], []
+    sp = p.species()
+    for k in range(lo + 1, hi + 1):
+        sim.step(1)
+        d = sim.diag()
+        cur.append(d["i_cathode"])
+        if k % 10 == 0:
+            f = sim.fields_host()
+            ne.append(G.block_peak(f["q_e"], p, sp[0][0]))
+            ni.append(G.block_peak(f["q_i"], p, sp[1][0]))
+            phim.append(d["phi_max"])
+            cnt.append(d["count"])
+        if k % 1000 == 0:
+            say(f"  step {k}: counts {d['count']}")
+    sim.close()
+    got = {"i_cathode_mean_a": np.mean(cur), "n_e_peak_m3": np.mean(ne),
+           "n_i_peak_m3": np.mean(ni), "phi_max_v": np.mean(phim),
+           "count_e": np.mean([c[0] for c in cnt]), "count_i": np.mean([c[1] for c in cnt])}
+    sem = np.std(cur) / math.sqrt(len(cur))
+    for k, v in got.items():
+        r = ref[k]
+        tol = 0.05 * abs(r)
+        if k == "i_cathode_mean_a":
+            tol = max(tol, 3.0 * math.hypot(sem, ref["i_cathode_sem_a"]))
+        say(f"  {k}: gpu {v:.6g} oracle {r:.6g} rel {abs(v - r) / abs(r):.2e} (tol {tol / abs(r):.2e})")
+        assert abs(v - r) <= tol, k
