@@ -114,6 +114,14 @@ typedef struct pic_config {
     double n_meta;              /* static metastable Ar* density (m^-3), the
                                    target of process (1d) (Section 3: 2.5e17)    */
     double e_iz_meta;           /* ionization threshold from Ar* (eV, 4.20)      */
+    int32_t deposit_fixed;      /* 1: FP64 state only; node charge summed as
+                                   64-bit fixed point (tent weights rounded to
+                                   multiples of 2^-42), so a step's result does
+                                   not depend on the order of the deposit's
+                                   additions: runs are bit-reproducible.  At
+                                   most 2^21 particles may share a node.
+                                   Single runs only (not ensembles).          */
+    int32_t pad_;
 } pic_config;
 
 /* Initial particles of one species (host, FP64, absolute positions).
@@ -153,6 +161,7 @@ typedef struct pic_field_view {
                                    particle precision                             */
     int64_t nodes;
     int32_t q_precision;
+    double *phi0_prev_dev;      /* phi0 of the previous step                      */
 } pic_field_view;
 
 typedef struct pic_poisson_stats {
@@ -193,13 +202,20 @@ typedef struct pic_diag_out {
     int64_t n_see_e;            /* electron-induced secondary electrons          */
 } pic_diag_out;
 
-/* Scalar state for checkpoint/resume (particle and field arrays are read and
- * written through the views). */
+/* Scalar state for checkpoint/resume.  A checkpoint is this state plus,
+ * through the views, slots 0..count-1 of both species' arrays and phi0 and
+ * phi0_prev (the field solve's warm start extrapolates from them).  To
+ * resume, create a handle with the same configuration (pic_init with no
+ * particles), write those arrays through its views, then call
+ * pic_set_state.  With deposit_fixed = 1 and PIC_DIRECT the resumed run is
+ * bit-identical to the uninterrupted one. */
 typedef struct pic_scalar_state {
     int64_t step;
     double vc, qc;
     uint32_t next_id[2];
     int64_t count[2];
+    int32_t sort_phase;         /* steps since the last cell sort (0..sort_every) */
+    int32_t pad_;
 } pic_scalar_state;
 
 /* Per-phase device time accumulated from HIP events (ms), when enabled. */
@@ -277,7 +293,12 @@ pic_status pic_set_phi(pic_handle *h, const double *phi);
 /* Cell-sort and compact both species now (drops absorbed slots). */
 pic_status pic_compact(pic_handle *h);
 
-/* Scalar state (step, circuit, id counters, counts) for checkpointing. */
+/* Scalar state (step, circuit, id counters, counts, sort phase) for
+ * checkpointing (Section 2's timestep carries no other state between steps
+ * than these, the particles and the potential).  pic_set_state also rebuilds
+ * phi = phi0 + V_c phi_L and the gather fields from the handle's phi0 and the
+ * restored V_c.  Errors: PIC_EINVAL (count above capacity, sort_phase outside
+ * 0..sort_every).  Both synchronize. */
 pic_status pic_get_state(const pic_handle *h, pic_scalar_state *out);
 pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in);
 

@@ -50,6 +50,7 @@ class pic_config(C.Structure):
         ("extra_current", C.c_double),
         ("pc_batch", C.c_int32), ("pc_maxit", C.c_int32),
         ("gamma_e", C.c_double), ("n_meta", C.c_double), ("e_iz_meta", C.c_double),
+        ("deposit_fixed", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -67,7 +68,8 @@ class pic_particle_view(C.Structure):
 
 class pic_field_view(C.Structure):
     _fields_ = [("phi_dev", C.c_void_p), ("phi0_dev", C.c_void_p), ("phi_l_dev", C.c_void_p),
-                ("q_dev", C.c_void_p * 2), ("nodes", C.c_int64), ("q_precision", C.c_int32)]
+                ("q_dev", C.c_void_p * 2), ("nodes", C.c_int64), ("q_precision", C.c_int32),
+                ("phi0_prev_dev", C.c_void_p)]
 
 
 class pic_poisson_stats(C.Structure):
@@ -110,7 +112,8 @@ class pic_diag_out(C.Structure):
 
 class pic_scalar_state(C.Structure):
     _fields_ = [("step", C.c_int64), ("vc", C.c_double), ("qc", C.c_double),
-                ("next_id", C.c_uint32 * 2), ("count", C.c_int64 * 2)]
+                ("next_id", C.c_uint32 * 2), ("count", C.c_int64 * 2),
+                ("sort_phase", C.c_int32), ("pad_", C.c_int32)]
 
 
 class pic_timers(C.Structure):

@@ -221,6 +221,10 @@ pic_status validate(const pic_config *c, pic_handle *h)
         return fail(h, PIC_EINVAL, "gamma_i, p_gas >= 0 and t_gas > 0 required");
     if (!(c->gamma_e >= 0) || !(c->n_meta >= 0) || !(c->e_iz_meta > 0))
         return fail(h, PIC_EINVAL, "gamma_e, n_meta >= 0 and e_iz_meta > 0 required");
+    if (c->deposit_fixed != 0 && c->deposit_fixed != 1)
+        return fail(h, PIC_EINVAL, "deposit_fixed must be 0 or 1");
+    if (c->deposit_fixed && c->precision != PIC_F64)
+        return fail(h, PIC_EINVAL, "the fixed-point deposit needs FP64 state");
     for (int k = 0; k < 3; ++k)
         if (c->wall_bc[k] != PIC_ABSORB && c->wall_bc[k] != PIC_REFLECT)
             return fail(h, PIC_EINVAL, "bad wall_bc[%d]", k);
@@ -927,6 +931,7 @@ PushParams<T> push_params(pic_handle *h, int deposit_only)
     P.any_reflect = (c.wall_bc[0] == PIC_REFLECT || c.wall_bc[1] == PIC_REFLECT ||
                      c.wall_bc[2] == PIC_REFLECT) ? 1 : 0;
     P.deposit_only = deposit_only;
+    P.fixed_q = c.deposit_fixed;
     P.key0 = (uint32_t)(c.seed & 0xffffffffu);
     P.key1 = (uint32_t)(c.seed >> 32);
     P.run = c.run;
@@ -1066,11 +1071,13 @@ ChildParams<T> child_params(const pic_handle *h)
         C.cap[s] = h->cap[s];
         C.q[s] = (T *)h->q[s];
         C.qw[s] = (T)(c.q[s] * c.w[s]);
+        C.qw64[s] = c.q[s] * c.w[s];
     }
     C.sc = h->sc;
     C.child = (const Child<T> *)h->child;
     C.child_cap = h->child_cap;
     C.nr = c.nr;
+    C.fixed_q = c.deposit_fixed;
     return C;
 }
 
@@ -1081,7 +1088,11 @@ void particle_events(pic_handle *h)
     timer_begin(h, ev, 1);
     launch_events<T>(event_params<T>(h), h->stream);
     launch_children<T>(child_params<T>(h), h->stream);
-    launch_finalize_step(h->sc, h->cap, h->stream);
+    const pic_config &c = h->cfg;
+    const double qw64[2] = {c.q[0] * c.w[0], c.q[1] * c.w[1]};
+    if (c.deposit_fixed)
+        launch_q_from_fixed(h->q[0], h->q[1], (int64_t)(c.nr + 1) * (c.nz + 1), qw64, h->stream);
+    launch_finalize_step(h->sc, h->cap, qw64, h->stream);
     timer_end(h, 1, ev);
 }
 
@@ -1222,6 +1233,10 @@ pic_status init_typed(pic_handle *h, const pic_species_host *init)
     // initial deposit, phi0, circuit state at V0, gather fields
     launch_begin_step(h->sc, h->q[0], h->q[1], nodes, (int)sizeof(T), s);
     launch_push_h<T>(h, 1);
+    if (c.deposit_fixed) {
+        const double qw64[2] = {c.q[0] * c.w[0], c.q[1] * c.w[1]};
+        launch_q_from_fixed(h->q[0], h->q[1], nodes, qw64, s);
+    }
     launch_zero(h->f.phi0, nodes * 8, s);
     if (c.field_solve) {
         st = solve<T>(h, h->f.phi0, (const T *)h->q[0], (const T *)h->q[1], 0.0, nullptr,
@@ -1895,6 +1910,7 @@ pic_status pic_fields(pic_handle *h, pic_field_view *out)
     out->q_dev[1] = h->q[1];
     out->nodes = (int64_t)(h->cfg.nr + 1) * (h->cfg.nz + 1);
     out->q_precision = h->prec;
+    out->phi0_prev_dev = h->f.phi0_prev;
     return PIC_OK;
 }
 
@@ -1933,6 +1949,8 @@ pic_status pic_get_state(const pic_handle *hc, pic_scalar_state *out)
     out->next_id[1] = sc.next_id[1];
     out->count[0] = sc.count[0];
     out->count[1] = sc.count[1];
+    out->sort_phase = h->steps_since_sort;
+    out->pad_ = 0;
     return PIC_OK;
 }
 
@@ -1942,6 +1960,8 @@ pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in)
     for (int s = 0; s < 2; ++s)
         if (in->count[s] < 0 || in->count[s] > h->cap[s])
             return fail(h, PIC_EINVAL, "count out of range");
+    if (in->sort_phase < 0 || in->sort_phase > h->cfg.sort_every)
+        return fail(h, PIC_EINVAL, "sort_phase outside [0, sort_every]");
     DevScalars sc;
     pic_status st = read_scalars(h, &sc);
     if (st != PIC_OK) return st;
@@ -1955,6 +1975,13 @@ pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in)
     HIPCHECK(h, hipMemcpy(h->sc, &sc, sizeof(sc), hipMemcpyHostToDevice));
     h->host_count[0] = in->count[0];
     h->host_count[1] = in->count[1];
+    h->steps_since_sort = in->sort_phase;
+    // phi and the gather fields from phi0 and the restored V_c
+    if (h->prec == PIC_F64)
+        launch_field_prep<double>(h->f, (double4 *)h->node, h->sc, h->cfg.scheme, 0, h->stream);
+    else
+        launch_field_prep<float>(h->f, (float4 *)h->node, h->sc, h->cfg.scheme, 0, h->stream);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
     return PIC_OK;
 }
 
@@ -2098,6 +2125,9 @@ pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *str
             return efail(nullptr, PIC_EINVAL, "run %d: every run must share the state precision", r);
         if (!h->cfg.field_solve)
             return efail(nullptr, PIC_EINVAL, "run %d: ensembles solve the field every step", r);
+        if (h->cfg.deposit_fixed)
+            return efail(nullptr, PIC_EINVAL, "run %d: the fixed-point deposit is a single-run mode",
+                         r);
         if (h->timers_on) return efail(nullptr, PIC_EINVAL, "run %d: timers must be off", r);
     }
     pic_ensemble *e = new pic_ensemble();

@@ -214,6 +214,7 @@ struct PushParams {
     int32_t deposit_only;       // 1: only deposit the current positions
     uint32_t key0, key1, run;
     int32_t nblk_e;             // blocks [0, nblk_e) push electrons, the rest ions
+    int32_t fixed_q;            // 1: fixed-point node charge (FP64 state)
 };
 
 template <typename T>
@@ -237,6 +238,8 @@ struct ChildParams {
     const Child<T> *child;
     int32_t child_cap;
     int32_t nr;
+    int32_t fixed_q;            // 1: fixed-point node charge (FP64 state)
+    double qw64[2];             // q w in FP64: the cathode charge of the step
 };
 
 // The cell sort of one species of a run: from the current buffer (src) into
@@ -372,6 +375,17 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+// Fixed-point node charge: a tent weight w (|w| < 512) rounded to the
+// nearest multiple of 2^-QFIX_BITS, as an integer.  w 2^42 + 1.5 2^52 lies in
+// [2^52, 2^53), where doubles are spaced by 1, so the one rounding of the
+// fused multiply-add leaves round(w 2^42) in the low mantissa bits.
+constexpr int QFIX_BITS = 42;
+__device__ __forceinline__ long long to_fixed(double w)
+{
+    const double m = __fma_rn(w, 0x1p42, 0x1.8p52);
+    return __double_as_longlong(m) - 0x4338000000000000LL;
+}
+
 // Global float/double atomic add using the hardware instruction (the
 // workspace is coarse-grained device memory).
 __device__ __forceinline__ void atomic_add_dev(float *p, float v) { unsafeAtomicAdd(p, v); }
@@ -399,7 +413,10 @@ template <typename T>
 void launch_events(const EventParams<T> &p, hipStream_t s);
 template <typename T>
 void launch_children(const ChildParams<T> &p, hipStream_t s);
-void launch_finalize_step(DevScalars *sc, const int64_t cap[2], hipStream_t s);
+void launch_finalize_step(DevScalars *sc, const int64_t cap[2], const double qw64[2],
+                          hipStream_t s);
+// fixed-point node charge (64-bit integers in place) to FP64 charge
+void launch_q_from_fixed(void *q0, void *q1, int64_t nodes, const double qw64[2], hipStream_t s);
 void launch_begin_step(DevScalars *sc, void *q0, void *q1, int64_t nodes, int elem_bytes,
                        hipStream_t s);
 template <typename T>

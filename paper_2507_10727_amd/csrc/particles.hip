@@ -100,7 +100,7 @@ template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return 
 template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
 
 struct Tally {
-    double ke = 0.0, pz = 0.0, dq = 0.0;
+    double ke = 0.0, pz = 0.0;
     unsigned int abs1 = 0, abs2 = 0, abs3 = 0, abs4 = 0;
     unsigned int cand = 0, el = 0, ex = 0, iz = 0, see = 0, fb = 0;
 };
@@ -117,49 +117,57 @@ __device__ __forceinline__ int advance(const PushParams<T> &P, T hqm,
                                        const typename Vec4<T>::type &a11, int &i, int &j, T &fr,
                                        T &fz, T &vr, T &vt, T &vz, T &ke_dot, T &pz_v)
 {
+    // Every rounding is written out (fused multiply-adds explicit, no
+    // contraction left to the compiler): the kernel handles up to four
+    // particles per thread in unrolled copies of this code, and a particle's
+    // result must not depend on which copy it falls in.
+#pragma clang fp contract(off)
     const int nr = P.nr, nz = P.nz;
     const T gr = (T)1 - fr, gz = (T)1 - fz;
     const T w00 = gr * gz, w10 = fr * gz, w01 = gr * fz, w11 = fr * fz;
+    auto tent = [&](T c00, T c10, T c01, T c11) {
+        return fma(w00, c00, fma(w10, c10, fma(w01, c01, w11 * c11)));
+    };
     T er, ez;
     if (SCHEME == PIC_EC) {
-        er = gz * a00.x + fz * a01.x;
-        ez = gr * a00.y + fr * a10.y;
+        er = fma(gz, a00.x, fz * a01.x);
+        ez = fma(gr, a00.y, fr * a10.y);
     } else {
-        er = w00 * a00.x + w10 * a10.x + w01 * a01.x + w11 * a11.x;
-        ez = w00 * a00.y + w10 * a10.y + w01 * a01.y + w11 * a11.y;
+        er = tent(a00.x, a10.x, a01.x, a11.x);
+        ez = tent(a00.y, a10.y, a01.y, a11.y);
     }
-    const T br = w00 * a00.z + w10 * a10.z + w01 * a01.z + w11 * a11.z;
-    const T bz = w00 * a00.w + w10 * a10.w + w01 * a01.w + w11 * a11.w;
+    const T br = tent(a00.z, a10.z, a01.z, a11.z);
+    const T bz = tent(a00.w, a10.w, a01.w, a11.w);
     // Boris: half kick, rotation about t = (q dt / 2m) B, half kick
-    const T mx = vr + hqm * er, my = vt, mz = vz + hqm * ez;
+    const T mx = fma(hqm, er, vr), my = vt, mz = fma(hqm, ez, vz);
     const T tx = hqm * br, tz = hqm * bz;
-    const T f2 = (T)2 * rcp<T>((T)1 + tx * tx + tz * tz);
+    const T f2 = (T)2 * rcp<T>(fma(tx, tx, fma(tz, tz, (T)1)));
     const T sx = f2 * tx, sz = f2 * tz;
-    const T px = mx + my * tz;
-    const T py = my + (mz * tx - mx * tz);
-    const T pzz = mz - my * tx;
-    const T qx = mx + py * sz;
-    const T qy = my + (pzz * sx - px * sz);
-    const T qz = mz - py * sx;
-    const T nx = qx + hqm * er, ny = qy, nzv = qz + hqm * ez;
-    ke_dot = vr * nx + vt * ny + vz * nzv;
+    const T px = fma(my, tz, mx);
+    const T py = my + fma(mz, tx, -(mx * tz));
+    const T pzz = fma(-my, tx, mz);
+    const T qx = fma(py, sz, mx);
+    const T qy = my + fma(pzz, sx, -(px * sz));
+    const T qz = fma(-py, sx, mz);
+    const T nx = fma(hqm, er, qx), ny = qy, nzv = fma(hqm, ez, qz);
+    ke_dot = fma(vr, nx, fma(vt, ny, vz * nzv));
     pz_v = nzv;
     // drift in (x, y, z) = (r, 0, z), rotate into the new meridional plane
     const T r = ((T)i + fr) * P.dr;
     const T dx = nx * P.dt, dy = ny * P.dt;
     const T x1 = r + dx;
-    const T r1 = fast_sqrt(x1 * x1 + dy * dy);
+    const T r1 = fast_sqrt(fma(x1, x1, dy * dy));
     T vr1 = nx, vt1 = ny, vz1 = nzv;
     if (r1 > (T)0) {
         const T inv = rcp<T>(r1);
         const T c = x1 * inv, sn = dy * inv;
-        vr1 = c * nx + sn * ny;
-        vt1 = c * ny - sn * nx;
+        vr1 = fma(c, nx, sn * ny);
+        vt1 = fma(c, ny, -(sn * nx));
     }
     const T den = r + r1;
-    const T drr = (den > (T)0) ? ((T)2 * r * dx + dx * dx + dy * dy) * rcp<T>(den) : (T)0;
-    const T xr = fr + drr * P.inv_dr;
-    const T xz = fz + nzv * P.dt * P.inv_dz;
+    const T drr = (den > (T)0) ? fma((T)2 * r, dx, fma(dx, dx, dy * dy)) * rcp<T>(den) : (T)0;
+    const T xr = fma(drr, P.inv_dr, fr);
+    const T xz = fma(nzv * P.dt, P.inv_dz, fz);
     const T flr = floor(xr), flz = floor(xz);
     int i1 = i + (int)flr, j1 = j + (int)flz;
     T fr1 = xr - flr, fz1 = xz - flz;
@@ -313,12 +321,16 @@ __device__ __forceinline__ float dpp_move(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
 }
 template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move(double v)
+__device__ __forceinline__ long long dpp_move(long long b)
 {
-    const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, true);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+    return ((long long)hi << 32) | (long long)(unsigned)lo;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    return __longlong_as_double(dpp_move<CTRL, ROWS>(__double_as_longlong(v)));
 }
 
 // Segmented inclusive sum over the wavefront: lane l ends with the sum of
@@ -347,29 +359,152 @@ __device__ __forceinline__ void wave_segment_sum(T &a0, T &a1, T &a2, T &a3, int
 #undef PIC_SEG_STEP
 }
 
-// Add one run's summed tent weights to its cell's four nodes.
+// How the deposit accumulates.  Floating: tent weights summed in T, scaled
+// by q w when added to a node.  Fixed point (FP64 state): each particle's
+// weights rounded to 64-bit fixed point and summed as integers, so the sums
+// do not depend on the order of the additions; q w is applied when the node
+// charge is converted after the step's last deposit.
+template <typename T, bool FIXED>
+struct DepAcc {
+    using A = T;
+    static __device__ __forceinline__ A weight(T w) { return w; }
+    static __device__ __forceinline__ A scaled(A a, T qw) { return qw * a; }
+    static __device__ __forceinline__ void lds_add(A *p, A v) { atomicAdd(p, v); }
+    static __device__ __forceinline__ void dev_add(A *p, A v) { atomic_add_dev(p, v); }
+};
 template <typename T>
-__device__ __forceinline__ void deposit_lds(T *lds, int ld, int key, T qw, T a00, T a10, T a01,
-                                            T a11)
+struct DepAcc<T, true> {
+    using A = long long;
+    static __device__ __forceinline__ A weight(T w) { return to_fixed((double)w); }
+    static __device__ __forceinline__ A scaled(A a, T) { return a; }
+    static __device__ __forceinline__ void lds_add(A *p, A v)
+    {
+        atomicAdd((unsigned long long *)p, (unsigned long long)v);
+    }
+    static __device__ __forceinline__ void dev_add(A *p, A v)
+    {
+        atomicAdd((unsigned long long *)p, (unsigned long long)v);
+    }
+};
+
+// Add one run's summed tent weights to its cell's four nodes.
+template <typename D, typename T>
+__device__ __forceinline__ void deposit_to(typename D::A *base, int64_t ld, int key, T qw,
+                                           typename D::A a00, typename D::A a10,
+                                           typename D::A a01, typename D::A a11, bool lds)
 {
     const int i = key & 0xffff, j = key >> 16;
-    T *p = lds + j * ld + i;
-    atomicAdd(p, qw * a00);
-    atomicAdd(p + 1, qw * a10);
-    atomicAdd(p + ld, qw * a01);
-    atomicAdd(p + ld + 1, qw * a11);
+    typename D::A *p = base + (int64_t)j * ld + i;
+    if (lds) {
+        D::lds_add(p, D::scaled(a00, qw));
+        D::lds_add(p + 1, D::scaled(a10, qw));
+        D::lds_add(p + ld, D::scaled(a01, qw));
+        D::lds_add(p + ld + 1, D::scaled(a11, qw));
+    } else {
+        D::dev_add(p, D::scaled(a00, qw));
+        D::dev_add(p + 1, D::scaled(a10, qw));
+        D::dev_add(p + ld, D::scaled(a01, qw));
+        D::dev_add(p + ld + 1, D::scaled(a11, qw));
+    }
 }
 
-template <typename T>
-__device__ __forceinline__ void deposit_global(T *q, int ld, int key, T qw, T a00, T a10, T a01,
-                                               T a11)
+// Deposit of the wavefront's chunk (up to four particles a lane; ok[k] is
+// the cell key of particle k, -1 for none): the chunk's node bounding box is
+// accumulated in the wavefront's own LDS tile when it fits (no wavefront
+// waits for another), else straight into global memory.
+template <typename T, bool FIXED, int WAVE_NODES>
+__device__ __forceinline__ void deposit_chunk(const int (&ok)[4], const T (&fr)[4],
+                                              const T (&fz)[4], void *tile_mem, void *q_mem,
+                                              int ldn, T qw, int lane, unsigned int &fb)
 {
-    const int i = key & 0xffff, j = key >> 16;
-    T *p = q + (int64_t)j * ld + i;
-    atomic_add_dev(p, qw * a00);
-    atomic_add_dev(p + 1, qw * a10);
-    atomic_add_dev(p + ld, qw * a01);
-    atomic_add_dev(p + ld + 1, qw * a11);
+    using D = DepAcc<T, FIXED>;
+    using A = typename D::A;
+    static_assert(sizeof(A) == sizeof(T) || !FIXED, "fixed point needs 8-byte tiles");
+    A *const tile = (A *)tile_mem;
+    A *const Q = (A *)q_mem;
+    int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (ok[k] < 0) continue;
+        const int i = ok[k] & 0xffff, j = ok[k] >> 16;
+        imin = min(imin, i); imax = max(imax, i);
+        jmin = min(jmin, j); jmax = max(jmax, j);
+    }
+    imin = wave_min(imin); imax = wave_max(imax);
+    jmin = wave_min(jmin); jmax = wave_max(jmax);
+    if (imax < imin) return;
+    const int bw = imax - imin + 2, bh = jmax - jmin + 2;
+    const bool use_lds = bw * bh <= WAVE_NODES;
+    if (use_lds) {
+        for (int q = lane; q < bw * bh; q += 64) tile[q] = (A)0;
+        wave_sync();
+    } else if (lane == 0) {
+        ++fb;
+    }
+    const int shift = (jmin << 16) | imin;
+    auto add_run = [&](int key, A a00, A a10, A a01, A a11) {
+        if (use_lds) deposit_to<D>(tile, bw, key - shift, qw, a00, a10, a01, a11, true);
+        else deposit_to<D>(Q, ldn, key, qw, a00, a10, a01, a11, false);
+    };
+    // the thread's particles summed per run of equal cells: the first run
+    // joins the wavefront's per-cell sum, later runs (the thread's particles
+    // span a cell boundary) are added directly
+    int cur = -1, key0 = -1;
+    A s00 = 0, s10 = 0, s01 = 0, s11 = 0;
+    A f00 = 0, f10 = 0, f01 = 0, f11 = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (ok[k] < 0) continue;
+        if (ok[k] != cur) {
+            if (cur >= 0) {
+                if (key0 < 0) {
+                    key0 = cur;
+                    f00 = s00; f10 = s10; f01 = s01; f11 = s11;
+                } else {
+                    add_run(cur, s00, s10, s01, s11);
+                }
+            }
+            cur = ok[k];
+            s00 = s10 = s01 = s11 = (A)0;
+        }
+        const T gr = (T)1 - fr[k], gz = (T)1 - fz[k];
+        s00 += D::weight(gr * gz);
+        s10 += D::weight(fr[k] * gz);
+        s01 += D::weight(gr * fz[k]);
+        s11 += D::weight(fr[k] * fz[k]);
+    }
+    if (cur >= 0) {
+        if (key0 < 0) {
+            key0 = cur;
+            f00 = s00; f10 = s10; f01 = s01; f11 = s11;
+        } else {
+            add_run(cur, s00, s10, s01, s11);
+        }
+    }
+    // per-cell sums over the wavefront's lanes: adjacent lanes whose first
+    // runs share a cell form a segment, its last lane adds the total (sorted
+    // particles make segments long, so few lanes add and the LDS atomics
+    // rarely meet on one address)
+    const bool valid = key0 >= 0;
+    const int prev = __shfl_up(key0, 1, 64), next = __shfl_down(key0, 1, 64);
+    const bool head = valid && (lane == 0 || prev != key0);
+    const bool tail = valid && (lane == 63 || next != key0);
+    const unsigned long long upto = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const unsigned long long hb = __ballot(head) & upto;
+    const int first = hb ? 63 - __clzll(hb) : lane;
+    wave_segment_sum(f00, f10, f01, f11, lane, first);
+    if (tail) add_run(key0, f00, f10, f01, f11);
+    if (use_lds) {
+        wave_sync();
+        for (int q = lane; q < bw * bh; q += 64) {
+            const A v = tile[q];
+            if (v != (A)0) {
+                const int lj = q / bw, li = q - lj * bw;
+                D::dev_add(&Q[(int64_t)(jmin + lj) * ldn + imin + li], v);
+            }
+        }
+        wave_sync();
+    }
 }
 
 // Append (slot, aux) to an event queue.  Entries past the capacity are
@@ -441,7 +576,7 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
     constexpr int NW = PUSH_THREADS / 64;
     constexpr int WAVE_NODES = LDS_NODES / NW;
     __shared__ T lds_q[LDS_NODES];
-    __shared__ double dred[3][NW];
+    __shared__ double dred[2][NW];
     __shared__ unsigned long long cred[10][NW];
 
     const int tid = threadIdx.x;
@@ -556,7 +691,6 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
                     kk[k] = -1;
                     if (fate == 1) {
                         ++t.abs1;
-                        t.dq += P.cold->qw64[s];
                         // emission is decided in the event kernel; the
                         // entry's slot carries the species in bit 31
                         if (emit)
@@ -626,119 +760,39 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
         t.ke += (double)ke_c;
         t.pz += (double)pz_c;
 
-        // ---- deposit: bounding box of the wavefront's cells, accumulated
-        // in the wavefront's own LDS tile (no wavefront waits for another)
-        int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (ok[k] < 0) continue;
-            const int i = ok[k] & 0xffff, j = ok[k] >> 16;
-            imin = min(imin, i); imax = max(imax, i);
-            jmin = min(jmin, j); jmax = max(jmax, j);
-        }
-        imin = wave_min(imin); imax = wave_max(imax);
-        jmin = wave_min(jmin); jmax = wave_max(jmax);
-        if (imax >= imin) {
-            const int bw = imax - imin + 2, bh = jmax - jmin + 2;
-            const bool use_lds = bw * bh <= WAVE_NODES;
-            if (use_lds) {
-                for (int q = lane; q < bw * bh; q += 64) tile[q] = (T)0;
-                wave_sync();
-            } else if (lane == 0) {
-                ++t.fb;
-            }
-            const int shift = (jmin << 16) | imin;
-            auto add_run = [&](int key, T a00, T a10, T a01, T a11) {
-                if (use_lds) deposit_lds(tile, bw, key - shift, qw, a00, a10, a01, a11);
-                else deposit_global(Q, ldn, key, qw, a00, a10, a01, a11);
-            };
-            // the thread's particles summed per run of equal cells: the first
-            // run joins the wavefront's per-cell sum, later runs (the thread's
-            // particles span a cell boundary) are added directly
-            int cur = -1, key0 = -1;
-            T s00 = 0, s10 = 0, s01 = 0, s11 = 0;
-            T f00 = 0, f10 = 0, f01 = 0, f11 = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (ok[k] < 0) continue;
-                if (ok[k] != cur) {
-                    if (cur >= 0) {
-                        if (key0 < 0) {
-                            key0 = cur;
-                            f00 = s00; f10 = s10; f01 = s01; f11 = s11;
-                        } else {
-                            add_run(cur, s00, s10, s01, s11);
-                        }
-                    }
-                    cur = ok[k];
-                    s00 = s10 = s01 = s11 = (T)0;
-                }
-                const T gr = (T)1 - fr[k], gz = (T)1 - fz[k];
-                s00 += gr * gz;
-                s10 += fr[k] * gz;
-                s01 += gr * fz[k];
-                s11 += fr[k] * fz[k];
-            }
-            if (cur >= 0) {
-                if (key0 < 0) {
-                    key0 = cur;
-                    f00 = s00; f10 = s10; f01 = s01; f11 = s11;
-                } else {
-                    add_run(cur, s00, s10, s01, s11);
-                }
-            }
-            // per-cell sums over the wavefront's lanes: adjacent lanes whose
-            // first runs share a cell form a segment, its last lane adds the
-            // total (sorted particles make segments long, so few lanes add
-            // and the LDS atomics rarely meet on one address)
-            const bool valid = key0 >= 0;
-            const int prev = __shfl_up(key0, 1, 64), next = __shfl_down(key0, 1, 64);
-            const bool head = valid && (lane == 0 || prev != key0);
-            const bool tail = valid && (lane == 63 || next != key0);
-            const unsigned long long upto =
-                (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
-            const unsigned long long hb = __ballot(head) & upto;
-            const int first = hb ? 63 - __clzll(hb) : lane;
-            wave_segment_sum(f00, f10, f01, f11, lane, first);
-            if (tail) add_run(key0, f00, f10, f01, f11);
-            if (use_lds) {
-                wave_sync();
-                for (int q = lane; q < bw * bh; q += 64) {
-                    const T v = tile[q];
-                    if (v != (T)0) {
-                        const int lj = q / bw, li = q - lj * bw;
-                        atomic_add_dev(&Q[(int64_t)(jmin + lj) * ldn + imin + li], v);
-                    }
-                }
-                wave_sync();
-            }
+        // ---- deposit of the chunk
+        if constexpr (sizeof(T) == 8) {
+            if (P.fixed_q)
+                deposit_chunk<T, true, WAVE_NODES>(ok, fr, fz, tile, Q, ldn, qw, lane, t.fb);
+            else
+                deposit_chunk<T, false, WAVE_NODES>(ok, fr, fz, tile, Q, ldn, qw, lane, t.fb);
+        } else {
+            deposit_chunk<T, false, WAVE_NODES>(ok, fr, fz, tile, Q, ldn, qw, lane, t.fb);
         }
     }
 
     // ---- block totals of the diagnostics, one atomic per quantity
     const double mw = P.mw[s];
-    double dv[3] = {wave_sum(0.5 * mw * t.ke), wave_sum(mw * t.pz), wave_sum(t.dq)};
+    double dv[2] = {wave_sum(0.5 * mw * t.ke), wave_sum(mw * t.pz)};
     unsigned long long c[10] = {t.abs1, t.abs2, t.abs3, t.abs4, 0, 0, 0, 0, 0, t.fb};
 #pragma unroll
     for (int q = 0; q < 10; ++q) c[q] = wave_sum_u64(c[q]);
     if (lane == 0) {
-        for (int q = 0; q < 3; ++q) dred[q][wid] = dv[q];
+        for (int q = 0; q < 2; ++q) dred[q][wid] = dv[q];
         for (int q = 0; q < 10; ++q) cred[q][wid] = c[q];
     }
     __syncthreads();
     if (tid == 0) {
-        double a = 0, b = 0, d = 0;
+        double a = 0, b = 0;
         unsigned long long tt[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int w = 0; w < NW; ++w) {
             a += dred[0][w];
             b += dred[1][w];
-            d += dred[2][w];
             for (int q = 0; q < 10; ++q) tt[q] += cred[q][w];
         }
         DevScalars *sc = P.sc;
         if (a != 0.0) atomic_add_dev(&sc->ke[s], a);
         if (b != 0.0) atomic_add_dev(&sc->pz[s], b);
-        if (d != 0.0) atomic_add_dev(&sc->dq_conv, d);
         for (int q = 0; q < 4; ++q)
             if (tt[q]) atomicAdd(&sc->n_abs[s][q + 1], tt[q]);
         if (tt[4]) atomicAdd(&sc->n_cand, tt[4]);
@@ -796,7 +850,6 @@ __device__ void events_body(const EventParams<T> P, int bid, int nb)
     const int nm = min(sc->n_mcc_q, P.ev_cap);
     const int ns = min(sc->n_see_q, P.ev_cap);
     unsigned int coll[4] = {0u, 0u, 0u, 0u}, see[2] = {0u, 0u};
-    double dq = 0.0;
     const uint32_t w_e = P.run << 8;
     for (int e = bid * blockDim.x + threadIdx.x; e < nm + ns; e += nb * blockDim.x) {
         if (e < nm) {
@@ -823,7 +876,6 @@ __device__ void events_body(const EventParams<T> P, int bid, int nb)
             const uint4 u = philox4x32_10(make_uint4(pid, word, step, 0u), P.key0, P.key1);
             if ((unsigned long long)u.x < C->t_see[s]) {
                 ++see[s];
-                dq -= C->qw64[0];
                 int ie;
                 T fe;
                 see_impact(P.sp[s], q, ie, fe);
@@ -837,7 +889,6 @@ __device__ void events_body(const EventParams<T> P, int bid, int nb)
         if (coll[q]) atomicAdd(&sc->n_coll[q], (unsigned long long)coll[q]);
     if (see[1]) atomicAdd(&sc->n_see, (unsigned long long)see[1]);
     if (see[0]) atomicAdd(&sc->n_see_e, (unsigned long long)see[0]);
-    if (dq != 0.0) atomic_add_dev(&sc->dq_conv, dq);
     if (bid == 0 && threadIdx.x == 0) {
         sc->n_cand = (unsigned long long)nm;
         if (sc->n_mcc_q > P.ev_cap || sc->n_see_q > P.ev_cap) atomicOr(&sc->flags, FLAG_CHILD_OVERFLOW);
@@ -936,10 +987,21 @@ __device__ void children_body(const ChildParams<T> P, int bid, int nb, unsigned 
                 S.id[slot] = P.sc->next_id[s] + (uint32_t)rank;
                 const int64_t n0 = (int64_t)j * ldn + i;
                 const T qw = P.qw[s], gr = (T)1 - fr, gz = (T)1 - fz;
-                atomic_add_dev(&P.q[s][n0], qw * gr * gz);
-                atomic_add_dev(&P.q[s][n0 + 1], qw * fr * gz);
-                atomic_add_dev(&P.q[s][n0 + ldn], qw * gr * fz);
-                atomic_add_dev(&P.q[s][n0 + ldn + 1], qw * fr * fz);
+                bool fixed = false;
+                if constexpr (sizeof(T) == 8) fixed = P.fixed_q != 0;
+                if (fixed) {
+                    using D = DepAcc<T, true>;
+                    long long *q = (long long *)P.q[s];
+                    D::dev_add(q + n0, D::weight(gr * gz));
+                    D::dev_add(q + n0 + 1, D::weight(fr * gz));
+                    D::dev_add(q + n0 + ldn, D::weight(gr * fz));
+                    D::dev_add(q + n0 + ldn + 1, D::weight(fr * fz));
+                } else {
+                    atomic_add_dev(&P.q[s][n0], qw * gr * gz);
+                    atomic_add_dev(&P.q[s][n0 + 1], qw * fr * gz);
+                    atomic_add_dev(&P.q[s][n0 + ldn], qw * gr * fz);
+                    atomic_add_dev(&P.q[s][n0 + ldn + 1], qw * fr * fz);
+                }
             }
         }
     }
@@ -983,10 +1045,15 @@ void launch_children_b(const PartBatch<T> &b, hipStream_t s)
 }
 
 // Counts and id counters advance by the children of the step; the step
-// counter advances.
-__device__ void finalize_body(DevScalars *sc, int64_t cap0, int64_t cap1)
+// counter advances.  The charge into the cathode is formed from the step's
+// integer tallies (particles of each species absorbed there, electrons
+// emitted from it), which makes it independent of the order of events.
+__device__ void finalize_body(DevScalars *sc, int64_t cap0, int64_t cap1, double qw_e,
+                              double qw_i)
 {
     const int64_t cap[2] = {cap0, cap1};
+    sc->dq_conv = (double)sc->n_abs[0][1] * qw_e + (double)sc->n_abs[1][1] * qw_i -
+                  (double)(sc->n_see + sc->n_see_e) * qw_e;
     for (int s = 0; s < 2; ++s) {
         int64_t c = sc->count[s] + sc->n_child_s[s];
         if (c > cap[s]) c = cap[s];
@@ -1001,10 +1068,11 @@ __device__ void finalize_body(DevScalars *sc, int64_t cap0, int64_t cap1)
     sc->step += 1;
 }
 
-__global__ void k_finalize_step(DevScalars *sc, int64_t cap0, int64_t cap1)
+__global__ void k_finalize_step(DevScalars *sc, int64_t cap0, int64_t cap1, double qw_e,
+                                double qw_i)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    finalize_body(sc, cap0, cap1);
+    finalize_body(sc, cap0, cap1, qw_e, qw_i);
 }
 
 // one thread per run
@@ -1014,12 +1082,35 @@ __global__ void k_finalize_b(PartBatch<T> B)
     const int r = (int)threadIdx.x;
     if (r >= B.nruns) return;
     const ChildParams<T> &C = B.p[r]->ch;
-    finalize_body(C.sc, C.cap[0], C.cap[1]);
+    finalize_body(C.sc, C.cap[0], C.cap[1], C.qw64[0], C.qw64[1]);
 }
 
-void launch_finalize_step(DevScalars *sc, const int64_t cap[2], hipStream_t s)
+void launch_finalize_step(DevScalars *sc, const int64_t cap[2], const double qw64[2],
+                          hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize_step, dim3(1), dim3(64), 0, s, sc, cap[0], cap[1]);
+    hipLaunchKernelGGL(k_finalize_step, dim3(1), dim3(64), 0, s, sc, cap[0], cap[1], qw64[0],
+                       qw64[1]);
+}
+
+// Node charge of both species from fixed point (in place): the integer sum
+// of rounded tent weights times q w 2^-42.  Exact conversion below 2^53,
+// then one rounding of the product.
+__global__ void k_q_from_fixed(long long *q0, long long *q1, int64_t nodes, double s0, double s1)
+{
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nodes;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        const long long a = q0[n], b = q1[n];
+        ((double *)q0)[n] = (double)a * s0;
+        ((double *)q1)[n] = (double)b * s1;
+    }
+}
+
+void launch_q_from_fixed(void *q0, void *q1, int64_t nodes, const double qw64[2], hipStream_t s)
+{
+    const double u = ldexp(1.0, -QFIX_BITS);
+    const int blocks = (int)std::min<int64_t>(1024, (nodes + 255) / 256);
+    hipLaunchKernelGGL(k_q_from_fixed, dim3(std::max(blocks, 1)), dim3(256), 0, s,
+                       (long long *)q0, (long long *)q1, nodes, qw64[0] * u, qw64[1] * u);
 }
 
 template <typename T>

@@ -33,6 +33,7 @@ def make_config(prob: W.Problem, b_r, b_z, sigma, de_table=W.DE_TABLE, capacity=
     c.gamma_e = prob.gamma_e
     c.n_meta = prob.n_meta
     c.e_iz_meta = prob.e_iz_meta
+    c.deposit_fixed = prob.deposit_fixed
     c.p_gas, c.t_gas = prob.p_gas, prob.t_gas
     c.e_exc, c.e_iz = prob.e_exc, prob.e_iz
     c.sigma = sig.ctypes.data_as(C.POINTER(C.c_double))
@@ -187,14 +188,61 @@ class Simulation:
         s = L.pic_scalar_state()
         L.check(self.lib.pic_get_state(self.h, C.byref(s)), self.h)
         return {"step": s.step, "vc": s.vc, "qc": s.qc, "next_id": tuple(s.next_id),
-                "count": tuple(s.count)}
+                "count": tuple(s.count), "sort_phase": s.sort_phase}
 
     def set_state(self, st):
         s = L.pic_scalar_state()
         s.step, s.vc, s.qc = st["step"], st["vc"], st["qc"]
         s.next_id[0], s.next_id[1] = st["next_id"]
         s.count[0], s.count[1] = st["count"]
+        s.sort_phase = st.get("sort_phase", 0)
         L.check(self.lib.pic_set_state(self.h, C.byref(s)), self.h)
+
+    def checkpoint(self):
+        """Host copy of everything a resumed run needs: the scalar state, the
+        used slots of both species' arrays, phi0 and phi0_prev."""
+        st = self.get_state()
+        ck = {"state": st}
+        for s in range(2):
+            t = self.particle_tensors(s)
+            ck[f"species{s}"] = {k: v.cpu().clone() for k, v in t.items()}
+        f = self.fields()
+        ck["phi0"] = f["phi0"].cpu().clone()
+        ck["phi0_prev"] = f["phi0_prev"].cpu().clone()
+        return ck
+
+    def restore(self, ck):
+        """Write a checkpoint into this simulation (same configuration): the
+        arrays through the views, then the scalar state, which rebuilds phi
+        and the gather fields."""
+        torch = self.torch
+        for s in range(2):
+            src = ck[f"species{s}"]
+            n = int(ck["state"]["count"][s])
+            v = L.pic_particle_view()
+            L.check(self.lib.pic_particles(self.h, int(s), C.byref(v)), self.h)
+            if n > v.capacity:
+                raise ValueError(f"species {s}: {n} particles exceed capacity {v.capacity}")
+            ft = torch.float64 if v.precision == 1 else torch.float32
+            dst = {"id": self._view(v.id_dev, n, torch.int32)}
+            if v.pos_bits:
+                dst["pr"] = self._view(v.fr_dev, n, torch.int32)
+                dst["pz"] = self._view(v.fz_dev, n, torch.int32)
+            else:
+                dst["key"] = self._view(v.key_dev, n, torch.int32)
+                dst["fr"] = self._view(v.fr_dev, n, ft)
+                dst["fz"] = self._view(v.fz_dev, n, ft)
+            for k in ("vr", "vt", "vz"):
+                dst[k] = self._view(getattr(v, k + "_dev"), n, ft)
+            if dst.keys() != src.keys():
+                raise ValueError("checkpoint taken with another state precision")
+            for k in dst:
+                dst[k].copy_(src[k][:n].to(self.device))
+        f = self.fields()
+        f["phi0"].copy_(ck["phi0"].to(self.device))
+        f["phi0_prev"].copy_(ck["phi0_prev"].to(self.device))
+        torch.cuda.synchronize(self.device)
+        self.set_state(ck["state"])
 
     # -- learned preconditioner ----------------------------------------------
     def pc_param_count(self):
@@ -327,6 +375,7 @@ class Simulation:
         qt = torch.float64 if v.q_precision == 1 else torch.float32
         return {"phi": self._view(v.phi_dev, n, torch.float64),
                 "phi0": self._view(v.phi0_dev, n, torch.float64),
+                "phi0_prev": self._view(v.phi0_prev_dev, n, torch.float64),
                 "phi_l": self._view(v.phi_l_dev, n, torch.float64),
                 "q_e": self._view(v.q_dev[0], n, qt), "q_i": self._view(v.q_dev[1], n, qt)}
 

@@ -75,6 +75,7 @@ class Problem:
     gamma_e: float = 0.0        # electron-induced yield (Section 3: 0.1)
     n_meta: float = 0.0         # static Ar* density (Section 3: 2.5e17 m^-3)
     e_iz_meta: float = 4.20     # ionization threshold from Ar* (eV)
+    deposit_fixed: int = 0      # 1: fixed-point node charge (FP64, bit-reproducible)
     p_gas: float = 5e-3 * TORR
     t_gas: float = 300.0
     e_exc: float = 11.5

@@ -74,6 +74,8 @@ def test_query_workspace_sizes():
     # the direct solve needs the cathode over the whole z = 0 row
     dict(poisson_mode=W.POISSON_DIRECT, cathode_rmax=0.85 * 0.02),
     dict(poisson_mode=W.POISSON_DIRECT, nr=2048, nz=64, lr=0.64),
+    # the fixed-point deposit sums 8-byte integers in the FP64 tiles
+    dict(deposit_fixed=1, precision=W.F32), dict(deposit_fixed=2),
 ])
 def test_invalid_configs_rejected(bad):
     lib = L.load()
@@ -82,6 +84,17 @@ def test_invalid_configs_rejected(bad):
     st = lib.pic_query_workspace(C.byref(cfg), C.byref(n))
     assert st == L.PIC_EINVAL
     assert lib.pic_last_error(None)
+
+
+def test_fixed_point_deposit_accepted_in_fp64():
+    lib = L.load()
+    n0, n1 = C.c_int64(), C.c_int64()
+    cfg, keep = _cfg(precision=W.F64)
+    assert lib.pic_query_workspace(C.byref(cfg), C.byref(n0)) == 0
+    cfg, keep = _cfg(precision=W.F64, deposit_fixed=1)
+    assert lib.pic_query_workspace(C.byref(cfg), C.byref(n1)) == 0
+    # the integer sums reuse the FP64 node-charge arrays
+    assert n0.value == n1.value
 
 
 def test_fp32_grid_limit_of_packed_positions():
