@@ -227,6 +227,88 @@ def gather_forms_bench(workload, steps=100, warmup=20, box_steps=4000, box_every
     return out
 
 
+def throughput(p, steps=20, warmup=5):
+    """Whole steps of one discharge: particle-steps/s, ms per step, and the
+    fused particle kernel's average time (HIP events on the library's
+    stream) and algorithmic HBM rate; deposit windows that fell back to
+    global atomics in the last step."""
+    import torch
+    from paper_2507_10727_amd import workloads as W
+    from paper_2507_10727_amd.sim import Simulation
+    br, bz, sig, parts = W.inputs(p)
+    sim = Simulation(p, br, bz, sig, parts, timers=False)
+    del parts
+    sim.step(warmup)
+    d0 = sim.diag()
+    sim.lib.pic_enable_timers(sim.h, 2)
+    sim.timers(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = sim.timers(reset=True)
+    d1 = sim.diag()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    ne = 0.5 * (d0["count"][0] + d1["count"][0])
+    ni = 0.5 * (d0["count"][1] + d1["count"][1])
+    dtype = "f32" if p.precision == W.F32 else "f64"
+    push_ms = tm["push_ms"] / max(tm["push_launches"], 1)
+    algo = ALGO_BYTES[dtype]["e"] * ne + ALGO_BYTES[dtype]["i"] * ni
+    gbs = algo / (push_ms * 1e-3) / 1e9
+    return {"workload": p.name, "scheme": "EC-PIC" if p.scheme == W.EC_PIC else "MC-PIC",
+            "particle_steps_per_s": (ne + ni) * steps / wall, "ms_per_step": wall / steps * 1e3,
+            "steps": steps, "push_avg_ms": push_ms, "push_gbs_algorithmic": gbs,
+            "push_frac": gbs / HBM_PEAK_GBS, "deposit_fallback_last_step": d1["deposit_fallback"],
+            "count": d1["count"]}
+
+
+def high_density_bench(steps=20, warmup=5, box_steps=2000, box_every=40):
+    """The high-density discharge (512 x 1024 cells, 5e7 + 5e7, n = 1e17):
+    both gather forms and the clustered load (half of each species in the
+    ring 0.35 R < r < 0.5 R, z < 0.1 L, about 3e3 particles per species per
+    cell there).  Then the closed thermal box at this discharge's grid, cell
+    (2.9 Debye lengths) and particle count with each gather form: EC-PIC's
+    total energy stays bounded, MC-PIC's electrons heat (Section 5)."""
+    import numpy as np
+    import torch
+    from paper_2507_10727_amd import workloads as W
+    from paper_2507_10727_amd.sim import Simulation
+    out = {}
+    for name in ("ec512x1024_f32", "mc512x1024_f32", "ec512x1024_clustered_f32"):
+        r = throughput(W.preset(name), steps, warmup)
+        log(f"[bench] {name}: {r}")
+        out[name] = r
+    base = W.preset("ec512x1024_f32")
+    ppc = max(1, base.n_per_species // (base.nr * base.nz))
+    box = {}
+    for form, scheme in (("ec", W.EC_PIC), ("mc", W.MC_PIC)):
+        bp, bparts = W.thermal_box(base.nr, base.nz, base.dr, ppc, scheme, base.precision)
+        bbr, bbz = W.magnetron_field(bp)
+        sim = Simulation(bp, bbr, bbz, W.cross_sections(bp.e_exc, bp.e_iz), bparts)
+        del bparts
+        ke, tot = [], []
+        for _ in range(box_steps // box_every):
+            sim.step(box_every)
+            d = sim.diag()
+            ke.append(d["ke"][0])
+            tot.append(d["ke"][0] + d["w_field"])
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        ke, tot = np.array(ke), np.array(tot)
+        m = max(1, len(ke) // 20)
+        box[form] = {"grid": f"{bp.nr}x{bp.nz}", "particles_per_species": bp.n_per_species,
+                     "density_m3": bp.density, "dt_s": bp.dt, "steps": box_steps,
+                     "total_energy_drift_max": float(np.abs(tot - tot[0]).max() / tot[0]),
+                     "electron_ke_growth": float(ke[-m:].mean() / ke[:m].mean() - 1.0)}
+        log(f"[bench] high-density box {form}: {box[form]}")
+    out["thermal_box"] = box
+    return out
+
+
 def ensemble_bench(n_runs=64, steps=10, scale=1.0):
     """The yield / resistance sweep (workloads.ensemble_problems): the runs
     advanced one after another through pic_step, then the same runs advanced
@@ -322,6 +404,10 @@ def main():
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched sweep against sequential runs (prints its JSON)")
     ap.add_argument("--ensemble-runs", type=int, default=64)
+    ap.add_argument("--no-high-density", action="store_true",
+                    help="skip the 512 x 1024 discharges (uniform EC/MC and clustered)")
+    ap.add_argument("--high-density-only", action="store_true",
+                    help="only the 512 x 1024 discharges (prints their JSON)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -339,6 +425,9 @@ def main():
         return
     if args.ensemble_only:
         print(json.dumps({"ensemble": ensemble_bench(args.ensemble_runs)}), flush=True)
+        return
+    if args.high_density_only:
+        print(json.dumps({"high_density": high_density_bench()}), flush=True)
         return
 
     if args.copy_calibration:
@@ -416,6 +505,10 @@ def main():
     if not args.no_forms:
         log("[bench] gather forms (EC-PIC / MC-PIC)")
         forms = gather_forms_bench(args.workload)
+    hd = None
+    if not args.no_high_density:
+        log("[bench] 512 x 1024 discharges")
+        hd = high_density_bench()
     ensemble = None
     if not args.no_ensemble:
         log(f"[bench] ensemble of {args.ensemble_runs} runs")
@@ -445,6 +538,7 @@ def main():
         "phase_ms_per_step": phases,
         "poisson": poisson,
         "gather_forms": forms,
+        "high_density": hd,
         "ensemble": ensemble,
         "diag": {"vc": d1["vc"], "i_cathode": d1["i_cathode"], "n_coll": d1["n_coll"],
                  "deposit_fallback": d1["deposit_fallback"], "count": d1["count"]},

@@ -87,7 +87,7 @@ struct pic_handle {
     // launch shape of the particle kernel (autotuned): total blocks and the
     // weight of an electron against an ion when splitting them
     int push_blocks = 1024;
-    double push_e_weight = 1.3;
+    double push_e_weight = 1.0;
     bool mg_one_level = false;      // V-cycle with one kernel per grid level
     // pinned host block the field solve reads its status and inner residuals
     // back into (a copy to pageable memory is staged and synchronous)

@@ -11,18 +11,20 @@ namespace pic {
 // Fused particle kernel.
 //
 // One launch covers both species: blocks [0, nblk_e) stream the electrons,
-// the rest the ions.  Each block walks its species in chunks of PUSH_CHUNK
-// consecutive slots (grid-stride); thread t owns the 4 consecutive slots
-// 4t..4t+3 of a chunk and moves them with one 16-byte load and store per
+// the rest the ions.  Each wavefront walks a contiguous range of its
+// species' slots in chunks of 256; lane l owns the 4 consecutive slots
+// 4l..4l+3 of a chunk and moves them with one 16-byte load and store per
 // array, so a wavefront reads and writes 1 KiB contiguous segments.
-// Particles are kept sorted by cell, so a thread's 4 particles usually share
+// Particles are kept sorted by cell, so a lane's 4 particles usually share
 // a cell: the 4 node 4-vectors of the gather are loaded once per distinct
-// cell, and the deposit is summed in registers per run of equal cells before
-// it goes to LDS.  Each wavefront accumulates its 256 particles' charge in
-// its own LDS tile over the box of nodes they touch and flushes it with one
-// global atomic per node; a box that does not fit (unsorted or scattered
-// particles) uses global atomics.  The wavefronts of a block never wait for
-// each other inside the chunk loop, so one's loads overlap another's deposit.
+// cell, and the deposit is summed in registers per run of equal cells, then
+// per run of equal cells across lanes, before it goes to LDS.  Each
+// wavefront accumulates its charge in a window of node rows held in its own
+// LDS tile, kept from chunk to chunk while its (sorted) particles stay
+// inside, and adds a window to the global charge with one atomic per
+// nonzero node when it moves on; a chunk too spread for a window uses global
+// atomics.  The wavefronts of a block never wait for each other, so one's
+// loads overlap another's deposit.
 //
 // Per particle (Section 2 for the gather, Section 3 for walls, emission and
 // collisions):
@@ -363,13 +365,16 @@ __device__ __forceinline__ void wave_segment_sum(T &a0, T &a1, T &a2, T &a3, int
 // by q w when added to a node.  Fixed point (FP64 state): each particle's
 // weights rounded to 64-bit fixed point and summed as integers, so the sums
 // do not depend on the order of the additions; q w is applied when the node
-// charge is converted after the step's last deposit.
+// charge is converted after the step's last deposit.  The wavefront's tile
+// is addressed through LDS pointers, so its atomics are LDS instructions.
+template <typename A>
+using lds_ptr = __attribute__((address_space(3))) A *;
+
 template <typename T, bool FIXED>
 struct DepAcc {
     using A = T;
     static __device__ __forceinline__ A weight(T w) { return w; }
     static __device__ __forceinline__ A scaled(A a, T qw) { return qw * a; }
-    static __device__ __forceinline__ void lds_add(A *p, A v) { atomicAdd(p, v); }
     static __device__ __forceinline__ void dev_add(A *p, A v) { atomic_add_dev(p, v); }
 };
 template <typename T>
@@ -377,74 +382,156 @@ struct DepAcc<T, true> {
     using A = long long;
     static __device__ __forceinline__ A weight(T w) { return to_fixed((double)w); }
     static __device__ __forceinline__ A scaled(A a, T) { return a; }
-    static __device__ __forceinline__ void lds_add(A *p, A v)
-    {
-        atomicAdd((unsigned long long *)p, (unsigned long long)v);
-    }
     static __device__ __forceinline__ void dev_add(A *p, A v)
     {
         atomicAdd((unsigned long long *)p, (unsigned long long)v);
     }
 };
 
-// Add one run's summed tent weights to its cell's four nodes.
+template <typename A>
+__device__ __forceinline__ void lds_add(lds_ptr<A> p, A v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Add one run's summed tent weights to its cell's four nodes: in the
+// wavefront's LDS tile (key relative to the tile) or in global memory.
 template <typename D, typename T>
-__device__ __forceinline__ void deposit_to(typename D::A *base, int64_t ld, int key, T qw,
-                                           typename D::A a00, typename D::A a10,
-                                           typename D::A a01, typename D::A a11, bool lds)
+__device__ __forceinline__ void deposit_lds(lds_ptr<typename D::A> tile, int ld, int key, T qw,
+                                            typename D::A a00, typename D::A a10,
+                                            typename D::A a01, typename D::A a11)
 {
     const int i = key & 0xffff, j = key >> 16;
-    typename D::A *p = base + (int64_t)j * ld + i;
-    if (lds) {
-        D::lds_add(p, D::scaled(a00, qw));
-        D::lds_add(p + 1, D::scaled(a10, qw));
-        D::lds_add(p + ld, D::scaled(a01, qw));
-        D::lds_add(p + ld + 1, D::scaled(a11, qw));
-    } else {
-        D::dev_add(p, D::scaled(a00, qw));
-        D::dev_add(p + 1, D::scaled(a10, qw));
-        D::dev_add(p + ld, D::scaled(a01, qw));
-        D::dev_add(p + ld + 1, D::scaled(a11, qw));
+    lds_ptr<typename D::A> p = tile + (j * ld + i);
+    lds_add(p, D::scaled(a00, qw));
+    lds_add(p + 1, D::scaled(a10, qw));
+    lds_add(p + ld, D::scaled(a01, qw));
+    lds_add(p + ld + 1, D::scaled(a11, qw));
+}
+template <typename D, typename T>
+__device__ __forceinline__ void deposit_dev(typename D::A *q, int ld, int key, T qw,
+                                            typename D::A a00, typename D::A a10,
+                                            typename D::A a01, typename D::A a11)
+{
+    const int i = key & 0xffff, j = key >> 16;
+    typename D::A *p = q + ((int64_t)j * ld + i);
+    D::dev_add(p, D::scaled(a00, qw));
+    D::dev_add(p + 1, D::scaled(a10, qw));
+    D::dev_add(p + ld, D::scaled(a01, qw));
+    D::dev_add(p + ld + 1, D::scaled(a11, qw));
+}
+
+// Wavefront-wide minimum / maximum, uniform in every lane: lane moves
+// within rows of 16 (DPP: swap neighbours, swap pairs, mirror halves,
+// mirror the row), then the four row results read from lanes 15, 31, 47, 63.
+template <bool MAX>
+__device__ __forceinline__ int wave_extreme(int v)
+{
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
+    const int a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
+    const int c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
+    return op(op(a, b), op(c, d));
+}
+
+// The wavefront's deposit window: node rows [j0, j0 + h) x columns
+// [i0, i0 + w) of the grid held in its LDS tile (h w <= the tile's nodes).
+// A wavefront walks a contiguous range of cell-sorted particles, so its
+// chunks mostly fall in one window; the window is written to global memory
+// (one atomic per nonzero node) only when a chunk leaves it and at the end.
+struct DepWindow {
+    int i0, j0, w, h;
+    bool on;
+};
+
+// Add the window's nonzero nodes to the global charge and clear them.
+template <typename D>
+__device__ __forceinline__ void window_flush(lds_ptr<typename D::A> tile, DepWindow &win,
+                                             typename D::A *Q, int ldn, int lane)
+{
+    using A = typename D::A;
+    if (!win.on) return;
+    wave_sync();
+    for (int r = 0; r < win.h; ++r) {
+        const lds_ptr<A> row = tile + r * win.w;
+        A *const qrow = Q + (int64_t)(win.j0 + r) * ldn + win.i0;
+        for (int c = lane; c < win.w; c += 64) {
+            const A v = row[c];
+            if (v != (A)0) {
+                D::dev_add(qrow + c, v);
+                row[c] = (A)0;
+            }
+        }
     }
+    wave_sync();
+    win.on = false;
 }
 
 // Deposit of the wavefront's chunk (up to four particles a lane; ok[k] is
-// the cell key of particle k, -1 for none): the chunk's node bounding box is
-// accumulated in the wavefront's own LDS tile when it fits (no wavefront
-// waits for another), else straight into global memory.
+// the cell key of particle k, -1 for none) into its window; a chunk outside
+// the window moves it (flush, then a window around the chunk's node
+// bounding box), and a chunk too spread for any window goes straight to
+// global memory.  Every lane of the wavefront takes part.
 template <typename T, bool FIXED, int WAVE_NODES>
 __device__ __forceinline__ void deposit_chunk(const int (&ok)[4], const T (&fr)[4],
-                                              const T (&fz)[4], void *tile_mem, void *q_mem,
-                                              int ldn, T qw, int lane, unsigned int &fb)
+                                              const T (&fz)[4], lds_ptr<T> tile_mem, void *q_mem,
+                                              int ldn, T qw, int lane, unsigned int &fb,
+                                              DepWindow &win)
 {
     using D = DepAcc<T, FIXED>;
     using A = typename D::A;
-    static_assert(sizeof(A) == sizeof(T) || !FIXED, "fixed point needs 8-byte tiles");
-    A *const tile = (A *)tile_mem;
+    static_assert(sizeof(A) == sizeof(T), "the tile holds T-sized words");
+    const lds_ptr<A> tile = (lds_ptr<A>)tile_mem;
     A *const Q = (A *)q_mem;
-    int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
+    bool fits = win.on;
+    if (fits) {
+        bool mine = true;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (ok[k] < 0) continue;
-        const int i = ok[k] & 0xffff, j = ok[k] >> 16;
-        imin = min(imin, i); imax = max(imax, i);
-        jmin = min(jmin, j); jmax = max(jmax, j);
+        for (int k = 0; k < 4; ++k) {
+            if (ok[k] < 0) continue;
+            const int i = ok[k] & 0xffff, j = ok[k] >> 16;
+            mine = mine && (unsigned)(i - win.i0) < (unsigned)(win.w - 1) &&
+                   (unsigned)(j - win.j0) < (unsigned)(win.h - 1);
+        }
+        fits = __ballot(!mine) == 0ull;
     }
-    imin = wave_min(imin); imax = wave_max(imax);
-    jmin = wave_min(jmin); jmax = wave_max(jmax);
-    if (imax < imin) return;
-    const int bw = imax - imin + 2, bh = jmax - jmin + 2;
-    const bool use_lds = bw * bh <= WAVE_NODES;
-    if (use_lds) {
-        for (int q = lane; q < bw * bh; q += 64) tile[q] = (A)0;
-        wave_sync();
-    } else if (lane == 0) {
-        ++fb;
+    if (!fits) {
+        int imin = INT_MAX, imax = INT_MIN, jmin = INT_MAX, jmax = INT_MIN;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (ok[k] < 0) continue;
+            const int i = ok[k] & 0xffff, j = ok[k] >> 16;
+            imin = min(imin, i); imax = max(imax, i);
+            jmin = min(jmin, j); jmax = max(jmax, j);
+        }
+        imin = wave_extreme<false>(imin); imax = wave_extreme<true>(imax);
+        jmin = wave_extreme<false>(jmin); jmax = wave_extreme<true>(jmax);
+        if (imax < imin) return;                 // no particle in the chunk
+        window_flush<D>(tile, win, Q, ldn, lane);
+        // three node rows (a cell row and its neighbours' drift), as many
+        // columns as the tile holds from one column before the chunk (the
+        // wavefront's later chunks lie at larger keys)
+        const int h = max(jmax - jmin + 2, 3);
+        const int i0 = max(imin - 1, 0);
+        const int w = min(WAVE_NODES / h, ldn - i0);
+        if (imax + 2 - i0 <= w) {
+            win.i0 = i0;
+            win.j0 = jmin;
+            win.w = w;
+            win.h = h;
+            win.on = true;
+        } else if (lane == 0) {
+            ++fb;
+        }
     }
-    const int shift = (jmin << 16) | imin;
+    const int shift = (win.j0 << 16) | win.i0;
+    const bool use_lds = win.on;
     auto add_run = [&](int key, A a00, A a10, A a01, A a11) {
-        if (use_lds) deposit_to<D>(tile, bw, key - shift, qw, a00, a10, a01, a11, true);
-        else deposit_to<D>(Q, ldn, key, qw, a00, a10, a01, a11, false);
+        if (use_lds) deposit_lds<D>(tile, win.w, key - shift, qw, a00, a10, a01, a11);
+        else deposit_dev<D>(Q, ldn, key, qw, a00, a10, a01, a11);
     };
     // the thread's particles summed per run of equal cells: the first run
     // joins the wavefront's per-cell sum, later runs (the thread's particles
@@ -486,7 +573,10 @@ __device__ __forceinline__ void deposit_chunk(const int (&ok)[4], const T (&fr)[
     // particles make segments long, so few lanes add and the LDS atomics
     // rarely meet on one address)
     const bool valid = key0 >= 0;
-    const int prev = __shfl_up(key0, 1, 64), next = __shfl_down(key0, 1, 64);
+    // neighbours' keys by whole-wavefront lane shifts (DPP wave_shr / wave_shl
+    // by one; the end lanes keep their own key and are decided by lane index)
+    const int prev = __builtin_amdgcn_update_dpp(key0, key0, 0x138, 0xF, 0xF, false);
+    const int next = __builtin_amdgcn_update_dpp(key0, key0, 0x130, 0xF, 0xF, false);
     const bool head = valid && (lane == 0 || prev != key0);
     const bool tail = valid && (lane == 63 || next != key0);
     const unsigned long long upto = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
@@ -494,17 +584,6 @@ __device__ __forceinline__ void deposit_chunk(const int (&ok)[4], const T (&fr)[
     const int first = hb ? 63 - __clzll(hb) : lane;
     wave_segment_sum(f00, f10, f01, f11, lane, first);
     if (tail) add_run(key0, f00, f10, f01, f11);
-    if (use_lds) {
-        wave_sync();
-        for (int q = lane; q < bw * bh; q += 64) {
-            const A v = tile[q];
-            if (v != (A)0) {
-                const int lj = q / bw, li = q - lj * bw;
-                D::dev_add(&Q[(int64_t)(jmin + lj) * ldn + imin + li], v);
-            }
-        }
-        wave_sync();
-    }
 }
 
 // Append (slot, aux) to an event queue.  Entries past the capacity are
@@ -581,7 +660,7 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    T *const tile = lds_q + wid * WAVE_NODES;
+    const lds_ptr<T> tile = (lds_ptr<T>)(lds_q + wid * WAVE_NODES);
     const int s = (bid < nblk_e) ? 0 : 1;
     const int blk = s ? bid - nblk_e : bid;
     const int nblk = s ? nb - nblk_e : nblk_e;
@@ -604,65 +683,87 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
     T *__restrict__ Q = P.q[s];
     Tally t;
 
-    for (int64_t base = (int64_t)blk * PUSH_CHUNK; base < n;
-         base += (int64_t)nblk * PUSH_CHUNK) {
-        const int64_t p0 = base + 4 * tid;
+    // Each wavefront takes a contiguous range of the species' chunks of 64 x
+    // PUSH_PPT particles.  The particles are cell-sorted, so the range covers
+    // a compact run of cells (its deposit stays in one LDS window), and
+    // wavefronts running at the same time work on distant cells (their
+    // global charge atomics do not meet on the same nodes).
+    constexpr int WCHUNK = 64 * PUSH_PPT;
+    const int64_t nch = (n + WCHUNK - 1) / WCHUNK;
+    const int64_t wv = (int64_t)blk * NW + wid, nwv = (int64_t)nblk * NW;
+    const int64_t c_end = (wv + 1) * nch / nwv;
+    DepWindow win = {0, 0, 0, 0, false};
+    for (int q = lane; q < WAVE_NODES; q += 64) tile[q] = (T)0;
+    // FP32: the deposit of a chunk runs in the next iteration, between the
+    // issue of that chunk's loads and their first use, so it overlaps their
+    // latency (FP64 deposits in place: the held words would cost occupancy)
+    int pok[4] = {-1, -1, -1, -1};
+    T pfr[4] = {(T)0, (T)0, (T)0, (T)0}, pfz[4] = {(T)0, (T)0, (T)0, (T)0};
+    auto deposit_prev = [&]() {
+        if constexpr (sizeof(T) == 8) {
+            if (P.fixed_q)
+                deposit_chunk<T, true, WAVE_NODES>(pok, pfr, pfz, tile, Q, ldn, qw, lane, t.fb, win);
+            else
+                deposit_chunk<T, false, WAVE_NODES>(pok, pfr, pfz, tile, Q, ldn, qw, lane, t.fb, win);
+        } else {
+            deposit_chunk<T, false, WAVE_NODES>(pok, pfr, pfz, tile, Q, ldn, qw, lane, t.fb, win);
+        }
+    };
+    for (int64_t c = wv * nch / nwv; c < c_end; ++c) {
+        const int64_t p0 = c * WCHUNK + 4 * lane;
         int kk[4];
         T fr[4], fz[4], vr[4], vt[4], vz[4];
         uint32_t id[4] = {0u, 0u, 0u, 0u};
+        // slots p0..p0+3 are inside the (4-rounded) capacity; those at or
+        // beyond the count are masked and written back unchanged; a lane past
+        // the end reads slot 0 and discards it.  Every load of the chunk is
+        // issued before any of them is used, so the wavefront waits for
+        // memory once per chunk.
         const bool any = p0 < n;
-        if (any) {
-            // slots p0..p0+3 are inside the (4-rounded) capacity; those at or
-            // beyond the count are masked and written back unchanged.  Every
-            // load of the chunk is issued before any of them is used, so the
-            // wavefront waits for memory once per chunk.
-            if constexpr (sizeof(T) == 4) {
-                const uint4 wr = stream_load((const uint4 *)(FR + p0));
-                const int4 wz = stream_load((const int4 *)(FZ + p0));
-                const T4 c = stream_load((const T4 *)(VR + p0));
-                const T4 d = stream_load((const T4 *)(VT + p0));
-                const T4 e = stream_load((const T4 *)(VZ + p0));
-                uint4 iv = make_uint4(0u, 0u, 0u, 0u);
-                if (collide_on) iv = stream_load((const uint4 *)(ID + p0));
-                const uint32_t r4[4] = {wr.x, wr.y, wr.z, wr.w};
-                const int32_t z4[4] = {wz.x, wz.y, wz.z, wz.w};
+        const int64_t pl = any ? p0 : 0;
+        if constexpr (sizeof(T) == 4) {
+            const uint4 wr = stream_load((const uint4 *)(FR + pl));
+            const int4 wz = stream_load((const int4 *)(FZ + pl));
+            const T4 c4 = stream_load((const T4 *)(VR + pl));
+            const T4 d = stream_load((const T4 *)(VT + pl));
+            const T4 e = stream_load((const T4 *)(VZ + pl));
+            uint4 iv = make_uint4(0u, 0u, 0u, 0u);
+            if (collide_on) iv = stream_load((const uint4 *)(ID + pl));
+            deposit_prev();
+            const uint32_t r4[4] = {wr.x, wr.y, wr.z, wr.w};
+            const int32_t z4[4] = {wz.x, wz.y, wz.z, wz.w};
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    // branch-free: an absorbed slot (pz = -1) gives key -1, fz 0
-                    const uint32_t zc = (uint32_t)max(z4[k], 0);
-                    fr[k] = pos_frac(r4[k]);
-                    fz[k] = pos_frac(zc);
-                    kk[k] = ((pos_cell(zc) << 16) | pos_cell(r4[k])) | (z4[k] >> 31);
-                }
-                vr[0] = c.x; vr[1] = c.y; vr[2] = c.z; vr[3] = c.w;
-                vt[0] = d.x; vt[1] = d.y; vt[2] = d.z; vt[3] = d.w;
-                vz[0] = e.x; vz[1] = e.y; vz[2] = e.z; vz[3] = e.w;
-                id[0] = iv.x; id[1] = iv.y; id[2] = iv.z; id[3] = iv.w;
-            } else {
-                const int4 k4 = stream_load((const int4 *)(KEY + p0));
-                const T4 a = stream_load((const T4 *)(FR + p0));
-                const T4 b = stream_load((const T4 *)(FZ + p0));
-                const T4 c = stream_load((const T4 *)(VR + p0));
-                const T4 d = stream_load((const T4 *)(VT + p0));
-                const T4 e = stream_load((const T4 *)(VZ + p0));
-                uint4 iv = make_uint4(0u, 0u, 0u, 0u);
-                if (collide_on) iv = stream_load((const uint4 *)(ID + p0));
-                kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
-                fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
-                fz[0] = b.x; fz[1] = b.y; fz[2] = b.z; fz[3] = b.w;
-                vr[0] = c.x; vr[1] = c.y; vr[2] = c.z; vr[3] = c.w;
-                vt[0] = d.x; vt[1] = d.y; vt[2] = d.z; vt[3] = d.w;
-                vz[0] = e.x; vz[1] = e.y; vz[2] = e.z; vz[3] = e.w;
-                id[0] = iv.x; id[1] = iv.y; id[2] = iv.z; id[3] = iv.w;
+            for (int k = 0; k < 4; ++k) {
+                // branch-free: an absorbed slot (pz = -1) gives key -1, fz 0
+                const uint32_t zc = (uint32_t)max(z4[k], 0);
+                fr[k] = pos_frac(r4[k]);
+                fz[k] = pos_frac(zc);
+                kk[k] = ((pos_cell(zc) << 16) | pos_cell(r4[k])) | (z4[k] >> 31);
             }
-#pragma unroll
-            for (int k = 1; k < 4; ++k)
-                if (p0 + k >= n) kk[k] = -1;
+            vr[0] = c4.x; vr[1] = c4.y; vr[2] = c4.z; vr[3] = c4.w;
+            vt[0] = d.x; vt[1] = d.y; vt[2] = d.z; vt[3] = d.w;
+            vz[0] = e.x; vz[1] = e.y; vz[2] = e.z; vz[3] = e.w;
+            id[0] = iv.x; id[1] = iv.y; id[2] = iv.z; id[3] = iv.w;
         } else {
-            kk[0] = kk[1] = kk[2] = kk[3] = -1;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) fr[k] = fz[k] = vr[k] = vt[k] = vz[k] = (T)0;
+            const int4 k4 = stream_load((const int4 *)(KEY + pl));
+            const T4 a = stream_load((const T4 *)(FR + pl));
+            const T4 b = stream_load((const T4 *)(FZ + pl));
+            const T4 c4 = stream_load((const T4 *)(VR + pl));
+            const T4 d = stream_load((const T4 *)(VT + pl));
+            const T4 e = stream_load((const T4 *)(VZ + pl));
+            uint4 iv = make_uint4(0u, 0u, 0u, 0u);
+            if (collide_on) iv = stream_load((const uint4 *)(ID + pl));
+            kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
+            fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
+            fz[0] = b.x; fz[1] = b.y; fz[2] = b.z; fz[3] = b.w;
+            vr[0] = c4.x; vr[1] = c4.y; vr[2] = c4.z; vr[3] = c4.w;
+            vt[0] = d.x; vt[1] = d.y; vt[2] = d.z; vt[3] = d.w;
+            vz[0] = e.x; vz[1] = e.y; vz[2] = e.z; vz[3] = e.w;
+            id[0] = iv.x; id[1] = iv.y; id[2] = iv.z; id[3] = iv.w;
         }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (p0 + k >= n) kk[k] = -1;
         int ok[4];   // cell key after the push, -1 if none
         T ke_c = (T)0, pz_c = (T)0;
         if (!frozen) {
@@ -760,15 +861,24 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
         t.ke += (double)ke_c;
         t.pz += (double)pz_c;
 
-        // ---- deposit of the chunk
-        if constexpr (sizeof(T) == 8) {
-            if (P.fixed_q)
-                deposit_chunk<T, true, WAVE_NODES>(ok, fr, fz, tile, Q, ldn, qw, lane, t.fb);
-            else
-                deposit_chunk<T, false, WAVE_NODES>(ok, fr, fz, tile, Q, ldn, qw, lane, t.fb);
-        } else {
-            deposit_chunk<T, false, WAVE_NODES>(ok, fr, fz, tile, Q, ldn, qw, lane, t.fb);
+        // ---- deposit of the chunk: FP32 in the next iteration (or after the
+        // loop), FP64 here
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            pok[k] = ok[k];
+            pfr[k] = fr[k];
+            pfz[k] = fz[k];
         }
+        if constexpr (sizeof(T) == 8) deposit_prev();
+    }
+    if constexpr (sizeof(T) == 4) deposit_prev();
+    if constexpr (sizeof(T) == 8) {
+        if (P.fixed_q)
+            window_flush<DepAcc<T, true>>((lds_ptr<long long>)tile, win, (long long *)Q, ldn, lane);
+        else
+            window_flush<DepAcc<T, false>>(tile, win, Q, ldn, lane);
+    } else {
+        window_flush<DepAcc<T, false>>(tile, win, Q, ldn, lane);
     }
 
     // ---- block totals of the diagnostics, one atomic per quantity

@@ -102,6 +102,8 @@ class Problem:
     pc_batch: int = 0           # training batch of the learned preconditioner
     pc_maxit: int = 0           # learned iterations before the multigrid fallback
     weight: Optional[float] = None  # macroparticle weight; default n*V/N
+    cluster: float = 0.0        # fraction of each species loaded in the ring
+    #                             0.35 R < r < 0.5 R, z < 0.1 L (deposit stress)
 
     def __post_init__(self):
         if self.cathode_rmax is None:
@@ -186,7 +188,12 @@ def preset(name: str) -> Problem:
                        peak B 0.05 T (the throughput case; mc256x512_f32 is
                        the same with the MC gather).
     ec512x1024_f32   : 512x1024 cells over 5x10 cm, 5e7 + 5e7, n = 1e17,
-                       20 mTorr, -500 V through 10/100 ohm (high-density case).
+                       20 mTorr, -500 V through 10/100 ohm (high-density case;
+                       mc512x1024_f32 the same with the MC gather).
+    ec512x1024_clustered_f32 : the high-density case with half of each
+                       species in the ring 0.35 R < r < 0.5 R, z < 0.1 L (the
+                       magnetised ring above the cathode): about 3e3
+                       particles per species per cell there (deposit stress).
     """
     if name == "small_mc64_f64":
         return Problem(name=name, poisson_mode=POISSON_DIRECT)
@@ -198,14 +205,15 @@ def preset(name: str) -> Problem:
             p_gas=10e-3 * TORR, b_peak=0.05, density=1e16,
             n_per_species=10_000_000, steps=20000, seed=250710728,
             capacity_factor=1.25, poisson_mode=POISSON_DIRECT)
-    if name in ("ec512x1024_f32", "mc512x1024_f32"):
+    if name in ("ec512x1024_f32", "mc512x1024_f32", "ec512x1024_clustered_f32"):
         return Problem(
             name=name, nr=512, nz=1024, lr=0.05, lz=0.10,
             scheme=EC_PIC if name.startswith("ec") else MC_PIC, precision=F32,
             circuit=RESISTOR, v_ext=-500.0, v_fixed=-500.0, r_ext=100.0,
             p_gas=20e-3 * TORR, b_peak=0.05, density=1e17,
             n_per_species=50_000_000, steps=20000, seed=250710729,
-            capacity_factor=1.1, poisson_mode=POISSON_DIRECT)
+            capacity_factor=1.1, poisson_mode=POISSON_DIRECT,
+            cluster=0.5 if "clustered" in name else 0.0)
     raise KeyError(name)
 
 
@@ -344,7 +352,9 @@ class SpeciesArrays:
 def load_uniform(p: Problem, n: Optional[int] = None, seed_offset: int = 0):
     """Uniform-in-volume positions (r = R sqrt(U), z = L U) and Maxwellian
     velocities (Te for electrons, Ti for ions); ids 0..N-1 per species.
-    Sampled velocities are taken as v^{n-1/2}.
+    Sampled velocities are taken as v^{n-1/2}.  With p.cluster = c > 0 the
+    first round(c N) particles of each species are instead uniform in volume
+    over the ring 0.35 R < r < 0.5 R, 0 <= z < 0.1 L.
     """
     n = p.n_per_species if n is None else n
     rng = np.random.Generator(np.random.PCG64(p.seed + 7919 * seed_offset))
@@ -354,6 +364,11 @@ def load_uniform(p: Problem, n: Optional[int] = None, seed_offset: int = 0):
         vth = math.sqrt(t_ev * E_CHARGE / m)
         r = p.lr * np.sqrt(rng.random(n))
         z = p.lz * rng.random(n)
+        nc = int(round(p.cluster * n))
+        if nc > 0:
+            r0, r1 = 0.35 * p.lr, 0.5 * p.lr
+            r[:nc] = np.sqrt(r0 * r0 + (r1 * r1 - r0 * r0) * rng.random(nc))
+            z[:nc] = 0.1 * p.lz * rng.random(nc)
         # keep strictly inside [0, L): rng.random() < 1 already
         v = rng.standard_normal((3, n)) * vth
         out.append(SpeciesArrays(r, z, v[0].copy(), v[1].copy(), v[2].copy(),

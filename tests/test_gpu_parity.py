@@ -530,3 +530,37 @@ def test_long_run_statistics_against_oracle(prec):
             tol = max(tol, 3.0 * math.hypot(sem, ref["i_cathode_sem_a"]))
         say(f"  {k}: gpu {v:.6g} oracle {r:.6g} rel {abs(v - r) / abs(r):.2e} (tol {tol / abs(r):.2e})")
         assert abs(v - r) <= tol, k
+
+
+@pytest.mark.parametrize("name", ["ec512x1024_clustered_f32", "ec512x1024_f32"])
+def test_f32_full_size_deposit_matches_oracle(name):
+    """The node charge of the 512 x 1024 discharge at full size (5e7 + 5e7,
+    the clustered load puts half of each species in the ring 0.35 R < r <
+    0.5 R, z < 0.1 L, about 3e3 per species per cell) after two steps,
+    against the oracle's deposit of the GPU's own particles, node by node.
+    FP32 weights summed in FP32 over up to ~1e4 particles a node: within
+    2e-6 of the largest node charge of the species, and the total charge
+    exact to 1e-6."""
+    p = W.preset(name)
+    br, bz, sig, parts = W.inputs(p)
+    say("case f32 full-size deposit", name, p.n_per_species, "cluster", p.cluster)
+    sim = gpu_sim(p, br, bz, sig, parts)
+    del parts
+    sim.step(2)
+    d = sim.diag()
+    say("  deposit fallbacks in the last step", d["deposit_fallback"])
+    f = sim.fields_host()
+    tiny = [W.SpeciesArrays(*(np.full(1, 0.5 * x) for x in (p.lr, p.lz)),
+                            *(np.zeros(1) for _ in range(3)), np.zeros(1, np.uint32))
+            for _ in range(2)]
+    o = O.Oracle(p, br, bz, sig, tiny, capacity=(1024, 1024))
+    for s, key in ((0, "q_e"), (1, "q_i")):
+        g = sim.particles(s)
+        qw = p.species()[s][0] * p.species()[s][2]
+        ref = o.deposit(g["r"], g["z"], qw)
+        got = f[key]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        say(f"  species {s}: {g['id'].shape[0]} particles, max node error {err:.2e}")
+        assert err <= 2e-6
+        assert got.sum() == approx(qw * g["id"].shape[0], rel=1e-6)
+    sim.close()
