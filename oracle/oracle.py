@@ -21,6 +21,7 @@ LIB_OMP = os.path.join(HERE, "liborc_omp.so")
 
 _dp = C.POINTER(C.c_double)
 _up = C.POINTER(C.c_uint32)
+_up64 = C.POINTER(C.c_uint64)
 
 
 class Problem(C.Structure):
@@ -44,6 +45,8 @@ class Problem(C.Structure):
         ("extra_current", C.c_double),
         ("poisson_rtol", C.c_double), ("poisson_maxit", C.c_int32),
         ("gamma_e", C.c_double), ("n_meta", C.c_double), ("e_iz_meta", C.c_double),
+        ("ied_emax", C.c_double), ("ied_r0", C.c_double), ("ied_r1", C.c_double),
+        ("ied_nbins", C.c_int32), ("ied_hist", _up64),
     ]
 
 
@@ -247,6 +250,32 @@ class Oracle:
             S.r, S.z, S.vr, S.vt, S.vz = (_d(arrs[k]) for k in ("r", "z", "vr", "vt", "vz"))
             S.id = _u(arrs["id"])
             S.n, S.cap = n, c
+
+    def ied_config(self, emax_ev, nbins, r0, r1):
+        """Record the energies of Ar+ absorbed by the cathode with r0 <= r <
+        r1 (Section 7) in nbins bins over [0, emax_ev) plus an overflow bin,
+        from the next step on."""
+        self.ied_hist = np.zeros(int(nbins) + 1, np.uint64)
+        self.P.ied_emax, self.P.ied_r0, self.P.ied_r1 = emax_ev, r0, r1
+        self.P.ied_nbins = int(nbins)
+        self.P.ied_hist = self.ied_hist.ctypes.data_as(_up64)
+
+    def ied(self):
+        return self.ied_hist.copy()
+
+    def reweight(self, k):
+        """Keep the particles whose id is a multiple of k and multiply both
+        species' weight by k (one in k kept, expected charge unchanged)."""
+        from oracle import diagnostics as D
+        for s in range(2):
+            n = self.S[s].n
+            a = self.arrays[s]
+            keep = D.reweight_keep(a["id"][:n], k)
+            m = int(keep.sum())
+            for key in a:
+                a[key][:m] = a[key][:n][keep]
+            self.S[s].n = m
+            self.P.w[s] *= k
 
     def init(self):
         rc = lib().orc_init(C.byref(self.P), self.S, C.byref(self.state), _d(self.phi),

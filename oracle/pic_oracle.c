@@ -839,6 +839,15 @@ int orc_step(const orc_problem *p, orc_species sp[2], orc_state *st,
                 a->n_abs[fate]++;
                 if (fate == 1) {
                     a->dq += p->q[s] * p->w[s];
+                    if (s == 1 && p->ied_hist && r1 >= p->ied_r0 && r1 < p->ied_r1) {
+                        const double e_ev = 0.5 * p->m[1] * (vr1 * vr1 + vt1 * vt1 + vz1 * vz1) / QE;
+                        double x = floor(e_ev / p->ied_emax * p->ied_nbins);
+                        const int64_t b = (x >= p->ied_nbins) ? p->ied_nbins : (int64_t)x;
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                        p->ied_hist[b]++;
+                    }
                     /* secondary emission (Section 3): ions with yield
                      * gamma_i, electrons with gamma_e, independently; the
                      * secondary is an electron at rest at (r', 0) */

@@ -56,6 +56,14 @@ typedef struct orc_problem {
     double gamma_e;            /* electron-induced secondary electron yield */
     double n_meta;             /* static Ar* (metastable) density (m^-3)    */
     double e_iz_meta;          /* ionization threshold from Ar* (eV)        */
+    /* Ion energy distribution at the cathode (Section 7): when ied_hist is
+     * not NULL, every Ar+ absorbed by the cathode with ied_r0 <= r' < ied_r1
+     * adds one count to bin floor(E / ied_emax * ied_nbins) of ied_hist,
+     * E = m |v|^2 / 2 (eV) with the velocity of its last push; energies at
+     * or above ied_emax go to bin ied_nbins (ied_nbins + 1 counters). */
+    double ied_emax, ied_r0, ied_r1;
+    int32_t ied_nbins;
+    uint64_t *ied_hist;
 } orc_problem;
 
 typedef struct orc_species {
