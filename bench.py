@@ -309,6 +309,50 @@ def high_density_bench(steps=20, warmup=5, box_steps=2000, box_every=40):
     return out
 
 
+def table1_bench(steps=200_000, chunk=2000):
+    """Table 1's trends on the 3 x 3 cm geometry of Section 3: ion yield 0.1
+    or 0.2 and R = 3000 or 1000 ohm (electron yield 0.1, -300 V), the four
+    runs advanced together as one ensemble.  Reports per run the cathode
+    voltage and the external-circuit current (V_ext - V_c) / R averaged over
+    the last quarter of the steps, and the particle counts."""
+    import numpy as np
+    import torch
+    from paper_2507_10727_amd import workloads as W
+    from paper_2507_10727_amd.sim import Ensemble, Simulation
+    probs = W.table1_problems(steps)
+    sims = []
+    for p in probs:
+        br, bz, sig, parts = W.inputs(p)
+        sims.append(Simulation(p, br, bz, sig, parts))
+    ens = Ensemble(sims)
+    hist = [[] for _ in probs]
+    t0 = time.perf_counter()
+    for k in range(steps // chunk):
+        ens.step(chunk)
+        for r, s in enumerate(sims):
+            d = s.diag()
+            hist[r].append((d["vc"], d["i_cathode"], d["count"][0], d["count"][1]))
+        if (k + 1) % 10 == 0:
+            log(f"[bench] table1 step {(k + 1) * chunk}: vc "
+                + " ".join(f"{h[-1][0]:.1f}" for h in hist)
+                + " counts " + " ".join(f"{h[-1][2]}" for h in hist))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"steps": steps, "dt_s": probs[0].dt, "wall_s": wall, "runs": []}
+    for p, h in zip(probs, hist):
+        a = np.array(h)
+        q = a[len(a) * 3 // 4:]
+        vc = float(q[:, 0].mean())
+        out["runs"].append({"gamma_i": p.gamma_i, "r_ohm": p.r_ext, "vc_v": vc,
+                            "i_circuit_a": (p.v_ext - vc) / p.r_ext,
+                            "i_cathode_sampled_a": float(q[:, 1].mean()),
+                            "electrons": int(q[-1, 2]), "ions": int(q[-1, 3])})
+    ens.close()
+    for s in sims:
+        s.close()
+    return out
+
+
 def ensemble_bench(n_runs=64, steps=10, scale=1.0):
     """The yield / resistance sweep (workloads.ensemble_problems): the runs
     advanced one after another through pic_step, then the same runs advanced
@@ -404,6 +448,9 @@ def main():
     ap.add_argument("--ensemble-only", action="store_true",
                     help="only the batched sweep against sequential runs (prints its JSON)")
     ap.add_argument("--ensemble-runs", type=int, default=64)
+    ap.add_argument("--table1-only", type=int, default=0, metavar="STEPS",
+                    help="only the Table 1 trend runs on the 3 x 3 cm geometry, STEPS steps "
+                         "(prints their JSON)")
     ap.add_argument("--no-high-density", action="store_true",
                     help="skip the 512 x 1024 discharges (uniform EC/MC and clustered)")
     ap.add_argument("--high-density-only", action="store_true",
@@ -425,6 +472,9 @@ def main():
         return
     if args.ensemble_only:
         print(json.dumps({"ensemble": ensemble_bench(args.ensemble_runs)}), flush=True)
+        return
+    if args.table1_only:
+        print(json.dumps({"table1": table1_bench(args.table1_only)}), flush=True)
         return
     if args.high_density_only:
         print(json.dumps({"high_density": high_density_bench()}), flush=True)

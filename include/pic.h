@@ -293,6 +293,68 @@ pic_status pic_set_phi(pic_handle *h, const double *phi);
 /* Cell-sort and compact both species now (drops absorbed slots). */
 pic_status pic_compact(pic_handle *h);
 
+/* ---- plasma diagnostics (Sections 4, 5 and 7) -------------------------------
+ * Electron moments per cell (nearest grid point: cell (i, j) holds
+ * i dr <= r < (i + 1) dr, j dz <= z < (j + 1) dz): count N, velocity sum S1
+ * and sum of squared speeds S2, in FP64.  Cell maps: n = N w / V_cell with
+ * V_cell = pi (r_{i+1}^2 - r_i^2) dz for both species; the electron
+ * temperature T = m (S2 / N - |S1 / N|^2) / (3 e) in eV (cells with at least
+ * two electrons; 0 elsewhere); the Debye length sqrt(eps0 T / (e n_e)) (m,
+ * +inf where n_e or T is zero).  Section 4 compares with the cell size the
+ * Debye length where the electron density is largest: lambda_d_peak is the
+ * one of the first cell of largest n_e (j-major order).
+ * Over the band of cells whose centre lies in [r0, r1) (Section 5 uses
+ * 1.0 cm < r < 1.5 cm): per cell row the band densities (counts times w over
+ * the band volume) and the band potential per node row (mean over the band
+ * cells of the midpoint of each cell's lower edge), E_z = -d phi / dz per cell
+ * row.  Sheath edge (Section 4: n_e = n_i / 2): the first cell row from the
+ * cathode with n_e >= n_i / 2, interpolated linearly from the row below
+ * between cell centres (0 if the first row qualifies, NaN if none).  Bulk
+ * edge (E_z = 0): above the sheath edge, the first change of E_z from
+ * negative to non-negative, interpolated likewise (NaN if none).  Region
+ * temperatures (Section 5): count-weighted means of the band cells'
+ * temperatures with the cell centre below the sheath edge (sheath), between
+ * the edges (pre-sheath) and above the bulk edge (bulk); with no sheath edge
+ * every band cell counts as sheath. */
+typedef struct pic_plasma_out {
+    double z_sheath, z_bulk;    /* m; NaN if not found                          */
+    double te_region[3];        /* eV: sheath, pre-sheath, bulk                 */
+    int64_t n_region[3];        /* electrons counted in each                    */
+    double lambda_d_peak;       /* m, in the cell of largest n_e                */
+    double n_e_peak;            /* m^-3, that cell's density                    */
+    double te_peak;             /* eV, that cell's temperature                  */
+    int32_t peak_cell[2];       /* (i, j) of that cell                          */
+    int32_t band_cells[2];      /* the band's cells [i0, i1)                    */
+} pic_plasma_out;
+
+/* Compute the diagnostics of the current state (particles as they stand,
+ * potential of the last step).  maps_host: NULL, or 4 nr nz doubles filled
+ * with the cell maps n_e, n_i, T_e, lambda_D (cell (i, j) at j nr + i, one map
+ * after the other).  Errors: PIC_EINVAL (r0 >= r1).  Synchronizes. */
+pic_status pic_plasma_diagnostics(pic_handle *h, double r0, double r1, pic_plasma_out *out,
+                                  double *maps_host);
+
+/* Ion energy distribution at the cathode (Section 7): from the next step on,
+ * every Ar+ absorbed by the cathode at radius r0 <= r < r1 adds one count to
+ * bin floor(E / emax_ev * nbins), E = m_i |v|^2 / 2 in eV with the velocity of
+ * its last push; E >= emax_ev counts in bin nbins.  nbins = 0 stops the
+ * record.  Clears the counts.  Ensembles take the setting of their runs when
+ * they are created.  Errors: PIC_EINVAL (nbins outside [0, 4096]; emax_ev <=
+ * 0 or r0 >= r1 with nbins > 0).  Synchronizes. */
+pic_status pic_ied_config(pic_handle *h, double emax_ev, int32_t nbins, double r0, double r1);
+
+/* Copy the nbins + 1 counters to counts (host, ncounts = nbins + 1) and clear
+ * them if reset != 0.  Errors: PIC_EINVAL (ncounts mismatch).  Synchronizes. */
+pic_status pic_ied_read(pic_handle *h, uint64_t *counts, int32_t ncounts, int32_t reset);
+
+/* Re-weighting (Section 5, removing particles and raising the weight when
+ * the particle count grows large): keep the particles of both species whose
+ * id is a multiple of keep_every, compact, and multiply both weights by
+ * keep_every (the expected charge is unchanged).  The node charge follows at
+ * the next step.  Not for runs that belong to an ensemble.  Errors:
+ * PIC_EINVAL (keep_every outside [1, 1000]).  Synchronizes. */
+pic_status pic_reweight(pic_handle *h, int32_t keep_every);
+
 /* Scalar state (step, circuit, id counters, counts, sort phase) for
  * checkpointing (Section 2's timestep carries no other state between steps
  * than these, the particles and the potential).  pic_set_state also rebuilds

@@ -116,6 +116,13 @@ class pic_scalar_state(C.Structure):
                 ("sort_phase", C.c_int32), ("pad_", C.c_int32)]
 
 
+class pic_plasma_out(C.Structure):
+    _fields_ = [("z_sheath", C.c_double), ("z_bulk", C.c_double),
+                ("te_region", C.c_double * 3), ("n_region", C.c_int64 * 3),
+                ("lambda_d_peak", C.c_double), ("n_e_peak", C.c_double), ("te_peak", C.c_double),
+                ("peak_cell", C.c_int32 * 2), ("band_cells", C.c_int32 * 2)]
+
+
 class pic_timers(C.Structure):
     _fields_ = [("push_ms", C.c_double), ("children_ms", C.c_double), ("sort_ms", C.c_double),
                 ("poisson_ms", C.c_double), ("circuit_ms", C.c_double), ("field_ms", C.c_double),
@@ -129,6 +136,7 @@ class pic_timers(C.Structure):
 EXPORTS = [
     "pic_query_workspace", "pic_init", "pic_step", "pic_poisson", "pic_diag",
     "pic_particles", "pic_fields", "pic_set_phi", "pic_compact", "pic_get_state",
+    "pic_plasma_diagnostics", "pic_ied_config", "pic_ied_read", "pic_reweight",
     "pic_set_state", "pic_enable_timers", "pic_get_timers", "pic_free", "pic_last_error",
     "pic_pc_param_count", "pic_pc_set_weights", "pic_pc_get_weights", "pic_pc_train_step",
     "pic_pc_apply", "pic_set_poisson_mode", "pic_apply_operator",
@@ -173,6 +181,11 @@ def load():
     L.pic_fields.argtypes = [H, C.POINTER(pic_field_view)]
     L.pic_set_phi.argtypes = [H, _dp]
     L.pic_compact.argtypes = [H]
+    L.pic_plasma_diagnostics.argtypes = [H, C.c_double, C.c_double, C.POINTER(pic_plasma_out),
+                                         _dp]
+    L.pic_ied_config.argtypes = [H, C.c_double, C.c_int32, C.c_double, C.c_double]
+    L.pic_ied_read.argtypes = [H, C.POINTER(C.c_uint64), C.c_int32, C.c_int32]
+    L.pic_reweight.argtypes = [H, C.c_int32]
     L.pic_get_state.argtypes = [H, C.POINTER(pic_scalar_state)]
     L.pic_set_state.argtypes = [H, C.POINTER(pic_scalar_state)]
     L.pic_enable_timers.argtypes = [H, C.c_int32]

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libpic.so")
 ARCH = os.environ.get("PIC_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["particles.hip", "sort.hip", "field.hip", "mg.hip", "cnn.hip", "fastsolve.hip",
-           "api.hip", "host_tables.cpp"]
+           "diagnostics.hip", "api.hip", "host_tables.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -88,6 +88,11 @@ struct pic_handle {
     // weight of an electron against an ion when splitting them
     int push_blocks = 1024;
     double push_e_weight = 1.0;
+    // plasma diagnostics buffers and the cathode ion-energy record
+    // (ied_nbins = 0: not recorded)
+    PlasmaDev pd = {};
+    int32_t ied_nbins = 0;
+    double ied_emax = 0.0, ied_r0 = 0.0, ied_r1 = 0.0;
     bool mg_one_level = false;      // V-cycle with one kernel per grid level
     // pinned host block the field solve reads its status and inner residuals
     // back into (a copy to pageable memory is staged and synchronous)
@@ -362,6 +367,17 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
     unsigned long long *live = cv.take<unsigned long long>(2 * 8);
     RunSolve *rsolve = cv.take<RunSolve>(sizeof(RunSolve));
     char *part_desc = cv.take<char>(4 * PART_DESC_BYTES);
+    // plasma diagnostics: moments of both species, cell maps, band profiles
+    PlasmaDev pd;
+    {
+        const int64_t ncell = (int64_t)c.nr * c.nz;
+        pd.mom[0] = cv.take<double>(5 * ncell * 8);
+        pd.mom[1] = cv.take<double>(5 * ncell * 8);
+        pd.maps = cv.take<double>(4 * ncell * 8);
+        pd.prof = cv.take<double>(3 * (int64_t)(c.nz + 1) * 8);
+        pd.out = cv.take<char>(sizeof(PlasmaOut));
+        pd.ied = cv.take<unsigned long long>((IED_MAX_BINS + 1) * 8);
+    }
     // direct solve: sine transform, right-hand side and its transform, tables
     FastSolve fs = {};
     const bool fs_on = c.poisson_mode == PIC_DIRECT;
@@ -387,6 +403,7 @@ int64_t layout(const pic_config &c, char *base, pic_handle *h)
         h->fs_on = fs_on;
         h->rsolve = rsolve;
         h->part_desc = part_desc;
+        h->pd = pd;
         h->pc_on = pc_on;
         if (pc_on) {
             h->net = net;
@@ -932,6 +949,7 @@ PushParams<T> push_params(pic_handle *h, int deposit_only)
                      c.wall_bc[2] == PIC_REFLECT) ? 1 : 0;
     P.deposit_only = deposit_only;
     P.fixed_q = c.deposit_fixed;
+    P.ied_on = h->ied_nbins > 0 ? 1 : 0;
     P.key0 = (uint32_t)(c.seed & 0xffffffffu);
     P.key1 = (uint32_t)(c.seed >> 32);
     P.run = c.run;
@@ -1057,6 +1075,15 @@ EventParams<T> event_params(const pic_handle *h)
     E.key0 = (uint32_t)(c.seed & 0xffffffffu);
     E.key1 = (uint32_t)(c.seed >> 32);
     E.run = c.run;
+    if (h->ied_nbins > 0) {
+        E.ied_hist = h->pd.ied;
+        E.ied_emax = h->ied_emax;
+        E.ied_r0 = h->ied_r0;
+        E.ied_r1 = h->ied_r1;
+        E.ied_nbins = h->ied_nbins;
+        E.ied_m = c.m[1];
+        E.dr = c.lr / c.nr;
+    }
     return E;
 }
 
@@ -1654,6 +1681,74 @@ int64_t static_scratch_bytes(const pic_handle *h)
     return up(sizeof(DevScalars)) + up(nodes * 8) + 2 * up(Mp * Np * 8);
 }
 
+template <typename T>
+pic_status plasma_typed(pic_handle *h, double r0, double r1, pic_plasma_out *out,
+                        double *maps_host)
+{
+    const pic_config &c = h->cfg;
+    const int64_t ncell = (int64_t)c.nr * c.nz;
+    hipStream_t s = h->stream;
+    launch_zero(h->pd.mom[0], 5 * ncell * 8, s);
+    launch_zero(h->pd.mom[1], 5 * ncell * 8, s);
+    for (int sp = 0; sp < 2; ++sp)
+        launch_cell_moments<T>(species_dev<T>(h->buf[sp][h->cur[sp]]), h->host_count[sp], c.nr,
+                               c.nz, h->pd.mom[sp], s);
+    PlasmaArgs A;
+    A.nr = c.nr;
+    A.nz = c.nz;
+    A.dr = c.lr / c.nr;
+    A.dz = c.lz / c.nz;
+    A.w[0] = c.w[0];
+    A.w[1] = c.w[1];
+    A.m_e = c.m[0];
+    // band cells: centre (i + 1/2) dr in [r0, r1)
+    A.ib0 = c.nr;
+    A.ib1 = c.nr;
+    for (int i = c.nr - 1; i >= 0; --i) {
+        const double rc = (i + 0.5) * A.dr;
+        if (rc >= r1) A.ib1 = i;
+        if (rc >= r0) A.ib0 = i;
+    }
+    if (A.ib1 < A.ib0) A.ib1 = A.ib0;
+    launch_plasma(h->pd, A, h->f.phi, s);
+    PlasmaOut o;
+    HIPCHECK(h, hipMemcpyAsync(&o, h->pd.out, sizeof(o), hipMemcpyDeviceToHost, s));
+    if (maps_host)
+        HIPCHECK(h, hipMemcpyAsync(maps_host, h->pd.maps, 4 * ncell * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(h, hipStreamSynchronize(s));
+    out->z_sheath = o.z_sheath;
+    out->z_bulk = o.z_bulk;
+    for (int r = 0; r < 3; ++r) {
+        out->te_region[r] = o.te_region[r];
+        out->n_region[r] = (int64_t)o.n_region[r];
+    }
+    out->lambda_d_peak = o.lambda_d_peak;
+    out->n_e_peak = o.n_e_peak;
+    out->te_peak = o.te_peak;
+    out->peak_cell[0] = o.peak_i;
+    out->peak_cell[1] = o.peak_j;
+    out->band_cells[0] = A.ib0;
+    out->band_cells[1] = A.ib1;
+    return PIC_OK;
+}
+
+template <typename T>
+pic_status reweight_typed(pic_handle *h, int32_t k)
+{
+    pic_config &c = h->cfg;
+    for (int s = 0; s < 2; ++s)
+        launch_reweight<T>(species_dev<T>(h->buf[s][h->cur[s]]), h->host_count[s], (uint32_t)k,
+                           h->stream);
+    sort_all<T>(h);
+    c.w[0] *= k;
+    c.w[1] *= k;
+    h->t_see[0] = host_see_threshold(c, 0);
+    h->t_see[1] = host_see_threshold(c, 1);
+    PushCold<T> C = push_cold<T>(h);
+    HIPCHECK(h, hipMemcpyAsync(h->cold, &C, sizeof(C), hipMemcpyHostToDevice, h->stream));
+    return check_flags(h);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1925,6 +2020,53 @@ pic_status pic_set_phi(pic_handle *h, const double *phi)
         launch_field_prep<float>(h->f, (float4 *)h->node, h->sc, h->cfg.scheme, 1, h->stream);
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     return PIC_OK;
+}
+
+pic_status pic_plasma_diagnostics(pic_handle *h, double r0, double r1, pic_plasma_out *out,
+                                  double *maps_host)
+{
+    if (!h || !out) return fail(h, PIC_EINVAL, "bad argument");
+    if (!(r0 < r1)) return fail(h, PIC_EINVAL, "radial band needs r0 < r1");
+    return h->prec == PIC_F64 ? plasma_typed<double>(h, r0, r1, out, maps_host)
+                              : plasma_typed<float>(h, r0, r1, out, maps_host);
+}
+
+pic_status pic_ied_config(pic_handle *h, double emax_ev, int32_t nbins, double r0, double r1)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (nbins < 0 || nbins > IED_MAX_BINS)
+        return fail(h, PIC_EINVAL, "nbins outside [0, %d]", IED_MAX_BINS);
+    if (nbins > 0 && (!(emax_ev > 0.0) || !(r0 < r1)))
+        return fail(h, PIC_EINVAL, "the energy record needs emax_ev > 0 and r0 < r1");
+    h->ied_nbins = nbins;
+    h->ied_emax = emax_ev;
+    h->ied_r0 = r0;
+    h->ied_r1 = r1;
+    launch_zero(h->pd.ied, (IED_MAX_BINS + 1) * 8, h->stream);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return PIC_OK;
+}
+
+pic_status pic_ied_read(pic_handle *h, uint64_t *counts, int32_t ncounts, int32_t reset)
+{
+    if (!h || !counts) return fail(h, PIC_EINVAL, "bad argument");
+    if (ncounts != h->ied_nbins + 1)
+        return fail(h, PIC_EINVAL, "ncounts must be nbins + 1 = %d", h->ied_nbins + 1);
+    HIPCHECK(h, hipMemcpyAsync(counts, h->pd.ied, (size_t)ncounts * 8, hipMemcpyDeviceToHost,
+                               h->stream));
+    if (reset) launch_zero(h->pd.ied, (IED_MAX_BINS + 1) * 8, h->stream);
+    HIPCHECK(h, hipStreamSynchronize(h->stream));
+    return PIC_OK;
+}
+
+pic_status pic_reweight(pic_handle *h, int32_t keep_every)
+{
+    if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
+    if (keep_every < 1 || keep_every > 1000)
+        return fail(h, PIC_EINVAL, "keep_every outside [1, 1000]");
+    if (keep_every == 1) return PIC_OK;
+    return h->prec == PIC_F64 ? reweight_typed<double>(h, keep_every)
+                              : reweight_typed<float>(h, keep_every);
 }
 
 pic_status pic_compact(pic_handle *h)

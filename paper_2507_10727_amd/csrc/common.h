@@ -215,6 +215,8 @@ struct PushParams {
     uint32_t key0, key1, run;
     int32_t nblk_e;             // blocks [0, nblk_e) push electrons, the rest ions
     int32_t fixed_q;            // 1: fixed-point node charge (FP64 state)
+    int32_t ied_on;             // 1: ions absorbed by the cathode are queued for the
+                                //    energy record even without emission
 };
 
 template <typename T>
@@ -226,6 +228,12 @@ struct EventParams {
     int32_t ev_cap;
     int32_t nr;
     uint32_t key0, key1, run;
+    // cathode ion-energy record (ied_hist == nullptr: off): ions absorbed with
+    // ied_r0 <= r < ied_r1 count in bin floor(E / ied_emax * ied_nbins),
+    // E = ied_m |v|^2 / 2 (eV), the last bin taking E >= ied_emax
+    unsigned long long *ied_hist;
+    double ied_emax, ied_r0, ied_r1, ied_m, dr;
+    int32_t ied_nbins;
 };
 
 template <typename T>
@@ -417,6 +425,35 @@ void launch_finalize_step(DevScalars *sc, const int64_t cap[2], const double qw6
                           hipStream_t s);
 // fixed-point node charge (64-bit integers in place) to FP64 charge
 void launch_q_from_fixed(void *q0, void *q1, int64_t nodes, const double qw64[2], hipStream_t s);
+
+// diagnostics.hip: plasma diagnostics of Sections 4, 5 and 7
+constexpr int IED_MAX_BINS = 4096;
+struct PlasmaDev {
+    double *mom[2];             // per species 5 x ncell: count, sum vr, vt, vz, |v|^2
+    double *maps;               // 4 x ncell: n_e, n_i, T_e, lambda_D
+    double *prof;               // 3 x (nz + 1): band n_e, n_i, phi
+    void *out;                  // PlasmaOut
+    unsigned long long *ied;    // IED_MAX_BINS + 1 counters
+};
+struct PlasmaOut {
+    double z_sheath, z_bulk;
+    double te_region[3];
+    double n_region[3];
+    double lambda_d_peak, n_e_peak, te_peak;
+    int32_t peak_i, peak_j;
+};
+struct PlasmaArgs {
+    int32_t nr, nz;
+    double dr, dz;
+    double w[2], m_e;
+    int32_t ib0, ib1;           // band cells [ib0, ib1)
+};
+template <typename T>
+void launch_cell_moments(const SpeciesDev<T> &S, int64_t n, int nr, int nz, double *mom,
+                         hipStream_t s);
+void launch_plasma(const PlasmaDev &D, const PlasmaArgs &A, const double *phi, hipStream_t s);
+template <typename T>
+void launch_reweight(const SpeciesDev<T> &S, int64_t n, uint32_t keep_every, hipStream_t s);
 void launch_begin_step(DevScalars *sc, void *q0, void *q1, int64_t nodes, int elem_bytes,
                        hipStream_t s);
 template <typename T>

@@ -794,7 +794,7 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
                         ++t.abs1;
                         // emission is decided in the event kernel; the
                         // entry's slot carries the species in bit 31
-                        if (emit)
+                        if (emit || (s == 1 && P.ied_on))
                             enqueue(P.see_q, &P.sc->n_see_q, P.ev_cap,
                                     (int)((uint32_t)(p0 + k) | ((uint32_t)s << 31)),
                                     see_aux<T>(i, fr[k]));
@@ -982,6 +982,21 @@ __device__ void events_body(const EventParams<T> P, int bid, int nb)
             const int s = (int)((uint32_t)q.x >> 31);
             q.x = (int)((uint32_t)q.x & 0x7fffffffu);
             const uint32_t pid = P.sp[s].id[q.x];
+            if (s == 1 && P.ied_hist) {
+                // energy record of the ion at the cathode (Section 7)
+                int ie;
+                T fe;
+                see_impact(P.sp[1], q, ie, fe);
+                const double r = ((double)ie + (double)fe) * P.dr;
+                if (r >= P.ied_r0 && r < P.ied_r1) {
+                    const double a = (double)P.sp[1].vr[q.x], b = (double)P.sp[1].vt[q.x];
+                    const double c = (double)P.sp[1].vz[q.x];
+                    const double e_ev = 0.5 * P.ied_m * (a * a + b * b + c * c) / 1.602176634e-19;
+                    const double x = floor(e_ev / P.ied_emax * P.ied_nbins);
+                    const int bin = (x >= (double)P.ied_nbins) ? P.ied_nbins : (int)x;
+                    atomicAdd(&P.ied_hist[bin], 1ull);
+                }
+            }
             const uint32_t word = (P.run << 8) | ((uint32_t)s << 4) | PURPOSE_SEE;
             const uint4 u = philox4x32_10(make_uint4(pid, word, step, 0u), P.key0, P.key1);
             if ((unsigned long long)u.x < C->t_see[s]) {

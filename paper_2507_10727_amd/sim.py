@@ -198,6 +198,39 @@ class Simulation:
         s.sort_phase = st.get("sort_phase", 0)
         L.check(self.lib.pic_set_state(self.h, C.byref(s)), self.h)
 
+    # -- plasma diagnostics ---------------------------------------------------
+    def plasma_diagnostics(self, r0, r1, maps=False):
+        """Region temperatures, sheath and bulk edges over the band of cells
+        with centres in [r0, r1), the Debye length at the density peak and,
+        with maps=True, the cell maps (n_e, n_i, T_e, lambda_D; each nz x nr)."""
+        o = L.pic_plasma_out()
+        buf = np.zeros(4 * self.prob.nr * self.prob.nz) if maps else None
+        ptr = buf.ctypes.data_as(C.POINTER(C.c_double)) if maps else None
+        L.check(self.lib.pic_plasma_diagnostics(self.h, float(r0), float(r1), C.byref(o), ptr),
+                self.h)
+        out = {"z_sheath": o.z_sheath, "z_bulk": o.z_bulk, "te_region": list(o.te_region),
+               "n_region": list(o.n_region), "lambda_d_peak": o.lambda_d_peak,
+               "n_e_peak": o.n_e_peak, "te_peak": o.te_peak,
+               "peak_cell": tuple(o.peak_cell), "band_cells": tuple(o.band_cells)}
+        if maps:
+            m = buf.reshape(4, self.prob.nz, self.prob.nr)
+            out["maps"] = {"n_e": m[0], "n_i": m[1], "te": m[2], "lambda_d": m[3]}
+        return out
+
+    def ied_config(self, emax_ev, nbins, r0, r1):
+        L.check(self.lib.pic_ied_config(self.h, float(emax_ev), int(nbins), float(r0),
+                                        float(r1)), self.h)
+        self._ied_bins = int(nbins)
+
+    def ied(self, reset=False):
+        a = np.zeros(self._ied_bins + 1, np.uint64)
+        L.check(self.lib.pic_ied_read(self.h, a.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                      a.shape[0], int(bool(reset))), self.h)
+        return a
+
+    def reweight(self, keep_every):
+        L.check(self.lib.pic_reweight(self.h, int(keep_every)), self.h)
+
     def checkpoint(self):
         """Host copy of everything a resumed run needs: the scalar state, the
         used slots of both species' arrays, phi0 and phi0_prev."""

@@ -104,6 +104,7 @@ class Problem:
     weight: Optional[float] = None  # macroparticle weight; default n*V/N
     cluster: float = 0.0        # fraction of each species loaded in the ring
     #                             0.35 R < r < 0.5 R, z < 0.1 L (deposit stress)
+    magnets: int = 0            # 0: one current loop; 1: the two-magnet layout
 
     def __post_init__(self):
         if self.cathode_rmax is None:
@@ -190,6 +191,13 @@ def preset(name: str) -> Problem:
     ec512x1024_f32   : 512x1024 cells over 5x10 cm, 5e7 + 5e7, n = 1e17,
                        20 mTorr, -500 V through 10/100 ohm (high-density case;
                        mc512x1024_f32 the same with the MC gather).
+    magnetron3x3_ec_f32 : the geometry of Section 3: 3 x 3 cm, 128 x 128
+                       cells, cathode over 0.85 L_r and a Neumann block
+                       beyond, the two-magnet field, -300 V through 3000 ohm,
+                       ion yield 0.1, electron yield 0.1, Ar* 2.5e17 m^-3,
+                       10 mTorr, EC-PIC (mc: MC-PIC), multigrid field solve,
+                       seeded with 2e5 + 2e5 at 1e15 m^-3 (capacity 20x for
+                       the discharge to grow).
     ec512x1024_clustered_f32 : the high-density case with half of each
                        species in the ring 0.35 R < r < 0.5 R, z < 0.1 L (the
                        magnetised ring above the cathode): about 3e3
@@ -214,7 +222,27 @@ def preset(name: str) -> Problem:
             n_per_species=50_000_000, steps=20000, seed=250710729,
             capacity_factor=1.1, poisson_mode=POISSON_DIRECT,
             cluster=0.5 if "clustered" in name else 0.0)
+    if name in ("magnetron3x3_ec_f32", "magnetron3x3_mc_f32"):
+        return Problem(
+            name=name, nr=128, nz=128, lr=0.03, lz=0.03, dt=4e-12,
+            scheme=EC_PIC if "_ec_" in name else MC_PIC, precision=F32,
+            cathode_rmax=0.85 * 0.03, circuit=RESISTOR, v_ext=-300.0, v_fixed=-300.0,
+            r_ext=3000.0, gamma_i=0.1, gamma_e=0.1, n_meta=2.5e17, p_gas=10e-3 * TORR,
+            density=1e15, te_ev=2.0, n_per_species=200_000, steps=1_000_000,
+            seed=250710740, capacity_factor=20.0, poisson_mode=POISSON_MGCG,
+            magnets=1)
     raise KeyError(name)
+
+
+def table1_problems(steps: int, base: str = "magnetron3x3_ec_f32") -> list:
+    """The yield / resistance combinations of Table 1 on the 3 x 3 cm
+    geometry: ion-induced yield 0.1 or 0.2, R = 3000 or 1000 ohm, electron
+    yield 0.1, -300 V source; run k draws random stream k."""
+    out = []
+    for k, (g, r) in enumerate(((0.1, 3000.0), (0.2, 3000.0), (0.1, 1000.0), (0.2, 1000.0))):
+        out.append(preset(base).replace(name=f"{base}_g{g}_r{int(r)}", gamma_i=g, r_ext=r,
+                                        run=k, steps=steps))
+    return out
 
 
 ENSEMBLE_GRIDS = (64, 96, 128, 160, 192, 224, 256)
@@ -294,6 +322,51 @@ def magnetron_field(p: Problem):
     s = p.b_peak / mag0 if mag0 > 0 else 0.0
     return (np.ascontiguousarray((br * s).ravel()),
             np.ascontiguousarray((bz * s).ravel()))
+
+
+def magnetized_cylinder_field(rho, z, a, z_bot, z_top, br_tesla, nquad=96):
+    """B of a cylinder of radius ``a`` uniformly magnetised along z (remanent
+    flux density ``br_tesla``, i.e. mu0 M) between z_bot and z_top.
+
+    The magnetisation is equivalent to an azimuthal surface current M per
+    unit length on the curved face (a finite solenoid), so the field is the
+    current-loop field integrated over the height (Gauss-Legendre, nquad
+    points).  Valid outside the magnet.  Returns (B_rho, B_z) in tesla.
+    """
+    x, wq = np.polynomial.legendre.leggauss(nquad)
+    zs = 0.5 * (z_top - z_bot) * x + 0.5 * (z_top + z_bot)
+    k_per_m = br_tesla / MU0            # M = surface current per unit length
+    br = np.zeros(np.broadcast(rho, z).shape)
+    bz = np.zeros_like(br)
+    for zq, wk in zip(zs, wq):
+        r_, z_ = loop_field(rho, z - zq, a, current=1.0)
+        f = 0.5 * (z_top - z_bot) * wk * k_per_m
+        br += f * r_
+        bz += f * z_
+    return br, bz
+
+
+def two_magnet_field(p: Problem, br_tesla=1.1, inner_radius=6.5e-3, outer_r0=0.017,
+                     outer_width=2e-3, top=-2e-3, height=10e-3):
+    """Nodal (B_r, B_z) of the unbalanced (type II) two-magnet layout of
+    Section 3: an inner cylinder of radius 6.5 mm and an outer ring at
+    L_1 = 1.7 cm, 2 mm wide, both magnetised at 1.1 T with opposite
+    polarity (outer to inner flux ratio (1.9^2 - 1.7^2) / 0.65^2 = 1.70).
+    Section 3 does not give the magnets' height or depth; they are taken
+    10 mm tall with their faces 2 mm behind the cathode plane.  The field is
+    that of the magnets in free space (equivalent surface currents), which is
+    what the paper's scalar-potential solve on an enlarged domain
+    approximates."""
+    r = np.arange(p.nr + 1) * p.dr
+    z = np.arange(p.nz + 1) * p.dz
+    R, Z = np.meshgrid(r, z)
+    zb, zt = top - height, top
+    b_in = magnetized_cylinder_field(R, Z, inner_radius, zb, zt, br_tesla)
+    b_o2 = magnetized_cylinder_field(R, Z, outer_r0 + outer_width, zb, zt, -br_tesla)
+    b_o1 = magnetized_cylinder_field(R, Z, outer_r0, zb, zt, br_tesla)
+    br = b_in[0] + b_o2[0] + b_o1[0]
+    bz = b_in[1] + b_o2[1] + b_o1[1]
+    return np.ascontiguousarray(br.ravel()), np.ascontiguousarray(bz.ravel())
 
 
 # ---------------------------------------------------------------------------
@@ -405,7 +478,7 @@ def thermal_box(nr: int, nz: int, cell: float, ppc: int, scheme: int, precision:
 
 def inputs(p: Problem, n: Optional[int] = None):
     """Everything a run needs: (B_r, B_z, sigma table, [electrons, ions])."""
-    br, bz = magnetron_field(p)
+    br, bz = two_magnet_field(p) if p.magnets == 1 else magnetron_field(p)
     sig = cross_sections(p.e_exc, p.e_iz, e_iz_meta=p.e_iz_meta)
     parts = load_uniform(p, n)
     return br, bz, sig, parts

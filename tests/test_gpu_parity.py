@@ -564,3 +564,32 @@ def test_f32_full_size_deposit_matches_oracle(name):
         assert err <= 2e-6
         assert got.sum() == approx(qw * g["id"].shape[0], rel=1e-6)
     sim.close()
+
+
+def test_magnetron_geometry_matches_oracle():
+    """The 3 x 3 cm geometry of Section 3 (cathode over 0.85 L_r with the
+    Neumann block beyond it, the two-magnet field, -300 V through 3000 ohm,
+    both emission yields, the metastable channel), FP64 with the multigrid
+    solve, 30 steps against the oracle: particles by id and the cathode
+    voltage to the solve tolerance, every decision identical."""
+    p = W.scaled(W.preset("magnetron3x3_ec_f32"), 20000).replace(
+        precision=W.F64, poisson_rtol=1e-12, capacity_factor=2.0)
+    br, bz, sig, parts = W.inputs(p)
+    say("case magnetron geometry", p.name)
+    sim = gpu_sim(p, br, bz, sig, [x.copy() for x in parts])
+    o = O.Oracle(p, br, bz, sig, [x.copy() for x in parts], rtol=1e-13)
+    o.init()
+    for k in range(1, 31):
+        sim.step(1)
+        d = o.step()
+        g = sim.diag()
+        for key in ("n_coll", "n_see", "n_see_e", "n_abs"):
+            assert np.array_equal(np.array(g[key]), np.array(d[key])), (k, key)
+    for s in range(2):
+        ep, ev, only = compare_particles(p, sim.particles(s), o.particles(s), s, 1e-10)
+        say("  species", s, "pos", ep, "vel", ev)
+        assert ep < 1e-10 and ev < 1e-10 and only == 0
+    st = sim.get_state()
+    say("  vc", st["vc"], o.state.vc)
+    assert abs(st["vc"] - o.state.vc) <= 1e-10 * abs(o.state.vc)
+    sim.close()
