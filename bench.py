@@ -118,8 +118,10 @@ def poisson_bench(train_seconds=60.0, reps=6):
     at that grid, cold (phi = 0) and warm (previous snapshot's solution).
 
     The network is trained first, on the GPU, on pairs the simulation makes:
-    (Q, phi0) snapshots of the same discharge and random potentials with
-    Q = K phi (see pc_train)."""
+    1024 (Q, phi0) snapshots of the same discharge and their negatives, and
+    192 random potentials with Q = K phi (see pc_train): 2240 pairs.  The
+    learned preconditioner's first approximation is the multigrid V-cycle
+    (pc_pre = 1), which the network corrects."""
     import numpy as np
     import torch
     from paper_2507_10727_amd import pc_train
@@ -131,10 +133,10 @@ def poisson_bench(train_seconds=60.0, reps=6):
     sim = Simulation(p, br, bz, sig, parts)
     sim.step(50)
     log("[bench] poisson: collecting snapshot pairs")
-    Qs, Ps = pc_train.snapshot_pairs(sim, 72, every=2)
-    held_q = Qs[64:].clone()
-    Qs, Ps = Qs[:64], Ps[:64]
-    Qf, Pf = pc_train.field_pairs(sim, 96, seed=250710731)
+    Qs, Ps = pc_train.snapshot_pairs(sim, 1032, every=2)
+    held_q = Qs[1024:].clone()
+    Qs, Ps = Qs[:1024], Ps[:1024]
+    Qf, Pf = pc_train.field_pairs(sim, 192, seed=250710731)
     Q = torch.cat([Qs, -Qs, Qf])
     P = torch.cat([Ps, -Ps, Pf])
     del Qs, Ps, Qf, Pf
@@ -146,6 +148,7 @@ def poisson_bench(train_seconds=60.0, reps=6):
     del Q, P
     torch.cuda.empty_cache()
     out = {"grid": "512x1024", "rtol": 1e-8, "rhs": "held-out charge snapshots",
+           "pairs": 2240, "first_step": "multigrid V-cycle",
            "training": tr}
     for name, mode in (("mg_cg", W.POISSON_MGCG), ("learned_fcg", W.POISSON_LEARNED)):
         sim.set_poisson_mode(mode)

@@ -121,7 +121,10 @@ typedef struct pic_config {
                                    additions: runs are bit-reproducible.  At
                                    most 2^21 particles may share a node.
                                    Single runs only (not ensembles).          */
-    int32_t pad_;
+    int32_t pc_pre;             /* learned preconditioner's first approximation
+                                   x1 of A x = r: 0 a red-black Gauss-Seidel
+                                   pair from zero, 1 one multigrid V-cycle
+                                   (the multigrid preconditioner's)           */
 } pic_config;
 
 /* Initial particles of one species (host, FP64, absolute positions).
@@ -375,10 +378,13 @@ pic_status pic_get_timers(pic_handle *h, pic_timers *out, int32_t reset);
 /* ---- learned preconditioner of the field solve -----------------------------
  * The field solve of every step (Section 3's Gauss's law over the R-Z control
  * volumes, K phi = Q) runs conjugate gradients; PIC_LEARNED preconditions
- * them with a 4-level convolutional network z = out_scale rms(r) f(r / rms(r),
- * i / 256) (15 3x3 convolutions with ReLU, average pooling, nearest
- * upsampling and additive skips; channels 16, 16, 48, 80), BF16 MFMA with
- * FP32 accumulation.  Because f is nonlinear the iteration is flexible CG
+ * them with a 4-level convolutional network f (15 3x3 convolutions with
+ * ReLU, average pooling, nearest upsampling and additive skips; channels 16,
+ * 16, 48, 80; inputs r1 / rms(r1) and i / 256), BF16 MFMA with FP32
+ * accumulation, inside z = post(x1 + out_scale rms(r1) f(...), r): x1 a first
+ * approximation of A x = r (pc_pre: one multigrid V-cycle, or a red-black
+ * Gauss-Seidel pair from zero), r1 = r - A x1, post a black and a red
+ * Gauss-Seidel sweep.  Because f is nonlinear the iteration is flexible CG
  * (Polak-Ribiere beta); when it reaches pc_maxit iterations without meeting
  * poisson_rtol, or stops reducing the residual, the solve continues from its
  * current iterate with multigrid-preconditioned CG (stats.fell_back = 1).
@@ -407,9 +413,9 @@ pic_status pic_pc_get_weights(pic_handle *h, float *theta, int64_t n, double *ou
 pic_status pic_pc_train_step(pic_handle *h, const double *q_dev, const double *phi_dev,
                              int32_t batch, float lr, double *loss, float *grad);
 
-/* z = out_scale rms(r) f(r / rms(r)) on unknown nodes (0 on Dirichlet
- * nodes); r_dev, z_dev FP64 node vectors in units of A = K / (2 pi eps0).
- * Synchronizes. */
+/* z = the preconditioner applied to r (see above; 0 on Dirichlet nodes);
+ * r_dev, z_dev FP64 node vectors in units of A = K / (2 pi eps0).  Uses the
+ * multigrid level-0 buffers when pc_pre = 1.  Synchronizes. */
 pic_status pic_pc_apply(pic_handle *h, const double *r_dev, double *z_dev);
 
 /* Switch the preconditioner of later solves (PIC_LEARNED needs weights). */

@@ -50,7 +50,7 @@ class pic_config(C.Structure):
         ("extra_current", C.c_double),
         ("pc_batch", C.c_int32), ("pc_maxit", C.c_int32),
         ("gamma_e", C.c_double), ("n_meta", C.c_double), ("e_iz_meta", C.c_double),
-        ("deposit_fixed", C.c_int32), ("pad_", C.c_int32),
+        ("deposit_fixed", C.c_int32), ("pc_pre", C.c_int32),
     ]
 
 

@@ -230,6 +230,8 @@ pic_status validate(const pic_config *c, pic_handle *h)
         return fail(h, PIC_EINVAL, "deposit_fixed must be 0 or 1");
     if (c->deposit_fixed && c->precision != PIC_F64)
         return fail(h, PIC_EINVAL, "the fixed-point deposit needs FP64 state");
+    if (c->pc_pre != 0 && c->pc_pre != 1)
+        return fail(h, PIC_EINVAL, "pc_pre must be 0 or 1");
     for (int k = 0; k < 3; ++k)
         if (c->wall_bc[k] != PIC_ABSORB && c->wall_bc[k] != PIC_REFLECT)
             return fail(h, PIC_EINVAL, "bad wall_bc[%d]", k);
@@ -649,14 +651,25 @@ pic_status readback(pic_handle *h, SolveReadback *rb, double *hist = nullptr, in
 
 // Preconditioner of CG iteration k: z = M r on the finest level, r.z into
 // pcg_rz[k] (and z_k.q_{k-1} into pcg_zq[k] for the learned one).
+// The learned preconditioner's first approximation: a multigrid V-cycle
+// (pc_pre = 1) or a red-black Gauss-Seidel pair.
+PcPre pc_pre_of(const pic_handle *h)
+{
+    PcPre p;
+    p.H = h->cfg.pc_pre ? &h->f.mg : nullptr;
+    p.two_level = !h->mg_one_level;
+    return p;
+}
+
 void enqueue_precond(pic_handle *h, int mode, int k)
 {
     hipStream_t s = h->stream;
     FieldDev &f = h->f;
     const MGHier &H = f.mg;
     if (mode == PIC_LEARNED)
-        pc_apply32(h->net, H.lv[0], h->n_unknown, H.lv[0].b, H.lv[0].xu, k > 0 ? f.q32 : nullptr,
-                   &h->sc->pcg_rz[k], &h->sc->pcg_zq[k], &h->sc->pcg_ss[k], s);
+        pc_apply32(h->net, pc_pre_of(h), H.lv[0], h->n_unknown, H.lv[0].b, H.lv[0].xu,
+                   k > 0 ? f.q32 : nullptr, &h->sc->pcg_rz[k], &h->sc->pcg_zq[k],
+                   &h->sc->pcg_ss[k], s);
     else if (mode == PIC_CG)
         pc_identity32(H.lv[0], H.lv[0].b, H.lv[0].xu, &h->sc->pcg_rz[k], s);
     else
@@ -2208,7 +2221,7 @@ pic_status pic_pc_train_step(pic_handle *h, const double *q_dev, const double *p
         return fail(h, PIC_EINVAL, "batch %d outside [1, %d]", batch, h->net.batch);
     if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(h, PIC_EINVAL, "lr must be >= 0");
     const double inv_2pi_eps0 = 1.0 / (2.0 * 3.14159265358979323846 * eps0());
-    pc_train_enqueue(h->net, h->f.mg.lv[0], h->n_unknown, q_dev, phi_dev, batch, lr, inv_2pi_eps0,
+    pc_train_enqueue(h->net, pc_pre_of(h), h->f.mg.lv[0], h->n_unknown, q_dev, phi_dev, batch, lr, inv_2pi_eps0,
                      h->stream);
     double l = 0.0;
     HIPCHECK(h, hipMemcpyAsync(&l, pc_loss_ptr(h->net, batch), 8, hipMemcpyDeviceToHost,
@@ -2229,7 +2242,7 @@ pic_status pic_pc_apply(pic_handle *h, const double *r_dev, double *z_dev)
     if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
     if (!h->pc_on || !h->net.has_weights) return fail(h, PIC_ESTATE, "no weights loaded");
     if (!r_dev || !z_dev) return fail(h, PIC_EINVAL, "r_dev and z_dev are required");
-    pc_apply64(h->net, h->f.mg.lv[0], h->n_unknown, r_dev, z_dev, &h->sc->pcg_ss[MAX_PCG + 1],
+    pc_apply64(h->net, pc_pre_of(h), h->f.mg.lv[0], h->n_unknown, r_dev, z_dev, &h->sc->pcg_ss[MAX_PCG + 1],
                h->stream);
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     HIPCHECK(h, hipGetLastError());

@@ -81,16 +81,24 @@ void pc_download_flat(const PcNet &n, const float *dev_master_like, float *flat_
                       std::vector<float> &tmp);
 void pc_pack(const PcNet &n, hipStream_t s);
 
+// Where the preconditioner's first approximation x1 of A x = r comes from:
+// a red-black Gauss-Seidel pair from zero (red, black), or one multigrid
+// V-cycle of the hierarchy H (the multigrid preconditioner of the solver;
+// it reads H.lv[0].b and writes H.lv[0].xu).
+struct PcPre {
+    const MGHier *H;            // nullptr: the Gauss-Seidel pair
+    bool two_level;
+};
+
 // Preconditioner application inside the FP32 CG on level L (the finest
-// multigrid level): x1 = red-black Gauss-Seidel from zero (red, black) on
-// A x = r, r1 = r - A x1, z = x1 + out_scale rho1 f(r1 / rho1) with rho1 the
-// rms of r1 over the unknowns, then a black and a red sweep on A z = r.
-// Accumulates r.z into *rz and, when q is given, z.q into *zq; *ss must be
-// zero on entry (rms accumulator).  Enqueue only.
-void pc_apply32(PcNet &n, const MGLevel &L, int64_t n_unknown, const float *r, float *z,
-                const float *q, double *rz, double *zq, double *ss, hipStream_t s);
-void pc_apply64(PcNet &n, const MGLevel &L, int64_t n_unknown, const double *r, double *z,
-                double *ss, hipStream_t s);
+// multigrid level): x1 from `pre`, r1 = r - A x1, z = x1 + out_scale rho1
+// f(r1 / rho1) with rho1 the rms of r1 over the unknowns, then a black and a
+// red sweep on A z = r.  Accumulates r.z into *rz and, when q is given, z.q
+// into *zq; *ss must be zero on entry (rms accumulator).  Enqueue only.
+void pc_apply32(PcNet &n, const PcPre &pre, const MGLevel &L, int64_t n_unknown, const float *r,
+                float *z, const float *q, double *rz, double *zq, double *ss, hipStream_t s);
+void pc_apply64(PcNet &n, const PcPre &pre, const MGLevel &L, int64_t n_unknown, const double *r,
+                double *z, double *ss, hipStream_t s);
 // identity "preconditioner" of plain CG: z = r, *rz += r.r
 void pc_identity32(const MGLevel &L, const float *r, float *z, double *rz, hipStream_t s);
 
@@ -99,8 +107,9 @@ void pc_identity32(const MGLevel &L, const float *r, float *z, double *rz, hipSt
 // rms, x1 = pre-smoothing of b, network input r1 = b - A x1 (unit rms), target
 // (phi / rms(b) - x1) / rms(r1); forward, loss, backward, Adam.  Leaves the
 // gradient in n.grad and the batch loss at pc_loss_ptr.
-void pc_train_enqueue(PcNet &n, const MGLevel &L, int64_t n_unknown, const double *q,
-                      const double *phi, int B, float lr, double inv_2pi_eps0, hipStream_t s);
+void pc_train_enqueue(PcNet &n, const PcPre &pre, const MGLevel &L, int64_t n_unknown,
+                      const double *q, const double *phi, int B, float lr, double inv_2pi_eps0,
+                      hipStream_t s);
 const double *pc_loss_ptr(const PcNet &n, int B);
 
 }  // namespace pic

@@ -1163,15 +1163,46 @@ void pc_download_flat(const PcNet &n, const float *dev, float *flat, std::vector
 // ---- application ------------------------------------------------------------------
 namespace {
 // z = post(x1 + correction(r - A x1), r), x1 = pre(r), all FP32 on level L
-void sandwich(PcNet &n, const MGLevel &L, double inv_nunk, const float *r, float *z,
-              const float *q, double *rz, double *zq, double *ss, hipStream_t s)
+__global__ void k_copy32(const float *a, float *b, int64_t n)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        b[k] = a[k];
+}
+
+void copy32(const float *a, float *b, int64_t n, hipStream_t s)
+{
+    if (a == b) return;
+    hipLaunchKernelGGL(k_copy32, dim3(eblocks(n)), dim3(EB), 0, s, a, b, n);
+}
+
+// x1 of one right-hand side r (float, level 0) into x: the Gauss-Seidel pair
+// from zero, or a multigrid V-cycle through the hierarchy's level-0 buffers
+void pre_step(const PcPre &pre, const MGLevel &L, const float *r, float *x, int64_t nn,
+              hipStream_t s)
+{
+    const dim3 g(rblocks(nn), 1);
+    const float *nf = nullptr;
+    double *nd = nullptr;
+    if (pre.H) {
+        const MGLevel &F = pre.H->lv[0];
+        copy32(r, F.b, nn, s);
+        launch_mg_vcycle(*pre.H, nullptr, s, pre.two_level);
+        copy32(F.xu, x, nn, s);
+    } else {
+        hipLaunchKernelGGL(k_rb_sweep, g, dim3(RB), 0, s, L, r, x, nn, 0, 1, nf, nf, nd, nd);
+        hipLaunchKernelGGL(k_rb_sweep, g, dim3(RB), 0, s, L, r, x, nn, 1, 0, nf, nf, nd, nd);
+    }
+}
+
+void sandwich(PcNet &n, const PcPre &pre, const MGLevel &L, double inv_nunk, const float *r,
+              float *z, const float *q, double *rz, double *zq, double *ss, hipStream_t s)
 {
     const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
     const dim3 g(rblocks(nn), 1);
     const float *nf = nullptr;
     double *nd = nullptr;
-    hipLaunchKernelGGL(k_rb_sweep, g, dim3(RB), 0, s, L, r, n.vx, nn, 0, 1, nf, nf, nd, nd);
-    hipLaunchKernelGGL(k_rb_sweep, g, dim3(RB), 0, s, L, r, n.vx, nn, 1, 0, nf, nf, nd, nd);
+    pre_step(pre, L, r, n.vx, nn, s);
     hipLaunchKernelGGL(k_residual32, g, dim3(RB), 0, s, L, r, (const float *)n.vx, n.vr, nn, ss);
     hipLaunchKernelGGL(k_pc_input<float>, dim3(eblocks(nn)), dim3(EB), 0, s, (const float *)n.vr,
                        nn, 1.0, (const double *)ss, inv_nunk, L, n.x, 1);
@@ -1183,22 +1214,22 @@ void sandwich(PcNet &n, const MGLevel &L, double inv_nunk, const float *r, float
 }
 }  // namespace
 
-void pc_apply32(PcNet &n, const MGLevel &L, int64_t n_unknown, const float *r, float *z,
-                const float *q, double *rz, double *zq, double *ss, hipStream_t s)
+void pc_apply32(PcNet &n, const PcPre &pre, const MGLevel &L, int64_t n_unknown, const float *r,
+                float *z, const float *q, double *rz, double *zq, double *ss, hipStream_t s)
 {
     const double inv = n_unknown > 0 ? 1.0 / (double)n_unknown : 0.0;
-    sandwich(n, L, inv, r, z, q, rz, zq, ss, s);
+    sandwich(n, pre, L, inv, r, z, q, rz, zq, ss, s);
 }
 
-void pc_apply64(PcNet &n, const MGLevel &L, int64_t n_unknown, const double *r, double *z,
-                double *ss, hipStream_t s)
+void pc_apply64(PcNet &n, const PcPre &pre, const MGLevel &L, int64_t n_unknown, const double *r,
+                double *z, double *ss, hipStream_t s)
 {
     const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
     const double inv = n_unknown > 0 ? 1.0 / (double)n_unknown : 0.0;
     launch_zero(ss, 8, s);
     hipLaunchKernelGGL(k_pc_scale_in<double>, dim3(eblocks(nn)), dim3(EB), 0, s, r, nn, 1.0,
                        (const double *)nullptr, inv, L, n.vb, 1);
-    sandwich(n, L, inv, n.vb, n.vz, nullptr, nullptr, nullptr, ss, s);
+    sandwich(n, pre, L, inv, n.vb, n.vz, nullptr, nullptr, nullptr, ss, s);
     hipLaunchKernelGGL(k_cast_out, dim3(eblocks(nn)), dim3(EB), 0, s, (const float *)n.vz, z, nn);
 }
 
@@ -1210,8 +1241,9 @@ void pc_identity32(const MGLevel &L, const float *r, float *z, double *rz, hipSt
 
 // ---- training -------------------------------------------------------------------------
 // scal: [0, B) sum b^2, [B, 2B) sum r1^2, [2B, 3B) den, [3B] loss
-void pc_train_enqueue(PcNet &n, const MGLevel &L, int64_t n_unknown, const double *q,
-                      const double *phi, int B, float lr, double inv_2pi_eps0, hipStream_t s)
+void pc_train_enqueue(PcNet &n, const PcPre &pre, const MGLevel &L, int64_t n_unknown,
+                      const double *q, const double *phi, int B, float lr, double inv_2pi_eps0,
+                      hipStream_t s)
 {
     const int64_t nn = (int64_t)(L.nr + 1) * (L.nz + 1);
     const double inv = n_unknown > 0 ? 1.0 / (double)n_unknown : 0.0;
@@ -1224,10 +1256,15 @@ void pc_train_enqueue(PcNet &n, const MGLevel &L, int64_t n_unknown, const doubl
     hipLaunchKernelGGL(k_pc_sumsq<double>, gbe, dim3(EB), 0, s, q, nn, inv_2pi_eps0, L, ss0);
     hipLaunchKernelGGL(k_pc_scale_in<double>, dim3(eblocks((int64_t)B * nn)), dim3(EB), 0, s, q, nn,
                        inv_2pi_eps0, (const double *)ss0, inv, L, n.vb, B);
-    hipLaunchKernelGGL(k_rb_sweep, gb, dim3(RB), 0, s, L, (const float *)n.vb, n.vx, nn, 0, 1, nf,
-                       nf, nd, nd);
-    hipLaunchKernelGGL(k_rb_sweep, gb, dim3(RB), 0, s, L, (const float *)n.vb, n.vx, nn, 1, 0, nf,
-                       nf, nd, nd);
+    if (pre.H) {
+        for (int b = 0; b < B; ++b)
+            pre_step(pre, L, (const float *)n.vb + (int64_t)b * nn, n.vx + (int64_t)b * nn, nn, s);
+    } else {
+        hipLaunchKernelGGL(k_rb_sweep, gb, dim3(RB), 0, s, L, (const float *)n.vb, n.vx, nn, 0,
+                           1, nf, nf, nd, nd);
+        hipLaunchKernelGGL(k_rb_sweep, gb, dim3(RB), 0, s, L, (const float *)n.vb, n.vx, nn, 1,
+                           0, nf, nf, nd, nd);
+    }
     hipLaunchKernelGGL(k_residual32, gb, dim3(RB), 0, s, L, (const float *)n.vb,
                        (const float *)n.vx, n.vr, nn, ss1);
     hipLaunchKernelGGL(k_pc_input<float>, dim3(eblocks((int64_t)B * nn)), dim3(EB), 0, s,

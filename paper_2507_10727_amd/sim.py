@@ -34,6 +34,7 @@ def make_config(prob: W.Problem, b_r, b_z, sigma, de_table=W.DE_TABLE, capacity=
     c.n_meta = prob.n_meta
     c.e_iz_meta = prob.e_iz_meta
     c.deposit_fixed = prob.deposit_fixed
+    c.pc_pre = prob.pc_pre
     c.p_gas, c.t_gas = prob.p_gas, prob.t_gas
     c.e_exc, c.e_iz = prob.e_exc, prob.e_iz
     c.sigma = sig.ctypes.data_as(C.POINTER(C.c_double))

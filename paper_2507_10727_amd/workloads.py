@@ -101,6 +101,7 @@ class Problem:
     poisson_mode: int = 0       # 0 multigrid, 1 learned network, 2 none (plain CG), 3 direct
     pc_batch: int = 0           # training batch of the learned preconditioner
     pc_maxit: int = 0           # learned iterations before the multigrid fallback
+    pc_pre: int = 1             # learned preconditioner's first step: 1 V-cycle, 0 GS pair
     weight: Optional[float] = None  # macroparticle weight; default n*V/N
     cluster: float = 0.0        # fraction of each species loaded in the ring
     #                             0.35 R < r < 0.5 R, z < 0.1 L (deposit stress)

@@ -50,8 +50,9 @@ def bf16(a):
 
 
 def problem(nr=100, nz=60, **kw):
+    # the Gauss-Seidel first step (pc_pre = 0) is the form the oracle computes
     base = dict(name="pc", nr=nr, nz=nz, lr=nr * 1e-4, lz=nz * 1e-4, n_per_species=0,
-                poisson_rtol=1e-8, poisson_maxit=512, pc_batch=4)
+                poisson_rtol=1e-8, poisson_maxit=512, pc_batch=4, pc_pre=0)
     base.update(kw)
     return W.Problem(**base)
 
@@ -308,6 +309,45 @@ def test_learned_fpcg_solve_and_gain():
     # what the trained network gains over the method without it
     assert st_sgs[0] == 0 and st["iterations"] < 0.6 * st_sgs[2]["iterations"]
     assert st_sgs[2]["iterations"] < st_cg[2]["iterations"]
+    sim.close()
+
+
+def test_vcycle_form_iterations_against_multigrid():
+    """pc_pre = 1: the preconditioner's first approximation is the multigrid
+    V-cycle (the one multigrid-PCG uses), the network corrects what it
+    leaves.  With a zero network the flexible CG is multigrid-PCG with two
+    extra Gauss-Seidel sweeps; after training it reaches the FP64-checked
+    1e-8 residual and the multigrid solution in at most the multigrid
+    iterations (and never more than twice them, the target)."""
+    p = problem(pc_pre=1)
+    say("case pc v-cycle form", p.nr, p.nz)
+    import torch
+    sim, o, kind, apply_a = setup(p)
+    rng = np.random.default_rng(43)
+    q = charges(p, kind, rng, 1)[0]
+    qd = dev(q)
+
+    def solve(mode):
+        sim.set_poisson_mode(mode)
+        for rep in range(2):
+            phi = torch.zeros(p.nodes, dtype=torch.float64, device="cuda")
+            status, st = sim.poisson_status(qd, -300.0, phi)
+            say("mode", mode, status, st)
+        return status, phi.cpu().numpy(), st
+
+    st_mg = solve(W.POISSON_MGCG)
+    assert st_mg[0] == 0
+    sim.pc_set_weights(np.zeros(N.param_count(), np.float32), 1.0)
+    st_zero = solve(W.POISSON_LEARNED)
+    assert st_zero[0] == 0 and st_zero[2]["fell_back"] == 0
+    assert st_zero[2]["iterations"] <= st_mg[2]["iterations"] + 1
+    losses = train(sim, p, o, kind, rng, steps=600)
+    say("trained loss", np.mean(losses[:5]), np.mean(losses[-10:]))
+    assert np.mean(losses[-10:]) < np.mean(losses[:5])
+    status, g, st = solve(W.POISSON_LEARNED)
+    assert status == 0 and st["converged"] and st["rel_res"] <= 1e-8 and st["fell_back"] == 0
+    assert st["iterations"] <= 2 * st_mg[2]["iterations"]
+    assert np.abs(g - st_mg[1]).max() <= 1e-6 * np.abs(st_mg[1]).max()
     sim.close()
 
 
