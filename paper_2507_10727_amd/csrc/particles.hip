@@ -646,6 +646,17 @@ __device__ __forceinline__ void stream_store(int4 *p, const int4 &v) { stream_st
 __device__ __forceinline__ void stream_store(float4 *p, const float4 &v) { stream_store_v<float4, float>(p, v); }
 __device__ __forceinline__ void stream_store(double4 *p, const double4 &v) { stream_store_v<double4, double>(p, v); }
 
+// Marks the four words of a loaded vector as used here.  Every word of a
+// chunk's loads is then waited for at one point on every path through the
+// loop body; a word left unread on some path (a masked-off particle, a frozen
+// species) would otherwise make the compiler wait for all memory operations
+// at the loop's back edge, the stores just issued included.
+template <typename V>
+__device__ __forceinline__ void consume(const V &v)
+{
+    asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+}
+
 // The particle kernel's work for block bid of the nb blocks given to one
 // run, of which the first nblk_e push electrons and the rest ions.
 template <typename T, int SCHEME>
@@ -709,6 +720,32 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
             deposit_chunk<T, false, WAVE_NODES>(pok, pfr, pfz, tile, Q, ldn, qw, lane, t.fb, win);
         }
     };
+    // Null-collision candidates of a chunk take one range of the event queue
+    // for the whole wavefront, reserved by one atomic (the ballots of the four
+    // particle positions rank the entries); the entries are written in the
+    // next iteration, once that chunk's loads are issued, so the end of an
+    // iteration holds only the particle stores.
+    unsigned int pend = 0;          // bit k: particle k of the lane's held chunk
+    int pend_base = 0, pleader = -1;
+    uint64_t pm[4] = {0ull, 0ull, 0ull, 0ull};
+    int64_t pp0 = 0;
+    auto flush_mcc = [&]() {
+        if (pleader < 0) return;
+        const int base = __builtin_amdgcn_readlane(pend_base, pleader);
+        int off = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (pend & (1u << k)) {
+                const int e = base + off +
+                              (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(pm[k] >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)pm[k], 0u));
+                if (e < P.ev_cap) P.mcc_q[e] = make_int2((int)(pp0 + k), 0);
+            }
+            off += __popcll(pm[k]);
+        }
+        pleader = -1;
+        pend = 0;
+    };
     for (int64_t c = wv * nch / nwv; c < c_end; ++c) {
         const int64_t p0 = c * WCHUNK + 4 * lane;
         int kk[4];
@@ -730,6 +767,12 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
             uint4 iv = make_uint4(0u, 0u, 0u, 0u);
             if (collide_on) iv = stream_load((const uint4 *)(ID + pl));
             deposit_prev();
+            consume(wr);
+            consume(wz);
+            consume(c4);
+            consume(d);
+            consume(e);
+            consume(iv);
             const uint32_t r4[4] = {wr.x, wr.y, wr.z, wr.w};
             const int32_t z4[4] = {wz.x, wz.y, wz.z, wz.w};
 #pragma unroll
@@ -753,6 +796,13 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
             const T4 e = stream_load((const T4 *)(VZ + pl));
             uint4 iv = make_uint4(0u, 0u, 0u, 0u);
             if (collide_on) iv = stream_load((const uint4 *)(ID + pl));
+            consume(k4);
+            consume(a);
+            consume(b);
+            consume(c4);
+            consume(d);
+            consume(e);
+            consume(iv);
             kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
             fr[0] = a.x; fr[1] = a.y; fr[2] = a.z; fr[3] = a.w;
             fz[0] = b.x; fz[1] = b.y; fz[2] = b.z; fz[3] = b.w;
@@ -764,6 +814,8 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (p0 + k >= n) kk[k] = -1;
+        flush_mcc();
+        unsigned int cmask = 0;
         int ok[4];   // cell key after the push, -1 if none
         T ke_c = (T)0, pz_c = (T)0;
         if (!frozen) {
@@ -812,12 +864,31 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
                     // done in the event kernel for the few candidates
                     const uint4 u = philox4x32_10(make_uint4(id[k], word1 | PURPOSE_MCC, step, 0u),
                                                   P.key0, P.key1);
-                    if ((unsigned long long)u.x < P.t_null)
-                        enqueue(P.mcc_q, &P.sc->n_mcc_q, P.ev_cap, (int)(p0 + k), 0);
+                    if ((unsigned long long)u.x < P.t_null) cmask |= 1u << k;
                 }
                 fr[k] = pos_round(fr[k]);   // the stored (FP32: rounded) offsets
                 fz[k] = pos_round(fz[k]);
                 kk[k] = ok[k] = (j << 16) | i;
+            }
+            if (collide_on) {
+                uint64_t m[4];
+                int tot = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    m[k] = __ballot((cmask >> k) & 1u);
+                    tot += __popcll(m[k]);
+                }
+                if (tot) {
+                    const int leader = __ffsll((long long)(m[0] | m[1] | m[2] | m[3])) - 1;
+                    int b = 0;
+                    if (lane == leader) b = atomicAdd(&P.sc->n_mcc_q, tot);
+                    pend_base = b;
+                    pleader = leader;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) pm[k] = m[k];
+                    pend = cmask;
+                    pp0 = p0;
+                }
             }
             if (any) {
                 if constexpr (sizeof(T) == 4) {
@@ -871,6 +942,7 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
         }
         if constexpr (sizeof(T) == 8) deposit_prev();
     }
+    flush_mcc();
     if constexpr (sizeof(T) == 4) deposit_prev();
     if constexpr (sizeof(T) == 8) {
         if (P.fixed_q)
