@@ -396,8 +396,7 @@ def ensemble_bench(n_runs=64, steps=10, scale=1.0):
     c1 = live()
     ps_seq = sum(0.5 * (a[0] + a[1] + b[0] + b[1]) for a, b in zip(c0, c1)) * steps
     # together
-    ns, stream_ms = autotune.best_stream_count(sims)
-    ens = Ensemble(sims, nstreams=ns)
+    ens = Ensemble(sims, nstreams=1)
     ens.step(1)
     c0 = live()
     torch.cuda.synchronize()
@@ -419,12 +418,11 @@ def ensemble_bench(n_runs=64, steps=10, scale=1.0):
     seq = ps_seq / t_seq
     bat = ps_ens / t_ens
     log(f"[bench] ensemble: sequential {seq:.3e}, batched {bat:.3e} particle-steps/s "
-        f"({bat / seq:.2f}x), {ns} streams")
+        f"({bat / seq:.2f}x)")
     return {"runs": n_runs, "steps": steps, "total_particles": int(sum(r["particles"] for r in runs)),
             "sequential_particle_steps_per_s": seq, "batched_particle_steps_per_s": bat,
             "speedup": bat / seq, "sequential_ms_per_step": t_seq / steps * 1e3,
-            "batched_ms_per_step": t_ens / steps * 1e3, "streams": ns,
-            "stream_ms_per_step": stream_ms, "tuning": cache.table,
+            "batched_ms_per_step": t_ens / steps * 1e3, "tuning": cache.table,
             "note": "per-run values after the measured steps (a few tens of ps of a discharge "
                     "that needs ~4 us to reach steady state)",
             "per_run": runs}

@@ -426,8 +426,12 @@ pic_status pic_set_poisson_mode(pic_handle *h, int32_t mode);
  * electron against an ion when those blocks are split between the species
  * (electrons carry the collision test).  pic_autotune times candidate shapes
  * on the live simulation (block counts 256..8192 at the current weight, then
- * weights 1.0, 1.3, 1.7 at the best count), steps_per_trial steps each, so
- * the run advances by 9 * steps_per_trial steps; it keeps the fastest.  The
+ * weights 1.0, 1.3, 1.7 at the best count), steps_per_trial steps each, and
+ * keeps the fastest.  The trials run on a copy of the state: the workspace
+ * (pic_query_workspace bytes) is copied to a device buffer the call
+ * allocates and frees, and copied back with the host-side solver state
+ * afterwards, so the simulation is where it was before the call.  Errors:
+ * PIC_EINVAL, PIC_EHIP (the copy's allocation or a trial's step).  The
  * shape changes no result beyond the summation order of the FP32 deposit.
  * pic_set_tuning applies a stored choice (e.g. from a run of the same size). */
 typedef struct pic_tuning {
@@ -463,8 +467,8 @@ pic_status pic_get_tuning(const pic_handle *h, pic_tuning *t);
  * synchronization per step for the runs' status.  Each kernel of the step
  * (the cell sort of a sort step included) runs once for a batch of up to 64
  * runs, a block finding its run from block offsets, so the step is one
- * stream's work; nstreams (1..16) is accepted and the streams are created,
- * but they no longer change the step.  Each field solve is multigrid-preconditioned and controlled on
+ * stream's work; nstreams must lie in 1..16 and is otherwise unused (kept so
+ * that the signature stays stable).  Each field solve is multigrid-preconditioned and controlled on
  * the device: the step's graph holds its first pass, and while the status
  * shows a run short of poisson_rtol a captured one-pass graph runs again
  * (at most two more passes) for the runs not yet converged, so a run

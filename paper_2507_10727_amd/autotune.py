@@ -1,5 +1,6 @@
 """Launch tuning with a cache: the particle kernel's shape per run size
-(pic_autotune, timed on the GPU) and the stream count of an ensemble.
+(pic_autotune, timed on the GPU; the simulation's state is restored after
+the trials).
 
 Choices are keyed by what sets the kernels' cost: grid, state precision,
 gather scheme and the particle count to within a factor of two.  The cache
@@ -10,7 +11,6 @@ from __future__ import annotations
 import json
 import math
 import os
-import time
 
 from . import workloads as W
 
@@ -49,22 +49,3 @@ class TuningCache:
         self.table[k] = {"push_blocks": t["push_blocks"], "push_e_weight": t["push_e_weight"],
                          "push_ms": t["push_ms"]}
         return self.table[k], True
-
-
-def best_stream_count(sims, candidates=(2, 4, 8, 16), steps=3):
-    """Time `steps` ensemble steps per stream count (after one capturing
-    step) and return (best count, {count: ms per step})."""
-    import torch
-    from .sim import Ensemble
-    times = {}
-    for ns in candidates:
-        ens = Ensemble(sims, nstreams=ns)
-        ens.step(1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ens.step(steps)
-        torch.cuda.synchronize()
-        times[ns] = (time.perf_counter() - t0) / steps * 1e3
-        ens.close()
-    best = min(times, key=times.get)
-    return best, times

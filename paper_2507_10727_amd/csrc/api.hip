@@ -1302,8 +1302,6 @@ struct pic_ensemble {
     std::vector<pic_handle *> runs;
     hipStream_t s0 = nullptr;
     bool own_s0 = false;
-    std::vector<hipStream_t> streams;
-    std::vector<hipEvent_t> events;     // fork + one join per stream
     RunStatus *status = nullptr;        // pinned host memory, one per run
     RunStatus *status_dev = nullptr;    // its device address
     std::vector<BatchPlan> plans;       // batches of at most MAX_BATCH runs
@@ -2297,18 +2295,13 @@ pic_status pic_ensemble_create(pic_handle *const *runs, int32_t nruns, void *str
         }
         e->own_s0 = true;
     }
-    e->streams.resize(nstreams);
-    e->events.resize(nstreams + 1);
     bool ok = true;
-    for (auto &s : e->streams) ok &= hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
-    for (auto &v : e->events)
-        ok &= hipEventCreateWithFlags(&v, hipEventDisableTiming) == hipSuccess;
     const int nbatch = (nruns + MAX_BATCH - 1) / MAX_BATCH;
     ok &= hipHostMalloc((void **)&e->status, sizeof(RunStatus) * nbatch * MAX_BATCH) == hipSuccess;
     ok = ok && hipHostGetDevicePointer((void **)&e->status_dev, e->status, 0) == hipSuccess;
     if (!ok) {
         pic_ensemble_free(e);
-        return efail(nullptr, PIC_EHIP, "cannot create the ensemble's streams or status buffer");
+        return efail(nullptr, PIC_EHIP, "cannot create the ensemble's status buffer");
     }
     memset(e->status, 0, sizeof(RunStatus) * nbatch * MAX_BATCH);
     // the descriptor of each run's batched field update, in its workspace
@@ -2409,10 +2402,6 @@ pic_status pic_ensemble_free(pic_ensemble *e)
     if (!e) return PIC_OK;
     if (e->s0) (void)hipStreamSynchronize(e->s0);
     drop_ensemble_graphs(e);
-    for (auto &s : e->streams)
-        if (s) (void)hipStreamDestroy(s);
-    for (auto &v : e->events)
-        if (v) (void)hipEventDestroy(v);
     if (e->status) (void)hipHostFree(e->status);
     if (e->own_s0 && e->s0) (void)hipStreamDestroy(e->s0);
     delete e;
@@ -2467,6 +2456,26 @@ pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out)
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     timers_collect(h);
     const pic_timers saved = h->timers;
+    // The trials step the live simulation; its state is copied first (the
+    // workspace into a device buffer, the handle's host-side solver state)
+    // and put back afterwards, so tuning leaves the run where it was.
+    const int64_t snap_bytes = layout(h->cfg, nullptr, nullptr);
+    char *snap = nullptr;
+    HIPCHECK(h, hipMalloc((void **)&snap, (size_t)snap_bytes));
+    {
+        const hipError_t e = hipMemcpyAsync(snap, h->ws, (size_t)snap_bytes,
+                                            hipMemcpyDeviceToDevice, h->stream);
+        if (e != hipSuccess) {
+            hipFree(snap);
+            return fail(h, PIC_EHIP, "autotune state copy: %s", hipGetErrorString(e));
+        }
+    }
+    const int cur0[2] = {h->cur[0], h->cur[1]};
+    const int64_t count0[2] = {h->host_count[0], h->host_count[1]};
+    const int sort0 = h->steps_since_sort;
+    const pic_poisson_stats last0 = h->last;
+    const double rho0 = h->rho, rel00 = h->rel0_est, rho_pc0 = h->rho_pc, rho_cg0 = h->rho_cg;
+    const int32_t flags0 = h->host_flags;
     h->timers_on = true;
     h->timers_push_only = true;
     // one trial: the mean device time of the particle kernel over the steps
@@ -2506,9 +2515,28 @@ pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out)
         }
     h->push_blocks = best.push_blocks;
     h->push_e_weight = best.push_e_weight;
+    // back to the saved state
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->ws, snap, (size_t)snap_bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    hipFree(snap);
+    h->cur[0] = cur0[0];
+    h->cur[1] = cur0[1];
+    h->host_count[0] = count0[0];
+    h->host_count[1] = count0[1];
+    h->steps_since_sort = sort0;
+    h->last = last0;
+    h->rho = rho0;
+    h->rel0_est = rel00;
+    h->rho_pc = rho_pc0;
+    h->rho_cg = rho_cg0;
+    h->host_flags = flags0;
+    timers_collect(h);
     h->timers = saved;
     h->timers_on = was_on;
     h->timers_push_only = was_push_only;
+    if (e != hipSuccess) return fail(h, PIC_EHIP, "autotune state restore: %s", hipGetErrorString(e));
     if (st != PIC_OK) return st;
     best.trials = (int32_t)(sizeof(blocks) / sizeof(blocks[0]) + sizeof(weights) / sizeof(weights[0]));
     if (out) *out = best;

@@ -117,6 +117,34 @@ __device__ __forceinline__ float pos_round(float f)
 }
 __device__ __forceinline__ double pos_round(double f) { return f; }
 
+// A step's displacement (cells) rounded to a whole number of position
+// quanta (2^-21 cell), down after adding d16 / 65536 of a quantum: the
+// rounding is exact on average.  The FP32 state holds the offset on the
+// quantum grid, so the new offset (old + rounded displacement) is exact; had
+// the sum been rounded to nearest instead, a particle of steady velocity
+// would lose the same fraction of a quantum every step, and one that moves
+// less than half a quantum per step would never move.
+__device__ __forceinline__ float step_round(float d, uint32_t d16)
+{
+    const float x = fmaf(d, (float)(1u << POS_BITS), (float)d16 * (1.0f / 65536.0f));
+    return floorf(x) * (1.0f / (float)(1u << POS_BITS));
+}
+
+// Dither bits of one particle slot and step: a 32-bit integer hash of the
+// slot, the step and the run's stream word (the lowbias32 mixer from
+// C. Wellons' hash-prospector search: xor-shift 16, multiply, xor-shift 15,
+// multiply, xor-shift 16), 16 bits for each axis.
+__device__ __forceinline__ uint32_t dither_bits(uint32_t slot, uint32_t step, uint32_t word)
+{
+    uint32_t x = slot ^ (step * 0x9E3779B9u) ^ (word * 0x85EBCA6Bu);
+    x ^= x >> 16;
+    x *= 0x7FEB352Du;
+    x ^= x >> 15;
+    x *= 0x846CA68Bu;
+    x ^= x >> 16;
+    return x;
+}
+
 // Position of slot p: returns the key j << 16 | i (-1 if absorbed) and the
 // fractions (also of an absorbed slot: its last cell and offsets).
 template <typename T>

@@ -112,7 +112,7 @@ struct Tally {
 // 2 Neumann block, 3 outer r, 4 anode).  ke_dot / pz_v receive
 // v^{n-1/2}.v^{n+1/2} and v_z^{n+1/2} for the diagnostics.
 template <typename T, int SCHEME>
-__device__ __forceinline__ int advance(const PushParams<T> &P, T hqm,
+__device__ __forceinline__ int advance(const PushParams<T> &P, T hqm, uint32_t dbits,
                                        const typename Vec4<T>::type &a00,
                                        const typename Vec4<T>::type &a10,
                                        const typename Vec4<T>::type &a01,
@@ -168,8 +168,16 @@ __device__ __forceinline__ int advance(const PushParams<T> &P, T hqm,
     }
     const T den = r + r1;
     const T drr = (den > (T)0) ? fma((T)2 * r, dx, fma(dx, dx, dy * dy)) * rcp<T>(den) : (T)0;
-    const T xr = fma(drr, P.inv_dr, fr);
-    const T xz = fma(nzv * P.dt, P.inv_dz, fz);
+    T xr, xz;
+    if constexpr (sizeof(T) == 4) {
+        // displacements rounded to the state's quanta without bias (dbits:
+        // 16 dither bits per axis), so the new offsets are exact
+        xr = fr + step_round(drr * P.inv_dr, dbits & 0xFFFFu);
+        xz = fz + step_round((nzv * P.dt) * P.inv_dz, dbits >> 16);
+    } else {
+        xr = fma(drr, P.inv_dr, fr);
+        xz = fma(nzv * P.dt, P.inv_dz, fz);
+    }
     const T flr = floor(xr), flz = floor(xz);
     int i1 = i + (int)flr, j1 = j + (int)flz;
     T fr1 = xr - flr, fz1 = xz - flz;
@@ -836,7 +844,8 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
                     prev = key;
                 }
                 T kd, pv;
-                const int fate = advance<T, SCHEME>(P, hqm, a00, a10, a01, a11, i, j, fr[k],
+                const uint32_t db = (sizeof(T) == 4) ? dither_bits((uint32_t)(p0 + k), step, word1) : 0u;
+                const int fate = advance<T, SCHEME>(P, hqm, db, a00, a10, a01, a11, i, j, fr[k],
                                                     fz[k], vr[k], vt[k], vz[k], kd, pv);
                 ke_c += kd;
                 pz_c += pv;

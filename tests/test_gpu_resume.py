@@ -134,3 +134,29 @@ def test_resume_bit_exact(scheme):
     c.close()
     say("  counts", got["state"]["count"], "vc", got["state"]["vc"])
     _assert_same_bits(ref, got, "resumed run")
+
+
+def test_autotune_leaves_the_run_where_it_was():
+    """pic_autotune steps the live simulation through its trials (nine
+    shapes, two steps each) and then puts the state back: the state right
+    after the call equals the state before it, and 30 further steps reach
+    the same bits as a run that was never tuned (the fixed-point deposit
+    makes the launch shape irrelevant to the result)."""
+    p = _problem(W.EC_PIC)
+    br, bz, sig, parts = W.inputs(p)
+    say("case autotune restores the state", p.name)
+    a = gpu_sim(p, br, bz, sig, [x.copy() for x in parts])
+    a.step(25)
+    before = _snapshot(a)
+    t = a.autotune(steps_per_trial=2)
+    say("  tuning", t)
+    after = _snapshot(a)
+    _assert_same_bits(before, after, "right after autotune")
+    a.step(30)
+    tuned = _snapshot(a)
+    a.close()
+    b = gpu_sim(p, br, bz, sig, [x.copy() for x in parts])
+    b.step(55)
+    ref = _snapshot(b)
+    b.close()
+    _assert_same_bits(ref, tuned, "tuned run")
