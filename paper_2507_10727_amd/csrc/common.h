@@ -130,19 +130,16 @@ __device__ __forceinline__ float step_round(float d, uint32_t d16)
     return floorf(x) * (1.0f / (float)(1u << POS_BITS));
 }
 
-// Dither bits of one particle slot and step: a 32-bit integer hash of the
-// slot, the step and the run's stream word (the lowbias32 mixer from
-// C. Wellons' hash-prospector search: xor-shift 16, multiply, xor-shift 15,
-// multiply, xor-shift 16), 16 bits for each axis.
+// Dither bits of one particle slot and step, 16 per axis: for a fixed slot
+// the top bits of a Weyl sequence in the step, offset per slot and run
+// (increments 0x9E3779B9 and 0x6A09E667, the fractional parts of the golden
+// ratio and of sqrt 2 in 32-bit fixed point), so over consecutive steps a
+// particle's dither visits [0, 1) evenly and its rounding errors cancel.
 __device__ __forceinline__ uint32_t dither_bits(uint32_t slot, uint32_t step, uint32_t word)
 {
-    uint32_t x = slot ^ (step * 0x9E3779B9u) ^ (word * 0x85EBCA6Bu);
-    x ^= x >> 16;
-    x *= 0x7FEB352Du;
-    x ^= x >> 15;
-    x *= 0x846CA68Bu;
-    x ^= x >> 16;
-    return x;
+    const uint32_t r = slot * 0x85EBCA6Bu + step * 0x9E3779B9u + word * 0xC2B2AE35u;
+    const uint32_t z = slot * 0x27D4EB2Fu + step * 0x6A09E667u + word * 0x165667B1u;
+    return (r >> 16) | (z & 0xFFFF0000u);
 }
 
 // Position of slot p: returns the key j << 16 | i (-1 if absorbed) and the

@@ -734,22 +734,16 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
     // next iteration, once that chunk's loads are issued, so the end of an
     // iteration holds only the particle stores.
     unsigned int pend = 0;          // bit k: particle k of the lane's held chunk
+    uint32_t prank = 0;             // byte k: entry of particle k within the range
     int pend_base = 0, pleader = -1;
-    uint64_t pm[4] = {0ull, 0ull, 0ull, 0ull};
     int64_t pp0 = 0;
     auto flush_mcc = [&]() {
         if (pleader < 0) return;
         const int base = __builtin_amdgcn_readlane(pend_base, pleader);
-        int off = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            if (pend & (1u << k)) {
-                const int e = base + off +
-                              (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(pm[k] >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)pm[k], 0u));
-                if (e < P.ev_cap) P.mcc_q[e] = make_int2((int)(pp0 + k), 0);
-            }
-            off += __popcll(pm[k]);
+            const int e = base + (int)((prank >> (8 * k)) & 0xFFu);
+            if ((pend & (1u << k)) && e < P.ev_cap) P.mcc_q[e] = make_int2((int)(pp0 + k), 0);
         }
         pleader = -1;
         pend = 0;
@@ -880,21 +874,29 @@ __device__ __forceinline__ void push_body(const PushParams<T> P, int bid, int nb
                 kk[k] = ok[k] = (j << 16) | i;
             }
             if (collide_on) {
-                uint64_t m[4];
+                // entry of particle k: candidates at positions < k in all
+                // lanes, then those at position k in lower lanes (at most
+                // 255 before the last of 256)
                 int tot = 0;
+                uint64_t any_m = 0ull;
+                uint32_t rank = 0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    m[k] = __ballot((cmask >> k) & 1u);
-                    tot += __popcll(m[k]);
+                    const uint64_t m = __ballot((cmask >> k) & 1u);
+                    const uint32_t r = (uint32_t)tot + __builtin_amdgcn_mbcnt_hi(
+                                                           (uint32_t)(m >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    rank |= (r & 0xFFu) << (8 * k);
+                    tot += __popcll(m);
+                    any_m |= m;
                 }
                 if (tot) {
-                    const int leader = __ffsll((long long)(m[0] | m[1] | m[2] | m[3])) - 1;
+                    const int leader = __ffsll((long long)any_m) - 1;
                     int b = 0;
                     if (lane == leader) b = atomicAdd(&P.sc->n_mcc_q, tot);
                     pend_base = b;
                     pleader = leader;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) pm[k] = m[k];
+                    prank = rank;
                     pend = cmask;
                     pp0 = p0;
                 }
