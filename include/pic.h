@@ -240,10 +240,19 @@ pic_status pic_query_workspace(const pic_config *cfg, int64_t *bytes);
 pic_status pic_init(const pic_config *cfg, void *workspace_dev, int64_t workspace_bytes,
                     void *stream, const pic_species_host *init, pic_handle **out);
 
-/* Advance nsteps timesteps (gather, push, walls and emission, collisions,
- * new particles, deposit, field solve, circuit).  Returns after the last
- * step's work is enqueued; synchronizes only where the field solve checks
- * its residual.  Errors: PIC_ECAPACITY, PIC_ENOCONV, PIC_EHIP. */
+/* Advance nsteps (>= 0) explicit timesteps of the electrostatic PIC-MCC
+ * cycle: field gather in the configured form (Section 2: EC-PIC edge fields
+ * or MC-PIC nodal fields), Boris push and the R-Z rotation, particle walls
+ * with ion- and electron-induced emission at the cathode (Section 3),
+ * null-collision Monte Carlo collisions 1a-1d with the background Ar and Ar*
+ * (Section 3), new particles, charge deposit, the field solve of Section 3's
+ * charge-form Poisson equation and the external circuit (Section 3,
+ * Table 1).  h: a handle from pic_init (not NULL).  Works on the handle's
+ * stream; returns after the last step's work is enqueued and synchronizes
+ * only where the field solve checks its residual.  A step that fails
+ * leaves the state at that step (diagnostics name the cause).  Errors:
+ * PIC_EINVAL (NULL handle, nsteps < 0), PIC_ECAPACITY (particle or child
+ * buffers full), PIC_ENOCONV (field solve), PIC_EHIP. */
 pic_status pic_step(pic_handle *h, int32_t nsteps);
 
 /* Standalone field solve on the handle's grid: K phi = q with the cathode
@@ -282,7 +291,12 @@ pic_status pic_poisson_static(pic_handle *h, const double *q_dev, double v_catho
  * node vectors.  Synchronizes. */
 pic_status pic_apply_operator(pic_handle *h, const double *phi_dev, double *out_dev);
 
-/* FP64 diagnostics of the current state.  Synchronizes. */
+/* FP64 diagnostics of the current state into *out (host memory, not NULL):
+ * counts, deposited and expected charge, kinetic energy and axial momentum,
+ * field energy, the cathode's current, voltage and charge (the Section 4
+ * observables: discharge current and voltage, peak densities, plasma
+ * potential phi_max) and the step's event counts.  Synchronizes the
+ * handle's stream.  Errors: PIC_EINVAL, PIC_EHIP. */
 pic_status pic_diag(pic_handle *h, pic_diag_out *out);
 
 /* Device views (synchronize to read counts). */
@@ -487,7 +501,10 @@ pic_status pic_ensemble_step(pic_ensemble *e, int32_t nsteps);
 pic_status pic_ensemble_free(pic_ensemble *e);
 const char *pic_ensemble_last_error(const pic_ensemble *e);
 
-/* Destroy the handle (does not free the caller's workspace). */
+/* Destroy the handle: waits for its stream, releases what the library
+ * allocated (pinned readback block, events, graphs); the caller's workspace
+ * and stream stay the caller's.  NULL is accepted.  Lifecycle only (no
+ * operation of the paper). */
 pic_status pic_free(pic_handle *h);
 
 /* Message of the last error on h (or of the last failed pic_init if h is
