@@ -238,10 +238,21 @@ __device__ __forceinline__ void sort_scatter_body(const SpeciesDev<T> &src,
     for (int q = threadIdx.x; q < SORT_WIN; q += 256) cnt[q] = 0;
     for (int64_t base = (int64_t)bid * SORT_CHUNK; base < n; base += (int64_t)nb * SORT_CHUNK) {
         int bins[SORT_PER_THREAD];
+        uint32_t wr[SORT_PER_THREAD], wz[SORT_PER_THREAD];   // FP32: the position words
 #pragma unroll
         for (int m = 0; m < SORT_PER_THREAD; ++m) {
             const int64_t p = base + m * 256 + threadIdx.x;
-            bins[m] = (p < n) ? sort_bin(src, p, nr) : -1;
+            if constexpr (sizeof(T) == 4) {
+                wr[m] = 0u;
+                wz[m] = 0xFFFFFFFFu;
+                if (p < n) {
+                    wr[m] = ((const uint32_t *)src.fr)[p];
+                    wz[m] = ((const uint32_t *)src.fz)[p];
+                }
+                bins[m] = ((int32_t)wz[m] < 0) ? -1 : pos_cell(wz[m]) * nr + pos_cell(wr[m]);
+            } else {
+                bins[m] = (p < n) ? sort_bin(src, p, nr) : -1;
+            }
         }
         const int w0 = chunk_min_bin(bins, red);       // (barrier: cnt is zero)
         // count the window's bins
@@ -260,7 +271,8 @@ __device__ __forceinline__ void sort_scatter_body(const SpeciesDev<T> &src,
             rk[q] = 0;
         }
         __syncthreads();
-        // rank within the bin (LDS) and move
+        // rank within the bin (LDS), then move
+        int dix[SORT_PER_THREAD];                      // destination slot, -1 if none
 #pragma unroll
         for (int m = 0; m < SORT_PER_THREAD; ++m) {
             const int bin = bins[m];
@@ -274,7 +286,52 @@ __device__ __forceinline__ void sort_scatter_body(const SpeciesDev<T> &src,
                 else first = atomicAdd(&off[bin], len);
             }
             first = __shfl(first, head, 64);
-            if (valid) copy_slot(src, dst, base + m * 256 + threadIdx.x, (int64_t)first + (lane - head));
+            dix[m] = valid ? first + (lane - head) : -1;
+        }
+        if constexpr (sizeof(T) == 4) {
+            // FP32: the position words are already held; the velocities and
+            // ids move in groups of four slots, every load of a group issued
+            // before its stores (one memory round trip per group)
+            const float *__restrict__ svr = (const float *)src.vr;
+            const float *__restrict__ svt = (const float *)src.vt;
+            const float *__restrict__ svz = (const float *)src.vz;
+            const uint32_t *__restrict__ sid = src.id;
+            uint32_t *__restrict__ dfr = (uint32_t *)dst.fr;
+            uint32_t *__restrict__ dfz = (uint32_t *)dst.fz;
+            float *__restrict__ dvr = (float *)dst.vr;
+            float *__restrict__ dvt = (float *)dst.vt;
+            float *__restrict__ dvz = (float *)dst.vz;
+            uint32_t *__restrict__ did = dst.id;
+#pragma unroll
+            for (int g = 0; g < SORT_PER_THREAD; g += 4) {
+                float a[4], b[4], c[4];
+                uint32_t e[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t p = base + (g + u) * 256 + threadIdx.x;
+                    const int64_t pl = dix[g + u] >= 0 ? p : 0;   // slot 0: a valid address
+                    a[u] = svr[pl];
+                    b[u] = svt[pl];
+                    c[u] = svz[pl];
+                    e[u] = sid[pl];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int d = dix[g + u];
+                    if (d >= 0) {
+                        dfr[d] = wr[g + u];
+                        dfz[d] = wz[g + u];
+                        dvr[d] = a[u];
+                        dvt[d] = b[u];
+                        dvz[d] = c[u];
+                        did[d] = e[u];
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < SORT_PER_THREAD; ++m)
+                if (dix[m] >= 0) copy_slot(src, dst, base + m * 256 + threadIdx.x, (int64_t)dix[m]);
         }
         __syncthreads();
         for (int q = threadIdx.x; q < SORT_WIN; q += 256) cnt[q] = 0;
