@@ -35,65 +35,66 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int GT = 32;       // C tile of a block (GT x GT), 4 waves of 16 x 16
-constexpr int GK = 32;       // K slice staged in LDS per pass
-constexpr int LDA_S = GK + 4;   // padded LDS row of the A slice (doubles)
-constexpr int LDB_S = GT + 4;   // padded LDS row of the B slice
+constexpr int GT = 16;       // C tile of a block (GT x GT)
+constexpr int GW = 8;        // waves of a block, one k range each
+constexpr int KB = 8;        // k steps (of 4) whose operands a wave loads at once
 
-// C = A B for padded row-major operands: A is Mp x Kp (lda), B is Kp x Np
-// (ldb); Mp, Np, Kp are multiples of 32.  Each of the 4 waves of a block
-// owns one 16 x 16 quarter of the block's 32 x 32 tile and accumulates it
-// with v_mfma_f64_16x16x4f64: A operand lane l = row l % 16, k = l / 16;
-// B operand lane l = column l % 16, k = l / 16; result item v (0..3) of
-// lane l is row l / 16 + 4 v of column l % 16 (measured on gfx950).
+// C = S B for padded row-major operands: S is the symmetric Mp x Mp sine
+// transform (lda = Mp), B is Mp x Np (ldb); Mp and Np are multiples of 32.
+// A block computes one 16 x 16 tile of C with v_mfma_f64_16x16x4f64; its
+// eight waves take one eighth of the k range each and their partial tiles
+// are summed in LDS in wave order (no atomics: the result does not depend
+// on timing).  Operands come straight from global memory (L2-resident): the
+// B operand of lane l is B[k + l / 16][n0 + l % 16], and since S is
+// symmetric the A operand S[m0 + l % 16][k + l / 16] is read as
+// S[k + l / 16][m0 + l % 16], so both are 128-byte row segments.  A wave
+// loads the operands of KB steps at a time, the next group's loads issued
+// before the current group's products.  Result item v (0..3) of lane l is
+// row l / 16 + 4 v of column l % 16 (measured on gfx950).
 // Epilogue: mode 0 stores the tile to C (ldc); mode 1 adds rows m < M,
 // columns n < N to the node array phi at ((m + 1) * ldp + n), the unknown
 // rows 1..nz-1 of the grid.
-__global__ void __launch_bounds__(256) k_gemm_f64(const double *__restrict__ A, int lda,
-                                                  const double *__restrict__ B, int ldb,
-                                                  double *__restrict__ C, int ldc, int Kp,
-                                                  int mode, int M, int N, int ldp)
+__global__ void __launch_bounds__(64 * GW) k_gemm_f64(const double *__restrict__ A, int lda,
+                                                      const double *__restrict__ B, int ldb,
+                                                      double *__restrict__ C, int ldc, int Kp,
+                                                      int mode, int M, int N, int ldp)
 {
-    __shared__ double As[2][GT * LDA_S];
-    __shared__ double Bs[2][GK * LDB_S];
+    __shared__ d4 part[GW - 1][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-    // staging: each thread moves 4 doubles of A and 4 of B per slice
-    // (two 16-byte loads each): A slice 32 rows x 32 k, B slice 32 k x 32 cols
-    const int ar = tid >> 3, ac = (tid & 7) * 4;     // A: row, first k
-    const int br = tid >> 3, bc = (tid & 7) * 4;     // B: k, first column
-    const double *Ag = A + (int64_t)(m0 + ar) * lda + ac;
-    const double *Bg = B + (int64_t)br * ldb + n0 + bc;
-    double2 ra0 = *(const double2 *)(Ag), ra1 = *(const double2 *)(Ag + 2);
-    double2 rb0 = *(const double2 *)(Bg), rb1 = *(const double2 *)(Bg + 2);
+    const int ks = Kp / (4 * GW);                     // k steps of a wave (>= 1)
+    const int kb = w * 4 * ks + (lane >> 4);
+    const double *Ap = A + (int64_t)kb * lda + m0 + (lane & 15);
+    const double *Bp = B + (int64_t)kb * ldb + n0 + (lane & 15);
     d4 acc = {0.0, 0.0, 0.0, 0.0};
-    const int nslice = Kp / GK;
-    for (int s = 0; s < nslice; ++s) {
-        const int buf = s & 1;
-        double *as = As[buf] + ar * LDA_S + ac;
-        as[0] = ra0.x; as[1] = ra0.y; as[2] = ra1.x; as[3] = ra1.y;
-        double *bs = Bs[buf] + br * LDB_S + bc;
-        bs[0] = rb0.x; bs[1] = rb0.y; bs[2] = rb1.x; bs[3] = rb1.y;
-        __syncthreads();
-        if (s + 1 < nslice) {
-            const double *An = Ag + (s + 1) * GK;
-            const double *Bn = Bg + (int64_t)(s + 1) * GK * ldb;
-            ra0 = *(const double2 *)(An);
-            ra1 = *(const double2 *)(An + 2);
-            rb0 = *(const double2 *)(Bn);
-            rb1 = *(const double2 *)(Bn + 2);
-        }
-        const double *ap = As[buf] + (wm * 16 + (lane & 15)) * LDA_S + (lane >> 4);
-        const double *bp = Bs[buf] + (lane >> 4) * LDB_S + wn * 16 + (lane & 15);
+    double a[2][KB], b[2][KB];
+    auto load = [&](int g, int t0) {
 #pragma unroll
-        for (int kk = 0; kk < GK; kk += 4)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[kk], bp[kk * LDB_S], acc, 0, 0, 0);
-        // the next pass writes the other buffer; this one is rewritten two
-        // passes later, after the barrier of the next pass
+        for (int t = 0; t < KB; ++t) {
+            const int st = min(t0 + t, ks - 1);       // clamped: a valid address
+            a[g][t] = Ap[(int64_t)(4 * st) * lda];
+            b[g][t] = Bp[(int64_t)(4 * st) * ldb];
+        }
+    };
+    auto mul = [&](int g, int t0) {
+#pragma unroll
+        for (int t = 0; t < KB; ++t)
+            if (t0 + t < ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[g][t], b[g][t], acc, 0, 0, 0);
+    };
+    load(0, 0);
+    for (int t0 = 0; t0 < ks; t0 += 2 * KB) {
+        if (t0 + KB < ks) load(1, t0 + KB);
+        mul(0, t0);
+        if (t0 + 2 * KB < ks) load(0, t0 + 2 * KB);
+        if (t0 + KB < ks) mul(1, t0 + KB);
     }
-    const int col = n0 + wn * 16 + (lane & 15);
-    const int row0 = m0 + wm * 16 + (lane >> 4);
+    if (w > 0) part[w - 1][lane] = acc;
+    __syncthreads();
+    if (w != 0) return;
+#pragma unroll
+    for (int q = 0; q < GW - 1; ++q) acc += part[q][lane];
+    const int col = n0 + (lane & 15);
+    const int row0 = m0 + (lane >> 4);
     if (mode == 0) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) C[(int64_t)(row0 + 4 * v) * ldc + col] = acc[v];
@@ -246,12 +247,12 @@ void launch_fast_solve(const FastSolve &F, const FieldDev &f, double *phi, DevSc
     const int rb = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (total + 255) / 256));
     hipLaunchKernelGGL(k_fs_rhs, dim3(rb), dim3(256), 0, s, nr, nz, (const double *)f.r64, F.b,
                        Np, Mp, sc->res_slots);
-    hipLaunchKernelGGL(k_gemm_f64, dim3(Np / GT, Mp / GT), dim3(256), 0, s, F.S, Mp, F.b, Np,
+    hipLaunchKernelGGL(k_gemm_f64, dim3(Np / GT, Mp / GT), dim3(64 * GW), 0, s, F.S, Mp, F.b, Np,
                        F.bh, Np, Mp, 0, M, nr, 0);
     int pt = 64;
     while (pt < nr) pt <<= 1;
     hipLaunchKernelGGL(k_fs_pcr, dim3(M), dim3(pt), 0, s, nr, F.ce1, F.cn1, F.lam, F.bh, Np);
-    hipLaunchKernelGGL(k_gemm_f64, dim3(Np / GT, Mp / GT), dim3(256), 0, s, F.S, Mp, F.bh, Np,
+    hipLaunchKernelGGL(k_gemm_f64, dim3(Np / GT, Mp / GT), dim3(64 * GW), 0, s, F.S, Mp, F.bh, Np,
                        phi, 0, Mp, 1, M, nr, nr + 1);
 }
 
