@@ -440,13 +440,16 @@ pic_status pic_set_poisson_mode(pic_handle *h, int32_t mode);
  * electron against an ion when those blocks are split between the species
  * (electrons carry the collision test).  pic_autotune times candidate shapes
  * on the live simulation (block counts 256..8192 at the current weight, then
- * weights 1.0, 1.3, 1.7 at the best count), steps_per_trial steps each, and
- * keeps the fastest.  The trials run on a copy of the state: the workspace
- * (pic_query_workspace bytes) is copied to a device buffer the call
- * allocates and frees, and copied back with the host-side solver state
- * afterwards, so the simulation is where it was before the call.  Errors:
- * PIC_EINVAL, PIC_EHIP (the copy's allocation or a trial's step).  The
- * shape changes no result beyond the summation order of the FP32 deposit.
+ * weights 1.0, 1.3, 1.7 at the best count), steps_per_trial (>= 1) steps
+ * each, and keeps the fastest.  scratch_dev: a device buffer of the
+ * caller's, at least pic_query_workspace bytes (scratch_bytes), into which
+ * the workspace is copied before the trials and from which it is copied
+ * back, with the host-side solver state, afterwards: the simulation is then
+ * where it was before the call.  scratch_dev NULL: no copy, and the run
+ * advances by 9 * steps_per_trial steps.  out (host, nullable) receives the
+ * choice.  Synchronizes.  Errors: PIC_EINVAL (scratch too small,
+ * steps_per_trial < 1), PIC_EHIP or a trial step's error.  The shape
+ * changes no result beyond the summation order of the FP32 deposit.
  * pic_set_tuning applies a stored choice (e.g. from a run of the same size). */
 typedef struct pic_tuning {
     int32_t push_blocks;        /* default 1024                                   */
@@ -469,7 +472,8 @@ typedef struct pic_tuning {
                                    node, the direct launches measured faster). */
 } pic_tuning;
 
-pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out);
+pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, void *scratch_dev,
+                        int64_t scratch_bytes, pic_tuning *out);
 pic_status pic_set_tuning(pic_handle *h, const pic_tuning *t);
 pic_status pic_get_tuning(const pic_handle *h, pic_tuning *t);
 

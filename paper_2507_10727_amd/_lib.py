@@ -203,7 +203,7 @@ def load():
     L.pic_ensemble_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_int32,
                                       C.POINTER(C.c_void_p)]
     L.pic_ensemble_step.argtypes = [C.c_void_p, C.c_int32]
-    L.pic_autotune.argtypes = [H, C.c_int32, C.POINTER(pic_tuning)]
+    L.pic_autotune.argtypes = [H, C.c_int32, C.c_void_p, C.c_int64, C.POINTER(pic_tuning)]
     L.pic_set_tuning.argtypes = [H, C.POINTER(pic_tuning)]
     L.pic_get_tuning.argtypes = [H, C.POINTER(pic_tuning)]
     L.pic_ensemble_free.argtypes = [C.c_void_p]

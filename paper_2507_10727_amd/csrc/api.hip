@@ -2448,28 +2448,27 @@ pic_status pic_get_tuning(const pic_handle *h, pic_tuning *t)
     return PIC_OK;
 }
 
-pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out)
+pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, void *scratch_dev,
+                        int64_t scratch_bytes, pic_tuning *out)
 {
     if (!h) return fail(nullptr, PIC_EINVAL, "handle is NULL");
     if (steps_per_trial < 1) return fail(h, PIC_EINVAL, "steps_per_trial < 1");
+    const int64_t snap_bytes = layout(h->cfg, nullptr, nullptr);
+    if (scratch_dev && scratch_bytes < snap_bytes)
+        return fail(h, PIC_EINVAL, "autotune scratch of %lld bytes < %lld needed",
+                    (long long)scratch_bytes, (long long)snap_bytes);
     const bool was_on = h->timers_on, was_push_only = h->timers_push_only;
     HIPCHECK(h, hipStreamSynchronize(h->stream));
     timers_collect(h);
     const pic_timers saved = h->timers;
-    // The trials step the live simulation; its state is copied first (the
-    // workspace into a device buffer, the handle's host-side solver state)
-    // and put back afterwards, so tuning leaves the run where it was.
-    const int64_t snap_bytes = layout(h->cfg, nullptr, nullptr);
-    char *snap = nullptr;
-    HIPCHECK(h, hipMalloc((void **)&snap, (size_t)snap_bytes));
-    {
-        const hipError_t e = hipMemcpyAsync(snap, h->ws, (size_t)snap_bytes,
-                                            hipMemcpyDeviceToDevice, h->stream);
-        if (e != hipSuccess) {
-            hipFree(snap);
-            return fail(h, PIC_EHIP, "autotune state copy: %s", hipGetErrorString(e));
-        }
-    }
+    // The trials step the live simulation.  With scratch, its state is
+    // copied first (the workspace into the caller's buffer, the handle's
+    // host-side solver state) and put back afterwards, so tuning leaves the
+    // run where it was.
+    char *snap = (char *)scratch_dev;
+    if (snap)
+        HIPCHECK(h, hipMemcpyAsync(snap, h->ws, (size_t)snap_bytes, hipMemcpyDeviceToDevice,
+                                   h->stream));
     const int cur0[2] = {h->cur[0], h->cur[1]};
     const int64_t count0[2] = {h->host_count[0], h->host_count[1]};
     const int sort0 = h->steps_since_sort;
@@ -2517,26 +2516,27 @@ pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, pic_tuning *out)
     h->push_e_weight = best.push_e_weight;
     // back to the saved state
     hipError_t e = hipStreamSynchronize(h->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(h->ws, snap, (size_t)snap_bytes, hipMemcpyDeviceToDevice, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    hipFree(snap);
-    h->cur[0] = cur0[0];
-    h->cur[1] = cur0[1];
-    h->host_count[0] = count0[0];
-    h->host_count[1] = count0[1];
-    h->steps_since_sort = sort0;
-    h->last = last0;
-    h->rho = rho0;
-    h->rel0_est = rel00;
-    h->rho_pc = rho_pc0;
-    h->rho_cg = rho_cg0;
-    h->host_flags = flags0;
+    if (snap) {
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->ws, snap, (size_t)snap_bytes, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        h->cur[0] = cur0[0];
+        h->cur[1] = cur0[1];
+        h->host_count[0] = count0[0];
+        h->host_count[1] = count0[1];
+        h->steps_since_sort = sort0;
+        h->last = last0;
+        h->rho = rho0;
+        h->rel0_est = rel00;
+        h->rho_pc = rho_pc0;
+        h->rho_cg = rho_cg0;
+        h->host_flags = flags0;
+    }
     timers_collect(h);
     h->timers = saved;
     h->timers_on = was_on;
     h->timers_push_only = was_push_only;
-    if (e != hipSuccess) return fail(h, PIC_EHIP, "autotune state restore: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(h, PIC_EHIP, "autotune: %s", hipGetErrorString(e));
     if (st != PIC_OK) return st;
     best.trials = (int32_t)(sizeof(blocks) / sizeof(blocks[0]) + sizeof(weights) / sizeof(weights[0]));
     if (out) *out = best;

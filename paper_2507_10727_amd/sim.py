@@ -319,9 +319,19 @@ class Simulation:
         L.check(self.lib.pic_apply_operator(self.h, C.c_void_p(phi.data_ptr()),
                                             C.c_void_p(out.data_ptr())), self.h)
 
-    def autotune(self, steps_per_trial=2):
+    def autotune(self, steps_per_trial=2, restore=True):
+        """Time launch shapes on the live run (pic_autotune); with restore,
+        the run's state is copied to a scratch tensor of the workspace's
+        size first and put back afterwards."""
         t = L.pic_tuning()
-        L.check(self.lib.pic_autotune(self.h, int(steps_per_trial), C.byref(t)), self.h)
+        scratch, nbytes = None, 0
+        if restore:
+            scratch = self.torch.empty_like(self.ws)
+            nbytes = scratch.numel()
+        L.check(self.lib.pic_autotune(self.h, int(steps_per_trial),
+                                      C.c_void_p(scratch.data_ptr() if scratch is not None else None),
+                                      C.c_int64(nbytes), C.byref(t)), self.h)
+        del scratch
         return t.as_dict()
 
     def set_tuning(self, push_blocks=None, push_e_weight=None, mg_one_level=None,
