@@ -15,8 +15,8 @@
 // r, (R + lambda_k D) psi_k = (S B)_k.  The solve is applied to the
 // correction equation K d = r of the current potential phi (r its FP64
 // residual: node charge plus Dirichlet couplings minus K phi):
-//   B     = r on the unknown block,
-//   B^    = S B       (FP64 MFMA matrix product over z),
+//   B^    = S r       (FP64 MFMA matrix product over z, r read from the
+//                      node residual on the unknown block),
 //   Psi   tridiagonal solve of every mode (parallel cyclic reduction in LDS),
 //   phi  += S Psi     (FP64 MFMA matrix product, added into the node array).
 // The rounding of the transforms is relative to the correction, not to phi,
@@ -51,21 +51,31 @@ constexpr int KB = 8;        // k steps (of 4) whose operands a wave loads at on
 // loads the operands of KB steps at a time, the next group's loads issued
 // before the current group's products.  Result item v (0..3) of lane l is
 // row l / 16 + 4 v of column l % 16 (measured on gfx950).
-// Epilogue: mode 0 stores the tile to C (ldc); mode 1 adds rows m < M,
-// columns n < N to the node array phi at ((m + 1) * ldp + n), the unknown
-// rows 1..nz-1 of the grid.
+// Modes: 0 and 1 store the tile to C (ldc), 2 adds rows m < M, columns
+// n < N to the node array phi at ((m + 1) * ldp + n), the unknown rows
+// 1..nz-1 of the grid; mode 1 reads B as the FP64 node residual instead of a
+// dense block: B[k][n] = r((k + 1) ldp + n) for k < M, n < N, else 0.
+// clear (nullable): the residual norms' slots, zeroed by the first block.
 __global__ void __launch_bounds__(64 * GW) k_gemm_f64(const double *__restrict__ A, int lda,
                                                       const double *__restrict__ B, int ldb,
                                                       double *__restrict__ C, int ldc, int Kp,
-                                                      int mode, int M, int N, int ldp)
+                                                      int mode, int M, int N, int ldp,
+                                                      double *__restrict__ clear)
 {
     __shared__ d4 part[GW - 1][64];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    if (clear && blockIdx.x == 0 && blockIdx.y == 0)
+        for (int k = tid; k < RES_SLOT_WORDS; k += 64 * GW) clear[k] = 0.0;
     const int ks = Kp / (4 * GW);                     // k steps of a wave (>= 1)
     const int kb = w * 4 * ks + (lane >> 4);
+    const int col = n0 + (lane & 15);
     const double *Ap = A + (int64_t)kb * lda + m0 + (lane & 15);
-    const double *Bp = B + (int64_t)kb * ldb + n0 + (lane & 15);
+    // mode 1: B is the node residual (row k of the block = node row k + 1,
+    // stride ldp), zero outside the M x N unknowns
+    const bool res = mode == 1;
+    const double *Bp = res ? B + (int64_t)(kb + 1) * ldp + col : B + (int64_t)kb * ldb + col;
+    const int64_t bstep = res ? (int64_t)4 * ldp : (int64_t)4 * ldb;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
     double a[2][KB], b[2][KB];
     auto load = [&](int g, int t0) {
@@ -73,7 +83,12 @@ __global__ void __launch_bounds__(64 * GW) k_gemm_f64(const double *__restrict__
         for (int t = 0; t < KB; ++t) {
             const int st = min(t0 + t, ks - 1);       // clamped: a valid address
             a[g][t] = Ap[(int64_t)(4 * st) * lda];
-            b[g][t] = Bp[(int64_t)(4 * st) * ldb];
+            if (!res) {
+                b[g][t] = Bp[st * bstep];
+            } else {
+                const int k = kb + 4 * st;
+                b[g][t] = (k < M && col < N) ? Bp[st * bstep] : 0.0;
+            }
         }
     };
     auto mul = [&](int g, int t0) {
@@ -93,9 +108,8 @@ __global__ void __launch_bounds__(64 * GW) k_gemm_f64(const double *__restrict__
     if (w != 0) return;
 #pragma unroll
     for (int q = 0; q < GW - 1; ++q) acc += part[q][lane];
-    const int col = n0 + (lane & 15);
     const int row0 = m0 + (lane >> 4);
-    if (mode == 0) {
+    if (mode == 0 || mode == 1) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) C[(int64_t)(row0 + 4 * v) * ldc + col] = acc[v];
     } else {
@@ -104,25 +118,6 @@ __global__ void __launch_bounds__(64 * GW) k_gemm_f64(const double *__restrict__
             const int m = row0 + 4 * v;
             if (m < M && col < N) C[(int64_t)(m + 1) * ldp + col] += acc[v];
         }
-    }
-}
-
-// Right-hand side of the correction equation on the unknown block:
-// B[j-1][i] = r(i, j), the FP64 residual of the current potential, for
-// i < nr, 1 <= j < nz, and zero on the rest of the padded Mp x ldb block
-// (so nothing earlier left in B matters).  Also clears the residual norms'
-// slots for the check that follows the correction.
-__global__ void k_fs_rhs(int32_t nr, int32_t nz, const double *__restrict__ r64,
-                         double *__restrict__ Bm, int ldb, int Mp, double *__restrict__ res_slots)
-{
-    if (blockIdx.x == 0)
-        for (int k = threadIdx.x; k < RES_SLOT_WORDS; k += blockDim.x) res_slots[k] = 0.0;
-    const int ld = nr + 1;
-    const int64_t total = (int64_t)Mp * ldb;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int jm = (int)(t / ldb), i = (int)(t - (int64_t)jm * ldb);
-        Bm[t] = (jm < nz - 1 && i < nr) ? r64[(int64_t)(jm + 1) * ld + i] : 0.0;
     }
 }
 
@@ -243,17 +238,15 @@ void launch_fast_solve(const FastSolve &F, const FieldDev &f, double *phi, DevSc
 {
     const int nr = f.nr, nz = f.nz;
     const int M = nz - 1, Mp = fs_pad(M), Np = fs_pad(nr);
-    const int64_t total = (int64_t)Mp * Np;
-    const int rb = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (total + 255) / 256));
-    hipLaunchKernelGGL(k_fs_rhs, dim3(rb), dim3(256), 0, s, nr, nz, (const double *)f.r64, F.b,
-                       Np, Mp, sc->res_slots);
-    hipLaunchKernelGGL(k_gemm_f64, dim3(Np / GT, Mp / GT), dim3(64 * GW), 0, s, F.S, Mp, F.b, Np,
-                       F.bh, Np, Mp, 0, M, nr, 0);
+    // B^ = S r straight from the node residual (clears the norms' slots for
+    // the check that follows the correction)
+    hipLaunchKernelGGL(k_gemm_f64, dim3(Np / GT, Mp / GT), dim3(64 * GW), 0, s, F.S, Mp,
+                       (const double *)f.r64, 0, F.bh, Np, Mp, 1, M, nr, nr + 1, sc->res_slots);
     int pt = 64;
     while (pt < nr) pt <<= 1;
     hipLaunchKernelGGL(k_fs_pcr, dim3(M), dim3(pt), 0, s, nr, F.ce1, F.cn1, F.lam, F.bh, Np);
     hipLaunchKernelGGL(k_gemm_f64, dim3(Np / GT, Mp / GT), dim3(64 * GW), 0, s, F.S, Mp, F.bh, Np,
-                       phi, 0, Mp, 1, M, nr, nr + 1);
+                       phi, 0, Mp, 2, M, nr, nr + 1, nullptr);
 }
 
 }  // namespace pic
