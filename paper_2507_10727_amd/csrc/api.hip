@@ -99,6 +99,7 @@ struct pic_handle {
     double *pinned = nullptr;
     hipEvent_t rb_done = nullptr;   // recorded after the copies; the host spins on it
     int32_t host_flags = 0;
+    double check_rtol2 = 0.0;       // a step's direct solve left its check to the circuit kernel
     bool timers_on = false;
     bool timers_push_only = false;  // time the particle kernel alone
     std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> pending;
@@ -781,14 +782,15 @@ pic_status solve(pic_handle *h, double *phi, const Q *q0, const Q *q1, double v_
     if (mode == PIC_DIRECT) {
         // residual correction with the direct FP64 solve: r = b - K phi,
         // phi += K^-1 r, and the FP64 residual of the result; a step's solve
-        // keeps the norms on the device (checked there by launch_solve_check),
-        // a synchronous one corrects again while short of the tolerance
+        // keeps the norms on the device (checked there by the circuit kernel
+        // that follows it), a synchronous one corrects again while short of
+        // the tolerance
         launch_residual64<Q>(f, phi, q0, q1, h->sc, s, false);
         launch_fast_solve(h->fs, f, phi, h->sc, s);
         launch_residual64<Q>(f, phi, q0, q1, h->sc, s, false);
         S.outer = 1;
         if (!sync) {
-            launch_solve_check(h->sc, rtol * rtol, s);
+            h->check_rtol2 = rtol * rtol;
             S.converged = -1;           // known at the next synchronization
             h->last = S;
             return PIC_OK;
@@ -1061,7 +1063,8 @@ pic_status field_update(pic_handle *h)
     if (st != PIC_OK) return st;
     timer_begin(h, ev, 4);
     launch_circuit<T>(h->f, (const T *)h->q[0], (const T *)h->q[1], h->sc, c.circuit, c.v_fixed,
-                      c.v_ext, c.r_ext, c.dt, c.extra_current * c.dt, h->stream);
+                      c.v_ext, c.r_ext, c.dt, c.extra_current * c.dt, h->stream, h->check_rtol2);
+    h->check_rtol2 = 0.0;
     timer_end(h, 4, ev);
     timer_begin(h, ev, 5);
     launch_field_prep<T>(h->f, (typename Vec4<T>::type *)h->node, h->sc, c.scheme, 0, h->stream);

@@ -647,8 +647,6 @@ void fs_tables(int nr, int nz, const double *ce, const double *cn, double *S, do
 // check that follows
 void launch_fast_solve(const FastSolve &F, const FieldDev &f, double *phi, DevScalars *sc,
                        hipStream_t s);
-// after a residual: flag FLAG_NOCONV when ||r||^2 > rtol2 ||b||^2 (slotted norms)
-void launch_solve_check(DevScalars *sc, double rtol2, hipStream_t s);
 
 // ---- batched field update of an ensemble ------------------------------------
 
@@ -754,7 +752,7 @@ void launch_solve_prep(const FieldDev &f, double *phi, bool extrapolate, double 
 template <typename T>
 void launch_circuit(const FieldDev &f, const T *q0, const T *q1, DevScalars *sc, int circuit,
                     double v_fixed, double v_ext, double r_ext, double dt, double extra_dq,
-                    hipStream_t s);
+                    hipStream_t s, double check_rtol2 = 0.0);
 template <typename T>
 void launch_field_prep(const FieldDev &f, typename Vec4<T>::type *node, DevScalars *sc,
                        int scheme, int use_phi, hipStream_t s);

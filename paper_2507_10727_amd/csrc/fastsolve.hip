@@ -170,23 +170,9 @@ __global__ void __launch_bounds__(1024) k_fs_pcr(int32_t nr, const double *__res
 
 // The residual's slotted norms of one solve, summed in slot order: flag the
 // solve when ||r||^2 > rtol2 ||b||^2 (the flag stays until the host reads it).
-__global__ void k_solve_check(DevScalars *sc, double rtol2)
-{
-    if (threadIdx.x != 0) return;
-    double rr = 0.0, bb = 0.0;
-    for (int k = 0; k < ACC_SLOTS; ++k) {
-        rr += sc->res_slots[k * ACC_STRIDE];
-        bb += sc->res_slots[(ACC_SLOTS + k) * ACC_STRIDE];
-    }
-    if (!(rr <= rtol2 * bb)) atomicOr(&sc->flags, FLAG_NOCONV);
-}
+
 
 }  // namespace
-
-void launch_solve_check(DevScalars *sc, double rtol2, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_solve_check, dim3(1), dim3(64), 0, s, sc, rtol2);
-}
 
 int fs_pad(int n) { return (n + 31) & ~31; }
 

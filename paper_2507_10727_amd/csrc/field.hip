@@ -246,8 +246,18 @@ template <typename T>
 __global__ void k_circuit(int32_t nr, const double *ce, const double *cn, const uint8_t *kind,
                           const double *phi0, const T *q0, const T *q1, DevScalars *sc,
                           int circuit, double v_fixed, double v_ext, double r_ext, double dt,
-                          double extra_dq)
+                          double extra_dq, double check_rtol2)
 {
+    // the preceding direct solve's check (check_rtol2 > 0): FLAG_NOCONV when
+    // its residual (slotted norms) exceeds the tolerance
+    if (check_rtol2 > 0.0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        double rr = 0.0, bb = 0.0;
+        for (int k = 0; k < ACC_SLOTS; ++k) {
+            rr += sc->res_slots[k * ACC_STRIDE];
+            bb += sc->res_slots[(ACC_SLOTS + k) * ACC_STRIDE];
+        }
+        if (!(rr <= check_rtol2 * bb)) atomicOr(&sc->flags, FLAG_NOCONV);
+    }
     circuit_body<T>(nr, ce, cn, kind, phi0, q0, q1, sc, circuit, v_fixed, v_ext, r_ext, dt, extra_dq, blockIdx.x, gridDim.x);
 }
 
@@ -617,10 +627,11 @@ void launch_solve_prep(const FieldDev &f, double *phi, bool extrapolate, double 
 template <typename T>
 void launch_circuit(const FieldDev &f, const T *q0, const T *q1, DevScalars *sc, int circuit,
                     double v_fixed, double v_ext, double r_ext, double dt, double extra_dq,
-                    hipStream_t s)
+                    hipStream_t s, double check_rtol2)
 {
     hipLaunchKernelGGL((k_circuit<T>), dim3(1), dim3(1024), 0, s, f.nr, f.ce64, f.cn64, f.kind,
-                       f.phi0, q0, q1, sc, circuit, v_fixed, v_ext, r_ext, dt, extra_dq);
+                       f.phi0, q0, q1, sc, circuit, v_fixed, v_ext, r_ext, dt, extra_dq,
+                       check_rtol2);
 }
 
 template <typename T>
@@ -671,10 +682,11 @@ template void launch_residual64<float>(const FieldDev &, const double *, const f
 template void launch_residual64<double>(const FieldDev &, const double *, const double *,
                                         const double *, DevScalars *, hipStream_t, bool);
 template void launch_circuit<float>(const FieldDev &, const float *, const float *, DevScalars *,
-                                    int, double, double, double, double, double, hipStream_t);
+                                    int, double, double, double, double, double, hipStream_t,
+                                    double);
 template void launch_circuit<double>(const FieldDev &, const double *, const double *,
                                      DevScalars *, int, double, double, double, double, double,
-                                     hipStream_t);
+                                     hipStream_t, double);
 void launch_nodes_b(const BatchPlan &P, int op, hipStream_t s, int n_iter)
 {
     BatchArgs a = node_args(P, op);
