@@ -1,6 +1,8 @@
 // Particle kernels of libpic.so: the fused timestep kernel (field gather,
-// Boris push, R-Z drift, walls and ion-induced emission, null-collision MCC,
-// charge deposit), child insertion, per-step bookkeeping and the loader.
+// Boris push, R-Z drift, walls, the cathode's emission queue, the
+// null-collision candidate test, charge deposit), the event kernel
+// (collisions, ion- and electron-induced emission, the cathode ion-energy
+// record), child insertion, per-step bookkeeping and the loader.
 #include <climits>
 
 #include "common.h"
