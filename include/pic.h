@@ -205,6 +205,13 @@ typedef struct pic_diag_out {
     int64_t n_see_e;            /* electron-induced secondary electrons          */
 } pic_diag_out;
 
+/* pic_step sorts the electrons every sort_every steps and the ions at
+ * every PIC_ION_SORT_EVERY-th of those sorts: an ion moves ~1e-4 of a cell
+ * per sort interval, so their order barely changes between sorts (the ions
+ * created in between, appended at the end, and absorbed slots wait for the
+ * next ion sort).  Ensembles sort both species at every sort step. */
+#define PIC_ION_SORT_EVERY 4
+
 /* Scalar state for checkpoint/resume.  A checkpoint is this state plus,
  * through the views, slots 0..count-1 of both species' arrays and phi0 and
  * phi0_prev (the field solve's warm start extrapolates from them).  To
@@ -218,7 +225,8 @@ typedef struct pic_scalar_state {
     uint32_t next_id[2];
     int64_t count[2];
     int32_t sort_phase;         /* steps since the last cell sort (0..sort_every) */
-    int32_t pad_;
+    int32_t ion_sort_phase;     /* cell sorts since the ions were last sorted
+                                   (0..PIC_ION_SORT_EVERY-1)                    */
 } pic_scalar_state;
 
 /* Per-phase device time accumulated from HIP events (ms), when enabled. */
@@ -377,7 +385,8 @@ pic_status pic_reweight(pic_handle *h, int32_t keep_every);
  * than these, the particles and the potential).  pic_set_state also rebuilds
  * phi = phi0 + V_c phi_L and the gather fields from the handle's phi0 and the
  * restored V_c.  Errors: PIC_EINVAL (count above capacity, sort_phase outside
- * 0..sort_every).  Both synchronize. */
+ * 0..sort_every, ion_sort_phase outside 0..PIC_ION_SORT_EVERY-1).  Both
+ * synchronize. */
 pic_status pic_get_state(const pic_handle *h, pic_scalar_state *out);
 pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in);
 

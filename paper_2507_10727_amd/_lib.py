@@ -113,7 +113,7 @@ class pic_diag_out(C.Structure):
 class pic_scalar_state(C.Structure):
     _fields_ = [("step", C.c_int64), ("vc", C.c_double), ("qc", C.c_double),
                 ("next_id", C.c_uint32 * 2), ("count", C.c_int64 * 2),
-                ("sort_phase", C.c_int32), ("pad_", C.c_int32)]
+                ("sort_phase", C.c_int32), ("ion_sort_phase", C.c_int32)]
 
 
 class pic_plasma_out(C.Structure):

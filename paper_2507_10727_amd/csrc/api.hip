@@ -64,6 +64,7 @@ struct pic_handle {
     unsigned long long t_null = 0, t_see[2] = {0, 0};
     int64_t host_count[2] = {0, 0};
     int steps_since_sort = 0;
+    int ion_sort_phase = 0;         // electron sorts since the last ion sort
     pic_poisson_stats last = {};
     double rho = 0.15, rel0_est = 1e-2;
     struct PassGraph {
@@ -1007,13 +1008,18 @@ void sort_species(pic_handle *h, int s)
     h->cur[s] = to;
 }
 
+// Cell sort (and compaction) of both species; periodic: the step's sort,
+// which takes the ions only at every PIC_ION_SORT_EVERY-th call.
 template <typename T>
-void sort_all(pic_handle *h)
+void sort_all(pic_handle *h, bool periodic = false)
 {
     hipEvent_t ev[2];
     timer_begin(h, ev, 2);
     sort_species<T>(h, 0);
-    sort_species<T>(h, 1);
+    if (!periodic || ++h->ion_sort_phase >= PIC_ION_SORT_EVERY) {
+        sort_species<T>(h, 1);
+        h->ion_sort_phase = 0;
+    }
     timer_end(h, 2, ev);
     h->steps_since_sort = 0;
 }
@@ -1156,7 +1162,7 @@ template <typename T>
 pic_status step_one(pic_handle *h)
 {
     const pic_config &c = h->cfg;
-    if (h->steps_since_sort >= c.sort_every) sort_all<T>(h);
+    if (h->steps_since_sort >= c.sort_every) sort_all<T>(h, true);
     particle_phase<T>(h);
     h->steps_since_sort++;
     if (c.field_solve) {
@@ -2106,7 +2112,7 @@ pic_status pic_get_state(const pic_handle *hc, pic_scalar_state *out)
     out->count[0] = sc.count[0];
     out->count[1] = sc.count[1];
     out->sort_phase = h->steps_since_sort;
-    out->pad_ = 0;
+    out->ion_sort_phase = h->ion_sort_phase;
     return PIC_OK;
 }
 
@@ -2118,6 +2124,8 @@ pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in)
             return fail(h, PIC_EINVAL, "count out of range");
     if (in->sort_phase < 0 || in->sort_phase > h->cfg.sort_every)
         return fail(h, PIC_EINVAL, "sort_phase outside [0, sort_every]");
+    if (in->ion_sort_phase < 0 || in->ion_sort_phase >= PIC_ION_SORT_EVERY)
+        return fail(h, PIC_EINVAL, "ion_sort_phase outside [0, %d)", PIC_ION_SORT_EVERY);
     DevScalars sc;
     pic_status st = read_scalars(h, &sc);
     if (st != PIC_OK) return st;
@@ -2132,6 +2140,7 @@ pic_status pic_set_state(pic_handle *h, const pic_scalar_state *in)
     h->host_count[0] = in->count[0];
     h->host_count[1] = in->count[1];
     h->steps_since_sort = in->sort_phase;
+    h->ion_sort_phase = in->ion_sort_phase;
     // phi and the gather fields from phi0 and the restored V_c
     if (h->prec == PIC_F64)
         launch_field_prep<double>(h->f, (double4 *)h->node, h->sc, h->cfg.scheme, 0, h->stream);
@@ -2474,7 +2483,7 @@ pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, void *scratch_de
                                    h->stream));
     const int cur0[2] = {h->cur[0], h->cur[1]};
     const int64_t count0[2] = {h->host_count[0], h->host_count[1]};
-    const int sort0 = h->steps_since_sort;
+    const int sort0 = h->steps_since_sort, ion_sort0 = h->ion_sort_phase;
     const pic_poisson_stats last0 = h->last;
     const double rho0 = h->rho, rel00 = h->rel0_est, rho_pc0 = h->rho_pc, rho_cg0 = h->rho_cg;
     const int32_t flags0 = h->host_flags;
@@ -2528,6 +2537,7 @@ pic_status pic_autotune(pic_handle *h, int32_t steps_per_trial, void *scratch_de
         h->host_count[0] = count0[0];
         h->host_count[1] = count0[1];
         h->steps_since_sort = sort0;
+        h->ion_sort_phase = ion_sort0;
         h->last = last0;
         h->rho = rho0;
         h->rel0_est = rel00;

@@ -189,7 +189,8 @@ class Simulation:
         s = L.pic_scalar_state()
         L.check(self.lib.pic_get_state(self.h, C.byref(s)), self.h)
         return {"step": s.step, "vc": s.vc, "qc": s.qc, "next_id": tuple(s.next_id),
-                "count": tuple(s.count), "sort_phase": s.sort_phase}
+                "count": tuple(s.count), "sort_phase": s.sort_phase,
+                "ion_sort_phase": s.ion_sort_phase}
 
     def set_state(self, st):
         s = L.pic_scalar_state()
@@ -197,6 +198,7 @@ class Simulation:
         s.next_id[0], s.next_id[1] = st["next_id"]
         s.count[0], s.count[1] = st["count"]
         s.sort_phase = st.get("sort_phase", 0)
+        s.ion_sort_phase = st.get("ion_sort_phase", 0)
         L.check(self.lib.pic_set_state(self.h, C.byref(s)), self.h)
 
     # -- plasma diagnostics ---------------------------------------------------
