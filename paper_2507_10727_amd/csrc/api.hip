@@ -222,6 +222,13 @@ pic_status validate(const pic_config *c, pic_handle *h)
     }
     if (c->pc_batch < 0 || c->pc_batch > 64)
         return fail(h, PIC_EINVAL, "pc_batch outside [0, 64]");
+    if (c->pc_batch > 0 || c->poisson_mode == PIC_LEARNED) {
+        PcNet t;
+        pc_describe(t, c->nr, c->nz, 1);
+        if (!pc_fits(t))
+            return fail(h, PIC_EINVAL, "grid too narrow for the learned preconditioner's "
+                                       "convolution blocks (their input patch exceeds LDS)");
+    }
     if (c->pc_maxit < 0 || c->pc_maxit > MAX_PCG)
         return fail(h, PIC_EINVAL, "pc_maxit outside [0, %d]", MAX_PCG);
     if (c->gamma_i < 0 || c->p_gas < 0 || !(c->t_gas > 0))

@@ -32,8 +32,8 @@ struct PcLayer {
     int32_t level;              // level of the output
     int32_t up_in;              // input is the coarser level, read nearest-neighbour
     int32_t relu;
-    int32_t kpad;               // forward BF16 row length
-    int32_t kpad_t;             // data-gradient BF16 row length
+    int32_t kpad;               // forward BF16 row length (9 cin_p rounded up to 32)
+    int32_t kpad_t;             // data-gradient BF16 row length (9 cout_p rounded up to 32)
     int32_t kw;                 // master row length (bias at column 9 cin_p)
     int32_t nt, nt_t;           // 16-row tiles of cout, of cin
     int64_t o_master;           // offsets: master / gradient / Adam (floats)
@@ -74,6 +74,7 @@ void pc_describe(PcNet &n, int nr, int nz, int batch);
 int64_t pc_bytes(const PcNet &n);
 void pc_bind(PcNet &n, char *base);
 int pc_kernel_setup();          // raises the dynamic-LDS limit of the conv kernels
+bool pc_fits(const PcNet &n);  // every convolution's block fits a CU's LDS
 
 // Flat parameters (host) <-> master (device); builds the BF16 copies, zeroes Adam.
 void pc_upload(PcNet &n, const float *flat, hipStream_t s);

@@ -2,17 +2,21 @@
 // gradient, weight gradient), pooling and upsampling with their adjoints,
 // the preconditioner's input and output maps, the training loss and Adam.
 //
-// MFMA v_mfma_f32_16x16x16bf16_1k computes D = A B + C for 16x16 tiles; lane
-// l (of 64) holds A[l % 16][4 (l / 16) + j], B[4 (l / 16) + j][l % 16] and
-// D[4 (l / 16) + j][l % 16], j = 0..3.
+// MFMA v_mfma_f32_16x16x32_bf16 (CDNA4) computes D = A B + C for a 16x32 A
+// and a 32x16 B; lane l (of 64) holds A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16], j = 0..7, and D[4 (l / 16) + i][l % 16],
+// i = 0..3.
 //
 // Convolution as an implicit GEMM: A = weights (rows = output channels),
 // B = the input patch (rows k = tap * cin_p + c, columns = pixels), so a lane
 // ends with 4 consecutive output channels of one pixel: one 16-byte NHWC
-// store.  A block is 4 waves over 4 rows x 64 columns of pixels; the input
-// patch (6 rows x 66 columns x cin_p, BF16, channel-contiguous with a 4-short
-// pad per pixel so that the 16 lanes' 8-byte reads fall in distinct banks)
-// is staged in LDS once and read by every k step.
+// store.  The image is cut into column bands about 64 wide; a block takes
+// 256 consecutive pixels of a band in row-major order (4 waves of 4 groups
+// of 16), so grids of 2^k + 1 columns leave no block nearly empty.  The
+// block's input patch (the band rows it touches plus a one-node halo, BF16,
+// channel-contiguous with a 4-short pad per pixel so that the 16 lanes'
+// 8-byte reads fall in distinct banks) is staged in LDS once and read by
+// every k step.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -25,14 +29,19 @@ namespace pic {
 namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int TR = 4;            // rows per block (one per wave)
-constexpr int TX = 64;           // columns per block
+constexpr int TR = 4;            // weight gradient: rows per pixel tile (one per wave)
+constexpr int TX = 64;           // weight gradient: columns per pixel tile
+constexpr int CONV_PIX = 256;    // forward / data gradient: pixels per block
+constexpr int BAND_MAX = 72;     // widest column band
 constexpr int PW = TX + 2;       // patch columns
 constexpr int PH = TR + 2;       // patch rows
 constexpr int EB = 256;          // threads of elementwise kernels
-constexpr int CONV_LDS_MAX = 150 * 1024;   // dynamic LDS of one conv block
+constexpr int CONV_LDS_MAX = 150 * 1024;   // dynamic LDS of a conv block of several channel tiles
+constexpr int CONV_LDS_LIMIT = 160 * 1024; // a CU's LDS: the most any conv block may take
 constexpr int STAGE = 8;                   // loads in flight per thread when staging tiles
 constexpr int RB = 1024;                   // threads of the kernels ending in an FP64 block sum
 inline int rblocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + RB - 1) / RB, 256)); }
@@ -59,7 +68,14 @@ struct ConvArgs {
     int32_t H, W, cout_p;
     int32_t relu, accumulate;
     int32_t nsplit;             // blocks per sample along the output tiles
+    int32_t nband, bpb;         // column bands, blocks per band
 };
+
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                   __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 
 // input value quad (4 channels from c4) of output-grid pixel (ys, xs)
 __device__ __forceinline__ float4 load_in(const float *x, int b, int ys, int xs, int H, int W,
@@ -80,16 +96,22 @@ template <int NT>
 __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
 {
     extern __shared__ __align__(16) char lds[];
+    // blockIdx.y = sample * nsplit + split: this block's 16-channel output
+    // tiles are [split * NT, split * NT + NT); blockIdx.x = band * bpb + chunk
+    const int b = blockIdx.y / a.nsplit, tile0 = (blockIdx.y - b * a.nsplit) * NT;
+    const int band = blockIdx.x / a.bpb, chunk = blockIdx.x - band * a.bpb;
+    const int c0 = (int)((int64_t)band * a.W / a.nband);
+    const int bw = (int)((int64_t)(band + 1) * a.W / a.nband) - c0;
+    const int npix = a.H * bw, i0 = chunk * CONV_PIX;
+    if (i0 >= npix) return;                     // the whole block: a band's spare chunk
+    const int i1 = min(npix, i0 + CONV_PIX);
+    const int ra = i0 / bw, prows = (i1 - 1) / bw - ra + 3, pw = bw + 2;
     const int cst = a.cin_p + 4;
-    short *patch = (short *)lds;
-    const int patch_bytes = (PH * PW * cst * 2 + 15) & ~15;
+    short *patch = (short *)lds;                // [prows][pw][cst], image row ra - 1 first
+    const int patch_bytes = (prows * pw * cst * 2 + 15) & ~15;
     int *off4 = (int *)(lds + patch_bytes);
     short *wl = (short *)(lds + patch_bytes + (((a.kpad >> 2) * 4 + 15) & ~15));
     const int wst = wrow_lds(a.kpad);
-    // blockIdx.z = sample * nsplit + split: this block's 16-channel output
-    // tiles are [split * NT, split * NT + NT)
-    const int b = blockIdx.z / a.nsplit, tile0 = (blockIdx.z - b * a.nsplit) * NT;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TR;
     // the block's weight rows, once, into LDS (16-byte pieces)
     // (every staging loop issues STAGE loads per thread before it stores any,
     // so a block waits for memory a few times, not once per piece)
@@ -102,6 +124,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
 #pragma unroll
             for (int u = 0; u < STAGE; ++u) {
                 const int t = t0 + u * 256;
+                v[u] = make_uint4(0u, 0u, 0u, 0u);   // defined on every path: kept in registers
                 if (t < total) {
                     const int row = t / pieces, pc = t - row * pieces;
                     v[u] = *(const uint4 *)(wsrc + (int64_t)row * a.kpad + 8 * pc);
@@ -119,7 +142,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
     }
     const int quads = a.cin_p >> 2;
     {
-        const int total = PH * PW * quads;
+        const int total = prows * pw * quads;
         for (int t0 = threadIdx.x; t0 < total; t0 += 256 * STAGE) {
             float4 v[STAGE];
 #pragma unroll
@@ -128,8 +151,8 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
                 v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (t < total) {
                     const int q = t % quads, pix = t / quads;
-                    const int r = pix / PW, col = pix - r * PW;
-                    v[u] = load_in(a.x, b, y0 + r - 1, x0 + col - 1, a.H, a.W, a.Hin, a.Win,
+                    const int r = pix / pw, col = pix - r * pw;
+                    v[u] = load_in(a.x, b, ra - 1 + r, c0 - 1 + col, a.H, a.W, a.Hin, a.Win,
                                    a.up_in, a.cin_p, 4 * q);
                 }
             }
@@ -148,46 +171,53 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
         const int k = 4 * kk;
         int o = -1;
         if (k < K) {
-            const int tap = k / a.cin_p, c0 = k - tap * a.cin_p;
+            const int tap = k / a.cin_p, c = k - tap * a.cin_p;
             const int kh = tap / 3, kw = tap - 3 * kh;
-            o = (kh * PW + kw) * cst + c0;
+            o = (kh * pw + kw) * cst + c;
         }
         off4[kk] = o;
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m = lane & 15, kq = (lane >> 4) * 4;
+    const int m = lane & 15, g = lane >> 4;
+    // this lane's pixel in each of the wave's four 16-pixel groups (the last
+    // valid pixel stands in past the end, its result not stored)
+    int prow[4], pcol[4], pofs[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int i = min(i0 + wave * 64 + t * 16 + m, i1 - 1);
+        prow[t] = i / bw;
+        pcol[t] = i - prow[t] * bw;
+        pofs[t] = ((prow[t] - ra) * pw + pcol[t]) * cst;
+    }
     v4f acc[4][NT];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[t][n] = v4f{0.f, 0.f, 0.f, 0.f};
-    const short *wbase = wl + m * wst + kq;
-    const short *pbase = patch + (wave * PW + m) * cst;
-    for (int kc = 0; kc < a.kpad; kc += 16) {
-        v4s wa[NT];
+    const short *wbase = wl + m * wst + 8 * g;
+    for (int kc = 0; kc < a.kpad; kc += 32) {
+        v8s wa[NT];
 #pragma unroll
-        for (int n = 0; n < NT; ++n) wa[n] = *(const v4s *)(wbase + n * 16 * wst + kc);
-        const int o = off4[(kc + kq) >> 2];
+        for (int n = 0; n < NT; ++n) wa[n] = *(const v8s *)(wbase + n * 16 * wst + kc);
+        const int o0 = off4[(kc >> 2) + 2 * g], o1 = off4[(kc >> 2) + 2 * g + 1];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            v4s pb = {0, 0, 0, 0};
-            if (o >= 0) pb = *(const v4s *)(pbase + o + t * 16 * cst);
+            v4s lo = {0, 0, 0, 0}, hi = {0, 0, 0, 0};
+            if (o0 >= 0) lo = *(const v4s *)(patch + pofs[t] + o0);
+            if (o1 >= 0) hi = *(const v4s *)(patch + pofs[t] + o1);
+            const v8s pb = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 #pragma unroll
-            for (int n = 0; n < NT; ++n)
-                acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[n], pb, acc[t][n], 0, 0, 0);
+            for (int n = 0; n < NT; ++n) acc[t][n] = mfma32(wa[n], pb, acc[t][n]);
         }
     }
-    const int yy = y0 + wave;
-    if (yy >= a.H) return;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int xx = x0 + t * 16 + m;
-        if (xx >= a.W) continue;
-        const int64_t pix = ((int64_t)b * a.H + yy) * a.W + xx;
+        if (i0 + wave * 64 + t * 16 + m >= i1) continue;
+        const int64_t pix = ((int64_t)b * a.H + prow[t]) * a.W + c0 + pcol[t];
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-            const int ch = (tile0 + n) * 16 + kq;
+            const int ch = (tile0 + n) * 16 + 4 * g;
             if (ch >= a.cout_p) continue;
             const int64_t o = pix * a.cout_p + ch;
             float4 v = make_float4(acc[t][n][0], acc[t][n][1], acc[t][n][2], acc[t][n][3]);
@@ -242,7 +272,7 @@ __global__ void __launch_bounds__(256) k_conv3x3_wgrad(WgradArgs a)
     short *gs = (short *)lds;                                   // [cout_p][TR * TX]
     short *xs = (short *)(lds + a.cout_p * TR * TX * 2);        // [cin_p][PH][PW]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m = lane & 15, kq = (lane >> 4) * 4;
+    const int m = lane & 15, g = lane >> 4;
     const int KT = a.kw >> 4, npairs = a.nt * KT;
     const int pair0 = (blockIdx.x * 4 + wave) * PPW;
     const int K = 9 * a.cin_p;
@@ -330,18 +360,20 @@ __global__ void __launch_bounds__(256) k_conv3x3_wgrad(WgradArgs a)
                 ones = true;
             }
             const bool nok = n < a.cout_p;
-            for (int ks = 0; ks < TR * TX / 16; ++ks) {
-                v4s av = {0, 0, 0, 0};
-                if (nok) av = *(const v4s *)(gs + n * TR * TX + ks * 16 + kq);
-                v4s bv = {0, 0, 0, 0};
+            // K = the tile's pixels, 32 (half a row) per MFMA
+            for (int ks = 0; ks < TR * TX / 32; ++ks) {
+                v8s av = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (nok) av = *(const v8s *)(gs + n * TR * TX + ks * 32 + 8 * g);
+                v8s bv = {0, 0, 0, 0, 0, 0, 0, 0};
                 if (xbase >= 0) {
-                    const int r = ks >> 2, col = (ks & 3) * 16 + kq;
+                    const int r = ks >> 1, col = (ks & 1) * 32 + 8 * g;
                     const short *px = xs + xbase + r * PW + col;
-                    bv = v4s{px[0], px[1], px[2], px[3]};
+                    bv = v8s{px[0], px[1], px[2], px[3], px[4], px[5], px[6], px[7]};
                 } else if (ones) {
-                    bv = v4s{(short)0x3f80, (short)0x3f80, (short)0x3f80, (short)0x3f80};
+                    const short one = (short)0x3f80;
+                    bv = v8s{one, one, one, one, one, one, one, one};
                 }
-                acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[i], 0, 0, 0);
+                acc[i] = mfma32(av, bv, acc[i]);
             }
         }
     }
@@ -353,7 +385,7 @@ __global__ void __launch_bounds__(256) k_conv3x3_wgrad(WgradArgs a)
         const int ntile = pr / KT, kt = pr - ntile * KT;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            dst[(int64_t)(ntile * 16 + kq + j) * a.kw + kt * 16 + m] = acc[i][j];
+            dst[(int64_t)(ntile * 16 + 4 * g + j) * a.kw + kt * 16 + m] = acc[i][j];
     }
 }
 
@@ -783,9 +815,26 @@ inline int eblocks(int64_t n)
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 // ---- launch helpers ------------------------------------------------------------
-int conv_lds(int cin_p, int kpad, int ntb)
+// Column bands of an H x W level for the forward / data-gradient kernel: the
+// band count, blocks per band, and the most patch rows and columns a block
+// stages (256 consecutive pixels of a band b wide span at most 2 + 255 / b
+// rows; one halo row above and below, one halo column each side).
+struct ConvGeom {
+    int nband, bpb, prows, pw;
+};
+ConvGeom conv_geom(int H, int W)
 {
-    return ((PH * PW * (cin_p + 4) * 2 + 15) & ~15) + (((kpad / 4) * 4 + 15) & ~15) +
+    ConvGeom c;
+    c.nband = std::max(1, (W + BAND_MAX - 1) / BAND_MAX);
+    const int bwmax = (W + c.nband - 1) / c.nband, bwmin = W / c.nband;
+    c.bpb = (int)(((int64_t)H * bwmax + CONV_PIX - 1) / CONV_PIX);
+    c.prows = std::min(H, 2 + (CONV_PIX - 1) / bwmin) + 2;
+    c.pw = bwmax + 2;
+    return c;
+}
+int conv_lds(const ConvGeom &c, int cin_p, int kpad, int ntb)
+{
+    return ((c.prows * c.pw * (cin_p + 4) * 2 + 15) & ~15) + (((kpad / 4) * 4 + 15) & ~15) +
            ntb * 16 * wrow_lds(kpad) * 2;
 }
 
@@ -814,15 +863,17 @@ void conv(const PcNet &n, int li, bool dgrad, const float *x, const float *skip,
     a.relu = relu;
     a.accumulate = accumulate;
     const int nt = dgrad ? l.nt_t : l.nt;
-    const int gx = (a.W + TX - 1) / TX, gy = (a.H + TR - 1) / TR;
+    const ConvGeom cg = conv_geom(a.H, a.W);
+    a.nband = cg.nband;
+    a.bpb = cg.bpb;
     // one block per tile of output channels when the grid alone is too
     // small to fill the chip or the block's weights would not fit in LDS
-    int ntb = (nt > 1 && ((int64_t)gx * gy * B < 1024 || conv_lds(a.cin_p, a.kpad, nt) > CONV_LDS_MAX))
-                  ? 1 : nt;
+    const int64_t blocks = (int64_t)cg.nband * cg.bpb * B;
+    int ntb = (nt > 1 && (blocks < 1024 || conv_lds(cg, a.cin_p, a.kpad, nt) > CONV_LDS_MAX)) ? 1 : nt;
     if (ntb != 3 && ntb != 5) ntb = 1;            // instantiated tile counts
     a.nsplit = nt / ntb;
-    dim3 g(gx, gy, B * a.nsplit);
-    const int lds = conv_lds(a.cin_p, a.kpad, ntb);
+    dim3 g(cg.nband * cg.bpb, B * a.nsplit);
+    const int lds = conv_lds(cg, a.cin_p, a.kpad, ntb);
     switch (ntb) {
         case 1: hipLaunchKernelGGL(k_conv3x3<1>, g, dim3(256), lds, s, a); break;
         case 3: hipLaunchKernelGGL(k_conv3x3<3>, g, dim3(256), lds, s, a); break;
@@ -995,8 +1046,8 @@ void pc_describe(PcNet &n, int nr, int nz, int batch)
         l.cout_p = (int)round_up(l.cout, 4);
         l.nt = (l.cout + 15) / 16;
         l.nt_t = (l.cin + 15) / 16;
-        l.kpad = (int)round_up(9 * l.cin_p, 16);
-        l.kpad_t = (int)round_up(9 * l.cout_p, 16);
+        l.kpad = (int)round_up(9 * l.cin_p, 32);   // whole 32-deep MFMA steps
+        l.kpad_t = (int)round_up(9 * l.cout_p, 32);
         l.kw = (int)round_up(9 * l.cin_p + 1, 16);
         l.o_master = om;
         l.o_wf = owf;
@@ -1101,9 +1152,21 @@ int64_t pc_bytes(const PcNet &n)
 
 void pc_bind(PcNet &n, char *base) { pc_carve(n, base); }
 
+bool pc_fits(const PcNet &n)
+{
+    for (int k = 0; k < PC_LAYERS; ++k) {
+        const PcLayer &l = n.L[k];
+        const ConvGeom cg = conv_geom(n.H[l.level], n.W[l.level]);
+        if (conv_lds(cg, l.cin_p, l.kpad, 1) > CONV_LDS_LIMIT ||
+            conv_lds(cg, l.cout_p, l.kpad_t, 1) > CONV_LDS_LIMIT)
+            return false;
+    }
+    return true;
+}
+
 int pc_kernel_setup()
 {
-    const int lim = 160 * 1024;
+    const int lim = CONV_LDS_LIMIT;
     int e = 0;
     e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
