@@ -1037,7 +1037,7 @@ __global__ void __launch_bounds__(PUSH_THREADS) k_push_b(PartBatch<T> B)
 // order does not matter.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ void events_body(const EventParams<T> P, int bid, int nb)
+__device__ __forceinline__ void events_body(const EventParams<T> &P, int bid, int nb)
 {
     const PushCold<T> *C = P.cold;
     DevScalars *sc = P.sc;
@@ -1157,7 +1157,7 @@ void launch_push(const PushParams<T> &p, int scheme, int nblocks, hipStream_t s)
 // next_id[s] + rank; its charge is deposited with global atomics.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ void children_body(const ChildParams<T> P, int bid, int nb, unsigned long long *tk,
+__device__ __forceinline__ void children_body(const ChildParams<T> &P, int bid, int nb, unsigned long long *tk,
                               int *ts)
 {
     const int n = min(P.sc->n_child, P.child_cap);
