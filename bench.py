@@ -312,6 +312,52 @@ def high_density_bench(steps=20, warmup=5, box_steps=2000, box_every=40):
     return out
 
 
+def high_density_sweep(steps=2000, every=500):
+    """The high-density discharge (512 x 1024 cells, 5e7 + 5e7, n = 1e17,
+    20 mTorr) at each ion-induced yield 0.1, 0.2, 0.3 and series resistance
+    10, 100 ohm, with each gather form: `steps` steps (10 ns) from the same
+    seeded load, the FP64 diagnostics every `every` steps (cathode voltage
+    and current, total energy = kinetic + field, collisions, emission)."""
+    import numpy as np
+    import torch
+    from paper_2507_10727_amd import workloads as W
+    from paper_2507_10727_amd.sim import Simulation
+    base = W.preset("ec512x1024_f32")
+    br, bz, sig, parts = W.inputs(base)
+    runs = []
+    for form, scheme in (("ec", W.EC_PIC), ("mc", W.MC_PIC)):
+        for gamma in (0.1, 0.2, 0.3):
+            for r_ohm in (10.0, 100.0):
+                p = base.replace(scheme=scheme, gamma_i=gamma, r_ext=r_ohm)
+                sim = Simulation(p, br, bz, sig, parts, timers=False)
+                d = sim.diag()
+                e0 = d["ke"][0] + d["ke"][1] + d["w_field"]
+                hist = []
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps // every):
+                    sim.step(every)
+                    d = sim.diag()
+                    hist.append({"step": d["step"], "vc": d["vc"], "i_cathode": d["i_cathode"],
+                                 "energy_j": d["ke"][0] + d["ke"][1] + d["w_field"]})
+                wall = time.perf_counter() - t0
+                sim.close()
+                del sim
+                torch.cuda.empty_cache()
+                r = {"form": form, "gamma_i": gamma, "r_ohm": r_ohm, "steps": steps,
+                     "ms_per_step_with_diag": wall / steps * 1e3,
+                     "vc": d["vc"], "i_cathode_a": d["i_cathode"],
+                     "i_cathode_mean_a": float(np.mean([h["i_cathode"] for h in hist])),
+                     "energy_change": (hist[-1]["energy_j"] - e0) / e0,
+                     "n_coll": list(d["n_coll"]), "n_see": d["n_see"], "count": list(d["count"]),
+                     "phi_max": d["phi_max"], "n_peak": list(d["n_peak"]), "history": hist}
+                log(f"[bench] sweep {form} gamma {gamma} R {r_ohm}: vc {r['vc']:.2f} V, "
+                    f"I {r['i_cathode_mean_a']:.4g} A, dE/E {r['energy_change']:+.3e}")
+                runs.append(r)
+    return {"grid": f"{base.nr}x{base.nz}", "particles_per_species": base.n_per_species,
+            "density_m3": base.density, "dt_s": base.dt, "runs": runs}
+
+
 def table1_bench(steps=200_000, chunk=2000):
     """Table 1's trends on the 3 x 3 cm geometry of Section 3: ion yield 0.1
     or 0.2 and R = 3000 or 1000 ohm (electron yield 0.1, -300 V), the four
@@ -456,6 +502,9 @@ def main():
                     help="skip the 512 x 1024 discharges (uniform EC/MC and clustered)")
     ap.add_argument("--high-density-only", action="store_true",
                     help="only the 512 x 1024 discharges (prints their JSON)")
+    ap.add_argument("--hd-sweep-only", action="store_true",
+                    help="only the 512 x 1024 discharge at ion yields 0.1/0.2/0.3 and "
+                         "10/100 ohm with each gather form, 2000 steps each (prints its JSON)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -479,6 +528,9 @@ def main():
         return
     if args.high_density_only:
         print(json.dumps({"high_density": high_density_bench()}), flush=True)
+        return
+    if args.hd_sweep_only:
+        print(json.dumps({"high_density_sweep": high_density_sweep()}), flush=True)
         return
 
     if args.copy_calibration:
