@@ -474,6 +474,62 @@ def ensemble_bench(n_runs=64, steps=10, scale=1.0):
             "per_run": runs}
 
 
+def ensemble_long(n_runs=64, steps=200_000, every=2000):
+    """The yield / resistance sweep advanced as one ensemble for `steps`
+    steps (2e5 steps of 5 ps: 1 us), each run's cathode current, voltage and
+    peak densities sampled every `every` steps; per run, the means and
+    spread of current and voltage over the last quarter of the samples.
+    Capacity 2x the initial load per species, for a discharge that grows."""
+    import numpy as np
+    import torch
+    from paper_2507_10727_amd import autotune
+    from paper_2507_10727_amd import workloads as W
+    from paper_2507_10727_amd.sim import Ensemble, Simulation
+    ps = [p.replace(capacity_factor=2.0) for p in W.ensemble_problems(n_runs=n_runs)]
+    sims = []
+    for p in ps:
+        br, bz, sig, parts = W.inputs(p)
+        sims.append(Simulation(p, br, bz, sig, parts))
+    cache = autotune.TuningCache()
+    for sim in sims:
+        cache.apply_or_tune(sim, steps_per_trial=2)
+    log(f"[bench] ensemble-long: {n_runs} runs initialised and tuned")
+    ens = Ensemble(sims, nstreams=1)
+    samples = [[] for _ in sims]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        ens.step(k)
+        done += k
+        tot = 0
+        for j, sim in enumerate(sims):
+            d = sim.diag()
+            samples[j].append((d["step"], d["i_cathode"], d["vc"], d["n_peak"][0], d["n_peak"][1],
+                               d["count"][0] + d["count"][1]))
+            tot += d["count"][0] + d["count"][1]
+        log(f"[bench] ensemble-long: {done} steps, {tot} particles, "
+            f"{(time.perf_counter() - t0):.1f} s")
+    wall = time.perf_counter() - t0
+    ens.close()
+    runs = []
+    for p, sim, sm in zip(ps, sims, samples):
+        a = np.array(sm, dtype=np.float64)
+        tail = a[-max(1, len(a) // 4):]
+        runs.append({"grid": p.nr, "gamma": p.gamma_i, "r_ohm": p.r_ext,
+                     "density_m3": p.density, "particles_start": p.n_per_species * 2,
+                     "particles_end": int(a[-1, 5]), "step": int(a[-1, 0]),
+                     "i_cathode_mean_a": float(tail[:, 1].mean()),
+                     "i_cathode_std_a": float(tail[:, 1].std()),
+                     "v_cathode_mean": float(tail[:, 2].mean()),
+                     "v_cathode_std": float(tail[:, 2].std()),
+                     "n_e_peak_m3": float(a[-1, 3]), "n_i_peak_m3": float(a[-1, 4])})
+        sim.close()
+    return {"runs": n_runs, "steps": steps, "sample_every": every,
+            "ms_per_step_with_sampling": wall / steps * 1e3, "per_run": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -502,6 +558,9 @@ def main():
                     help="skip the 512 x 1024 discharges (uniform EC/MC and clustered)")
     ap.add_argument("--high-density-only", action="store_true",
                     help="only the 512 x 1024 discharges (prints their JSON)")
+    ap.add_argument("--ensemble-long", type=int, default=0, metavar="STEPS",
+                    help="only the 64-run sweep as one ensemble for STEPS steps with per-run "
+                         "current / voltage sampling (prints its JSON)")
     ap.add_argument("--hd-sweep-only", action="store_true",
                     help="only the 512 x 1024 discharge at ion yields 0.1/0.2/0.3 and "
                          "10/100 ohm with each gather form, 2000 steps each (prints its JSON)")
@@ -531,6 +590,9 @@ def main():
         return
     if args.hd_sweep_only:
         print(json.dumps({"high_density_sweep": high_density_sweep()}), flush=True)
+        return
+    if args.ensemble_long:
+        print(json.dumps({"ensemble_long": ensemble_long(steps=args.ensemble_long)}), flush=True)
         return
 
     if args.copy_calibration:
