@@ -177,7 +177,7 @@ def poisson_bench(train_seconds=60.0, reps=6):
     return out
 
 
-def gather_forms_bench(workload, steps=100, warmup=20, box_steps=4000, box_every=40):
+def gather_forms_bench(workload, steps=100, warmup=20, box_steps=20000, box_every=200):
     """Both gather forms of the paper (Section 2).  Throughput: the bench
     workload's full step with each form (EC-PIC is the headline value, MC-PIC
     the same discharge with the nodal-field gather).  Energy: the closed
