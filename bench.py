@@ -111,15 +111,16 @@ def cpu_baseline(prob, br, bz, sig, parts, budget_s=12.0, max_steps=64):
             "seconds": par["seconds"], "serial": serial, "openmp": par, **cpu_info()}
 
 
-def poisson_bench(train_seconds=60.0, reps=6):
+def poisson_bench(train_seconds=60.0, reps=6, n_snap=1024, train_steps=3000):
     """Field solve on the 512 x 1024 R-Z operator to an FP64-checked 1e-8
     relative residual: multigrid-preconditioned CG against flexible CG with
     the learned preconditioner, on held-out charge snapshots of a discharge
     at that grid, cold (phi = 0) and warm (previous snapshot's solution).
 
     The network is trained first, on the GPU, on pairs the simulation makes:
-    1024 (Q, phi0) snapshots of the same discharge and their negatives, and
-    192 random potentials with Q = K phi (see pc_train): 2240 pairs.  The
+    n_snap (Q, phi0) snapshots of the same discharge and their negatives, and
+    192 random potentials with Q = K phi (see pc_train): 2240 pairs by
+    default, 20192 with n_snap = 10000 (--pc-snapshots).  The
     learned preconditioner's first approximation is the multigrid V-cycle
     (pc_pre = 1), which the network corrects."""
     import numpy as np
@@ -127,28 +128,36 @@ def poisson_bench(train_seconds=60.0, reps=6):
     from paper_2507_10727_amd import pc_train
     from paper_2507_10727_amd import workloads as W
     from paper_2507_10727_amd.sim import Simulation
+    # (capacity 4x the load: a long snapshot collection lets the discharge grow)
     p = W.preset("ec512x1024_f32").replace(n_per_species=2_000_000, poisson_rtol=1e-8,
-                                           poisson_maxit=500, pc_batch=8)
+                                           poisson_maxit=500, pc_batch=8, capacity_factor=4.0)
     br, bz, sig, parts = W.inputs(p)
     sim = Simulation(p, br, bz, sig, parts)
     sim.step(50)
-    log("[bench] poisson: collecting snapshot pairs")
-    Qs, Ps = pc_train.snapshot_pairs(sim, 1032, every=2)
-    held_q = Qs[1024:].clone()
-    Qs, Ps = Qs[:1024], Ps[:1024]
-    Qf, Pf = pc_train.field_pairs(sim, 192, seed=250710731)
-    Q = torch.cat([Qs, -Qs, Qf])
-    P = torch.cat([Ps, -Ps, Pf])
-    del Qs, Ps, Qf, Pf
+    log(f"[bench] poisson: collecting {n_snap + 8} charge snapshots")
+    # one buffer per side for the snapshots, their negatives and the random
+    # potentials, filled in place (at 2e4 pairs each side holds ~85 GB)
+    nf = 192
+    Q = torch.empty((2 * n_snap + nf, p.nodes), dtype=torch.float64, device="cuda")
+    P = torch.empty_like(Q)
+    pc_train.snapshot_pairs(sim, n_snap + 8, every=2, out=(Q, P))
+    held_q = Q[n_snap:n_snap + 8].clone()
+    torch.neg(Q[:n_snap], out=Q[n_snap:2 * n_snap])
+    torch.neg(P[:n_snap], out=P[n_snap:2 * n_snap])
+    Qf, Pf = pc_train.field_pairs(sim, nf, seed=250710731)
+    Q[2 * n_snap:].copy_(Qf)
+    P[2 * n_snap:].copy_(Pf)
+    del Qf, Pf
     log(f"[bench] poisson: training on {Q.shape[0]} pairs for <= {train_seconds:.0f} s")
-    tr = pc_train.train(sim, Q, P, steps=3000, batch=8, lr=1e-3, seed=1,
-                        time_limit=train_seconds)
+    tr = pc_train.train(sim, Q, P, steps=train_steps, batch=8, lr=1e-3, seed=1,
+                        time_limit=train_seconds,
+                        report=lambda k, loss: log(f"[bench] poisson: step {k}, loss {loss:.4f}"))
     log(f"[bench] poisson: {tr['steps']} steps, loss {tr['loss_first']:.3f} -> "
         f"{tr['loss_last']:.4f}, {tr['ms_per_step']:.1f} ms/step")
     del Q, P
     torch.cuda.empty_cache()
     out = {"grid": "512x1024", "rtol": 1e-8, "rhs": "held-out charge snapshots",
-           "pairs": 2240, "first_step": "multigrid V-cycle",
+           "pairs": 2 * n_snap + nf, "first_step": "multigrid V-cycle",
            "training": tr}
     for name, mode in (("mg_cg", W.POISSON_MGCG), ("learned_fcg", W.POISSON_LEARNED)):
         sim.set_poisson_mode(mode)
@@ -544,6 +553,11 @@ def main():
     ap.add_argument("--poisson-only", action="store_true",
                     help="only the field-solve comparison (prints its JSON)")
     ap.add_argument("--train-seconds", type=float, default=60.0)
+    ap.add_argument("--train-steps", type=int, default=3000,
+                    help="most Adam steps of the network training (the time limit may stop it first)")
+    ap.add_argument("--pc-snapshots", type=int, default=1024,
+                    help="charge snapshots of the training set (with their negatives and 192 "
+                         "random potentials: 2 N + 192 pairs)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the EC-PIC / MC-PIC throughput and energy comparison")
     ap.add_argument("--no-ensemble", action="store_true",
@@ -577,7 +591,8 @@ def main():
     from paper_2507_10727_amd.sim import Simulation
 
     if args.poisson_only:
-        print(json.dumps({"poisson": poisson_bench(args.train_seconds)}), flush=True)
+        print(json.dumps({"poisson": poisson_bench(args.train_seconds, n_snap=args.pc_snapshots,
+                                                   train_steps=args.train_steps)}), flush=True)
         return
     if args.ensemble_only:
         print(json.dumps({"ensemble": ensemble_bench(args.ensemble_runs)}), flush=True)

@@ -18,13 +18,16 @@ import numpy as np
 from . import workloads as W
 
 
-def snapshot_pairs(sim, n, every=2):
+def snapshot_pairs(sim, n, every=2, out=None):
     """n (Q, phi0) pairs from sim, one every `every` steps: device tensors
-    [n, nodes] (float64)."""
+    [n, nodes] (float64), or written into the first n rows of out = (Q, P)."""
     torch = sim.torch
     nodes = sim.prob.nodes
-    Q = torch.empty((n, nodes), dtype=torch.float64, device=sim.device)
-    P = torch.empty_like(Q)
+    if out is None:
+        Q = torch.empty((n, nodes), dtype=torch.float64, device=sim.device)
+        P = torch.empty_like(Q)
+    else:
+        Q, P = out
     for k in range(n):
         sim.step(every)
         f = sim.fields()
@@ -47,18 +50,24 @@ def field_pairs(sim, n, seed):
     return Q, P
 
 
-def output_scale(Q, P, unknown):
-    """Typical size of phi / rms(Q / (2 pi eps0)): the network output scale."""
+def output_scale(Q, P, unknown, rows=64):
+    """Typical size of phi / rms(Q / (2 pi eps0)): the network output scale
+    (the mean over pairs, taken `rows` pairs at a time)."""
     two_pi_eps0 = 2 * np.pi * 8.8541878128e-12
-    q = Q[:, unknown].double() / two_pi_eps0
-    ph = P[:, unknown].double()
-    rho = q.pow(2).mean(dim=1).sqrt()
-    return float((ph / rho[:, None]).pow(2).mean(dim=1).sqrt().mean())
+    total = 0.0
+    for a in range(0, Q.shape[0], rows):
+        q = Q[a:a + rows][:, unknown].double() / two_pi_eps0
+        ph = P[a:a + rows][:, unknown].double()
+        rho = q.pow(2).mean(dim=1).sqrt()
+        total += float((ph / rho[:, None]).pow(2).mean(dim=1).sqrt().sum())
+    return total / Q.shape[0]
 
 
-def train(sim, Q, P, steps=2000, batch=8, lr=1e-3, seed=0, time_limit=None, theta=None):
+def train(sim, Q, P, steps=2000, batch=8, lr=1e-3, seed=0, time_limit=None, theta=None,
+          report=None, report_seconds=30.0):
     """Adam on random batches of the pairs; the last quarter of the steps
-    at 0.3 lr.  Returns a summary dict."""
+    at 0.3 lr.  report(steps_done, loss), if given, is called about every
+    report_seconds.  Returns a summary dict."""
     torch = sim.torch
     rng = np.random.default_rng(seed)
     n = Q.shape[0]
@@ -67,7 +76,7 @@ def train(sim, Q, P, steps=2000, batch=8, lr=1e-3, seed=0, time_limit=None, thet
         theta = init_params(rng)
     sim.pc_set_weights(theta, output_scale(Q, P, unknown))
     losses = []
-    t0 = time.perf_counter()
+    t0 = t_rep = time.perf_counter()
     done = 0
     for s in range(steps):
         if time_limit is not None and time.perf_counter() - t0 > time_limit:
@@ -76,6 +85,9 @@ def train(sim, Q, P, steps=2000, batch=8, lr=1e-3, seed=0, time_limit=None, thet
         rate = lr if s < 0.75 * steps else 0.3 * lr
         losses.append(sim.pc_train_step(Q[idx].contiguous(), P[idx].contiguous(), rate))
         done += 1
+        if report is not None and time.perf_counter() - t_rep > report_seconds:
+            report(done, losses[-1])
+            t_rep = time.perf_counter()
     secs = time.perf_counter() - t0
     return {"steps": done, "batch": min(batch, n), "pairs": n, "seconds": secs,
             "ms_per_step": secs / max(done, 1) * 1e3,
