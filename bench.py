@@ -37,6 +37,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def copy_rate_gbs(bytes_moved, reps=10):
+    """Rate of a plain device-to-device copy that moves `bytes_moved` bytes
+    (half read, half written), timed with HIP events: what streaming alone
+    reaches on this GPU at the particle kernel's size."""
+    import torch
+    n = max(1, int(bytes_moved // 2) // 4)
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def traffic_from_profile(workload):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
@@ -662,11 +683,14 @@ def main():
     push_avg_ms = tm["push_ms"] / max(tm["push_launches"], 1)
     algo_bytes = ALGO_BYTES[dtype]["e"] * ne + ALGO_BYTES[dtype]["i"] * ni
     achieved = algo_bytes / (push_avg_ms * 1e-3) / 1e9
+    copy_gbs = copy_rate_gbs(algo_bytes)
+    log(f"[bench] device copy of the same bytes: {copy_gbs:.0f} GB/s")
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(args.workload),
             "kernel": "k_push (gather+Boris+walls+SEE+MCC+deposit)",
             "avg_ms": push_avg_ms, "launches": tm["push_launches"],
-            "algorithmic_bytes_per_launch": algo_bytes}
+            "algorithmic_bytes_per_launch": algo_bytes,
+            "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs}
     phases = {k: tm_all[k] / n_ph for k in ("push_ms", "children_ms", "sort_ms", "poisson_ms",
                                             "circuit_ms", "field_ms")}
     phases["steps"] = n_ph
