@@ -38,9 +38,10 @@ def log(*a):
 
 
 def copy_rate_gbs(bytes_moved, reps=10):
-    """Rate of a plain device-to-device copy that moves `bytes_moved` bytes
-    (half read, half written), timed with HIP events: what streaming alone
-    reaches on this GPU at the particle kernel's size."""
+    """Rate of a device-to-device copy through torch (Tensor.copy_) that
+    moves `bytes_moved` bytes (half read, half written), timed with HIP
+    events: what plain streaming reaches on this GPU at the particle
+    kernel's size (context for the roofline, not a bound)."""
     import torch
     n = max(1, int(bytes_moved // 2) // 4)
     src = torch.ones(n, dtype=torch.float32, device="cuda")
