@@ -92,7 +92,10 @@ __device__ __forceinline__ float4 load_in(const float *x, int b, int ys, int xs,
 // the 16 rows a wavefront reads at one column fall in different banks.
 __host__ __device__ __forceinline__ int wrow_lds(int kpad) { return kpad + 8; }
 
-template <int NT>
+// WG: the weights are read from global memory (L2) in the k loop, one step
+// ahead, instead of staged in LDS; the block then holds only its patch in
+// LDS, so more blocks fit a CU where the weights would have kept one out
+template <int NT, bool WG>
 __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
 {
     extern __shared__ __align__(16) char lds[];
@@ -115,7 +118,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
     // the block's weight rows, once, into LDS (16-byte pieces)
     // (every staging loop issues STAGE loads per thread before it stores any,
     // so a block waits for memory a few times, not once per piece)
-    {
+    if constexpr (!WG) {
         const int pieces = a.kpad >> 3;            // 8 shorts per piece
         const int total = NT * 16 * pieces;
         const short *wsrc = a.w + (int64_t)tile0 * 16 * a.kpad;
@@ -195,11 +198,25 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a)
     for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[t][n] = v4f{0.f, 0.f, 0.f, 0.f};
-    const short *wbase = wl + m * wst + 8 * g;
+    const short *wbase = WG ? a.w + ((int64_t)tile0 * 16 + m) * a.kpad + 8 * g : wl + m * wst + 8 * g;
+    const int wrow = WG ? a.kpad : wst;
+    v8s wn[NT];
+    if constexpr (WG) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) wn[n] = *(const v8s *)(wbase + n * 16 * wrow);
+    }
     for (int kc = 0; kc < a.kpad; kc += 32) {
         v8s wa[NT];
+        if constexpr (WG) {
 #pragma unroll
-        for (int n = 0; n < NT; ++n) wa[n] = *(const v8s *)(wbase + n * 16 * wst + kc);
+            for (int n = 0; n < NT; ++n) {
+                wa[n] = wn[n];
+                if (kc + 32 < a.kpad) wn[n] = *(const v8s *)(wbase + n * 16 * wrow + kc + 32);
+            }
+        } else {
+#pragma unroll
+            for (int n = 0; n < NT; ++n) wa[n] = *(const v8s *)(wbase + n * 16 * wrow + kc);
+        }
         const int o0 = off4[(kc >> 2) + 2 * g], o1 = off4[(kc >> 2) + 2 * g + 1];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -874,10 +891,17 @@ void conv(const PcNet &n, int li, bool dgrad, const float *x, const float *skip,
     a.nsplit = nt / ntb;
     dim3 g(cg.nband * cg.bpb, B * a.nsplit);
     const int lds = conv_lds(cg, a.cin_p, a.kpad, ntb);
+    // one channel tile of a wide layer: read the weights from L2 when
+    // leaving them out of LDS fits more blocks on a CU
+    const int lds_wg = conv_lds(cg, a.cin_p, a.kpad, 0);
+    if (ntb == 1 && a.cin_p >= 48 && CONV_LDS_LIMIT / lds_wg > CONV_LDS_LIMIT / lds) {
+        hipLaunchKernelGGL((k_conv3x3<1, true>), g, dim3(256), lds_wg, s, a);
+        return;
+    }
     switch (ntb) {
-        case 1: hipLaunchKernelGGL(k_conv3x3<1>, g, dim3(256), lds, s, a); break;
-        case 3: hipLaunchKernelGGL(k_conv3x3<3>, g, dim3(256), lds, s, a); break;
-        default: hipLaunchKernelGGL(k_conv3x3<5>, g, dim3(256), lds, s, a); break;
+        case 1: hipLaunchKernelGGL((k_conv3x3<1, false>), g, dim3(256), lds, s, a); break;
+        case 3: hipLaunchKernelGGL((k_conv3x3<3, false>), g, dim3(256), lds, s, a); break;
+        default: hipLaunchKernelGGL((k_conv3x3<5, false>), g, dim3(256), lds, s, a); break;
     }
 }
 
@@ -1168,9 +1192,10 @@ int pc_kernel_setup()
 {
     const int lim = CONV_LDS_LIMIT;
     int e = 0;
-    e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<5>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<1, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<1, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<3, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    e |= (int)hipFuncSetAttribute((const void *)k_conv3x3<5, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     e |= (int)hipFuncSetAttribute((const void *)k_conv3x3_wgrad, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     return e;
 }
