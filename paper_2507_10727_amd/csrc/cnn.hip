@@ -891,10 +891,11 @@ void conv(const PcNet &n, int li, bool dgrad, const float *x, const float *skip,
     a.nsplit = nt / ntb;
     dim3 g(cg.nband * cg.bpb, B * a.nsplit);
     const int lds = conv_lds(cg, a.cin_p, a.kpad, ntb);
-    // one channel tile of a wide layer: read the weights from L2 when
-    // leaving them out of LDS fits more blocks on a CU
+    // one channel tile of 16 or more input channels: read the weights from
+    // L2 when leaving them out of LDS fits more blocks on a CU (the 2-channel
+    // input layer, 64 k values, is faster with them in LDS)
     const int lds_wg = conv_lds(cg, a.cin_p, a.kpad, 0);
-    if (ntb == 1 && a.cin_p >= 48 && CONV_LDS_LIMIT / lds_wg > CONV_LDS_LIMIT / lds) {
+    if (ntb == 1 && a.cin_p >= 16 && CONV_LDS_LIMIT / lds_wg > CONV_LDS_LIMIT / lds) {
         hipLaunchKernelGGL((k_conv3x3<1, true>), g, dim3(256), lds_wg, s, a);
         return;
     }
